@@ -1,0 +1,98 @@
+/*
+ * FP64 CPU oracle of the coupled FD-LBM step (Kulyk, Berger, Smith, Harting,
+ * "Catalytic flow with a coupled Finite Difference - Lattice Boltzmann scheme").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, obviously-correct reference
+ * used by the tests and by the benchmark's CPU-baseline leg.  The product (the
+ * HIP library) never links, loads or calls it, and it shares no code, header or
+ * table with the product.
+ *
+ * Everything is double precision, plain nested loops, one thread.  Equation
+ * numbers refer to the paper in the order of its display equations:
+ *   Eq.(1)  two-step BGK kinetic equation          Eq.(2)  species lattice velocities
+ *   Eq.(4)  mixture equilibrium                     Eq.(5)  mixture moments
+ *   Eq.(6)  auxiliary equilibrium f*                Eq.(7-8) tau2, mixture diffusion
+ *   Eq.(11) diffusion-velocity correction U^c       Eq.(12-13) its forcing, psi vectors
+ *   Eq.(14-17) Wilke viscosity, tau1                Eq.(19-21) Prandtl correction
+ *   Eq.(23) g-transform   Eq.(24) trapezoidal collision   Eq.(25) f-moments from g
+ *   Eq.(33-36) off-lattice streaming interpolation  Eq.(37-41) reactive diffusive wall
+ *   Eq.(42) reaction enthalpy   Eq.(46-48) solid FD heat step and interface
+ *   Eq.(50) surface rate law
+ */
+#ifndef FDLBM_ORACLE_H
+#define FDLBM_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORACLE_MAXS 8
+
+typedef struct oracle_sim oracle_sim;
+
+typedef struct {
+  double mass[ORACLE_MAXS];   /* per-species gas mass incl. wall-emitted pops in flight */
+  double e_gas;               /* (1/2) sum c^2 g over gas pops and wall-emitted pops    */
+  double e_solid;             /* sum C_s T^s over solid nodes                            */
+  double moles_reacted;       /* cumulative sum over steps and wall nodes of r_w          */
+  double heat_released;       /* cumulative -dH * r_w                                     */
+  double heat_boundary;       /* cumulative heat into the solid through Dirichlet faces   */
+  double work_body;           /* cumulative work of the body force on the gas             */
+  double T_min, T_max, u_max, rho_min;
+  double Ts_min, Ts_max;
+  int64_t step;
+  int32_t bad;                /* 1 if a NaN/Inf, negative density or temperature seen   */
+  int32_t n_gas, n_wall, n_solid;
+} oracle_obs;
+
+/* lattice: 2 = D2Q9, 3 = D3Q19.  periodic[a] nonzero: axis a wraps.
+ * inout: 1 = planes x=0,1 are inlet ghosts and x=nx-2,nx-1 outlet ghosts. */
+oracle_sim *oracle_create(int lattice, int nx, int ny, int nz, const int *periodic,
+                          int n_species);
+void oracle_destroy(oracle_sim *s);
+const char *oracle_error(const oracle_sim *s);
+
+int oracle_set_geometry(oracle_sim *s, const uint8_t *mask, int inout);
+int oracle_set_species(oracle_sim *s, const double *M, const double *mu0, double mu_T_exp,
+                       const double *Djk0, double D_T_exp, double D_p_exp, double T_ref,
+                       double p_ref, double Pr, unsigned flags);
+int oracle_set_solid(oracle_sim *s, double alpha_s, double C_s, const double *T_bc6);
+int oracle_set_reaction(oracle_sim *s, const double *nu, const double *order, double k0,
+                        double ea, double T_ref, double dH, int wall_mode, double T_iso,
+                        double tol, int max_iter);
+int oracle_set_flow(oracle_sim *s, const double *F3, const double *X_in, double p_in,
+                    double T_in);
+/* rho[j*n + node], u[a*n + node] (3 rows), T[n], Ts[n]; populations set to f^eq. */
+int oracle_init_fields(oracle_sim *s, const double *rho, const double *u, const double *T,
+                       const double *Ts);
+int oracle_step(oracle_sim *s, int64_t n_steps);
+int oracle_observe(oracle_sim *s, oracle_obs *out);
+
+/* field ids for oracle_get_field (dst holds n doubles, POP holds Q*n) */
+enum { OF_RHO = 0, OF_U = 1, OF_T = 2, OF_TS = 3, OF_POP = 4, OF_KIND = 5, OF_WALL_R = 6,
+       OF_WALL_DE = 7 };
+int oracle_get_field(oracle_sim *s, int field, int comp, double *dst);
+
+/* ---- building blocks exposed for the pin tests ---- */
+/* equilibrium populations of one species, Eq.(4)/(6) (D2Q9) or the D3Q19 reading */
+int oracle_equilibrium(int lattice, double rho_j, double M_j, const double *u3, double T,
+                       double *f_out);
+/* source shapes: which = 0 psi_x, 1 psi_y, 2 psi_z, 3..8 pi_xx,yy,zz,xy,xz,yz,
+ * 9..11 chi_x,y,z, 12 phi (energy); unscaled (c_j = 1) */
+int oracle_shape(int lattice, int which, double *out);
+/* Lagrange weights of stencil class k (0..6) at shift s, taps at t = offsets */
+int oracle_interp_weights(int cls, double s, double *w3, int *t3, int *ntaps);
+/* lattice velocity table (c[i*3+a]), returns Q */
+int oracle_velocities(int lattice, int *c_out);
+/* lattice-minus-Maxwellian third moments Q'_aaa, Q'_xyz and energy flux R'_ab */
+int oracle_deviations(int lattice, double rho_j, double M_j, const double *u3, double T,
+                      double *Qaaa, double *Qxyz, double *R9);
+/* transport at a state: tau1[j], tau2[j] (Eq.(7-8), (14-17)) */
+int oracle_transport(oracle_sim *s, const double *rho, double T, double *tau1, double *tau2);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

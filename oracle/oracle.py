@@ -1,0 +1,225 @@
+"""ctypes wrapper around the FP64 CPU oracle (oracle/fdlbm_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+benchmark's CPU-baseline leg.  The product path never imports this module.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SOURCES = [os.path.join(HERE, "fdlbm_oracle.c")]
+
+MAXS = 8
+OF_RHO, OF_U, OF_T, OF_TS, OF_POP, OF_KIND, OF_WALL_R, OF_WALL_DE = range(8)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc into oracle/liboracle.so."""
+    if force or not os.path.exists(LIB_PATH):
+        cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall", "-o", LIB_PATH + ".tmp",
+               *SOURCES, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+class Obs(ct.Structure):
+    _fields_ = [("mass", ct.c_double * MAXS), ("e_gas", ct.c_double), ("e_solid", ct.c_double),
+                ("moles_reacted", ct.c_double), ("heat_released", ct.c_double),
+                ("heat_boundary", ct.c_double), ("work_body", ct.c_double),
+                ("T_min", ct.c_double), ("T_max", ct.c_double),
+                ("u_max", ct.c_double), ("rho_min", ct.c_double), ("Ts_min", ct.c_double),
+                ("Ts_max", ct.c_double), ("step", ct.c_int64), ("bad", ct.c_int32),
+                ("n_gas", ct.c_int32), ("n_wall", ct.c_int32), ("n_solid", ct.c_int32)]
+
+    def as_dict(self, ns: int) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "mass"}
+        d["mass"] = np.array(self.mass[:ns])
+        return d
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ct.CDLL(LIB_PATH)
+        dp = ct.POINTER(ct.c_double)
+        L.oracle_create.restype = ct.c_void_p
+        L.oracle_create.argtypes = [ct.c_int, ct.c_int, ct.c_int, ct.c_int,
+                                    ct.POINTER(ct.c_int), ct.c_int]
+        L.oracle_destroy.argtypes = [ct.c_void_p]
+        L.oracle_error.restype = ct.c_char_p
+        L.oracle_error.argtypes = [ct.c_void_p]
+        L.oracle_set_geometry.argtypes = [ct.c_void_p, ct.POINTER(ct.c_uint8), ct.c_int]
+        L.oracle_set_species.argtypes = [ct.c_void_p, dp, dp, ct.c_double, dp, ct.c_double,
+                                         ct.c_double, ct.c_double, ct.c_double, ct.c_double,
+                                         ct.c_uint]
+        L.oracle_set_solid.argtypes = [ct.c_void_p, ct.c_double, ct.c_double, dp]
+        L.oracle_set_reaction.argtypes = [ct.c_void_p, dp, dp, ct.c_double, ct.c_double,
+                                          ct.c_double, ct.c_double, ct.c_int, ct.c_double,
+                                          ct.c_double, ct.c_int]
+        L.oracle_set_flow.argtypes = [ct.c_void_p, dp, dp, ct.c_double, ct.c_double]
+        L.oracle_init_fields.argtypes = [ct.c_void_p, dp, dp, dp, dp]
+        L.oracle_step.argtypes = [ct.c_void_p, ct.c_int64]
+        L.oracle_observe.argtypes = [ct.c_void_p, ct.POINTER(Obs)]
+        L.oracle_get_field.argtypes = [ct.c_void_p, ct.c_int, ct.c_int, dp]
+        L.oracle_equilibrium.argtypes = [ct.c_int, ct.c_double, ct.c_double, dp, ct.c_double, dp]
+        L.oracle_shape.argtypes = [ct.c_int, ct.c_int, dp]
+        L.oracle_interp_weights.argtypes = [ct.c_int, ct.c_double, dp, ct.POINTER(ct.c_int),
+                                            ct.POINTER(ct.c_int)]
+        L.oracle_velocities.argtypes = [ct.c_int, ct.POINTER(ct.c_int)]
+        L.oracle_deviations.argtypes = [ct.c_int, ct.c_double, ct.c_double, dp, ct.c_double, dp,
+                                        dp, dp]
+        L.oracle_transport.argtypes = [ct.c_void_p, dp, ct.c_double, dp, dp]
+        _lib = L
+    return _lib
+
+
+def _d(a) -> ct.POINTER(ct.c_double):
+    return a.ctypes.data_as(ct.POINTER(ct.c_double))
+
+
+def _arr(x) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+
+
+# ---------------------------------------------------------------------------
+# building blocks
+# ---------------------------------------------------------------------------
+
+def velocities(lattice: int) -> np.ndarray:
+    c = (ct.c_int * 57)()
+    q = lib().oracle_velocities(lattice, c)
+    return np.array(c[:3 * q]).reshape(q, 3)
+
+
+def equilibrium(lattice: int, rho: float, M: float, u, T: float) -> np.ndarray:
+    q = 9 if lattice == 2 else 19
+    out = np.zeros(q)
+    u3 = _arr(list(u) + [0.0] * (3 - len(u)))
+    lib().oracle_equilibrium(lattice, rho, M, _d(u3), T, _d(out))
+    return out
+
+
+def deviations(lattice: int, rho: float, M: float, u, T: float):
+    q3, r9 = np.zeros(3), np.zeros(9)
+    qxyz = ct.c_double()
+    u3 = _arr(list(u) + [0.0] * (3 - len(u)))
+    lib().oracle_deviations(lattice, rho, M, _d(u3), T, _d(q3), ct.byref(qxyz), _d(r9))
+    return q3, qxyz.value, r9.reshape(3, 3)
+
+
+def shape(lattice: int, which: int) -> np.ndarray:
+    q = 9 if lattice == 2 else 19
+    out = np.zeros(q)
+    lib().oracle_shape(lattice, which, _d(out))
+    return out
+
+
+def interp_weights(cls: int, s: float):
+    w = np.zeros(3)
+    t = (ct.c_int * 3)()
+    m = ct.c_int()
+    lib().oracle_interp_weights(cls, s, _d(w), t, ct.byref(m))
+    return w[:m.value], list(t[:m.value])
+
+
+class OracleSim:
+    """One oracle simulation built from a workload dict (see workloads.py)."""
+
+    def __init__(self, cfg: dict, init: dict | None = None):
+        L = lib()
+        self.cfg = cfg
+        self.ns = len(cfg["species"]["M"])
+        self.nx, self.ny, self.nz = cfg["nx"], cfg["ny"], cfg["nz"]
+        self.n = self.nx * self.ny * self.nz
+        self.Q = 9 if cfg["lattice"] == 2 else 19
+        per = (ct.c_int * 3)(*[int(p) for p in cfg["periodic"]])
+        h = L.oracle_create(cfg["lattice"], self.nx, self.ny, self.nz, per, self.ns)
+        if not h:
+            raise ValueError("oracle_create failed")
+        self.h = h
+        mask = np.ascontiguousarray(np.asarray(cfg["mask"], dtype=np.uint8).reshape(-1))
+        self._check(L.oracle_set_geometry(h, mask.ctypes.data_as(ct.POINTER(ct.c_uint8)),
+                                          int(cfg.get("inout", 0))))
+        sp = cfg["species"]
+        M, mu0, Djk = _arr(sp["M"]), _arr(sp["mu0"]), _arr(sp["Djk0"]).reshape(-1)
+        self._check(L.oracle_set_species(h, _d(M), _d(mu0), sp["mu_T_exp"], _d(Djk), sp["D_T_exp"],
+                                         sp["D_p_exp"], sp["T_ref"], sp["p_ref"], sp["Pr"],
+                                         int(sp["flags"])))
+        so = cfg["solid"]
+        tbc = _arr(so["T_bc"])
+        self._check(L.oracle_set_solid(h, so["alpha_s"], so["C_s"], _d(tbc)))
+        rx = cfg["reaction"]
+        nu, order = _arr(rx["nu"]), _arr(rx["order"])
+        self._check(L.oracle_set_reaction(h, _d(nu), _d(order), rx["k0"], rx["ea"], rx["T_ref"],
+                                          rx["dH"], int(rx["wall_mode"]), rx["T_iso"], rx["tol"],
+                                          int(rx["max_iter"])))
+        fl = cfg["flow"]
+        F, Xin = _arr(fl["F"]), _arr(fl["X_in"])
+        self._check(L.oracle_set_flow(h, _d(F), _d(Xin), fl["p_in"], fl["T_in"]))
+        if init is not None:
+            self.init_fields(init)
+
+    def _check(self, rc: int):
+        if rc != 0:
+            raise ValueError(lib().oracle_error(self.h).decode())
+
+    def init_fields(self, init: dict):
+        rho, u = _arr(init["rho"]).reshape(-1), _arr(init["u"]).reshape(-1)
+        T, Ts = _arr(init["T"]), _arr(init["Ts"])
+        self._check(lib().oracle_init_fields(self.h, _d(rho), _d(u), _d(T), _d(Ts)))
+
+    def step(self, n: int = 1):
+        self._check(lib().oracle_step(self.h, int(n)))
+
+    def observe(self) -> dict:
+        o = Obs()
+        self._check(lib().oracle_observe(self.h, ct.byref(o)))
+        return o.as_dict(self.ns)
+
+    def field(self, fid: int, comp: int = 0) -> np.ndarray:
+        size = self.Q * self.n if fid == OF_POP else self.n
+        out = np.zeros(size)
+        self._check(lib().oracle_get_field(self.h, fid, comp, _d(out)))
+        return out
+
+    def transport(self, rho, T):
+        t1, t2 = np.zeros(self.ns), np.zeros(self.ns)
+        r = _arr(rho)
+        self._check(lib().oracle_transport(self.h, _d(r), T, _d(t1), _d(t2)))
+        return t1, t2
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().oracle_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+R_GAS = 8.314462618
+
+
+def lattice_units(dx_m: float, T0_K: float, M0_kg_per_mol: float) -> dict:
+    """Eq.(28)-(32): velocity scale U' = sqrt(3 R T0 / M0) (the lightest
+    species moves one lattice constant per step), length scale L' = dx,
+    time scale t' = L'/U', temperature scale T0/(1/3), mu' = D' = kappa' = L'U',
+    pressure scale U'^2, density scale 1."""
+    U = (3.0 * R_GAS * T0_K / M0_kg_per_mol) ** 0.5
+    return dict(U=U, L=dx_m, t=dx_m / U, T=T0_K / (1.0 / 3.0), mu=dx_m * U, D=dx_m * U,
+                kappa=dx_m * U, P=U * U, rho=1.0)
