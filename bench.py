@@ -1,0 +1,194 @@
+"""Throughput of the coupled FD-LBM step on one MI355X.
+
+Workload (default): the packed-bed configuration -- 128^3 D3Q19 lattice,
+random overlapping spheres of radius 6 (SplitMix64 seed 12345) at bed
+porosity 0.6, five gas species (CO, H2O, CO2, H2, N2) with water-gas-shift
+chemistry on the sphere surfaces, FD heat conduction in the solid, body-force
+flow with inlet/outlet planes, FP32 storage and arithmetic.  A "step" is one
+full time step of the method (wall BC, streaming, moments, collision with all
+corrections, solid FD, inlet/outlet).
+
+Prints ONE JSON line: MLUPS x species (gas nodes x species x steps / s / 1e6),
+the fraction of the HBM roofline of the dominant kernel measured with HIP
+events on the library's stream over the timed region, and the FP64 CPU oracle
+timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, 8 TB/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--n", type=int, default=128, help="bed edge length (nodes)")
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one device copy of this size first (counter calibration)")
+    ap.add_argument("--traffic-gb", type=float, default=None,
+                    help="measured HBM bytes per launch of the dominant kernel (GB), from rocprofv3")
+    return ap.parse_args()
+
+
+def algorithmic_bytes(n_gas, n_wall_links, n_solid, ns, Q, b):
+    """Per-step algorithmic bytes: every gas population read once and written
+    once, every wall link's populations read and written once, the solid
+    temperature read and written once."""
+    return n_gas * 2 * Q * ns * b + n_wall_links * 2 * ns * b + n_solid * 2 * b
+
+
+def cpu_baseline(cfg, init, steps):
+    """The FP64 oracle (single thread) on the same geometry and state: setup
+    excluded, `steps` full time steps timed."""
+    from oracle import oracle
+    oracle.build(force=not os.path.exists(oracle.LIB_PATH))
+    sim = oracle.OracleSim(cfg, init)
+    t0 = time.perf_counter()
+    sim.step(steps)
+    dt = time.perf_counter() - t0
+    o = sim.observe()
+    ns = len(cfg["species"]["M"])
+    val = o["n_gas"] * ns * steps / dt / 1e6
+    sim.close()
+    return dict(value=round(val, 4), unit="MLUPS*species", cores=1, kind="oracle",
+                sample=f"{steps} full step(s) of the same {cfg['nx']}x{cfg['ny']}x{cfg['nz']} "
+                       f"bed, FP64, one thread, {dt:.1f} s")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
+                                   "design-only (see DESIGN.md)", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1804_07588_amd import fdlbm, workloads as W
+
+    torch.cuda.set_device(0)
+    if args.calib_copy_mib:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters
+        # calibrate the traffic figures of the method's kernels
+        src = torch.ones(args.calib_copy_mib * 262144, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    mask, nsph = W.sphere_pack_mask(args.n, radius=6.0, porosity=0.6, seed=12345, buffer=8)
+    cfg = W.packed_bed(mask=mask)
+    init = W.uniform_init(cfg)
+    prec = fdlbm.F32 if args.precision == "f32" else fdlbm.F64
+    b = 4 if prec == fdlbm.F32 else 8
+    sim = fdlbm.Sim(cfg, precision=prec, init=init)
+    n_gas, n_wall, n_solid = sim.counts()
+    kind = sim.field(fdlbm.FIELD_KIND).astype(np.int64)
+    ns, Q = 5, 19
+    # wall links = incoming links of all wall nodes (each carries one population per species)
+    n_links = int(_count_wall_links(kind, cfg))
+    B_alg = algorithmic_bytes(n_gas, n_links, n_solid, ns, Q, b)
+
+    sim.step(args.warmup)
+    sim.sync()
+    sim.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    times, launches = sim.kernel_times()
+    sim.set_profiling(False)
+    obs = sim.observe()
+    if obs["bad"]:
+        print(json.dumps({"error": "non-finite or negative state after the timed run"}))
+        sys.exit(3)
+
+    ms_per_step = dt * 1e3 / args.steps
+    mlups_species = n_gas * ns * args.steps / dt / 1e6
+    # dominant kernel: the collision kernel reads every gas population once
+    # (through the interpolation taps) and writes it once
+    dom = max(times, key=times.get)
+    kernel_alg_bytes = {
+        "k_collide": n_gas * 2 * Q * ns * b,
+        "k_moments": n_gas * Q * ns * b,
+        "k_wall": n_links * 2 * ns * b,
+        "k_solid": n_solid * 2 * b,
+        "k_inout": 2 * cfg["ny"] * cfg["nz"] * 2 * Q * ns * b,
+    }
+    achieved = kernel_alg_bytes[dom] / (times[dom] * 1e-3) / 1e9
+    out = {
+        "metric": "MLUPS*species (gas nodes x species x steps / s / 1e6) and % of HBM peak",
+        "value": round(mlups_species, 2),
+        "unit": "MLUPS*species",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == fdlbm.F32 else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"packed bed {args.n}^3 D3Q19, spheres r=6 porosity 0.6 (seed 12345), "
+                        f"5 species WGS, FD solid, inlet/outlet, body force",
+            "nodes": int(cfg["nx"] * cfg["ny"] * cfg["nz"]), "gas_nodes": n_gas,
+            "wall_nodes": n_wall, "solid_nodes": n_solid, "wall_links": n_links,
+            "spheres": nsph, "species": ns,
+        },
+        "step_effective_GBs": round(B_alg * args.steps / dt / 1e9, 1),
+        "step_hbm_frac": round(B_alg * args.steps / dt / 1e9 / HBM_PEAK_GBS, 4),
+        "kernel_ms": {k: round(v, 5) for k, v in times.items()},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dom,
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": args.traffic_gb,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, init, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+def _count_wall_links(kind, cfg):
+    """Number of (wall node, incoming direction) pairs: links from a gas node
+    into a wall node."""
+    import numpy as np
+    nz, ny, nx = cfg["nz"], cfg["ny"], cfg["nx"]
+    k = kind.reshape(nz, ny, nx)
+    gas = (k == 0) | (k >= 3)
+    wall = k == 2
+    total = 0
+    moving = [(a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)
+              if 0 < a * a + b * b + c * c <= 2]
+    for cx, cy, cz in moving:
+        src = np.roll(gas, shift=(cz, cy, cx), axis=(0, 1, 2))
+        if cx != 0:
+            # x is closed: no wrap-around
+            if cx > 0:
+                src[:, :, :cx] = False
+            else:
+                src[:, :, cx:] = False
+        total += int(np.count_nonzero(wall & src))
+    return total
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,213 @@
+/*
+ * fdlbm.h -- C ABI of the MI355X (gfx950) implementation of the coupled
+ * finite-difference / lattice-Boltzmann step for catalytic reactive flow
+ * (Kulyk, Berger, Smith, Harting, "Catalytic flow with a coupled Finite
+ * Difference - Lattice Boltzmann scheme").
+ *
+ * One time step advances
+ *   - the gas: Kang et al.'s thermal multicomponent LBM, one population set per
+ *     species with species lattice speeds c_j = sqrt(M_0/M_j) (Eq.(2)), pull
+ *     streaming with the off-lattice interpolation of Eq.(33)-(36), the
+ *     two-step BGK collision in its trapezoidal form Eq.(24) with the moments
+ *     of Eq.(25), and the correction sources of Sec. 3 (diffusion velocity
+ *     Eq.(11)-(13), Prandtl number Eq.(19)-(21), lattice-deviation terms);
+ *   - the reactive diffusive wall on the solid nodes, Eq.(37)-(41) with the
+ *     rate law Eq.(50) and the reaction enthalpy Eq.(42);
+ *   - the solid: forward-Euler heat equation Eq.(45)-(47) coupled at the wall
+ *     nodes (Eq.(48), flux-matched form).
+ *
+ * Units: lattice units.  Masses relative to the lightest species (>= 1);
+ * the reference temperature is 1/3; pressure p = C T with C = sum rho_j/M_j.
+ *
+ * Memory: the caller allocates ONE device buffer (e.g. a torch tensor) of
+ * fdlbm_workspace_bytes() bytes, 256-byte aligned, and binds it; the library
+ * allocates no device memory of its own and never frees the caller's buffer.
+ * All kernels run on the stream given at creation (NULL = default stream).
+ * Host arrays passed in are copied before the call returns.
+ *
+ * Errors: every int-returning call returns FDLBM_OK (0) or a negative code;
+ * fdlbm_last_error() gives a message.  No exception crosses the ABI.
+ * Thread-compatible: one context per host thread.
+ *
+ * Layouts: node index = x + nx*(y + ny*z).  Populations of species j and
+ * direction i live at [(j*Q + i)*n + node] (structure of arrays).  Direction
+ * order: D2Q9 as Eq.(2) (rest, +x, +y, -x, -y, (1,1), (-1,1), (-1,-1), (1,-1));
+ * D3Q19 rest, +x, -x, +y, -y, +z, -z, then the xy, xz, yz edges, each in the
+ * order (+,+), (-,+), (-,-), (+,-).
+ */
+#ifndef FDLBM_H
+#define FDLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define FDLBM_OK 0
+#define FDLBM_E_INVALID -1   /* bad argument or parameter out of range        */
+#define FDLBM_E_GEOMETRY -2  /* mask rejected (no gas, gas on a closed edge)  */
+#define FDLBM_E_ALIGN -3     /* workspace too small or not 256-byte aligned   */
+#define FDLBM_E_HIP -4       /* a HIP runtime call failed                     */
+#define FDLBM_E_UNSTABLE -5  /* NaN/Inf, negative density or temperature seen  */
+#define FDLBM_E_STATE -6     /* call made out of order                        */
+
+/* lattices and precisions */
+#define FDLBM_D2Q9 2
+#define FDLBM_D3Q19 3
+#define FDLBM_F64 0
+#define FDLBM_F32 1
+
+/* correction-term switches (Sec. 3 / Sec. 4.1) */
+#define FDLBM_CORR_DIFFUSION 1u  /* diffusion-velocity correction, Eq.(11)-(13)  */
+#define FDLBM_CORR_VISCOUS 2u    /* third-moment lattice-deviation correction    */
+#define FDLBM_CORR_ENERGY 4u     /* energy-flux lattice-deviation correction     */
+#define FDLBM_CORR_PRANDTL 8u    /* variable Prandtl number, Eq.(19)-(21)        */
+#define FDLBM_CORR_ALL 15u
+
+/* wall modes */
+#define FDLBM_WALL_REACTIVE 0   /* T_w = solid temperature, heat exchanged (Sec. 5) */
+#define FDLBM_WALL_ISOTHERMAL 1 /* fixed T_w, no exchange with the solid (prior art) */
+
+/* field ids for fdlbm_get_field */
+#define FDLBM_FIELD_RHO 0     /* species density (comp = species)              */
+#define FDLBM_FIELD_U 1       /* mixture velocity (comp = axis)                */
+#define FDLBM_FIELD_T 2       /* gas temperature                               */
+#define FDLBM_FIELD_TS 3      /* solid temperature                             */
+#define FDLBM_FIELD_POP 4     /* stored populations of species comp (Q*n)      */
+#define FDLBM_FIELD_KIND 5    /* node class: 0 gas 1 solid 2 wall 3 inlet 4 outlet */
+#define FDLBM_FIELD_WALL_R 6  /* molar rate per wall node in the last step      */
+#define FDLBM_FIELD_WALL_DE 7 /* kinetic energy the wall gave the gas, last step */
+
+#define FDLBM_MAX_SPECIES 8
+
+typedef struct fdlbm_ctx fdlbm_ctx;
+
+typedef struct {
+  int lattice;      /* FDLBM_D2Q9 or FDLBM_D3Q19                                 */
+  int nx, ny, nz;   /* grid; nz = 1 for D2Q9                                    */
+  int periodic[3];  /* nonzero: axis wraps                                      */
+  int precision;    /* FDLBM_F64 or FDLBM_F32 (storage and arithmetic)          */
+  int n_species;    /* 1 .. FDLBM_MAX_SPECIES                                   */
+  void *hip_stream; /* hipStream_t to run on; NULL = default stream             */
+} fdlbm_desc;
+
+typedef struct {
+  double mass[FDLBM_MAX_SPECIES]; /* per-species gas mass incl. wall-emitted pops */
+  double e_gas;          /* (1/2) sum_j sum_i c_ji^2 g over gas + wall-emitted pops */
+  double e_solid;        /* sum over solid nodes of C_s T^s                         */
+  double moles_reacted;  /* cumulative reaction extent, sum over steps and walls    */
+  double heat_released;  /* cumulative -dH * moles_reacted (Eq.(42))               */
+  double heat_boundary;  /* cumulative heat into the solid through Dirichlet faces */
+  double work_body;      /* cumulative work of the body force on the gas          */
+  double T_min, T_max, u_max, rho_min;
+  double Ts_min, Ts_max;
+  int64_t step;
+  int32_t bad;           /* 1 if NaN/Inf, negative density or temperature seen    */
+  int32_t n_gas, n_wall, n_solid;
+} fdlbm_obs;
+
+/* Create a context (no device memory yet).  *out owned by the caller until
+ * fdlbm_destroy.  Errors: FDLBM_E_INVALID on bad sizes or counts. */
+int fdlbm_create(const fdlbm_desc *d, fdlbm_ctx **out);
+
+/* Release the context.  Does not free the caller's workspace. */
+void fdlbm_destroy(fdlbm_ctx *ctx);
+
+/* Message of the last error on this context (static storage of ctx). */
+const char *fdlbm_last_error(const fdlbm_ctx *ctx);
+
+/* Geometry (Sec. 4.3, wall on the first solid node): mask_host[n] with 0 =
+ * gas, 1 = solid, copied.  Wall nodes are the solid nodes with a gas node
+ * among their lattice neighbours.  inout = 1 turns the planes x = 0, 1 into
+ * inlet nodes (equilibrium at the inlet state, Sec. 6) and x = nx-2, nx-1
+ * into outlet nodes (zero-gradient copy); x must then be non-periodic and
+ * those planes gas.  FDLBM_E_GEOMETRY if no gas node exists or a gas node
+ * touches a closed domain edge. */
+int fdlbm_set_geometry(fdlbm_ctx *ctx, const uint8_t *mask_host, int inout);
+
+/* Species and transport (Sec. 3, Eq.(7)-(8), (14)-(17), (19)-(21)):
+ * M[j] relative masses (>= 1); mu0[j] viscosities at T_ref, mu_j = mu0_j
+ * (T/T_ref)^mu_T_exp; Djk0[j*ns+k] symmetric binary diffusivities at
+ * (T_ref, p_ref), D_jk = Djk0 (T/T_ref)^D_T_exp (p_ref/p)^D_p_exp; Pr the
+ * Prandtl number; corr_flags a mask of FDLBM_CORR_*.  Copied. */
+int fdlbm_set_species(fdlbm_ctx *ctx, const double *M, const double *mu0, double mu_T_exp,
+                      const double *Djk0, double D_T_exp, double D_p_exp, double T_ref,
+                      double p_ref, double Pr, unsigned corr_flags);
+
+/* Solid (Eq.(45)-(47)): thermal diffusivity alpha_s (0 <= alpha_s <= 1/(2D),
+ * the forward-Euler bound, else FDLBM_E_INVALID), volumetric heat capacity
+ * C_s > 0, and T_bc6[6] Dirichlet temperatures of the closed domain faces
+ * (-x, +x, -y, +y, -z, +z; NaN = adiabatic; NULL = all adiabatic). */
+int fdlbm_set_solid(fdlbm_ctx *ctx, double alpha_s, double C_s, const double *T_bc6);
+
+/* Surface reaction (Eq.(50) generalised): molar rate per wall node and step
+ * r = k0 exp[ea (1 - T_ref/T_w)] prod_j C_jw^order_j, species j produced at
+ * nu_j per unit extent (nu < 0 reactants); orders must be integers 0..3.
+ * dH reaction enthalpy per unit extent (< 0 exothermic), Eq.(42).
+ * wall_mode FDLBM_WALL_*; T_iso the wall temperature in isothermal mode;
+ * tol / max_iter bound the wall-density fixed point of Sec. 4.3. */
+int fdlbm_set_reaction(fdlbm_ctx *ctx, const double *nu, const double *order, double k0,
+                       double ea, double T_ref, double dH, int wall_mode, double T_iso,
+                       double tol, int max_iter);
+
+/* Flow: body force per unit mass F3[3]; inlet mole fractions X_in[ns],
+ * pressure p_in and temperature T_in (used when inout = 1). */
+int fdlbm_set_flow(fdlbm_ctx *ctx, const double *F3, const double *X_in, double p_in,
+                   double T_in);
+
+/* Device bytes the caller must provide (valid after fdlbm_create). */
+int fdlbm_workspace_bytes(const fdlbm_ctx *ctx, size_t *bytes);
+
+/* Bind the caller's device buffer (>= fdlbm_workspace_bytes, 256-byte
+ * aligned, else FDLBM_E_ALIGN).  Requires the geometry; uploads it. */
+int fdlbm_bind_workspace(fdlbm_ctx *ctx, void *dev_ptr, size_t bytes);
+
+/* Initial state from host arrays: rho[j*n + node], u[a*n + node] (3 rows),
+ * T[n], Ts[n].  Gas populations are set to f^eq (Eq.(4)); wall nodes emit
+ * rho_w f^eq(1, 0, T_w) with rho_w the mean density of their gas partners.
+ * Resets the step counter and the cumulative counters. */
+int fdlbm_init_fields(fdlbm_ctx *ctx, const double *rho, const double *u, const double *T,
+                      const double *Ts);
+
+/* Enqueue n_steps time steps on the context's stream (asynchronous). */
+int fdlbm_step(fdlbm_ctx *ctx, int64_t n_steps);
+
+/* Wait for the stream. */
+int fdlbm_sync(fdlbm_ctx *ctx);
+
+/* Synchronise and reduce the observables (FP64, deterministic order). */
+int fdlbm_observe(fdlbm_ctx *ctx, fdlbm_obs *out);
+
+/* Copy a field into dst_host (double): n values, or Q*n for FDLBM_FIELD_POP.
+ * RHO/U/T are the moments of f of the last step at gas nodes (the wall state
+ * at wall nodes, 0 elsewhere); valid after at least one step. */
+int fdlbm_get_field(fdlbm_ctx *ctx, int field, int comp, double *dst_host);
+
+/* Checkpoint: bytes needed, save to / restore from a host buffer (bitwise). */
+int fdlbm_state_bytes(const fdlbm_ctx *ctx, size_t *bytes);
+int fdlbm_save_state(fdlbm_ctx *ctx, void *host_buf, size_t bytes);
+int fdlbm_load_state(fdlbm_ctx *ctx, const void *host_buf, size_t bytes);
+
+/* Timing of the last fdlbm_step call's gas collision kernel on its stream,
+ * when enabled with fdlbm_set_profiling(ctx, 1): per-kernel average duration
+ * in milliseconds over the recorded launches (kernel ids below). */
+#define FDLBM_K_WALL 0
+#define FDLBM_K_MOMENTS 1
+#define FDLBM_K_COLLIDE 2
+#define FDLBM_K_SOLID 3
+#define FDLBM_K_INOUT 4
+#define FDLBM_K_COUNT 5
+int fdlbm_set_profiling(fdlbm_ctx *ctx, int enable);
+int fdlbm_kernel_times(fdlbm_ctx *ctx, double *avg_ms, int64_t *launches);
+
+/* Node counts after fdlbm_set_geometry: gas (incl. inlet/outlet), wall,
+ * solid (incl. wall). */
+int fdlbm_counts(const fdlbm_ctx *ctx, int64_t *n_gas, int64_t *n_wall, int64_t *n_solid);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -773,6 +773,11 @@ static void wall_bc(oracle_sim *s) {
      * The paper's fixed-point iteration for rho_w, started here from the
      * non-reactive wall density A_j / Z; each pass treats a reactant's own
      * concentration implicitly (rho_j = A_j / (Z + |nu_j| r / C_j)). */
+    /* reading: S_j of Eq.(50) is a flux per unit wall area, so a wall node
+     * reacts in proportion to its wetted area, measured by its equilibrium
+     * emission Z relative to that of a flat lattice wall, which is T_w / 2
+     * on both lattices (area factor exactly 1 on the paper's planar walls) */
+    double area = Z / (0.5 * Tw);
     double rw[MAXS];
     for (int j = 0; j < ns; ++j) rw[j] = A[j] / Z;
     for (int it = 0; it < s->max_iter; ++it) {
@@ -781,7 +786,7 @@ static void wall_bc(oracle_sim *s) {
         nw[j] = rw[j];
         if (s->nu[j] < 0.0 && s->order[j] > 0.0) {
           /* r / C_j with C_j's own power lowered by one */
-          double R = s->k0 * exp(s->ea * (1.0 - s->T_ref_rxn / Tw));
+          double R = area * s->k0 * exp(s->ea * (1.0 - s->T_ref_rxn / Tw));
           for (int m = 0; m < ns; ++m) {
             double o = s->order[m] - (m == j ? 1.0 : 0.0);
             if (o != 0.0) R *= pow(rw[m] / s->M[m], o);
@@ -794,7 +799,7 @@ static void wall_bc(oracle_sim *s) {
       for (int j = 0; j < ns; ++j) rw[j] = nw[j];
       if (dmax <= s->tol) break;
     }
-    double r = rate(s, rw, Tw);
+    double r = area * rate(s, rw, Tw);
     /* final wall densities from the exact mass balance at the final rate */
     for (int j = 0; j < ns; ++j) rw[j] = (A[j] + s->nu[j] * s->M[j] * r) / Z;
     double Eout = 0.0;

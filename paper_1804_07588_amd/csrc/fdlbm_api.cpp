@@ -1,0 +1,818 @@
+// Host side of the C ABI declared in include/fdlbm.h: parameter validation,
+// geometry pre-processing (node classes, streaming stencil classes, node
+// lists), workspace layout, initial state, step scheduling, observables,
+// field export and checkpoints.  All device work runs on the caller's stream.
+#include "fdlbm.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fdlbm_device.h"
+#include "fdlbm_launch.h"
+
+using namespace fdlbm;
+
+namespace {
+constexpr int NPROF = 4096;  // event pairs kept per kernel when profiling
+}
+
+struct fdlbm_ctx {
+  fdlbm_desc d{};
+  int D = 2, Q = 9, ns = 1, n = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  // parameters (double on the host)
+  double M[MAXS]{}, mu0[MAXS]{}, mu_T_exp = 0, Djk0[MAXS * MAXS]{}, D_T_exp = 0, D_p_exp = 0,
+         T_ref = 1.0 / 3, p_ref = 1.0 / 3, Pr = 1;
+  unsigned flags = FDLBM_CORR_ALL;
+  double alpha_s = 0, C_s = 1, T_bc[6];
+  double nu[MAXS]{}, order[MAXS]{}, k0 = 0, ea = 0, T_ref_rxn = 1.0 / 3, dH = 0, T_iso = 1.0 / 3,
+         tol = 1e-13;
+  int wall_mode = 0, max_iter = 64;
+  double F[3]{}, X_in[MAXS]{}, p_in = 1.0 / 3, T_in = 1.0 / 3;
+  bool species_set = false, geometry_set = false, bound = false, initialized = false;
+  // geometry
+  int inout = 0;
+  std::vector<uint8_t> kind;
+  std::vector<uint64_t> cls;
+  std::vector<uint32_t> emask, gas_list, wall_list;
+  int64_t n_gas_fast = 0, n_wall_fast = 0;
+  int64_t n_solid = 0;
+  // workspace
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  size_t off_G[2]{}, off_Gs = 0, off_F = 0, off_Ts[2]{}, off_wr = 0, off_wde = 0, off_kind = 0, off_cls = 0,
+         off_em = 0, off_gl = 0, off_wl = 0, off_am = 0, off_aw = 0, off_ab = 0, off_part = 0;
+  size_t total = 0;
+  int acc_slots = 0, obs_blocks = 0;
+  int cur = 0;
+  int64_t step = 0;
+  // profiling
+  bool prof = false;
+  std::vector<hipEvent_t> events;  // [launch][kernel][2]
+  int64_t prof_launches = 0;
+  bool prof_recorded[K_NUM]{};  // kernel ids whose events the step records
+};
+
+static int set_err(fdlbm_ctx *c, int code, const char *fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return code;
+}
+
+#define HIPCHK(c, call)                                                                     \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) return set_err(c, FDLBM_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+static size_t real_size(const fdlbm_ctx *c) { return c->d.precision == FDLBM_F64 ? 8 : 4; }
+
+static void layout(fdlbm_ctx *c) {
+  const size_t b = real_size(c), n = (size_t)c->n;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  const size_t pops = (size_t)c->ns * c->Q * n * b;
+  c->off_G[0] = take(pops);
+  c->off_G[1] = take(pops);
+  c->off_Gs = take(pops);
+  c->off_F = take((size_t)n_fields(c->D, c->ns) * n * b);
+  c->off_Ts[0] = take(n * b);
+  c->off_Ts[1] = take(n * b);
+  c->off_wr = take(n * b);
+  c->off_wde = take(n * b);
+  c->off_kind = take(n);
+  c->off_cls = take(n * 8);
+  c->off_em = take(n * 4);
+  c->off_gl = take(n * 4);
+  c->off_wl = take(n * 4);
+  // one accumulator slot per block of the largest grid that accumulates
+  const int tiles = c->D == 2 ? solid_tiles<2>(c->d.nx, c->d.ny, c->d.nz)
+                              : solid_tiles<3>(c->d.nx, c->d.ny, c->d.nz);
+  c->acc_slots = std::max((int)((n + BLOCK - 1) / BLOCK), tiles) + 8;
+  c->off_am = take((size_t)c->acc_slots * 8);
+  c->off_aw = take((size_t)c->acc_slots * 8);
+  c->off_ab = take((size_t)c->acc_slots * 8);
+  c->obs_blocks = 1024;
+  c->off_part = take((size_t)c->obs_blocks * (MAXS + 9) * 8);
+  c->total = o;
+}
+
+template <typename real>
+static Bufs<real> bufs(const fdlbm_ctx *c) {
+  Bufs<real> b;
+  char *w = c->ws;
+  b.G[0] = (real *)(w + c->off_G[0]);
+  b.G[1] = (real *)(w + c->off_G[1]);
+  b.Gs = (real *)(w + c->off_Gs);
+  b.F = (real *)(w + c->off_F);
+  b.Ts[0] = (real *)(w + c->off_Ts[0]);
+  b.Ts[1] = (real *)(w + c->off_Ts[1]);
+  b.wall_r = (real *)(w + c->off_wr);
+  b.wall_dE = (real *)(w + c->off_wde);
+  b.kind = (const uint8_t *)(w + c->off_kind);
+  b.cls = (const uint64_t *)(w + c->off_cls);
+  b.emask = (const uint32_t *)(w + c->off_em);
+  b.gas_list = (const uint32_t *)(w + c->off_gl);
+  b.wall_list = (const uint32_t *)(w + c->off_wl);
+  b.acc_moles = (double *)(w + c->off_am);
+  b.acc_work = (double *)(w + c->off_aw);
+  b.acc_bheat = (double *)(w + c->off_ab);
+  b.partials = (double *)(w + c->off_part);
+  return b;
+}
+
+// Streaming weights of each stencil class at shift s (quadratic or degraded
+// Lagrange interpolation through the class's taps), in the tap order of
+// stencil_off().
+static void class_weights(double s, double w[7][3]) {
+  w[0][0] = 0.5 * s * (s - 1.0);
+  w[0][1] = 1.0 - s * s;
+  w[0][2] = 0.5 * s * (s + 1.0);
+  w[1][0] = 0.5 * (1.0 - s) * (2.0 - s);
+  w[1][1] = s * (2.0 - s);
+  w[1][2] = 0.5 * s * (s - 1.0);
+  w[2][0] = 0.5 * (1.0 + s) * (2.0 + s);
+  w[2][1] = -s * (2.0 + s);
+  w[2][2] = 0.5 * s * (1.0 + s);
+  w[3][0] = 1.0 - s;
+  w[3][1] = s;
+  w[3][2] = 0;
+  w[4][0] = -s;
+  w[4][1] = 1.0 + s;
+  w[4][2] = 0;
+  w[5][0] = 1.0;
+  w[5][1] = w[5][2] = 0;
+  w[6][0] = 1.0;
+  w[6][1] = w[6][2] = 0;
+}
+
+template <typename real>
+static Params<real> params(const fdlbm_ctx *c) {
+  Params<real> p;
+  std::memset(&p, 0, sizeof p);
+  p.ns = c->ns;
+  p.nx = c->d.nx;
+  p.ny = c->d.ny;
+  p.nz = c->d.nz;
+  p.n = c->n;
+  for (int a = 0; a < 3; ++a) p.per[a] = c->d.periodic[a] ? 1 : 0;
+  if (c->D == 2) p.per[2] = 1;
+  p.inout = c->inout;
+  p.flags = c->flags;
+  p.wall_mode = c->wall_mode;
+  p.n_gas = (int)c->gas_list.size();
+  p.n_wall = (int)c->wall_list.size();
+  p.n_ghost_cols = c->inout ? c->d.ny * c->d.nz : 0;
+  p.n_gas_fast = (int)c->n_gas_fast;
+  p.n_wall_fast = (int)c->n_wall_fast;
+  p.slot_off_gas = (int)((c->n_gas_fast + BLOCK - 1) / BLOCK);
+  p.slot_off_wall = (int)((c->n_wall_fast + BLOCK - 1) / BLOCK);
+  for (int j = 0; j < c->ns; ++j) {
+    const double cj = std::sqrt(1.0 / c->M[j]);
+    p.M[j] = (real)c->M[j];
+    p.invM[j] = (real)(1.0 / c->M[j]);
+    p.sqM[j] = (real)std::sqrt(c->M[j]);
+    p.cj[j] = (real)cj;
+    p.cj2[j] = (real)(1.0 / c->M[j]);
+    p.invcj[j] = (real)std::sqrt(c->M[j]);
+    p.onlat[j] = c->M[j] == 1.0;
+    double w[7][3];
+    class_weights(1.0 - cj, w);
+    for (int k = 0; k < 7; ++k)
+      for (int q = 0; q < 3; ++q) p.wint[j][k][q] = (real)w[k][q];
+    p.mu0[j] = (real)c->mu0[j];
+    p.nu[j] = (real)c->nu[j];
+    p.order[j] = (int)c->order[j];
+    p.rho_in[j] = (real)(c->M[j] * c->X_in[j] * c->p_in / c->T_in);
+  }
+  // Wilke's phi_jk, Eq.(15) with the square of the bracket (phi_jj = 1); the
+  // viscosity ratios are temperature independent (common exponent)
+  for (int j = 0; j < c->ns; ++j)
+    for (int k = 0; k < c->ns; ++k) {
+      const double br = 1.0 + std::sqrt(c->mu0[j] / c->mu0[k]) * std::pow(c->M[k] / c->M[j], 0.25);
+      p.wilke[j][k] = (real)(br * br / (std::sqrt(8.0) * std::sqrt(1.0 + c->M[j] / c->M[k])));
+      p.invD0[j][k] = j == k ? real(0) : (real)(1.0 / c->Djk0[j * c->ns + k]);
+    }
+  p.mu_T_exp = (real)c->mu_T_exp;
+  p.D_T_exp = (real)c->D_T_exp;
+  p.D_p_exp = (real)c->D_p_exp;
+  p.T_ref = (real)c->T_ref;
+  p.p_ref = (real)c->p_ref;
+  p.kpr = (real)((c->D + 2.0) * (1.0 / c->Pr - 1.0));
+  p.alpha_s = (real)c->alpha_s;
+  p.C_s = (real)c->C_s;
+  p.invCs = (real)(1.0 / c->C_s);
+  for (int a = 0; a < 6; ++a) {
+    p.has_bc[a] = !std::isnan(c->T_bc[a]);
+    p.T_bc[a] = p.has_bc[a] ? (real)c->T_bc[a] : real(0);
+  }
+  p.k0 = (real)c->k0;
+  p.ea = (real)c->ea;
+  p.T_ref_rxn = (real)c->T_ref_rxn;
+  p.dH = (real)c->dH;
+  p.T_iso = (real)c->T_iso;
+  p.tol = (real)std::max(c->tol, c->d.precision == FDLBM_F64 ? 0.0 : 4.0 * 1.1920929e-7);
+  p.max_iter = c->max_iter;
+  for (int a = 0; a < 3; ++a) p.F[a] = a < c->D ? (real)c->F[a] : real(0);
+  p.T_in = (real)c->T_in;
+  return p;
+}
+
+// ---------------------------------------------------------------------------
+// geometry pre-processing
+// ---------------------------------------------------------------------------
+static void lattice_c(int D, int i, int *cv) {
+  for (int a = 0; a < 3; ++a) cv[a] = D == 2 ? cvec<2>(i, a) : cvec<3>(i, a);
+}
+
+// node + k e_i, or -1 beyond a closed axis
+static int shifted(const fdlbm_ctx *c, int node, int i, int k) {
+  int cv[3];
+  lattice_c(c->D, i, cv);
+  const int lim[3] = {c->d.nx, c->d.ny, c->d.nz};
+  int p[3] = {node % lim[0], (node / lim[0]) % lim[1], node / (lim[0] * lim[1])};
+  for (int a = 0; a < 3; ++a) {
+    p[a] += k * cv[a];
+    if (p[a] < 0 || p[a] >= lim[a]) {
+      const bool per = a == 2 && c->D == 2 ? true : c->d.periodic[a] != 0;
+      if (!per) return -1;
+      p[a] = ((p[a] % lim[a]) + lim[a]) % lim[a];
+    }
+  }
+  return p[0] + lim[0] * (p[1] + lim[1] * p[2]);
+}
+
+int fdlbm_set_geometry(fdlbm_ctx *c, const uint8_t *mask, int inout) {
+  if (!c || !mask) return set_err(c, FDLBM_E_INVALID, "null argument");
+  if (c->bound) return set_err(c, FDLBM_E_STATE, "geometry must be set before binding the workspace");
+  const int nx = c->d.nx, n = c->n, Q = c->Q;
+  if (inout && (c->d.periodic[0] || nx < 6))
+    return set_err(c, FDLBM_E_GEOMETRY, "inlet/outlet needs a closed x axis of at least 6 nodes");
+  c->inout = inout ? 1 : 0;
+  c->kind.assign(n, KIND_GAS);
+  for (int node = 0; node < n; ++node) {
+    const int x = node % nx;
+    if (mask[node] > 1) return set_err(c, FDLBM_E_GEOMETRY, "mask values must be 0 or 1");
+    const bool ghost_in = c->inout && x <= 1, ghost_out = c->inout && x >= nx - 2;
+    if (mask[node] == 0) {
+      c->kind[node] = ghost_in ? KIND_INLET : (ghost_out ? KIND_OUTLET : KIND_GAS);
+    } else {
+      if (ghost_in || ghost_out) return set_err(c, FDLBM_E_GEOMETRY, "inlet/outlet planes must be gas");
+      c->kind[node] = KIND_SOLID;
+    }
+  }
+  int64_t ngas = 0;
+  for (int node = 0; node < n; ++node) {
+    if (gaslike(c->kind[node])) {
+      ++ngas;
+      if (c->kind[node] == KIND_GAS)
+        for (int i = 1; i < Q; ++i)
+          if (shifted(c, node, i, 1) < 0)
+            return set_err(c, FDLBM_E_GEOMETRY, "gas node %d touches a closed domain edge", node);
+      continue;
+    }
+    for (int i = 1; i < Q; ++i) {
+      const int y = shifted(c, node, i, 1);
+      if (y >= 0 && gaslike(c->kind[y])) {
+        c->kind[node] = KIND_WALL;
+        break;
+      }
+    }
+  }
+  if (ngas == 0) return set_err(c, FDLBM_E_GEOMETRY, "no gas node");
+  // emission masks: gas emits along every direction, a wall node along the
+  // directions that lead into the gas
+  c->emask.assign(n, 0u);
+  for (int node = 0; node < n; ++node) {
+    const uint8_t k = c->kind[node];
+    if (gaslike(k)) c->emask[node] = (1u << Q) - 1u;
+    else if (k == KIND_WALL)
+      for (int i = 1; i < Q; ++i) {
+        const int y = shifted(c, node, i, 1);
+        if (y >= 0 && gaslike(c->kind[y])) c->emask[node] |= 1u << i;
+      }
+  }
+  auto emits = [&](int y, int i) { return y >= 0 && ((c->emask[y] >> i) & 1u); };
+  // stencil class of each (destination, direction): the first of central,
+  // forward, backward, two-point, two-point, one-point, one-point whose taps
+  // all emit along the direction (Eq.(34)-(36) and their degraded forms)
+  c->cls.assign(n, ~uint64_t(0));
+  c->gas_list.clear();
+  c->wall_list.clear();
+  c->n_solid = 0;
+  for (int node = 0; node < n; ++node) {
+    const uint8_t k = c->kind[node];
+    if (k == KIND_SOLID || k == KIND_WALL) ++c->n_solid;
+    if (!(gaslike(k) || k == KIND_WALL)) continue;
+    uint64_t w = 0;
+    for (int i = 1; i < Q; ++i) {
+      int cl = CLS_NONE;
+      const bool dest = gaslike(k) || (k == KIND_WALL && [&] {
+                          const int y = shifted(c, node, i, -1);
+                          return y >= 0 && gaslike(c->kind[y]);
+                        }());
+      if (dest) {
+        for (int cand = 0; cand < 7; ++cand) {
+          bool ok = true;
+          for (int q = 0; q < stencil_ntaps(cand) && ok; ++q)
+            ok = emits(shifted(c, node, i, stencil_off(cand, q)), i);
+          if (ok) {
+            cl = cand;
+            break;
+          }
+        }
+        if (cl == CLS_NONE) return set_err(c, FDLBM_E_GEOMETRY, "no stencil at node %d", node);
+      }
+      w |= uint64_t(cl) << (3 * (i - 1));
+    }
+    c->cls[node] = w;
+    if (gaslike(k)) c->gas_list.push_back((uint32_t)node);
+    else c->wall_list.push_back((uint32_t)node);
+  }
+  // order each list: nodes whose taps (up to 3 nodes away) never wrap a
+  // periodic axis first, so the kernels for them use plain strides
+  auto no_wrap = [&](uint32_t node) {
+    const int lim[3] = {c->d.nx, c->d.ny, c->d.nz};
+    const int q[3] = {(int)(node % lim[0]), (int)((node / lim[0]) % lim[1]), (int)(node / (lim[0] * lim[1]))};
+    for (int a = 0; a < c->D; ++a)
+      if (c->d.periodic[a] && (q[a] < 3 || q[a] >= lim[a] - 3)) return false;
+    return true;
+  };
+  auto split = [&](std::vector<uint32_t> &v) {
+    auto mid = std::stable_partition(v.begin(), v.end(), no_wrap);
+    return (int64_t)(mid - v.begin());
+  };
+  c->n_gas_fast = split(c->gas_list);
+  c->n_wall_fast = split(c->wall_list);
+  c->geometry_set = true;
+  return FDLBM_OK;
+}
+
+template <typename real>
+static int copy_field(fdlbm_ctx *c, size_t off_bytes, size_t count, double *dst) {
+  std::vector<real> tmp(count);
+  HIPCHK(c, hipMemcpyAsync(tmp.data(), c->ws + off_bytes, count * sizeof(real), hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (size_t k = 0; k < count; ++k) dst[k] = (double)tmp[k];
+  return FDLBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+// The public functions take C linkage from their declarations in fdlbm.h.
+
+int fdlbm_create(const fdlbm_desc *d, fdlbm_ctx **out) {
+  if (!d || !out) return FDLBM_E_INVALID;
+  *out = nullptr;
+  if ((d->lattice != FDLBM_D2Q9 && d->lattice != FDLBM_D3Q19) || d->nx < 1 || d->ny < 1 ||
+      d->nz < 1 || (d->lattice == FDLBM_D2Q9 && d->nz != 1) || d->n_species < 1 ||
+      d->n_species > MAX_NS || (d->precision != FDLBM_F64 && d->precision != FDLBM_F32))
+    return FDLBM_E_INVALID;
+  const double nn = (double)d->nx * d->ny * d->nz;
+  if (nn > 2.0e9 || nn * d->n_species * 19 > 9.0e18) return FDLBM_E_INVALID;
+  fdlbm_ctx *c = new fdlbm_ctx();
+  c->d = *d;
+  c->D = d->lattice;
+  c->Q = d->lattice == FDLBM_D2Q9 ? 9 : 19;
+  c->ns = d->n_species;
+  c->n = d->nx * d->ny * d->nz;
+  c->stream = (hipStream_t)d->hip_stream;
+  for (int a = 0; a < 6; ++a) c->T_bc[a] = NAN;
+  layout(c);
+  *out = c;
+  return FDLBM_OK;
+}
+
+void fdlbm_destroy(fdlbm_ctx *c) {
+  if (!c) return;
+  for (auto &e : c->events) (void)hipEventDestroy(e);
+  delete c;
+}
+
+const char *fdlbm_last_error(const fdlbm_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int fdlbm_set_species(fdlbm_ctx *c, const double *M, const double *mu0, double mu_T_exp,
+                      const double *Djk0, double D_T_exp, double D_p_exp, double T_ref,
+                      double p_ref, double Pr, unsigned flags) {
+  if (!c || !M || !mu0 || !Djk0) return set_err(c, FDLBM_E_INVALID, "null argument");
+  for (int j = 0; j < c->ns; ++j) {
+    if (!(M[j] >= 1.0) || !std::isfinite(M[j]))
+      return set_err(c, FDLBM_E_INVALID, "masses are relative to the lightest species (>= 1)");
+    if (!(mu0[j] > 0.0)) return set_err(c, FDLBM_E_INVALID, "viscosities must be positive");
+    for (int k = 0; k < c->ns; ++k) {
+      if (j != k && !(Djk0[j * c->ns + k] > 0.0))
+        return set_err(c, FDLBM_E_INVALID, "binary diffusivities must be positive");
+      if (j != k && Djk0[j * c->ns + k] != Djk0[k * c->ns + j])
+        return set_err(c, FDLBM_E_INVALID, "binary diffusivities must be symmetric");
+    }
+  }
+  if (!(T_ref > 0 && p_ref > 0 && Pr > 0)) return set_err(c, FDLBM_E_INVALID, "T_ref, p_ref, Pr must be positive");
+  if (flags & ~FDLBM_CORR_ALL) return set_err(c, FDLBM_E_INVALID, "unknown correction flag");
+  for (int j = 0; j < c->ns; ++j) {
+    c->M[j] = M[j];
+    c->mu0[j] = mu0[j];
+    for (int k = 0; k < c->ns; ++k) c->Djk0[j * c->ns + k] = Djk0[j * c->ns + k];
+  }
+  c->mu_T_exp = mu_T_exp;
+  c->D_T_exp = D_T_exp;
+  c->D_p_exp = D_p_exp;
+  c->T_ref = T_ref;
+  c->p_ref = p_ref;
+  c->Pr = Pr;
+  c->flags = flags;
+  c->species_set = true;
+  return FDLBM_OK;
+}
+
+int fdlbm_set_solid(fdlbm_ctx *c, double alpha_s, double C_s, const double *T_bc6) {
+  if (!c) return FDLBM_E_INVALID;
+  if (!(alpha_s >= 0.0 && alpha_s <= 0.5 / c->D))
+    return set_err(c, FDLBM_E_INVALID, "alpha_s must lie in [0, 1/(2D)] (forward-Euler stability)");
+  if (!(C_s > 0.0)) return set_err(c, FDLBM_E_INVALID, "C_s must be positive");
+  c->alpha_s = alpha_s;
+  c->C_s = C_s;
+  for (int a = 0; a < 6; ++a) c->T_bc[a] = T_bc6 ? T_bc6[a] : NAN;
+  return FDLBM_OK;
+}
+
+int fdlbm_set_reaction(fdlbm_ctx *c, const double *nu, const double *order, double k0, double ea,
+                       double T_ref, double dH, int wall_mode, double T_iso, double tol,
+                       int max_iter) {
+  if (!c || !nu || !order) return set_err(c, FDLBM_E_INVALID, "null argument");
+  for (int j = 0; j < c->ns; ++j)
+    if (!(order[j] >= 0 && order[j] <= 3 && order[j] == std::floor(order[j])))
+      return set_err(c, FDLBM_E_INVALID, "reaction orders must be integers 0..3");
+  if (wall_mode != FDLBM_WALL_REACTIVE && wall_mode != FDLBM_WALL_ISOTHERMAL)
+    return set_err(c, FDLBM_E_INVALID, "unknown wall mode");
+  if (!(k0 >= 0) || !(T_ref > 0) || !(T_iso > 0) || max_iter < 0 || !(tol >= 0))
+    return set_err(c, FDLBM_E_INVALID, "reaction parameters out of range");
+  for (int j = 0; j < c->ns; ++j) {
+    c->nu[j] = nu[j];
+    c->order[j] = order[j];
+  }
+  c->k0 = k0;
+  c->ea = ea;
+  c->T_ref_rxn = T_ref;
+  c->dH = dH;
+  c->wall_mode = wall_mode;
+  c->T_iso = T_iso;
+  c->tol = tol;
+  c->max_iter = max_iter;
+  return FDLBM_OK;
+}
+
+int fdlbm_set_flow(fdlbm_ctx *c, const double *F3, const double *X_in, double p_in, double T_in) {
+  if (!c) return FDLBM_E_INVALID;
+  if (!(p_in > 0 && T_in > 0)) return set_err(c, FDLBM_E_INVALID, "inlet p and T must be positive");
+  for (int a = 0; a < 3; ++a) c->F[a] = F3 ? F3[a] : 0.0;
+  for (int j = 0; j < c->ns; ++j) c->X_in[j] = X_in ? X_in[j] : 0.0;
+  c->p_in = p_in;
+  c->T_in = T_in;
+  return FDLBM_OK;
+}
+
+int fdlbm_workspace_bytes(const fdlbm_ctx *c, size_t *bytes) {
+  if (!c || !bytes) return FDLBM_E_INVALID;
+  *bytes = c->total;
+  return FDLBM_OK;
+}
+
+int fdlbm_counts(const fdlbm_ctx *c, int64_t *ng, int64_t *nw, int64_t *ns) {
+  if (!c || !c->geometry_set) return FDLBM_E_STATE;
+  if (ng) *ng = (int64_t)c->gas_list.size();
+  if (nw) *nw = (int64_t)c->wall_list.size();
+  if (ns) *ns = c->n_solid;
+  return FDLBM_OK;
+}
+
+int fdlbm_bind_workspace(fdlbm_ctx *c, void *dev, size_t bytes) {
+  if (!c) return FDLBM_E_INVALID;
+  if (!c->geometry_set) return set_err(c, FDLBM_E_STATE, "set the geometry before binding");
+  if (!dev || ((uintptr_t)dev & 255u) || bytes < c->total)
+    return set_err(c, FDLBM_E_ALIGN, "workspace must be >= %zu bytes and 256-byte aligned", c->total);
+  c->ws = (char *)dev;
+  c->ws_bytes = bytes;
+  const size_t n = (size_t)c->n;
+  HIPCHK(c, hipMemsetAsync(c->ws, 0, c->total, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->ws + c->off_kind, c->kind.data(), n, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->ws + c->off_cls, c->cls.data(), n * 8, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->ws + c->off_em, c->emask.data(), n * 4, hipMemcpyHostToDevice, c->stream));
+  if (!c->gas_list.empty())
+    HIPCHK(c, hipMemcpyAsync(c->ws + c->off_gl, c->gas_list.data(), c->gas_list.size() * 4,
+                             hipMemcpyHostToDevice, c->stream));
+  if (!c->wall_list.empty())
+    HIPCHK(c, hipMemcpyAsync(c->ws + c->off_wl, c->wall_list.data(), c->wall_list.size() * 4,
+                             hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->bound = true;
+  c->initialized = false;
+  return FDLBM_OK;
+}
+
+// host-side equilibrium for the initial state (same closed form as the kernels)
+template <typename real>
+static int init_impl(fdlbm_ctx *c, const double *rho, const double *u, const double *T,
+                     const double *Ts) {
+  const size_t n = (size_t)c->n;
+  const int Q = c->Q, ns = c->ns;
+  std::vector<real> G((size_t)ns * Q * n, real(0)), hT(n, real(0));
+  for (size_t node = 0; node < n; ++node) {
+    hT[node] = (real)Ts[node];
+    if (!gaslike(c->kind[node])) continue;
+    real uu[3] = {(real)u[node], (real)u[n + node], (real)u[2 * n + node]};
+    for (int j = 0; j < ns; ++j) {
+      real f[19];
+      const real sq = (real)std::sqrt(c->M[j]);
+      if (c->D == 2) equilibrium<real, 2>((real)rho[j * n + node], sq, uu, (real)T[node], f);
+      else equilibrium<real, 3>((real)rho[j * n + node], sq, uu, (real)T[node], f);
+      for (int i = 0; i < Q; ++i) G[((size_t)j * Q + i) * n + node] = f[i];
+    }
+  }
+  for (size_t node = 0; node < n; ++node) {
+    if (c->kind[node] != KIND_WALL) continue;
+    const real Tw = c->wall_mode == FDLBM_WALL_ISOTHERMAL ? (real)c->T_iso : (real)Ts[node];
+    real wt[19];
+    const real u0[3] = {0, 0, 0};
+    if (c->D == 2) equilibrium<real, 2>(real(1), real(1), u0, Tw, wt);
+    else equilibrium<real, 3>(real(1), real(1), u0, Tw, wt);
+    for (int j = 0; j < ns; ++j) {
+      double sum = 0;
+      int cnt = 0;
+      for (int i = 1; i < Q; ++i) {
+        const int y = shifted(c, (int)node, i, 1);
+        if (y >= 0 && gaslike(c->kind[y])) {
+          sum += rho[j * n + y];
+          ++cnt;
+        }
+      }
+      const real rw = (real)(sum / cnt);
+      for (int i = 1; i < Q; ++i)
+        if ((c->emask[node] >> i) & 1u) G[((size_t)j * Q + i) * n + node] = rw * wt[i];
+    }
+  }
+  c->cur = 0;
+  HIPCHK(c, hipMemcpyAsync(c->ws + c->off_G[0], G.data(), G.size() * sizeof(real),
+                           hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->ws + c->off_Ts[0], hT.data(), n * sizeof(real), hipMemcpyHostToDevice,
+                           c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->ws + c->off_Ts[1], hT.data(), n * sizeof(real), hipMemcpyHostToDevice,
+                           c->stream));
+  HIPCHK(c, hipMemsetAsync(c->ws + c->off_am, 0, (size_t)c->acc_slots * 8, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->ws + c->off_aw, 0, (size_t)c->acc_slots * 8, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->ws + c->off_ab, 0, (size_t)c->acc_slots * 8, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->step = 0;
+  c->initialized = true;
+  return FDLBM_OK;
+}
+
+int fdlbm_init_fields(fdlbm_ctx *c, const double *rho, const double *u, const double *T,
+                      const double *Ts) {
+  if (!c) return FDLBM_E_INVALID;
+  if (!c->bound || !c->species_set) return set_err(c, FDLBM_E_STATE, "bind the workspace and set species first");
+  if (!rho || !u || !T || !Ts) return set_err(c, FDLBM_E_INVALID, "null argument");
+  return c->d.precision == FDLBM_F64 ? init_impl<double>(c, rho, u, T, Ts)
+                                     : init_impl<float>(c, rho, u, T, Ts);
+}
+
+int fdlbm_set_profiling(fdlbm_ctx *c, int enable) {
+  if (!c) return FDLBM_E_INVALID;
+  if (enable && c->events.empty()) {
+    c->events.resize((size_t)NPROF * K_NUM * 2);
+    for (auto &e : c->events) HIPCHK(c, hipEventCreate(&e));
+  }
+  c->prof = enable != 0;
+  c->prof_launches = 0;
+  return FDLBM_OK;
+}
+
+int fdlbm_kernel_times(fdlbm_ctx *c, double *avg_ms, int64_t *launches) {
+  if (!c || !avg_ms) return FDLBM_E_INVALID;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const int64_t L = std::min<int64_t>(c->prof_launches, NPROF);
+  for (int k = 0; k < K_NUM; ++k) {
+    double tot = 0;
+    int64_t cnt = 0;
+    for (int64_t l = 0; l < L && c->prof_recorded[k]; ++l) {
+      hipEvent_t a = c->events[((size_t)l * K_NUM + k) * 2], b = c->events[((size_t)l * K_NUM + k) * 2 + 1];
+      float ms = 0;
+      if (hipEventQuery(b) == hipSuccess && hipEventElapsedTime(&ms, a, b) == hipSuccess) {
+        tot += ms;
+        ++cnt;
+      }
+    }
+    avg_ms[k] = cnt ? tot / cnt : 0.0;
+  }
+  (void)hipGetLastError();  // event queries must not leave a sticky error behind
+  if (launches) *launches = L;
+  return FDLBM_OK;
+}
+
+int fdlbm_step(fdlbm_ctx *c, int64_t n_steps) {
+  if (!c) return FDLBM_E_INVALID;
+  if (!c->initialized) return set_err(c, FDLBM_E_STATE, "initialise the fields first");
+  if (n_steps < 0) return set_err(c, FDLBM_E_INVALID, "negative step count");
+  const bool f64 = c->d.precision == FDLBM_F64;
+  Params<double> pd;
+  Params<float> pf;
+  if (f64) pd = params<double>(c);
+  else pf = params<float>(c);
+  const Bufs<double> bd = bufs<double>(c);
+  const Bufs<float> bf = bufs<float>(c);
+  for (int64_t s = 0; s < n_steps; ++s) {
+    LaunchInfo li;
+    li.stream = c->stream;
+    li.n_solid = (int)c->n_solid;
+    li.events = nullptr;
+    for (int k = 0; k < K_NUM; ++k) li.recorded[k] = false;
+    if (c->prof && c->prof_launches < NPROF)
+      li.events = &c->events[(size_t)c->prof_launches * K_NUM * 2];
+    hipError_t e = f64 ? launch_step<double>(c->D, pd, bd, c->cur, li)
+                       : launch_step<float>(c->D, pf, bf, c->cur, li);
+    if (e != hipSuccess) return set_err(c, FDLBM_E_HIP, "kernel launch: %s", hipGetErrorString(e));
+    if (li.events) {
+      ++c->prof_launches;
+      for (int k = 0; k < K_NUM; ++k) c->prof_recorded[k] = li.recorded[k];
+    }
+    c->cur ^= 1;
+    ++c->step;
+  }
+  return FDLBM_OK;
+}
+
+int fdlbm_sync(fdlbm_ctx *c) {
+  if (!c) return FDLBM_E_INVALID;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return FDLBM_OK;
+}
+
+int fdlbm_observe(fdlbm_ctx *c, fdlbm_obs *o) {
+  if (!c || !o) return FDLBM_E_INVALID;
+  if (!c->initialized) return set_err(c, FDLBM_E_STATE, "initialise the fields first");
+  const bool f64 = c->d.precision == FDLBM_F64;
+  hipError_t e = f64 ? launch_observe<double>(c->D, params<double>(c), bufs<double>(c), c->cur,
+                                              c->obs_blocks, c->stream)
+                     : launch_observe<float>(c->D, params<float>(c), bufs<float>(c), c->cur,
+                                             c->obs_blocks, c->stream);
+  if (e != hipSuccess) return set_err(c, FDLBM_E_HIP, "observe launch: %s", hipGetErrorString(e));
+  const int NP = c->ns + 9;
+  std::vector<double> part((size_t)c->obs_blocks * NP);
+  std::vector<double> acc(3 * (size_t)c->acc_slots);
+  HIPCHK(c, hipMemcpyAsync(part.data(), c->ws + c->off_part, part.size() * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(acc.data(), c->ws + c->off_am, (size_t)c->acc_slots * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(acc.data() + c->acc_slots, c->ws + c->off_aw, (size_t)c->acc_slots * 8,
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(acc.data() + 2 * c->acc_slots, c->ws + c->off_ab, (size_t)c->acc_slots * 8,
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::memset(o, 0, sizeof *o);
+  const int ns = c->ns;
+  o->T_min = o->rho_min = o->Ts_min = 1e300;
+  o->T_max = o->Ts_max = -1e300;
+  for (int bk = 0; bk < c->obs_blocks; ++bk) {
+    const double *q = &part[(size_t)bk * NP];
+    for (int j = 0; j < ns; ++j) o->mass[j] += q[j];
+    o->e_gas += q[ns];
+    o->e_solid += q[ns + 1];
+    o->T_min = std::min(o->T_min, q[ns + 2]);
+    o->T_max = std::max(o->T_max, q[ns + 3]);
+    o->u_max = std::max(o->u_max, q[ns + 4]);
+    o->rho_min = std::min(o->rho_min, q[ns + 5]);
+    o->Ts_min = std::min(o->Ts_min, q[ns + 6]);
+    o->Ts_max = std::max(o->Ts_max, q[ns + 7]);
+    if (q[ns + 8] != 0.0) o->bad = 1;
+  }
+  for (int s = 0; s < c->acc_slots; ++s) {
+    o->moles_reacted += acc[s];
+    o->work_body += acc[c->acc_slots + s];
+    o->heat_boundary += acc[2 * c->acc_slots + s];
+  }
+  o->heat_released = -c->dH * o->moles_reacted;
+  if (o->rho_min < 0) o->bad = 1;
+  o->step = c->step;
+  o->n_gas = (int32_t)c->gas_list.size();
+  o->n_wall = (int32_t)c->wall_list.size();
+  o->n_solid = (int32_t)c->n_solid;
+  return FDLBM_OK;
+}
+
+int fdlbm_get_field(fdlbm_ctx *c, int field, int comp, double *dst) {
+  if (!c || !dst) return FDLBM_E_INVALID;
+  if (!c->initialized) return set_err(c, FDLBM_E_STATE, "initialise the fields first");
+  const size_t n = (size_t)c->n, b = real_size(c);
+  const bool f64 = c->d.precision == FDLBM_F64;
+  auto cp = [&](size_t off, size_t count) {
+    return f64 ? copy_field<double>(c, off, count, dst) : copy_field<float>(c, off, count, dst);
+  };
+  int rc = FDLBM_OK;
+  switch (field) {
+    case FDLBM_FIELD_RHO:
+    case FDLBM_FIELD_U:
+    case FDLBM_FIELD_T: {
+      if (c->step == 0) return set_err(c, FDLBM_E_STATE, "moments exist after the first step");
+      size_t k;
+      if (field == FDLBM_FIELD_RHO) {
+        if (comp < 0 || comp >= c->ns) return set_err(c, FDLBM_E_INVALID, "bad species");
+        k = (size_t)fo_rho(comp);
+      } else if (field == FDLBM_FIELD_U) {
+        if (comp < 0 || comp > 2) return set_err(c, FDLBM_E_INVALID, "bad axis");
+        if (comp >= c->D) {
+          std::fill(dst, dst + n, 0.0);
+          return FDLBM_OK;
+        }
+        k = (size_t)fo_u(c->ns, comp);
+      } else {
+        k = (size_t)(3 * c->ns + c->D);
+      }
+      rc = cp(c->off_F + k * n * b, n);
+      if (rc) return rc;
+      for (size_t x = 0; x < n; ++x)
+        if (!(gaslike(c->kind[x]) || c->kind[x] == KIND_WALL)) dst[x] = 0.0;
+      return FDLBM_OK;
+    }
+    case FDLBM_FIELD_TS:
+      rc = cp(c->off_Ts[c->cur], n);
+      if (rc) return rc;
+      for (size_t x = 0; x < n; ++x)
+        if (!(c->kind[x] == KIND_SOLID || c->kind[x] == KIND_WALL)) dst[x] = 0.0;
+      return FDLBM_OK;
+    case FDLBM_FIELD_POP:
+      if (comp < 0 || comp >= c->ns) return set_err(c, FDLBM_E_INVALID, "bad species");
+      return cp(c->off_G[c->cur] + (size_t)comp * c->Q * n * b, (size_t)c->Q * n);
+    case FDLBM_FIELD_KIND:
+      for (size_t x = 0; x < n; ++x) dst[x] = c->kind[x];
+      return FDLBM_OK;
+    case FDLBM_FIELD_WALL_R:
+    case FDLBM_FIELD_WALL_DE:
+      if (c->step == 0) return set_err(c, FDLBM_E_STATE, "wall values exist after the first step");
+      rc = cp(field == FDLBM_FIELD_WALL_R ? c->off_wr : c->off_wde, n);
+      if (rc) return rc;
+      for (size_t x = 0; x < n; ++x)
+        if (c->kind[x] != KIND_WALL) dst[x] = 0.0;
+      return FDLBM_OK;
+  }
+  return set_err(c, FDLBM_E_INVALID, "unknown field");
+}
+
+// checkpoint: header, populations (current buffer), solid temperature,
+// per-step wall arrays, moments, accumulators
+struct StateHeader {
+  uint64_t magic, total, step;
+  int32_t cur, pad;
+};
+
+int fdlbm_state_bytes(const fdlbm_ctx *c, size_t *bytes) {
+  if (!c || !bytes) return FDLBM_E_INVALID;
+  *bytes = sizeof(StateHeader) + c->total;
+  return FDLBM_OK;
+}
+
+int fdlbm_save_state(fdlbm_ctx *c, void *host, size_t bytes) {
+  if (!c || !host) return FDLBM_E_INVALID;
+  if (!c->initialized) return set_err(c, FDLBM_E_STATE, "nothing to save");
+  if (bytes < sizeof(StateHeader) + c->total) return set_err(c, FDLBM_E_INVALID, "buffer too small");
+  StateHeader h{0x46444c424d535431ull, c->total, (uint64_t)c->step, c->cur, 0};
+  std::memcpy(host, &h, sizeof h);
+  HIPCHK(c, hipMemcpyAsync((char *)host + sizeof h, c->ws, c->total, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return FDLBM_OK;
+}
+
+int fdlbm_load_state(fdlbm_ctx *c, const void *host, size_t bytes) {
+  if (!c || !host) return FDLBM_E_INVALID;
+  if (!c->bound) return set_err(c, FDLBM_E_STATE, "bind the workspace first");
+  StateHeader h;
+  if (bytes < sizeof h) return set_err(c, FDLBM_E_INVALID, "buffer too small");
+  std::memcpy(&h, host, sizeof h);
+  if (h.magic != 0x46444c424d535431ull || h.total != c->total || bytes < sizeof h + c->total)
+    return set_err(c, FDLBM_E_INVALID, "state does not match this context");
+  HIPCHK(c, hipMemcpyAsync(c->ws, (const char *)host + sizeof h, c->total, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->step = (int64_t)h.step;
+  c->cur = h.cur;
+  c->initialized = true;
+  return FDLBM_OK;
+}
+

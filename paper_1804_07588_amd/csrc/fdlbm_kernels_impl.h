@@ -1,0 +1,960 @@
+// HIP kernels (gfx950) of the coupled FD-LBM time step.
+//
+// Per step, on one stream:
+//   k_wall     reactive diffusive wall at every wall node: streaming of the
+//              populations arriving from the gas, wall densities and the
+//              thermalised emission (Eq.(37)-(42), (50))
+//   k_moments  streaming into every gas node (Eq.(33)-(36)), stored for the
+//              collision, and everything local: moments, transport, U^c,
+//              species momenta of f (Eq.(3), (5), (7)-(8), (11), (14)-(17), (25))
+//   k_collide  correction sources from the node's and its face neighbours'
+//              moments, temperature of f, equilibria and the trapezoidal
+//              collision (Eq.(4), (6), (12)-(13), (19)-(21), (24)); writes the
+//              inlet/outlet planes directly
+//   k_solid    forward-Euler heat step in the solid on an LDS tile with the
+//              wall-node interface source (Eq.(45)-(48))
+// Populations are structure-of-arrays [(j*Q + i)*n + node], so a wavefront of
+// consecutive gas nodes touches 64 consecutive values per (species, direction).
+#pragma once
+#include <type_traits>
+
+#include "fdlbm_device.h"
+#include "fdlbm_launch.h"
+
+namespace fdlbm {
+
+// periodic wrap of v in [-3, n + 2] (any n >= 1), branch-free
+__device__ inline int wrapc(int v, int n) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    v = v < 0 ? v + n : v;
+    v = v >= n ? v - n : v;
+  }
+  return v;
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs.  Give each XCD a
+// contiguous run of logical blocks, so node-list neighbours (adjacent rows)
+// are processed by one XCD close in time and share its L2.  Launch
+// xcd_grid(nb) blocks; logical ids >= nb do nothing.
+constexpr int NXCD = 8;
+__host__ __device__ inline int xcd_grid(int nb) { return ((nb + NXCD - 1) / NXCD) * NXCD; }
+__device__ inline int xcd_block(int nb) {
+  const int per = (nb + NXCD - 1) / NXCD;
+  return (int)(blockIdx.x % NXCD) * per + (int)(blockIdx.x / NXCD);
+}
+
+// Per-thread addressing: taps are node + k*stride(i) unless a periodic axis
+// wraps within 3 nodes (FAST = the node list holds no such node).
+template <int D>
+struct Addr {
+  int node, x, y, z, nx, ny, nz;
+  template <typename real>
+  __device__ Addr(int nd, const Params<real> &p) : node(nd), nx(p.nx), ny(p.ny), nz(p.nz) {
+    x = nd % nx;
+    const int r = nd / nx;
+    y = r % ny;
+    z = r / ny;
+  }
+  template <bool FAST>
+  __device__ inline int at(int i, int k) const {
+    if constexpr (FAST) {
+      return node + k * (cvec<D>(i, 0) + nx * (cvec<D>(i, 1) + ny * cvec<D>(i, 2)));
+    } else {
+      const int xx = wrapc(x + k * cvec<D>(i, 0), nx);
+      const int yy = wrapc(y + k * cvec<D>(i, 1), ny);
+      const int zz = D == 3 ? wrapc(z + k * cvec<D>(i, 2), nz) : 0;
+      return xx + nx * (yy + ny * zz);
+    }
+  }
+  // face neighbour along axis a, direction d (+1/-1); -1 outside a closed axis
+  template <typename real>
+  __device__ inline int face(const Params<real> &p, int a, int d) const {
+    int q[3] = {x, y, z};
+    const int lim[3] = {nx, ny, nz};
+    q[a] += d;
+    if (q[a] < 0 || q[a] >= lim[a]) {
+      if (!p.per[a]) return -1;
+      q[a] = q[a] < 0 ? q[a] + lim[a] : q[a] - lim[a];
+    }
+    return q[0] + nx * (q[1] + ny * q[2]);
+  }
+};
+
+// Streaming weights per species and stencil class, staged in LDS by every
+// kernel that streams (taps beyond a class's count carry weight 0).
+template <typename real>
+struct WTab {
+  real w[MAX_NS][8][3];
+};
+
+template <typename real, int NS>
+__device__ inline void load_wtab(const Params<real> &p, WTab<real> &wt) {
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < NS; ++j)
+#pragma unroll
+      for (int c = 0; c < 7; ++c)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) wt.w[j][c][k] = p.wint[j][c][k];
+  }
+  __syncthreads();
+}
+
+// Tap offsets (units of e_i from the destination) of each stencil class,
+// packed 3 bits each (offset + 3); a class with fewer than three taps
+// repeats one of its taps with weight 0.
+// class: 0 (-2,-1,0)  1 (-1,0,1)  2 (-1,-2,-3)  3 (-1,0,0)  4 (-2,-1,-1)
+//        5 (-1,-1,-1) 6 (0,0,0)
+__device__ constexpr uint64_t pack_offsets() {
+  constexpr int off[7][3] = {{-2, -1, 0}, {-1, 0, 1}, {-1, -2, -3}, {-1, 0, 0},
+                             {-2, -1, -1}, {-1, -1, -1}, {0, 0, 0}};
+  uint64_t v = 0;
+  for (int c = 0; c < 7; ++c)
+    for (int k = 0; k < 3; ++k) v |= uint64_t(off[c][k] + 3) << (9 * c + 3 * k);
+  return v;
+}
+
+// load base[idx] with a uniform base (SGPRs) and a 32-bit per-lane byte offset
+template <typename real>
+__device__ inline real ld(const real *__restrict__ base, int idx) {
+  const uint32_t off = uint32_t(idx) * uint32_t(sizeof(real));
+  return *reinterpret_cast<const real *>(reinterpret_cast<const char *>(base) + off);
+}
+template <typename real>
+__device__ inline void st(real *__restrict__ base, int idx, real v) {
+  const uint32_t off = uint32_t(idx) * uint32_t(sizeof(real));
+  *reinterpret_cast<real *>(reinterpret_cast<char *>(base) + off) = v;
+}
+
+// Pre-collision population of species j, direction i at a destination node,
+// Eq.(33)-(36): the interpolant through the taps of the node's stencil class
+// evaluated at the off-lattice shift s_j; one branch-free code path for all
+// classes.  On-lattice species (c_j = 1) read the upstream node only.
+template <bool FAST, typename real, int D>
+__device__ inline real stream_pop(const real *__restrict__ Gji, const Params<real> &p,
+                                  const Addr<D> &ad, int j, int i, int cls, const WTab<real> &wt) {
+  if (p.onlat[j]) return ld(Gji, ad.template at<FAST>(i, cls == 6 ? 0 : -1));  // uniform branch
+  constexpr uint64_t OFF = pack_offsets();
+  const int sh = 9 * cls;
+  const int o0 = int((OFF >> sh) & 7u) - 3, o1 = int((OFF >> (sh + 3)) & 7u) - 3,
+            o2 = int((OFF >> (sh + 6)) & 7u) - 3;
+  return wt.w[j][cls][0] * ld(Gji, ad.template at<FAST>(i, o0)) +
+         wt.w[j][cls][1] * ld(Gji, ad.template at<FAST>(i, o1)) +
+         wt.w[j][cls][2] * ld(Gji, ad.template at<FAST>(i, o2));
+}
+
+// compile-time loop: f(std::integral_constant<int, I>) for I in [B, E)
+template <int B, int E, typename F>
+__device__ inline void static_for(F &&f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+__device__ inline int cls_at(uint64_t w, int i) { return int((w >> (3 * (i - 1))) & 7u); }
+
+// block-wide FP64 sum in a fixed order (deterministic); result in thread 0
+__device__ inline double block_sum(double v) {
+  __shared__ double sh[BLOCK];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = BLOCK / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+template <typename real>
+__device__ inline real tiny() {
+  return sizeof(real) == 4 ? real(1e-30f) : real(1e-300);
+}
+
+template <typename real>
+__device__ inline real ipow(real x, int k) {
+  real r = real(1);
+  for (int q = 0; q < k; ++q) r *= x;
+  return r;
+}
+
+// ===========================================================================
+// k_wall: the reactive diffusive wall, one thread per wall node
+// ===========================================================================
+template <bool FAST, typename real, int D, int NS>
+__device__ inline double wall_node(const Params<real> &p, const Bufs<real> &b, int cur,
+                                   const WTab<real> &wtab, const int w, const Addr<D> &ad) {
+  constexpr int Q = lat_q<D>();
+  const uint64_t cw = b.cls[w];
+  const uint32_t em = b.emask[w];
+  const real *G = b.G[cur];
+  real *Gn = b.G[cur ^ 1];
+  const int n = p.n;
+  const real Tw = p.wall_mode == 1 ? p.T_iso : b.Ts[cur][w];
+  real wt[Q];
+  const real u0[3] = {0, 0, 0};
+  equilibrium<real, D>(real(1), real(1), u0, Tw, wt);
+  // Z: thermalised emission weight summed over the links into the gas
+  real Z = 0;
+#pragma unroll
+  for (int i = 1; i < Q; ++i)
+    if (em & (1u << i)) Z += wt[i];
+  // A_j: mass arriving from the gas (incoming links), with its energy
+  real A[NS], Ein = 0;
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    asm volatile("" ::: "memory");
+    A[j] = 0;
+    real Ej = 0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const int cls = cls_at(cw, i);
+      if (cls == CLS_NONE) continue;
+      const real g = stream_pop<FAST, real, D>(G + (size_t)(j * Q + i) * n, p, ad, j, i, cls, wtab);
+      A[j] += g;
+      Ej += real(cnorm2<D>(i)) * g;
+    }
+    Ein += p.cj2[j] * Ej;
+  }
+  // wall densities: rho_w,j Z = A_j + nu_j M_j r (Eq.(41) with Eq.(50));
+  // fixed point started at the non-reactive density, each reactant's own
+  // concentration treated implicitly
+  real rw[NS];
+#pragma unroll
+  for (int j = 0; j < NS; ++j) rw[j] = A[j] / Z;
+  // the rate law is a flux per unit wall area: scale by the node's wetted
+  // area, its emission Z relative to a flat wall's T_w / 2
+  const real keff = (Z / (real(0.5) * Tw)) * p.k0 * exp(p.ea * (real(1) - p.T_ref_rxn / Tw));
+  for (int it = 0; it < p.max_iter; ++it) {
+    real nw[NS], dmax = 0;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      nw[j] = rw[j];
+      if (p.nu[j] < real(0) && p.order[j] > 0) {
+        real R = keff;
+#pragma unroll
+        for (int m = 0; m < NS; ++m) R *= ipow(rw[m] * p.invM[m], p.order[m] - (m == j ? 1 : 0));
+        nw[j] = A[j] / (Z - p.nu[j] * R);
+      }
+      const real d = fabs(nw[j] - rw[j]) / fmax(fabs(nw[j]), tiny<real>());
+      dmax = fmax(dmax, d);
+    }
+#pragma unroll
+    for (int j = 0; j < NS; ++j) rw[j] = nw[j];
+    if (dmax <= p.tol) break;
+  }
+  real r = keff;
+#pragma unroll
+  for (int m = 0; m < NS; ++m) r *= ipow(rw[m] * p.invM[m], p.order[m]);
+  real Eout = 0;
+  const real invZ = real(1) / Z;
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    rw[j] = (A[j] + p.nu[j] * p.M[j] * r) * invZ;
+    real Ej = 0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      if (!(em & (1u << i))) continue;
+      const real W = rw[j] * wt[i];
+      Gn[(size_t)(j * Q + i) * n + w] = W;
+      Ej += real(cnorm2<D>(i)) * W;
+    }
+    Eout += p.cj2[j] * Ej;
+    b.F[(size_t)fo_rho(j) * n + w] = rw[j];
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a) b.F[(size_t)fo_u(NS, a) * n + w] = real(0);
+  b.F[(size_t)fo_T<D>(NS) * n + w] = Tw;
+  b.wall_r[w] = r;
+  b.wall_dE[w] = real(0.5) * (Eout - Ein);
+  return (double)r;
+}
+
+// FAST: the node list holds only nodes whose taps never wrap a periodic axis
+template <bool FAST, typename real, int D, int NS>
+__global__ void __launch_bounds__(BLOCK) k_wall(Params<real> p, Bufs<real> b, int cur) {
+  __shared__ WTab<real> wtab;
+  load_wtab<real, NS>(p, wtab);
+  const int first = FAST ? 0 : p.n_wall_fast, count = FAST ? p.n_wall_fast : p.n_wall - p.n_wall_fast;
+  const int nb = (count + BLOCK - 1) / BLOCK, lb = xcd_block(nb);
+  if (lb >= nb) return;  // whole block: no barrier follows for it
+  const int t = lb * BLOCK + threadIdx.x;
+  const bool active = t < count;
+  const int w = active ? (int)b.wall_list[first + t] : 0;
+  const Addr<D> ad(w, p);
+  double r_out = 0.0;
+  if (active) r_out = wall_node<FAST, real, D, NS>(p, b, cur, wtab, w, ad);
+  const double s = block_sum(r_out);
+  if (threadIdx.x == 0) b.acc_moles[lb + (FAST ? 0 : p.slot_off_wall)] += s;
+}
+
+// ===========================================================================
+// k_moments: streaming and every local quantity of each gas node (pass 1)
+// ===========================================================================
+template <bool FAST, typename real, int D, int NS>
+__device__ inline void moments_node(const Params<real> &p, const Bufs<real> &b, int cur,
+                                    const WTab<real> &wtab, const int node, const Addr<D> &ad) {
+  constexpr int Q = lat_q<D>();
+  const uint64_t cw = b.cls[node];
+  const real *G = b.G[cur];
+  real *Gs = b.Gs;
+  real *F = b.F;
+  const int n = p.n;
+  real rho[NS], Jg[NS][D], E = 0;
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    asm volatile("" ::: "memory");
+    const real g0 = ld(G + (size_t)(j * Q) * n, node);
+    st(Gs + (size_t)(j * Q) * n, node, g0);
+    real r = g0, Jj[D], Ej = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) Jj[a] = 0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const real g = stream_pop<FAST, real, D>(G + (size_t)(j * Q + i) * n, p, ad, j, i, cls_at(cw, i), wtab);
+      st(Gs + (size_t)(j * Q + i) * n, node, g);
+      r += g;
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+        if (cvec<D>(i, a) != 0) Jj[a] += cvec<D>(i, a) > 0 ? g : -g;
+      Ej += real(cnorm2<D>(i)) * g;
+    }
+    rho[j] = r;
+#pragma unroll
+    for (int a = 0; a < D; ++a) Jg[j][a] = p.cj[j] * Jj[a];
+    E += p.cj2[j] * Ej;
+  }
+  real rhot = 0, C = 0;
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    rhot += rho[j];
+    C += rho[j] * p.invM[j];
+  }
+  // mixture velocity of f: total momentum is conserved by the collision, so
+  // J(f) = J(g) + rho F / 2
+  real u[D], u2 = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    real J = 0;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) J += Jg[j][a];
+    u[a] = (J + real(0.5) * rhot * p.F[a]) / rhot;
+    u2 += u[a] * u[a];
+  }
+  const real T = (E - rhot * u2) / (real(D) * C);
+  // transport with floored mole fractions
+  real Xh[NS], sX = 0, sMX = 0;
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    Xh[j] = fmax(rho[j] * p.invM[j] / C, real(1e-6));
+    sX += Xh[j];
+  }
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    Xh[j] /= sX;
+    sMX += p.M[j] * Xh[j];
+  }
+  const real lT = log(T / p.T_ref);
+  const real fmu = p.mu_T_exp == real(0) ? real(1) : exp(p.mu_T_exp * lT);
+  const real CT = C * T;
+  real tau2[NS];
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    real den = 0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) den += Xh[k] * p.wilke[j][k];
+    const real tau1 = p.mu0[j] * fmu / (CT * den);  // Eq.(17)
+    st(F + (size_t)fo_tau1(NS, j) * n, node, tau1);
+    st(F + (size_t)fo_rho(j) * n, node, rho[j]);
+    tau2[j] = tau1;
+  }
+  if (NS > 1) {
+    const real gD = exp(p.D_T_exp * lT + p.D_p_exp * log(p.p_ref / CT));
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      real sum = 0;
+#pragma unroll
+      for (int k = 0; k < NS; ++k)
+        if (k != j) sum += Xh[k] * p.invD0[j][k];
+      const real Dj = gD * (real(1) - p.M[j] * Xh[j] / sMX) / sum;  // Eq.(8)
+      tau2[j] = p.M[j] * Dj / T;                                    // Eq.(7)
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NS; ++j) st(F + (size_t)fo_tau2(NS, j) * n, node, tau2[j]);
+#pragma unroll
+  for (int a = 0; a < D; ++a) st(F + (size_t)fo_u(NS, a) * n, node, u[a]);
+  st(F + (size_t)fo_T<D>(NS) * n, node, T);
+  // Eq.(25) with Eq.(11): species momenta of f and U^c in closed form
+  const bool cdiff = (p.flags & 1u) && NS > 1;
+  real ediff = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    real num = 0, den = 0, K[NS], ah[NS];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      ah[j] = real(0.5) / tau2[j];
+      K[j] = (Jg[j][a] + ah[j] * rho[j] * u[a] + real(0.5) * rho[j] * p.F[a]) / (real(1) + ah[j]);
+      num += ah[j] * (K[j] - rho[j] * u[a]);
+      den += ah[j] * rho[j] / (real(1) + ah[j]);
+    }
+    const real Uc = cdiff ? num / den : real(0);
+    st(F + (size_t)fo_Uc<D>(NS, a) * n, node, Uc);
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      const real Jf = K[j] + ah[j] * rho[j] * Uc / (real(1) + ah[j]);
+      const real uja = rho[j] > tiny<real>() ? Jf / rho[j] : u[a];
+      st(F + (size_t)fo_uj<D>(NS, j, a) * n, node, uja);
+      ediff += rho[j] * (uja - u[a]) * (uja - u[a]);
+    }
+  }
+  st(F + (size_t)fo_ediff<D>(NS) * n, node, ediff);
+}
+
+template <bool FAST, typename real, int D, int NS>
+__global__ void __launch_bounds__(BLOCK) k_moments(Params<real> p, Bufs<real> b, int cur) {
+  __shared__ WTab<real> wtab;
+  load_wtab<real, NS>(p, wtab);
+  const int first = FAST ? 0 : p.n_gas_fast, count = FAST ? p.n_gas_fast : p.n_gas - p.n_gas_fast;
+  const int nb = (count + BLOCK - 1) / BLOCK, lb = xcd_block(nb);
+  const int t = lb * BLOCK + threadIdx.x;
+  if (lb >= nb || t >= count) return;
+  const int node = (int)b.gas_list[first + t];
+  const Addr<D> ad(node, p);
+  moments_node<FAST, real, D, NS>(p, b, cur, wtab, node, ad);
+}
+
+// ===========================================================================
+// k_collide: sources, temperature of f, equilibria and Eq.(24) (pass 2)
+// ===========================================================================
+template <typename real, int D>
+__device__ inline real q_dev(real rho, real invM, real ua, real T) {
+  // lattice-minus-Maxwellian third moment Q'_aaa of the equilibria above
+  return rho * invM * ua * (real(1) - real(3) * T) - rho * ua * ua * ua;
+}
+template <typename real, int D>
+__device__ inline real r_dev(real rho, real invM, const real *u, real T, int a, int b) {
+  // lattice-minus-Maxwellian energy flux R'_ab of the equilibria above
+  if (a == b) {
+    const real ua2 = u[a] * u[a];
+    return rho * (T * (real(1) - real(3) * T) * invM * invM + ua2 * (real(1) - real(6) * T) * invM -
+                  ua2 * ua2);
+  }
+  real u2 = 0;
+#pragma unroll
+  for (int c = 0; c < D; ++c) u2 += u[c] * u[c];
+  return rho * u[a] * u[b] * ((real(2) - real(D + 4) * T) * invM - u2);
+}
+
+// Per-axis factors of the equilibrium (see equilibrium() in fdlbm_device.h)
+template <typename real, int D>
+struct EqFactors {
+  real P0[3], Pp[3], Pm[3], U2[3], perp_base;
+  __device__ inline void set(real sqM, const real *u, real T) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const real U = a < D ? sqM * u[a] : real(0);
+      U2[a] = U * U;
+      P0[a] = real(1) - T - U2[a];
+      Pp[a] = real(0.5) * (T + U2[a] + U);
+      Pm[a] = real(0.5) * (T + U2[a] - U);
+    }
+    perp_base = real(1) - real(2) * T;
+  }
+  // population of a moving direction i (per unit density)
+  template <int i>
+  __device__ inline real moving() const {
+    if constexpr (D == 2) {
+      constexpr int cx = cvec<D>(i, 0), cy = cvec<D>(i, 1);
+      const real fx = cx == 0 ? P0[0] : (cx > 0 ? Pp[0] : Pm[0]);
+      const real fy = cy == 0 ? P0[1] : (cy > 0 ? Pp[1] : Pm[1]);
+      return fx * fy;
+    } else if constexpr (is_face<D>(i)) {
+      constexpr int a = edge_axis<D>(i, 0);
+      constexpr int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
+      return (cvec<D>(i, a) > 0 ? Pp[a] : Pm[a]) * (perp_base - U2[b1] - U2[b2]);
+    } else {
+      constexpr int a0 = edge_axis<D>(i, 0), a1 = edge_axis<D>(i, 1);
+      return (cvec<D>(i, a0) > 0 ? Pp[a0] : Pm[a0]) * (cvec<D>(i, a1) > 0 ? Pp[a1] : Pm[a1]);
+    }
+  }
+  // rest population (per unit density): D2Q9 product, D3Q19 the remainder
+  __device__ inline real rest(real sum_moving) const {
+    if constexpr (D == 2) return P0[0] * P0[1];
+    else return real(1) - sum_moving;
+  }
+};
+
+// face-neighbour values of the gradient stencils shared by all species
+template <typename real, int D>
+struct NbCommon {
+  real u[D], T;
+  int node;  // node supplying rho_j and tau1_j (self when missing)
+  bool wall, missing;
+};
+
+template <typename real, int D, int NS>
+__device__ inline double collide_node(const Params<real> &p, const Bufs<real> &b, int cur,
+                                      const int node, const int src) {
+  // src: node whose collision is computed (an outlet node takes the result of
+  // the last interior node of its row); node: where it is stored
+  constexpr int Q = lat_q<D>();
+  const int n = p.n;
+  const real *__restrict__ F = b.F;
+  const real *__restrict__ Gs = b.Gs;
+  const Addr<D> ad(src, p);
+  real u[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) u[a] = ld(F + (size_t)fo_u(NS, a) * n, src);
+  const real Tt = ld(F + (size_t)fo_T<D>(NS) * n, src);
+  real C = 0;
+#pragma unroll
+  for (int j = 0; j < NS; ++j) C += ld(F + (size_t)fo_rho(j) * n, src) * p.invM[j];
+  // ---- neighbours: velocity and temperature shared by all species ----
+  const bool cdiff = (p.flags & 1u) && NS > 1;
+  const bool cvisc = p.flags & 2u, cener = p.flags & 4u, cpr = (p.flags & 8u) && p.kpr != real(0);
+  const bool cgrad = cvisc || cener || cpr;
+  NbCommon<real, D> nb[D][2];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      NbCommon<real, D> &v = nb[a][s];
+      const int q = cgrad ? ad.face(p, a, s == 0 ? +1 : -1) : src;
+      const uint8_t k = q >= 0 ? b.kind[q] : KIND_SOLID;
+      v.wall = q >= 0 && k == KIND_WALL;
+      v.missing = !(q >= 0 && (gaslike(k) || k == KIND_WALL)) || q == src;
+      v.node = v.missing ? src : q;
+      if (cgrad) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) v.u[c] = ld(F + (size_t)fo_u(NS, c) * n, v.node);
+        v.T = ld(F + (size_t)fo_T<D>(NS) * n, v.node);
+      }
+    }
+  // source moments of species j: momentum m, second moments P (diagonal Pd,
+  // off-diagonal Po: xy, xz, yz), energy flux Y, energy e
+  auto sources = [&](const int j, const real rj, real (&m)[D], real (&Pd)[D], real (&Po)[3],
+                     real (&Y)[D], real &e, const bool energy_only) __attribute__((always_inline)) {
+    const real iM = p.invM[j];
+    e = 0;
+    const real tau2x = ld(F + (size_t)fo_tau2(NS, j) * n, src);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const real Uca = cdiff ? ld(F + (size_t)fo_Uc<D>(NS, a) * n, src) : real(0);
+      m[a] = (cdiff ? rj * Uca / tau2x : real(0)) + rj * p.F[a];  // Eq.(12) + body force
+      Pd[a] = real(2) * rj * u[a] * p.F[a];
+      Y[a] = 0;
+    }
+    Po[0] = rj * (u[0] * p.F[1] + u[1] * p.F[0]);
+    Po[1] = Po[2] = 0;
+    if constexpr (D == 3) {
+      Po[1] = rj * (u[0] * p.F[2] + u[2] * p.F[0]);
+      Po[2] = rj * (u[1] * p.F[2] + u[2] * p.F[1]);
+    }
+    if (!cgrad) return;
+    const real tau1x = ld(F + (size_t)fo_tau1(NS, j) * n, src);
+    const real Kx = p.kpr * tau1x * rj * iM * Tt * iM;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const NbCommon<real, D> &sp = nb[a][0], &sm = nb[a][1];
+      const real rp = ld(F + (size_t)fo_rho(j) * n, sp.node), rm = ld(F + (size_t)fo_rho(j) * n, sm.node);
+      if (cvisc) {
+        // d_a Q'_aaa; a wall face carries no correction flux (mirror value)
+        const real qx = q_dev<real, D>(rj, iM, u[a], Tt);
+        const real qp = sp.wall ? -qx : q_dev<real, D>(rp, iM, sp.u[a], sp.T);
+        const real qm = sm.wall ? -qx : q_dev<real, D>(rm, iM, sm.u[a], sm.T);
+        Pd[a] += real(0.5) * (qp - qm);
+        if constexpr (D == 3) {
+          if (!energy_only) {
+            // d_a of Q'_xyz = -rho u_x u_y u_z feeds the off-diagonal pair not containing a
+            const real dq = real(0.5) * (-rp * sp.u[0] * sp.u[1] * sp.u[2] + rm * sm.u[0] * sm.u[1] * sm.u[2]);
+            Po[2 - a] += dq;  // a = x -> yz (2), y -> xz (1), z -> xy (0)
+          }
+        }
+      }
+      if (cener && !energy_only) {
+#pragma unroll
+        for (int c = 0; c < D; ++c)
+          Y[c] += real(0.5) * (r_dev<real, D>(rp, iM, sp.u, sp.T, c, a) -
+                               r_dev<real, D>(rm, iM, sm.u, sm.T, c, a));
+      }
+      if (cpr) {
+        // Eq.(19)-(21), face-flux form; wall faces carry no correction flux
+        if (!sp.wall && !sp.missing) {
+          const real tp = ld(F + (size_t)fo_tau1(NS, j) * n, sp.node);
+          e += real(0.5) * (Kx + p.kpr * tp * rp * iM * sp.T * iM) * (sp.T - Tt);
+        }
+        if (!sm.wall && !sm.missing) {
+          const real tm = ld(F + (size_t)fo_tau1(NS, j) * n, sm.node);
+          e += real(0.5) * (Kx + p.kpr * tm * rm * iM * sm.T * iM) * (sm.T - Tt);
+        }
+      }
+    }
+  };
+  // ---- temperature of f from the energy of all sources, Eq.(25) ----
+  real esum = 0;
+#pragma unroll 1
+  for (int j = 0; j < NS; ++j) {
+    real m[D], Pd[D], Po[3], Y[D], e;
+    sources(j, ld(F + (size_t)fo_rho(j) * n, src), m, Pd, Po, Y, e, true);
+    esum += e;
+#pragma unroll
+    for (int a = 0; a < D; ++a) esum += Pd[a];
+  }
+  const real Tf = Tt + esum / (real(2 * D) * C);
+  // f* temperature: quasi-equilibrium at fixed species momenta and energy
+  const real Tst = Tf - ld(F + (size_t)fo_ediff<D>(NS) * n, src) / (real(D) * C);
+  // ---- per species: sources, equilibria and Eq.(24) ----
+  real *__restrict__ Gn = b.G[cur ^ 1];
+#pragma unroll 1
+  for (int j = 0; j < NS; ++j) {
+    const real rj = ld(F + (size_t)fo_rho(j) * n, src);
+    real uj[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) uj[a] = ld(F + (size_t)fo_uj<D>(NS, j, a) * n, src);
+    real m[D], Pd[D], Po[3], Y[D], e;
+    sources(j, rj, m, Pd, Po, Y, e, false);
+    EqFactors<real, D> fe, fs;
+    fe.set(p.sqM[j], u, Tf);
+    fs.set(p.sqM[j], uj, Tst);
+    const real tau1 = ld(F + (size_t)fo_tau1(NS, j) * n, src);
+    const real tau2 = ld(F + (size_t)fo_tau2(NS, j) * n, src);
+    const real w1 = real(2) / (real(1) + real(2) * tau1);
+    const real r12 = tau1 / tau2;
+    const real wt = w1 * tau1;
+    const real ic = p.invcj[j], ic2 = ic * ic, ic3 = ic2 * ic;
+    real trP = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) trP += Pd[a];
+    real se = 0, ss = 0;  // sums of the moving populations of f^eq and f* (per unit density)
+    const real *__restrict__ Gsj = Gs + (size_t)(j * Q) * n;
+    real *__restrict__ Gnj = Gn + (size_t)(j * Q) * n;
+    static_for<1, Q>([&](auto ic_) __attribute__((always_inline)) {
+      constexpr int i = decltype(ic_)::value;
+      real S;
+      if constexpr (is_face<D>(i)) {
+        constexpr int a = edge_axis<D>(i, 0);
+        constexpr real sg = real(cvec<D>(i, a));
+        S = sg * m[a] * ic + real(0.5) * Pd[a] * ic2 - real(0.5) * sg * Y[a] * ic3 +
+            e * ic2 / real(2 * D);
+      } else {
+        constexpr real kd = D == 2 ? real(0.25) : real(0.125);
+        constexpr int a0 = edge_axis<D>(i, 0), a1 = edge_axis<D>(i, 1);
+        constexpr int s0 = cvec<D>(i, a0), s1 = cvec<D>(i, a1);
+        constexpr int po = D == 2 ? 0 : (a0 == 0 ? (a1 == 1 ? 0 : 1) : 2);
+        S = -kd * (real(s0) * m[a0] + real(s1) * m[a1]) * ic + real(0.25 * s0 * s1) * Po[po] * ic2 +
+            kd * (real(s0) * Y[a0] + real(s1) * Y[a1]) * ic3;
+      }
+      const real pe = fe.template moving<i>(), ps = fs.template moving<i>();
+      se += pe;
+      ss += ps;
+      const real gi = ld(Gsj + (size_t)i * n, src);
+      const real feq = rj * pe, fst = rj * ps;
+      st(Gnj + (size_t)i * n, node, gi - w1 * (gi - fst) - w1 * r12 * (fst - feq) + wt * S);
+    });
+    const real S0 = -(trP + e) * ic2;
+    const real feq = rj * fe.rest(se), fst = rj * fs.rest(ss);
+    const real gi = ld(Gsj, src);
+    st(Gnj, node, gi - w1 * (gi - fst) - w1 * r12 * (fst - feq) + wt * S0);
+  }
+  return 0.0;
+}
+
+// inlet node: equilibrium at the inlet state with the velocity of the first
+// interior plane of its row (Sec. 6)
+template <typename real, int D, int NS>
+__device__ inline void inlet_node(const Params<real> &p, const Bufs<real> &b, int cur, int node) {
+  constexpr int Q = lat_q<D>();
+  const int n = p.n;
+  const int row = node - node % p.nx;
+  const int src = row + 2;
+  const bool ok = gaslike(b.kind[src]);
+  real u[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) u[a] = ok ? ld(b.F + (size_t)fo_u(NS, a) * n, src) : real(0);
+  real *Gn = b.G[cur ^ 1];
+#pragma unroll 1
+  for (int j = 0; j < NS; ++j) {
+    real f[Q];
+    equilibrium<real, D>(p.rho_in[j], p.sqM[j], u, p.T_in, f);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) st(Gn + (size_t)(j * Q + i) * n, node, f[i]);
+  }
+}
+
+template <typename real, int D, int NS>
+__global__ void __launch_bounds__(BLOCK) k_collide(Params<real> p, Bufs<real> b, int cur) {
+  const int nb = (p.n_gas + BLOCK - 1) / BLOCK, lb = xcd_block(nb);
+  if (lb >= nb) return;  // whole block: no barrier follows for it
+  const int t = lb * BLOCK + threadIdx.x;
+  double work = 0.0;
+  if (t < p.n_gas) {
+    const int node = (int)b.gas_list[t];
+    const uint8_t k = b.kind[node];
+    if (p.F[0] != real(0) || p.F[1] != real(0) || (D == 3 && p.F[2] != real(0))) {
+      // work of the body force this step, rho u.F (half the trace of its source)
+      const int n = p.n;
+      real rhot = 0, uf = 0;
+#pragma unroll
+      for (int j = 0; j < NS; ++j) rhot += ld(b.F + (size_t)fo_rho(j) * n, node);
+#pragma unroll
+      for (int a = 0; a < D; ++a) uf += ld(b.F + (size_t)fo_u(NS, a) * n, node) * p.F[a];
+      work = (double)(rhot * uf);
+    }
+    if (k == KIND_INLET) {
+      inlet_node<real, D, NS>(p, b, cur, node);
+    } else {
+      const int src = k == KIND_OUTLET ? node - node % p.nx + p.nx - 3 : node;
+      collide_node<real, D, NS>(p, b, cur, node, src);
+    }
+  }
+  const double s = block_sum(work);
+  if (threadIdx.x == 0 && s != 0.0) b.acc_work[lb] += s;
+}
+
+// ===========================================================================
+// k_solid: forward-Euler heat step over an LDS tile with a one-node halo
+// ===========================================================================
+template <typename real, int D>
+__global__ void __launch_bounds__(BLOCK) k_solid(Params<real> p, Bufs<real> b, int cur) {
+  constexpr int TX = SolidTile<D>::TX, TY = SolidTile<D>::TY, TZ = SolidTile<D>::TZ;
+  constexpr int HX = TX + 2, HY = TY + 2, HZ = D == 3 ? TZ + 2 : 1;
+  __shared__ real sT[HZ * HY * HX];
+  __shared__ uint8_t sK[HZ * HY * HX];  // 1 solid, 0 not solid, 2 outside a closed axis
+  const int tilesX = (p.nx + TX - 1) / TX, tilesY = (p.ny + TY - 1) / TY;
+  int bid = blockIdx.x;
+  const int bx = bid % tilesX;
+  bid /= tilesX;
+  const int by = bid % tilesY;
+  const int bz = bid / tilesY;
+  const int x0 = bx * TX - 1, y0 = by * TY - 1, z0 = D == 3 ? bz * TZ - 1 : 0;
+  const real *Ts = b.Ts[cur];
+  for (int q = threadIdx.x; q < HZ * HY * HX; q += BLOCK) {
+    const int hx = q % HX, hy = (q / HX) % HY, hz = q / (HX * HY);
+    int x = x0 + hx, y = y0 + hy, z = z0 + hz;
+    uint8_t k = 0;
+    real v = 0;
+    bool out = false;
+    if (x < 0 || x >= p.nx) {
+      if (p.per[0]) x = (x + p.nx) % p.nx;
+      else out = true;
+    }
+    if (y < 0 || y >= p.ny) {
+      if (p.per[1]) y = (y + p.ny) % p.ny;
+      else out = true;
+    }
+    if (D == 3 && (z < 0 || z >= p.nz)) {
+      if (p.per[2]) z = (z + p.nz) % p.nz;
+      else out = true;
+    }
+    if (out) {
+      k = 2;
+    } else {
+      const int nd = x + p.nx * (y + p.ny * z);
+      const uint8_t kd = b.kind[nd];
+      if (kd == KIND_SOLID || kd == KIND_WALL) {
+        k = 1;
+        v = Ts[nd];
+      }
+    }
+    sK[q] = k;
+    sT[q] = v;
+  }
+  __syncthreads();
+  double bflux = 0.0;
+  for (int q = threadIdx.x; q < TX * TY * TZ; q += BLOCK) {
+    const int lx = q % TX, ly = (q / TX) % TY, lz = q / (TX * TY);
+    const int x = x0 + 1 + lx, y = y0 + 1 + ly, z = z0 + (D == 3 ? 1 : 0) + lz;
+    if (x >= p.nx || y >= p.ny || (D == 3 && z >= p.nz)) continue;
+    const int hc = (lz + (D == 3 ? 1 : 0)) * HY * HX + (ly + 1) * HX + (lx + 1);
+    if (sK[hc] != 1) continue;
+    const real T = sT[hc];
+    real lap = 0, bf = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int d = -1; d <= 1; d += 2) {
+        const int off = a == 0 ? d : (a == 1 ? d * HX : d * HX * HY);
+        const uint8_t kn = sK[hc + off];
+        if (kn == 1) lap += sT[hc + off] - T;
+        else if (kn == 2) {
+          const int face = 2 * a + (d > 0 ? 1 : 0);
+          if (p.has_bc[face]) {
+            lap += p.T_bc[face] - T;
+            bf += p.T_bc[face] - T;
+          }
+        }
+      }
+    const int nd = x + p.nx * (y + p.ny * z);
+    real Tn = T + p.alpha_s * lap;
+    if (p.wall_mode == 0 && b.kind[nd] == KIND_WALL)
+      Tn += (-p.dH * b.wall_r[nd] - b.wall_dE[nd]) * p.invCs;
+    b.Ts[cur ^ 1][nd] = Tn;
+    bflux += (double)(p.alpha_s * p.C_s * bf);
+  }
+  const double s = block_sum(bflux);
+  if (threadIdx.x == 0 && s != 0.0) b.acc_bheat[blockIdx.x] += s;
+}
+
+// ===========================================================================
+// k_observe: FP64 partial sums per block over all nodes.  Slots per block:
+// [0, NS) species mass; then e_gas, e_solid, T_min, T_max, u_max, rho_min,
+// Ts_min, Ts_max, bad.
+// ===========================================================================
+template <typename real, int D, int NS>
+__global__ void __launch_bounds__(BLOCK) k_observe(Params<real> p, Bufs<real> b, int cur) {
+  constexpr int Q = lat_q<D>();
+  constexpr int NP = NS + 9;
+  constexpr int S_EG = NS, S_ES = NS + 1, S_TMIN = NS + 2, S_TMAX = NS + 3, S_UMAX = NS + 4,
+                S_RMIN = NS + 5, S_TSMIN = NS + 6, S_TSMAX = NS + 7, S_BAD = NS + 8;
+  __shared__ double sh[NP][BLOCK];
+  double acc[NP];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) acc[k] = 0.0;
+  acc[S_EG] = acc[S_ES] = acc[S_UMAX] = acc[S_BAD] = 0.0;
+  acc[S_TMIN] = acc[S_RMIN] = acc[S_TSMIN] = 1e300;
+  acc[S_TMAX] = acc[S_TSMAX] = -1e300;
+  const real *G = b.G[cur];
+  const int n = p.n;
+  for (int node = blockIdx.x * BLOCK + threadIdx.x; node < n; node += gridDim.x * BLOCK) {
+    const uint8_t k = b.kind[node];
+    if (k == KIND_SOLID || k == KIND_WALL) {
+      const double ts = (double)b.Ts[cur][node];
+      acc[S_ES] += (double)p.C_s * ts;
+      acc[S_TSMIN] = fmin(acc[S_TSMIN], ts);
+      acc[S_TSMAX] = fmax(acc[S_TSMAX], ts);
+      if (!(ts > 0.0) || !isfinite(ts)) acc[S_BAD] = 1.0;
+    }
+    if (!(gaslike(k) || k == KIND_WALL)) continue;
+    const uint32_t em = b.emask[node];
+    double E = 0, rhot = 0, C = 0, J[3] = {0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      double rj = 0, Ej = 0, Jj[3] = {0, 0, 0};
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        if (k == KIND_WALL && !(em & (1u << i))) continue;
+        const double gv = (double)G[(size_t)(j * Q + i) * n + node];
+        if (!isfinite(gv)) acc[S_BAD] = 1.0;
+        rj += gv;
+        Ej += (double)cnorm2<D>(i) * gv;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Jj[a] += (double)cvec<D>(i, a) * gv;
+      }
+      acc[j] += rj;
+      E += (double)p.cj2[j] * Ej;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) J[a] += (double)p.cj[j] * Jj[a];
+      if (gaslike(k)) {
+        rhot += rj;
+        C += rj / (double)p.M[j];
+        acc[S_RMIN] = fmin(acc[S_RMIN], rj);
+      }
+    }
+    acc[S_EG] += 0.5 * E;
+    if (gaslike(k)) {
+      const double u2 = (J[0] * J[0] + J[1] * J[1] + J[2] * J[2]) / (rhot * rhot);
+      const double T = (E - rhot * u2) / (D * C);
+      acc[S_TMIN] = fmin(acc[S_TMIN], T);
+      acc[S_TMAX] = fmax(acc[S_TMAX], T);
+      acc[S_UMAX] = fmax(acc[S_UMAX], sqrt(u2));
+      if (!(T > 0.0) || !(rhot > 0.0)) acc[S_BAD] = 1.0;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NP; ++k) sh[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int s = BLOCK / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      const int o = threadIdx.x + s;
+#pragma unroll
+      for (int k = 0; k < NS + 2; ++k) sh[k][threadIdx.x] += sh[k][o];
+      sh[S_TMIN][threadIdx.x] = fmin(sh[S_TMIN][threadIdx.x], sh[S_TMIN][o]);
+      sh[S_TMAX][threadIdx.x] = fmax(sh[S_TMAX][threadIdx.x], sh[S_TMAX][o]);
+      sh[S_UMAX][threadIdx.x] = fmax(sh[S_UMAX][threadIdx.x], sh[S_UMAX][o]);
+      sh[S_RMIN][threadIdx.x] = fmin(sh[S_RMIN][threadIdx.x], sh[S_RMIN][o]);
+      sh[S_TSMIN][threadIdx.x] = fmin(sh[S_TSMIN][threadIdx.x], sh[S_TSMIN][o]);
+      sh[S_TSMAX][threadIdx.x] = fmax(sh[S_TSMAX][threadIdx.x], sh[S_TSMAX][o]);
+      sh[S_BAD][threadIdx.x] = fmax(sh[S_BAD][threadIdx.x], sh[S_BAD][o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < NP; ++k) b.partials[(size_t)blockIdx.x * NP + k] = sh[k][0];
+}
+
+// ===========================================================================
+// launchers
+// ===========================================================================
+template <typename real, int D, int NS>
+inline hipError_t step_impl(const Params<real> &p, const Bufs<real> &b, int cur,
+                            LaunchInfo &li) {
+  const int gwf = (p.n_wall_fast + BLOCK - 1) / BLOCK, gws = (p.n_wall - p.n_wall_fast + BLOCK - 1) / BLOCK;
+  const int ggf = (p.n_gas_fast + BLOCK - 1) / BLOCK, ggs = (p.n_gas - p.n_gas_fast + BLOCK - 1) / BLOCK;
+  const int gg = (p.n_gas + BLOCK - 1) / BLOCK;
+  hipStream_t st = li.stream;
+  auto mark = [&](int k, int which) {
+    if (li.events) {
+      (void)hipEventRecord(li.events[2 * k + which], st);
+      li.recorded[k] = true;
+    }
+  };
+  mark(K_WALL_ID, 0);
+  if (gwf > 0) hipLaunchKernelGGL((k_wall<true, real, D, NS>), dim3(xcd_grid(gwf)), dim3(BLOCK), 0, st, p, b, cur);
+  if (gws > 0) hipLaunchKernelGGL((k_wall<false, real, D, NS>), dim3(xcd_grid(gws)), dim3(BLOCK), 0, st, p, b, cur);
+  mark(K_WALL_ID, 1);
+  mark(K_MOMENTS_ID, 0);
+  if (ggf > 0) hipLaunchKernelGGL((k_moments<true, real, D, NS>), dim3(xcd_grid(ggf)), dim3(BLOCK), 0, st, p, b, cur);
+  if (ggs > 0) hipLaunchKernelGGL((k_moments<false, real, D, NS>), dim3(xcd_grid(ggs)), dim3(BLOCK), 0, st, p, b, cur);
+  mark(K_MOMENTS_ID, 1);
+  mark(K_COLLIDE_ID, 0);
+  if (gg > 0) hipLaunchKernelGGL((k_collide<real, D, NS>), dim3(xcd_grid(gg)), dim3(BLOCK), 0, st, p, b, cur);
+  mark(K_COLLIDE_ID, 1);
+  if (li.n_solid > 0) {
+    const int tiles = solid_tiles<D>(p.nx, p.ny, p.nz);
+    mark(K_SOLID_ID, 0);
+    hipLaunchKernelGGL((k_solid<real, D>), dim3(tiles), dim3(BLOCK), 0, st, p, b, cur);
+    mark(K_SOLID_ID, 1);
+  }
+  return hipGetLastError();
+}
+
+template <typename real, int D, int NS>
+inline hipError_t observe_impl(const Params<real> &p, const Bufs<real> &b, int cur, int blocks,
+                               hipStream_t st) {
+  hipLaunchKernelGGL((k_observe<real, D, NS>), dim3(blocks), dim3(BLOCK), 0, st, p, b, cur);
+  return hipGetLastError();
+}
+
+// species-count dispatch for one (precision, lattice); FDLBM_NS_CASES lists
+// the species counts this translation unit instantiates
+template <typename real, int D>
+hipError_t step_lat(const Params<real> &p, const Bufs<real> &b, int cur, LaunchInfo &li) {
+  switch (p.ns) {
+#define FDLBM_CASE(k) \
+  case k:             \
+    return step_impl<real, D, k>(p, b, cur, li);
+    FDLBM_NS_CASES
+#undef FDLBM_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename real, int D>
+hipError_t observe_lat(const Params<real> &p, const Bufs<real> &b, int cur, int blocks,
+                       hipStream_t st) {
+  switch (p.ns) {
+#define FDLBM_CASE(k) \
+  case k:             \
+    return observe_impl<real, D, k>(p, b, cur, blocks, st);
+    FDLBM_NS_CASES
+#undef FDLBM_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace fdlbm

@@ -1,0 +1,42 @@
+// Host-callable launchers of the step and observe kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fdlbm_device.h"
+
+namespace fdlbm {
+
+enum { K_WALL_ID = 0, K_MOMENTS_ID = 1, K_COLLIDE_ID = 2, K_SOLID_ID = 3, K_INOUT_ID = 4,
+       K_NUM = 5 };
+
+struct LaunchInfo {
+  hipStream_t stream;
+  int n_solid;
+  hipEvent_t *events;  // 2 per kernel id (start, stop) or null
+  bool recorded[K_NUM];  // set by the launcher for the ids it recorded
+};
+
+// one time step on lattice D: wall, moments, collide, solid, inlet/outlet
+template <typename real, int D>
+hipError_t step_lat(const Params<real> &p, const Bufs<real> &b, int cur, LaunchInfo &li);
+
+// observables: writes (ns + 9) doubles per block into b.partials
+template <typename real, int D>
+hipError_t observe_lat(const Params<real> &p, const Bufs<real> &b, int cur, int blocks,
+                       hipStream_t st);
+
+template <typename real>
+inline hipError_t launch_step(int D, const Params<real> &p, const Bufs<real> &b, int cur,
+                              LaunchInfo &li) {
+  return D == 2 ? step_lat<real, 2>(p, b, cur, li) : step_lat<real, 3>(p, b, cur, li);
+}
+
+template <typename real>
+inline hipError_t launch_observe(int D, const Params<real> &p, const Bufs<real> &b, int cur,
+                                 int blocks, hipStream_t st) {
+  return D == 2 ? observe_lat<real, 2>(p, b, cur, blocks, st)
+                : observe_lat<real, 3>(p, b, cur, blocks, st);
+}
+
+}  // namespace fdlbm

@@ -1,0 +1,228 @@
+"""Python binding of the HIP library libfdlbm.so (C ABI in include/fdlbm.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  PyTorch provides the device workspace (one uint8 tensor) and the
+stream.  If the library is not built, importing works but creating a `Sim`
+raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfdlbm.so")
+
+# constants mirrored from include/fdlbm.h
+OK, E_INVALID, E_GEOMETRY, E_ALIGN, E_HIP, E_UNSTABLE, E_STATE = 0, -1, -2, -3, -4, -5, -6
+D2Q9, D3Q19 = 2, 3
+F64, F32 = 0, 1
+CORR_DIFFUSION, CORR_VISCOUS, CORR_ENERGY, CORR_PRANDTL, CORR_ALL = 1, 2, 4, 8, 15
+WALL_REACTIVE, WALL_ISOTHERMAL = 0, 1
+FIELD_RHO, FIELD_U, FIELD_T, FIELD_TS, FIELD_POP, FIELD_KIND, FIELD_WALL_R, FIELD_WALL_DE = range(8)
+K_WALL, K_MOMENTS, K_COLLIDE, K_SOLID, K_INOUT = range(5)
+KERNEL_NAMES = ["k_wall", "k_moments", "k_collide", "k_solid", "k_inout"]
+MAX_SPECIES = 8
+
+EXPORTS = ["fdlbm_create", "fdlbm_destroy", "fdlbm_last_error", "fdlbm_set_geometry",
+           "fdlbm_set_species", "fdlbm_set_solid", "fdlbm_set_reaction", "fdlbm_set_flow",
+           "fdlbm_workspace_bytes", "fdlbm_bind_workspace", "fdlbm_init_fields", "fdlbm_step",
+           "fdlbm_sync", "fdlbm_observe", "fdlbm_get_field", "fdlbm_state_bytes",
+           "fdlbm_save_state", "fdlbm_load_state", "fdlbm_set_profiling", "fdlbm_kernel_times",
+           "fdlbm_counts"]
+
+
+class FdlbmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"fdlbm error {code}: {msg}")
+        self.code = code
+
+
+class Desc(ct.Structure):
+    _fields_ = [("lattice", ct.c_int), ("nx", ct.c_int), ("ny", ct.c_int), ("nz", ct.c_int),
+                ("periodic", ct.c_int * 3), ("precision", ct.c_int), ("n_species", ct.c_int),
+                ("hip_stream", ct.c_void_p)]
+
+
+class Obs(ct.Structure):
+    _fields_ = [("mass", ct.c_double * MAX_SPECIES), ("e_gas", ct.c_double),
+                ("e_solid", ct.c_double), ("moles_reacted", ct.c_double),
+                ("heat_released", ct.c_double), ("heat_boundary", ct.c_double),
+                ("work_body", ct.c_double), ("T_min", ct.c_double), ("T_max", ct.c_double),
+                ("u_max", ct.c_double), ("rho_min", ct.c_double), ("Ts_min", ct.c_double),
+                ("Ts_max", ct.c_double), ("step", ct.c_int64), ("bad", ct.c_int32),
+                ("n_gas", ct.c_int32), ("n_wall", ct.c_int32), ("n_solid", ct.c_int32)]
+
+    def as_dict(self, ns: int) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "mass"}
+        d["mass"] = np.array(self.mass[:ns])
+        return d
+
+
+_lib = None
+
+
+def lib() -> ct.CDLL:
+    """Load libfdlbm.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FdlbmError(E_STATE, f"{LIB_PATH} is not built (run paper_1804_07588_amd/build.py)")
+        L = ct.CDLL(LIB_PATH)
+        vp, dp, i64 = ct.c_void_p, ct.POINTER(ct.c_double), ct.c_int64
+        L.fdlbm_create.argtypes = [ct.POINTER(Desc), ct.POINTER(vp)]
+        L.fdlbm_destroy.argtypes = [vp]
+        L.fdlbm_destroy.restype = None
+        L.fdlbm_last_error.argtypes = [vp]
+        L.fdlbm_last_error.restype = ct.c_char_p
+        L.fdlbm_set_geometry.argtypes = [vp, ct.POINTER(ct.c_uint8), ct.c_int]
+        L.fdlbm_set_species.argtypes = [vp, dp, dp, ct.c_double, dp, ct.c_double, ct.c_double,
+                                        ct.c_double, ct.c_double, ct.c_double, ct.c_uint]
+        L.fdlbm_set_solid.argtypes = [vp, ct.c_double, ct.c_double, dp]
+        L.fdlbm_set_reaction.argtypes = [vp, dp, dp, ct.c_double, ct.c_double, ct.c_double,
+                                         ct.c_double, ct.c_int, ct.c_double, ct.c_double, ct.c_int]
+        L.fdlbm_set_flow.argtypes = [vp, dp, dp, ct.c_double, ct.c_double]
+        L.fdlbm_workspace_bytes.argtypes = [vp, ct.POINTER(ct.c_size_t)]
+        L.fdlbm_bind_workspace.argtypes = [vp, vp, ct.c_size_t]
+        L.fdlbm_init_fields.argtypes = [vp, dp, dp, dp, dp]
+        L.fdlbm_step.argtypes = [vp, i64]
+        L.fdlbm_sync.argtypes = [vp]
+        L.fdlbm_observe.argtypes = [vp, ct.POINTER(Obs)]
+        L.fdlbm_get_field.argtypes = [vp, ct.c_int, ct.c_int, dp]
+        L.fdlbm_state_bytes.argtypes = [vp, ct.POINTER(ct.c_size_t)]
+        L.fdlbm_save_state.argtypes = [vp, vp, ct.c_size_t]
+        L.fdlbm_load_state.argtypes = [vp, vp, ct.c_size_t]
+        L.fdlbm_set_profiling.argtypes = [vp, ct.c_int]
+        L.fdlbm_kernel_times.argtypes = [vp, dp, ct.POINTER(i64)]
+        L.fdlbm_counts.argtypes = [vp, ct.POINTER(i64), ct.POINTER(i64), ct.POINTER(i64)]
+        _lib = L
+    return _lib
+
+
+def _d(a: np.ndarray):
+    return a.ctypes.data_as(ct.POINTER(ct.c_double))
+
+
+def _arr(x) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+
+
+class Sim:
+    """One simulation on the current HIP device, built from a workload dict
+    (see workloads.py).  precision: F64 or F32.  stream: a torch.cuda.Stream
+    or None for torch's current stream."""
+
+    def __init__(self, cfg: dict, precision: int = F32, init: dict | None = None, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise FdlbmError(E_STATE, "no HIP device available")
+        L = lib()
+        self.cfg = cfg
+        self.ns = len(cfg["species"]["M"])
+        self.nx, self.ny, self.nz = cfg["nx"], cfg["ny"], cfg["nz"]
+        self.n = self.nx * self.ny * self.nz
+        self.Q = 9 if cfg["lattice"] == 2 else 19
+        self.precision = precision
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        d = Desc(cfg["lattice"], self.nx, self.ny, self.nz,
+                 (ct.c_int * 3)(*[int(p) for p in cfg["periodic"]]), precision, self.ns,
+                 ct.c_void_p(self.stream.cuda_stream))
+        h = ct.c_void_p()
+        rc = L.fdlbm_create(ct.byref(d), ct.byref(h))
+        if rc != OK:
+            raise FdlbmError(rc, "fdlbm_create rejected the description")
+        self.h = h
+        mask = np.ascontiguousarray(np.asarray(cfg["mask"], dtype=np.uint8).reshape(-1))
+        self._check(L.fdlbm_set_geometry(h, mask.ctypes.data_as(ct.POINTER(ct.c_uint8)),
+                                         int(cfg.get("inout", 0))))
+        sp = cfg["species"]
+        M, mu0, Djk = _arr(sp["M"]), _arr(sp["mu0"]), _arr(sp["Djk0"]).reshape(-1)
+        self._check(L.fdlbm_set_species(h, _d(M), _d(mu0), sp["mu_T_exp"], _d(Djk), sp["D_T_exp"],
+                                        sp["D_p_exp"], sp["T_ref"], sp["p_ref"], sp["Pr"],
+                                        int(sp["flags"])))
+        so = cfg["solid"]
+        tbc = _arr(so["T_bc"])
+        self._check(L.fdlbm_set_solid(h, so["alpha_s"], so["C_s"], _d(tbc)))
+        rx = cfg["reaction"]
+        nu, order = _arr(rx["nu"]), _arr(rx["order"])
+        self._check(L.fdlbm_set_reaction(h, _d(nu), _d(order), rx["k0"], rx["ea"], rx["T_ref"],
+                                         rx["dH"], int(rx["wall_mode"]), rx["T_iso"], rx["tol"],
+                                         int(rx["max_iter"])))
+        fl = cfg["flow"]
+        F, Xin = _arr(fl["F"]), _arr(fl["X_in"])
+        self._check(L.fdlbm_set_flow(h, _d(F), _d(Xin), fl["p_in"], fl["T_in"]))
+        nbytes = ct.c_size_t()
+        self._check(L.fdlbm_workspace_bytes(h, ct.byref(nbytes)))
+        self.workspace_bytes = nbytes.value
+        with torch.cuda.stream(self.stream):
+            self.workspace = torch.empty(nbytes.value + 256, dtype=torch.uint8, device="cuda")
+        ptr = self.workspace.data_ptr()
+        aligned = (ptr + 255) & ~255
+        self._check(L.fdlbm_bind_workspace(h, ct.c_void_p(aligned), nbytes.value))
+        if init is not None:
+            self.init_fields(init)
+
+    def _check(self, rc: int):
+        if rc != OK:
+            raise FdlbmError(rc, lib().fdlbm_last_error(self.h).decode())
+
+    def counts(self) -> tuple[int, int, int]:
+        a, b, c = ct.c_int64(), ct.c_int64(), ct.c_int64()
+        self._check(lib().fdlbm_counts(self.h, ct.byref(a), ct.byref(b), ct.byref(c)))
+        return a.value, b.value, c.value
+
+    def init_fields(self, init: dict):
+        rho, u = _arr(init["rho"]).reshape(-1), _arr(init["u"]).reshape(-1)
+        T, Ts = _arr(init["T"]), _arr(init["Ts"])
+        self._check(lib().fdlbm_init_fields(self.h, _d(rho), _d(u), _d(T), _d(Ts)))
+
+    def step(self, n: int = 1):
+        self._check(lib().fdlbm_step(self.h, int(n)))
+
+    def sync(self):
+        self._check(lib().fdlbm_sync(self.h))
+
+    def observe(self) -> dict:
+        o = Obs()
+        self._check(lib().fdlbm_observe(self.h, ct.byref(o)))
+        return o.as_dict(self.ns)
+
+    def field(self, fid: int, comp: int = 0) -> np.ndarray:
+        size = self.Q * self.n if fid == FIELD_POP else self.n
+        out = np.zeros(size)
+        self._check(lib().fdlbm_get_field(self.h, fid, comp, _d(out)))
+        return out
+
+    def save_state(self) -> bytes:
+        nb = ct.c_size_t()
+        self._check(lib().fdlbm_state_bytes(self.h, ct.byref(nb)))
+        buf = ct.create_string_buffer(nb.value)
+        self._check(lib().fdlbm_save_state(self.h, buf, nb.value))
+        return buf.raw
+
+    def load_state(self, data: bytes):
+        buf = ct.create_string_buffer(data, len(data))
+        self._check(lib().fdlbm_load_state(self.h, buf, len(data)))
+
+    def set_profiling(self, on: bool):
+        self._check(lib().fdlbm_set_profiling(self.h, 1 if on else 0))
+
+    def kernel_times(self) -> tuple[dict, int]:
+        avg = np.zeros(5)
+        cnt = ct.c_int64()
+        self._check(lib().fdlbm_kernel_times(self.h, _d(avg), ct.byref(cnt)))
+        return {KERNEL_NAMES[k]: float(avg[k]) for k in range(5)}, cnt.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fdlbm_destroy(self.h)
+            self.h = None
+            self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -156,11 +156,12 @@ WGS_M = [14.0, 9.0, 22.0, 1.0, 14.0]
 def packed_bed(n: int = 128, radius: float = 6.0, porosity: float = 0.6,
                seed: int = 12345, buffer: int = 8, mask: np.ndarray | None = None,
                k0: float = 1e-3, force: float = 2e-5, mu_scale: float = 0.0218,
-               d_scale: float = 0.0471) -> dict:
+               d_scale: float = 0.0471, trace: float = 1e-4) -> dict:
     """3-D D3Q19 packed bed with water-gas-shift chemistry on the sphere surfaces.
 
     Species CO, H2O, CO2, H2, N2 (masses 14, 9, 22, 1, 14 relative to H2);
-    inlet mole fractions 0.1, 0.3, 1e-6, 1e-6, rest N2; T0 = 1/3 (403 K),
+    inlet mole fractions 0.1, 0.3, `trace`, `trace` (products start as traces:
+    a zero density has no species velocity), rest N2; T0 = 1/3 (403 K),
     C = 1.  Rate r = k0 exp[ea (1 - T_ref/T_w)] C_CO C_H2O with ea = 84 kJ/mol /
     (R 403 K) = 25.07, reaction enthalpy -4.1 kJ/mol = -0.408 lattice units
     (one lattice energy per mole = 3 R 403 K).  Synthetic transport:
@@ -175,7 +176,7 @@ def packed_bed(n: int = 128, radius: float = 6.0, porosity: float = 0.6,
     ns = len(M)
     djk = [[0.0 if j == k else d_scale * float(np.sqrt(0.5 * (1.0 / M[j] + 1.0 / M[k])))
             for k in range(ns)] for j in range(ns)]
-    X_in = [0.1, 0.3, 1e-6, 1e-6]
+    X_in = [0.1, 0.3, trace, trace]
     X_in.append(1.0 - sum(X_in))
     cs = 100.0 * 2.5
     nz, ny, nx = mask.shape

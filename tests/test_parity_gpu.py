@@ -1,0 +1,192 @@
+"""GPU (HIP library, through the C ABI) versus the FP64 CPU oracle on the same
+seeded inputs.  Parity metric per field q: max|q_gpu - q_oracle| / scale_q,
+with scale_q = max|q_oracle| for densities, populations, temperatures and
+the reaction rate, and the lattice sound speed sqrt(T0) = 0.577 for the
+velocity components (the natural velocity scale of the scheme: max|u| is
+~1e-4..1e-2 in these runs, far below the population scale the FP32 storage
+rounds at).
+
+Tolerances: FP64 runs agree to rounding (1e-10 after hundreds of steps: the
+two sides sum in different orders and the GPU uses closed forms where the
+oracle inverts matrices).  FP32 runs: 1e-5 relative on every field except
+the wall reaction rate, a product of two FP32 wall densities (2e-5).
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as of
+from paper_1804_07588_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+T0 = 1.0 / 3.0
+
+
+@pytest.fixture(scope="module")
+def fd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1804_07588_amd import fdlbm
+    fdlbm.lib()  # raises if the library is missing: no fallback
+    return fdlbm
+
+
+def run_both(oracle_lib, fd, cfg, init, steps, precision):
+    print(f"[parity] {cfg['lattice']}D n={cfg['nx']}x{cfg['ny']}x{cfg['nz']} ns="
+          f"{len(cfg['species']['M'])} steps={steps} prec={'f64' if precision == fd.F64 else 'f32'}",
+          flush=True)
+    o = oracle_lib.OracleSim(cfg, init)
+    g = fd.Sim(cfg, precision=precision, init=init)
+    o.step(steps)
+    g.step(steps)
+    g.sync()
+    return o, g
+
+
+def rel_err(a, b):
+    scale = np.abs(b).max()
+    return np.abs(a - b).max() / (scale if scale > 0 else 1.0)
+
+
+def field_errors(o, g, fd, ns, D):
+    errs = {}
+    for j in range(ns):
+        errs[f"rho{j}"] = rel_err(g.field(fd.FIELD_RHO, j), o.field(of.OF_RHO, j))
+        errs[f"pop{j}"] = rel_err(g.field(fd.FIELD_POP, j), o.field(of.OF_POP, j))
+    # velocity components relative to the lattice sound speed sqrt(T0)
+    cs = np.sqrt(T0)
+    for a in range(D):
+        errs[f"u{a}"] = np.abs(g.field(fd.FIELD_U, a) - o.field(of.OF_U, a)).max() / cs
+    errs["T"] = rel_err(g.field(fd.FIELD_T), o.field(of.OF_T))
+    errs["Ts"] = rel_err(g.field(fd.FIELD_TS), o.field(of.OF_TS))
+    errs["wall_r"] = rel_err(g.field(fd.FIELD_WALL_R), o.field(of.OF_WALL_R))
+    return errs
+
+
+def assert_errs(errs, tol, tol_rate=None):
+    print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k, v in errs.items():
+        t = tol_rate if (tol_rate is not None and k == "wall_r") else tol
+        assert v <= t, (k, v)
+
+
+def noisy_2d(seed=11, nx=32, ny=24, M=(1.0, 4.0, 9.0)):
+    rng = np.random.default_rng(seed)
+    mask = (rng.random((1, ny, nx)) < 0.3).astype(np.uint8)
+    mask[:, :2, :] = 1
+    mask[:, -2:, :] = 1
+    ns = len(M)
+    dab = 0.05
+    cfg = W.channel_c1(nx=nx, ny=ny, wall=2)
+    cfg["mask"] = mask
+    cfg["species"].update(M=list(M), mu0=[0.05 * np.sqrt(m) for m in M],
+                          Djk0=[[0 if j == k else dab for k in range(ns)] for j in range(ns)],
+                          Pr=0.71)
+    cfg["reaction"].update(nu=[-1.0, 1.0, 0.0][:ns], order=[1.0, 0.0, 0.0][:ns], k0=5e-3, ea=3.0,
+                           dH=-0.2)
+    cfg["flow"].update(F=[2e-6, 0, 0], X_in=[0.5, 0.2, 0.3][:ns])
+    cfg["init"].update(X=[0.5, 0.2, 0.3][:ns])
+    return cfg
+
+
+def small_bed(n=20, inout=1, seed=3):
+    mask, _ = W.sphere_pack_mask(n, radius=3.0, porosity=0.6, seed=seed, buffer=4)
+    cfg = W.packed_bed(mask=mask, k0=1e-3, force=1e-5)
+    if not inout:
+        cfg["inout"] = 0
+        cfg["periodic"] = (1, 1, 1)
+    return cfg
+
+
+def test_c1_fp64_parity(oracle_lib, fd):
+    cfg = W.channel_c1()
+    o, g = run_both(oracle_lib, fd, cfg, W.uniform_init(cfg), 1000, fd.F64)
+    assert_errs(field_errors(o, g, fd, 2, 2), 1e-10)
+
+
+def test_c1_interpolated_species_fp64(oracle_lib, fd):
+    cfg = W.with_changes(W.channel_c1(), init=dict(X=[0.7, 0.3]))
+    cfg["species"].update(M=[1.0, 4.0], mu0=[0.1, 0.2])
+    o, g = run_both(oracle_lib, fd, cfg, W.perturbed_init(cfg, 5), 300, fd.F64)
+    assert_errs(field_errors(o, g, fd, 2, 2), 1e-10)
+
+
+def test_porous_2d_three_species_fp64(oracle_lib, fd):
+    """Random porous 2-D geometry: concave corners, thin throats and the
+    degraded stencil classes; three species of masses 1, 4, 9; Pr = 0.71."""
+    cfg = noisy_2d()
+    o, g = run_both(oracle_lib, fd, cfg, W.perturbed_init(cfg, 9), 200, fd.F64)
+    assert_errs(field_errors(o, g, fd, 3, 2), 1e-10)
+
+
+def test_bed_3d_fp64(oracle_lib, fd):
+    """D3Q19 sphere pack with water-gas-shift chemistry, five species,
+    inlet/outlet planes, body force."""
+    cfg = small_bed()
+    o, g = run_both(oracle_lib, fd, cfg, W.perturbed_init(cfg, 4, amp_u=0.005), 40, fd.F64)
+    assert_errs(field_errors(o, g, fd, 5, 3), 1e-10)
+
+
+def test_bed_3d_fp32(oracle_lib, fd):
+    cfg = small_bed(n=20)
+    o, g = run_both(oracle_lib, fd, cfg, W.perturbed_init(cfg, 4, amp_u=0.005), 100, fd.F32)
+    assert_errs(field_errors(o, g, fd, 5, 3), 1e-5, tol_rate=2e-5)
+
+
+def test_c1_fp32(oracle_lib, fd):
+    cfg = W.channel_c1()
+    o, g = run_both(oracle_lib, fd, cfg, W.uniform_init(cfg), 1000, fd.F32)
+    errs = field_errors(o, g, fd, 2, 2)
+    assert_errs(errs, 1e-5, tol_rate=2e-5)
+
+
+def test_observables_fp64(oracle_lib, fd):
+    cfg = noisy_2d()
+    o, g = run_both(oracle_lib, fd, cfg, W.perturbed_init(cfg, 9), 100, fd.F64)
+    a, b = g.observe(), o.observe()
+    print(a, b, flush=True)
+    assert np.allclose(a["mass"], b["mass"], rtol=1e-12)
+    for k in ("e_gas", "e_solid", "moles_reacted", "heat_released", "work_body", "T_min", "T_max",
+              "u_max", "rho_min", "Ts_min", "Ts_max"):
+        assert a[k] == pytest.approx(b[k], rel=1e-10, abs=1e-14), k
+    assert a["heat_boundary"] == pytest.approx(b["heat_boundary"], rel=1e-8, abs=1e-12)
+    for k in ("n_gas", "n_wall", "n_solid", "bad", "step"):
+        assert a[k] == b[k], k
+
+
+def test_deterministic_and_checkpoint(fd):
+    """Two runs from the same state are bitwise identical; a saved state
+    restores bitwise."""
+    cfg = small_bed(n=20)
+    init = W.perturbed_init(cfg, 4, amp_u=0.005)
+    g1 = fd.Sim(cfg, precision=fd.F32, init=init)
+    g2 = fd.Sim(cfg, precision=fd.F32, init=init)
+    g1.step(30)
+    state = g1.save_state()
+    g1.step(20)
+    g2.step(50)
+    for j in range(5):
+        assert np.array_equal(g1.field(fd.FIELD_POP, j), g2.field(fd.FIELD_POP, j))
+    g2.load_state(state)
+    g2.step(20)
+    for j in range(5):
+        assert np.array_equal(g1.field(fd.FIELD_POP, j), g2.field(fd.FIELD_POP, j))
+    assert np.array_equal(g1.field(fd.FIELD_TS), g2.field(fd.FIELD_TS))
+    assert g1.observe()["moles_reacted"] == g2.observe()["moles_reacted"]
+
+
+def test_single_species_and_no_walls(oracle_lib, fd):
+    """Degenerate cases: one species (f* = f^eq), a fully periodic box with
+    no wall node at all."""
+    cfg = dict(lattice=3, nx=12, ny=10, nz=9, periodic=(1, 1, 1),
+               mask=np.zeros((9, 10, 12), np.uint8), inout=0,
+               species=dict(M=[1.0], mu0=[0.1], mu_T_exp=0.5, Djk0=[[0.0]], D_T_exp=1.5,
+                            D_p_exp=1.0, T_ref=T0, p_ref=T0, Pr=0.71, flags=15),
+               solid=dict(alpha_s=0.0, C_s=1.0, T_bc=[np.nan] * 6),
+               reaction=dict(nu=[0.0], order=[0.0], k0=0.0, ea=0.0, T_ref=T0, dH=0.0, wall_mode=0,
+                             T_iso=T0, tol=1e-13, max_iter=8),
+               flow=dict(F=[1e-5, 0, 0], X_in=[1.0], p_in=T0, T_in=T0),
+               init=dict(X=[1.0], C=1.0, T=T0, Ts=T0, u=[0, 0, 0]))
+    o, g = run_both(oracle_lib, fd, cfg, W.perturbed_init(cfg, 1), 50, fd.F64)
+    assert_errs(field_errors(o, g, fd, 1, 3), 1e-11)
