@@ -198,7 +198,7 @@ int fdlbm_load_state(fdlbm_ctx *ctx, const void *host_buf, size_t bytes);
 #define FDLBM_K_MOMENTS 1
 #define FDLBM_K_COLLIDE 2
 #define FDLBM_K_SOLID 3
-#define FDLBM_K_INOUT 4
+#define FDLBM_K_ESUM 4
 #define FDLBM_K_COUNT 5
 int fdlbm_set_profiling(fdlbm_ctx *ctx, int enable);
 int fdlbm_kernel_times(fdlbm_ctx *ctx, double *avg_ms, int64_t *launches);

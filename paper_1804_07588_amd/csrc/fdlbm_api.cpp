@@ -41,14 +41,14 @@ struct fdlbm_ctx {
   // geometry
   int inout = 0;
   std::vector<uint8_t> kind;
-  std::vector<uint64_t> cls;
+  std::vector<uint64_t> cls, gas_cls_host;
   std::vector<uint32_t> emask, gas_list, wall_list;
   int64_t n_gas_fast = 0, n_wall_fast = 0;
   int64_t n_solid = 0;
   // workspace
   char *ws = nullptr;
   size_t ws_bytes = 0;
-  size_t off_G[2]{}, off_Gs = 0, off_F = 0, off_Ts[2]{}, off_wr = 0, off_wde = 0, off_kind = 0, off_cls = 0,
+  size_t off_G[2]{}, off_Gs = 0, off_SM = 0, off_F = 0, off_Ts[2]{}, off_wr = 0, off_wde = 0, off_kind = 0, off_cls = 0, off_gcls = 0,
          off_em = 0, off_gl = 0, off_wl = 0, off_am = 0, off_aw = 0, off_ab = 0, off_part = 0;
   size_t total = 0;
   int acc_slots = 0, obs_blocks = 0;
@@ -95,6 +95,7 @@ static void layout(fdlbm_ctx *c) {
   c->off_G[0] = take(pops);
   c->off_G[1] = take(pops);
   c->off_Gs = take(pops);
+  c->off_SM = take((size_t)c->ns * (c->D + 2) * n * b);
   c->off_F = take((size_t)n_fields(c->D, c->ns) * n * b);
   c->off_Ts[0] = take(n * b);
   c->off_Ts[1] = take(n * b);
@@ -102,13 +103,14 @@ static void layout(fdlbm_ctx *c) {
   c->off_wde = take(n * b);
   c->off_kind = take(n);
   c->off_cls = take(n * 8);
+  c->off_gcls = take(n * 8);
   c->off_em = take(n * 4);
   c->off_gl = take(n * 4);
   c->off_wl = take(n * 4);
   // one accumulator slot per block of the largest grid that accumulates
   const int tiles = c->D == 2 ? solid_tiles<2>(c->d.nx, c->d.ny, c->d.nz)
                               : solid_tiles<3>(c->d.nx, c->d.ny, c->d.nz);
-  c->acc_slots = std::max((int)((n + BLOCK - 1) / BLOCK), tiles) + 8;
+  c->acc_slots = std::max((int)((n + BLOCK - 1) / BLOCK) * c->ns, tiles) + 8 * c->ns + 8;
   c->off_am = take((size_t)c->acc_slots * 8);
   c->off_aw = take((size_t)c->acc_slots * 8);
   c->off_ab = take((size_t)c->acc_slots * 8);
@@ -124,6 +126,7 @@ static Bufs<real> bufs(const fdlbm_ctx *c) {
   b.G[0] = (real *)(w + c->off_G[0]);
   b.G[1] = (real *)(w + c->off_G[1]);
   b.Gs = (real *)(w + c->off_Gs);
+  b.SM = (real *)(w + c->off_SM);
   b.F = (real *)(w + c->off_F);
   b.Ts[0] = (real *)(w + c->off_Ts[0]);
   b.Ts[1] = (real *)(w + c->off_Ts[1]);
@@ -131,6 +134,7 @@ static Bufs<real> bufs(const fdlbm_ctx *c) {
   b.wall_dE = (real *)(w + c->off_wde);
   b.kind = (const uint8_t *)(w + c->off_kind);
   b.cls = (const uint64_t *)(w + c->off_cls);
+  b.gas_cls = (const uint64_t *)(w + c->off_gcls);
   b.emask = (const uint32_t *)(w + c->off_em);
   b.gas_list = (const uint32_t *)(w + c->off_gl);
   b.wall_list = (const uint32_t *)(w + c->off_wl);
@@ -519,9 +523,14 @@ int fdlbm_bind_workspace(fdlbm_ctx *c, void *dev, size_t bytes) {
   HIPCHK(c, hipMemcpyAsync(c->ws + c->off_kind, c->kind.data(), n, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->ws + c->off_cls, c->cls.data(), n * 8, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->ws + c->off_em, c->emask.data(), n * 4, hipMemcpyHostToDevice, c->stream));
-  if (!c->gas_list.empty())
+  if (!c->gas_list.empty()) {
     HIPCHK(c, hipMemcpyAsync(c->ws + c->off_gl, c->gas_list.data(), c->gas_list.size() * 4,
                              hipMemcpyHostToDevice, c->stream));
+    c->gas_cls_host.resize(c->gas_list.size());
+    for (size_t q = 0; q < c->gas_list.size(); ++q) c->gas_cls_host[q] = c->cls[c->gas_list[q]];
+    HIPCHK(c, hipMemcpyAsync(c->ws + c->off_gcls, c->gas_cls_host.data(), c->gas_list.size() * 8,
+                             hipMemcpyHostToDevice, c->stream));
+  }
   if (!c->wall_list.empty())
     HIPCHK(c, hipMemcpyAsync(c->ws + c->off_wl, c->wall_list.data(), c->wall_list.size() * 4,
                              hipMemcpyHostToDevice, c->stream));

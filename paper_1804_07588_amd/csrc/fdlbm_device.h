@@ -111,12 +111,14 @@ template <typename real>
 struct Bufs {
   real *G[2];         // populations [(j*Q + i)*n + node], double-buffered
   real *Gs;           // streamed (pre-collision) populations of the gas nodes
+  real *SM;           // species moments of the streamed populations: rho_j, J_j (D), E_j
   real *F;            // per-step moments: rho_j, tau1_j, tau2_j, u_a (D), T
   real *Ts[2];        // solid temperature, double-buffered
   real *wall_r;       // molar rate per wall node of the last step
   real *wall_dE;      // kinetic energy the wall gave the gas, last step
   const uint8_t *kind;
   const uint64_t *cls;
+  const uint64_t *gas_cls;   // class words in gas-list order
   const uint32_t *emask;
   const uint32_t *gas_list;
   const uint32_t *wall_list;
@@ -149,7 +151,16 @@ template <int D>
 __host__ __device__ inline int fo_ediff(int ns) {
   return 3 * ns + D + 1 + ns * D + D;
 }
-__host__ __device__ inline int n_fields(int D, int ns) { return 3 * ns + D + 1 + ns * D + D + 1; }
+// temperature of f (with the energy of the sources) and of the auxiliary state
+template <int D>
+__host__ __device__ inline int fo_Tf(int ns) {
+  return 3 * ns + D + 1 + ns * D + D + 1;
+}
+template <int D>
+__host__ __device__ inline int fo_Tst(int ns) {
+  return 3 * ns + D + 1 + ns * D + D + 2;
+}
+__host__ __device__ inline int n_fields(int D, int ns) { return 3 * ns + D + 1 + ns * D + D + 3; }
 
 enum : uint8_t { KIND_GAS = 0, KIND_SOLID = 1, KIND_WALL = 2, KIND_INLET = 3, KIND_OUTLET = 4 };
 __host__ __device__ inline bool gaslike(uint8_t k) { return k == KIND_GAS || k >= KIND_INLET; }

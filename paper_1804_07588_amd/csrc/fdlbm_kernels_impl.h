@@ -292,30 +292,60 @@ __global__ void __launch_bounds__(BLOCK) k_wall(Params<real> p, Bufs<real> b, in
 }
 
 // ===========================================================================
-// k_moments: streaming and every local quantity of each gas node (pass 1)
+// k_stream: streaming into every gas node (Eq.(33)-(36)), one thread per
+// (node, moving direction) handling every species (the taps are the same
+// nodes for all species; only the weights differ).  The direction is uniform
+// per block and each XCD walks a contiguous run of (direction, node block),
+// so it works through NS population arrays at a time and the taps a plane
+// away are still in its L2.  The rest population does not move and is read
+// in place by the later kernels.
 // ===========================================================================
 template <bool FAST, typename real, int D, int NS>
-__device__ inline void moments_node(const Params<real> &p, const Bufs<real> &b, int cur,
-                                    const WTab<real> &wtab, const int node, const Addr<D> &ad) {
+__global__ void __launch_bounds__(BLOCK) k_stream(Params<real> p, Bufs<real> b, int cur) {
   constexpr int Q = lat_q<D>();
-  const uint64_t cw = b.cls[node];
-  const real *G = b.G[cur];
-  real *Gs = b.Gs;
+  __shared__ WTab<real> wtab;
+  load_wtab<real, NS>(p, wtab);
+  const int first = FAST ? 0 : p.n_gas_fast, count = FAST ? p.n_gas_fast : p.n_gas - p.n_gas_fast;
+  const int nbn = (count + BLOCK - 1) / BLOCK, nb = nbn * (Q - 1), lb = xcd_block(nb);
+  if (lb >= nb) return;
+  const int im = lb / nbn;  // moving direction index - 1 of this block
+  const int i = 1 + im;
+  const int t = (lb - im * nbn) * BLOCK + threadIdx.x;
+  if (t >= count) return;
+  const int node = (int)b.gas_list[first + t];
+  const int cls = cls_at(b.gas_cls[first + t], i);
+  const Addr<D> ad(node, p);
+  const int n = p.n;
+  real g[NS];
+#pragma unroll
+  for (int j = 0; j < NS; ++j)
+    g[j] = stream_pop<FAST, real, D>(b.G[cur] + (size_t)(j * Q + i) * n, p, ad, j, i, cls, wtab);
+#pragma unroll
+  for (int j = 0; j < NS; ++j) st(b.Gs + (size_t)(j * Q + i) * n, node, g[j]);
+}
+
+// ===========================================================================
+// k_moments: moments of the streamed populations and every local quantity of
+// each gas node (Eq.(3), (5), (7)-(8), (11), (14)-(17), (25)), one thread per node
+// ===========================================================================
+template <typename real, int D, int NS>
+__global__ void __launch_bounds__(BLOCK) k_moments(Params<real> p, Bufs<real> b, int cur) {
+  constexpr int Q = lat_q<D>();
+  const int nb = (p.n_gas + BLOCK - 1) / BLOCK, lb = xcd_block(nb);
+  const int t = lb * BLOCK + threadIdx.x;
+  if (lb >= nb || t >= p.n_gas) return;
+  const int node = (int)b.gas_list[t];
   real *F = b.F;
   const int n = p.n;
   real rho[NS], Jg[NS][D], E = 0;
 #pragma unroll
   for (int j = 0; j < NS; ++j) {
-    asm volatile("" ::: "memory");
-    const real g0 = ld(G + (size_t)(j * Q) * n, node);
-    st(Gs + (size_t)(j * Q) * n, node, g0);
-    real r = g0, Jj[D], Ej = 0;
+    real r = ld(b.G[cur] + (size_t)(j * Q) * n, node), Jj[D], Ej = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) Jj[a] = 0;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-      const real g = stream_pop<FAST, real, D>(G + (size_t)(j * Q + i) * n, p, ad, j, i, cls_at(cw, i), wtab);
-      st(Gs + (size_t)(j * Q + i) * n, node, g);
+      const real g = ld(b.Gs + (size_t)(j * Q + i) * n, node);
       r += g;
 #pragma unroll
       for (int a = 0; a < D; ++a)
@@ -414,21 +444,8 @@ __device__ inline void moments_node(const Params<real> &p, const Bufs<real> &b, 
   st(F + (size_t)fo_ediff<D>(NS) * n, node, ediff);
 }
 
-template <bool FAST, typename real, int D, int NS>
-__global__ void __launch_bounds__(BLOCK) k_moments(Params<real> p, Bufs<real> b, int cur) {
-  __shared__ WTab<real> wtab;
-  load_wtab<real, NS>(p, wtab);
-  const int first = FAST ? 0 : p.n_gas_fast, count = FAST ? p.n_gas_fast : p.n_gas - p.n_gas_fast;
-  const int nb = (count + BLOCK - 1) / BLOCK, lb = xcd_block(nb);
-  const int t = lb * BLOCK + threadIdx.x;
-  if (lb >= nb || t >= count) return;
-  const int node = (int)b.gas_list[first + t];
-  const Addr<D> ad(node, p);
-  moments_node<FAST, real, D, NS>(p, b, cur, wtab, node, ad);
-}
-
 // ===========================================================================
-// k_collide: sources, temperature of f, equilibria and Eq.(24) (pass 2)
+// shared pieces of the source terms
 // ===========================================================================
 template <typename real, int D>
 __device__ inline real q_dev(real rho, real invM, real ua, real T) {
@@ -449,6 +466,108 @@ __device__ inline real r_dev(real rho, real invM, const real *u, real T, int a, 
   return rho * u[a] * u[b] * ((real(2) - real(D + 4) * T) * invM - u2);
 }
 
+// face-neighbour values of the gradient stencils shared by all species
+template <typename real, int D>
+struct NbCommon {
+  real u[D], T;
+  int node;  // node supplying rho_j and tau1_j (self when missing)
+  bool wall, missing;
+};
+
+// face neighbours of src: indices and kinds (no load depends on another)
+template <typename real, int D, int NS>
+__device__ inline void load_neighbours(const Params<real> &p, const Bufs<real> &b, int src,
+                                       NbCommon<real, D> (&nb)[D][2]) {
+  const Addr<D> ad(src, p);
+  const int n = p.n;
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      NbCommon<real, D> &v = nb[a][s];
+      const int q = ad.face(p, a, s == 0 ? +1 : -1);
+      const int qq = q >= 0 ? q : src;
+      const uint8_t k = b.kind[qq];
+      v.wall = q >= 0 && k == KIND_WALL;
+      v.missing = !(q >= 0 && (gaslike(k) || k == KIND_WALL)) || q == src;
+      v.node = v.missing ? src : q;
+#pragma unroll
+      for (int c = 0; c < D; ++c) v.u[c] = ld(b.F + (size_t)fo_u(NS, c) * n, v.node);
+      v.T = ld(b.F + (size_t)fo_T<D>(NS) * n, v.node);
+    }
+}
+
+// energy moment of species j's sources: trace of the second-moment source
+// (body force work, viscous correction) plus the Prandtl energy source
+template <typename real, int D, int NS>
+__device__ inline real energy_source(const Params<real> &p, const Bufs<real> &b, int src, int j,
+                                     const real *u, real Tt, const NbCommon<real, D> (&nb)[D][2]) {
+  const int n = p.n;
+  const real *F = b.F;
+  const bool cvisc = p.flags & 2u, cpr = (p.flags & 8u) && p.kpr != real(0);
+  const real iM = p.invM[j];
+  const real rj = ld(F + (size_t)fo_rho(j) * n, src);
+  real e = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) e += real(2) * rj * u[a] * p.F[a];
+  if (!(cvisc || cpr)) return e;
+  const real tau1x = ld(F + (size_t)fo_tau1(NS, j) * n, src);
+  const real Kx = p.kpr * tau1x * rj * iM * Tt * iM;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const NbCommon<real, D> &sp = nb[a][0], &sm = nb[a][1];
+    const real rp = ld(F + (size_t)fo_rho(j) * n, sp.node), rm = ld(F + (size_t)fo_rho(j) * n, sm.node);
+    if (cvisc) {
+      const real qx = q_dev<real, D>(rj, iM, u[a], Tt);
+      const real qp = sp.wall ? -qx : q_dev<real, D>(rp, iM, sp.u[a], sp.T);
+      const real qm = sm.wall ? -qx : q_dev<real, D>(rm, iM, sm.u[a], sm.T);
+      e += real(0.5) * (qp - qm);
+    }
+    if (cpr) {
+      const real tp = ld(F + (size_t)fo_tau1(NS, j) * n, sp.node);
+      const real tm = ld(F + (size_t)fo_tau1(NS, j) * n, sm.node);
+      if (!sp.wall && !sp.missing) e += real(0.5) * (Kx + p.kpr * tp * rp * iM * sp.T * iM) * (sp.T - Tt);
+      if (!sm.wall && !sm.missing) e += real(0.5) * (Kx + p.kpr * tm * rm * iM * sm.T * iM) * (sm.T - Tt);
+    }
+  }
+  return e;
+}
+
+// ===========================================================================
+// k_esum: temperature of f (Eq.(25): T plus half the energy of all sources)
+// and of the auxiliary state f* (quasi-equilibrium at fixed species momenta
+// and energy), one thread per gas node
+// ===========================================================================
+template <typename real, int D, int NS>
+__global__ void __launch_bounds__(BLOCK) k_esum(Params<real> p, Bufs<real> b, int cur) {
+  const int nblk = (p.n_gas + BLOCK - 1) / BLOCK, lb = xcd_block(nblk);
+  const int t = lb * BLOCK + threadIdx.x;
+  if (lb >= nblk || t >= p.n_gas) return;
+  const int node = (int)b.gas_list[t];
+  const int src = b.kind[node] == KIND_OUTLET ? node - node % p.nx + p.nx - 3 : node;
+  const int n = p.n;
+  real u[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) u[a] = ld(b.F + (size_t)fo_u(NS, a) * n, src);
+  const real Tt = ld(b.F + (size_t)fo_T<D>(NS) * n, src);
+  NbCommon<real, D> nb[D][2];
+  const bool cgrad = (p.flags & 10u) != 0;
+  if (cgrad) load_neighbours<real, D, NS>(p, b, src, nb);
+  real C = 0, esum = 0;
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    C += ld(b.F + (size_t)fo_rho(j) * n, src) * p.invM[j];
+    esum += energy_source<real, D, NS>(p, b, src, j, u, Tt, nb);
+  }
+  const real Tf = Tt + esum / (real(2 * D) * C);
+  const real Tst = Tf - ld(b.F + (size_t)fo_ediff<D>(NS) * n, src) / (real(D) * C);
+  st(b.F + (size_t)fo_Tf<D>(NS) * n, node, Tf);
+  st(b.F + (size_t)fo_Tst<D>(NS) * n, node, Tst);
+}
+
+// ===========================================================================
+// k_collide: sources, temperature of f, equilibria and Eq.(24) (pass 2)
+// ===========================================================================
 // Per-axis factors of the equilibrium (see equilibrium() in fdlbm_device.h)
 template <typename real, int D>
 struct EqFactors {
@@ -488,52 +607,26 @@ struct EqFactors {
   }
 };
 
-// face-neighbour values of the gradient stencils shared by all species
-template <typename real, int D>
-struct NbCommon {
-  real u[D], T;
-  int node;  // node supplying rho_j and tau1_j (self when missing)
-  bool wall, missing;
-};
-
 template <typename real, int D, int NS>
-__device__ inline double collide_node(const Params<real> &p, const Bufs<real> &b, int cur,
-                                      const int node, const int src) {
+__device__ inline void collide_node(const Params<real> &p, const Bufs<real> &b, int cur,
+                                    const int node, const int src, const int j) {
   // src: node whose collision is computed (an outlet node takes the result of
   // the last interior node of its row); node: where it is stored
   constexpr int Q = lat_q<D>();
   const int n = p.n;
   const real *__restrict__ F = b.F;
   const real *__restrict__ Gs = b.Gs;
-  const Addr<D> ad(src, p);
   real u[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) u[a] = ld(F + (size_t)fo_u(NS, a) * n, src);
   const real Tt = ld(F + (size_t)fo_T<D>(NS) * n, src);
-  real C = 0;
-#pragma unroll
-  for (int j = 0; j < NS; ++j) C += ld(F + (size_t)fo_rho(j) * n, src) * p.invM[j];
-  // ---- neighbours: velocity and temperature shared by all species ----
+  const real Tf = ld(F + (size_t)fo_Tf<D>(NS) * n, node);
+  const real Tst = ld(F + (size_t)fo_Tst<D>(NS) * n, node);
   const bool cdiff = (p.flags & 1u) && NS > 1;
   const bool cvisc = p.flags & 2u, cener = p.flags & 4u, cpr = (p.flags & 8u) && p.kpr != real(0);
   const bool cgrad = cvisc || cener || cpr;
   NbCommon<real, D> nb[D][2];
-#pragma unroll
-  for (int a = 0; a < D; ++a)
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      NbCommon<real, D> &v = nb[a][s];
-      const int q = cgrad ? ad.face(p, a, s == 0 ? +1 : -1) : src;
-      const uint8_t k = q >= 0 ? b.kind[q] : KIND_SOLID;
-      v.wall = q >= 0 && k == KIND_WALL;
-      v.missing = !(q >= 0 && (gaslike(k) || k == KIND_WALL)) || q == src;
-      v.node = v.missing ? src : q;
-      if (cgrad) {
-#pragma unroll
-        for (int c = 0; c < D; ++c) v.u[c] = ld(F + (size_t)fo_u(NS, c) * n, v.node);
-        v.T = ld(F + (size_t)fo_T<D>(NS) * n, v.node);
-      }
-    }
+  if (cgrad) load_neighbours<real, D, NS>(p, b, src, nb);
   // source moments of species j: momentum m, second moments P (diagonal Pd,
   // off-diagonal Po: xy, xz, yz), energy flux Y, energy e
   auto sources = [&](const int j, const real rj, real (&m)[D], real (&Pd)[D], real (&Po)[3],
@@ -594,23 +687,9 @@ __device__ inline double collide_node(const Params<real> &p, const Bufs<real> &b
       }
     }
   };
-  // ---- temperature of f from the energy of all sources, Eq.(25) ----
-  real esum = 0;
-#pragma unroll 1
-  for (int j = 0; j < NS; ++j) {
-    real m[D], Pd[D], Po[3], Y[D], e;
-    sources(j, ld(F + (size_t)fo_rho(j) * n, src), m, Pd, Po, Y, e, true);
-    esum += e;
-#pragma unroll
-    for (int a = 0; a < D; ++a) esum += Pd[a];
-  }
-  const real Tf = Tt + esum / (real(2 * D) * C);
-  // f* temperature: quasi-equilibrium at fixed species momenta and energy
-  const real Tst = Tf - ld(F + (size_t)fo_ediff<D>(NS) * n, src) / (real(D) * C);
-  // ---- per species: sources, equilibria and Eq.(24) ----
+  // ---- species j: sources, equilibria and Eq.(24) ----
   real *__restrict__ Gn = b.G[cur ^ 1];
-#pragma unroll 1
-  for (int j = 0; j < NS; ++j) {
+  {
     const real rj = ld(F + (size_t)fo_rho(j) * n, src);
     real uj[D];
 #pragma unroll
@@ -657,16 +736,16 @@ __device__ inline double collide_node(const Params<real> &p, const Bufs<real> &b
     });
     const real S0 = -(trP + e) * ic2;
     const real feq = rj * fe.rest(se), fst = rj * fs.rest(ss);
-    const real gi = ld(Gsj, src);
+    const real gi = ld(b.G[cur] + (size_t)(j * Q) * n, src);  // rest: not streamed
     st(Gnj, node, gi - w1 * (gi - fst) - w1 * r12 * (fst - feq) + wt * S0);
   }
-  return 0.0;
 }
 
 // inlet node: equilibrium at the inlet state with the velocity of the first
 // interior plane of its row (Sec. 6)
 template <typename real, int D, int NS>
-__device__ inline void inlet_node(const Params<real> &p, const Bufs<real> &b, int cur, int node) {
+__device__ inline void inlet_node(const Params<real> &p, const Bufs<real> &b, int cur, int node,
+                                  int j) {
   constexpr int Q = lat_q<D>();
   const int n = p.n;
   const int row = node - node % p.nx;
@@ -676,39 +755,39 @@ __device__ inline void inlet_node(const Params<real> &p, const Bufs<real> &b, in
 #pragma unroll
   for (int a = 0; a < D; ++a) u[a] = ok ? ld(b.F + (size_t)fo_u(NS, a) * n, src) : real(0);
   real *Gn = b.G[cur ^ 1];
-#pragma unroll 1
-  for (int j = 0; j < NS; ++j) {
-    real f[Q];
-    equilibrium<real, D>(p.rho_in[j], p.sqM[j], u, p.T_in, f);
+  real f[Q];
+  equilibrium<real, D>(p.rho_in[j], p.sqM[j], u, p.T_in, f);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) st(Gn + (size_t)(j * Q + i) * n, node, f[i]);
-  }
+  for (int i = 0; i < Q; ++i) st(Gn + (size_t)(j * Q + i) * n, node, f[i]);
 }
 
+// one thread per (node, species); the species is uniform per block
 template <typename real, int D, int NS>
 __global__ void __launch_bounds__(BLOCK) k_collide(Params<real> p, Bufs<real> b, int cur) {
-  const int nb = (p.n_gas + BLOCK - 1) / BLOCK, lb = xcd_block(nb);
+  // species fastest: the NS blocks of one node block run together on one XCD
+  // and share the node's and its neighbours' moments in L2
+  const int nbn = (p.n_gas + BLOCK - 1) / BLOCK, nb = nbn * NS, lb = xcd_block(nb);
   if (lb >= nb) return;  // whole block: no barrier follows for it
-  const int t = lb * BLOCK + threadIdx.x;
+  const int j = lb % NS;
+  const int t = (lb / NS) * BLOCK + threadIdx.x;
   double work = 0.0;
   if (t < p.n_gas) {
     const int node = (int)b.gas_list[t];
     const uint8_t k = b.kind[node];
     if (p.F[0] != real(0) || p.F[1] != real(0) || (D == 3 && p.F[2] != real(0))) {
-      // work of the body force this step, rho u.F (half the trace of its source)
+      // work of the body force on species j this step, rho_j u.F (half the
+      // trace of its source)
       const int n = p.n;
-      real rhot = 0, uf = 0;
-#pragma unroll
-      for (int j = 0; j < NS; ++j) rhot += ld(b.F + (size_t)fo_rho(j) * n, node);
+      real uf = 0;
 #pragma unroll
       for (int a = 0; a < D; ++a) uf += ld(b.F + (size_t)fo_u(NS, a) * n, node) * p.F[a];
-      work = (double)(rhot * uf);
+      work = (double)(ld(b.F + (size_t)fo_rho(j) * n, node) * uf);
     }
     if (k == KIND_INLET) {
-      inlet_node<real, D, NS>(p, b, cur, node);
+      inlet_node<real, D, NS>(p, b, cur, node, j);
     } else {
       const int src = k == KIND_OUTLET ? node - node % p.nx + p.nx - 3 : node;
-      collide_node<real, D, NS>(p, b, cur, node, src);
+      collide_node<real, D, NS>(p, b, cur, node, src, j);
     }
   }
   const double s = block_sum(work);
@@ -908,11 +987,16 @@ inline hipError_t step_impl(const Params<real> &p, const Bufs<real> &b, int cur,
   if (gws > 0) hipLaunchKernelGGL((k_wall<false, real, D, NS>), dim3(xcd_grid(gws)), dim3(BLOCK), 0, st, p, b, cur);
   mark(K_WALL_ID, 1);
   mark(K_MOMENTS_ID, 0);
-  if (ggf > 0) hipLaunchKernelGGL((k_moments<true, real, D, NS>), dim3(xcd_grid(ggf)), dim3(BLOCK), 0, st, p, b, cur);
-  if (ggs > 0) hipLaunchKernelGGL((k_moments<false, real, D, NS>), dim3(xcd_grid(ggs)), dim3(BLOCK), 0, st, p, b, cur);
+  constexpr int QM = lat_q<D>() - 1;
+  if (ggf > 0) hipLaunchKernelGGL((k_stream<true, real, D, NS>), dim3(xcd_grid(ggf * QM)), dim3(BLOCK), 0, st, p, b, cur);
+  if (ggs > 0) hipLaunchKernelGGL((k_stream<false, real, D, NS>), dim3(xcd_grid(ggs * QM)), dim3(BLOCK), 0, st, p, b, cur);
+  if (gg > 0) hipLaunchKernelGGL((k_moments<real, D, NS>), dim3(xcd_grid(gg)), dim3(BLOCK), 0, st, p, b, cur);
   mark(K_MOMENTS_ID, 1);
+  mark(K_ESUM_ID, 0);
+  if (gg > 0) hipLaunchKernelGGL((k_esum<real, D, NS>), dim3(xcd_grid(gg)), dim3(BLOCK), 0, st, p, b, cur);
+  mark(K_ESUM_ID, 1);
   mark(K_COLLIDE_ID, 0);
-  if (gg > 0) hipLaunchKernelGGL((k_collide<real, D, NS>), dim3(xcd_grid(gg)), dim3(BLOCK), 0, st, p, b, cur);
+  if (gg > 0) hipLaunchKernelGGL((k_collide<real, D, NS>), dim3(xcd_grid(gg * NS)), dim3(BLOCK), 0, st, p, b, cur);
   mark(K_COLLIDE_ID, 1);
   if (li.n_solid > 0) {
     const int tiles = solid_tiles<D>(p.nx, p.ny, p.nz);

@@ -7,7 +7,7 @@
 
 namespace fdlbm {
 
-enum { K_WALL_ID = 0, K_MOMENTS_ID = 1, K_COLLIDE_ID = 2, K_SOLID_ID = 3, K_INOUT_ID = 4,
+enum { K_WALL_ID = 0, K_MOMENTS_ID = 1, K_COLLIDE_ID = 2, K_SOLID_ID = 3, K_ESUM_ID = 4,
        K_NUM = 5 };
 
 struct LaunchInfo {
