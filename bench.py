@@ -6,7 +6,8 @@ porosity 0.6, five gas species (CO, H2O, CO2, H2, N2) with water-gas-shift
 chemistry on the sphere surfaces, FD heat conduction in the solid, body-force
 flow with inlet/outlet planes, FP32 storage and arithmetic.  A "step" is one
 full time step of the method (wall BC, streaming, moments, collision with all
-corrections, solid FD, inlet/outlet).
+corrections, solid FD, inlet/outlet).  Inputs are resident in device memory
+before the timed region.
 
 Prints ONE JSON line: MLUPS x species (gas nodes x species x steps / s / 1e6),
 the fraction of the HBM roofline of the dominant kernel measured with HIP
@@ -16,6 +17,7 @@ timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import ctypes as ct
 import json
 import os
 import sys
@@ -25,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, 8 TB/s
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bed128_f32.json")
 
 
 def parse():
@@ -35,26 +38,28 @@ def parse():
     ap.add_argument("--n", type=int, default=128, help="bed edge length (nodes)")
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-n", type=int, default=96,
+                    help="edge length of the bed the CPU oracle is timed on (bounded sample)")
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
-                    help="run one device copy of this size first (counter calibration)")
-    ap.add_argument("--traffic-gb", type=float, default=None,
-                    help="measured HBM bytes per launch of the dominant kernel (GB), from rocprofv3")
+                    help="run one plain device copy of this size first (counter calibration)")
     return ap.parse_args()
 
 
-def algorithmic_bytes(n_gas, n_wall_links, n_solid, ns, Q, b):
-    """Per-step algorithmic bytes: every gas population read once and written
-    once, every wall link's populations read and written once, the solid
-    temperature read and written once."""
-    return n_gas * 2 * Q * ns * b + n_wall_links * 2 * ns * b + n_solid * 2 * b
+def bed(n):
+    from paper_1804_07588_amd import workloads as W
+    mask, nsph = W.sphere_pack_mask(n, radius=6.0, porosity=0.6, seed=12345, buffer=8)
+    cfg = W.packed_bed(mask=mask)
+    return cfg, W.uniform_init(cfg), nsph
 
 
-def cpu_baseline(cfg, init, steps):
-    """The FP64 oracle (single thread) on the same geometry and state: setup
-    excluded, `steps` full time steps timed."""
+def cpu_baseline(n, steps):
+    """The FP64 oracle (single thread) on a bed of edge n built the same way
+    (same sphere radius, porosity, chemistry and flow): setup excluded,
+    `steps` full time steps timed."""
     from oracle import oracle
     oracle.build(force=not os.path.exists(oracle.LIB_PATH))
+    cfg, init, _ = bed(n)
     sim = oracle.OracleSim(cfg, init)
     t0 = time.perf_counter()
     sim.step(steps)
@@ -64,41 +69,78 @@ def cpu_baseline(cfg, init, steps):
     val = o["n_gas"] * ns * steps / dt / 1e6
     sim.close()
     return dict(value=round(val, 4), unit="MLUPS*species", cores=1, kind="oracle",
-                sample=f"{steps} full step(s) of the same {cfg['nx']}x{cfg['ny']}x{cfg['nz']} "
-                       f"bed, FP64, one thread, {dt:.1f} s")
+                sample=f"{steps} full step(s) of a {n}^3 bed of the same construction "
+                       f"({o['n_gas']} gas nodes), FP64, one thread, {dt:.1f} s")
+
+
+def calib_copy(mib):
+    """One plain device copy of mib MiB (4-byte words): reads and writes
+    exactly that many bytes; its byte counters calibrate the others."""
+    import torch
+    from paper_1804_07588_amd import build as hb
+    L = ct.CDLL(hb.CALIB_LIB)
+    L.fdlbm_calib_copy.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p]
+    words = mib * 262144
+    src = torch.ones(words, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    rc = L.fdlbm_calib_copy(ct.c_void_p(src.data_ptr()), ct.c_void_p(dst.data_ptr()), words,
+                            ct.c_void_p(torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    if rc != 0:
+        raise RuntimeError(f"calibration copy failed ({rc})")
+    del src, dst
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter record,
+    or None if there is none or the library sources changed since."""
+    from paper_1804_07588_amd import profsummary
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except OSError:
+        return None
+    if rec.get("source_sha256") != profsummary.source_hash() or kernel not in rec.get("kernels", {}):
+        return None
+    k = rec["kernels"][kernel]
+    return k["fetch_bytes"] + k["write_bytes"]
 
 
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
-                                   "design-only (see DESIGN.md)", "n_gpus": args.gpus}))
+                                   "design-only", "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
     import torch
-    from paper_1804_07588_amd import fdlbm, workloads as W
+    from paper_1804_07588_amd import fdlbm
 
     torch.cuda.set_device(0)
     if args.calib_copy_mib:
-        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters
-        # calibrate the traffic figures of the method's kernels
-        src = torch.ones(args.calib_copy_mib * 262144, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.mul(src, 2.0, out=dst)   # elementwise kernel: reads and writes the size once
-        torch.cuda.synchronize()
-        del src, dst
-    mask, nsph = W.sphere_pack_mask(args.n, radius=6.0, porosity=0.6, seed=12345, buffer=8)
-    cfg = W.packed_bed(mask=mask)
-    init = W.uniform_init(cfg)
+        calib_copy(args.calib_copy_mib)
+    cfg, init, nsph = bed(args.n)
     prec = fdlbm.F32 if args.precision == "f32" else fdlbm.F64
     b = 4 if prec == fdlbm.F32 else 8
     sim = fdlbm.Sim(cfg, precision=prec, init=init)
     n_gas, n_wall, n_solid = sim.counts()
     kind = sim.field(fdlbm.FIELD_KIND).astype(np.int64)
-    ns, Q = 5, 19
+    ns, Q = len(cfg["species"]["M"]), 19
     # wall links = incoming links of all wall nodes (each carries one population per species)
     n_links = int(_count_wall_links(kind, cfg))
-    B_alg = algorithmic_bytes(n_gas, n_links, n_solid, ns, Q, b)
+    # algorithmic bytes per step: every gas population read once and written
+    # once, every wall link's populations read and written once, the solid
+    # temperature read and written once
+    B_alg = n_gas * 2 * Q * ns * b + n_links * 2 * ns * b + n_solid * 2 * b
+    # ... and per kernel group and launch
+    kernel_alg_bytes = {
+        "k_collide": n_gas * 2 * Q * ns * b,   # pre-collision pops in, post-collision pops out
+        "k_moments": n_gas * Q * ns * b,       # pre-collision pops in
+        "k_wall": n_links * 2 * ns * b,        # link pops in, emitted pops out
+        "k_solid": n_solid * 2 * b,            # solid temperature in and out
+        "k_esum": 0,                           # node fields only: no algorithmic bytes
+    }
 
     sim.step(args.warmup)
     sim.sync()
@@ -118,17 +160,9 @@ def main():
 
     ms_per_step = dt * 1e3 / args.steps
     mlups_species = n_gas * ns * args.steps / dt / 1e6
-    # dominant kernel: the collision kernel reads every gas population once
-    # (through the interpolation taps) and writes it once
-    dom = max(times, key=times.get)
-    kernel_alg_bytes = {
-        "k_collide": n_gas * 2 * Q * ns * b,
-        "k_stream+k_moments": n_gas * Q * ns * b,
-        "k_wall": n_links * 2 * ns * b,
-        "k_solid": n_solid * 2 * b,
-        "k_esum": 0,
-    }
+    dom = max(times, key=times.get)   # dominant kernel group by event time
     achieved = kernel_alg_bytes[dom] / (times[dom] * 1e-3) / 1e9
+    traffic = measured_traffic(dom) if (args.n == 128 and prec == fdlbm.F32) else None
     out = {
         "metric": "MLUPS*species (gas nodes x species x steps / s / 1e6) and % of HBM peak",
         "value": round(mlups_species, 2),
@@ -149,9 +183,11 @@ def main():
             "wall_nodes": n_wall, "solid_nodes": n_solid, "wall_links": n_links,
             "spheres": nsph, "species": ns,
         },
+        "step_alg_bytes": B_alg,
         "step_effective_GBs": round(B_alg * args.steps / dt / 1e9, 1),
         "step_hbm_frac": round(B_alg * args.steps / dt / 1e9 / HBM_PEAK_GBS, 4),
         "kernel_ms": {k: round(v, 5) for k, v in times.items()},
+        "timed_launches": launches,
         "roofline": {
             "bound": "hbm",
             "kernel": dom,
@@ -159,11 +195,12 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": args.traffic_gb,
+            "alg_bytes": kernel_alg_bytes[dom],
+            "traffic": traffic,
         },
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, init, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.cpu_steps)
     print(json.dumps(out), flush=True)
 
 

@@ -29,8 +29,10 @@
  * fdlbm_last_error() gives a message.  No exception crosses the ABI.
  * Thread-compatible: one context per host thread.
  *
- * Layouts: node index = x + nx*(y + ny*z).  Populations of species j and
- * direction i live at [(j*Q + i)*n + node] (structure of arrays).  Direction
+ * Layouts: node index = x + nx*(y + ny*z).  Host arrays are per node; the
+ * workspace stores populations and moments per slot (gas nodes, then wall
+ * nodes), and fdlbm_get_field returns populations of species j, direction i
+ * at [i*n + node] (structure of arrays, zero where a node stores none).  Direction
  * order: D2Q9 as Eq.(2) (rest, +x, +y, -x, -y, (1,1), (-1,1), (-1,-1), (1,-1));
  * D3Q19 rest, +x, -x, +y, -y, +z, -z, then the xy, xz, yz edges, each in the
  * order (+,+), (-,+), (-,-), (+,-).
@@ -123,9 +125,10 @@ const char *fdlbm_last_error(const fdlbm_ctx *ctx);
  * gas, 1 = solid, copied.  Wall nodes are the solid nodes with a gas node
  * among their lattice neighbours.  inout = 1 turns the planes x = 0, 1 into
  * inlet nodes (equilibrium at the inlet state, Sec. 6) and x = nx-2, nx-1
- * into outlet nodes (zero-gradient copy); x must then be non-periodic and
- * those planes gas.  FDLBM_E_GEOMETRY if no gas node exists or a gas node
- * touches a closed domain edge. */
+ * into outlet nodes (zero-gradient copy of x = nx-3); x must then be
+ * non-periodic, those planes gas and x = nx-3 gas wherever the outlet is.
+ * FDLBM_E_GEOMETRY if no gas node exists, a gas node touches a closed domain
+ * edge or an outlet row has no interior gas node to copy. */
 int fdlbm_set_geometry(fdlbm_ctx *ctx, const uint8_t *mask_host, int inout);
 
 /* Species and transport (Sec. 3, Eq.(7)-(8), (14)-(17), (19)-(21)):
@@ -158,7 +161,8 @@ int fdlbm_set_reaction(fdlbm_ctx *ctx, const double *nu, const double *order, do
 int fdlbm_set_flow(fdlbm_ctx *ctx, const double *F3, const double *X_in, double p_in,
                    double T_in);
 
-/* Device bytes the caller must provide (valid after fdlbm_create). */
+/* Device bytes the caller must provide (depends on the geometry: valid after
+ * fdlbm_set_geometry, else FDLBM_E_STATE). */
 int fdlbm_workspace_bytes(const fdlbm_ctx *ctx, size_t *bytes);
 
 /* Bind the caller's device buffer (>= fdlbm_workspace_bytes, 256-byte
@@ -191,14 +195,18 @@ int fdlbm_state_bytes(const fdlbm_ctx *ctx, size_t *bytes);
 int fdlbm_save_state(fdlbm_ctx *ctx, void *host_buf, size_t bytes);
 int fdlbm_load_state(fdlbm_ctx *ctx, const void *host_buf, size_t bytes);
 
-/* Timing of the last fdlbm_step call's gas collision kernel on its stream,
- * when enabled with fdlbm_set_profiling(ctx, 1): per-kernel average duration
- * in milliseconds over the recorded launches (kernel ids below). */
-#define FDLBM_K_WALL 0
-#define FDLBM_K_MOMENTS 1
-#define FDLBM_K_COLLIDE 2
-#define FDLBM_K_SOLID 3
-#define FDLBM_K_ESUM 4
+/* Per-kernel timing with HIP events on the context's stream.  While enabled
+ * (fdlbm_set_profiling(ctx, 1), which also resets the record), each step
+ * brackets its kernels with events, for up to 4096 steps; fdlbm_kernel_times
+ * synchronises and writes avg_ms[FDLBM_K_COUNT], the average duration in
+ * milliseconds of each kernel group over the recorded steps (0 for a group
+ * that did not run), and the number of recorded steps.  A group covers both
+ * launches (periodic-wrap and plain) of its kernel. */
+#define FDLBM_K_WALL 0     /* reactive wall                                  */
+#define FDLBM_K_MOMENTS 1  /* streaming + moments + transport                */
+#define FDLBM_K_COLLIDE 2  /* streaming + sources + collision + inlet/outlet */
+#define FDLBM_K_SOLID 3    /* solid heat step                                */
+#define FDLBM_K_ESUM 4     /* temperature of f and of the auxiliary state    */
 #define FDLBM_K_COUNT 5
 int fdlbm_set_profiling(fdlbm_ctx *ctx, int enable);
 int fdlbm_kernel_times(fdlbm_ctx *ctx, double *avg_ms, int64_t *launches);

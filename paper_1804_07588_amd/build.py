@@ -1,4 +1,5 @@
-"""Build the HIP library libfdlbm.so in-tree for gfx950 with hipcc."""
+"""Build the HIP library libfdlbm.so in-tree for gfx950 with hipcc, and the
+counter-calibration copy kernel libfdlbm_calib.so (measurement aid only)."""
 from __future__ import annotations
 
 import os
@@ -9,6 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfdlbm.so")
+CALIB_LIB = os.path.join(HERE, "libfdlbm_calib.so")
+CALIB_SRC = os.path.join(CSRC, "calib_copy.hip")
 SOURCES = [os.path.join(CSRC, f) for f in
            ("kern_f32_d3q19.hip", "kern_f64_d3q19.hip", "kern_f32_d2q9.hip", "kern_f64_d2q9.hip",
             "fdlbm_api.cpp")]
@@ -21,6 +24,8 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 
 def build(verbose: bool = False, jobs: int | None = None) -> str:
     """Compile every source for gfx950 (in parallel) and link libfdlbm.so."""
+    calib = subprocess.Popen([HIPCC, *FLAGS, "-shared", "-o", CALIB_LIB + ".tmp", CALIB_SRC],
+                             stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
     objs, procs = [], []
     jobs = jobs or min(len(SOURCES), max(1, min(os.cpu_count() or 1, 16)))
     pending = list(SOURCES)
@@ -49,6 +54,11 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     os.replace(tmp, LIB)
     for o in objs:
         os.remove(o)
+    _, err = calib.communicate()
+    if calib.returncode != 0:
+        sys.stderr.write(err)
+        raise RuntimeError(f"hipcc failed on {CALIB_SRC}")
+    os.replace(CALIB_LIB + ".tmp", CALIB_LIB)
     return LIB
 
 

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "fdlbm_device.h"
@@ -41,15 +42,22 @@ struct fdlbm_ctx {
   // geometry
   int inout = 0;
   std::vector<uint8_t> kind;
-  std::vector<uint64_t> cls, gas_cls_host;
-  std::vector<uint32_t> emask, gas_list, wall_list;
+  std::vector<uint64_t> cls;       // class word per node (host only)
+  std::vector<uint32_t> emask;     // emission mask per node (host only)
+  std::vector<uint32_t> gas_list, wall_list;
+  std::vector<int32_t> slot_of;    // slot per node (null slot for interior solid)
+  std::vector<uint64_t> scls;      // class word per slot
+  std::vector<uint32_t> wem;       // emission mask per wall node
   int64_t n_gas_fast = 0, n_wall_fast = 0;
   int64_t n_solid = 0;
+  int nsl = 0;                     // slot stride
+  int tile_rows = 0;               // y rows per tile of the processing order
   // workspace
   char *ws = nullptr;
   size_t ws_bytes = 0;
-  size_t off_G[2]{}, off_Gs = 0, off_SM = 0, off_F = 0, off_Ts[2]{}, off_wr = 0, off_wde = 0, off_kind = 0, off_cls = 0, off_gcls = 0,
-         off_em = 0, off_gl = 0, off_wl = 0, off_am = 0, off_aw = 0, off_ab = 0, off_part = 0;
+  size_t off_G[2]{}, off_F = 0, off_Ts[2]{}, off_wr = 0, off_wde = 0, off_kind = 0, off_slot = 0,
+         off_scls = 0, off_wem = 0, off_gl = 0, off_wl = 0, off_am = 0, off_aw = 0, off_ab = 0,
+         off_part = 0;
   size_t total = 0;
   int acc_slots = 0, obs_blocks = 0;
   int cur = 0;
@@ -83,30 +91,34 @@ static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 static size_t real_size(const fdlbm_ctx *c) { return c->d.precision == FDLBM_F64 ? 8 : 4; }
 
+// Workspace layout; depends on the geometry (slot counts).  Per-slot arrays
+// have stride nsl = n_gas + n_wall + 1 rounded up to 64 (the +1 is the null
+// slot of interior solid nodes).
 static void layout(fdlbm_ctx *c) {
   const size_t b = real_size(c), n = (size_t)c->n;
+  const size_t ng = c->gas_list.size(), nw = c->wall_list.size();
+  c->nsl = (int)((ng + nw + 1 + 63) / 64 * 64);
+  const size_t nsl = (size_t)c->nsl;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t at = o;
     o = align256(o + bytes);
     return at;
   };
-  const size_t pops = (size_t)c->ns * c->Q * n * b;
+  const size_t pops = (size_t)c->ns * c->Q * nsl * b;
   c->off_G[0] = take(pops);
   c->off_G[1] = take(pops);
-  c->off_Gs = take(pops);
-  c->off_SM = take((size_t)c->ns * (c->D + 2) * n * b);
-  c->off_F = take((size_t)n_fields(c->D, c->ns) * n * b);
+  c->off_F = take((size_t)n_fields(c->D, c->ns) * nsl * b);
   c->off_Ts[0] = take(n * b);
   c->off_Ts[1] = take(n * b);
   c->off_wr = take(n * b);
   c->off_wde = take(n * b);
   c->off_kind = take(n);
-  c->off_cls = take(n * 8);
-  c->off_gcls = take(n * 8);
-  c->off_em = take(n * 4);
-  c->off_gl = take(n * 4);
-  c->off_wl = take(n * 4);
+  c->off_slot = take(n * 4);
+  c->off_scls = take(nsl * 8);
+  c->off_wem = take(std::max<size_t>(nw, 1) * 4);
+  c->off_gl = take(std::max<size_t>(ng, 1) * 4);
+  c->off_wl = take(std::max<size_t>(nw, 1) * 4);
   // one accumulator slot per block of the largest grid that accumulates
   const int tiles = c->D == 2 ? solid_tiles<2>(c->d.nx, c->d.ny, c->d.nz)
                               : solid_tiles<3>(c->d.nx, c->d.ny, c->d.nz);
@@ -125,17 +137,15 @@ static Bufs<real> bufs(const fdlbm_ctx *c) {
   char *w = c->ws;
   b.G[0] = (real *)(w + c->off_G[0]);
   b.G[1] = (real *)(w + c->off_G[1]);
-  b.Gs = (real *)(w + c->off_Gs);
-  b.SM = (real *)(w + c->off_SM);
   b.F = (real *)(w + c->off_F);
   b.Ts[0] = (real *)(w + c->off_Ts[0]);
   b.Ts[1] = (real *)(w + c->off_Ts[1]);
   b.wall_r = (real *)(w + c->off_wr);
   b.wall_dE = (real *)(w + c->off_wde);
   b.kind = (const uint8_t *)(w + c->off_kind);
-  b.cls = (const uint64_t *)(w + c->off_cls);
-  b.gas_cls = (const uint64_t *)(w + c->off_gcls);
-  b.emask = (const uint32_t *)(w + c->off_em);
+  b.slot_of = (const int32_t *)(w + c->off_slot);
+  b.scls = (const uint64_t *)(w + c->off_scls);
+  b.wem = (const uint32_t *)(w + c->off_wem);
   b.gas_list = (const uint32_t *)(w + c->off_gl);
   b.wall_list = (const uint32_t *)(w + c->off_wl);
   b.acc_moles = (double *)(w + c->off_am);
@@ -186,7 +196,7 @@ static Params<real> params(const fdlbm_ctx *c) {
   p.wall_mode = c->wall_mode;
   p.n_gas = (int)c->gas_list.size();
   p.n_wall = (int)c->wall_list.size();
-  p.n_ghost_cols = c->inout ? c->d.ny * c->d.nz : 0;
+  p.nsl = c->nsl;
   p.n_gas_fast = (int)c->n_gas_fast;
   p.n_wall_fast = (int)c->n_wall_fast;
   p.slot_off_gas = (int)((c->n_gas_fast + BLOCK - 1) / BLOCK);
@@ -199,7 +209,6 @@ static Params<real> params(const fdlbm_ctx *c) {
     p.cj[j] = (real)cj;
     p.cj2[j] = (real)(1.0 / c->M[j]);
     p.invcj[j] = (real)std::sqrt(c->M[j]);
-    p.onlat[j] = c->M[j] == 1.0;
     double w[7][3];
     class_weights(1.0 - cj, w);
     for (int k = 0; k < 7; ++k)
@@ -304,6 +313,10 @@ int fdlbm_set_geometry(fdlbm_ctx *c, const uint8_t *mask, int inout) {
     }
   }
   if (ngas == 0) return set_err(c, FDLBM_E_GEOMETRY, "no gas node");
+  // an outlet node copies the collision of the last interior node of its row
+  for (int node = 0; node < n; ++node)
+    if (c->kind[node] == KIND_OUTLET && c->kind[node - node % nx + nx - 3] != KIND_GAS)
+      return set_err(c, FDLBM_E_GEOMETRY, "outlet row of node %d has no gas node at x = nx - 3", node);
   // emission masks: gas emits along every direction, a wall node along the
   // directions that lead into the gas
   c->emask.assign(n, 0u);
@@ -353,8 +366,27 @@ int fdlbm_set_geometry(fdlbm_ctx *c, const uint8_t *mask, int inout) {
     if (gaslike(k)) c->gas_list.push_back((uint32_t)node);
     else c->wall_list.push_back((uint32_t)node);
   }
-  // order each list: nodes whose taps (up to 3 nodes away) never wrap a
-  // periodic axis first, so the kernels for them use plain strides
+  // Processing (and slot) order: y-tiles of yt rows, within a tile z, then
+  // y, then x.  A tap two planes upstream along z was then touched about
+  // 2*yt*nx nodes earlier, a distance whose population traffic fits one
+  // XCD's 4 MiB L2; in plain node order it would be two whole planes.
+  {
+    const double per_node = 2.0 * c->Q * c->ns * (double)real_size(c);
+    int yt = 4;
+    while (yt * 2 <= c->d.ny && 2.0 * c->d.nx * (yt * 2) * per_node <= 4.0 * 1048576.0) yt *= 2;
+    if (c->D == 2) yt = c->d.ny;
+    c->tile_rows = yt;
+    const int nxx = c->d.nx, nyy = c->d.ny;
+    auto key = [&](uint32_t node) {
+      const int x = (int)(node % nxx), y = (int)((node / nxx) % nyy), z = (int)(node / ((uint32_t)nxx * nyy));
+      return std::make_tuple(y / yt, z, y % yt, x);
+    };
+    auto by_tile = [&](uint32_t a, uint32_t b) { return key(a) < key(b); };
+    std::stable_sort(c->gas_list.begin(), c->gas_list.end(), by_tile);
+    std::stable_sort(c->wall_list.begin(), c->wall_list.end(), by_tile);
+  }
+  // then nodes whose taps (up to 3 nodes away) never wrap a periodic axis
+  // first, so the kernels for them use plain strides
   auto no_wrap = [&](uint32_t node) {
     const int lim[3] = {c->d.nx, c->d.ny, c->d.nz};
     const int q[3] = {(int)(node % lim[0]), (int)((node / lim[0]) % lim[1]), (int)(node / (lim[0] * lim[1]))};
@@ -368,6 +400,21 @@ int fdlbm_set_geometry(fdlbm_ctx *c, const uint8_t *mask, int inout) {
   };
   c->n_gas_fast = split(c->gas_list);
   c->n_wall_fast = split(c->wall_list);
+  // slots: gas nodes in list order, then wall nodes, then the null slot
+  const int ng = (int)c->gas_list.size(), nw = (int)c->wall_list.size();
+  c->slot_of.assign(n, ng + nw);
+  c->scls.assign((size_t)ng + nw, ~uint64_t(0));
+  c->wem.assign((size_t)std::max(nw, 1), 0u);
+  for (int t = 0; t < ng; ++t) {
+    c->slot_of[c->gas_list[t]] = t;
+    c->scls[t] = c->cls[c->gas_list[t]];
+  }
+  for (int w = 0; w < nw; ++w) {
+    c->slot_of[c->wall_list[w]] = ng + w;
+    c->scls[(size_t)ng + w] = c->cls[c->wall_list[w]];
+    c->wem[w] = c->emask[c->wall_list[w]];
+  }
+  layout(c);
   c->geometry_set = true;
   return FDLBM_OK;
 }
@@ -404,7 +451,6 @@ int fdlbm_create(const fdlbm_desc *d, fdlbm_ctx **out) {
   c->n = d->nx * d->ny * d->nz;
   c->stream = (hipStream_t)d->hip_stream;
   for (int a = 0; a < 6; ++a) c->T_bc[a] = NAN;
-  layout(c);
   *out = c;
   return FDLBM_OK;
 }
@@ -499,6 +545,7 @@ int fdlbm_set_flow(fdlbm_ctx *c, const double *F3, const double *X_in, double p_
 
 int fdlbm_workspace_bytes(const fdlbm_ctx *c, size_t *bytes) {
   if (!c || !bytes) return FDLBM_E_INVALID;
+  if (!c->geometry_set) return FDLBM_E_STATE;
   *bytes = c->total;
   return FDLBM_OK;
 }
@@ -520,20 +567,15 @@ int fdlbm_bind_workspace(fdlbm_ctx *c, void *dev, size_t bytes) {
   c->ws_bytes = bytes;
   const size_t n = (size_t)c->n;
   HIPCHK(c, hipMemsetAsync(c->ws, 0, c->total, c->stream));
-  HIPCHK(c, hipMemcpyAsync(c->ws + c->off_kind, c->kind.data(), n, hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(c->ws + c->off_cls, c->cls.data(), n * 8, hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(c->ws + c->off_em, c->emask.data(), n * 4, hipMemcpyHostToDevice, c->stream));
-  if (!c->gas_list.empty()) {
-    HIPCHK(c, hipMemcpyAsync(c->ws + c->off_gl, c->gas_list.data(), c->gas_list.size() * 4,
-                             hipMemcpyHostToDevice, c->stream));
-    c->gas_cls_host.resize(c->gas_list.size());
-    for (size_t q = 0; q < c->gas_list.size(); ++q) c->gas_cls_host[q] = c->cls[c->gas_list[q]];
-    HIPCHK(c, hipMemcpyAsync(c->ws + c->off_gcls, c->gas_cls_host.data(), c->gas_list.size() * 8,
-                             hipMemcpyHostToDevice, c->stream));
-  }
-  if (!c->wall_list.empty())
-    HIPCHK(c, hipMemcpyAsync(c->ws + c->off_wl, c->wall_list.data(), c->wall_list.size() * 4,
-                             hipMemcpyHostToDevice, c->stream));
+  auto up = [&](size_t off, const void *src, size_t bytes) {
+    return bytes ? hipMemcpyAsync(c->ws + off, src, bytes, hipMemcpyHostToDevice, c->stream) : hipSuccess;
+  };
+  HIPCHK(c, up(c->off_kind, c->kind.data(), n));
+  HIPCHK(c, up(c->off_slot, c->slot_of.data(), n * 4));
+  HIPCHK(c, up(c->off_scls, c->scls.data(), c->scls.size() * 8));
+  HIPCHK(c, up(c->off_wem, c->wem.data(), c->wem.size() * 4));
+  HIPCHK(c, up(c->off_gl, c->gas_list.data(), c->gas_list.size() * 4));
+  HIPCHK(c, up(c->off_wl, c->wall_list.data(), c->wall_list.size() * 4));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->bound = true;
   c->initialized = false;
@@ -544,19 +586,20 @@ int fdlbm_bind_workspace(fdlbm_ctx *c, void *dev, size_t bytes) {
 template <typename real>
 static int init_impl(fdlbm_ctx *c, const double *rho, const double *u, const double *T,
                      const double *Ts) {
-  const size_t n = (size_t)c->n;
+  const size_t n = (size_t)c->n, nsl = (size_t)c->nsl;
   const int Q = c->Q, ns = c->ns;
-  std::vector<real> G((size_t)ns * Q * n, real(0)), hT(n, real(0));
+  std::vector<real> G((size_t)ns * Q * nsl, real(0)), hT(n, real(0));
   for (size_t node = 0; node < n; ++node) {
     hT[node] = (real)Ts[node];
     if (!gaslike(c->kind[node])) continue;
+    const size_t slot = (size_t)c->slot_of[node];
     real uu[3] = {(real)u[node], (real)u[n + node], (real)u[2 * n + node]};
     for (int j = 0; j < ns; ++j) {
       real f[19];
       const real sq = (real)std::sqrt(c->M[j]);
       if (c->D == 2) equilibrium<real, 2>((real)rho[j * n + node], sq, uu, (real)T[node], f);
       else equilibrium<real, 3>((real)rho[j * n + node], sq, uu, (real)T[node], f);
-      for (int i = 0; i < Q; ++i) G[((size_t)j * Q + i) * n + node] = f[i];
+      for (int i = 0; i < Q; ++i) G[((size_t)j * Q + i) * nsl + slot] = f[i];
     }
   }
   for (size_t node = 0; node < n; ++node) {
@@ -578,7 +621,7 @@ static int init_impl(fdlbm_ctx *c, const double *rho, const double *u, const dou
       }
       const real rw = (real)(sum / cnt);
       for (int i = 1; i < Q; ++i)
-        if ((c->emask[node] >> i) & 1u) G[((size_t)j * Q + i) * n + node] = rw * wt[i];
+        if ((c->emask[node] >> i) & 1u) G[((size_t)j * Q + i) * nsl + c->slot_of[node]] = rw * wt[i];
     }
   }
   c->cur = 0;
@@ -755,10 +798,12 @@ int fdlbm_get_field(fdlbm_ctx *c, int field, int comp, double *dst) {
       } else {
         k = (size_t)(3 * c->ns + c->D);
       }
-      rc = cp(c->off_F + k * n * b, n);
+      std::vector<double> v(c->nsl);
+      rc = f64 ? copy_field<double>(c, c->off_F + k * c->nsl * b, c->nsl, v.data())
+               : copy_field<float>(c, c->off_F + k * c->nsl * b, c->nsl, v.data());
       if (rc) return rc;
       for (size_t x = 0; x < n; ++x)
-        if (!(gaslike(c->kind[x]) || c->kind[x] == KIND_WALL)) dst[x] = 0.0;
+        dst[x] = (gaslike(c->kind[x]) || c->kind[x] == KIND_WALL) ? v[c->slot_of[x]] : 0.0;
       return FDLBM_OK;
     }
     case FDLBM_FIELD_TS:
@@ -767,9 +812,20 @@ int fdlbm_get_field(fdlbm_ctx *c, int field, int comp, double *dst) {
       for (size_t x = 0; x < n; ++x)
         if (!(c->kind[x] == KIND_SOLID || c->kind[x] == KIND_WALL)) dst[x] = 0.0;
       return FDLBM_OK;
-    case FDLBM_FIELD_POP:
+    case FDLBM_FIELD_POP: {
       if (comp < 0 || comp >= c->ns) return set_err(c, FDLBM_E_INVALID, "bad species");
-      return cp(c->off_G[c->cur] + (size_t)comp * c->Q * n * b, (size_t)c->Q * n);
+      const size_t nsl = (size_t)c->nsl, null_slot = c->gas_list.size() + c->wall_list.size();
+      std::vector<double> v((size_t)c->Q * nsl);
+      const size_t off = c->off_G[c->cur] + (size_t)comp * c->Q * nsl * b;
+      rc = f64 ? copy_field<double>(c, off, v.size(), v.data()) : copy_field<float>(c, off, v.size(), v.data());
+      if (rc) return rc;
+      for (int i = 0; i < c->Q; ++i)
+        for (size_t x = 0; x < n; ++x) {
+          const size_t sl = (size_t)c->slot_of[x];
+          dst[(size_t)i * n + x] = sl == null_slot ? 0.0 : v[i * nsl + sl];
+        }
+      return FDLBM_OK;
+    }
     case FDLBM_FIELD_KIND:
       for (size_t x = 0; x < n; ++x) dst[x] = c->kind[x];
       return FDLBM_OK;

@@ -81,12 +81,12 @@ struct Params {
   int inout;
   unsigned flags;
   int wall_mode;
-  int n_gas, n_wall, n_ghost_cols;
+  int n_gas, n_wall;
+  int nsl;                          // slot stride of the per-slot arrays (>= n_gas + n_wall + 1)
   int n_gas_fast, n_wall_fast;      // leading list entries whose taps never wrap
-  int slot_off_gas, slot_off_wall;  // accumulator slot offsets of the wrapping launches
+  int slot_off_gas, slot_off_wall;  // accumulator block offsets of the wrapping launches
   // species
   real M[MAXS], invM[MAXS], sqM[MAXS], cj[MAXS], cj2[MAXS], invcj[MAXS];
-  int onlat[MAXS];                 // c_j == 1: plain streaming
   real wint[MAXS][7][3];           // stencil weights per species and class
   real mu0[MAXS], mu_T_exp;
   real wilke[MAXS][MAXS];          // phi_jk of Eq.(15) (temperature independent)
@@ -106,29 +106,30 @@ struct Params {
   real rho_in[MAXS], T_in;
 };
 
-// workspace pointers
+// Workspace pointers.  Populations and moments live in compact SLOT order:
+// gas-like nodes in gas-list order (slot = list index), then the wall nodes
+// (slot = n_gas + wall index), then one null slot that no valid tap reads;
+// slot_of maps a node to its slot (the null slot for interior solid nodes).
 template <typename real>
 struct Bufs {
-  real *G[2];         // populations [(j*Q + i)*n + node], double-buffered
-  real *Gs;           // streamed (pre-collision) populations of the gas nodes
-  real *SM;           // species moments of the streamed populations: rho_j, J_j (D), E_j
-  real *F;            // per-step moments: rho_j, tau1_j, tau2_j, u_a (D), T
-  real *Ts[2];        // solid temperature, double-buffered
-  real *wall_r;       // molar rate per wall node of the last step
-  real *wall_dE;      // kinetic energy the wall gave the gas, last step
-  const uint8_t *kind;
-  const uint64_t *cls;
-  const uint64_t *gas_cls;   // class words in gas-list order
-  const uint32_t *emask;
-  const uint32_t *gas_list;
-  const uint32_t *wall_list;
+  real *G[2];         // populations [(j*Q + i)*nsl + slot], double-buffered
+  real *F;            // per-step moments [field*nsl + slot] (offsets below)
+  real *Ts[2];        // solid temperature per node, double-buffered
+  real *wall_r;       // molar rate per node (wall nodes) of the last step
+  real *wall_dE;      // kinetic energy the wall gave the gas, per node, last step
+  const uint8_t *kind;       // node class per node
+  const int32_t *slot_of;    // slot per node
+  const uint64_t *scls;      // streaming class word per gas/wall slot
+  const uint32_t *wem;       // emission mask per wall node (wall order)
+  const uint32_t *gas_list;  // node of each gas slot
+  const uint32_t *wall_list; // node of each wall node
   double *acc_moles;  // per-block cumulative reaction extent
   double *acc_work;   // per-block cumulative body-force work
   double *acc_bheat;  // per-block cumulative Dirichlet-face heat
   double *partials;   // observe reduction partials
 };
 
-// Moments field offsets inside F (units of n): rho_j, tau1_j, tau2_j, u_a,
+// Moments field offsets inside F (units of nsl): rho_j, tau1_j, tau2_j, u_a,
 // T, then the species velocities of f u_ja, the diffusion-velocity
 // correction U^c_a and the quasi-equilibrium energy defect sum_j rho_j |u_j - u|^2
 __host__ __device__ inline int fo_rho(int j) { return j; }

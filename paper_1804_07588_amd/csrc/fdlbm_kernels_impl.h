@@ -4,17 +4,25 @@
 //   k_wall     reactive diffusive wall at every wall node: streaming of the
 //              populations arriving from the gas, wall densities and the
 //              thermalised emission (Eq.(37)-(42), (50))
-//   k_moments  streaming into every gas node (Eq.(33)-(36)), stored for the
-//              collision, and everything local: moments, transport, U^c,
-//              species momenta of f (Eq.(3), (5), (7)-(8), (11), (14)-(17), (25))
-//   k_collide  correction sources from the node's and its face neighbours'
-//              moments, temperature of f, equilibria and the trapezoidal
+//   k_moments  streaming into every gas node (Eq.(33)-(36)), evaluated on the
+//              fly, and everything local: moments, transport, U^c, species
+//              momenta of f (Eq.(3), (5), (7)-(8), (11), (14)-(17), (25))
+//   k_esum     temperature of f and of the auxiliary state from the energy
+//              moments of all species' sources
+//   k_collide  streaming again, correction sources from the node's and its
+//              face neighbours' moments, equilibria and the trapezoidal
 //              collision (Eq.(4), (6), (12)-(13), (19)-(21), (24)); writes the
 //              inlet/outlet planes directly
 //   k_solid    forward-Euler heat step in the solid on an LDS tile with the
 //              wall-node interface source (Eq.(45)-(48))
-// Populations are structure-of-arrays [(j*Q + i)*n + node], so a wavefront of
-// consecutive gas nodes touches 64 consecutive values per (species, direction).
+//
+// Populations and moments are stored per SLOT (gas nodes in list order, then
+// wall nodes), structure of arrays [(j*Q + i)*nsl + slot]: a wavefront of
+// consecutive gas slots reads and writes 64 consecutive values per (species,
+// direction) with no solid node in between.  The streamed populations are
+// never stored: the moments kernel and the collision kernel each rebuild them
+// from the taps, so a step reads the population array twice and writes it
+// once.
 #pragma once
 #include <type_traits>
 
@@ -34,9 +42,9 @@ __device__ inline int wrapc(int v, int n) {
 }
 
 // Blocks are dispatched round-robin over the 8 XCDs.  Give each XCD a
-// contiguous run of logical blocks, so node-list neighbours (adjacent rows)
-// are processed by one XCD close in time and share its L2.  Launch
-// xcd_grid(nb) blocks; logical ids >= nb do nothing.
+// contiguous run of logical blocks, so slot neighbours (adjacent rows) are
+// processed by one XCD close in time and share its L2.  Launch xcd_grid(nb)
+// blocks; logical ids >= nb do nothing.
 constexpr int NXCD = 8;
 __host__ __device__ inline int xcd_grid(int nb) { return ((nb + NXCD - 1) / NXCD) * NXCD; }
 __device__ inline int xcd_block(int nb) {
@@ -116,32 +124,44 @@ __device__ constexpr uint64_t pack_offsets() {
 }
 
 // load base[idx] with a uniform base (SGPRs) and a 32-bit per-lane byte offset
-template <typename real>
-__device__ inline real ld(const real *__restrict__ base, int idx) {
-  const uint32_t off = uint32_t(idx) * uint32_t(sizeof(real));
-  return *reinterpret_cast<const real *>(reinterpret_cast<const char *>(base) + off);
+template <typename T>
+__device__ inline T ld(const T *__restrict__ base, int idx) {
+  const uint32_t off = uint32_t(idx) * uint32_t(sizeof(T));
+  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + off);
 }
-template <typename real>
-__device__ inline void st(real *__restrict__ base, int idx, real v) {
-  const uint32_t off = uint32_t(idx) * uint32_t(sizeof(real));
-  *reinterpret_cast<real *>(reinterpret_cast<char *>(base) + off) = v;
+template <typename T>
+__device__ inline void st(T *__restrict__ base, int idx, T v) {
+  const uint32_t off = uint32_t(idx) * uint32_t(sizeof(T));
+  *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + off) = v;
 }
 
-// Pre-collision population of species j, direction i at a destination node,
-// Eq.(33)-(36): the interpolant through the taps of the node's stencil class
-// evaluated at the off-lattice shift s_j; one branch-free code path for all
-// classes.  On-lattice species (c_j = 1) read the upstream node only.
+// Slots of the three taps of direction i for stencil class cls around the
+// node of ad, Eq.(33)-(36).  No branch: class 7 (not a destination) reads
+// the node itself like class 6 and the caller discards the value, so every
+// load of a direction can be issued together.
+struct TapSlots {
+  int s[3];
+};
 template <bool FAST, typename real, int D>
-__device__ inline real stream_pop(const real *__restrict__ Gji, const Params<real> &p,
-                                  const Addr<D> &ad, int j, int i, int cls, const WTab<real> &wt) {
-  if (p.onlat[j]) return ld(Gji, ad.template at<FAST>(i, cls == 6 ? 0 : -1));  // uniform branch
+__device__ inline TapSlots tap_slots(const Bufs<real> &b, const Addr<D> &ad, int i, int cls) {
   constexpr uint64_t OFF = pack_offsets();
-  const int sh = 9 * cls;
-  const int o0 = int((OFF >> sh) & 7u) - 3, o1 = int((OFF >> (sh + 3)) & 7u) - 3,
-            o2 = int((OFF >> (sh + 6)) & 7u) - 3;
-  return wt.w[j][cls][0] * ld(Gji, ad.template at<FAST>(i, o0)) +
-         wt.w[j][cls][1] * ld(Gji, ad.template at<FAST>(i, o1)) +
-         wt.w[j][cls][2] * ld(Gji, ad.template at<FAST>(i, o2));
+  const int sh = 9 * (cls < 7 ? cls : 6);
+  TapSlots t;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int o = int((OFF >> (sh + 3 * k)) & 7u) - 3;
+    t.s[k] = ld(b.slot_of, ad.template at<FAST>(i, o));
+  }
+  return t;
+}
+
+// Pre-collision population of one species from its direction-i array Gji:
+// the interpolant through the class's taps at the species' shift.  An
+// on-lattice species (c_j = 1) has weights that are exactly one 1 and two 0s,
+// so the same expression returns the upstream value unrounded.
+template <typename real>
+__device__ inline real interp(const real *__restrict__ Gji, const TapSlots &t, const real *w) {
+  return w[0] * ld(Gji, t.s[0]) + w[1] * ld(Gji, t.s[1]) + w[2] * ld(Gji, t.s[2]);
 }
 
 // compile-time loop: f(std::integral_constant<int, I>) for I in [B, E)
@@ -186,13 +206,16 @@ __device__ inline real ipow(real x, int k) {
 // ===========================================================================
 template <bool FAST, typename real, int D, int NS>
 __device__ inline double wall_node(const Params<real> &p, const Bufs<real> &b, int cur,
-                                   const WTab<real> &wtab, const int w, const Addr<D> &ad) {
+                                   const WTab<real> &wtab, const int wi) {
   constexpr int Q = lat_q<D>();
-  const uint64_t cw = b.cls[w];
-  const uint32_t em = b.emask[w];
-  const real *G = b.G[cur];
-  real *Gn = b.G[cur ^ 1];
-  const int n = p.n;
+  const int slot = p.n_gas + wi;
+  const int w = (int)b.wall_list[wi];
+  const Addr<D> ad(w, p);
+  const uint64_t cw = b.scls[slot];
+  const uint32_t em = b.wem[wi];
+  const real *__restrict__ G = b.G[cur];
+  real *__restrict__ Gn = b.G[cur ^ 1];
+  const int nsl = p.nsl;
   const real Tw = p.wall_mode == 1 ? p.T_iso : b.Ts[cur][w];
   real wt[Q];
   const real u0[3] = {0, 0, 0};
@@ -203,22 +226,24 @@ __device__ inline double wall_node(const Params<real> &p, const Bufs<real> &b, i
   for (int i = 1; i < Q; ++i)
     if (em & (1u << i)) Z += wt[i];
   // A_j: mass arriving from the gas (incoming links), with its energy
-  real A[NS], Ein = 0;
+  real A[NS], Ej[NS];
 #pragma unroll
-  for (int j = 0; j < NS; ++j) {
-    asm volatile("" ::: "memory");
-    A[j] = 0;
-    real Ej = 0;
+  for (int j = 0; j < NS; ++j) A[j] = Ej[j] = 0;
 #pragma unroll
-    for (int i = 1; i < Q; ++i) {
-      const int cls = cls_at(cw, i);
-      if (cls == CLS_NONE) continue;
-      const real g = stream_pop<FAST, real, D>(G + (size_t)(j * Q + i) * n, p, ad, j, i, cls, wtab);
+  for (int i = 1; i < Q; ++i) {
+    const int cls = cls_at(cw, i);
+    if (cls == CLS_NONE) continue;  // direction i does not arrive from the gas
+    const TapSlots ts = tap_slots<FAST, real, D>(b, ad, i, cls);
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      const real g = interp(G + (size_t)(j * Q + i) * nsl, ts, wtab.w[j][cls]);
       A[j] += g;
-      Ej += real(cnorm2<D>(i)) * g;
+      Ej[j] += real(cnorm2<D>(i)) * g;
     }
-    Ein += p.cj2[j] * Ej;
   }
+  real Ein = 0;
+#pragma unroll
+  for (int j = 0; j < NS; ++j) Ein += p.cj2[j] * Ej[j];
   // wall densities: rho_w,j Z = A_j + nu_j M_j r (Eq.(41) with Eq.(50));
   // fixed point started at the non-reactive density, each reactant's own
   // concentration treated implicitly
@@ -254,20 +279,20 @@ __device__ inline double wall_node(const Params<real> &p, const Bufs<real> &b, i
 #pragma unroll
   for (int j = 0; j < NS; ++j) {
     rw[j] = (A[j] + p.nu[j] * p.M[j] * r) * invZ;
-    real Ej = 0;
+    real Eo = 0;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
       if (!(em & (1u << i))) continue;
       const real W = rw[j] * wt[i];
-      Gn[(size_t)(j * Q + i) * n + w] = W;
-      Ej += real(cnorm2<D>(i)) * W;
+      st(Gn + (size_t)(j * Q + i) * nsl, slot, W);
+      Eo += real(cnorm2<D>(i)) * W;
     }
-    Eout += p.cj2[j] * Ej;
-    b.F[(size_t)fo_rho(j) * n + w] = rw[j];
+    Eout += p.cj2[j] * Eo;
+    st(b.F + (size_t)fo_rho(j) * nsl, slot, rw[j]);
   }
 #pragma unroll
-  for (int a = 0; a < D; ++a) b.F[(size_t)fo_u(NS, a) * n + w] = real(0);
-  b.F[(size_t)fo_T<D>(NS) * n + w] = Tw;
+  for (int a = 0; a < D; ++a) st(b.F + (size_t)fo_u(NS, a) * nsl, slot, real(0));
+  st(b.F + (size_t)fo_T<D>(NS) * nsl, slot, Tw);
   b.wall_r[w] = r;
   b.wall_dE[w] = real(0.5) * (Eout - Ein);
   return (double)r;
@@ -282,80 +307,63 @@ __global__ void __launch_bounds__(BLOCK) k_wall(Params<real> p, Bufs<real> b, in
   const int nb = (count + BLOCK - 1) / BLOCK, lb = xcd_block(nb);
   if (lb >= nb) return;  // whole block: no barrier follows for it
   const int t = lb * BLOCK + threadIdx.x;
-  const bool active = t < count;
-  const int w = active ? (int)b.wall_list[first + t] : 0;
-  const Addr<D> ad(w, p);
   double r_out = 0.0;
-  if (active) r_out = wall_node<FAST, real, D, NS>(p, b, cur, wtab, w, ad);
+  if (t < count) r_out = wall_node<FAST, real, D, NS>(p, b, cur, wtab, first + t);
   const double s = block_sum(r_out);
   if (threadIdx.x == 0) b.acc_moles[lb + (FAST ? 0 : p.slot_off_wall)] += s;
 }
 
 // ===========================================================================
-// k_stream: streaming into every gas node (Eq.(33)-(36)), one thread per
-// (node, moving direction) handling every species (the taps are the same
-// nodes for all species; only the weights differ).  The direction is uniform
-// per block and each XCD walks a contiguous run of (direction, node block),
-// so it works through NS population arrays at a time and the taps a plane
-// away are still in its L2.  The rest population does not move and is read
-// in place by the later kernels.
+// k_moments: streaming into every gas node (evaluated, not stored), the
+// moments of the streamed populations and every local quantity of the node
+// (Eq.(3), (5), (7)-(8), (11), (14)-(17), (25)), one thread per node.  The
+// taps of a direction are the same slots for every species.
 // ===========================================================================
 template <bool FAST, typename real, int D, int NS>
-__global__ void __launch_bounds__(BLOCK) k_stream(Params<real> p, Bufs<real> b, int cur) {
+__global__ void __launch_bounds__(BLOCK) k_moments(Params<real> p, Bufs<real> b, int cur) {
   constexpr int Q = lat_q<D>();
   __shared__ WTab<real> wtab;
   load_wtab<real, NS>(p, wtab);
   const int first = FAST ? 0 : p.n_gas_fast, count = FAST ? p.n_gas_fast : p.n_gas - p.n_gas_fast;
-  const int nbn = (count + BLOCK - 1) / BLOCK, nb = nbn * (Q - 1), lb = xcd_block(nb);
+  const int nb = (count + BLOCK - 1) / BLOCK, lb = xcd_block(nb);
   if (lb >= nb) return;
-  const int im = lb / nbn;  // moving direction index - 1 of this block
-  const int i = 1 + im;
-  const int t = (lb - im * nbn) * BLOCK + threadIdx.x;
-  if (t >= count) return;
-  const int node = (int)b.gas_list[first + t];
-  const int cls = cls_at(b.gas_cls[first + t], i);
-  const Addr<D> ad(node, p);
-  const int n = p.n;
-  real g[NS];
-#pragma unroll
-  for (int j = 0; j < NS; ++j)
-    g[j] = stream_pop<FAST, real, D>(b.G[cur] + (size_t)(j * Q + i) * n, p, ad, j, i, cls, wtab);
-#pragma unroll
-  for (int j = 0; j < NS; ++j) st(b.Gs + (size_t)(j * Q + i) * n, node, g[j]);
-}
-
-// ===========================================================================
-// k_moments: moments of the streamed populations and every local quantity of
-// each gas node (Eq.(3), (5), (7)-(8), (11), (14)-(17), (25)), one thread per node
-// ===========================================================================
-template <typename real, int D, int NS>
-__global__ void __launch_bounds__(BLOCK) k_moments(Params<real> p, Bufs<real> b, int cur) {
-  constexpr int Q = lat_q<D>();
-  const int nb = (p.n_gas + BLOCK - 1) / BLOCK, lb = xcd_block(nb);
-  const int t = lb * BLOCK + threadIdx.x;
-  if (lb >= nb || t >= p.n_gas) return;
+  const int tl = lb * BLOCK + threadIdx.x;
+  if (tl >= count) return;
+  const int t = first + tl;  // slot
   const int node = (int)b.gas_list[t];
-  real *F = b.F;
-  const int n = p.n;
-  real rho[NS], Jg[NS][D], E = 0;
+  const Addr<D> ad(node, p);
+  const uint64_t cw = b.scls[t];
+  const real *__restrict__ G = b.G[cur];
+  real *__restrict__ F = b.F;
+  const int nsl = p.nsl;
+  real rho[NS], Jg[NS][D], Es[NS];
 #pragma unroll
   for (int j = 0; j < NS; ++j) {
-    real r = ld(b.G[cur] + (size_t)(j * Q) * n, node), Jj[D], Ej = 0;
+    rho[j] = ld(G + (size_t)(j * Q) * nsl, t);  // rest population: not streamed
+    Es[j] = 0;
 #pragma unroll
-    for (int a = 0; a < D; ++a) Jj[a] = 0;
+    for (int a = 0; a < D; ++a) Jg[j][a] = 0;
+  }
+  static_for<1, Q>([&](auto ic_) __attribute__((always_inline)) {
+    constexpr int i = decltype(ic_)::value;
+    const int cls = cls_at(cw, i);
+    const TapSlots ts = tap_slots<FAST, real, D>(b, ad, i, cls);
 #pragma unroll
-    for (int i = 1; i < Q; ++i) {
-      const real g = ld(b.Gs + (size_t)(j * Q + i) * n, node);
-      r += g;
+    for (int j = 0; j < NS; ++j) {
+      const real g = interp(G + (size_t)(j * Q + i) * nsl, ts, wtab.w[j][cls]);
+      rho[j] += g;
 #pragma unroll
       for (int a = 0; a < D; ++a)
-        if (cvec<D>(i, a) != 0) Jj[a] += cvec<D>(i, a) > 0 ? g : -g;
-      Ej += real(cnorm2<D>(i)) * g;
+        if (cvec<D>(i, a) != 0) Jg[j][a] += cvec<D>(i, a) > 0 ? g : -g;
+      Es[j] += real(cnorm2<D>(i)) * g;
     }
-    rho[j] = r;
+  });
+  real E = 0;
 #pragma unroll
-    for (int a = 0; a < D; ++a) Jg[j][a] = p.cj[j] * Jj[a];
-    E += p.cj2[j] * Ej;
+  for (int j = 0; j < NS; ++j) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) Jg[j][a] *= p.cj[j];
+    E += p.cj2[j] * Es[j];
   }
   real rhot = 0, C = 0;
 #pragma unroll
@@ -397,8 +405,8 @@ __global__ void __launch_bounds__(BLOCK) k_moments(Params<real> p, Bufs<real> b,
 #pragma unroll
     for (int k = 0; k < NS; ++k) den += Xh[k] * p.wilke[j][k];
     const real tau1 = p.mu0[j] * fmu / (CT * den);  // Eq.(17)
-    st(F + (size_t)fo_tau1(NS, j) * n, node, tau1);
-    st(F + (size_t)fo_rho(j) * n, node, rho[j]);
+    st(F + (size_t)fo_tau1(NS, j) * nsl, t, tau1);
+    st(F + (size_t)fo_rho(j) * nsl, t, rho[j]);
     tau2[j] = tau1;
   }
   if (NS > 1) {
@@ -414,10 +422,10 @@ __global__ void __launch_bounds__(BLOCK) k_moments(Params<real> p, Bufs<real> b,
     }
   }
 #pragma unroll
-  for (int j = 0; j < NS; ++j) st(F + (size_t)fo_tau2(NS, j) * n, node, tau2[j]);
+  for (int j = 0; j < NS; ++j) st(F + (size_t)fo_tau2(NS, j) * nsl, t, tau2[j]);
 #pragma unroll
-  for (int a = 0; a < D; ++a) st(F + (size_t)fo_u(NS, a) * n, node, u[a]);
-  st(F + (size_t)fo_T<D>(NS) * n, node, T);
+  for (int a = 0; a < D; ++a) st(F + (size_t)fo_u(NS, a) * nsl, t, u[a]);
+  st(F + (size_t)fo_T<D>(NS) * nsl, t, T);
   // Eq.(25) with Eq.(11): species momenta of f and U^c in closed form
   const bool cdiff = (p.flags & 1u) && NS > 1;
   real ediff = 0;
@@ -432,16 +440,16 @@ __global__ void __launch_bounds__(BLOCK) k_moments(Params<real> p, Bufs<real> b,
       den += ah[j] * rho[j] / (real(1) + ah[j]);
     }
     const real Uc = cdiff ? num / den : real(0);
-    st(F + (size_t)fo_Uc<D>(NS, a) * n, node, Uc);
+    st(F + (size_t)fo_Uc<D>(NS, a) * nsl, t, Uc);
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
       const real Jf = K[j] + ah[j] * rho[j] * Uc / (real(1) + ah[j]);
       const real uja = rho[j] > tiny<real>() ? Jf / rho[j] : u[a];
-      st(F + (size_t)fo_uj<D>(NS, j, a) * n, node, uja);
+      st(F + (size_t)fo_uj<D>(NS, j, a) * nsl, t, uja);
       ediff += rho[j] * (uja - u[a]) * (uja - u[a]);
     }
   }
-  st(F + (size_t)fo_ediff<D>(NS) * n, node, ediff);
+  st(F + (size_t)fo_ediff<D>(NS) * nsl, t, ediff);
 }
 
 // ===========================================================================
@@ -470,53 +478,54 @@ __device__ inline real r_dev(real rho, real invM, const real *u, real T, int a, 
 template <typename real, int D>
 struct NbCommon {
   real u[D], T;
-  int node;  // node supplying rho_j and tau1_j (self when missing)
+  int slot;  // slot supplying rho_j and tau1_j (the centre's when missing)
   bool wall, missing;
 };
 
-// face neighbours of src: indices and kinds (no load depends on another)
+// face neighbours of the node srcn (slot ss): slots, classes and the
+// mixture fields (a wall neighbour supplies the wall state)
 template <typename real, int D, int NS>
-__device__ inline void load_neighbours(const Params<real> &p, const Bufs<real> &b, int src,
+__device__ inline void load_neighbours(const Params<real> &p, const Bufs<real> &b, int srcn, int ss,
                                        NbCommon<real, D> (&nb)[D][2]) {
-  const Addr<D> ad(src, p);
-  const int n = p.n;
+  const Addr<D> ad(srcn, p);
+  const int nsl = p.nsl, null_slot = p.n_gas + p.n_wall;
 #pragma unroll
   for (int a = 0; a < D; ++a)
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       NbCommon<real, D> &v = nb[a][s];
       const int q = ad.face(p, a, s == 0 ? +1 : -1);
-      const int qq = q >= 0 ? q : src;
-      const uint8_t k = b.kind[qq];
-      v.wall = q >= 0 && k == KIND_WALL;
-      v.missing = !(q >= 0 && (gaslike(k) || k == KIND_WALL)) || q == src;
-      v.node = v.missing ? src : q;
+      const int ql = ld(b.slot_of, q >= 0 ? q : srcn);  // unconditional load
+      const int qs = q >= 0 ? ql : null_slot;
+      v.wall = qs >= p.n_gas && qs < null_slot;
+      v.missing = qs == null_slot || q == srcn;
+      v.slot = v.missing ? ss : qs;
 #pragma unroll
-      for (int c = 0; c < D; ++c) v.u[c] = ld(b.F + (size_t)fo_u(NS, c) * n, v.node);
-      v.T = ld(b.F + (size_t)fo_T<D>(NS) * n, v.node);
+      for (int c = 0; c < D; ++c) v.u[c] = ld(b.F + (size_t)fo_u(NS, c) * nsl, v.slot);
+      v.T = ld(b.F + (size_t)fo_T<D>(NS) * nsl, v.slot);
     }
 }
 
 // energy moment of species j's sources: trace of the second-moment source
 // (body force work, viscous correction) plus the Prandtl energy source
 template <typename real, int D, int NS>
-__device__ inline real energy_source(const Params<real> &p, const Bufs<real> &b, int src, int j,
+__device__ inline real energy_source(const Params<real> &p, const Bufs<real> &b, int ss, int j,
                                      const real *u, real Tt, const NbCommon<real, D> (&nb)[D][2]) {
-  const int n = p.n;
+  const int nsl = p.nsl;
   const real *F = b.F;
   const bool cvisc = p.flags & 2u, cpr = (p.flags & 8u) && p.kpr != real(0);
   const real iM = p.invM[j];
-  const real rj = ld(F + (size_t)fo_rho(j) * n, src);
+  const real rj = ld(F + (size_t)fo_rho(j) * nsl, ss);
   real e = 0;
 #pragma unroll
   for (int a = 0; a < D; ++a) e += real(2) * rj * u[a] * p.F[a];
   if (!(cvisc || cpr)) return e;
-  const real tau1x = ld(F + (size_t)fo_tau1(NS, j) * n, src);
+  const real tau1x = ld(F + (size_t)fo_tau1(NS, j) * nsl, ss);
   const real Kx = p.kpr * tau1x * rj * iM * Tt * iM;
 #pragma unroll
   for (int a = 0; a < D; ++a) {
     const NbCommon<real, D> &sp = nb[a][0], &sm = nb[a][1];
-    const real rp = ld(F + (size_t)fo_rho(j) * n, sp.node), rm = ld(F + (size_t)fo_rho(j) * n, sm.node);
+    const real rp = ld(F + (size_t)fo_rho(j) * nsl, sp.slot), rm = ld(F + (size_t)fo_rho(j) * nsl, sm.slot);
     if (cvisc) {
       const real qx = q_dev<real, D>(rj, iM, u[a], Tt);
       const real qp = sp.wall ? -qx : q_dev<real, D>(rp, iM, sp.u[a], sp.T);
@@ -524,13 +533,28 @@ __device__ inline real energy_source(const Params<real> &p, const Bufs<real> &b,
       e += real(0.5) * (qp - qm);
     }
     if (cpr) {
-      const real tp = ld(F + (size_t)fo_tau1(NS, j) * n, sp.node);
-      const real tm = ld(F + (size_t)fo_tau1(NS, j) * n, sm.node);
-      if (!sp.wall && !sp.missing) e += real(0.5) * (Kx + p.kpr * tp * rp * iM * sp.T * iM) * (sp.T - Tt);
-      if (!sm.wall && !sm.missing) e += real(0.5) * (Kx + p.kpr * tm * rm * iM * sm.T * iM) * (sm.T - Tt);
+      const real tp = ld(F + (size_t)fo_tau1(NS, j) * nsl, sp.slot);
+      const real tm = ld(F + (size_t)fo_tau1(NS, j) * nsl, sm.slot);
+      const real ep = real(0.5) * (Kx + p.kpr * tp * rp * iM * sp.T * iM) * (sp.T - Tt);
+      const real em = real(0.5) * (Kx + p.kpr * tm * rm * iM * sm.T * iM) * (sm.T - Tt);
+      e += (!sp.wall && !sp.missing) ? ep : real(0);
+      e += (!sm.wall && !sm.missing) ? em : real(0);
     }
   }
   return e;
+}
+
+// the node whose collision a gas node stores: an outlet node takes the last
+// interior node of its row (zero-gradient outlet), every other node itself
+struct SrcNode {
+  int node, slot;
+};
+template <typename real>
+__device__ inline SrcNode collision_source(const Params<real> &p, const Bufs<real> &b, int node, int t) {
+  // outlet rows exist only with nx >= 6, and slot_of(node) = t otherwise:
+  // one unconditional load serves both cases
+  const int sn = b.kind[node] == KIND_OUTLET ? node - node % p.nx + p.nx - 3 : node;
+  return {sn, ld(b.slot_of, sn)};
 }
 
 // ===========================================================================
@@ -543,30 +567,29 @@ __global__ void __launch_bounds__(BLOCK) k_esum(Params<real> p, Bufs<real> b, in
   const int nblk = (p.n_gas + BLOCK - 1) / BLOCK, lb = xcd_block(nblk);
   const int t = lb * BLOCK + threadIdx.x;
   if (lb >= nblk || t >= p.n_gas) return;
-  const int node = (int)b.gas_list[t];
-  const int src = b.kind[node] == KIND_OUTLET ? node - node % p.nx + p.nx - 3 : node;
-  const int n = p.n;
+  const SrcNode sc = collision_source(p, b, (int)b.gas_list[t], t);
+  const int nsl = p.nsl;
   real u[D];
 #pragma unroll
-  for (int a = 0; a < D; ++a) u[a] = ld(b.F + (size_t)fo_u(NS, a) * n, src);
-  const real Tt = ld(b.F + (size_t)fo_T<D>(NS) * n, src);
+  for (int a = 0; a < D; ++a) u[a] = ld(b.F + (size_t)fo_u(NS, a) * nsl, sc.slot);
+  const real Tt = ld(b.F + (size_t)fo_T<D>(NS) * nsl, sc.slot);
   NbCommon<real, D> nb[D][2];
   const bool cgrad = (p.flags & 10u) != 0;
-  if (cgrad) load_neighbours<real, D, NS>(p, b, src, nb);
+  if (cgrad) load_neighbours<real, D, NS>(p, b, sc.node, sc.slot, nb);
   real C = 0, esum = 0;
 #pragma unroll
   for (int j = 0; j < NS; ++j) {
-    C += ld(b.F + (size_t)fo_rho(j) * n, src) * p.invM[j];
-    esum += energy_source<real, D, NS>(p, b, src, j, u, Tt, nb);
+    C += ld(b.F + (size_t)fo_rho(j) * nsl, sc.slot) * p.invM[j];
+    esum += energy_source<real, D, NS>(p, b, sc.slot, j, u, Tt, nb);
   }
   const real Tf = Tt + esum / (real(2 * D) * C);
-  const real Tst = Tf - ld(b.F + (size_t)fo_ediff<D>(NS) * n, src) / (real(D) * C);
-  st(b.F + (size_t)fo_Tf<D>(NS) * n, node, Tf);
-  st(b.F + (size_t)fo_Tst<D>(NS) * n, node, Tst);
+  const real Tst = Tf - ld(b.F + (size_t)fo_ediff<D>(NS) * nsl, sc.slot) / (real(D) * C);
+  st(b.F + (size_t)fo_Tf<D>(NS) * nsl, t, Tf);
+  st(b.F + (size_t)fo_Tst<D>(NS) * nsl, t, Tst);
 }
 
 // ===========================================================================
-// k_collide: sources, temperature of f, equilibria and Eq.(24) (pass 2)
+// k_collide: streaming, sources, equilibria and Eq.(24)
 // ===========================================================================
 // Per-axis factors of the equilibrium (see equilibrium() in fdlbm_device.h)
 template <typename real, int D>
@@ -607,191 +630,189 @@ struct EqFactors {
   }
 };
 
-template <typename real, int D, int NS>
+// Collision of species j at gas slot t, computed at the source node sc (an
+// outlet node takes the last interior node of its row) and stored at t.
+// Straight-line code: every load is unconditional (addresses are always
+// valid) and the switches act through selects, so the compiler can issue the
+// tap loads, the node's fields and the neighbours' fields together.
+template <bool FAST, typename real, int D, int NS>
 __device__ inline void collide_node(const Params<real> &p, const Bufs<real> &b, int cur,
-                                    const int node, const int src, const int j) {
-  // src: node whose collision is computed (an outlet node takes the result of
-  // the last interior node of its row); node: where it is stored
+                                    const WTab<real> &wtab, const int t, const SrcNode sc,
+                                    const int j) {
   constexpr int Q = lat_q<D>();
-  const int n = p.n;
+  const int nsl = p.nsl;
+  const int ss = sc.slot;
   const real *__restrict__ F = b.F;
-  const real *__restrict__ Gs = b.Gs;
-  real u[D];
+  // streamed populations of species j at the source node (Eq.(33)-(36))
+  const Addr<D> ad(sc.node, p);
+  const uint64_t cw = b.scls[ss];
+  const real *__restrict__ Gj = b.G[cur] + (size_t)(j * Q) * nsl;
+  real g[Q];
+  g[0] = ld(Gj, ss);  // rest: not streamed
+  static_for<1, Q>([&](auto ic_) __attribute__((always_inline)) {
+    constexpr int i = decltype(ic_)::value;
+    const int cls = cls_at(cw, i);
+    g[i] = interp(Gj + (size_t)i * nsl, tap_slots<FAST, real, D>(b, ad, i, cls), wtab.w[j][cls]);
+  });
+  // node fields
+  real u[D], uj[D], Uc[D];
 #pragma unroll
-  for (int a = 0; a < D; ++a) u[a] = ld(F + (size_t)fo_u(NS, a) * n, src);
-  const real Tt = ld(F + (size_t)fo_T<D>(NS) * n, src);
-  const real Tf = ld(F + (size_t)fo_Tf<D>(NS) * n, node);
-  const real Tst = ld(F + (size_t)fo_Tst<D>(NS) * n, node);
-  const bool cdiff = (p.flags & 1u) && NS > 1;
-  const bool cvisc = p.flags & 2u, cener = p.flags & 4u, cpr = (p.flags & 8u) && p.kpr != real(0);
-  const bool cgrad = cvisc || cener || cpr;
+  for (int a = 0; a < D; ++a) {
+    u[a] = ld(F + (size_t)fo_u(NS, a) * nsl, ss);
+    uj[a] = ld(F + (size_t)fo_uj<D>(NS, j, a) * nsl, ss);
+    Uc[a] = ld(F + (size_t)fo_Uc<D>(NS, a) * nsl, ss);
+  }
+  const real Tt = ld(F + (size_t)fo_T<D>(NS) * nsl, ss);
+  const real Tf = ld(F + (size_t)fo_Tf<D>(NS) * nsl, t);
+  const real Tst = ld(F + (size_t)fo_Tst<D>(NS) * nsl, t);
+  const real rj = ld(F + (size_t)fo_rho(j) * nsl, ss);
+  const real tau1 = ld(F + (size_t)fo_tau1(NS, j) * nsl, ss);
+  const real tau2 = ld(F + (size_t)fo_tau2(NS, j) * nsl, ss);
   NbCommon<real, D> nb[D][2];
-  if (cgrad) load_neighbours<real, D, NS>(p, b, src, nb);
+  load_neighbours<real, D, NS>(p, b, sc.node, ss, nb);
+  real rnb[D][2], tnb[D][2];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      rnb[a][s] = ld(F + (size_t)fo_rho(j) * nsl, nb[a][s].slot);
+      tnb[a][s] = ld(F + (size_t)fo_tau1(NS, j) * nsl, nb[a][s].slot);
+    }
+  // switches (uniform): 1 or 0
+  const real kdiff = ((p.flags & 1u) && NS > 1) ? real(1) : real(0);
+  const real kvisc = (p.flags & 2u) ? real(1) : real(0);
+  const real kener = (p.flags & 4u) ? real(1) : real(0);
+  const real kpr = (p.flags & 8u) ? p.kpr : real(0);
   // source moments of species j: momentum m, second moments P (diagonal Pd,
   // off-diagonal Po: xy, xz, yz), energy flux Y, energy e
-  auto sources = [&](const int j, const real rj, real (&m)[D], real (&Pd)[D], real (&Po)[3],
-                     real (&Y)[D], real &e, const bool energy_only) __attribute__((always_inline)) {
-    const real iM = p.invM[j];
-    e = 0;
-    const real tau2x = ld(F + (size_t)fo_tau2(NS, j) * n, src);
+  const real iM = p.invM[j];
+  real m[D], Pd[D], Po[3], Y[D], e = 0;
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
-      const real Uca = cdiff ? ld(F + (size_t)fo_Uc<D>(NS, a) * n, src) : real(0);
-      m[a] = (cdiff ? rj * Uca / tau2x : real(0)) + rj * p.F[a];  // Eq.(12) + body force
-      Pd[a] = real(2) * rj * u[a] * p.F[a];
-      Y[a] = 0;
-    }
-    Po[0] = rj * (u[0] * p.F[1] + u[1] * p.F[0]);
-    Po[1] = Po[2] = 0;
-    if constexpr (D == 3) {
-      Po[1] = rj * (u[0] * p.F[2] + u[2] * p.F[0]);
-      Po[2] = rj * (u[1] * p.F[2] + u[2] * p.F[1]);
-    }
-    if (!cgrad) return;
-    const real tau1x = ld(F + (size_t)fo_tau1(NS, j) * n, src);
-    const real Kx = p.kpr * tau1x * rj * iM * Tt * iM;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      const NbCommon<real, D> &sp = nb[a][0], &sm = nb[a][1];
-      const real rp = ld(F + (size_t)fo_rho(j) * n, sp.node), rm = ld(F + (size_t)fo_rho(j) * n, sm.node);
-      if (cvisc) {
-        // d_a Q'_aaa; a wall face carries no correction flux (mirror value)
-        const real qx = q_dev<real, D>(rj, iM, u[a], Tt);
-        const real qp = sp.wall ? -qx : q_dev<real, D>(rp, iM, sp.u[a], sp.T);
-        const real qm = sm.wall ? -qx : q_dev<real, D>(rm, iM, sm.u[a], sm.T);
-        Pd[a] += real(0.5) * (qp - qm);
-        if constexpr (D == 3) {
-          if (!energy_only) {
-            // d_a of Q'_xyz = -rho u_x u_y u_z feeds the off-diagonal pair not containing a
-            const real dq = real(0.5) * (-rp * sp.u[0] * sp.u[1] * sp.u[2] + rm * sm.u[0] * sm.u[1] * sm.u[2]);
-            Po[2 - a] += dq;  // a = x -> yz (2), y -> xz (1), z -> xy (0)
-          }
-        }
-      }
-      if (cener && !energy_only) {
-#pragma unroll
-        for (int c = 0; c < D; ++c)
-          Y[c] += real(0.5) * (r_dev<real, D>(rp, iM, sp.u, sp.T, c, a) -
-                               r_dev<real, D>(rm, iM, sm.u, sm.T, c, a));
-      }
-      if (cpr) {
-        // Eq.(19)-(21), face-flux form; wall faces carry no correction flux
-        if (!sp.wall && !sp.missing) {
-          const real tp = ld(F + (size_t)fo_tau1(NS, j) * n, sp.node);
-          e += real(0.5) * (Kx + p.kpr * tp * rp * iM * sp.T * iM) * (sp.T - Tt);
-        }
-        if (!sm.wall && !sm.missing) {
-          const real tm = ld(F + (size_t)fo_tau1(NS, j) * n, sm.node);
-          e += real(0.5) * (Kx + p.kpr * tm * rm * iM * sm.T * iM) * (sm.T - Tt);
-        }
-      }
-    }
-  };
-  // ---- species j: sources, equilibria and Eq.(24) ----
-  real *__restrict__ Gn = b.G[cur ^ 1];
-  {
-    const real rj = ld(F + (size_t)fo_rho(j) * n, src);
-    real uj[D];
-#pragma unroll
-    for (int a = 0; a < D; ++a) uj[a] = ld(F + (size_t)fo_uj<D>(NS, j, a) * n, src);
-    real m[D], Pd[D], Po[3], Y[D], e;
-    sources(j, rj, m, Pd, Po, Y, e, false);
-    EqFactors<real, D> fe, fs;
-    fe.set(p.sqM[j], u, Tf);
-    fs.set(p.sqM[j], uj, Tst);
-    const real tau1 = ld(F + (size_t)fo_tau1(NS, j) * n, src);
-    const real tau2 = ld(F + (size_t)fo_tau2(NS, j) * n, src);
-    const real w1 = real(2) / (real(1) + real(2) * tau1);
-    const real r12 = tau1 / tau2;
-    const real wt = w1 * tau1;
-    const real ic = p.invcj[j], ic2 = ic * ic, ic3 = ic2 * ic;
-    real trP = 0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) trP += Pd[a];
-    real se = 0, ss = 0;  // sums of the moving populations of f^eq and f* (per unit density)
-    const real *__restrict__ Gsj = Gs + (size_t)(j * Q) * n;
-    real *__restrict__ Gnj = Gn + (size_t)(j * Q) * n;
-    static_for<1, Q>([&](auto ic_) __attribute__((always_inline)) {
-      constexpr int i = decltype(ic_)::value;
-      real S;
-      if constexpr (is_face<D>(i)) {
-        constexpr int a = edge_axis<D>(i, 0);
-        constexpr real sg = real(cvec<D>(i, a));
-        S = sg * m[a] * ic + real(0.5) * Pd[a] * ic2 - real(0.5) * sg * Y[a] * ic3 +
-            e * ic2 / real(2 * D);
-      } else {
-        constexpr real kd = D == 2 ? real(0.25) : real(0.125);
-        constexpr int a0 = edge_axis<D>(i, 0), a1 = edge_axis<D>(i, 1);
-        constexpr int s0 = cvec<D>(i, a0), s1 = cvec<D>(i, a1);
-        constexpr int po = D == 2 ? 0 : (a0 == 0 ? (a1 == 1 ? 0 : 1) : 2);
-        S = -kd * (real(s0) * m[a0] + real(s1) * m[a1]) * ic + real(0.25 * s0 * s1) * Po[po] * ic2 +
-            kd * (real(s0) * Y[a0] + real(s1) * Y[a1]) * ic3;
-      }
-      const real pe = fe.template moving<i>(), ps = fs.template moving<i>();
-      se += pe;
-      ss += ps;
-      const real gi = ld(Gsj + (size_t)i * n, src);
-      const real feq = rj * pe, fst = rj * ps;
-      st(Gnj + (size_t)i * n, node, gi - w1 * (gi - fst) - w1 * r12 * (fst - feq) + wt * S);
-    });
-    const real S0 = -(trP + e) * ic2;
-    const real feq = rj * fe.rest(se), fst = rj * fs.rest(ss);
-    const real gi = ld(b.G[cur] + (size_t)(j * Q) * n, src);  // rest: not streamed
-    st(Gnj, node, gi - w1 * (gi - fst) - w1 * r12 * (fst - feq) + wt * S0);
+  for (int a = 0; a < D; ++a) {
+    m[a] = kdiff * rj * Uc[a] / tau2 + rj * p.F[a];  // Eq.(12) + body force
+    Pd[a] = real(2) * rj * u[a] * p.F[a];
+    Y[a] = 0;
   }
+  Po[0] = rj * (u[0] * p.F[1] + u[1] * p.F[0]);
+  Po[1] = Po[2] = 0;
+  if constexpr (D == 3) {
+    Po[1] = rj * (u[0] * p.F[2] + u[2] * p.F[0]);
+    Po[2] = rj * (u[1] * p.F[2] + u[2] * p.F[1]);
+  }
+  const real Kx = kpr * tau1 * rj * iM * Tt * iM;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const NbCommon<real, D> &sp = nb[a][0], &sm = nb[a][1];
+    const real rp = rnb[a][0], rm = rnb[a][1];
+    // d_a Q'_aaa; a wall face carries no correction flux (mirror value)
+    const real qx = q_dev<real, D>(rj, iM, u[a], Tt);
+    const real qp = sp.wall ? -qx : q_dev<real, D>(rp, iM, sp.u[a], sp.T);
+    const real qm = sm.wall ? -qx : q_dev<real, D>(rm, iM, sm.u[a], sm.T);
+    Pd[a] += kvisc * real(0.5) * (qp - qm);
+    if constexpr (D == 3) {
+      // d_a of Q'_xyz = -rho u_x u_y u_z feeds the off-diagonal pair not containing a
+      const real dq = real(0.5) * (-rp * sp.u[0] * sp.u[1] * sp.u[2] + rm * sm.u[0] * sm.u[1] * sm.u[2]);
+      Po[2 - a] += kvisc * dq;  // a = x -> yz (2), y -> xz (1), z -> xy (0)
+    }
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+      Y[c] += kener * real(0.5) * (r_dev<real, D>(rp, iM, sp.u, sp.T, c, a) -
+                                   r_dev<real, D>(rm, iM, sm.u, sm.T, c, a));
+    // Eq.(19)-(21), face-flux form; wall faces carry no correction flux
+    const real ep = real(0.5) * (Kx + kpr * tnb[a][0] * rp * iM * sp.T * iM) * (sp.T - Tt);
+    const real em = real(0.5) * (Kx + kpr * tnb[a][1] * rm * iM * sm.T * iM) * (sm.T - Tt);
+    e += (!sp.wall && !sp.missing) ? ep : real(0);
+    e += (!sm.wall && !sm.missing) ? em : real(0);
+  }
+  EqFactors<real, D> fe, fs;
+  fe.set(p.sqM[j], u, Tf);
+  fs.set(p.sqM[j], uj, Tst);
+  const real w1 = real(2) / (real(1) + real(2) * tau1);
+  const real r12 = tau1 / tau2;
+  const real wt = w1 * tau1;
+  const real ic = p.invcj[j], ic2 = ic * ic, ic3 = ic2 * ic;
+  real trP = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) trP += Pd[a];
+  real *__restrict__ Gnj = b.G[cur ^ 1] + (size_t)(j * Q) * nsl;
+  real se = 0, ss_ = 0;  // sums of the moving populations of f^eq and f* (per unit density)
+  static_for<1, Q>([&](auto ic_) __attribute__((always_inline)) {
+    constexpr int i = decltype(ic_)::value;
+    real S;
+    if constexpr (is_face<D>(i)) {
+      constexpr int a = edge_axis<D>(i, 0);
+      constexpr real sg = real(cvec<D>(i, a));
+      S = sg * m[a] * ic + real(0.5) * Pd[a] * ic2 - real(0.5) * sg * Y[a] * ic3 + e * ic2 / real(2 * D);
+    } else {
+      constexpr real kd = D == 2 ? real(0.25) : real(0.125);
+      constexpr int a0 = edge_axis<D>(i, 0), a1 = edge_axis<D>(i, 1);
+      constexpr int s0 = cvec<D>(i, a0), s1 = cvec<D>(i, a1);
+      constexpr int po = D == 2 ? 0 : (a0 == 0 ? (a1 == 1 ? 0 : 1) : 2);
+      S = -kd * (real(s0) * m[a0] + real(s1) * m[a1]) * ic + real(0.25 * s0 * s1) * Po[po] * ic2 +
+          kd * (real(s0) * Y[a0] + real(s1) * Y[a1]) * ic3;
+    }
+    const real pe = fe.template moving<i>(), ps = fs.template moving<i>();
+    se += pe;
+    ss_ += ps;
+    const real gi = g[i];
+    const real feq = rj * pe, fst = rj * ps;
+    st(Gnj + (size_t)i * nsl, t, gi - w1 * (gi - fst) - w1 * r12 * (fst - feq) + wt * S);
+  });
+  const real S0 = -(trP + e) * ic2;
+  const real feq = rj * fe.rest(se), fst = rj * fs.rest(ss_);
+  st(Gnj, t, g[0] - w1 * (g[0] - fst) - w1 * r12 * (fst - feq) + wt * S0);
 }
 
 // inlet node: equilibrium at the inlet state with the velocity of the first
 // interior plane of its row (Sec. 6)
 template <typename real, int D, int NS>
-__device__ inline void inlet_node(const Params<real> &p, const Bufs<real> &b, int cur, int node,
-                                  int j) {
+__device__ inline void inlet_node(const Params<real> &p, const Bufs<real> &b, int cur, int t,
+                                  int node, int j) {
   constexpr int Q = lat_q<D>();
-  const int n = p.n;
-  const int row = node - node % p.nx;
-  const int src = row + 2;
+  const int nsl = p.nsl;
+  const int src = node - node % p.nx + 2;
   const bool ok = gaslike(b.kind[src]);
+  const int ssl = ok ? ld(b.slot_of, src) : t;
   real u[D];
 #pragma unroll
-  for (int a = 0; a < D; ++a) u[a] = ok ? ld(b.F + (size_t)fo_u(NS, a) * n, src) : real(0);
+  for (int a = 0; a < D; ++a) u[a] = ok ? ld(b.F + (size_t)fo_u(NS, a) * nsl, ssl) : real(0);
   real *Gn = b.G[cur ^ 1];
   real f[Q];
   equilibrium<real, D>(p.rho_in[j], p.sqM[j], u, p.T_in, f);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) st(Gn + (size_t)(j * Q + i) * n, node, f[i]);
+  for (int i = 0; i < Q; ++i) st(Gn + (size_t)(j * Q + i) * nsl, t, f[i]);
 }
 
-// one thread per (node, species); the species is uniform per block
-template <typename real, int D, int NS>
+// one thread per (gas node, species); the species is uniform per block and
+// varies fastest over the logical blocks, so the NS blocks of one run of
+// nodes work together on one XCD and share the moments and taps in its L2
+template <bool FAST, typename real, int D, int NS>
 __global__ void __launch_bounds__(BLOCK) k_collide(Params<real> p, Bufs<real> b, int cur) {
-  // species fastest: the NS blocks of one node block run together on one XCD
-  // and share the node's and its neighbours' moments in L2
-  const int nbn = (p.n_gas + BLOCK - 1) / BLOCK, nb = nbn * NS, lb = xcd_block(nb);
+  __shared__ WTab<real> wtab;
+  load_wtab<real, NS>(p, wtab);
+  const int first = FAST ? 0 : p.n_gas_fast, count = FAST ? p.n_gas_fast : p.n_gas - p.n_gas_fast;
+  const int nbn = (count + BLOCK - 1) / BLOCK, nb = nbn * NS, lb = xcd_block(nb);
   if (lb >= nb) return;  // whole block: no barrier follows for it
   const int j = lb % NS;
-  const int t = (lb / NS) * BLOCK + threadIdx.x;
+  const int tl = (lb / NS) * BLOCK + threadIdx.x;
   double work = 0.0;
-  if (t < p.n_gas) {
+  if (tl < count) {
+    const int t = first + tl;
     const int node = (int)b.gas_list[t];
-    const uint8_t k = b.kind[node];
-    if (p.F[0] != real(0) || p.F[1] != real(0) || (D == 3 && p.F[2] != real(0))) {
+    {
       // work of the body force on species j this step, rho_j u.F (half the
       // trace of its source)
-      const int n = p.n;
+      const int nsl = p.nsl;
       real uf = 0;
 #pragma unroll
-      for (int a = 0; a < D; ++a) uf += ld(b.F + (size_t)fo_u(NS, a) * n, node) * p.F[a];
-      work = (double)(ld(b.F + (size_t)fo_rho(j) * n, node) * uf);
+      for (int a = 0; a < D; ++a) uf += ld(b.F + (size_t)fo_u(NS, a) * nsl, t) * p.F[a];
+      work = (double)(ld(b.F + (size_t)fo_rho(j) * nsl, t) * uf);
     }
-    if (k == KIND_INLET) {
-      inlet_node<real, D, NS>(p, b, cur, node, j);
-    } else {
-      const int src = k == KIND_OUTLET ? node - node % p.nx + p.nx - 3 : node;
-      collide_node<real, D, NS>(p, b, cur, node, src, j);
-    }
+    if (b.kind[node] == KIND_INLET) inlet_node<real, D, NS>(p, b, cur, t, node, j);
+    else collide_node<FAST, real, D, NS>(p, b, cur, wtab, t, collision_source(p, b, node, t), j);
   }
   const double s = block_sum(work);
-  if (threadIdx.x == 0 && s != 0.0) b.acc_work[lb] += s;
+  if (threadIdx.x == 0 && s != 0.0) b.acc_work[lb + (FAST ? 0 : p.slot_off_gas * NS)] += s;
 }
 
 // ===========================================================================
@@ -879,9 +900,9 @@ __global__ void __launch_bounds__(BLOCK) k_solid(Params<real> p, Bufs<real> b, i
 }
 
 // ===========================================================================
-// k_observe: FP64 partial sums per block over all nodes.  Slots per block:
-// [0, NS) species mass; then e_gas, e_solid, T_min, T_max, u_max, rho_min,
-// Ts_min, Ts_max, bad.
+// k_observe: FP64 partial sums per block.  Slots per block: [0, NS) species
+// mass; then e_gas, e_solid, T_min, T_max, u_max, rho_min, Ts_min, Ts_max,
+// bad.  Gas and wall populations are read per slot, the solid per node.
 // ===========================================================================
 template <typename real, int D, int NS>
 __global__ void __launch_bounds__(BLOCK) k_observe(Params<real> p, Bufs<real> b, int cur) {
@@ -897,8 +918,9 @@ __global__ void __launch_bounds__(BLOCK) k_observe(Params<real> p, Bufs<real> b,
   acc[S_TMIN] = acc[S_RMIN] = acc[S_TSMIN] = 1e300;
   acc[S_TMAX] = acc[S_TSMAX] = -1e300;
   const real *G = b.G[cur];
-  const int n = p.n;
-  for (int node = blockIdx.x * BLOCK + threadIdx.x; node < n; node += gridDim.x * BLOCK) {
+  const int n = p.n, nsl = p.nsl;
+  const int gid = blockIdx.x * BLOCK + threadIdx.x, stride = gridDim.x * BLOCK;
+  for (int node = gid; node < n; node += stride) {
     const uint8_t k = b.kind[node];
     if (k == KIND_SOLID || k == KIND_WALL) {
       const double ts = (double)b.Ts[cur][node];
@@ -907,16 +929,18 @@ __global__ void __launch_bounds__(BLOCK) k_observe(Params<real> p, Bufs<real> b,
       acc[S_TSMAX] = fmax(acc[S_TSMAX], ts);
       if (!(ts > 0.0) || !isfinite(ts)) acc[S_BAD] = 1.0;
     }
-    if (!(gaslike(k) || k == KIND_WALL)) continue;
-    const uint32_t em = b.emask[node];
+  }
+  for (int s = gid; s < p.n_gas + p.n_wall; s += stride) {
+    const bool gas = s < p.n_gas;
+    const uint32_t em = gas ? ~0u : b.wem[s - p.n_gas];
     double E = 0, rhot = 0, C = 0, J[3] = {0, 0, 0};
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
       double rj = 0, Ej = 0, Jj[3] = {0, 0, 0};
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
-        if (k == KIND_WALL && !(em & (1u << i))) continue;
-        const double gv = (double)G[(size_t)(j * Q + i) * n + node];
+        if (!(em & (1u << i))) continue;
+        const double gv = (double)G[(size_t)(j * Q + i) * nsl + s];
         if (!isfinite(gv)) acc[S_BAD] = 1.0;
         rj += gv;
         Ej += (double)cnorm2<D>(i) * gv;
@@ -927,14 +951,14 @@ __global__ void __launch_bounds__(BLOCK) k_observe(Params<real> p, Bufs<real> b,
       E += (double)p.cj2[j] * Ej;
 #pragma unroll
       for (int a = 0; a < 3; ++a) J[a] += (double)p.cj[j] * Jj[a];
-      if (gaslike(k)) {
+      if (gas) {
         rhot += rj;
         C += rj / (double)p.M[j];
         acc[S_RMIN] = fmin(acc[S_RMIN], rj);
       }
     }
     acc[S_EG] += 0.5 * E;
-    if (gaslike(k)) {
+    if (gas) {
       const double u2 = (J[0] * J[0] + J[1] * J[1] + J[2] * J[2]) / (rhot * rhot);
       const double T = (E - rhot * u2) / (D * C);
       acc[S_TMIN] = fmin(acc[S_TMIN], T);
@@ -982,26 +1006,26 @@ inline hipError_t step_impl(const Params<real> &p, const Bufs<real> &b, int cur,
       li.recorded[k] = true;
     }
   };
+  const dim3 blk(BLOCK);
   mark(K_WALL_ID, 0);
-  if (gwf > 0) hipLaunchKernelGGL((k_wall<true, real, D, NS>), dim3(xcd_grid(gwf)), dim3(BLOCK), 0, st, p, b, cur);
-  if (gws > 0) hipLaunchKernelGGL((k_wall<false, real, D, NS>), dim3(xcd_grid(gws)), dim3(BLOCK), 0, st, p, b, cur);
+  if (gwf > 0) hipLaunchKernelGGL((k_wall<true, real, D, NS>), dim3(xcd_grid(gwf)), blk, 0, st, p, b, cur);
+  if (gws > 0) hipLaunchKernelGGL((k_wall<false, real, D, NS>), dim3(xcd_grid(gws)), blk, 0, st, p, b, cur);
   mark(K_WALL_ID, 1);
   mark(K_MOMENTS_ID, 0);
-  constexpr int QM = lat_q<D>() - 1;
-  if (ggf > 0) hipLaunchKernelGGL((k_stream<true, real, D, NS>), dim3(xcd_grid(ggf * QM)), dim3(BLOCK), 0, st, p, b, cur);
-  if (ggs > 0) hipLaunchKernelGGL((k_stream<false, real, D, NS>), dim3(xcd_grid(ggs * QM)), dim3(BLOCK), 0, st, p, b, cur);
-  if (gg > 0) hipLaunchKernelGGL((k_moments<real, D, NS>), dim3(xcd_grid(gg)), dim3(BLOCK), 0, st, p, b, cur);
+  if (ggf > 0) hipLaunchKernelGGL((k_moments<true, real, D, NS>), dim3(xcd_grid(ggf)), blk, 0, st, p, b, cur);
+  if (ggs > 0) hipLaunchKernelGGL((k_moments<false, real, D, NS>), dim3(xcd_grid(ggs)), blk, 0, st, p, b, cur);
   mark(K_MOMENTS_ID, 1);
   mark(K_ESUM_ID, 0);
-  if (gg > 0) hipLaunchKernelGGL((k_esum<real, D, NS>), dim3(xcd_grid(gg)), dim3(BLOCK), 0, st, p, b, cur);
+  if (gg > 0) hipLaunchKernelGGL((k_esum<real, D, NS>), dim3(xcd_grid(gg)), blk, 0, st, p, b, cur);
   mark(K_ESUM_ID, 1);
   mark(K_COLLIDE_ID, 0);
-  if (gg > 0) hipLaunchKernelGGL((k_collide<real, D, NS>), dim3(xcd_grid(gg * NS)), dim3(BLOCK), 0, st, p, b, cur);
+  if (ggf > 0) hipLaunchKernelGGL((k_collide<true, real, D, NS>), dim3(xcd_grid(ggf * NS)), blk, 0, st, p, b, cur);
+  if (ggs > 0) hipLaunchKernelGGL((k_collide<false, real, D, NS>), dim3(xcd_grid(ggs * NS)), blk, 0, st, p, b, cur);
   mark(K_COLLIDE_ID, 1);
   if (li.n_solid > 0) {
     const int tiles = solid_tiles<D>(p.nx, p.ny, p.nz);
     mark(K_SOLID_ID, 0);
-    hipLaunchKernelGGL((k_solid<real, D>), dim3(tiles), dim3(BLOCK), 0, st, p, b, cur);
+    hipLaunchKernelGGL((k_solid<real, D>), dim3(tiles), blk, 0, st, p, b, cur);
     mark(K_SOLID_ID, 1);
   }
   return hipGetLastError();

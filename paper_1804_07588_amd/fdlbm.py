@@ -23,7 +23,7 @@ CORR_DIFFUSION, CORR_VISCOUS, CORR_ENERGY, CORR_PRANDTL, CORR_ALL = 1, 2, 4, 8, 
 WALL_REACTIVE, WALL_ISOTHERMAL = 0, 1
 FIELD_RHO, FIELD_U, FIELD_T, FIELD_TS, FIELD_POP, FIELD_KIND, FIELD_WALL_R, FIELD_WALL_DE = range(8)
 K_WALL, K_MOMENTS, K_COLLIDE, K_SOLID, K_ESUM = range(5)
-KERNEL_NAMES = ["k_wall", "k_stream+k_moments", "k_collide", "k_solid", "k_esum"]
+KERNEL_NAMES = ["k_wall", "k_moments", "k_collide", "k_solid", "k_esum"]
 MAX_SPECIES = 8
 
 EXPORTS = ["fdlbm_create", "fdlbm_destroy", "fdlbm_last_error", "fdlbm_set_geometry",
