@@ -139,7 +139,6 @@ def main():
         "k_moments": n_gas * Q * ns * b,       # pre-collision pops in
         "k_wall": n_links * 2 * ns * b,        # link pops in, emitted pops out
         "k_solid": n_solid * 2 * b,            # solid temperature in and out
-        "k_esum": 0,                           # node fields only: no algorithmic bytes
     }
 
     sim.step(args.warmup)

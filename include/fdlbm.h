@@ -30,7 +30,8 @@
  * Thread-compatible: one context per host thread.
  *
  * Layouts: node index = x + nx*(y + ny*z).  Host arrays are per node; the
- * workspace stores populations and moments per slot (gas nodes, then wall
+ * workspace stores populations per (direction, slot) as records of all
+ * species and moments as per-slot records (slots: gas nodes, then wall
  * nodes), and fdlbm_get_field returns populations of species j, direction i
  * at [i*n + node] (structure of arrays, zero where a node stores none).  Direction
  * order: D2Q9 as Eq.(2) (rest, +x, +y, -x, -y, (1,1), (-1,1), (-1,-1), (1,-1));
@@ -206,8 +207,7 @@ int fdlbm_load_state(fdlbm_ctx *ctx, const void *host_buf, size_t bytes);
 #define FDLBM_K_MOMENTS 1  /* streaming + moments + transport                */
 #define FDLBM_K_COLLIDE 2  /* streaming + sources + collision + inlet/outlet */
 #define FDLBM_K_SOLID 3    /* solid heat step                                */
-#define FDLBM_K_ESUM 4     /* temperature of f and of the auxiliary state    */
-#define FDLBM_K_COUNT 5
+#define FDLBM_K_COUNT 4
 int fdlbm_set_profiling(fdlbm_ctx *ctx, int enable);
 int fdlbm_kernel_times(fdlbm_ctx *ctx, double *avg_ms, int64_t *launches);
 

@@ -55,7 +55,7 @@ struct fdlbm_ctx {
   // workspace
   char *ws = nullptr;
   size_t ws_bytes = 0;
-  size_t off_G[2]{}, off_F = 0, off_Ts[2]{}, off_wr = 0, off_wde = 0, off_kind = 0, off_slot = 0,
+  size_t off_G[2]{}, off_FR = 0, off_FX = 0, off_Ts[2]{}, off_wr = 0, off_wde = 0, off_kind = 0, off_slot = 0,
          off_scls = 0, off_wem = 0, off_gl = 0, off_wl = 0, off_am = 0, off_aw = 0, off_ab = 0,
          off_part = 0;
   size_t total = 0;
@@ -108,7 +108,8 @@ static void layout(fdlbm_ctx *c) {
   const size_t pops = (size_t)c->ns * c->Q * nsl * b;
   c->off_G[0] = take(pops);
   c->off_G[1] = take(pops);
-  c->off_F = take((size_t)n_fields(c->D, c->ns) * nsl * b);
+  c->off_FR = take((size_t)fr_count(c->D, c->ns) * nsl * b);
+  c->off_FX = take((size_t)fx_count(c->D, c->ns) * nsl * b);
   c->off_Ts[0] = take(n * b);
   c->off_Ts[1] = take(n * b);
   c->off_wr = take(n * b);
@@ -137,7 +138,8 @@ static Bufs<real> bufs(const fdlbm_ctx *c) {
   char *w = c->ws;
   b.G[0] = (real *)(w + c->off_G[0]);
   b.G[1] = (real *)(w + c->off_G[1]);
-  b.F = (real *)(w + c->off_F);
+  b.FR = (real *)(w + c->off_FR);
+  b.FX = (real *)(w + c->off_FX);
   b.Ts[0] = (real *)(w + c->off_Ts[0]);
   b.Ts[1] = (real *)(w + c->off_Ts[1]);
   b.wall_r = (real *)(w + c->off_wr);
@@ -599,7 +601,7 @@ static int init_impl(fdlbm_ctx *c, const double *rho, const double *u, const dou
       const real sq = (real)std::sqrt(c->M[j]);
       if (c->D == 2) equilibrium<real, 2>((real)rho[j * n + node], sq, uu, (real)T[node], f);
       else equilibrium<real, 3>((real)rho[j * n + node], sq, uu, (real)T[node], f);
-      for (int i = 0; i < Q; ++i) G[((size_t)j * Q + i) * nsl + slot] = f[i];
+      for (int i = 0; i < Q; ++i) G[((size_t)i * nsl + slot) * ns + j] = f[i];
     }
   }
   for (size_t node = 0; node < n; ++node) {
@@ -621,7 +623,7 @@ static int init_impl(fdlbm_ctx *c, const double *rho, const double *u, const dou
       }
       const real rw = (real)(sum / cnt);
       for (int i = 1; i < Q; ++i)
-        if ((c->emask[node] >> i) & 1u) G[((size_t)j * Q + i) * nsl + c->slot_of[node]] = rw * wt[i];
+        if ((c->emask[node] >> i) & 1u) G[((size_t)i * nsl + c->slot_of[node]) * ns + j] = rw * wt[i];
     }
   }
   c->cur = 0;
@@ -784,26 +786,27 @@ int fdlbm_get_field(fdlbm_ctx *c, int field, int comp, double *dst) {
     case FDLBM_FIELD_U:
     case FDLBM_FIELD_T: {
       if (c->step == 0) return set_err(c, FDLBM_E_STATE, "moments exist after the first step");
-      size_t k;
+      int k;
       if (field == FDLBM_FIELD_RHO) {
         if (comp < 0 || comp >= c->ns) return set_err(c, FDLBM_E_INVALID, "bad species");
-        k = (size_t)fo_rho(comp);
+        k = fr_rho(c->D, comp);
       } else if (field == FDLBM_FIELD_U) {
         if (comp < 0 || comp > 2) return set_err(c, FDLBM_E_INVALID, "bad axis");
         if (comp >= c->D) {
           std::fill(dst, dst + n, 0.0);
           return FDLBM_OK;
         }
-        k = (size_t)fo_u(c->ns, comp);
+        k = fr_u(comp);
       } else {
-        k = (size_t)(3 * c->ns + c->D);
+        k = fr_T(c->D);
       }
-      std::vector<double> v(c->nsl);
-      rc = f64 ? copy_field<double>(c, c->off_F + k * c->nsl * b, c->nsl, v.data())
-               : copy_field<float>(c, c->off_F + k * c->nsl * b, c->nsl, v.data());
+      const size_t NR = (size_t)fr_count(c->D, c->ns);
+      std::vector<double> v((size_t)c->nsl * NR);
+      rc = f64 ? copy_field<double>(c, c->off_FR, v.size(), v.data())
+               : copy_field<float>(c, c->off_FR, v.size(), v.data());
       if (rc) return rc;
       for (size_t x = 0; x < n; ++x)
-        dst[x] = (gaslike(c->kind[x]) || c->kind[x] == KIND_WALL) ? v[c->slot_of[x]] : 0.0;
+        dst[x] = (gaslike(c->kind[x]) || c->kind[x] == KIND_WALL) ? v[(size_t)c->slot_of[x] * NR + k] : 0.0;
       return FDLBM_OK;
     }
     case FDLBM_FIELD_TS:
@@ -815,14 +818,15 @@ int fdlbm_get_field(fdlbm_ctx *c, int field, int comp, double *dst) {
     case FDLBM_FIELD_POP: {
       if (comp < 0 || comp >= c->ns) return set_err(c, FDLBM_E_INVALID, "bad species");
       const size_t nsl = (size_t)c->nsl, null_slot = c->gas_list.size() + c->wall_list.size();
-      std::vector<double> v((size_t)c->Q * nsl);
-      const size_t off = c->off_G[c->cur] + (size_t)comp * c->Q * nsl * b;
-      rc = f64 ? copy_field<double>(c, off, v.size(), v.data()) : copy_field<float>(c, off, v.size(), v.data());
+      const size_t ns = (size_t)c->ns;
+      std::vector<double> v((size_t)c->Q * nsl * ns);
+      rc = f64 ? copy_field<double>(c, c->off_G[c->cur], v.size(), v.data())
+               : copy_field<float>(c, c->off_G[c->cur], v.size(), v.data());
       if (rc) return rc;
       for (int i = 0; i < c->Q; ++i)
         for (size_t x = 0; x < n; ++x) {
           const size_t sl = (size_t)c->slot_of[x];
-          dst[(size_t)i * n + x] = sl == null_slot ? 0.0 : v[i * nsl + sl];
+          dst[(size_t)i * n + x] = sl == null_slot ? 0.0 : v[((size_t)i * nsl + sl) * ns + comp];
         }
       return FDLBM_OK;
     }

@@ -107,13 +107,16 @@ struct Params {
 };
 
 // Workspace pointers.  Populations and moments live in compact SLOT order:
-// gas-like nodes in gas-list order (slot = list index), then the wall nodes
-// (slot = n_gas + wall index), then one null slot that no valid tap reads;
-// slot_of maps a node to its slot (the null slot for interior solid nodes).
+// gas-like nodes in processing order (slot = gas-list index), then the wall
+// nodes (slot = n_gas + wall index), then one null slot that no valid tap
+// reads; slot_of maps a node to its slot (the null slot for interior solid).
+// Populations are records of the NS species per (direction, slot), so one
+// tap is one contiguous NS-value load for every species.
 template <typename real>
 struct Bufs {
-  real *G[2];         // populations [(j*Q + i)*nsl + slot], double-buffered
-  real *F;            // per-step moments [field*nsl + slot] (offsets below)
+  real *G[2];         // populations [((i*nsl + slot)*NS + j], double-buffered
+  real *FR;           // per-slot record read by neighbours: u, T, rho_j, tau1_j
+  real *FX;           // per-slot record of the node itself: tau2_j, u_j, U^c, energy defect
   real *Ts[2];        // solid temperature per node, double-buffered
   real *wall_r;       // molar rate per node (wall nodes) of the last step
   real *wall_dE;      // kinetic energy the wall gave the gas, per node, last step
@@ -129,39 +132,19 @@ struct Bufs {
   double *partials;   // observe reduction partials
 };
 
-// Moments field offsets inside F (units of nsl): rho_j, tau1_j, tau2_j, u_a,
-// T, then the species velocities of f u_ja, the diffusion-velocity
-// correction U^c_a and the quasi-equilibrium energy defect sum_j rho_j |u_j - u|^2
-__host__ __device__ inline int fo_rho(int j) { return j; }
-__host__ __device__ inline int fo_tau1(int ns, int j) { return ns + j; }
-__host__ __device__ inline int fo_tau2(int ns, int j) { return 2 * ns + j; }
-__host__ __device__ inline int fo_u(int ns, int a) { return 3 * ns + a; }
-template <int D>
-__host__ __device__ inline int fo_T(int ns) {
-  return 3 * ns + D;
-}
-template <int D>
-__host__ __device__ inline int fo_uj(int ns, int j, int a) {
-  return 3 * ns + D + 1 + j * D + a;
-}
-template <int D>
-__host__ __device__ inline int fo_Uc(int ns, int a) {
-  return 3 * ns + D + 1 + ns * D + a;
-}
-template <int D>
-__host__ __device__ inline int fo_ediff(int ns) {
-  return 3 * ns + D + 1 + ns * D + D;
-}
-// temperature of f (with the energy of the sources) and of the auxiliary state
-template <int D>
-__host__ __device__ inline int fo_Tf(int ns) {
-  return 3 * ns + D + 1 + ns * D + D + 1;
-}
-template <int D>
-__host__ __device__ inline int fo_Tst(int ns) {
-  return 3 * ns + D + 1 + ns * D + D + 2;
-}
-__host__ __device__ inline int n_fields(int D, int ns) { return 3 * ns + D + 1 + ns * D + D + 3; }
+// Field records per slot.  FR (what the face neighbours' gradient stencils
+// read): u_a, T, rho_j, tau1_j.  FX (read by the node itself): tau2_j, the
+// species velocities u_ja of f, U^c_a, and sum_j rho_j |u_j - u|^2.
+__host__ __device__ constexpr int fr_u(int a) { return a; }
+__host__ __device__ constexpr int fr_T(int D) { return D; }
+__host__ __device__ constexpr int fr_rho(int D, int j) { return D + 1 + j; }
+__host__ __device__ constexpr int fr_tau1(int D, int ns, int j) { return D + 1 + ns + j; }
+__host__ __device__ constexpr int fr_count(int D, int ns) { return D + 1 + 2 * ns; }
+__host__ __device__ constexpr int fx_tau2(int j) { return j; }
+__host__ __device__ constexpr int fx_uj(int D, int ns, int j, int a) { return ns + j * D + a; }
+__host__ __device__ constexpr int fx_Uc(int D, int ns, int a) { return ns + ns * D + a; }
+__host__ __device__ constexpr int fx_ediff(int D, int ns) { return ns + ns * D + D; }
+__host__ __device__ constexpr int fx_count(int D, int ns) { return ns + ns * D + D + 1; }
 
 enum : uint8_t { KIND_GAS = 0, KIND_SOLID = 1, KIND_WALL = 2, KIND_INLET = 3, KIND_OUTLET = 4 };
 __host__ __device__ inline bool gaslike(uint8_t k) { return k == KIND_GAS || k >= KIND_INLET; }

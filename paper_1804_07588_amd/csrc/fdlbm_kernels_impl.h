@@ -7,22 +7,21 @@
 //   k_moments  streaming into every gas node (Eq.(33)-(36)), evaluated on the
 //              fly, and everything local: moments, transport, U^c, species
 //              momenta of f (Eq.(3), (5), (7)-(8), (11), (14)-(17), (25))
-//   k_esum     temperature of f and of the auxiliary state from the energy
-//              moments of all species' sources
-//   k_collide  streaming again, correction sources from the node's and its
-//              face neighbours' moments, equilibria and the trapezoidal
+//   k_collide  streaming again, correction sources of all species from the
+//              node's and its face neighbours' moments, the temperatures of f
+//              and of the auxiliary state, equilibria and the trapezoidal
 //              collision (Eq.(4), (6), (12)-(13), (19)-(21), (24)); writes the
 //              inlet/outlet planes directly
 //   k_solid    forward-Euler heat step in the solid on an LDS tile with the
 //              wall-node interface source (Eq.(45)-(48))
 //
-// Populations and moments are stored per SLOT (gas nodes in list order, then
-// wall nodes), structure of arrays [(j*Q + i)*nsl + slot]: a wavefront of
-// consecutive gas slots reads and writes 64 consecutive values per (species,
-// direction) with no solid node in between.  The streamed populations are
-// never stored: the moments kernel and the collision kernel each rebuild them
-// from the taps, so a step reads the population array twice and writes it
-// once.
+// Storage is per SLOT (gas nodes in processing order, then wall nodes).
+// Populations are records of the NS species per (direction, slot),
+// [((i*nsl + slot)*NS + j]: a tap of one direction is one contiguous record
+// load that serves every species, and a wavefront of consecutive slots reads
+// consecutive records.  The streamed populations are never stored: the moments
+// and the collision kernel each rebuild them from the taps, so a step reads
+// the population array twice and writes it once.
 #pragma once
 #include <type_traits>
 
@@ -135,17 +134,37 @@ __device__ inline void st(T *__restrict__ base, int idx, T v) {
   *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + off) = v;
 }
 
-// Slots of the three taps of direction i for stencil class cls around the
-// node of ad, Eq.(33)-(36).  No branch: class 7 (not a destination) reads
-// the node itself like class 6 and the caller discards the value, so every
-// load of a direction can be issued together.
+// N consecutive values: record `rec` of an array of N-value records, moved as
+// one contiguous access per lane (the compiler splits it into the widest
+// loads and stores the element alignment allows)
+template <typename real, int N>
+struct Rec {
+  real v[N];
+};
+template <typename real, int N>
+__device__ inline Rec<real, N> ldrec(const real *__restrict__ base, int rec) {
+  const uint32_t off = uint32_t(rec) * uint32_t(N * sizeof(real));
+  const real *p = reinterpret_cast<const real *>(reinterpret_cast<const char *>(base) + off);
+  Rec<real, N> r;
+  __builtin_memcpy(&r, p, sizeof r);
+  return r;
+}
+template <typename real, int N>
+__device__ inline void strec(real *__restrict__ base, int rec, const Rec<real, N> &r) {
+  const uint32_t off = uint32_t(rec) * uint32_t(N * sizeof(real));
+  real *p = reinterpret_cast<real *>(reinterpret_cast<char *>(base) + off);
+  __builtin_memcpy(p, &r, sizeof r);
+}
+
+// Slots of the three taps of direction i for stencil class cls (0..6) around
+// the node of ad, Eq.(33)-(36).
 struct TapSlots {
   int s[3];
 };
 template <bool FAST, typename real, int D>
 __device__ inline TapSlots tap_slots(const Bufs<real> &b, const Addr<D> &ad, int i, int cls) {
   constexpr uint64_t OFF = pack_offsets();
-  const int sh = 9 * (cls < 7 ? cls : 6);
+  const int sh = 9 * cls;
   TapSlots t;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -155,13 +174,21 @@ __device__ inline TapSlots tap_slots(const Bufs<real> &b, const Addr<D> &ad, int
   return t;
 }
 
-// Pre-collision population of one species from its direction-i array Gji:
-// the interpolant through the class's taps at the species' shift.  An
-// on-lattice species (c_j = 1) has weights that are exactly one 1 and two 0s,
-// so the same expression returns the upstream value unrounded.
-template <typename real>
-__device__ inline real interp(const real *__restrict__ Gji, const TapSlots &t, const real *w) {
-  return w[0] * ld(Gji, t.s[0]) + w[1] * ld(Gji, t.s[1]) + w[2] * ld(Gji, t.s[2]);
+// Pre-collision populations of all NS species in direction i (array Gi, the
+// records of direction i): the interpolant through the class's taps at each
+// species' shift.  An on-lattice species (c_j = 1) has weights exactly one 1
+// and two 0s, so it gets the upstream value unrounded.
+template <typename real, int NS>
+__device__ inline Rec<real, NS> stream_rec(const real *__restrict__ Gi, const TapSlots &t,
+                                           const WTab<real> &wt, int cls) {
+  const Rec<real, NS> r0 = ldrec<real, NS>(Gi, t.s[0]);
+  const Rec<real, NS> r1 = ldrec<real, NS>(Gi, t.s[1]);
+  const Rec<real, NS> r2 = ldrec<real, NS>(Gi, t.s[2]);
+  Rec<real, NS> g;
+#pragma unroll
+  for (int j = 0; j < NS; ++j)
+    g.v[j] = wt.w[j][cls][0] * r0.v[j] + wt.w[j][cls][1] * r1.v[j] + wt.w[j][cls][2] * r2.v[j];
+  return g;
 }
 
 // compile-time loop: f(std::integral_constant<int, I>) for I in [B, E)
@@ -208,6 +235,7 @@ template <bool FAST, typename real, int D, int NS>
 __device__ inline double wall_node(const Params<real> &p, const Bufs<real> &b, int cur,
                                    const WTab<real> &wtab, const int wi) {
   constexpr int Q = lat_q<D>();
+  constexpr int NR = fr_count(D, NS);
   const int slot = p.n_gas + wi;
   const int w = (int)b.wall_list[wi];
   const Addr<D> ad(w, p);
@@ -233,12 +261,12 @@ __device__ inline double wall_node(const Params<real> &p, const Bufs<real> &b, i
   for (int i = 1; i < Q; ++i) {
     const int cls = cls_at(cw, i);
     if (cls == CLS_NONE) continue;  // direction i does not arrive from the gas
-    const TapSlots ts = tap_slots<FAST, real, D>(b, ad, i, cls);
+    const Rec<real, NS> g = stream_rec<real, NS>(G + (size_t)i * nsl * NS,
+                                                 tap_slots<FAST, real, D>(b, ad, i, cls), wtab, cls);
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
-      const real g = interp(G + (size_t)(j * Q + i) * nsl, ts, wtab.w[j][cls]);
-      A[j] += g;
-      Ej[j] += real(cnorm2<D>(i)) * g;
+      A[j] += g.v[j];
+      Ej[j] += real(cnorm2<D>(i)) * g.v[j];
     }
   }
   real Ein = 0;
@@ -274,25 +302,35 @@ __device__ inline double wall_node(const Params<real> &p, const Bufs<real> &b, i
   real r = keff;
 #pragma unroll
   for (int m = 0; m < NS; ++m) r *= ipow(rw[m] * p.invM[m], p.order[m]);
-  real Eout = 0;
   const real invZ = real(1) / Z;
 #pragma unroll
-  for (int j = 0; j < NS; ++j) {
-    rw[j] = (A[j] + p.nu[j] * p.M[j] * r) * invZ;
-    real Eo = 0;
+  for (int j = 0; j < NS; ++j) rw[j] = (A[j] + p.nu[j] * p.M[j] * r) * invZ;
+  // emission: rho_w,j f^eq_i(1, 0, T_w) on the links into the gas
+  real Eout = 0;
 #pragma unroll
-    for (int i = 1; i < Q; ++i) {
-      if (!(em & (1u << i))) continue;
-      const real W = rw[j] * wt[i];
-      st(Gn + (size_t)(j * Q + i) * nsl, slot, W);
-      Eo += real(cnorm2<D>(i)) * W;
+  for (int i = 1; i < Q; ++i) {
+    if (!(em & (1u << i))) continue;
+    Rec<real, NS> W;
+    real Ei = 0;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      W.v[j] = rw[j] * wt[i];
+      Ei += p.cj2[j] * W.v[j];
     }
-    Eout += p.cj2[j] * Eo;
-    st(b.F + (size_t)fo_rho(j) * nsl, slot, rw[j]);
+    strec<real, NS>(Gn + (size_t)i * nsl * NS, slot, W);
+    Eout += real(cnorm2<D>(i)) * Ei;
   }
+  // wall state seen by the neighbours' gradient stencils
+  Rec<real, NR> fr;
 #pragma unroll
-  for (int a = 0; a < D; ++a) st(b.F + (size_t)fo_u(NS, a) * nsl, slot, real(0));
-  st(b.F + (size_t)fo_T<D>(NS) * nsl, slot, Tw);
+  for (int a = 0; a < D; ++a) fr.v[fr_u(a)] = real(0);
+  fr.v[fr_T(D)] = Tw;
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    fr.v[fr_rho(D, j)] = rw[j];
+    fr.v[fr_tau1(D, NS, j)] = real(0);
+  }
+  strec<real, NR>(b.FR, slot, fr);
   b.wall_r[w] = r;
   b.wall_dE[w] = real(0.5) * (Eout - Ein);
   return (double)r;
@@ -316,12 +354,12 @@ __global__ void __launch_bounds__(BLOCK) k_wall(Params<real> p, Bufs<real> b, in
 // ===========================================================================
 // k_moments: streaming into every gas node (evaluated, not stored), the
 // moments of the streamed populations and every local quantity of the node
-// (Eq.(3), (5), (7)-(8), (11), (14)-(17), (25)), one thread per node.  The
-// taps of a direction are the same slots for every species.
+// (Eq.(3), (5), (7)-(8), (11), (14)-(17), (25)), one thread per node.
 // ===========================================================================
 template <bool FAST, typename real, int D, int NS>
 __global__ void __launch_bounds__(BLOCK) k_moments(Params<real> p, Bufs<real> b, int cur) {
   constexpr int Q = lat_q<D>();
+  constexpr int NR = fr_count(D, NS), NX = fx_count(D, NS);
   __shared__ WTab<real> wtab;
   load_wtab<real, NS>(p, wtab);
   const int first = FAST ? 0 : p.n_gas_fast, count = FAST ? p.n_gas_fast : p.n_gas - p.n_gas_fast;
@@ -334,28 +372,30 @@ __global__ void __launch_bounds__(BLOCK) k_moments(Params<real> p, Bufs<real> b,
   const Addr<D> ad(node, p);
   const uint64_t cw = b.scls[t];
   const real *__restrict__ G = b.G[cur];
-  real *__restrict__ F = b.F;
   const int nsl = p.nsl;
   real rho[NS], Jg[NS][D], Es[NS];
+  {
+    const Rec<real, NS> g0 = ldrec<real, NS>(G, t);  // rest population: not streamed
 #pragma unroll
-  for (int j = 0; j < NS; ++j) {
-    rho[j] = ld(G + (size_t)(j * Q) * nsl, t);  // rest population: not streamed
-    Es[j] = 0;
+    for (int j = 0; j < NS; ++j) {
+      rho[j] = g0.v[j];
+      Es[j] = 0;
 #pragma unroll
-    for (int a = 0; a < D; ++a) Jg[j][a] = 0;
+      for (int a = 0; a < D; ++a) Jg[j][a] = 0;
+    }
   }
   static_for<1, Q>([&](auto ic_) __attribute__((always_inline)) {
     constexpr int i = decltype(ic_)::value;
     const int cls = cls_at(cw, i);
-    const TapSlots ts = tap_slots<FAST, real, D>(b, ad, i, cls);
+    const Rec<real, NS> g =
+        stream_rec<real, NS>(G + (size_t)i * nsl * NS, tap_slots<FAST, real, D>(b, ad, i, cls), wtab, cls);
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
-      const real g = interp(G + (size_t)(j * Q + i) * nsl, ts, wtab.w[j][cls]);
-      rho[j] += g;
+      rho[j] += g.v[j];
 #pragma unroll
       for (int a = 0; a < D; ++a)
-        if (cvec<D>(i, a) != 0) Jg[j][a] += cvec<D>(i, a) > 0 ? g : -g;
-      Es[j] += real(cnorm2<D>(i)) * g;
+        if (cvec<D>(i, a) != 0) Jg[j][a] += cvec<D>(i, a) > 0 ? g.v[j] : -g.v[j];
+      Es[j] += real(cnorm2<D>(i)) * g.v[j];
     }
   });
   real E = 0;
@@ -398,6 +438,8 @@ __global__ void __launch_bounds__(BLOCK) k_moments(Params<real> p, Bufs<real> b,
   const real lT = log(T / p.T_ref);
   const real fmu = p.mu_T_exp == real(0) ? real(1) : exp(p.mu_T_exp * lT);
   const real CT = C * T;
+  Rec<real, NR> fr;
+  Rec<real, NX> fx;
   real tau2[NS];
 #pragma unroll
   for (int j = 0; j < NS; ++j) {
@@ -405,8 +447,8 @@ __global__ void __launch_bounds__(BLOCK) k_moments(Params<real> p, Bufs<real> b,
 #pragma unroll
     for (int k = 0; k < NS; ++k) den += Xh[k] * p.wilke[j][k];
     const real tau1 = p.mu0[j] * fmu / (CT * den);  // Eq.(17)
-    st(F + (size_t)fo_tau1(NS, j) * nsl, t, tau1);
-    st(F + (size_t)fo_rho(j) * nsl, t, rho[j]);
+    fr.v[fr_tau1(D, NS, j)] = tau1;
+    fr.v[fr_rho(D, j)] = rho[j];
     tau2[j] = tau1;
   }
   if (NS > 1) {
@@ -422,10 +464,10 @@ __global__ void __launch_bounds__(BLOCK) k_moments(Params<real> p, Bufs<real> b,
     }
   }
 #pragma unroll
-  for (int j = 0; j < NS; ++j) st(F + (size_t)fo_tau2(NS, j) * nsl, t, tau2[j]);
+  for (int j = 0; j < NS; ++j) fx.v[fx_tau2(j)] = tau2[j];
 #pragma unroll
-  for (int a = 0; a < D; ++a) st(F + (size_t)fo_u(NS, a) * nsl, t, u[a]);
-  st(F + (size_t)fo_T<D>(NS) * nsl, t, T);
+  for (int a = 0; a < D; ++a) fr.v[fr_u(a)] = u[a];
+  fr.v[fr_T(D)] = T;
   // Eq.(25) with Eq.(11): species momenta of f and U^c in closed form
   const bool cdiff = (p.flags & 1u) && NS > 1;
   real ediff = 0;
@@ -440,29 +482,31 @@ __global__ void __launch_bounds__(BLOCK) k_moments(Params<real> p, Bufs<real> b,
       den += ah[j] * rho[j] / (real(1) + ah[j]);
     }
     const real Uc = cdiff ? num / den : real(0);
-    st(F + (size_t)fo_Uc<D>(NS, a) * nsl, t, Uc);
+    fx.v[fx_Uc(D, NS, a)] = Uc;
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
       const real Jf = K[j] + ah[j] * rho[j] * Uc / (real(1) + ah[j]);
       const real uja = rho[j] > tiny<real>() ? Jf / rho[j] : u[a];
-      st(F + (size_t)fo_uj<D>(NS, j, a) * nsl, t, uja);
+      fx.v[fx_uj(D, NS, j, a)] = uja;
       ediff += rho[j] * (uja - u[a]) * (uja - u[a]);
     }
   }
-  st(F + (size_t)fo_ediff<D>(NS) * nsl, t, ediff);
+  fx.v[fx_ediff(D, NS)] = ediff;
+  strec<real, NR>(b.FR, t, fr);
+  strec<real, NX>(b.FX, t, fx);
 }
 
 // ===========================================================================
-// shared pieces of the source terms
+// k_collide: streaming, sources, temperatures, equilibria and Eq.(24)
 // ===========================================================================
-template <typename real, int D>
+// lattice-minus-Maxwellian third moment Q'_aaa of the equilibria
+template <typename real>
 __device__ inline real q_dev(real rho, real invM, real ua, real T) {
-  // lattice-minus-Maxwellian third moment Q'_aaa of the equilibria above
   return rho * invM * ua * (real(1) - real(3) * T) - rho * ua * ua * ua;
 }
+// lattice-minus-Maxwellian energy flux R'_ab of the equilibria
 template <typename real, int D>
 __device__ inline real r_dev(real rho, real invM, const real *u, real T, int a, int b) {
-  // lattice-minus-Maxwellian energy flux R'_ab of the equilibria above
   if (a == b) {
     const real ua2 = u[a] * u[a];
     return rho * (T * (real(1) - real(3) * T) * invM * invM + ua2 * (real(1) - real(6) * T) * invM -
@@ -474,74 +518,41 @@ __device__ inline real r_dev(real rho, real invM, const real *u, real T, int a, 
   return rho * u[a] * u[b] * ((real(2) - real(D + 4) * T) * invM - u2);
 }
 
-// face-neighbour values of the gradient stencils shared by all species
-template <typename real, int D>
-struct NbCommon {
-  real u[D], T;
-  int slot;  // slot supplying rho_j and tau1_j (the centre's when missing)
-  bool wall, missing;
-};
-
-// face neighbours of the node srcn (slot ss): slots, classes and the
-// mixture fields (a wall neighbour supplies the wall state)
-template <typename real, int D, int NS>
-__device__ inline void load_neighbours(const Params<real> &p, const Bufs<real> &b, int srcn, int ss,
-                                       NbCommon<real, D> (&nb)[D][2]) {
-  const Addr<D> ad(srcn, p);
-  const int nsl = p.nsl, null_slot = p.n_gas + p.n_wall;
-#pragma unroll
-  for (int a = 0; a < D; ++a)
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      NbCommon<real, D> &v = nb[a][s];
-      const int q = ad.face(p, a, s == 0 ? +1 : -1);
-      const int ql = ld(b.slot_of, q >= 0 ? q : srcn);  // unconditional load
-      const int qs = q >= 0 ? ql : null_slot;
-      v.wall = qs >= p.n_gas && qs < null_slot;
-      v.missing = qs == null_slot || q == srcn;
-      v.slot = v.missing ? ss : qs;
-#pragma unroll
-      for (int c = 0; c < D; ++c) v.u[c] = ld(b.F + (size_t)fo_u(NS, c) * nsl, v.slot);
-      v.T = ld(b.F + (size_t)fo_T<D>(NS) * nsl, v.slot);
-    }
-}
-
-// energy moment of species j's sources: trace of the second-moment source
-// (body force work, viscous correction) plus the Prandtl energy source
-template <typename real, int D, int NS>
-__device__ inline real energy_source(const Params<real> &p, const Bufs<real> &b, int ss, int j,
-                                     const real *u, real Tt, const NbCommon<real, D> (&nb)[D][2]) {
-  const int nsl = p.nsl;
-  const real *F = b.F;
-  const bool cvisc = p.flags & 2u, cpr = (p.flags & 8u) && p.kpr != real(0);
-  const real iM = p.invM[j];
-  const real rj = ld(F + (size_t)fo_rho(j) * nsl, ss);
-  real e = 0;
-#pragma unroll
-  for (int a = 0; a < D; ++a) e += real(2) * rj * u[a] * p.F[a];
-  if (!(cvisc || cpr)) return e;
-  const real tau1x = ld(F + (size_t)fo_tau1(NS, j) * nsl, ss);
-  const real Kx = p.kpr * tau1x * rj * iM * Tt * iM;
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    const NbCommon<real, D> &sp = nb[a][0], &sm = nb[a][1];
-    const real rp = ld(F + (size_t)fo_rho(j) * nsl, sp.slot), rm = ld(F + (size_t)fo_rho(j) * nsl, sm.slot);
-    if (cvisc) {
-      const real qx = q_dev<real, D>(rj, iM, u[a], Tt);
-      const real qp = sp.wall ? -qx : q_dev<real, D>(rp, iM, sp.u[a], sp.T);
-      const real qm = sm.wall ? -qx : q_dev<real, D>(rm, iM, sm.u[a], sm.T);
-      e += real(0.5) * (qp - qm);
-    }
-    if (cpr) {
-      const real tp = ld(F + (size_t)fo_tau1(NS, j) * nsl, sp.slot);
-      const real tm = ld(F + (size_t)fo_tau1(NS, j) * nsl, sm.slot);
-      const real ep = real(0.5) * (Kx + p.kpr * tp * rp * iM * sp.T * iM) * (sp.T - Tt);
-      const real em = real(0.5) * (Kx + p.kpr * tm * rm * iM * sm.T * iM) * (sm.T - Tt);
-      e += (!sp.wall && !sp.missing) ? ep : real(0);
-      e += (!sm.wall && !sm.missing) ? em : real(0);
-    }
+// Equilibrium of Eq.(4)/(6) per unit density from the per-axis factors
+// P0 = 1 - T - U^2, P+- = (T + U^2 +- U)/2 at the scaled velocity U =
+// sqrt(M_j) u: a moving direction i (D2Q9 product; D3Q19 faces
+// P_a (1 - 2T - U_b^2 - U_c^2), edges P_a P_b) ...
+template <typename real, int D, int i>
+__device__ inline real eq_moving(const real *U, real T) {
+  if constexpr (D == 2) {
+    constexpr int cx = cvec<D>(i, 0), cy = cvec<D>(i, 1);
+    const real fx = cx == 0 ? real(1) - T - U[0] * U[0] : real(0.5) * (T + U[0] * U[0] + real(cx) * U[0]);
+    const real fy = cy == 0 ? real(1) - T - U[1] * U[1] : real(0.5) * (T + U[1] * U[1] + real(cy) * U[1]);
+    return fx * fy;
+  } else if constexpr (is_face<D>(i)) {
+    constexpr int a = edge_axis<D>(i, 0);
+    constexpr int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
+    constexpr real sg = real(cvec<D>(i, a));
+    return real(0.5) * (T + U[a] * U[a] + sg * U[a]) * (real(1) - real(2) * T - U[b1] * U[b1] - U[b2] * U[b2]);
+  } else {
+    constexpr int a0 = edge_axis<D>(i, 0), a1 = edge_axis<D>(i, 1);
+    constexpr real s0 = real(cvec<D>(i, a0)), s1 = real(cvec<D>(i, a1));
+    return real(0.25) * (T + U[a0] * U[a0] + s0 * U[a0]) * (T + U[a1] * U[a1] + s1 * U[a1]);
   }
-  return e;
+}
+// ... and the rest population (D3Q19: one minus all moving populations, in
+// closed form)
+template <typename real, int D>
+__device__ inline real eq_rest(const real *U, real T) {
+  if constexpr (D == 2) {
+    return (real(1) - T - U[0] * U[0]) * (real(1) - T - U[1] * U[1]);
+  } else {
+    const real s0 = T + U[0] * U[0], s1 = T + U[1] * U[1], s2 = T + U[2] * U[2];
+    const real q0 = U[0] * U[0], q1 = U[1] * U[1], q2 = U[2] * U[2];
+    const real faces = s0 * (real(1) - real(2) * T - q1 - q2) + s1 * (real(1) - real(2) * T - q0 - q2) +
+                       s2 * (real(1) - real(2) * T - q0 - q1);
+    return real(1) - faces - (s0 * s1 + s0 * s2 + s1 * s2);
+  }
 }
 
 // the node whose collision a gas node stores: an outlet node takes the last
@@ -557,262 +568,265 @@ __device__ inline SrcNode collision_source(const Params<real> &p, const Bufs<rea
   return {sn, ld(b.slot_of, sn)};
 }
 
-// ===========================================================================
-// k_esum: temperature of f (Eq.(25): T plus half the energy of all sources)
-// and of the auxiliary state f* (quasi-equilibrium at fixed species momenta
-// and energy), one thread per gas node
-// ===========================================================================
-template <typename real, int D, int NS>
-__global__ void __launch_bounds__(BLOCK) k_esum(Params<real> p, Bufs<real> b, int cur) {
-  const int nblk = (p.n_gas + BLOCK - 1) / BLOCK, lb = xcd_block(nblk);
-  const int t = lb * BLOCK + threadIdx.x;
-  if (lb >= nblk || t >= p.n_gas) return;
-  const SrcNode sc = collision_source(p, b, (int)b.gas_list[t], t);
-  const int nsl = p.nsl;
-  real u[D];
-#pragma unroll
-  for (int a = 0; a < D; ++a) u[a] = ld(b.F + (size_t)fo_u(NS, a) * nsl, sc.slot);
-  const real Tt = ld(b.F + (size_t)fo_T<D>(NS) * nsl, sc.slot);
-  NbCommon<real, D> nb[D][2];
-  const bool cgrad = (p.flags & 10u) != 0;
-  if (cgrad) load_neighbours<real, D, NS>(p, b, sc.node, sc.slot, nb);
-  real C = 0, esum = 0;
-#pragma unroll
-  for (int j = 0; j < NS; ++j) {
-    C += ld(b.F + (size_t)fo_rho(j) * nsl, sc.slot) * p.invM[j];
-    esum += energy_source<real, D, NS>(p, b, sc.slot, j, u, Tt, nb);
-  }
-  const real Tf = Tt + esum / (real(2 * D) * C);
-  const real Tst = Tf - ld(b.F + (size_t)fo_ediff<D>(NS) * nsl, sc.slot) / (real(D) * C);
-  st(b.F + (size_t)fo_Tf<D>(NS) * nsl, t, Tf);
-  st(b.F + (size_t)fo_Tst<D>(NS) * nsl, t, Tst);
-}
-
-// ===========================================================================
-// k_collide: streaming, sources, equilibria and Eq.(24)
-// ===========================================================================
-// Per-axis factors of the equilibrium (see equilibrium() in fdlbm_device.h)
+// Per-species constants of the collision at one node, for Eq.(24) in its
+// difference form g+ = g - w (g - rho P*) - w (tau1/tau2) rho (P* - P^eq) +
+// w tau1 S (P*, P^eq: equilibria per unit density; f* and f^eq differ only by
+// the diffusion velocity, so their difference is formed directly), with the
+// source moments pre-scaled by w tau1 and the species lattice speed.
 template <typename real, int D>
-struct EqFactors {
-  real P0[3], Pp[3], Pm[3], U2[3], perp_base;
-  __device__ inline void set(real sqM, const real *u, real T) {
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const real U = a < D ? sqM * u[a] : real(0);
-      U2[a] = U * U;
-      P0[a] = real(1) - T - U2[a];
-      Pp[a] = real(0.5) * (T + U2[a] + U);
-      Pm[a] = real(0.5) * (T + U2[a] - U);
-    }
-    perp_base = real(1) - real(2) * T;
-  }
-  // population of a moving direction i (per unit density)
-  template <int i>
-  __device__ inline real moving() const {
-    if constexpr (D == 2) {
-      constexpr int cx = cvec<D>(i, 0), cy = cvec<D>(i, 1);
-      const real fx = cx == 0 ? P0[0] : (cx > 0 ? Pp[0] : Pm[0]);
-      const real fy = cy == 0 ? P0[1] : (cy > 0 ? Pp[1] : Pm[1]);
-      return fx * fy;
-    } else if constexpr (is_face<D>(i)) {
-      constexpr int a = edge_axis<D>(i, 0);
-      constexpr int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
-      return (cvec<D>(i, a) > 0 ? Pp[a] : Pm[a]) * (perp_base - U2[b1] - U2[b2]);
-    } else {
-      constexpr int a0 = edge_axis<D>(i, 0), a1 = edge_axis<D>(i, 1);
-      return (cvec<D>(i, a0) > 0 ? Pp[a0] : Pm[a0]) * (cvec<D>(i, a1) > 0 ? Pp[a1] : Pm[a1]);
-    }
-  }
-  // rest population (per unit density): D2Q9 product, D3Q19 the remainder
-  __device__ inline real rest(real sum_moving) const {
-    if constexpr (D == 2) return P0[0] * P0[1];
-    else return real(1) - sum_moving;
-  }
+struct SpeciesColl {
+  real w, rho, a2;            // w = 2/(1 + 2 tau1), a2 = w (tau1/tau2) rho
+  real Us[3];                 // sqrt(M_j) u_j (auxiliary-state velocity)
+  real mS[D], PdS[D], YS[D];  // momentum, diagonal second moment, energy flux
+  real PoS[3];                // off-diagonal second moments xy, xz, yz
+  real eS;                    // energy (Prandtl term)
+  real r_st, r_rest;          // rest population: rho P*_0 and a2 (P*_0 - P^eq_0) - w tau1 S_0
 };
 
-// Collision of species j at gas slot t, computed at the source node sc (an
-// outlet node takes the last interior node of its row) and stored at t.
-// Straight-line code: every load is unconditional (addresses are always
-// valid) and the switches act through selects, so the compiler can issue the
-// tap loads, the node's fields and the neighbours' fields together.
+// Collision of all species at gas slot t, computed at the source node sc and
+// stored at t.
 template <bool FAST, typename real, int D, int NS>
 __device__ inline void collide_node(const Params<real> &p, const Bufs<real> &b, int cur,
-                                    const WTab<real> &wtab, const int t, const SrcNode sc,
-                                    const int j) {
+                                      const WTab<real> &wtab, const int t, const SrcNode sc) {
   constexpr int Q = lat_q<D>();
+  constexpr int NR = fr_count(D, NS), NX = fx_count(D, NS);
   const int nsl = p.nsl;
   const int ss = sc.slot;
-  const real *__restrict__ F = b.F;
-  // streamed populations of species j at the source node (Eq.(33)-(36))
-  const Addr<D> ad(sc.node, p);
-  const uint64_t cw = b.scls[ss];
-  const real *__restrict__ Gj = b.G[cur] + (size_t)(j * Q) * nsl;
-  real g[Q];
-  g[0] = ld(Gj, ss);  // rest: not streamed
-  static_for<1, Q>([&](auto ic_) __attribute__((always_inline)) {
-    constexpr int i = decltype(ic_)::value;
-    const int cls = cls_at(cw, i);
-    g[i] = interp(Gj + (size_t)i * nsl, tap_slots<FAST, real, D>(b, ad, i, cls), wtab.w[j][cls]);
-  });
-  // node fields
-  real u[D], uj[D], Uc[D];
+  // ---- the node's fields (pass 1) ----
+  const Rec<real, NR> me = ldrec<real, NR>(b.FR, ss);
+  const Rec<real, NX> mx = ldrec<real, NX>(b.FX, ss);
+  real u[D];
 #pragma unroll
-  for (int a = 0; a < D; ++a) {
-    u[a] = ld(F + (size_t)fo_u(NS, a) * nsl, ss);
-    uj[a] = ld(F + (size_t)fo_uj<D>(NS, j, a) * nsl, ss);
-    Uc[a] = ld(F + (size_t)fo_Uc<D>(NS, a) * nsl, ss);
-  }
-  const real Tt = ld(F + (size_t)fo_T<D>(NS) * nsl, ss);
-  const real Tf = ld(F + (size_t)fo_Tf<D>(NS) * nsl, t);
-  const real Tst = ld(F + (size_t)fo_Tst<D>(NS) * nsl, t);
-  const real rj = ld(F + (size_t)fo_rho(j) * nsl, ss);
-  const real tau1 = ld(F + (size_t)fo_tau1(NS, j) * nsl, ss);
-  const real tau2 = ld(F + (size_t)fo_tau2(NS, j) * nsl, ss);
-  NbCommon<real, D> nb[D][2];
-  load_neighbours<real, D, NS>(p, b, sc.node, ss, nb);
-  real rnb[D][2], tnb[D][2];
+  for (int a = 0; a < D; ++a) u[a] = me.v[fr_u(a)];
+  const real Tt = me.v[fr_T(D)];
+  real C = 0;
 #pragma unroll
-  for (int a = 0; a < D; ++a)
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      rnb[a][s] = ld(F + (size_t)fo_rho(j) * nsl, nb[a][s].slot);
-      tnb[a][s] = ld(F + (size_t)fo_tau1(NS, j) * nsl, nb[a][s].slot);
-    }
+  for (int j = 0; j < NS; ++j) C += me.v[fr_rho(D, j)] * p.invM[j];
   // switches (uniform): 1 or 0
   const real kdiff = ((p.flags & 1u) && NS > 1) ? real(1) : real(0);
   const real kvisc = (p.flags & 2u) ? real(1) : real(0);
   const real kener = (p.flags & 4u) ? real(1) : real(0);
   const real kpr = (p.flags & 8u) ? p.kpr : real(0);
-  // source moments of species j: momentum m, second moments P (diagonal Pd,
-  // off-diagonal Po: xy, xz, yz), energy flux Y, energy e
-  const real iM = p.invM[j];
-  real m[D], Pd[D], Po[3], Y[D], e = 0;
+  // ---- source moments of every species ----
+  real m[NS][D], Pd[NS][D], Po[NS][3], Y[NS][D], e[NS];
 #pragma unroll
-  for (int a = 0; a < D; ++a) {
-    m[a] = kdiff * rj * Uc[a] / tau2 + rj * p.F[a];  // Eq.(12) + body force
-    Pd[a] = real(2) * rj * u[a] * p.F[a];
-    Y[a] = 0;
-  }
-  Po[0] = rj * (u[0] * p.F[1] + u[1] * p.F[0]);
-  Po[1] = Po[2] = 0;
-  if constexpr (D == 3) {
-    Po[1] = rj * (u[0] * p.F[2] + u[2] * p.F[0]);
-    Po[2] = rj * (u[1] * p.F[2] + u[2] * p.F[1]);
-  }
-  const real Kx = kpr * tau1 * rj * iM * Tt * iM;
+  for (int j = 0; j < NS; ++j) {
+    const real rj = me.v[fr_rho(D, j)];
+    const real tau2 = mx.v[fx_tau2(j)];
 #pragma unroll
-  for (int a = 0; a < D; ++a) {
-    const NbCommon<real, D> &sp = nb[a][0], &sm = nb[a][1];
-    const real rp = rnb[a][0], rm = rnb[a][1];
-    // d_a Q'_aaa; a wall face carries no correction flux (mirror value)
-    const real qx = q_dev<real, D>(rj, iM, u[a], Tt);
-    const real qp = sp.wall ? -qx : q_dev<real, D>(rp, iM, sp.u[a], sp.T);
-    const real qm = sm.wall ? -qx : q_dev<real, D>(rm, iM, sm.u[a], sm.T);
-    Pd[a] += kvisc * real(0.5) * (qp - qm);
-    if constexpr (D == 3) {
-      // d_a of Q'_xyz = -rho u_x u_y u_z feeds the off-diagonal pair not containing a
-      const real dq = real(0.5) * (-rp * sp.u[0] * sp.u[1] * sp.u[2] + rm * sm.u[0] * sm.u[1] * sm.u[2]);
-      Po[2 - a] += kvisc * dq;  // a = x -> yz (2), y -> xz (1), z -> xy (0)
+    for (int a = 0; a < D; ++a) {
+      m[j][a] = kdiff * rj * mx.v[fx_Uc(D, NS, a)] / tau2 + rj * p.F[a];  // Eq.(12) + body force
+      Pd[j][a] = real(2) * rj * u[a] * p.F[a];
+      Y[j][a] = 0;
     }
-#pragma unroll
-    for (int c = 0; c < D; ++c)
-      Y[c] += kener * real(0.5) * (r_dev<real, D>(rp, iM, sp.u, sp.T, c, a) -
-                                   r_dev<real, D>(rm, iM, sm.u, sm.T, c, a));
-    // Eq.(19)-(21), face-flux form; wall faces carry no correction flux
-    const real ep = real(0.5) * (Kx + kpr * tnb[a][0] * rp * iM * sp.T * iM) * (sp.T - Tt);
-    const real em = real(0.5) * (Kx + kpr * tnb[a][1] * rm * iM * sm.T * iM) * (sm.T - Tt);
-    e += (!sp.wall && !sp.missing) ? ep : real(0);
-    e += (!sm.wall && !sm.missing) ? em : real(0);
+    Po[j][0] = rj * (u[0] * p.F[1] + u[1] * p.F[0]);
+    Po[j][1] = Po[j][2] = 0;
+    if constexpr (D == 3) {
+      Po[j][1] = rj * (u[0] * p.F[2] + u[2] * p.F[0]);
+      Po[j][2] = rj * (u[1] * p.F[2] + u[2] * p.F[1]);
+    }
+    e[j] = 0;
   }
-  EqFactors<real, D> fe, fs;
-  fe.set(p.sqM[j], u, Tf);
-  fs.set(p.sqM[j], uj, Tst);
-  const real w1 = real(2) / (real(1) + real(2) * tau1);
-  const real r12 = tau1 / tau2;
-  const real wt = w1 * tau1;
-  const real ic = p.invcj[j], ic2 = ic * ic, ic3 = ic2 * ic;
-  real trP = 0;
+  const Addr<D> ad(sc.node, p);
+  const int null_slot = p.n_gas + p.n_wall;
 #pragma unroll
-  for (int a = 0; a < D; ++a) trP += Pd[a];
-  real *__restrict__ Gnj = b.G[cur ^ 1] + (size_t)(j * Q) * nsl;
-  real se = 0, ss_ = 0;  // sums of the moving populations of f^eq and f* (per unit density)
+  for (int a = 0; a < D; ++a) {
+    // face neighbours along a: slot (the node itself when missing) and kind
+    Rec<real, NR> nr[2];
+    bool wall[2], miss[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int q = ad.face(p, a, s == 0 ? +1 : -1);
+      const int ql = ld(b.slot_of, q >= 0 ? q : sc.node);  // unconditional load
+      const int qs = q >= 0 ? ql : null_slot;
+      wall[s] = qs >= p.n_gas && qs < null_slot;
+      miss[s] = qs == null_slot || q == sc.node;
+      nr[s] = ldrec<real, NR>(b.FR, miss[s] ? ss : qs);
+    }
+    real up[D], um[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      up[c] = nr[0].v[fr_u(c)];
+      um[c] = nr[1].v[fr_u(c)];
+    }
+    const real Tp = nr[0].v[fr_T(D)], Tm = nr[1].v[fr_T(D)];
+    const bool fp = !wall[0] && !miss[0], fm = !wall[1] && !miss[1];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      const real iM = p.invM[j];
+      const real rj = me.v[fr_rho(D, j)];
+      const real rp = nr[0].v[fr_rho(D, j)], rm = nr[1].v[fr_rho(D, j)];
+      // d_a Q'_aaa; a wall face carries no correction flux (mirror value)
+      const real qx = q_dev<real>(rj, iM, u[a], Tt);
+      const real qp = wall[0] ? -qx : q_dev<real>(rp, iM, up[a], Tp);
+      const real qm = wall[1] ? -qx : q_dev<real>(rm, iM, um[a], Tm);
+      Pd[j][a] += kvisc * real(0.5) * (qp - qm);
+      if constexpr (D == 3) {
+        // d_a of Q'_xyz = -rho u_x u_y u_z feeds the off-diagonal pair not containing a
+        const real dq = real(0.5) * (-rp * up[0] * up[1] * up[2] + rm * um[0] * um[1] * um[2]);
+        Po[j][2 - a] += kvisc * dq;  // a = x -> yz (2), y -> xz (1), z -> xy (0)
+      }
+#pragma unroll
+      for (int c = 0; c < D; ++c)
+        Y[j][c] += kener * real(0.5) * (r_dev<real, D>(rp, iM, up, Tp, c, a) - r_dev<real, D>(rm, iM, um, Tm, c, a));
+      // Eq.(19)-(21), face-flux form; wall faces carry no correction flux
+      const real Kx = kpr * me.v[fr_tau1(D, NS, j)] * rj * iM * Tt * iM;
+      const real ep = real(0.5) * (Kx + kpr * nr[0].v[fr_tau1(D, NS, j)] * rp * iM * Tp * iM) * (Tp - Tt);
+      const real em = real(0.5) * (Kx + kpr * nr[1].v[fr_tau1(D, NS, j)] * rm * iM * Tm * iM) * (Tm - Tt);
+      e[j] += (fp ? ep : real(0)) + (fm ? em : real(0));
+    }
+  }
+  // ---- temperatures of f (Eq.(25): T plus half the source energy) and of
+  // the auxiliary state (quasi-equilibrium at fixed species momenta and energy)
+  real esum = 0;
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    real trP = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) trP += Pd[j][a];
+    esum += trP + e[j];
+  }
+  const real Tf = Tt + esum / (real(2 * D) * C);
+  const real Tst = Tf - mx.v[fx_ediff(D, NS)] / (real(D) * C);
+  // ---- per-species constants ----
+  SpeciesColl<real, D> sp[NS];
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    SpeciesColl<real, D> &c = sp[j];
+    const real rj = me.v[fr_rho(D, j)];
+    const real tau1 = me.v[fr_tau1(D, NS, j)], tau2 = mx.v[fx_tau2(j)];
+    const real w1 = real(2) / (real(1) + real(2) * tau1);
+    const real r12 = tau1 / tau2;
+    const real wt = w1 * tau1;
+    c.w = w1;
+    c.rho = rj;
+    c.a2 = w1 * r12 * rj;
+    const real ic = p.invcj[j], ic2 = ic * ic, ic3 = ic2 * ic;
+    real trP = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      c.Us[a] = p.sqM[j] * mx.v[fx_uj(D, NS, j, a)];
+      c.mS[a] = wt * m[j][a] * ic;
+      c.PdS[a] = wt * real(0.5) * Pd[j][a] * ic2;
+      c.YS[a] = wt * Y[j][a] * ic3;
+      trP += Pd[j][a];
+    }
+    if constexpr (D == 2) c.Us[2] = real(0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) c.PoS[k] = wt * real(0.25) * Po[j][k] * ic2;
+    c.eS = wt * e[j] * ic2 / real(2 * D);
+    real Ue[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < D; ++a) Ue[a] = p.sqM[j] * u[a];
+    const real ps0 = eq_rest<real, D>(c.Us, Tst), pe0 = eq_rest<real, D>(Ue, Tf);
+    c.r_st = rj * ps0;
+    c.r_rest = c.a2 * (ps0 - pe0) + wt * (trP + e[j]) * ic2;
+  }
+  // ---- streaming and collision, one direction at a time ----
+  const real *__restrict__ G = b.G[cur];
+  real *__restrict__ Gn = b.G[cur ^ 1];
+  {
+    const Rec<real, NS> g0 = ldrec<real, NS>(G, ss);  // rest: not streamed
+    Rec<real, NS> o;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) o.v[j] = g0.v[j] - sp[j].w * (g0.v[j] - sp[j].r_st) - sp[j].r_rest;
+    strec<real, NS>(Gn, t, o);
+  }
+  const uint64_t cw = b.scls[ss];
   static_for<1, Q>([&](auto ic_) __attribute__((always_inline)) {
     constexpr int i = decltype(ic_)::value;
-    real S;
-    if constexpr (is_face<D>(i)) {
-      constexpr int a = edge_axis<D>(i, 0);
-      constexpr real sg = real(cvec<D>(i, a));
-      S = sg * m[a] * ic + real(0.5) * Pd[a] * ic2 - real(0.5) * sg * Y[a] * ic3 + e * ic2 / real(2 * D);
-    } else {
-      constexpr real kd = D == 2 ? real(0.25) : real(0.125);
-      constexpr int a0 = edge_axis<D>(i, 0), a1 = edge_axis<D>(i, 1);
-      constexpr int s0 = cvec<D>(i, a0), s1 = cvec<D>(i, a1);
-      constexpr int po = D == 2 ? 0 : (a0 == 0 ? (a1 == 1 ? 0 : 1) : 2);
-      S = -kd * (real(s0) * m[a0] + real(s1) * m[a1]) * ic + real(0.25 * s0 * s1) * Po[po] * ic2 +
-          kd * (real(s0) * Y[a0] + real(s1) * Y[a1]) * ic3;
+    const int cls = cls_at(cw, i);
+    const Rec<real, NS> g =
+        stream_rec<real, NS>(G + (size_t)i * nsl * NS, tap_slots<FAST, real, D>(b, ad, i, cls), wtab, cls);
+    Rec<real, NS> o;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      const SpeciesColl<real, D> &c = sp[j];
+      real Ue[3] = {0, 0, 0};
+#pragma unroll
+      for (int a = 0; a < D; ++a) Ue[a] = p.sqM[j] * u[a];
+      const real pe = eq_moving<real, D, i>(Ue, Tf), ps = eq_moving<real, D, i>(c.Us, Tst);
+      real S;
+      if constexpr (is_face<D>(i)) {
+        constexpr int a = edge_axis<D>(i, 0);
+        constexpr real sg = real(cvec<D>(i, a));
+        S = sg * c.mS[a] + c.PdS[a] - real(0.5) * sg * c.YS[a] + c.eS;
+      } else {
+        constexpr real kd = D == 2 ? real(0.25) : real(0.125);
+        constexpr int a0 = edge_axis<D>(i, 0), a1 = edge_axis<D>(i, 1);
+        constexpr int s0 = cvec<D>(i, a0), s1 = cvec<D>(i, a1);
+        constexpr int po = D == 2 ? 0 : (a0 == 0 ? (a1 == 1 ? 0 : 1) : 2);
+        S = -kd * (real(s0) * c.mS[a0] + real(s1) * c.mS[a1]) + real(s0 * s1) * c.PoS[po] +
+            kd * (real(s0) * c.YS[a0] + real(s1) * c.YS[a1]);
+      }
+      o.v[j] = g.v[j] - c.w * (g.v[j] - c.rho * ps) - c.a2 * (ps - pe) + S;
     }
-    const real pe = fe.template moving<i>(), ps = fs.template moving<i>();
-    se += pe;
-    ss_ += ps;
-    const real gi = g[i];
-    const real feq = rj * pe, fst = rj * ps;
-    st(Gnj + (size_t)i * nsl, t, gi - w1 * (gi - fst) - w1 * r12 * (fst - feq) + wt * S);
+    strec<real, NS>(Gn + (size_t)i * nsl * NS, t, o);
   });
-  const real S0 = -(trP + e) * ic2;
-  const real feq = rj * fe.rest(se), fst = rj * fs.rest(ss_);
-  st(Gnj, t, g[0] - w1 * (g[0] - fst) - w1 * r12 * (fst - feq) + wt * S0);
 }
 
 // inlet node: equilibrium at the inlet state with the velocity of the first
 // interior plane of its row (Sec. 6)
 template <typename real, int D, int NS>
 __device__ inline void inlet_node(const Params<real> &p, const Bufs<real> &b, int cur, int t,
-                                  int node, int j) {
+                                  int node) {
   constexpr int Q = lat_q<D>();
+  constexpr int NR = fr_count(D, NS);
   const int nsl = p.nsl;
   const int src = node - node % p.nx + 2;
   const bool ok = gaslike(b.kind[src]);
-  const int ssl = ok ? ld(b.slot_of, src) : t;
-  real u[D];
+  const Rec<real, NR> fr = ldrec<real, NR>(b.FR, ok ? ld(b.slot_of, src) : t);
+  real *__restrict__ Gn = b.G[cur ^ 1];
+  real U[NS][3];
 #pragma unroll
-  for (int a = 0; a < D; ++a) u[a] = ok ? ld(b.F + (size_t)fo_u(NS, a) * nsl, ssl) : real(0);
-  real *Gn = b.G[cur ^ 1];
-  real f[Q];
-  equilibrium<real, D>(p.rho_in[j], p.sqM[j], u, p.T_in, f);
+  for (int j = 0; j < NS; ++j)
 #pragma unroll
-  for (int i = 0; i < Q; ++i) st(Gn + (size_t)(j * Q + i) * nsl, t, f[i]);
+    for (int a = 0; a < 3; ++a) U[j][a] = (ok && a < D) ? p.sqM[j] * fr.v[fr_u(a)] : real(0);
+  {
+    Rec<real, NS> o;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) o.v[j] = p.rho_in[j] * eq_rest<real, D>(U[j], p.T_in);
+    strec<real, NS>(Gn, t, o);
+  }
+  static_for<1, Q>([&](auto ic_) __attribute__((always_inline)) {
+    constexpr int i = decltype(ic_)::value;
+    Rec<real, NS> o;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) o.v[j] = p.rho_in[j] * eq_moving<real, D, i>(U[j], p.T_in);
+    strec<real, NS>(Gn + (size_t)i * nsl * NS, t, o);
+  });
 }
 
-// one thread per (gas node, species); the species is uniform per block and
-// varies fastest over the logical blocks, so the NS blocks of one run of
-// nodes work together on one XCD and share the moments and taps in its L2
+// one thread per gas node, all species
 template <bool FAST, typename real, int D, int NS>
 __global__ void __launch_bounds__(BLOCK) k_collide(Params<real> p, Bufs<real> b, int cur) {
   __shared__ WTab<real> wtab;
   load_wtab<real, NS>(p, wtab);
   const int first = FAST ? 0 : p.n_gas_fast, count = FAST ? p.n_gas_fast : p.n_gas - p.n_gas_fast;
-  const int nbn = (count + BLOCK - 1) / BLOCK, nb = nbn * NS, lb = xcd_block(nb);
+  const int nb = (count + BLOCK - 1) / BLOCK, lb = xcd_block(nb);
   if (lb >= nb) return;  // whole block: no barrier follows for it
-  const int j = lb % NS;
-  const int tl = (lb / NS) * BLOCK + threadIdx.x;
+  const int tl = lb * BLOCK + threadIdx.x;
   double work = 0.0;
   if (tl < count) {
     const int t = first + tl;
     const int node = (int)b.gas_list[t];
     {
-      // work of the body force on species j this step, rho_j u.F (half the
+      // work of the body force on the gas at t this step, rho u.F (half the
       // trace of its source)
-      const int nsl = p.nsl;
-      real uf = 0;
+      constexpr int NR = fr_count(D, NS);
+      const Rec<real, NR> at = ldrec<real, NR>(b.FR, t);
+      real uf = 0, rt = 0;
 #pragma unroll
-      for (int a = 0; a < D; ++a) uf += ld(b.F + (size_t)fo_u(NS, a) * nsl, t) * p.F[a];
-      work = (double)(ld(b.F + (size_t)fo_rho(j) * nsl, t) * uf);
+      for (int a = 0; a < D; ++a) uf += at.v[fr_u(a)] * p.F[a];
+#pragma unroll
+      for (int j = 0; j < NS; ++j) rt += at.v[fr_rho(D, j)];
+      work = (double)(rt * uf);
     }
-    if (b.kind[node] == KIND_INLET) inlet_node<real, D, NS>(p, b, cur, t, node, j);
-    else collide_node<FAST, real, D, NS>(p, b, cur, wtab, t, collision_source(p, b, node, t), j);
+    if (b.kind[node] == KIND_INLET) inlet_node<real, D, NS>(p, b, cur, t, node);
+    else collide_node<FAST, real, D, NS>(p, b, cur, wtab, t, collision_source(p, b, node, t));
   }
   const double s = block_sum(work);
-  if (threadIdx.x == 0 && s != 0.0) b.acc_work[lb + (FAST ? 0 : p.slot_off_gas * NS)] += s;
+  if (threadIdx.x == 0 && s != 0.0) b.acc_work[lb + (FAST ? 0 : p.slot_off_gas)] += s;
 }
 
 // ===========================================================================
@@ -899,6 +913,7 @@ __global__ void __launch_bounds__(BLOCK) k_solid(Params<real> p, Bufs<real> b, i
   if (threadIdx.x == 0 && s != 0.0) b.acc_bheat[blockIdx.x] += s;
 }
 
+
 // ===========================================================================
 // k_observe: FP64 partial sums per block.  Slots per block: [0, NS) species
 // mass; then e_gas, e_solid, T_min, T_max, u_max, rho_min, Ts_min, Ts_max,
@@ -933,28 +948,36 @@ __global__ void __launch_bounds__(BLOCK) k_observe(Params<real> p, Bufs<real> b,
   for (int s = gid; s < p.n_gas + p.n_wall; s += stride) {
     const bool gas = s < p.n_gas;
     const uint32_t em = gas ? ~0u : b.wem[s - p.n_gas];
+    double rj[NS], Ej[NS], Jj[NS][3];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      rj[j] = Ej[j] = 0.0;
+      Jj[j][0] = Jj[j][1] = Jj[j][2] = 0.0;
+    }
+    for (int i = 0; i < Q; ++i) {
+      if (!(em & (1u << i))) continue;
+      const real *rec = G + ((size_t)i * nsl + s) * NS;
+#pragma unroll
+      for (int j = 0; j < NS; ++j) {
+        const double gv = (double)rec[j];
+        if (!isfinite(gv)) acc[S_BAD] = 1.0;
+        rj[j] += gv;
+        Ej[j] += (double)cnorm2<D>(i) * gv;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Jj[j][a] += (double)cvec<D>(i, a) * gv;
+      }
+    }
     double E = 0, rhot = 0, C = 0, J[3] = {0, 0, 0};
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
-      double rj = 0, Ej = 0, Jj[3] = {0, 0, 0};
+      acc[j] += rj[j];
+      E += (double)p.cj2[j] * Ej[j];
 #pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        if (!(em & (1u << i))) continue;
-        const double gv = (double)G[(size_t)(j * Q + i) * nsl + s];
-        if (!isfinite(gv)) acc[S_BAD] = 1.0;
-        rj += gv;
-        Ej += (double)cnorm2<D>(i) * gv;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) Jj[a] += (double)cvec<D>(i, a) * gv;
-      }
-      acc[j] += rj;
-      E += (double)p.cj2[j] * Ej;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) J[a] += (double)p.cj[j] * Jj[a];
+      for (int a = 0; a < 3; ++a) J[a] += (double)p.cj[j] * Jj[j][a];
       if (gas) {
-        rhot += rj;
-        C += rj / (double)p.M[j];
-        acc[S_RMIN] = fmin(acc[S_RMIN], rj);
+        rhot += rj[j];
+        C += rj[j] / (double)p.M[j];
+        acc[S_RMIN] = fmin(acc[S_RMIN], rj[j]);
       }
     }
     acc[S_EG] += 0.5 * E;
@@ -998,7 +1021,6 @@ inline hipError_t step_impl(const Params<real> &p, const Bufs<real> &b, int cur,
                             LaunchInfo &li) {
   const int gwf = (p.n_wall_fast + BLOCK - 1) / BLOCK, gws = (p.n_wall - p.n_wall_fast + BLOCK - 1) / BLOCK;
   const int ggf = (p.n_gas_fast + BLOCK - 1) / BLOCK, ggs = (p.n_gas - p.n_gas_fast + BLOCK - 1) / BLOCK;
-  const int gg = (p.n_gas + BLOCK - 1) / BLOCK;
   hipStream_t st = li.stream;
   auto mark = [&](int k, int which) {
     if (li.events) {
@@ -1015,12 +1037,9 @@ inline hipError_t step_impl(const Params<real> &p, const Bufs<real> &b, int cur,
   if (ggf > 0) hipLaunchKernelGGL((k_moments<true, real, D, NS>), dim3(xcd_grid(ggf)), blk, 0, st, p, b, cur);
   if (ggs > 0) hipLaunchKernelGGL((k_moments<false, real, D, NS>), dim3(xcd_grid(ggs)), blk, 0, st, p, b, cur);
   mark(K_MOMENTS_ID, 1);
-  mark(K_ESUM_ID, 0);
-  if (gg > 0) hipLaunchKernelGGL((k_esum<real, D, NS>), dim3(xcd_grid(gg)), blk, 0, st, p, b, cur);
-  mark(K_ESUM_ID, 1);
   mark(K_COLLIDE_ID, 0);
-  if (ggf > 0) hipLaunchKernelGGL((k_collide<true, real, D, NS>), dim3(xcd_grid(ggf * NS)), blk, 0, st, p, b, cur);
-  if (ggs > 0) hipLaunchKernelGGL((k_collide<false, real, D, NS>), dim3(xcd_grid(ggs * NS)), blk, 0, st, p, b, cur);
+  if (ggf > 0) hipLaunchKernelGGL((k_collide<true, real, D, NS>), dim3(xcd_grid(ggf)), blk, 0, st, p, b, cur);
+  if (ggs > 0) hipLaunchKernelGGL((k_collide<false, real, D, NS>), dim3(xcd_grid(ggs)), blk, 0, st, p, b, cur);
   mark(K_COLLIDE_ID, 1);
   if (li.n_solid > 0) {
     const int tiles = solid_tiles<D>(p.nx, p.ny, p.nz);

@@ -7,8 +7,7 @@
 
 namespace fdlbm {
 
-enum { K_WALL_ID = 0, K_MOMENTS_ID = 1, K_COLLIDE_ID = 2, K_SOLID_ID = 3, K_ESUM_ID = 4,
-       K_NUM = 5 };
+enum { K_WALL_ID = 0, K_MOMENTS_ID = 1, K_COLLIDE_ID = 2, K_SOLID_ID = 3, K_NUM = 4 };
 
 struct LaunchInfo {
   hipStream_t stream;
@@ -17,7 +16,7 @@ struct LaunchInfo {
   bool recorded[K_NUM];  // set by the launcher for the ids it recorded
 };
 
-// one time step on lattice D: wall, moments, collide, solid, inlet/outlet
+// one time step on lattice D: wall, moments, collide (with inlet/outlet), solid
 template <typename real, int D>
 hipError_t step_lat(const Params<real> &p, const Bufs<real> &b, int cur, LaunchInfo &li);
 

@@ -22,8 +22,8 @@ F64, F32 = 0, 1
 CORR_DIFFUSION, CORR_VISCOUS, CORR_ENERGY, CORR_PRANDTL, CORR_ALL = 1, 2, 4, 8, 15
 WALL_REACTIVE, WALL_ISOTHERMAL = 0, 1
 FIELD_RHO, FIELD_U, FIELD_T, FIELD_TS, FIELD_POP, FIELD_KIND, FIELD_WALL_R, FIELD_WALL_DE = range(8)
-K_WALL, K_MOMENTS, K_COLLIDE, K_SOLID, K_ESUM = range(5)
-KERNEL_NAMES = ["k_wall", "k_moments", "k_collide", "k_solid", "k_esum"]
+K_WALL, K_MOMENTS, K_COLLIDE, K_SOLID = range(4)
+KERNEL_NAMES = ["k_wall", "k_moments", "k_collide", "k_solid"]
 MAX_SPECIES = 8
 
 EXPORTS = ["fdlbm_create", "fdlbm_destroy", "fdlbm_last_error", "fdlbm_set_geometry",
@@ -210,10 +210,10 @@ class Sim:
         self._check(lib().fdlbm_set_profiling(self.h, 1 if on else 0))
 
     def kernel_times(self) -> tuple[dict, int]:
-        avg = np.zeros(5)
+        avg = np.zeros(len(KERNEL_NAMES))
         cnt = ct.c_int64()
         self._check(lib().fdlbm_kernel_times(self.h, _d(avg), ct.byref(cnt)))
-        return {KERNEL_NAMES[k]: float(avg[k]) for k in range(5)}, cnt.value
+        return {name: float(avg[k]) for k, name in enumerate(KERNEL_NAMES)}, cnt.value
 
     def close(self):
         if getattr(self, "h", None):
