@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--n", type=int, default=128, help="bed edge length (nodes)")
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=96,
+    ap.add_argument("--cpu-n", type=int, default=128,
                     help="edge length of the bed the CPU oracle is timed on (bounded sample)")
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--calib-copy-mib", type=int, default=0,

@@ -132,19 +132,20 @@ struct Bufs {
   double *partials;   // observe reduction partials
 };
 
-// Field records per slot.  FR (what the face neighbours' gradient stencils
-// read): u_a, T, rho_j, tau1_j.  FX (read by the node itself): tau2_j, the
-// species velocities u_ja of f, U^c_a, and sum_j rho_j |u_j - u|^2.
+// Field records per slot, grouped so that a kernel working on one species
+// loads only that species' values.  FR (what the face neighbours' gradient
+// stencils read): u_a, T, then (rho_j, tau1_j) pairs.  FX (read by the node
+// itself): U^c_a, sum_j rho_j |u_j - u|^2, then (tau2_j, u_ja) groups of D+1.
 __host__ __device__ constexpr int fr_u(int a) { return a; }
 __host__ __device__ constexpr int fr_T(int D) { return D; }
-__host__ __device__ constexpr int fr_rho(int D, int j) { return D + 1 + j; }
-__host__ __device__ constexpr int fr_tau1(int D, int ns, int j) { return D + 1 + ns + j; }
+__host__ __device__ constexpr int fr_rho(int D, int j) { return D + 1 + 2 * j; }
+__host__ __device__ constexpr int fr_tau1(int D, int j) { return D + 2 + 2 * j; }
 __host__ __device__ constexpr int fr_count(int D, int ns) { return D + 1 + 2 * ns; }
-__host__ __device__ constexpr int fx_tau2(int j) { return j; }
-__host__ __device__ constexpr int fx_uj(int D, int ns, int j, int a) { return ns + j * D + a; }
-__host__ __device__ constexpr int fx_Uc(int D, int ns, int a) { return ns + ns * D + a; }
-__host__ __device__ constexpr int fx_ediff(int D, int ns) { return ns + ns * D + D; }
-__host__ __device__ constexpr int fx_count(int D, int ns) { return ns + ns * D + D + 1; }
+__host__ __device__ constexpr int fx_Uc(int a) { return a; }
+__host__ __device__ constexpr int fx_ediff(int D) { return D; }
+__host__ __device__ constexpr int fx_tau2(int D, int j) { return (D + 1) * (j + 1); }
+__host__ __device__ constexpr int fx_uj(int D, int j, int a) { return (D + 1) * (j + 1) + 1 + a; }
+__host__ __device__ constexpr int fx_count(int D, int ns) { return (D + 1) * (ns + 1); }
 
 enum : uint8_t { KIND_GAS = 0, KIND_SOLID = 1, KIND_WALL = 2, KIND_INLET = 3, KIND_OUTLET = 4 };
 __host__ __device__ inline bool gaslike(uint8_t k) { return k == KIND_GAS || k >= KIND_INLET; }

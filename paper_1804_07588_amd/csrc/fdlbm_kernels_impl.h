@@ -328,7 +328,7 @@ __device__ inline double wall_node(const Params<real> &p, const Bufs<real> &b, i
 #pragma unroll
   for (int j = 0; j < NS; ++j) {
     fr.v[fr_rho(D, j)] = rw[j];
-    fr.v[fr_tau1(D, NS, j)] = real(0);
+    fr.v[fr_tau1(D, j)] = real(0);
   }
   strec<real, NR>(b.FR, slot, fr);
   b.wall_r[w] = r;
@@ -447,7 +447,7 @@ __global__ void __launch_bounds__(BLOCK) k_moments(Params<real> p, Bufs<real> b,
 #pragma unroll
     for (int k = 0; k < NS; ++k) den += Xh[k] * p.wilke[j][k];
     const real tau1 = p.mu0[j] * fmu / (CT * den);  // Eq.(17)
-    fr.v[fr_tau1(D, NS, j)] = tau1;
+    fr.v[fr_tau1(D, j)] = tau1;
     fr.v[fr_rho(D, j)] = rho[j];
     tau2[j] = tau1;
   }
@@ -464,7 +464,7 @@ __global__ void __launch_bounds__(BLOCK) k_moments(Params<real> p, Bufs<real> b,
     }
   }
 #pragma unroll
-  for (int j = 0; j < NS; ++j) fx.v[fx_tau2(j)] = tau2[j];
+  for (int j = 0; j < NS; ++j) fx.v[fx_tau2(D, j)] = tau2[j];
 #pragma unroll
   for (int a = 0; a < D; ++a) fr.v[fr_u(a)] = u[a];
   fr.v[fr_T(D)] = T;
@@ -482,16 +482,16 @@ __global__ void __launch_bounds__(BLOCK) k_moments(Params<real> p, Bufs<real> b,
       den += ah[j] * rho[j] / (real(1) + ah[j]);
     }
     const real Uc = cdiff ? num / den : real(0);
-    fx.v[fx_Uc(D, NS, a)] = Uc;
+    fx.v[fx_Uc(a)] = Uc;
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
       const real Jf = K[j] + ah[j] * rho[j] * Uc / (real(1) + ah[j]);
       const real uja = rho[j] > tiny<real>() ? Jf / rho[j] : u[a];
-      fx.v[fx_uj(D, NS, j, a)] = uja;
+      fx.v[fx_uj(D, j, a)] = uja;
       ediff += rho[j] * (uja - u[a]) * (uja - u[a]);
     }
   }
-  fx.v[fx_ediff(D, NS)] = ediff;
+  fx.v[fx_ediff(D)] = ediff;
   strec<real, NR>(b.FR, t, fr);
   strec<real, NX>(b.FX, t, fx);
 }
@@ -612,10 +612,10 @@ __device__ inline void collide_node(const Params<real> &p, const Bufs<real> &b, 
 #pragma unroll
   for (int j = 0; j < NS; ++j) {
     const real rj = me.v[fr_rho(D, j)];
-    const real tau2 = mx.v[fx_tau2(j)];
+    const real tau2 = mx.v[fx_tau2(D, j)];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      m[j][a] = kdiff * rj * mx.v[fx_Uc(D, NS, a)] / tau2 + rj * p.F[a];  // Eq.(12) + body force
+      m[j][a] = kdiff * rj * mx.v[fx_Uc(a)] / tau2 + rj * p.F[a];  // Eq.(12) + body force
       Pd[j][a] = real(2) * rj * u[a] * p.F[a];
       Y[j][a] = 0;
     }
@@ -670,9 +670,9 @@ __device__ inline void collide_node(const Params<real> &p, const Bufs<real> &b, 
       for (int c = 0; c < D; ++c)
         Y[j][c] += kener * real(0.5) * (r_dev<real, D>(rp, iM, up, Tp, c, a) - r_dev<real, D>(rm, iM, um, Tm, c, a));
       // Eq.(19)-(21), face-flux form; wall faces carry no correction flux
-      const real Kx = kpr * me.v[fr_tau1(D, NS, j)] * rj * iM * Tt * iM;
-      const real ep = real(0.5) * (Kx + kpr * nr[0].v[fr_tau1(D, NS, j)] * rp * iM * Tp * iM) * (Tp - Tt);
-      const real em = real(0.5) * (Kx + kpr * nr[1].v[fr_tau1(D, NS, j)] * rm * iM * Tm * iM) * (Tm - Tt);
+      const real Kx = kpr * me.v[fr_tau1(D, j)] * rj * iM * Tt * iM;
+      const real ep = real(0.5) * (Kx + kpr * nr[0].v[fr_tau1(D, j)] * rp * iM * Tp * iM) * (Tp - Tt);
+      const real em = real(0.5) * (Kx + kpr * nr[1].v[fr_tau1(D, j)] * rm * iM * Tm * iM) * (Tm - Tt);
       e[j] += (fp ? ep : real(0)) + (fm ? em : real(0));
     }
   }
@@ -687,14 +687,14 @@ __device__ inline void collide_node(const Params<real> &p, const Bufs<real> &b, 
     esum += trP + e[j];
   }
   const real Tf = Tt + esum / (real(2 * D) * C);
-  const real Tst = Tf - mx.v[fx_ediff(D, NS)] / (real(D) * C);
+  const real Tst = Tf - mx.v[fx_ediff(D)] / (real(D) * C);
   // ---- per-species constants ----
   SpeciesColl<real, D> sp[NS];
 #pragma unroll
   for (int j = 0; j < NS; ++j) {
     SpeciesColl<real, D> &c = sp[j];
     const real rj = me.v[fr_rho(D, j)];
-    const real tau1 = me.v[fr_tau1(D, NS, j)], tau2 = mx.v[fx_tau2(j)];
+    const real tau1 = me.v[fr_tau1(D, j)], tau2 = mx.v[fx_tau2(D, j)];
     const real w1 = real(2) / (real(1) + real(2) * tau1);
     const real r12 = tau1 / tau2;
     const real wt = w1 * tau1;
@@ -705,7 +705,7 @@ __device__ inline void collide_node(const Params<real> &p, const Bufs<real> &b, 
     real trP = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      c.Us[a] = p.sqM[j] * mx.v[fx_uj(D, NS, j, a)];
+      c.Us[a] = p.sqM[j] * mx.v[fx_uj(D, j, a)];
       c.mS[a] = wt * m[j][a] * ic;
       c.PdS[a] = wt * real(0.5) * Pd[j][a] * ic2;
       c.YS[a] = wt * Y[j][a] * ic3;

@@ -84,7 +84,10 @@ def main(argv):
     cal_f = calib_bytes / (fetch["k_copy_words"] * 1024)
     cal_w = calib_bytes / (write["k_copy_words"] * 1024)
     lines = ["rocprofv3 summary of the packed-bed step (128^3 D3Q19, 5 species, FP32)", "",
-             "kernel trace:    " + cmd_kt, "counter passes:  " + cmd_pmc, "",
+             "kernel trace:    " + cmd_kt, "counter passes:  " + cmd_pmc,
+             "summary:         python3 -m paper_1804_07588_amd.profsummary " + " ".join(argv[1:5]) +
+             " '<kernel trace command>' '<counter command>'",
+             "(rocprofv3 runs from the repository root after cd /tmp && export TMPDIR=/tmp)", "",
              f"calibration: k_copy_words over {calib_mib} MiB reads and writes {calib_bytes} B;",
              f"  FETCH_SIZE reports {fetch['k_copy_words'] * 1024:.4g} B -> factor {cal_f:.3f}",
              f"  WRITE_SIZE reports {write['k_copy_words'] * 1024:.4g} B -> factor {cal_w:.3f}", "",
