@@ -55,7 +55,7 @@ struct fdlbm_ctx {
   // workspace
   char *ws = nullptr;
   size_t ws_bytes = 0;
-  size_t off_G[2]{}, off_FR = 0, off_FX = 0, off_Ts[2]{}, off_wr = 0, off_wde = 0, off_kind = 0, off_slot = 0,
+  size_t off_G[2]{}, off_Gs = 0, off_FR = 0, off_FX = 0, off_Ts[2]{}, off_wr = 0, off_wde = 0, off_kind = 0, off_slot = 0,
          off_scls = 0, off_wem = 0, off_gl = 0, off_wl = 0, off_am = 0, off_aw = 0, off_ab = 0,
          off_part = 0;
   size_t total = 0;
@@ -108,6 +108,7 @@ static void layout(fdlbm_ctx *c) {
   const size_t pops = (size_t)c->ns * c->Q * nsl * b;
   c->off_G[0] = take(pops);
   c->off_G[1] = take(pops);
+  c->off_Gs = take(pops);
   c->off_FR = take((size_t)fr_count(c->D, c->ns) * nsl * b);
   c->off_FX = take((size_t)fx_count(c->D, c->ns) * nsl * b);
   c->off_Ts[0] = take(n * b);
@@ -138,6 +139,7 @@ static Bufs<real> bufs(const fdlbm_ctx *c) {
   char *w = c->ws;
   b.G[0] = (real *)(w + c->off_G[0]);
   b.G[1] = (real *)(w + c->off_G[1]);
+  b.Gs = (real *)(w + c->off_Gs);
   b.FR = (real *)(w + c->off_FR);
   b.FX = (real *)(w + c->off_FX);
   b.Ts[0] = (real *)(w + c->off_Ts[0]);

@@ -115,6 +115,7 @@ struct Params {
 template <typename real>
 struct Bufs {
   real *G[2];         // populations [((i*nsl + slot)*NS + j], double-buffered
+  real *Gs;           // streamed (pre-collision) populations of the gas slots, same layout
   real *FR;           // per-slot record read by neighbours: u, T, rho_j, tau1_j
   real *FX;           // per-slot record of the node itself: tau2_j, u_j, U^c, energy defect
   real *Ts[2];        // solid temperature per node, double-buffered

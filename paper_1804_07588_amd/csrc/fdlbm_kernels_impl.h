@@ -4,10 +4,10 @@
 //   k_wall     reactive diffusive wall at every wall node: streaming of the
 //              populations arriving from the gas, wall densities and the
 //              thermalised emission (Eq.(37)-(42), (50))
-//   k_moments  streaming into every gas node (Eq.(33)-(36)), evaluated on the
-//              fly, and everything local: moments, transport, U^c, species
-//              momenta of f (Eq.(3), (5), (7)-(8), (11), (14)-(17), (25))
-//   k_collide  streaming again, correction sources of all species from the
+//   k_moments  streaming into every gas node (Eq.(33)-(36)), stored for the
+//              collision, and everything local: moments, transport, U^c,
+//              species momenta of f (Eq.(3), (5), (7)-(8), (11), (14)-(17), (25))
+//   k_collide  correction sources of all species from the
 //              node's and its face neighbours' moments, the temperatures of f
 //              and of the auxiliary state, equilibria and the trapezoidal
 //              collision (Eq.(4), (6), (12)-(13), (19)-(21), (24)); writes the
@@ -19,9 +19,9 @@
 // Populations are records of the NS species per (direction, slot),
 // [((i*nsl + slot)*NS + j]: a tap of one direction is one contiguous record
 // load that serves every species, and a wavefront of consecutive slots reads
-// consecutive records.  The streamed populations are never stored: the moments
-// and the collision kernel each rebuild them from the taps, so a step reads
-// the population array twice and writes it once.
+// consecutive records.  Only the moments kernel gathers taps; it stores the
+// streamed records in slot order, so the collision reads them as contiguous
+// records (a gather costs several times a coalesced load on this GPU).
 #pragma once
 #include <type_traits>
 
@@ -352,7 +352,7 @@ __global__ void __launch_bounds__(BLOCK) k_wall(Params<real> p, Bufs<real> b, in
 }
 
 // ===========================================================================
-// k_moments: streaming into every gas node (evaluated, not stored), the
+// k_moments: streaming into every gas node (stored for the collision), the
 // moments of the streamed populations and every local quantity of the node
 // (Eq.(3), (5), (7)-(8), (11), (14)-(17), (25)), one thread per node.
 // ===========================================================================
@@ -389,6 +389,7 @@ __global__ void __launch_bounds__(BLOCK) k_moments(Params<real> p, Bufs<real> b,
     const int cls = cls_at(cw, i);
     const Rec<real, NS> g =
         stream_rec<real, NS>(G + (size_t)i * nsl * NS, tap_slots<FAST, real, D>(b, ad, i, cls), wtab, cls);
+    strec<real, NS>(b.Gs + (size_t)i * nsl * NS, t, g);  // for the collision
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
       rho[j] += g.v[j];
@@ -585,9 +586,9 @@ struct SpeciesColl {
 
 // Collision of all species at gas slot t, computed at the source node sc and
 // stored at t.
-template <bool FAST, typename real, int D, int NS>
-__device__ inline void collide_node(const Params<real> &p, const Bufs<real> &b, int cur,
-                                      const WTab<real> &wtab, const int t, const SrcNode sc) {
+template <typename real, int D, int NS>
+__device__ inline void collide_node(const Params<real> &p, const Bufs<real> &b, int cur, const int t,
+                                    const SrcNode sc) {
   constexpr int Q = lat_q<D>();
   constexpr int NR = fr_count(D, NS), NX = fx_count(D, NS);
   const int nsl = p.nsl;
@@ -732,12 +733,9 @@ __device__ inline void collide_node(const Params<real> &p, const Bufs<real> &b, 
     for (int j = 0; j < NS; ++j) o.v[j] = g0.v[j] - sp[j].w * (g0.v[j] - sp[j].r_st) - sp[j].r_rest;
     strec<real, NS>(Gn, t, o);
   }
-  const uint64_t cw = b.scls[ss];
   static_for<1, Q>([&](auto ic_) __attribute__((always_inline)) {
     constexpr int i = decltype(ic_)::value;
-    const int cls = cls_at(cw, i);
-    const Rec<real, NS> g =
-        stream_rec<real, NS>(G + (size_t)i * nsl * NS, tap_slots<FAST, real, D>(b, ad, i, cls), wtab, cls);
+    const Rec<real, NS> g = ldrec<real, NS>(b.Gs + (size_t)i * nsl * NS, ss);
     Rec<real, NS> o;
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
@@ -797,18 +795,14 @@ __device__ inline void inlet_node(const Params<real> &p, const Bufs<real> &b, in
   });
 }
 
-// one thread per gas node, all species
-template <bool FAST, typename real, int D, int NS>
+// one thread per gas node, all species, in slot order
+template <typename real, int D, int NS>
 __global__ void __launch_bounds__(BLOCK) k_collide(Params<real> p, Bufs<real> b, int cur) {
-  __shared__ WTab<real> wtab;
-  load_wtab<real, NS>(p, wtab);
-  const int first = FAST ? 0 : p.n_gas_fast, count = FAST ? p.n_gas_fast : p.n_gas - p.n_gas_fast;
-  const int nb = (count + BLOCK - 1) / BLOCK, lb = xcd_block(nb);
+  const int nb = (p.n_gas + BLOCK - 1) / BLOCK, lb = xcd_block(nb);
   if (lb >= nb) return;  // whole block: no barrier follows for it
-  const int tl = lb * BLOCK + threadIdx.x;
+  const int t = lb * BLOCK + threadIdx.x;
   double work = 0.0;
-  if (tl < count) {
-    const int t = first + tl;
+  if (t < p.n_gas) {
     const int node = (int)b.gas_list[t];
     {
       // work of the body force on the gas at t this step, rho u.F (half the
@@ -823,10 +817,10 @@ __global__ void __launch_bounds__(BLOCK) k_collide(Params<real> p, Bufs<real> b,
       work = (double)(rt * uf);
     }
     if (b.kind[node] == KIND_INLET) inlet_node<real, D, NS>(p, b, cur, t, node);
-    else collide_node<FAST, real, D, NS>(p, b, cur, wtab, t, collision_source(p, b, node, t));
+    else collide_node<real, D, NS>(p, b, cur, t, collision_source(p, b, node, t));
   }
   const double s = block_sum(work);
-  if (threadIdx.x == 0 && s != 0.0) b.acc_work[lb + (FAST ? 0 : p.slot_off_gas)] += s;
+  if (threadIdx.x == 0 && s != 0.0) b.acc_work[lb] += s;
 }
 
 // ===========================================================================
@@ -1038,8 +1032,8 @@ inline hipError_t step_impl(const Params<real> &p, const Bufs<real> &b, int cur,
   if (ggs > 0) hipLaunchKernelGGL((k_moments<false, real, D, NS>), dim3(xcd_grid(ggs)), blk, 0, st, p, b, cur);
   mark(K_MOMENTS_ID, 1);
   mark(K_COLLIDE_ID, 0);
-  if (ggf > 0) hipLaunchKernelGGL((k_collide<true, real, D, NS>), dim3(xcd_grid(ggf)), blk, 0, st, p, b, cur);
-  if (ggs > 0) hipLaunchKernelGGL((k_collide<false, real, D, NS>), dim3(xcd_grid(ggs)), blk, 0, st, p, b, cur);
+  const int gg = (p.n_gas + BLOCK - 1) / BLOCK;
+  if (gg > 0) hipLaunchKernelGGL((k_collide<real, D, NS>), dim3(xcd_grid(gg)), blk, 0, st, p, b, cur);
   mark(K_COLLIDE_ID, 1);
   if (li.n_solid > 0) {
     const int tiles = solid_tiles<D>(p.nx, p.ny, p.nz);
