@@ -191,6 +191,51 @@ __device__ inline Rec<real, NS> stream_rec(const real *__restrict__ Gi, const Ta
   return g;
 }
 
+// Gas destinations: a gas node emits along every direction, so the class
+// search never reaches class 2 (it needs x - e and x - 2e, which would make
+// class 0 valid).  Every other class can then list its taps as (two looked-up
+// nodes, the node itself), so one of the three taps is the destination's own
+// slot: no slot lookup, and a coalesced record load across the wavefront.
+// Offsets of the two looked-up taps per class, and where each original tap
+// weight goes (original tap k -> new position, -1: the weight is 0 and the
+// original tap is dropped).
+__device__ constexpr int gas_off(int cls, int k) {
+  constexpr int off[7][2] = {{-2, -1}, {-1, 1}, {-1, -2}, {-1, -1}, {-2, -1}, {-1, -1}, {0, 0}};
+  return off[cls][k];
+}
+template <typename real, int NS>
+__device__ inline void load_wtab_gas(const Params<real> &p, WTab<real> &wt) {
+  // new tap order per class: (looked-up 0, looked-up 1, own node)
+  constexpr int src[7][3] = {{0, 1, 2}, {0, 2, 1}, {0, 1, 2}, {0, -1, 1}, {0, 1, -1}, {0, -1, -1}, {-1, -1, 0}};
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < NS; ++j)
+#pragma unroll
+      for (int c = 0; c < 7; ++c)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) wt.w[j][c][k] = src[c][k] < 0 ? real(0) : p.wint[j][c][src[c][k]];
+  }
+  __syncthreads();
+}
+template <bool FAST, typename real, int D>
+__device__ inline TapSlots gas_tap_slots(const Bufs<real> &b, const Addr<D> &ad, int i, int cls, int t) {
+  constexpr uint64_t OFF = [] {
+    uint64_t v = 0;
+    for (int c = 0; c < 7; ++c)
+      for (int k = 0; k < 2; ++k) v |= uint64_t(gas_off(c, k) + 3) << (6 * c + 3 * k);
+    return v;
+  }();
+  const int sh = 6 * cls;
+  TapSlots ts;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int o = int((OFF >> (sh + 3 * k)) & 7u) - 3;
+    ts.s[k] = ld(b.slot_of, ad.template at<FAST>(i, o));
+  }
+  ts.s[2] = t;
+  return ts;
+}
+
 // compile-time loop: f(std::integral_constant<int, I>) for I in [B, E)
 template <int B, int E, typename F>
 __device__ inline void static_for(F &&f) {
@@ -361,7 +406,7 @@ __global__ void __launch_bounds__(BLOCK) k_moments(Params<real> p, Bufs<real> b,
   constexpr int Q = lat_q<D>();
   constexpr int NR = fr_count(D, NS), NX = fx_count(D, NS);
   __shared__ WTab<real> wtab;
-  load_wtab<real, NS>(p, wtab);
+  load_wtab_gas<real, NS>(p, wtab);
   const int first = FAST ? 0 : p.n_gas_fast, count = FAST ? p.n_gas_fast : p.n_gas - p.n_gas_fast;
   const int nb = (count + BLOCK - 1) / BLOCK, lb = xcd_block(nb);
   if (lb >= nb) return;
@@ -388,7 +433,7 @@ __global__ void __launch_bounds__(BLOCK) k_moments(Params<real> p, Bufs<real> b,
     constexpr int i = decltype(ic_)::value;
     const int cls = cls_at(cw, i);
     const Rec<real, NS> g =
-        stream_rec<real, NS>(G + (size_t)i * nsl * NS, tap_slots<FAST, real, D>(b, ad, i, cls), wtab, cls);
+        stream_rec<real, NS>(G + (size_t)i * nsl * NS, gas_tap_slots<FAST, real, D>(b, ad, i, cls, t), wtab, cls);
     strec<real, NS>(b.Gs + (size_t)i * nsl * NS, t, g);  // for the collision
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
