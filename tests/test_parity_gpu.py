@@ -190,3 +190,23 @@ def test_single_species_and_no_walls(oracle_lib, fd):
                init=dict(X=[1.0], C=1.0, T=T0, Ts=T0, u=[0, 0, 0]))
     o, g = run_both(oracle_lib, fd, cfg, W.perturbed_init(cfg, 1), 50, fd.F64)
     assert_errs(field_errors(o, g, fd, 1, 3), 1e-11)
+
+
+def test_full_bed_two_steps_fp32_and_fp64(oracle_lib, fd):
+    """The full 128^3 packed bed of the throughput benchmark (same geometry,
+    chemistry and launch configuration), from a perturbed state, two steps:
+    every stored population, moment and solid temperature against the oracle
+    (FP32 at the benchmark's precision, FP64 to rounding)."""
+    mask, _ = W.sphere_pack_mask(128, radius=6.0, porosity=0.6, seed=12345, buffer=8)
+    cfg = W.packed_bed(mask=mask)
+    init = W.perturbed_init(cfg, 7, amp_u=0.005)
+    print("[parity] full bed 128^3, 2 steps", flush=True)
+    o = oracle_lib.OracleSim(cfg, init)
+    o.step(2)
+    for prec, tol, tol_rate in ((fd.F32, 1e-5, 2e-5), (fd.F64, 1e-10, 1e-10)):
+        g = fd.Sim(cfg, precision=prec, init=init)
+        g.step(2)
+        g.sync()
+        assert_errs(field_errors(o, g, fd, 5, 3), tol, tol_rate)
+        g.close()
+    o.close()
