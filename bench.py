@@ -36,7 +36,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--n", type=int, default=128, help="bed edge length (nodes)")
-    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64", "f16", "bf16"],
+                    help="f16/bf16: 16-bit population storage with FP32 arithmetic")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=128,
                     help="edge length of the bed the CPU oracle is timed on (bounded sample)")
@@ -121,8 +122,8 @@ def main():
     if args.calib_copy_mib:
         calib_copy(args.calib_copy_mib)
     cfg, init, nsph = bed(args.n)
-    prec = fdlbm.F32 if args.precision == "f32" else fdlbm.F64
-    b = 4 if prec == fdlbm.F32 else 8
+    prec = {"f32": fdlbm.F32, "f64": fdlbm.F64, "f16": fdlbm.F16, "bf16": fdlbm.BF16}[args.precision]
+    b = {"f32": 4, "f64": 8, "f16": 2, "bf16": 2}[args.precision]   # bytes per stored population
     sim = fdlbm.Sim(cfg, precision=prec, init=init)
     n_gas, n_wall, n_solid = sim.counts()
     kind = sim.field(fdlbm.FIELD_KIND).astype(np.int64)
@@ -173,7 +174,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if prec == fdlbm.F32 else "f64",
+        "dtype": "f64" if prec == fdlbm.F64 else "f32",
+        "population_storage": args.precision,
         "data": "synthetic",
         "config": {
             "workload": f"packed bed {args.n}^3 D3Q19, spheres r=6 porosity 0.6 (seed 12345), "

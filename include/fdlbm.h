@@ -62,6 +62,8 @@ extern "C" {
 #define FDLBM_D3Q19 3
 #define FDLBM_F64 0
 #define FDLBM_F32 1
+#define FDLBM_F16 2   /* populations stored as FP16 deviations from w_i rho_ref,j; FP32 arithmetic */
+#define FDLBM_BF16 3  /* populations stored as BF16 deviations from w_i rho_ref,j; FP32 arithmetic */
 
 /* correction-term switches (Sec. 3 / Sec. 4.1) */
 #define FDLBM_CORR_DIFFUSION 1u  /* diffusion-velocity correction, Eq.(11)-(13)  */
@@ -92,7 +94,9 @@ typedef struct {
   int lattice;      /* FDLBM_D2Q9 or FDLBM_D3Q19                                 */
   int nx, ny, nz;   /* grid; nz = 1 for D2Q9                                    */
   int periodic[3];  /* nonzero: axis wraps                                      */
-  int precision;    /* FDLBM_F64 or FDLBM_F32 (storage and arithmetic)          */
+  int precision;    /* FDLBM_F64, FDLBM_F32 (storage and arithmetic), or         *
+                     * FDLBM_F16 / FDLBM_BF16 (16-bit population storage, FP32   *
+                     * arithmetic and every other field FP32)                    */
   int n_species;    /* 1 .. FDLBM_MAX_SPECIES                                   */
   void *hip_stream; /* hipStream_t to run on; NULL = default stream             */
 } fdlbm_desc;
@@ -173,7 +177,11 @@ int fdlbm_bind_workspace(fdlbm_ctx *ctx, void *dev_ptr, size_t bytes);
 /* Initial state from host arrays: rho[j*n + node], u[a*n + node] (3 rows),
  * T[n], Ts[n].  Gas populations are set to f^eq (Eq.(4)); wall nodes emit
  * rho_w f^eq(1, 0, T_w) with rho_w the mean density of their gas partners.
- * Resets the step counter and the cumulative counters. */
+ * Resets the step counter and the cumulative counters.  With 16-bit storage
+ * it also fixes the reference densities rho_ref,j (mean initial density of
+ * species j over the gas nodes; kept in checkpoints); the stored value of a
+ * population is g - w_i rho_ref,j with w_i the lattice weights at rest and
+ * T = 1/3. */
 int fdlbm_init_fields(fdlbm_ctx *ctx, const double *rho, const double *u, const double *T,
                       const double *Ts);
 

@@ -39,6 +39,7 @@ struct fdlbm_ctx {
          tol = 1e-13;
   int wall_mode = 0, max_iter = 64;
   double F[3]{}, X_in[MAXS]{}, p_in = 1.0 / 3, T_in = 1.0 / 3;
+  double rho_ref[MAXS]{};  // reference densities of 16-bit storage (mean initial density)
   bool species_set = false, geometry_set = false, bound = false, initialized = false;
   // geometry
   int inout = 0;
@@ -90,7 +91,31 @@ static int set_err(fdlbm_ctx *c, int code, const char *fmt, ...) {
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+static double wlat_of(int D, int i) { return D == 2 ? wlat<2>(i) : wlat<3>(i); }
+
+// arithmetic type (moments, solid, wall arrays) and population storage type
 static size_t real_size(const fdlbm_ctx *c) { return c->d.precision == FDLBM_F64 ? 8 : 4; }
+static size_t pop_size(const fdlbm_ctx *c) {
+  return c->d.precision == FDLBM_F64 ? 8 : (c->d.precision == FDLBM_F32 ? 4 : 2);
+}
+// values per population record (species, padded to an even count for 16-bit storage)
+static int rec_count(const fdlbm_ctx *c) { return pop_size(c) == 2 ? (c->ns + 1) / 2 * 2 : c->ns; }
+
+template <typename R, typename P>
+struct PrecTag {
+  using real = R;
+  using pop = P;
+};
+// call fn(PrecTag<real, pop>{}) for the context's precision
+template <typename Fn>
+static int with_prec(const fdlbm_ctx *c, Fn &&fn) {
+  switch (c->d.precision) {
+    case FDLBM_F64: return fn(PrecTag<double, double>{});
+    case FDLBM_F16: return fn(PrecTag<float, _Float16>{});
+    case FDLBM_BF16: return fn(PrecTag<float, __bf16>{});
+    default: return fn(PrecTag<float, float>{});
+  }
+}
 
 // Workspace layout; depends on the geometry (slot counts).  Per-slot arrays
 // have stride nsl = n_gas + n_wall + 1 rounded up to 64 (the +1 is the null
@@ -106,7 +131,7 @@ static void layout(fdlbm_ctx *c) {
     o = align256(o + bytes);
     return at;
   };
-  const size_t pops = (size_t)c->ns * c->Q * nsl * b;
+  const size_t pops = (size_t)rec_count(c) * c->Q * nsl * pop_size(c);
   c->off_G[0] = take(pops);
   c->off_G[1] = take(pops);
   c->off_Gs = take(pops);
@@ -134,13 +159,13 @@ static void layout(fdlbm_ctx *c) {
   c->total = o;
 }
 
-template <typename real>
-static Bufs<real> bufs(const fdlbm_ctx *c) {
-  Bufs<real> b;
+template <typename real, typename PT>
+static Bufs<real, PT> bufs(const fdlbm_ctx *c) {
+  Bufs<real, PT> b;
   char *w = c->ws;
-  b.G[0] = (real *)(w + c->off_G[0]);
-  b.G[1] = (real *)(w + c->off_G[1]);
-  b.Gs = (real *)(w + c->off_Gs);
+  b.G[0] = (PT *)(w + c->off_G[0]);
+  b.G[1] = (PT *)(w + c->off_G[1]);
+  b.Gs = (PT *)(w + c->off_Gs);
   b.FR = (real *)(w + c->off_FR);
   b.FX = (real *)(w + c->off_FX);
   b.Ts[0] = (real *)(w + c->off_Ts[0]);
@@ -253,6 +278,7 @@ static Params<real> params(const fdlbm_ctx *c) {
   p.max_iter = c->max_iter;
   for (int a = 0; a < 3; ++a) p.F[a] = a < c->D ? (real)c->F[a] : real(0);
   p.T_in = (real)c->T_in;
+  for (int j = 0; j < c->ns; ++j) p.rho_ref[j] = (real)c->rho_ref[j];
   return p;
 }
 
@@ -376,7 +402,7 @@ int fdlbm_set_geometry(fdlbm_ctx *c, const uint8_t *mask, int inout) {
   // 2*yt*nx nodes earlier, a distance whose population traffic fits one
   // XCD's 4 MiB L2; in plain node order it would be two whole planes.
   {
-    const double per_node = 2.0 * c->Q * c->ns * (double)real_size(c);
+    const double per_node = 2.0 * c->Q * rec_count(c) * (double)pop_size(c);
     int yt = 4;
     while (yt * 2 <= c->d.ny && 2.0 * c->d.nx * (yt * 2) * per_node <= 4.0 * 1048576.0) yt *= 2;
     if (c->D == 2) yt = c->d.ny;
@@ -424,13 +450,16 @@ int fdlbm_set_geometry(fdlbm_ctx *c, const uint8_t *mask, int inout) {
   return FDLBM_OK;
 }
 
-template <typename real>
+template <typename T>
 static int copy_field(fdlbm_ctx *c, size_t off_bytes, size_t count, double *dst) {
-  std::vector<real> tmp(count);
-  HIPCHK(c, hipMemcpyAsync(tmp.data(), c->ws + off_bytes, count * sizeof(real), hipMemcpyDeviceToHost,
+  std::vector<T> tmp(count);
+  HIPCHK(c, hipMemcpyAsync(tmp.data(), c->ws + off_bytes, count * sizeof(T), hipMemcpyDeviceToHost,
                            c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  for (size_t k = 0; k < count; ++k) dst[k] = (double)tmp[k];
+  for (size_t k = 0; k < count; ++k) {
+    if constexpr (sizeof(T) == 8) dst[k] = (double)tmp[k];
+    else dst[k] = (double)(float)tmp[k];  // 16-bit types convert through float
+  }
   return FDLBM_OK;
 }
 
@@ -444,7 +473,7 @@ int fdlbm_create(const fdlbm_desc *d, fdlbm_ctx **out) {
   *out = nullptr;
   if ((d->lattice != FDLBM_D2Q9 && d->lattice != FDLBM_D3Q19) || d->nx < 1 || d->ny < 1 ||
       d->nz < 1 || (d->lattice == FDLBM_D2Q9 && d->nz != 1) || d->n_species < 1 ||
-      d->n_species > MAX_NS || (d->precision != FDLBM_F64 && d->precision != FDLBM_F32))
+      d->n_species > MAX_NS || d->precision < FDLBM_F64 || d->precision > FDLBM_BF16)
     return FDLBM_E_INVALID;
   const double nn = (double)d->nx * d->ny * d->nz;
   if (nn > 2.0e9 || nn * d->n_species * 19 > 9.0e18) return FDLBM_E_INVALID;
@@ -588,12 +617,24 @@ int fdlbm_bind_workspace(fdlbm_ctx *c, void *dev, size_t bytes) {
 }
 
 // host-side equilibrium for the initial state (same closed form as the kernels)
-template <typename real>
+template <typename real, typename PT>
 static int init_impl(fdlbm_ctx *c, const double *rho, const double *u, const double *T,
                      const double *Ts) {
   const size_t n = (size_t)c->n, nsl = (size_t)c->nsl;
-  const int Q = c->Q, ns = c->ns;
-  std::vector<real> G((size_t)ns * Q * nsl, real(0)), hT(n, real(0));
+  const int Q = c->Q, ns = c->ns, RL = rec_count(c);
+  // reference densities of 16-bit storage: mean initial density per species
+  for (int j = 0; j < ns; ++j) {
+    double sum = 0;
+    for (uint32_t node : c->gas_list) sum += rho[(size_t)j * n + node];
+    c->rho_ref[j] = sum / (double)c->gas_list.size();
+  }
+  const Params<real> pr = params<real>(c);
+  std::vector<PT> G((size_t)RL * Q * nsl, PT(0.0f));
+  std::vector<real> hT(n, real(0));
+  auto put = [&](int i, size_t slot, int j, real v) {
+    if (narrow<PT>()) v -= real(wlat_of(c->D, i)) * pr.rho_ref[j];  // as the kernels do
+    G[((size_t)i * nsl + slot) * RL + j] = PT(v);
+  };
   for (size_t node = 0; node < n; ++node) {
     hT[node] = (real)Ts[node];
     if (!gaslike(c->kind[node])) continue;
@@ -604,7 +645,7 @@ static int init_impl(fdlbm_ctx *c, const double *rho, const double *u, const dou
       const real sq = (real)std::sqrt(c->M[j]);
       if (c->D == 2) equilibrium<real, 2>((real)rho[j * n + node], sq, uu, (real)T[node], f);
       else equilibrium<real, 3>((real)rho[j * n + node], sq, uu, (real)T[node], f);
-      for (int i = 0; i < Q; ++i) G[((size_t)i * nsl + slot) * ns + j] = f[i];
+      for (int i = 0; i < Q; ++i) put(i, slot, j, f[i]);
     }
   }
   for (size_t node = 0; node < n; ++node) {
@@ -626,11 +667,11 @@ static int init_impl(fdlbm_ctx *c, const double *rho, const double *u, const dou
       }
       const real rw = (real)(sum / cnt);
       for (int i = 1; i < Q; ++i)
-        if ((c->emask[node] >> i) & 1u) G[((size_t)i * nsl + c->slot_of[node]) * ns + j] = rw * wt[i];
+        if ((c->emask[node] >> i) & 1u) put(i, (size_t)c->slot_of[node], j, rw * wt[i]);
     }
   }
   c->cur = 0;
-  HIPCHK(c, hipMemcpyAsync(c->ws + c->off_G[0], G.data(), G.size() * sizeof(real),
+  HIPCHK(c, hipMemcpyAsync(c->ws + c->off_G[0], G.data(), G.size() * sizeof(PT),
                            hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->ws + c->off_Ts[0], hT.data(), n * sizeof(real), hipMemcpyHostToDevice,
                            c->stream));
@@ -650,8 +691,10 @@ int fdlbm_init_fields(fdlbm_ctx *c, const double *rho, const double *u, const do
   if (!c) return FDLBM_E_INVALID;
   if (!c->bound || !c->species_set) return set_err(c, FDLBM_E_STATE, "bind the workspace and set species first");
   if (!rho || !u || !T || !Ts) return set_err(c, FDLBM_E_INVALID, "null argument");
-  return c->d.precision == FDLBM_F64 ? init_impl<double>(c, rho, u, T, Ts)
-                                     : init_impl<float>(c, rho, u, T, Ts);
+  return with_prec(c, [&](auto tag) {
+    using Tg = decltype(tag);
+    return init_impl<typename Tg::real, typename Tg::pop>(c, rho, u, T, Ts);
+  });
 }
 
 int fdlbm_set_profiling(fdlbm_ctx *c, int enable) {
@@ -687,17 +730,10 @@ int fdlbm_kernel_times(fdlbm_ctx *c, double *avg_ms, int64_t *launches) {
   return FDLBM_OK;
 }
 
-int fdlbm_step(fdlbm_ctx *c, int64_t n_steps) {
-  if (!c) return FDLBM_E_INVALID;
-  if (!c->initialized) return set_err(c, FDLBM_E_STATE, "initialise the fields first");
-  if (n_steps < 0) return set_err(c, FDLBM_E_INVALID, "negative step count");
-  const bool f64 = c->d.precision == FDLBM_F64;
-  Params<double> pd;
-  Params<float> pf;
-  if (f64) pd = params<double>(c);
-  else pf = params<float>(c);
-  const Bufs<double> bd = bufs<double>(c);
-  const Bufs<float> bf = bufs<float>(c);
+template <typename real, typename PT>
+static int step_impl(fdlbm_ctx *c, int64_t n_steps) {
+  const Params<real> pr = params<real>(c);
+  const Bufs<real, PT> bu = bufs<real, PT>(c);
   for (int64_t s = 0; s < n_steps; ++s) {
     LaunchInfo li;
     li.stream = c->stream;
@@ -706,8 +742,7 @@ int fdlbm_step(fdlbm_ctx *c, int64_t n_steps) {
     for (int k = 0; k < K_NUM; ++k) li.recorded[k] = false;
     if (c->prof && c->prof_launches < NPROF)
       li.events = &c->events[(size_t)c->prof_launches * K_NUM * 2];
-    hipError_t e = f64 ? launch_step<double>(c->D, pd, bd, c->cur, li)
-                       : launch_step<float>(c->D, pf, bf, c->cur, li);
+    hipError_t e = launch_step<real, PT>(c->D, pr, bu, c->cur, li);
     if (e != hipSuccess) return set_err(c, FDLBM_E_HIP, "kernel launch: %s", hipGetErrorString(e));
     if (li.events) {
       ++c->prof_launches;
@@ -719,6 +754,16 @@ int fdlbm_step(fdlbm_ctx *c, int64_t n_steps) {
   return FDLBM_OK;
 }
 
+int fdlbm_step(fdlbm_ctx *c, int64_t n_steps) {
+  if (!c) return FDLBM_E_INVALID;
+  if (!c->initialized) return set_err(c, FDLBM_E_STATE, "initialise the fields first");
+  if (n_steps < 0) return set_err(c, FDLBM_E_INVALID, "negative step count");
+  return with_prec(c, [&](auto tag) {
+    using Tg = decltype(tag);
+    return step_impl<typename Tg::real, typename Tg::pop>(c, n_steps);
+  });
+}
+
 int fdlbm_sync(fdlbm_ctx *c) {
   if (!c) return FDLBM_E_INVALID;
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -728,11 +773,13 @@ int fdlbm_sync(fdlbm_ctx *c) {
 int fdlbm_observe(fdlbm_ctx *c, fdlbm_obs *o) {
   if (!c || !o) return FDLBM_E_INVALID;
   if (!c->initialized) return set_err(c, FDLBM_E_STATE, "initialise the fields first");
-  const bool f64 = c->d.precision == FDLBM_F64;
-  hipError_t e = f64 ? launch_observe<double>(c->D, params<double>(c), bufs<double>(c), c->cur,
-                                              c->obs_blocks, c->stream)
-                     : launch_observe<float>(c->D, params<float>(c), bufs<float>(c), c->cur,
-                                             c->obs_blocks, c->stream);
+  const hipError_t e = (hipError_t)with_prec(c, [&](auto tag) {
+    using Tg = decltype(tag);
+    using real = typename Tg::real;
+    using PT = typename Tg::pop;
+    return (int)launch_observe<real, PT>(c->D, params<real>(c), bufs<real, PT>(c), c->cur, c->obs_blocks,
+                                         c->stream);
+  });
   if (e != hipSuccess) return set_err(c, FDLBM_E_HIP, "observe launch: %s", hipGetErrorString(e));
   const int NP = c->ns + 9;
   std::vector<double> part((size_t)c->obs_blocks * NP);
@@ -821,16 +868,25 @@ int fdlbm_get_field(fdlbm_ctx *c, int field, int comp, double *dst) {
     case FDLBM_FIELD_POP: {
       if (comp < 0 || comp >= c->ns) return set_err(c, FDLBM_E_INVALID, "bad species");
       const size_t nsl = (size_t)c->nsl, null_slot = c->gas_list.size() + c->wall_list.size();
-      const size_t ns = (size_t)c->ns;
-      std::vector<double> v((size_t)c->Q * nsl * ns);
-      rc = f64 ? copy_field<double>(c, c->off_G[c->cur], v.size(), v.data())
-               : copy_field<float>(c, c->off_G[c->cur], v.size(), v.data());
+      const size_t RL = (size_t)rec_count(c);
+      std::vector<double> v((size_t)c->Q * nsl * RL);
+      rc = with_prec(c, [&](auto tag) {
+        using PT = typename decltype(tag)::pop;
+        return copy_field<PT>(c, c->off_G[c->cur], v.size(), v.data());
+      });
       if (rc) return rc;
-      for (int i = 0; i < c->Q; ++i)
+      // 16-bit storage holds deviations from wlat_i rho_ref_j (offset in FP32, as the kernels)
+      // (a wall node stores nothing on the directions it does not emit along)
+      const bool dev = pop_size(c) == 2;
+      const size_t ng = c->gas_list.size();
+      for (int i = 0; i < c->Q; ++i) {
+        const double off = dev ? (double)((float)wlat_of(c->D, i) * (float)c->rho_ref[comp]) : 0.0;
         for (size_t x = 0; x < n; ++x) {
           const size_t sl = (size_t)c->slot_of[x];
-          dst[(size_t)i * n + x] = sl == null_slot ? 0.0 : v[((size_t)i * nsl + sl) * ns + comp];
+          const bool stored = sl < ng || (sl < null_slot && ((c->wem[sl - ng] >> i) & 1u));
+          dst[(size_t)i * n + x] = stored ? v[((size_t)i * nsl + sl) * RL + comp] + off : 0.0;
         }
+      }
       return FDLBM_OK;
     }
     case FDLBM_FIELD_KIND:
@@ -853,6 +909,7 @@ int fdlbm_get_field(fdlbm_ctx *c, int field, int comp, double *dst) {
 struct StateHeader {
   uint64_t magic, total, step;
   int32_t cur, pad;
+  double rho_ref[MAXS];  // reference densities of 16-bit population storage
 };
 
 int fdlbm_state_bytes(const fdlbm_ctx *c, size_t *bytes) {
@@ -865,7 +922,8 @@ int fdlbm_save_state(fdlbm_ctx *c, void *host, size_t bytes) {
   if (!c || !host) return FDLBM_E_INVALID;
   if (!c->initialized) return set_err(c, FDLBM_E_STATE, "nothing to save");
   if (bytes < sizeof(StateHeader) + c->total) return set_err(c, FDLBM_E_INVALID, "buffer too small");
-  StateHeader h{0x46444c424d535431ull, c->total, (uint64_t)c->step, c->cur, 0};
+  StateHeader h{0x46444c424d535432ull, c->total, (uint64_t)c->step, c->cur, 0, {}};
+  for (int j = 0; j < MAXS; ++j) h.rho_ref[j] = c->rho_ref[j];
   std::memcpy(host, &h, sizeof h);
   HIPCHK(c, hipMemcpyAsync((char *)host + sizeof h, c->ws, c->total, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -878,12 +936,13 @@ int fdlbm_load_state(fdlbm_ctx *c, const void *host, size_t bytes) {
   StateHeader h;
   if (bytes < sizeof h) return set_err(c, FDLBM_E_INVALID, "buffer too small");
   std::memcpy(&h, host, sizeof h);
-  if (h.magic != 0x46444c424d535431ull || h.total != c->total || bytes < sizeof h + c->total)
+  if (h.magic != 0x46444c424d535432ull || h.total != c->total || bytes < sizeof h + c->total)
     return set_err(c, FDLBM_E_INVALID, "state does not match this context");
   HIPCHK(c, hipMemcpyAsync(c->ws, (const char *)host + sizeof h, c->total, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->step = (int64_t)h.step;
   c->cur = h.cur;
+  for (int j = 0; j < MAXS; ++j) c->rho_ref[j] = h.rho_ref[j];
   c->initialized = true;
   return FDLBM_OK;
 }

@@ -104,7 +104,29 @@ struct Params {
   // flow
   real F[3];
   real rho_in[MAXS], T_in;
+  // 16-bit population storage: deviations from wlat_i rho_ref_j
+  real rho_ref[MAXS];  // reference density per species
 };
+
+// lattice weights at rest and T = 1/3 (the equilibrium of Eq.(4) at u = 0):
+// D2Q9 4/9, 1/9, 1/36; D3Q19 1/3, 1/18, 1/36
+template <int D>
+__host__ __device__ constexpr double wlat(int i) {
+  return i == 0 ? (D == 2 ? 4.0 / 9.0 : 1.0 / 3.0)
+                : (cnorm2<D>(i) == 1 ? (D == 2 ? 1.0 / 9.0 : 1.0 / 18.0) : 1.0 / 36.0);
+}
+
+// Population storage type PT: the arithmetic type itself (FP32, FP64) holds
+// the populations; a 16-bit type (FP16, BF16) holds their deviations from
+// wlat_i rho_ref_j, in records padded to an even length (4-byte aligned).
+template <typename PT>
+__host__ __device__ constexpr bool narrow() {
+  return sizeof(PT) == 2;
+}
+template <typename PT>
+__host__ __device__ constexpr int rec_len(int ns) {
+  return narrow<PT>() ? (ns + 1) / 2 * 2 : ns;
+}
 
 // Workspace pointers.  Populations and moments live in compact SLOT order:
 // gas-like nodes in processing order (slot = gas-list index), then the wall
@@ -112,10 +134,10 @@ struct Params {
 // reads; slot_of maps a node to its slot (the null slot for interior solid).
 // Populations are records of the NS species per (direction, slot), so one
 // tap is one contiguous NS-value load for every species.
-template <typename real>
+template <typename real, typename PT = real>
 struct Bufs {
-  real *G[2];         // populations [((i*nsl + slot)*NS + j], double-buffered
-  real *Gs;           // streamed (pre-collision) populations of the gas slots, same layout
+  PT *G[2];           // populations [((i*nsl + slot)*RL + j] (RL = rec_len(NS)), double-buffered
+  PT *Gs;             // streamed (pre-collision) populations of the gas slots, same layout
   real *FR;           // per-slot record read by neighbours: u, T, rho_j, tau1_j
   real *FX;           // per-slot record of the node itself: tau2_j, u_j, U^c, energy defect
   real *Ts[2];        // solid temperature per node, double-buffered

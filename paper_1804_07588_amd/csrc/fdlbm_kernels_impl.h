@@ -156,13 +156,69 @@ __device__ inline void strec(real *__restrict__ base, int rec, const Rec<real, N
   __builtin_memcpy(p, &r, sizeof r);
 }
 
+// Population records: RL = rec_len<PT>(NS) stored values per (direction,
+// slot).  For a 16-bit storage type the record is moved as 4-byte words and
+// holds deviations from wlat_i rho_ref_j; pop_load / pop_store convert to and
+// from the populations themselves.
+template <typename real, typename PT, int NS>
+__device__ inline Rec<real, NS> pop_load_raw(const PT *__restrict__ Gi, int slot) {
+  constexpr int RL = rec_len<PT>(NS);
+  Rec<real, NS> r;
+  if constexpr (narrow<PT>()) {
+    const uint32_t off = uint32_t(slot) * uint32_t(RL * sizeof(PT));
+    const uint32_t *p = reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(Gi) + off);
+    Rec<uint32_t, RL / 2> w;
+    __builtin_memcpy(&w, p, sizeof w);
+    PT h[RL];
+    __builtin_memcpy(h, &w, sizeof h);
+#pragma unroll
+    for (int j = 0; j < NS; ++j) r.v[j] = real(float(h[j]));
+  } else {
+    r = ldrec<real, NS>(Gi, slot);
+  }
+  return r;
+}
+template <typename real, typename PT, int NS>
+__device__ inline void pop_store_raw(PT *__restrict__ Gi, int slot, const Rec<real, NS> &v) {
+  constexpr int RL = rec_len<PT>(NS);
+  if constexpr (narrow<PT>()) {
+    PT h[RL];
+#pragma unroll
+    for (int j = 0; j < RL; ++j) h[j] = j < NS ? PT(float(v.v[j])) : PT(0.0f);
+    Rec<uint32_t, RL / 2> w;
+    __builtin_memcpy(&w, h, sizeof w);
+    const uint32_t off = uint32_t(slot) * uint32_t(RL * sizeof(PT));
+    uint32_t *p = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(Gi) + off);
+    __builtin_memcpy(p, &w, sizeof w);
+  } else {
+    strec<real, NS>(Gi, slot, v);
+  }
+}
+template <typename real, typename PT, int D, int NS>
+__device__ inline Rec<real, NS> pop_load(const Params<real> &p, const PT *__restrict__ Gi, int slot, int i) {
+  Rec<real, NS> r = pop_load_raw<real, PT, NS>(Gi, slot);
+  if constexpr (narrow<PT>()) {
+#pragma unroll
+    for (int j = 0; j < NS; ++j) r.v[j] += real(wlat<D>(i)) * p.rho_ref[j];
+  }
+  return r;
+}
+template <typename real, typename PT, int D, int NS>
+__device__ inline void pop_store(const Params<real> &p, PT *__restrict__ Gi, int slot, int i, Rec<real, NS> v) {
+  if constexpr (narrow<PT>()) {
+#pragma unroll
+    for (int j = 0; j < NS; ++j) v.v[j] -= real(wlat<D>(i)) * p.rho_ref[j];
+  }
+  pop_store_raw<real, PT, NS>(Gi, slot, v);
+}
+
 // Slots of the three taps of direction i for stencil class cls (0..6) around
 // the node of ad, Eq.(33)-(36).
 struct TapSlots {
   int s[3];
 };
-template <bool FAST, typename real, int D>
-__device__ inline TapSlots tap_slots(const Bufs<real> &b, const Addr<D> &ad, int i, int cls) {
+template <bool FAST, int D, typename BF>
+__device__ inline TapSlots tap_slots(const BF &b, const Addr<D> &ad, int i, int cls) {
   constexpr uint64_t OFF = pack_offsets();
   const int sh = 9 * cls;
   TapSlots t;
@@ -178,16 +234,19 @@ __device__ inline TapSlots tap_slots(const Bufs<real> &b, const Addr<D> &ad, int
 // records of direction i): the interpolant through the class's taps at each
 // species' shift.  An on-lattice species (c_j = 1) has weights exactly one 1
 // and two 0s, so it gets the upstream value unrounded.
-template <typename real, int NS>
-__device__ inline Rec<real, NS> stream_rec(const real *__restrict__ Gi, const TapSlots &t,
-                                           const WTab<real> &wt, int cls) {
-  const Rec<real, NS> r0 = ldrec<real, NS>(Gi, t.s[0]);
-  const Rec<real, NS> r1 = ldrec<real, NS>(Gi, t.s[1]);
-  const Rec<real, NS> r2 = ldrec<real, NS>(Gi, t.s[2]);
+template <typename real, typename PT, int D, int NS>
+__device__ inline Rec<real, NS> stream_rec(const Params<real> &p, const PT *__restrict__ Gi, const TapSlots &t,
+                                           const WTab<real> &wt, int cls, int i) {
+  const Rec<real, NS> r0 = pop_load_raw<real, PT, NS>(Gi, t.s[0]);
+  const Rec<real, NS> r1 = pop_load_raw<real, PT, NS>(Gi, t.s[1]);
+  const Rec<real, NS> r2 = pop_load_raw<real, PT, NS>(Gi, t.s[2]);
   Rec<real, NS> g;
 #pragma unroll
-  for (int j = 0; j < NS; ++j)
+  for (int j = 0; j < NS; ++j) {
     g.v[j] = wt.w[j][cls][0] * r0.v[j] + wt.w[j][cls][1] * r1.v[j] + wt.w[j][cls][2] * r2.v[j];
+    // the weights sum to one: deviations interpolate like the populations
+    if constexpr (narrow<PT>()) g.v[j] += real(wlat<D>(i)) * p.rho_ref[j];
+  }
   return g;
 }
 
@@ -217,8 +276,8 @@ __device__ inline void load_wtab_gas(const Params<real> &p, WTab<real> &wt) {
   }
   __syncthreads();
 }
-template <bool FAST, typename real, int D>
-__device__ inline TapSlots gas_tap_slots(const Bufs<real> &b, const Addr<D> &ad, int i, int cls, int t) {
+template <bool FAST, int D, typename BF>
+__device__ inline TapSlots gas_tap_slots(const BF &b, const Addr<D> &ad, int i, int cls, int t) {
   constexpr uint64_t OFF = [] {
     uint64_t v = 0;
     for (int c = 0; c < 7; ++c)
@@ -276,8 +335,8 @@ __device__ inline real ipow(real x, int k) {
 // ===========================================================================
 // k_wall: the reactive diffusive wall, one thread per wall node
 // ===========================================================================
-template <bool FAST, typename real, int D, int NS>
-__device__ inline double wall_node(const Params<real> &p, const Bufs<real> &b, int cur,
+template <bool FAST, typename real, typename PT, int D, int NS>
+__device__ inline double wall_node(const Params<real> &p, const Bufs<real, PT> &b, int cur,
                                    const WTab<real> &wtab, const int wi) {
   constexpr int Q = lat_q<D>();
   constexpr int NR = fr_count(D, NS);
@@ -286,8 +345,9 @@ __device__ inline double wall_node(const Params<real> &p, const Bufs<real> &b, i
   const Addr<D> ad(w, p);
   const uint64_t cw = b.scls[slot];
   const uint32_t em = b.wem[wi];
-  const real *__restrict__ G = b.G[cur];
-  real *__restrict__ Gn = b.G[cur ^ 1];
+  constexpr int RL = rec_len<PT>(NS);
+  const PT *__restrict__ G = b.G[cur];
+  PT *__restrict__ Gn = b.G[cur ^ 1];
   const int nsl = p.nsl;
   const real Tw = p.wall_mode == 1 ? p.T_iso : b.Ts[cur][w];
   real wt[Q];
@@ -306,8 +366,8 @@ __device__ inline double wall_node(const Params<real> &p, const Bufs<real> &b, i
   for (int i = 1; i < Q; ++i) {
     const int cls = cls_at(cw, i);
     if (cls == CLS_NONE) continue;  // direction i does not arrive from the gas
-    const Rec<real, NS> g = stream_rec<real, NS>(G + (size_t)i * nsl * NS,
-                                                 tap_slots<FAST, real, D>(b, ad, i, cls), wtab, cls);
+    const Rec<real, NS> g =
+        stream_rec<real, PT, D, NS>(p, G + (size_t)i * nsl * RL, tap_slots<FAST>(b, ad, i, cls), wtab, cls, i);
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
       A[j] += g.v[j];
@@ -362,7 +422,7 @@ __device__ inline double wall_node(const Params<real> &p, const Bufs<real> &b, i
       W.v[j] = rw[j] * wt[i];
       Ei += p.cj2[j] * W.v[j];
     }
-    strec<real, NS>(Gn + (size_t)i * nsl * NS, slot, W);
+    pop_store<real, PT, D, NS>(p, Gn + (size_t)i * nsl * RL, slot, i, W);
     Eout += real(cnorm2<D>(i)) * Ei;
   }
   // wall state seen by the neighbours' gradient stencils
@@ -382,8 +442,8 @@ __device__ inline double wall_node(const Params<real> &p, const Bufs<real> &b, i
 }
 
 // FAST: the node list holds only nodes whose taps never wrap a periodic axis
-template <bool FAST, typename real, int D, int NS>
-__global__ void __launch_bounds__(BLOCK) k_wall(Params<real> p, Bufs<real> b, int cur) {
+template <bool FAST, typename real, typename PT, int D, int NS>
+__global__ void __launch_bounds__(BLOCK) k_wall(Params<real> p, Bufs<real, PT> b, int cur) {
   __shared__ WTab<real> wtab;
   load_wtab<real, NS>(p, wtab);
   const int first = FAST ? 0 : p.n_wall_fast, count = FAST ? p.n_wall_fast : p.n_wall - p.n_wall_fast;
@@ -391,7 +451,7 @@ __global__ void __launch_bounds__(BLOCK) k_wall(Params<real> p, Bufs<real> b, in
   if (lb >= nb) return;  // whole block: no barrier follows for it
   const int t = lb * BLOCK + threadIdx.x;
   double r_out = 0.0;
-  if (t < count) r_out = wall_node<FAST, real, D, NS>(p, b, cur, wtab, first + t);
+  if (t < count) r_out = wall_node<FAST, real, PT, D, NS>(p, b, cur, wtab, first + t);
   const double s = block_sum(r_out);
   if (threadIdx.x == 0) b.acc_moles[lb + (FAST ? 0 : p.slot_off_wall)] += s;
 }
@@ -401,8 +461,8 @@ __global__ void __launch_bounds__(BLOCK) k_wall(Params<real> p, Bufs<real> b, in
 // moments of the streamed populations and every local quantity of the node
 // (Eq.(3), (5), (7)-(8), (11), (14)-(17), (25)), one thread per node.
 // ===========================================================================
-template <bool FAST, typename real, int D, int NS>
-__global__ void __launch_bounds__(BLOCK) k_moments(Params<real> p, Bufs<real> b, int cur) {
+template <bool FAST, typename real, typename PT, int D, int NS>
+__global__ void __launch_bounds__(BLOCK) k_moments(Params<real> p, Bufs<real, PT> b, int cur) {
   constexpr int Q = lat_q<D>();
   constexpr int NR = fr_count(D, NS), NX = fx_count(D, NS);
   __shared__ WTab<real> wtab;
@@ -416,11 +476,12 @@ __global__ void __launch_bounds__(BLOCK) k_moments(Params<real> p, Bufs<real> b,
   const int node = (int)b.gas_list[t];
   const Addr<D> ad(node, p);
   const uint64_t cw = b.scls[t];
-  const real *__restrict__ G = b.G[cur];
+  constexpr int RL = rec_len<PT>(NS);
+  const PT *__restrict__ G = b.G[cur];
   const int nsl = p.nsl;
   real rho[NS], Jg[NS][D], Es[NS];
   {
-    const Rec<real, NS> g0 = ldrec<real, NS>(G, t);  // rest population: not streamed
+    const Rec<real, NS> g0 = pop_load<real, PT, D, NS>(p, G, t, 0);  // rest population: not streamed
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
       rho[j] = g0.v[j];
@@ -432,9 +493,9 @@ __global__ void __launch_bounds__(BLOCK) k_moments(Params<real> p, Bufs<real> b,
   static_for<1, Q>([&](auto ic_) __attribute__((always_inline)) {
     constexpr int i = decltype(ic_)::value;
     const int cls = cls_at(cw, i);
-    const Rec<real, NS> g =
-        stream_rec<real, NS>(G + (size_t)i * nsl * NS, gas_tap_slots<FAST, real, D>(b, ad, i, cls, t), wtab, cls);
-    strec<real, NS>(b.Gs + (size_t)i * nsl * NS, t, g);  // for the collision
+    const Rec<real, NS> g = stream_rec<real, PT, D, NS>(p, G + (size_t)i * nsl * RL,
+                                                     gas_tap_slots<FAST>(b, ad, i, cls, t), wtab, cls, i);
+    pop_store<real, PT, D, NS>(p, b.Gs + (size_t)i * nsl * RL, t, i, g);  // for the collision
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
       rho[j] += g.v[j];
@@ -606,8 +667,8 @@ __device__ inline real eq_rest(const real *U, real T) {
 struct SrcNode {
   int node, slot;
 };
-template <typename real>
-__device__ inline SrcNode collision_source(const Params<real> &p, const Bufs<real> &b, int node, int t) {
+template <typename real, typename BF>
+__device__ inline SrcNode collision_source(const Params<real> &p, const BF &b, int node, int t) {
   // outlet rows exist only with nx >= 6, and slot_of(node) = t otherwise:
   // one unconditional load serves both cases
   const int sn = b.kind[node] == KIND_OUTLET ? node - node % p.nx + p.nx - 3 : node;
@@ -631,8 +692,8 @@ struct SpeciesColl {
 
 // Collision of all species at gas slot t, computed at the source node sc and
 // stored at t.
-template <typename real, int D, int NS>
-__device__ inline void collide_node(const Params<real> &p, const Bufs<real> &b, int cur, const int t,
+template <typename real, typename PT, int D, int NS>
+__device__ inline void collide_node(const Params<real> &p, const Bufs<real, PT> &b, int cur, const int t,
                                     const SrcNode sc) {
   constexpr int Q = lat_q<D>();
   constexpr int NR = fr_count(D, NS), NX = fx_count(D, NS);
@@ -769,18 +830,22 @@ __device__ inline void collide_node(const Params<real> &p, const Bufs<real> &b, 
     c.r_rest = c.a2 * (ps0 - pe0) + wt * (trP + e[j]) * ic2;
   }
   // ---- streaming and collision, one direction at a time ----
-  const real *__restrict__ G = b.G[cur];
-  real *__restrict__ Gn = b.G[cur ^ 1];
+  // (keep the scheduler from hoisting this phase's loads into the source
+  // phase above, where most registers are already live)
+  __builtin_amdgcn_sched_barrier(0);
+  constexpr int RL = rec_len<PT>(NS);
+  const PT *__restrict__ G = b.G[cur];
+  PT *__restrict__ Gn = b.G[cur ^ 1];
   {
-    const Rec<real, NS> g0 = ldrec<real, NS>(G, ss);  // rest: not streamed
+    const Rec<real, NS> g0 = pop_load<real, PT, D, NS>(p, G, ss, 0);  // rest: not streamed
     Rec<real, NS> o;
 #pragma unroll
     for (int j = 0; j < NS; ++j) o.v[j] = g0.v[j] - sp[j].w * (g0.v[j] - sp[j].r_st) - sp[j].r_rest;
-    strec<real, NS>(Gn, t, o);
+    pop_store<real, PT, D, NS>(p, Gn, t, 0, o);
   }
   static_for<1, Q>([&](auto ic_) __attribute__((always_inline)) {
     constexpr int i = decltype(ic_)::value;
-    const Rec<real, NS> g = ldrec<real, NS>(b.Gs + (size_t)i * nsl * NS, ss);
+    const Rec<real, NS> g = pop_load<real, PT, D, NS>(p, b.Gs + (size_t)i * nsl * RL, ss, i);
     Rec<real, NS> o;
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
@@ -804,14 +869,14 @@ __device__ inline void collide_node(const Params<real> &p, const Bufs<real> &b, 
       }
       o.v[j] = g.v[j] - c.w * (g.v[j] - c.rho * ps) - c.a2 * (ps - pe) + S;
     }
-    strec<real, NS>(Gn + (size_t)i * nsl * NS, t, o);
+    pop_store<real, PT, D, NS>(p, Gn + (size_t)i * nsl * RL, t, i, o);
   });
 }
 
 // inlet node: equilibrium at the inlet state with the velocity of the first
 // interior plane of its row (Sec. 6)
-template <typename real, int D, int NS>
-__device__ inline void inlet_node(const Params<real> &p, const Bufs<real> &b, int cur, int t,
+template <typename real, typename PT, int D, int NS>
+__device__ inline void inlet_node(const Params<real> &p, const Bufs<real, PT> &b, int cur, int t,
                                   int node) {
   constexpr int Q = lat_q<D>();
   constexpr int NR = fr_count(D, NS);
@@ -819,7 +884,8 @@ __device__ inline void inlet_node(const Params<real> &p, const Bufs<real> &b, in
   const int src = node - node % p.nx + 2;
   const bool ok = gaslike(b.kind[src]);
   const Rec<real, NR> fr = ldrec<real, NR>(b.FR, ok ? ld(b.slot_of, src) : t);
-  real *__restrict__ Gn = b.G[cur ^ 1];
+  constexpr int RL = rec_len<PT>(NS);
+  PT *__restrict__ Gn = b.G[cur ^ 1];
   real U[NS][3];
 #pragma unroll
   for (int j = 0; j < NS; ++j)
@@ -829,20 +895,22 @@ __device__ inline void inlet_node(const Params<real> &p, const Bufs<real> &b, in
     Rec<real, NS> o;
 #pragma unroll
     for (int j = 0; j < NS; ++j) o.v[j] = p.rho_in[j] * eq_rest<real, D>(U[j], p.T_in);
-    strec<real, NS>(Gn, t, o);
+    pop_store<real, PT, D, NS>(p, Gn, t, 0, o);
   }
   static_for<1, Q>([&](auto ic_) __attribute__((always_inline)) {
     constexpr int i = decltype(ic_)::value;
     Rec<real, NS> o;
 #pragma unroll
     for (int j = 0; j < NS; ++j) o.v[j] = p.rho_in[j] * eq_moving<real, D, i>(U[j], p.T_in);
-    strec<real, NS>(Gn + (size_t)i * nsl * NS, t, o);
+    pop_store<real, PT, D, NS>(p, Gn + (size_t)i * nsl * RL, t, i, o);
   });
 }
 
 // one thread per gas node, all species, in slot order
-template <typename real, int D, int NS>
-__global__ void __launch_bounds__(BLOCK) k_collide(Params<real> p, Bufs<real> b, int cur) {
+// (FP32 arithmetic: at least 2 waves per SIMD, i.e. at most 256 VGPRs; the
+// 16-bit storage variants would otherwise spill into AGPRs and run 1 wave)
+template <typename real, typename PT, int D, int NS>
+__global__ void __launch_bounds__(BLOCK, sizeof(real) == 4 ? 2 : 1) k_collide(Params<real> p, Bufs<real, PT> b, int cur) {
   const int nb = (p.n_gas + BLOCK - 1) / BLOCK, lb = xcd_block(nb);
   if (lb >= nb) return;  // whole block: no barrier follows for it
   const int t = lb * BLOCK + threadIdx.x;
@@ -861,8 +929,8 @@ __global__ void __launch_bounds__(BLOCK) k_collide(Params<real> p, Bufs<real> b,
       for (int j = 0; j < NS; ++j) rt += at.v[fr_rho(D, j)];
       work = (double)(rt * uf);
     }
-    if (b.kind[node] == KIND_INLET) inlet_node<real, D, NS>(p, b, cur, t, node);
-    else collide_node<real, D, NS>(p, b, cur, t, collision_source(p, b, node, t));
+    if (b.kind[node] == KIND_INLET) inlet_node<real, PT, D, NS>(p, b, cur, t, node);
+    else collide_node<real, PT, D, NS>(p, b, cur, t, collision_source(p, b, node, t));
   }
   const double s = block_sum(work);
   if (threadIdx.x == 0 && s != 0.0) b.acc_work[lb] += s;
@@ -871,8 +939,8 @@ __global__ void __launch_bounds__(BLOCK) k_collide(Params<real> p, Bufs<real> b,
 // ===========================================================================
 // k_solid: forward-Euler heat step over an LDS tile with a one-node halo
 // ===========================================================================
-template <typename real, int D>
-__global__ void __launch_bounds__(BLOCK) k_solid(Params<real> p, Bufs<real> b, int cur) {
+template <typename real, typename PT, int D>
+__global__ void __launch_bounds__(BLOCK) k_solid(Params<real> p, Bufs<real, PT> b, int cur) {
   constexpr int TX = SolidTile<D>::TX, TY = SolidTile<D>::TY, TZ = SolidTile<D>::TZ;
   constexpr int HX = TX + 2, HY = TY + 2, HZ = D == 3 ? TZ + 2 : 1;
   __shared__ real sT[HZ * HY * HX];
@@ -958,8 +1026,8 @@ __global__ void __launch_bounds__(BLOCK) k_solid(Params<real> p, Bufs<real> b, i
 // mass; then e_gas, e_solid, T_min, T_max, u_max, rho_min, Ts_min, Ts_max,
 // bad.  Gas and wall populations are read per slot, the solid per node.
 // ===========================================================================
-template <typename real, int D, int NS>
-__global__ void __launch_bounds__(BLOCK) k_observe(Params<real> p, Bufs<real> b, int cur) {
+template <typename real, typename PT, int D, int NS>
+__global__ void __launch_bounds__(BLOCK) k_observe(Params<real> p, Bufs<real, PT> b, int cur) {
   constexpr int Q = lat_q<D>();
   constexpr int NP = NS + 9;
   constexpr int S_EG = NS, S_ES = NS + 1, S_TMIN = NS + 2, S_TMAX = NS + 3, S_UMAX = NS + 4,
@@ -971,7 +1039,8 @@ __global__ void __launch_bounds__(BLOCK) k_observe(Params<real> p, Bufs<real> b,
   acc[S_EG] = acc[S_ES] = acc[S_UMAX] = acc[S_BAD] = 0.0;
   acc[S_TMIN] = acc[S_RMIN] = acc[S_TSMIN] = 1e300;
   acc[S_TMAX] = acc[S_TSMAX] = -1e300;
-  const real *G = b.G[cur];
+  constexpr int RL = rec_len<PT>(NS);
+  const PT *G = b.G[cur];
   const int n = p.n, nsl = p.nsl;
   const int gid = blockIdx.x * BLOCK + threadIdx.x, stride = gridDim.x * BLOCK;
   for (int node = gid; node < n; node += stride) {
@@ -995,10 +1064,10 @@ __global__ void __launch_bounds__(BLOCK) k_observe(Params<real> p, Bufs<real> b,
     }
     for (int i = 0; i < Q; ++i) {
       if (!(em & (1u << i))) continue;
-      const real *rec = G + ((size_t)i * nsl + s) * NS;
+      const Rec<real, NS> rec = pop_load<real, PT, D, NS>(p, G + (size_t)i * nsl * RL, s, i);
 #pragma unroll
       for (int j = 0; j < NS; ++j) {
-        const double gv = (double)rec[j];
+        const double gv = (double)rec.v[j];
         if (!isfinite(gv)) acc[S_BAD] = 1.0;
         rj[j] += gv;
         Ej[j] += (double)cnorm2<D>(i) * gv;
@@ -1055,8 +1124,8 @@ __global__ void __launch_bounds__(BLOCK) k_observe(Params<real> p, Bufs<real> b,
 // ===========================================================================
 // launchers
 // ===========================================================================
-template <typename real, int D, int NS>
-inline hipError_t step_impl(const Params<real> &p, const Bufs<real> &b, int cur,
+template <typename real, typename PT, int D, int NS>
+inline hipError_t step_impl(const Params<real> &p, const Bufs<real, PT> &b, int cur,
                             LaunchInfo &li) {
   const int gwf = (p.n_wall_fast + BLOCK - 1) / BLOCK, gws = (p.n_wall - p.n_wall_fast + BLOCK - 1) / BLOCK;
   const int ggf = (p.n_gas_fast + BLOCK - 1) / BLOCK, ggs = (p.n_gas - p.n_gas_fast + BLOCK - 1) / BLOCK;
@@ -1069,54 +1138,54 @@ inline hipError_t step_impl(const Params<real> &p, const Bufs<real> &b, int cur,
   };
   const dim3 blk(BLOCK);
   mark(K_WALL_ID, 0);
-  if (gwf > 0) hipLaunchKernelGGL((k_wall<true, real, D, NS>), dim3(xcd_grid(gwf)), blk, 0, st, p, b, cur);
-  if (gws > 0) hipLaunchKernelGGL((k_wall<false, real, D, NS>), dim3(xcd_grid(gws)), blk, 0, st, p, b, cur);
+  if (gwf > 0) hipLaunchKernelGGL((k_wall<true, real, PT, D, NS>), dim3(xcd_grid(gwf)), blk, 0, st, p, b, cur);
+  if (gws > 0) hipLaunchKernelGGL((k_wall<false, real, PT, D, NS>), dim3(xcd_grid(gws)), blk, 0, st, p, b, cur);
   mark(K_WALL_ID, 1);
   mark(K_MOMENTS_ID, 0);
-  if (ggf > 0) hipLaunchKernelGGL((k_moments<true, real, D, NS>), dim3(xcd_grid(ggf)), blk, 0, st, p, b, cur);
-  if (ggs > 0) hipLaunchKernelGGL((k_moments<false, real, D, NS>), dim3(xcd_grid(ggs)), blk, 0, st, p, b, cur);
+  if (ggf > 0) hipLaunchKernelGGL((k_moments<true, real, PT, D, NS>), dim3(xcd_grid(ggf)), blk, 0, st, p, b, cur);
+  if (ggs > 0) hipLaunchKernelGGL((k_moments<false, real, PT, D, NS>), dim3(xcd_grid(ggs)), blk, 0, st, p, b, cur);
   mark(K_MOMENTS_ID, 1);
   mark(K_COLLIDE_ID, 0);
   const int gg = (p.n_gas + BLOCK - 1) / BLOCK;
-  if (gg > 0) hipLaunchKernelGGL((k_collide<real, D, NS>), dim3(xcd_grid(gg)), blk, 0, st, p, b, cur);
+  if (gg > 0) hipLaunchKernelGGL((k_collide<real, PT, D, NS>), dim3(xcd_grid(gg)), blk, 0, st, p, b, cur);
   mark(K_COLLIDE_ID, 1);
   if (li.n_solid > 0) {
     const int tiles = solid_tiles<D>(p.nx, p.ny, p.nz);
     mark(K_SOLID_ID, 0);
-    hipLaunchKernelGGL((k_solid<real, D>), dim3(tiles), blk, 0, st, p, b, cur);
+    hipLaunchKernelGGL((k_solid<real, PT, D>), dim3(tiles), blk, 0, st, p, b, cur);
     mark(K_SOLID_ID, 1);
   }
   return hipGetLastError();
 }
 
-template <typename real, int D, int NS>
-inline hipError_t observe_impl(const Params<real> &p, const Bufs<real> &b, int cur, int blocks,
+template <typename real, typename PT, int D, int NS>
+inline hipError_t observe_impl(const Params<real> &p, const Bufs<real, PT> &b, int cur, int blocks,
                                hipStream_t st) {
-  hipLaunchKernelGGL((k_observe<real, D, NS>), dim3(blocks), dim3(BLOCK), 0, st, p, b, cur);
+  hipLaunchKernelGGL((k_observe<real, PT, D, NS>), dim3(blocks), dim3(BLOCK), 0, st, p, b, cur);
   return hipGetLastError();
 }
 
 // species-count dispatch for one (precision, lattice); FDLBM_NS_CASES lists
 // the species counts this translation unit instantiates
-template <typename real, int D>
-hipError_t step_lat(const Params<real> &p, const Bufs<real> &b, int cur, LaunchInfo &li) {
+template <typename real, typename PT, int D>
+hipError_t step_lat(const Params<real> &p, const Bufs<real, PT> &b, int cur, LaunchInfo &li) {
   switch (p.ns) {
 #define FDLBM_CASE(k) \
   case k:             \
-    return step_impl<real, D, k>(p, b, cur, li);
+    return step_impl<real, PT, D, k>(p, b, cur, li);
     FDLBM_NS_CASES
 #undef FDLBM_CASE
   }
   return hipErrorInvalidValue;
 }
 
-template <typename real, int D>
-hipError_t observe_lat(const Params<real> &p, const Bufs<real> &b, int cur, int blocks,
+template <typename real, typename PT, int D>
+hipError_t observe_lat(const Params<real> &p, const Bufs<real, PT> &b, int cur, int blocks,
                        hipStream_t st) {
   switch (p.ns) {
 #define FDLBM_CASE(k) \
   case k:             \
-    return observe_impl<real, D, k>(p, b, cur, blocks, st);
+    return observe_impl<real, PT, D, k>(p, b, cur, blocks, st);
     FDLBM_NS_CASES
 #undef FDLBM_CASE
   }

@@ -16,26 +16,27 @@ struct LaunchInfo {
   bool recorded[K_NUM];  // set by the launcher for the ids it recorded
 };
 
-// one time step on lattice D: wall, moments, collide (with inlet/outlet), solid
-template <typename real, int D>
-hipError_t step_lat(const Params<real> &p, const Bufs<real> &b, int cur, LaunchInfo &li);
+// one time step on lattice D: wall, moments, collide (with inlet/outlet),
+// solid; real = arithmetic type, PT = population storage type
+template <typename real, typename PT, int D>
+hipError_t step_lat(const Params<real> &p, const Bufs<real, PT> &b, int cur, LaunchInfo &li);
 
 // observables: writes (ns + 9) doubles per block into b.partials
-template <typename real, int D>
-hipError_t observe_lat(const Params<real> &p, const Bufs<real> &b, int cur, int blocks,
+template <typename real, typename PT, int D>
+hipError_t observe_lat(const Params<real> &p, const Bufs<real, PT> &b, int cur, int blocks,
                        hipStream_t st);
 
-template <typename real>
-inline hipError_t launch_step(int D, const Params<real> &p, const Bufs<real> &b, int cur,
+template <typename real, typename PT>
+inline hipError_t launch_step(int D, const Params<real> &p, const Bufs<real, PT> &b, int cur,
                               LaunchInfo &li) {
-  return D == 2 ? step_lat<real, 2>(p, b, cur, li) : step_lat<real, 3>(p, b, cur, li);
+  return D == 2 ? step_lat<real, PT, 2>(p, b, cur, li) : step_lat<real, PT, 3>(p, b, cur, li);
 }
 
-template <typename real>
-inline hipError_t launch_observe(int D, const Params<real> &p, const Bufs<real> &b, int cur,
+template <typename real, typename PT>
+inline hipError_t launch_observe(int D, const Params<real> &p, const Bufs<real, PT> &b, int cur,
                                  int blocks, hipStream_t st) {
-  return D == 2 ? observe_lat<real, 2>(p, b, cur, blocks, st)
-                : observe_lat<real, 3>(p, b, cur, blocks, st);
+  return D == 2 ? observe_lat<real, PT, 2>(p, b, cur, blocks, st)
+                : observe_lat<real, PT, 3>(p, b, cur, blocks, st);
 }
 
 }  // namespace fdlbm

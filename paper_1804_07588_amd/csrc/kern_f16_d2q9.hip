@@ -1,0 +1,10 @@
+// Kernel instantiations: FP16 population storage (deviations), float arithmetic on the D2Q9 lattice.
+#define FDLBM_NS_CASES FDLBM_CASE(1) FDLBM_CASE(2) FDLBM_CASE(3) FDLBM_CASE(4) FDLBM_CASE(5) FDLBM_CASE(6)
+#include "fdlbm_kernels_impl.h"
+
+namespace fdlbm {
+template hipError_t step_lat<float, _Float16, 2>(const Params<float> &, const Bufs<float, _Float16> &, int,
+                                          LaunchInfo &);
+template hipError_t observe_lat<float, _Float16, 2>(const Params<float> &, const Bufs<float, _Float16> &, int,
+                                             int, hipStream_t);
+}  // namespace fdlbm

@@ -1,10 +1,10 @@
-// Kernel instantiations for float storage on the D3Q19 lattice.
+// Kernel instantiations: float storage and arithmetic on the D3Q19 lattice.
 #define FDLBM_NS_CASES FDLBM_CASE(1) FDLBM_CASE(2) FDLBM_CASE(3) FDLBM_CASE(4) FDLBM_CASE(5) FDLBM_CASE(6)
 #include "fdlbm_kernels_impl.h"
 
 namespace fdlbm {
-template hipError_t step_lat<float, 3>(const Params<float> &, const Bufs<float> &, int,
-                                        LaunchInfo &);
-template hipError_t observe_lat<float, 3>(const Params<float> &, const Bufs<float> &, int, int,
-                                           hipStream_t);
+template hipError_t step_lat<float, float, 3>(const Params<float> &, const Bufs<float, float> &, int,
+                                          LaunchInfo &);
+template hipError_t observe_lat<float, float, 3>(const Params<float> &, const Bufs<float, float> &, int,
+                                             int, hipStream_t);
 }  // namespace fdlbm

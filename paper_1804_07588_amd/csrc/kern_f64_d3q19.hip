@@ -1,10 +1,10 @@
-// Kernel instantiations for double storage on the D3Q19 lattice.
+// Kernel instantiations: double storage and arithmetic on the D3Q19 lattice.
 #define FDLBM_NS_CASES FDLBM_CASE(1) FDLBM_CASE(2) FDLBM_CASE(3) FDLBM_CASE(4) FDLBM_CASE(5) FDLBM_CASE(6)
 #include "fdlbm_kernels_impl.h"
 
 namespace fdlbm {
-template hipError_t step_lat<double, 3>(const Params<double> &, const Bufs<double> &, int,
-                                        LaunchInfo &);
-template hipError_t observe_lat<double, 3>(const Params<double> &, const Bufs<double> &, int, int,
-                                           hipStream_t);
+template hipError_t step_lat<double, double, 3>(const Params<double> &, const Bufs<double, double> &, int,
+                                          LaunchInfo &);
+template hipError_t observe_lat<double, double, 3>(const Params<double> &, const Bufs<double, double> &, int,
+                                             int, hipStream_t);
 }  // namespace fdlbm

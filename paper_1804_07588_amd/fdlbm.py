@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libfdlbm.so")
 # constants mirrored from include/fdlbm.h
 OK, E_INVALID, E_GEOMETRY, E_ALIGN, E_HIP, E_UNSTABLE, E_STATE = 0, -1, -2, -3, -4, -5, -6
 D2Q9, D3Q19 = 2, 3
-F64, F32 = 0, 1
+F64, F32, F16, BF16 = 0, 1, 2, 3  # F16/BF16: 16-bit population storage, FP32 arithmetic
 CORR_DIFFUSION, CORR_VISCOUS, CORR_ENERGY, CORR_PRANDTL, CORR_ALL = 1, 2, 4, 8, 15
 WALL_REACTIVE, WALL_ISOTHERMAL = 0, 1
 FIELD_RHO, FIELD_U, FIELD_T, FIELD_TS, FIELD_POP, FIELD_KIND, FIELD_WALL_R, FIELD_WALL_DE = range(8)
