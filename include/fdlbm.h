@@ -62,8 +62,8 @@ extern "C" {
 #define FDLBM_D3Q19 3
 #define FDLBM_F64 0
 #define FDLBM_F32 1
-#define FDLBM_F16 2   /* populations stored as FP16 deviations from w_i rho_ref,j; FP32 arithmetic */
-#define FDLBM_BF16 3  /* populations stored as BF16 deviations from w_i rho_ref,j; FP32 arithmetic */
+#define FDLBM_F16 2   /* populations stored as FP16 g/rho_ref,j - w_i; FP32 arithmetic */
+#define FDLBM_BF16 3  /* populations stored as BF16 g/rho_ref,j - w_i; FP32 arithmetic */
 
 /* correction-term switches (Sec. 3 / Sec. 4.1) */
 #define FDLBM_CORR_DIFFUSION 1u  /* diffusion-velocity correction, Eq.(11)-(13)  */
@@ -179,9 +179,11 @@ int fdlbm_bind_workspace(fdlbm_ctx *ctx, void *dev_ptr, size_t bytes);
  * rho_w f^eq(1, 0, T_w) with rho_w the mean density of their gas partners.
  * Resets the step counter and the cumulative counters.  With 16-bit storage
  * it also fixes the reference densities rho_ref,j (mean initial density of
- * species j over the gas nodes; kept in checkpoints); the stored value of a
- * population is g - w_i rho_ref,j with w_i the lattice weights at rest and
- * T = 1/3. */
+ * species j over the gas nodes, floored at 1e-12 of the total; kept in
+ * checkpoints); the stored value of a population is g / rho_ref,j - w_i with
+ * w_i the lattice weights at rest and T = 1/3.  FP16 overflows (the state
+ * turns non-finite and fdlbm_observe reports it) if a species grows beyond
+ * about 6e4 times its reference density. */
 int fdlbm_init_fields(fdlbm_ctx *ctx, const double *rho, const double *u, const double *T,
                       const double *Ts);
 

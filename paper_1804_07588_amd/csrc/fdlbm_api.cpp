@@ -278,7 +278,10 @@ static Params<real> params(const fdlbm_ctx *c) {
   p.max_iter = c->max_iter;
   for (int a = 0; a < 3; ++a) p.F[a] = a < c->D ? (real)c->F[a] : real(0);
   p.T_in = (real)c->T_in;
-  for (int j = 0; j < c->ns; ++j) p.rho_ref[j] = (real)c->rho_ref[j];
+  for (int j = 0; j < c->ns; ++j) {
+    p.rho_ref[j] = (real)c->rho_ref[j];
+    p.inv_rho_ref[j] = (real)(1.0 / c->rho_ref[j]);
+  }
   return p;
 }
 
@@ -623,16 +626,20 @@ static int init_impl(fdlbm_ctx *c, const double *rho, const double *u, const dou
   const size_t n = (size_t)c->n, nsl = (size_t)c->nsl;
   const int Q = c->Q, ns = c->ns, RL = rec_count(c);
   // reference densities of 16-bit storage: mean initial density per species
+  // (floored at 1e-12 of the mean total density so that it can be inverted)
+  double tot = 0;
   for (int j = 0; j < ns; ++j) {
     double sum = 0;
     for (uint32_t node : c->gas_list) sum += rho[(size_t)j * n + node];
     c->rho_ref[j] = sum / (double)c->gas_list.size();
+    tot += c->rho_ref[j];
   }
+  for (int j = 0; j < ns; ++j) c->rho_ref[j] = std::max(c->rho_ref[j], 1e-12 * tot);
   const Params<real> pr = params<real>(c);
   std::vector<PT> G((size_t)RL * Q * nsl, PT(0.0f));
   std::vector<real> hT(n, real(0));
   auto put = [&](int i, size_t slot, int j, real v) {
-    if (narrow<PT>()) v -= real(wlat_of(c->D, i)) * pr.rho_ref[j];  // as the kernels do
+    if (narrow<PT>()) v = v * pr.inv_rho_ref[j] - real(wlat_of(c->D, i));  // as the kernels do
     G[((size_t)i * nsl + slot) * RL + j] = PT(v);
   };
   for (size_t node = 0; node < n; ++node) {
@@ -875,16 +882,18 @@ int fdlbm_get_field(fdlbm_ctx *c, int field, int comp, double *dst) {
         return copy_field<PT>(c, c->off_G[c->cur], v.size(), v.data());
       });
       if (rc) return rc;
-      // 16-bit storage holds deviations from wlat_i rho_ref_j (offset in FP32, as the kernels)
-      // (a wall node stores nothing on the directions it does not emit along)
+      // 16-bit storage holds g / rho_ref_j - wlat_i (decoded in FP32, as the kernels);
+      // a wall node stores nothing on the directions it does not emit along
       const bool dev = pop_size(c) == 2;
       const size_t ng = c->gas_list.size();
+      const float rref = (float)c->rho_ref[comp];
       for (int i = 0; i < c->Q; ++i) {
-        const double off = dev ? (double)((float)wlat_of(c->D, i) * (float)c->rho_ref[comp]) : 0.0;
+        const float wl = (float)wlat_of(c->D, i);
         for (size_t x = 0; x < n; ++x) {
           const size_t sl = (size_t)c->slot_of[x];
           const bool stored = sl < ng || (sl < null_slot && ((c->wem[sl - ng] >> i) & 1u));
-          dst[(size_t)i * n + x] = stored ? v[((size_t)i * nsl + sl) * RL + comp] + off : 0.0;
+          const double raw = stored ? v[((size_t)i * nsl + sl) * RL + comp] : 0.0;
+          dst[(size_t)i * n + x] = !stored ? 0.0 : (dev ? (double)(((float)raw + wl) * rref) : raw);
         }
       }
       return FDLBM_OK;

@@ -104,8 +104,8 @@ struct Params {
   // flow
   real F[3];
   real rho_in[MAXS], T_in;
-  // 16-bit population storage: deviations from wlat_i rho_ref_j
-  real rho_ref[MAXS];  // reference density per species
+  // 16-bit population storage: relative deviations g / rho_ref_j - wlat_i
+  real rho_ref[MAXS], inv_rho_ref[MAXS];  // reference density per species
 };
 
 // lattice weights at rest and T = 1/3 (the equilibrium of Eq.(4) at u = 0):
@@ -117,8 +117,10 @@ __host__ __device__ constexpr double wlat(int i) {
 }
 
 // Population storage type PT: the arithmetic type itself (FP32, FP64) holds
-// the populations; a 16-bit type (FP16, BF16) holds their deviations from
-// wlat_i rho_ref_j, in records padded to an even length (4-byte aligned).
+// the populations; a 16-bit type (FP16, BF16) holds their relative deviations
+// from the rest equilibrium at the reference density, g / rho_ref_j - wlat_i
+// (O(0.01 - 1) for every species, inside FP16's normal range), in records
+// padded to an even length (4-byte aligned).
 template <typename PT>
 __host__ __device__ constexpr bool narrow() {
   return sizeof(PT) == 2;

@@ -158,8 +158,8 @@ __device__ inline void strec(real *__restrict__ base, int rec, const Rec<real, N
 
 // Population records: RL = rec_len<PT>(NS) stored values per (direction,
 // slot).  For a 16-bit storage type the record is moved as 4-byte words and
-// holds deviations from wlat_i rho_ref_j; pop_load / pop_store convert to and
-// from the populations themselves.
+// holds relative deviations g / rho_ref_j - wlat_i; pop_load / pop_store
+// convert to and from the populations themselves.
 template <typename real, typename PT, int NS>
 __device__ inline Rec<real, NS> pop_load_raw(const PT *__restrict__ Gi, int slot) {
   constexpr int RL = rec_len<PT>(NS);
@@ -199,7 +199,7 @@ __device__ inline Rec<real, NS> pop_load(const Params<real> &p, const PT *__rest
   Rec<real, NS> r = pop_load_raw<real, PT, NS>(Gi, slot);
   if constexpr (narrow<PT>()) {
 #pragma unroll
-    for (int j = 0; j < NS; ++j) r.v[j] += real(wlat<D>(i)) * p.rho_ref[j];
+    for (int j = 0; j < NS; ++j) r.v[j] = (r.v[j] + real(wlat<D>(i))) * p.rho_ref[j];
   }
   return r;
 }
@@ -207,7 +207,7 @@ template <typename real, typename PT, int D, int NS>
 __device__ inline void pop_store(const Params<real> &p, PT *__restrict__ Gi, int slot, int i, Rec<real, NS> v) {
   if constexpr (narrow<PT>()) {
 #pragma unroll
-    for (int j = 0; j < NS; ++j) v.v[j] -= real(wlat<D>(i)) * p.rho_ref[j];
+    for (int j = 0; j < NS; ++j) v.v[j] = v.v[j] * p.inv_rho_ref[j] - real(wlat<D>(i));
   }
   pop_store_raw<real, PT, NS>(Gi, slot, v);
 }
@@ -245,7 +245,7 @@ __device__ inline Rec<real, NS> stream_rec(const Params<real> &p, const PT *__re
   for (int j = 0; j < NS; ++j) {
     g.v[j] = wt.w[j][cls][0] * r0.v[j] + wt.w[j][cls][1] * r1.v[j] + wt.w[j][cls][2] * r2.v[j];
     // the weights sum to one: deviations interpolate like the populations
-    if constexpr (narrow<PT>()) g.v[j] += real(wlat<D>(i)) * p.rho_ref[j];
+    if constexpr (narrow<PT>()) g.v[j] = (g.v[j] + real(wlat<D>(i))) * p.rho_ref[j];
   }
   return g;
 }

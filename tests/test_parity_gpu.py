@@ -192,18 +192,22 @@ def test_single_species_and_no_walls(oracle_lib, fd):
     assert_errs(field_errors(o, g, fd, 1, 3), 1e-11)
 
 
-def test_full_bed_two_steps_fp32_and_fp64(oracle_lib, fd):
+def test_full_bed_two_steps_all_precisions(oracle_lib, fd):
     """The full 128^3 packed bed of the throughput benchmark (same geometry,
     chemistry and launch configuration), from a perturbed state, two steps:
     every stored population, moment and solid temperature against the oracle
-    (FP32 at the benchmark's precision, FP64 to rounding)."""
+    (FP32 at the benchmark's precision, FP64 to rounding, and the 16-bit
+    storage modes with their stated bounds)."""
     mask, _ = W.sphere_pack_mask(128, radius=6.0, porosity=0.6, seed=12345, buffer=8)
     cfg = W.packed_bed(mask=mask)
     init = W.perturbed_init(cfg, 7, amp_u=0.005)
     print("[parity] full bed 128^3, 2 steps", flush=True)
     o = oracle_lib.OracleSim(cfg, init)
     o.step(2)
-    for prec, tol, tol_rate in ((fd.F32, 1e-5, 2e-5), (fd.F64, 1e-10, 1e-10)):
+    # 16-bit storage: one rounding of a few-percent deviation already costs
+    # ~1e-4 (FP16, 11-bit significand) or ~1e-3 (BF16, 8-bit) of a density
+    for prec, tol, tol_rate in ((fd.F32, 1e-5, 2e-5), (fd.F64, 1e-10, 1e-10), (fd.F16, 5e-4, 5e-4),
+                                (fd.BF16, 5e-3, 5e-3)):
         g = fd.Sim(cfg, precision=prec, init=init)
         g.step(2)
         g.sync()
