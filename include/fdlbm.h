@@ -130,7 +130,8 @@ const char *fdlbm_last_error(const fdlbm_ctx *ctx);
  * gas, 1 = solid, copied.  Wall nodes are the solid nodes with a gas node
  * among their lattice neighbours.  inout = 1 turns the planes x = 0, 1 into
  * inlet nodes (equilibrium at the inlet state, Sec. 6) and x = nx-2, nx-1
- * into outlet nodes (zero-gradient copy of x = nx-3); x must then be
+ * into outlet nodes (equilibrium at the inlet pressure with the mole
+ * fractions, temperature and velocity of x = nx-3); x must then be
  * non-periodic, those planes gas and x = nx-3 gas wherever the outlet is.
  * FDLBM_E_GEOMETRY if no gas node exists, a gas node touches a closed domain
  * edge or an outlet row has no interior gas node to copy. */
@@ -195,6 +196,16 @@ int fdlbm_sync(fdlbm_ctx *ctx);
 
 /* Synchronise and reduce the observables (FP64, deterministic order). */
 int fdlbm_observe(fdlbm_ctx *ctx, fdlbm_obs *out);
+
+/* Steady-state residual (the convergence test of the time-to-steady-state
+ * measurement): for each field group q -- mole fractions X_j and temperature
+ * and velocity at the gas nodes, solid temperature -- r_q = ||q(t) - q(s)||_2
+ * / ((t - s) ||q(t)||_2) with s the step of the previous call, then a new
+ * snapshot is taken.  r5[0..3] = X, T, u, T^s; r5[4] = their maximum.  The
+ * first call after fdlbm_init_fields or fdlbm_load_state (no snapshot yet)
+ * returns +inf.  Synchronises the stream.  FDLBM_E_STATE before the first
+ * step. */
+int fdlbm_residual(fdlbm_ctx *ctx, double *r5);
 
 /* Copy a field into dst_host (double): n values, or Q*n for FDLBM_FIELD_POP.
  * RHO/U/T are the moments of f of the last step at gas nodes (the wall state

@@ -507,6 +507,10 @@ int oracle_set_geometry(oracle_sim *s, const uint8_t *mask, int inout) {
       s->kind[node] = K_SOLID;
     }
   }
+  /* the outlet takes the state of the last interior plane: it must be gas */
+  for (int node = 0; node < s->n; ++node)
+    if (s->kind[node] == K_OUTLET && s->kind[node - node % s->nx + s->nx - 3] != K_GAS)
+      return fail(s, "an outlet row has no gas node at x = nx - 3");
   int n_gas = 0;
   for (int node = 0; node < s->n; ++node) {
     if (gaslike(s, node)) {
@@ -1097,7 +1101,11 @@ static void solid(oracle_sim *s) {
 }
 
 /* 7. inlet (equilibrium at the prescribed state, velocity of the first
- * interior plane) and outlet (zero-gradient copy), reading for Sec. 6 */
+ * interior plane) and outlet, reading for Sec. 6: equilibrium at the inlet
+ * pressure with the mole fractions, temperature and velocity of the last
+ * interior plane (zero gradient of those; a zero-gradient copy of the whole
+ * state would leave the outlet pressure free, and a body-force-driven flow
+ * then drains the domain and accelerates without bound). */
 static void inlet_outlet(oracle_sim *s) {
   if (!s->inout) return;
   int n = s->n, Q = s->Q, nx = s->nx;
@@ -1117,10 +1125,18 @@ static void inlet_outlet(oracle_sim *s) {
         }
       }
       int last = node_of(s, nx - 3, y, z);
+      double ul[3], Cl = 0.0, Tl = s->T[last];
+      for (int a = 0; a < 3; ++a) ul[a] = s->u[(size_t)a * n + last];
+      for (int j = 0; j < s->ns; ++j) Cl += s->rho[(size_t)j * n + last] / s->M[j];
+      double Cout = s->p_in / Tl;
       for (int xg = nx - 2; xg < nx; ++xg) {
         int g = node_of(s, xg, y, z);
-        for (int j = 0; j < s->ns; ++j)
-          for (int i = 0; i < Q; ++i) *pop(s, s->Gn, j, i, g) = *pop(s, s->Gn, j, i, last);
+        for (int j = 0; j < s->ns; ++j) {
+          double Xj = s->rho[(size_t)j * n + last] / s->M[j] / Cl;
+          double f[MAXQ];
+          equilibrium(s->D, Q, s->c, s->M[j] * Xj * Cout, s->M[j], ul, Tl, f);
+          for (int i = 0; i < Q; ++i) *pop(s, s->Gn, j, i, g) = f[i];
+        }
       }
     }
 }

@@ -59,7 +59,9 @@ struct fdlbm_ctx {
   size_t ws_bytes = 0;
   size_t off_G[2]{}, off_Gs = 0, off_FR = 0, off_FX = 0, off_Ts[2]{}, off_wr = 0, off_wde = 0, off_kind = 0, off_slot = 0,
          off_scls = 0, off_wem = 0, off_gl = 0, off_wl = 0, off_am = 0, off_aw = 0, off_ab = 0,
-         off_part = 0;
+         off_part = 0, off_snap = 0, off_snapts = 0;
+  bool snap_valid = false;  // a residual snapshot exists
+  int64_t snap_step = 0;    // step of the snapshot
   size_t total = 0;
   int acc_slots = 0, obs_blocks = 0;
   int cur = 0;
@@ -156,6 +158,8 @@ static void layout(fdlbm_ctx *c) {
   c->off_ab = take((size_t)c->acc_slots * 8);
   c->obs_blocks = 1024;
   c->off_part = take((size_t)c->obs_blocks * (MAXS + 9) * 8);
+  c->off_snap = take((size_t)sn_count(c->D, c->ns) * nsl * b);
+  c->off_snapts = take(n * b);
   c->total = o;
 }
 
@@ -182,6 +186,8 @@ static Bufs<real, PT> bufs(const fdlbm_ctx *c) {
   b.acc_work = (double *)(w + c->off_aw);
   b.acc_bheat = (double *)(w + c->off_ab);
   b.partials = (double *)(w + c->off_part);
+  b.snap = (real *)(w + c->off_snap);
+  b.snap_ts = (real *)(w + c->off_snapts);
   return b;
 }
 
@@ -278,6 +284,7 @@ static Params<real> params(const fdlbm_ctx *c) {
   p.max_iter = c->max_iter;
   for (int a = 0; a < 3; ++a) p.F[a] = a < c->D ? (real)c->F[a] : real(0);
   p.T_in = (real)c->T_in;
+  p.p_in = (real)c->p_in;
   for (int j = 0; j < c->ns; ++j) {
     p.rho_ref[j] = (real)c->rho_ref[j];
     p.inv_rho_ref[j] = (real)(1.0 / c->rho_ref[j]);
@@ -690,6 +697,7 @@ static int init_impl(fdlbm_ctx *c, const double *rho, const double *u, const dou
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->step = 0;
   c->initialized = true;
+  c->snap_valid = false;
   return FDLBM_OK;
 }
 
@@ -829,6 +837,39 @@ int fdlbm_observe(fdlbm_ctx *c, fdlbm_obs *o) {
   return FDLBM_OK;
 }
 
+int fdlbm_residual(fdlbm_ctx *c, double *r5) {
+  if (!c || !r5) return FDLBM_E_INVALID;
+  if (!c->initialized || c->step == 0) return set_err(c, FDLBM_E_STATE, "the residual needs a completed step");
+  const hipError_t e = (hipError_t)with_prec(c, [&](auto tag) {
+    using Tg = decltype(tag);
+    using real = typename Tg::real;
+    using PT = typename Tg::pop;
+    return (int)launch_residual<real, PT>(c->D, params<real>(c), bufs<real, PT>(c), c->cur, c->obs_blocks,
+                                          c->stream);
+  });
+  if (e != hipSuccess) return set_err(c, FDLBM_E_HIP, "residual launch: %s", hipGetErrorString(e));
+  std::vector<double> part((size_t)c->obs_blocks * 8);
+  HIPCHK(c, hipMemcpyAsync(part.data(), c->ws + c->off_part, part.size() * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double sums[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int bk = 0; bk < c->obs_blocks; ++bk)
+    for (int k = 0; k < 8; ++k) sums[k] += part[(size_t)bk * 8 + k];
+  const double K = (double)(c->step - c->snap_step);
+  double rmax = 0;
+  for (int g = 0; g < 4; ++g) {
+    double r;
+    if (!c->snap_valid || K <= 0) r = HUGE_VAL;
+    else if (sums[2 * g] == 0.0) r = 0.0;
+    else r = sums[2 * g + 1] > 0.0 ? std::sqrt(sums[2 * g]) / (K * std::sqrt(sums[2 * g + 1])) : HUGE_VAL;
+    r5[g] = r;
+    rmax = std::max(rmax, r);
+  }
+  r5[4] = rmax;
+  c->snap_valid = true;
+  c->snap_step = c->step;
+  return FDLBM_OK;
+}
+
 int fdlbm_get_field(fdlbm_ctx *c, int field, int comp, double *dst) {
   if (!c || !dst) return FDLBM_E_INVALID;
   if (!c->initialized) return set_err(c, FDLBM_E_STATE, "initialise the fields first");
@@ -952,6 +993,7 @@ int fdlbm_load_state(fdlbm_ctx *c, const void *host, size_t bytes) {
   c->step = (int64_t)h.step;
   c->cur = h.cur;
   for (int j = 0; j < MAXS; ++j) c->rho_ref[j] = h.rho_ref[j];
+  c->snap_valid = false;
   c->initialized = true;
   return FDLBM_OK;
 }

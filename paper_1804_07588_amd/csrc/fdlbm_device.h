@@ -103,7 +103,7 @@ struct Params {
   int max_iter;
   // flow
   real F[3];
-  real rho_in[MAXS], T_in;
+  real rho_in[MAXS], T_in, p_in;
   // 16-bit population storage: relative deviations g / rho_ref_j - wlat_i
   real rho_ref[MAXS], inv_rho_ref[MAXS];  // reference density per species
 };
@@ -154,8 +154,13 @@ struct Bufs {
   double *acc_moles;  // per-block cumulative reaction extent
   double *acc_work;   // per-block cumulative body-force work
   double *acc_bheat;  // per-block cumulative Dirichlet-face heat
-  double *partials;   // observe reduction partials
+  double *partials;   // observe / residual reduction partials
+  real *snap;         // residual snapshot per gas slot: X_j, T, u_a (sn_count values)
+  real *snap_ts;      // residual snapshot of the solid temperature per node
 };
+
+// values per gas slot in the residual snapshot: mole fractions, T, u
+__host__ __device__ constexpr int sn_count(int D, int ns) { return ns + 1 + D; }
 
 // Field records per slot, grouped so that a kernel working on one species
 // loads only that species' values.  FR (what the face neighbours' gradient

@@ -662,18 +662,11 @@ __device__ inline real eq_rest(const real *U, real T) {
   }
 }
 
-// the node whose collision a gas node stores: an outlet node takes the last
-// interior node of its row (zero-gradient outlet), every other node itself
+// the collision's source node: the node itself (inlet and outlet nodes are
+// set to equilibria instead)
 struct SrcNode {
   int node, slot;
 };
-template <typename real, typename BF>
-__device__ inline SrcNode collision_source(const Params<real> &p, const BF &b, int node, int t) {
-  // outlet rows exist only with nx >= 6, and slot_of(node) = t otherwise:
-  // one unconditional load serves both cases
-  const int sn = b.kind[node] == KIND_OUTLET ? node - node % p.nx + p.nx - 3 : node;
-  return {sn, ld(b.slot_of, sn)};
-}
 
 // Per-species constants of the collision at one node, for Eq.(24) in its
 // difference form g+ = g - w (g - rho P*) - w (tau1/tau2) rho (P* - P^eq) +
@@ -690,8 +683,7 @@ struct SpeciesColl {
   real r_st, r_rest;          // rest population: rho P*_0 and a2 (P*_0 - P^eq_0) - w tau1 S_0
 };
 
-// Collision of all species at gas slot t, computed at the source node sc and
-// stored at t.
+// Collision of all species at gas slot t (node sc.node, slot sc.slot == t).
 template <typename real, typename PT, int D, int NS>
 __device__ inline void collide_node(const Params<real> &p, const Bufs<real, PT> &b, int cur, const int t,
                                     const SrcNode sc) {
@@ -906,6 +898,47 @@ __device__ inline void inlet_node(const Params<real> &p, const Bufs<real, PT> &b
   });
 }
 
+// outlet node: equilibrium at the inlet pressure with the mole fractions,
+// temperature and velocity of the last interior plane of its row (Sec. 6; a
+// copy of the whole state would leave the outlet pressure free, and a
+// body-force-driven flow would drain the domain)
+template <typename real, typename PT, int D, int NS>
+__device__ inline void outlet_node(const Params<real> &p, const Bufs<real, PT> &b, int cur, int t,
+                                   int node) {
+  constexpr int Q = lat_q<D>();
+  constexpr int NR = fr_count(D, NS);
+  constexpr int RL = rec_len<PT>(NS);
+  const int nsl = p.nsl;
+  const int src = node - node % p.nx + p.nx - 3;  // gas (checked with the geometry)
+  const Rec<real, NR> fr = ldrec<real, NR>(b.FR, ld(b.slot_of, src));
+  const real T = fr.v[fr_T(D)];
+  real C = 0;
+#pragma unroll
+  for (int j = 0; j < NS; ++j) C += fr.v[fr_rho(D, j)] * p.invM[j];
+  const real scale = p.p_in / (T * C);  // rho_j -> M_j X_j p_in / T
+  PT *__restrict__ Gn = b.G[cur ^ 1];
+  real U[NS][3], rj[NS];
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    rj[j] = fr.v[fr_rho(D, j)] * scale;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) U[j][a] = a < D ? p.sqM[j] * fr.v[fr_u(a)] : real(0);
+  }
+  {
+    Rec<real, NS> o;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) o.v[j] = rj[j] * eq_rest<real, D>(U[j], T);
+    pop_store<real, PT, D, NS>(p, Gn, t, 0, o);
+  }
+  static_for<1, Q>([&](auto ic_) __attribute__((always_inline)) {
+    constexpr int i = decltype(ic_)::value;
+    Rec<real, NS> o;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) o.v[j] = rj[j] * eq_moving<real, D, i>(U[j], T);
+    pop_store<real, PT, D, NS>(p, Gn + (size_t)i * nsl * RL, t, i, o);
+  });
+}
+
 // one thread per gas node, all species, in slot order
 // (FP32 arithmetic: at least 2 waves per SIMD, i.e. at most 256 VGPRs; the
 // 16-bit storage variants would otherwise spill into AGPRs and run 1 wave)
@@ -929,8 +962,10 @@ __global__ void __launch_bounds__(BLOCK, sizeof(real) == 4 ? 2 : 1) k_collide(Pa
       for (int j = 0; j < NS; ++j) rt += at.v[fr_rho(D, j)];
       work = (double)(rt * uf);
     }
-    if (b.kind[node] == KIND_INLET) inlet_node<real, PT, D, NS>(p, b, cur, t, node);
-    else collide_node<real, PT, D, NS>(p, b, cur, t, collision_source(p, b, node, t));
+    const uint8_t k = b.kind[node];
+    if (k == KIND_INLET) inlet_node<real, PT, D, NS>(p, b, cur, t, node);
+    else if (k == KIND_OUTLET) outlet_node<real, PT, D, NS>(p, b, cur, t, node);
+    else collide_node<real, PT, D, NS>(p, b, cur, t, SrcNode{node, t});
   }
   const double s = block_sum(work);
   if (threadIdx.x == 0 && s != 0.0) b.acc_work[lb] += s;
@@ -1122,6 +1157,62 @@ __global__ void __launch_bounds__(BLOCK) k_observe(Params<real> p, Bufs<real, PT
 }
 
 // ===========================================================================
+// k_residual: change of the fields since the last snapshot, for the steady-
+// state test.  FP64 partial sums per block over the gas slots (mole fractions
+// X_j, temperature, velocity) and the solid nodes (T^s): sum (q - q_snap)^2
+// and sum q^2 per group, 8 values per block; then the snapshot is replaced.
+// ===========================================================================
+template <typename real, typename PT, int D, int NS>
+__global__ void __launch_bounds__(BLOCK) k_residual(Params<real> p, Bufs<real, PT> b, int cur) {
+  constexpr int NR = fr_count(D, NS), NSN = sn_count(D, NS);
+  __shared__ double sh[8][BLOCK];
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const int gid = blockIdx.x * BLOCK + threadIdx.x, stride = gridDim.x * BLOCK;
+  for (int t = gid; t < p.n_gas; t += stride) {
+    const Rec<real, NR> fr = ldrec<real, NR>(b.FR, t);
+    Rec<real, NSN> q;
+    real C = 0;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) C += fr.v[fr_rho(D, j)] * p.invM[j];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) q.v[j] = fr.v[fr_rho(D, j)] * p.invM[j] / C;
+    q.v[NS] = fr.v[fr_T(D)];
+#pragma unroll
+    for (int a = 0; a < D; ++a) q.v[NS + 1 + a] = fr.v[fr_u(a)];
+    const Rec<real, NSN> o = ldrec<real, NSN>(b.snap, t);
+#pragma unroll
+    for (int k = 0; k < NSN; ++k) {
+      const int g = k < NS ? 0 : (k == NS ? 1 : 2);
+      const double d = (double)q.v[k] - (double)o.v[k];
+      acc[2 * g] += d * d;
+      acc[2 * g + 1] += (double)q.v[k] * (double)q.v[k];
+    }
+    strec<real, NSN>(b.snap, t, q);
+  }
+  for (int node = gid; node < p.n; node += stride) {
+    const uint8_t k = b.kind[node];
+    if (!(k == KIND_SOLID || k == KIND_WALL)) continue;
+    const real ts = b.Ts[cur][node];
+    const double d = (double)ts - (double)b.snap_ts[node];
+    acc[6] += d * d;
+    acc[7] += (double)ts * (double)ts;
+    b.snap_ts[node] = ts;
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) sh[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int s = BLOCK / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) b.partials[(size_t)blockIdx.x * 8 + k] = sh[k][0];
+}
+
+// ===========================================================================
 // launchers
 // ===========================================================================
 template <typename real, typename PT, int D, int NS>
@@ -1159,6 +1250,13 @@ inline hipError_t step_impl(const Params<real> &p, const Bufs<real, PT> &b, int 
 }
 
 template <typename real, typename PT, int D, int NS>
+inline hipError_t residual_impl(const Params<real> &p, const Bufs<real, PT> &b, int cur, int blocks,
+                                hipStream_t st) {
+  hipLaunchKernelGGL((k_residual<real, PT, D, NS>), dim3(blocks), dim3(BLOCK), 0, st, p, b, cur);
+  return hipGetLastError();
+}
+
+template <typename real, typename PT, int D, int NS>
 inline hipError_t observe_impl(const Params<real> &p, const Bufs<real, PT> &b, int cur, int blocks,
                                hipStream_t st) {
   hipLaunchKernelGGL((k_observe<real, PT, D, NS>), dim3(blocks), dim3(BLOCK), 0, st, p, b, cur);
@@ -1173,6 +1271,19 @@ hipError_t step_lat(const Params<real> &p, const Bufs<real, PT> &b, int cur, Lau
 #define FDLBM_CASE(k) \
   case k:             \
     return step_impl<real, PT, D, k>(p, b, cur, li);
+    FDLBM_NS_CASES
+#undef FDLBM_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename real, typename PT, int D>
+hipError_t residual_lat(const Params<real> &p, const Bufs<real, PT> &b, int cur, int blocks,
+                        hipStream_t st) {
+  switch (p.ns) {
+#define FDLBM_CASE(k) \
+  case k:             \
+    return residual_impl<real, PT, D, k>(p, b, cur, blocks, st);
     FDLBM_NS_CASES
 #undef FDLBM_CASE
   }

@@ -26,6 +26,18 @@ template <typename real, typename PT, int D>
 hipError_t observe_lat(const Params<real> &p, const Bufs<real, PT> &b, int cur, int blocks,
                        hipStream_t st);
 
+// residual of the steady-state test: 8 doubles per block into b.partials
+template <typename real, typename PT, int D>
+hipError_t residual_lat(const Params<real> &p, const Bufs<real, PT> &b, int cur, int blocks,
+                        hipStream_t st);
+
+template <typename real, typename PT>
+inline hipError_t launch_residual(int D, const Params<real> &p, const Bufs<real, PT> &b, int cur,
+                                  int blocks, hipStream_t st) {
+  return D == 2 ? residual_lat<real, PT, 2>(p, b, cur, blocks, st)
+                : residual_lat<real, PT, 3>(p, b, cur, blocks, st);
+}
+
 template <typename real, typename PT>
 inline hipError_t launch_step(int D, const Params<real> &p, const Bufs<real, PT> &b, int cur,
                               LaunchInfo &li) {

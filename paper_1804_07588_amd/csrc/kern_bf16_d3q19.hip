@@ -7,4 +7,6 @@ template hipError_t step_lat<float, __bf16, 3>(const Params<float> &, const Bufs
                                           LaunchInfo &);
 template hipError_t observe_lat<float, __bf16, 3>(const Params<float> &, const Bufs<float, __bf16> &, int,
                                              int, hipStream_t);
+template hipError_t residual_lat<float, __bf16, 3>(const Params<float> &, const Bufs<float, __bf16> &, int, int,
+                                           hipStream_t);
 }  // namespace fdlbm

@@ -7,4 +7,6 @@ template hipError_t step_lat<float, _Float16, 2>(const Params<float> &, const Bu
                                           LaunchInfo &);
 template hipError_t observe_lat<float, _Float16, 2>(const Params<float> &, const Bufs<float, _Float16> &, int,
                                              int, hipStream_t);
+template hipError_t residual_lat<float, _Float16, 2>(const Params<float> &, const Bufs<float, _Float16> &, int, int,
+                                           hipStream_t);
 }  // namespace fdlbm

@@ -7,4 +7,6 @@ template hipError_t step_lat<float, float, 3>(const Params<float> &, const Bufs<
                                           LaunchInfo &);
 template hipError_t observe_lat<float, float, 3>(const Params<float> &, const Bufs<float, float> &, int,
                                              int, hipStream_t);
+template hipError_t residual_lat<float, float, 3>(const Params<float> &, const Bufs<float, float> &, int, int,
+                                           hipStream_t);
 }  // namespace fdlbm

@@ -7,4 +7,6 @@ template hipError_t step_lat<double, double, 3>(const Params<double> &, const Bu
                                           LaunchInfo &);
 template hipError_t observe_lat<double, double, 3>(const Params<double> &, const Bufs<double, double> &, int,
                                              int, hipStream_t);
+template hipError_t residual_lat<double, double, 3>(const Params<double> &, const Bufs<double, double> &, int, int,
+                                           hipStream_t);
 }  // namespace fdlbm

@@ -31,7 +31,7 @@ EXPORTS = ["fdlbm_create", "fdlbm_destroy", "fdlbm_last_error", "fdlbm_set_geome
            "fdlbm_workspace_bytes", "fdlbm_bind_workspace", "fdlbm_init_fields", "fdlbm_step",
            "fdlbm_sync", "fdlbm_observe", "fdlbm_get_field", "fdlbm_state_bytes",
            "fdlbm_save_state", "fdlbm_load_state", "fdlbm_set_profiling", "fdlbm_kernel_times",
-           "fdlbm_counts"]
+           "fdlbm_counts", "fdlbm_residual"]
 
 
 class FdlbmError(RuntimeError):
@@ -97,6 +97,7 @@ def lib() -> ct.CDLL:
         L.fdlbm_set_profiling.argtypes = [vp, ct.c_int]
         L.fdlbm_kernel_times.argtypes = [vp, dp, ct.POINTER(i64)]
         L.fdlbm_counts.argtypes = [vp, ct.POINTER(i64), ct.POINTER(i64), ct.POINTER(i64)]
+        L.fdlbm_residual.argtypes = [vp, dp]
         _lib = L
     return _lib
 
@@ -205,6 +206,13 @@ class Sim:
     def load_state(self, data: bytes):
         buf = ct.create_string_buffer(data, len(data))
         self._check(lib().fdlbm_load_state(self.h, buf, len(data)))
+
+    def residual(self) -> dict:
+        """Steady-state residual since the previous call (inf on the first):
+        per field group X, T, u, Ts and their maximum."""
+        r = np.zeros(5)
+        self._check(lib().fdlbm_residual(self.h, _d(r)))
+        return dict(X=r[0], T=r[1], u=r[2], Ts=r[3], max=r[4])
 
     def set_profiling(self, on: bool):
         self._check(lib().fdlbm_set_profiling(self.h, 1 if on else 0))

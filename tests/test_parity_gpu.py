@@ -241,3 +241,34 @@ def test_16bit_storage_errors(oracle_lib, fd, prec_name):
         errs = field_errors(o, g, fd, ns, D)
         print(prec_name, name, flush=True)
         assert_errs(errs, BOUNDS_16[(prec_name, name)])
+
+
+def test_residual_matches_field_differences(fd):
+    """fdlbm_residual against the same definition evaluated from exported
+    fields: r_q = ||q(t) - q(s)|| / ((t - s) ||q(t)||) for X_j, T, u (gas
+    nodes) and T^s (solid nodes)."""
+    cfg = small_bed(n=20)
+    g = fd.Sim(cfg, precision=fd.F64, init=W.perturbed_init(cfg, 4, amp_u=0.005))
+    kind = g.field(fd.FIELD_KIND)
+    gas = (kind == 0) | (kind >= 3)
+    solid = (kind == 1) | (kind == 2)
+    M = np.asarray(cfg["species"]["M"])
+
+    def fields():
+        rho = np.stack([g.field(fd.FIELD_RHO, j) for j in range(len(M))])
+        C = (rho / M[:, None]).sum(0)
+        X = (rho / M[:, None])[:, gas] / C[gas]
+        u = np.stack([g.field(fd.FIELD_U, a) for a in range(3)])[:, gas]
+        return dict(X=X, T=g.field(fd.FIELD_T)[gas], u=u, Ts=g.field(fd.FIELD_TS)[solid])
+
+    g.step(3)
+    assert np.isinf(g.residual()["max"])
+    a = fields()
+    g.step(10)
+    r = g.residual()
+    b = fields()
+    for k in ("X", "T", "u", "Ts"):
+        ref = np.linalg.norm(b[k] - a[k]) / (10 * np.linalg.norm(b[k]))
+        assert r[k] == pytest.approx(ref, rel=1e-9, abs=1e-300), k
+    assert r["max"] == max(r["X"], r["T"], r["u"], r["Ts"])
+    g.close()
