@@ -58,7 +58,7 @@ def slab_mask(nx: int, ny: int, solid_lo: int, solid_hi: int, nz: int = 1) -> np
 
 def sphere_pack_mask(n: int = 128, radius: float = 6.0, porosity: float = 0.6,
                      seed: int = 12345, buffer: int = 8, ny: int | None = None,
-                     nz: int | None = None) -> tuple[np.ndarray, int]:
+                     nz: int | None = None, fill_closed: bool = True) -> tuple[np.ndarray, int]:
     """Random overlapping spheres in a box of n (x) by ny by nz nodes.
 
     Sphere centres are i.i.d. uniform over the bed x in [buffer, n-buffer),
@@ -67,6 +67,8 @@ def sphere_pack_mask(n: int = 128, radius: float = 6.0, porosity: float = 0.6,
     <= radius**2, with y and z periodic and x clipped to the bed.  Spheres are
     added until the gas fraction of the bed region drops to `porosity` or below.
     The `buffer` planes at both x ends stay gas (inlet / outlet buffers).
+    With `fill_closed`, gas cavities with no lattice path to the inlet plane
+    are then filled (fill_closed_pores).
     Returns (mask[nz, ny, nx], number of spheres placed).
     """
     ny = n if ny is None else ny
@@ -100,7 +102,73 @@ def sphere_pack_mask(n: int = 128, radius: float = 6.0, porosity: float = 0.6,
         placed += 1
         if (bed_nodes - solid) / bed_nodes <= porosity:
             break
+    if fill_closed:
+        m = fill_closed_pores(m, periodic=(0, 1, 1))
     return m, placed
+
+
+def _link_offsets(dims: int) -> list[tuple[int, int, int]]:
+    """(dz, dy, dx) of the D2Q9 / D3Q19 links: face and edge neighbours."""
+    out = []
+    rng = (-1, 0, 1)
+    for dz in (rng if dims == 3 else (0,)):
+        for dy in rng:
+            for dx in rng:
+                k = abs(dx) + abs(dy) + abs(dz)
+                if 0 < k <= 2:
+                    out.append((dz, dy, dx))
+    return out
+
+
+def fill_closed_pores(mask: np.ndarray, periodic=(0, 1, 1)) -> np.ndarray:
+    """Turn gas that no lattice path joins to the x = 0 plane into solid.
+
+    Connectivity is that of the lattice links (face and edge neighbours, the
+    D3Q19 / D2Q9 velocity set), across the periodic y / z faces where
+    `periodic` (x, y, z flags) says so.  Closed cavities, often single nodes
+    walled in by overlapping spheres, exchange nothing with the flow; they are
+    standard pore-space preprocessing debris, so they are removed.
+    """
+    from scipy import ndimage
+
+    nz, ny, nx = mask.shape
+    dims = 2 if nz == 1 else 3
+    gas = mask == 0
+    st = ndimage.generate_binary_structure(3, 2)
+    if dims == 2:
+        st[0] = False
+        st[2] = False
+    lab, nl = ndimage.label(gas, structure=st)
+    parent = np.arange(nl + 1)
+
+    def find(a: int) -> int:
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    # links that wrap across a periodic face join labels the plain labelling split
+    for dz, dy, dx in _link_offsets(dims):
+        nb = np.roll(lab, shift=(-dz, -dy, -dx), axis=(0, 1, 2))
+        ok = (lab > 0) & (nb > 0) & (lab != nb)
+        for ax, d, per, size in ((2, dx, periodic[0], nx), (1, dy, periodic[1], ny),
+                                 (0, dz, periodic[2], nz)):
+            if d != 0 and not per:
+                idx = [slice(None)] * 3
+                idx[ax] = size - 1 if d > 0 else 0
+                ok[tuple(idx)] = False
+        for a, b in set(zip(lab[ok].tolist(), nb[ok].tolist())):
+            ra, rb = find(a), find(b)
+            if ra != rb:
+                parent[max(ra, rb)] = min(ra, rb)
+    roots = np.array([find(a) for a in range(nl + 1)])
+    keep = np.zeros(nl + 1, dtype=bool)
+    keep[np.unique(roots[lab[:, :, 0][lab[:, :, 0] > 0]])] = True
+    keep[0] = False
+    open_gas = keep[roots[lab]]
+    out = mask.copy()
+    out[gas & ~open_gas] = 1
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -155,7 +223,7 @@ WGS_M = [14.0, 9.0, 22.0, 1.0, 14.0]
 
 def packed_bed(n: int = 128, radius: float = 6.0, porosity: float = 0.6,
                seed: int = 12345, buffer: int = 8, mask: np.ndarray | None = None,
-               k0: float = 1e-3, force: float = 2e-5, mu_scale: float = 0.0218,
+               k0: float = 1e-3, force: float = 1e-5, mu_scale: float = 0.0218,
                d_scale: float = 0.0471, trace: float = 1e-4) -> dict:
     """3-D D3Q19 packed bed with water-gas-shift chemistry on the sphere surfaces.
 
