@@ -236,6 +236,72 @@ int fdlbm_kernel_times(fdlbm_ctx *ctx, double *avg_ms, int64_t *launches);
  * solid (incl. wall). */
 int fdlbm_counts(const fdlbm_ctx *ctx, int64_t *n_gas, int64_t *n_wall, int64_t *n_solid);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent samples (contexts) advanced together.  Every
+ * launch of a step serves all active samples at once: a persistent grid of
+ * workgroups walks a device work list of (sample, block) pairs, so samples
+ * of uneven size share the GPU without a launch per sample, and runs of
+ * steps replay a captured HIP graph.  The physics of each sample is exactly
+ * that of fdlbm_step on its own context (the same kernels per node and the
+ * same per-block accumulation order, so the results are bitwise equal).
+ * Members must be initialised, share lattice, species count, precision and
+ * stream, and keep their workspaces bound while the batch lives.  Parameters
+ * changed on a member after fdlbm_batch_bind_workspace take effect at the
+ * next fdlbm_batch_set_active.  Each member's own calls (observe, residual,
+ * get_field, save/load) keep working between batch steps; fdlbm_step on a
+ * member while it is active in a batch is a call-order error the library
+ * does not detect (the batch would then launch with the wrong parity).
+ * ------------------------------------------------------------------------ */
+typedef struct fdlbm_batch fdlbm_batch;
+
+/* launch kinds of a batched step (persistent grids are set per kind) */
+#define FDLBM_BL_WALL_FAST 0  /* wall nodes whose taps never wrap          */
+#define FDLBM_BL_WALL_SLOW 1  /* wall nodes near a periodic face           */
+#define FDLBM_BL_GAS_FAST 2   /* streaming + moments, no periodic wrap     */
+#define FDLBM_BL_GAS_SLOW 3   /* streaming + moments near a periodic face  */
+#define FDLBM_BL_COLLIDE 4    /* sources + collision + inlet/outlet        */
+#define FDLBM_BL_SOLID 5      /* solid heat step                           */
+#define FDLBM_BL_COUNT 6
+
+/* Group n contexts (array copied; the contexts stay owned by the caller and
+ * must outlive the batch).  All samples start active. */
+int fdlbm_batch_create(fdlbm_ctx *const *ctxs, int n, fdlbm_batch **out);
+void fdlbm_batch_destroy(fdlbm_batch *b);
+const char *fdlbm_batch_last_error(const fdlbm_batch *b);
+
+/* Caller-allocated device workspace (per-sample parameter and buffer tables,
+ * work lists), >= fdlbm_batch_workspace_bytes, 256-byte aligned, kept alive
+ * until destroy.  Binding uploads the tables (synchronises the stream). */
+int fdlbm_batch_workspace_bytes(const fdlbm_batch *b, size_t *bytes);
+int fdlbm_batch_bind_workspace(fdlbm_batch *b, void *dev_ptr, size_t bytes);
+
+/* active[n]: nonzero = the sample advances in fdlbm_batch_step, zero = its
+ * state is frozen (e.g. converged).  Re-uploads parameters and work lists;
+ * synchronises the stream.  Captured graphs stay valid (the kernels read the
+ * list lengths from device memory). */
+int fdlbm_batch_set_active(fdlbm_batch *b, const uint8_t *active);
+
+/* Advance every active sample by n_steps: whole runs of graph_steps steps
+ * replay a captured graph (captured on first use per parity), the rest are
+ * launched directly (all of them on the NULL stream, which cannot be
+ * captured).  Asynchronous on the stream; updates the members' step
+ * counters. */
+int fdlbm_batch_step(fdlbm_batch *b, int64_t n_steps);
+
+/* Persistent grid per launch kind (FDLBM_BL_COUNT values, positive multiples
+ * of 8 workgroups; NULL keeps them) and steps per captured graph (even, > 0;
+ * 0 keeps it).  Drops captured graphs. */
+int fdlbm_batch_set_grid(fdlbm_batch *b, const int *grid, int graph_steps);
+int fdlbm_batch_get_grid(const fdlbm_batch *b, int *grid, int *graph_steps);
+
+/* Autotuner of the launch shapes: for each candidate grid (256 ... 16384
+ * workgroups, capped at one workgroup per block of work), every launch kind
+ * is timed with HIP events over `steps` steps after one warm-up step, and each
+ * kind keeps its fastest grid (written to grid_out[FDLBM_BL_COUNT] if not
+ * NULL).  The tuning steps are real steps of the active samples (their step
+ * counters advance).  Synchronises the stream. */
+int fdlbm_batch_autotune(fdlbm_batch *b, int steps, int *grid_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -998,3 +998,364 @@ int fdlbm_load_state(fdlbm_ctx *c, const void *host, size_t bytes) {
   return FDLBM_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// batches: many contexts advanced by shared persistent launches
+// ---------------------------------------------------------------------------
+struct fdlbm_batch {
+  std::vector<fdlbm_ctx *> ctx;
+  int n = 0, D = 3, ns = 1, precision = FDLBM_F32;
+  hipStream_t stream = nullptr;
+  std::string err;
+  char *ws = nullptr;
+  size_t ws_bytes = 0, total = 0;
+  size_t p_size = 0, b_size = 0;
+  size_t off_params = 0, off_bufs = 0, off_count = 0, off_items[BL_NUM]{};
+  int max_items[BL_NUM]{};
+  int n_items[BL_NUM]{};
+  int grid[BL_NUM]{};
+  std::vector<uint8_t> active;
+  std::vector<char> h_params, h_bufs;        // host images (kept alive for async uploads)
+  std::vector<int2> h_items[BL_NUM];
+  int h_count[BL_NUM]{};
+  int cur = 0;                               // parity the kernels are launched with
+  int graph_steps = 20;
+  hipGraphExec_t exec[2] = {nullptr, nullptr};  // one per starting parity
+  bool bound = false;
+};
+
+static int bset_err(fdlbm_batch *b, int code, const char *fmt, ...) {
+  if (b) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    b->err = buf;
+  }
+  return code;
+}
+
+#define BHIPCHK(b, call)                                                                   \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess) return bset_err(b, FDLBM_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+static void batch_drop_graphs(fdlbm_batch *b) {
+  for (auto &e : b->exec) {
+    if (e) (void)hipGraphExecDestroy(e);
+    e = nullptr;
+  }
+}
+
+// logical blocks of each launch kind for one context
+static void batch_blocks(const fdlbm_ctx *c, int nbk[BL_NUM]) {
+  auto nb = [](int64_t cnt) { return (int)((cnt + BLOCK - 1) / BLOCK); };
+  const int64_t ng = (int64_t)c->gas_list.size(), nw = (int64_t)c->wall_list.size();
+  nbk[BL_WALL_FAST] = nb(c->n_wall_fast);
+  nbk[BL_WALL_SLOW] = nb(nw - c->n_wall_fast);
+  nbk[BL_GAS_FAST] = nb(c->n_gas_fast);
+  nbk[BL_GAS_SLOW] = nb(ng - c->n_gas_fast);
+  nbk[BL_COLLIDE] = nb(ng);
+  nbk[BL_SOLID] = c->n_solid > 0 ? (c->D == 2 ? solid_tiles<2>(c->d.nx, c->d.ny, c->d.nz)
+                                              : solid_tiles<3>(c->d.nx, c->d.ny, c->d.nz))
+                                 : 0;
+}
+
+static int round8(int v) { return (v + 7) / 8 * 8; }
+
+int fdlbm_batch_create(fdlbm_ctx *const *ctxs, int n, fdlbm_batch **out) {
+  if (!out) return FDLBM_E_INVALID;
+  *out = nullptr;
+  if (!ctxs || n <= 0 || n > 65536) return FDLBM_E_INVALID;
+  auto *b = new fdlbm_batch;
+  b->n = n;
+  b->ctx.assign(ctxs, ctxs + n);
+  auto fail = [&](const char *msg) {
+    if (ctxs[0]) set_err(ctxs[0], FDLBM_E_INVALID, "batch: %s", msg);
+    delete b;
+    return FDLBM_E_INVALID;
+  };
+  for (int s = 0; s < n; ++s) {
+    const fdlbm_ctx *c = ctxs[s];
+    if (!c) return fail("null context");
+    if (!c->initialized) return fail("every context needs initialised fields");
+    if (c->D != ctxs[0]->D || c->ns != ctxs[0]->ns || c->d.precision != ctxs[0]->d.precision ||
+        c->stream != ctxs[0]->stream)
+      return fail("contexts differ in lattice, species count, precision or stream");
+    for (int r = 0; r < s; ++r)
+      if (ctxs[r] == c) return fail("a context appears twice");
+  }
+  b->D = ctxs[0]->D;
+  b->ns = ctxs[0]->ns;
+  b->precision = ctxs[0]->d.precision;
+  b->stream = ctxs[0]->stream;
+  b->cur = ctxs[0]->cur;
+  b->active.assign(n, 1);
+  with_prec(ctxs[0], [&](auto tag) {
+    using Tg = decltype(tag);
+    b->p_size = sizeof(Params<typename Tg::real>);
+    b->b_size = sizeof(Bufs<typename Tg::real, typename Tg::pop>);
+    return 0;
+  });
+  for (int s = 0; s < n; ++s) {
+    int nbk[BL_NUM];
+    batch_blocks(ctxs[s], nbk);
+    for (int k = 0; k < BL_NUM; ++k) b->max_items[k] += nbk[k];
+  }
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) / 256 * 256;
+    return o;
+  };
+  b->off_params = take(b->p_size * n);
+  b->off_bufs = take(b->b_size * n);
+  b->off_count = take(sizeof(int) * BL_NUM);
+  for (int k = 0; k < BL_NUM; ++k) b->off_items[k] = take(sizeof(int2) * std::max(1, b->max_items[k]));
+  b->total = off;
+  // default persistent grids: every logical block its own workgroup up to
+  // 8 per CU (256 CUs), a multiple of the 8 XCDs
+  for (int k = 0; k < BL_NUM; ++k) b->grid[k] = round8(std::min(b->max_items[k], 2048));
+  *out = b;
+  return FDLBM_OK;
+}
+
+void fdlbm_batch_destroy(fdlbm_batch *b) {
+  if (!b) return;
+  batch_drop_graphs(b);
+  delete b;
+}
+
+const char *fdlbm_batch_last_error(const fdlbm_batch *b) { return b ? b->err.c_str() : "null batch"; }
+
+int fdlbm_batch_workspace_bytes(const fdlbm_batch *b, size_t *bytes) {
+  if (!b || !bytes) return FDLBM_E_INVALID;
+  *bytes = b->total;
+  return FDLBM_OK;
+}
+
+// Upload per-sample parameters, buffer tables (with each sample's population
+// and solid-temperature buffers swapped where its parity differs from the
+// batch's) and the work lists of the active samples; synchronous.
+static int batch_upload(fdlbm_batch *b) {
+  b->h_params.assign(b->p_size * b->n, 0);
+  b->h_bufs.assign(b->b_size * b->n, 0);
+  for (int s = 0; s < b->n; ++s) {
+    const fdlbm_ctx *c = b->ctx[s];
+    const bool flip = (c->cur ^ b->cur) != 0;
+    with_prec(c, [&](auto tag) {
+      using Tg = decltype(tag);
+      using real = typename Tg::real;
+      using PT = typename Tg::pop;
+      const Params<real> p = params<real>(c);
+      Bufs<real, PT> bu = bufs<real, PT>(c);
+      if (flip) {
+        std::swap(bu.G[0], bu.G[1]);
+        std::swap(bu.Ts[0], bu.Ts[1]);
+      }
+      std::memcpy(b->h_params.data() + b->p_size * s, &p, sizeof p);
+      std::memcpy(b->h_bufs.data() + b->b_size * s, &bu, sizeof bu);
+      return 0;
+    });
+  }
+  for (int k = 0; k < BL_NUM; ++k) b->h_items[k].clear();
+  for (int s = 0; s < b->n; ++s) {
+    if (!b->active[s]) continue;
+    int nbk[BL_NUM];
+    batch_blocks(b->ctx[s], nbk);
+    for (int k = 0; k < BL_NUM; ++k)
+      for (int q = 0; q < nbk[k]; ++q) b->h_items[k].push_back(make_int2(s, q));
+  }
+  for (int k = 0; k < BL_NUM; ++k) {
+    b->n_items[k] = b->h_count[k] = (int)b->h_items[k].size();
+    if (b->n_items[k])
+      BHIPCHK(b, hipMemcpyAsync(b->ws + b->off_items[k], b->h_items[k].data(), b->h_items[k].size() * sizeof(int2),
+                                hipMemcpyHostToDevice, b->stream));
+  }
+  BHIPCHK(b, hipMemcpyAsync(b->ws + b->off_params, b->h_params.data(), b->h_params.size(), hipMemcpyHostToDevice,
+                            b->stream));
+  BHIPCHK(b, hipMemcpyAsync(b->ws + b->off_bufs, b->h_bufs.data(), b->h_bufs.size(), hipMemcpyHostToDevice,
+                            b->stream));
+  BHIPCHK(b, hipMemcpyAsync(b->ws + b->off_count, b->h_count, sizeof b->h_count, hipMemcpyHostToDevice, b->stream));
+  BHIPCHK(b, hipStreamSynchronize(b->stream));
+  return FDLBM_OK;
+}
+
+int fdlbm_batch_bind_workspace(fdlbm_batch *b, void *dev, size_t bytes) {
+  if (!b) return FDLBM_E_INVALID;
+  if (!dev || ((uintptr_t)dev & 255u) || bytes < b->total)
+    return bset_err(b, FDLBM_E_ALIGN, "batch workspace must be >= %zu bytes and 256-byte aligned", b->total);
+  batch_drop_graphs(b);
+  b->ws = (char *)dev;
+  b->ws_bytes = bytes;
+  const int rc = batch_upload(b);
+  if (rc != FDLBM_OK) return rc;
+  b->bound = true;
+  return FDLBM_OK;
+}
+
+int fdlbm_batch_set_active(fdlbm_batch *b, const uint8_t *active) {
+  if (!b || !active) return FDLBM_E_INVALID;
+  if (!b->bound) return bset_err(b, FDLBM_E_STATE, "bind the batch workspace first");
+  for (int s = 0; s < b->n; ++s) b->active[s] = active[s] ? 1 : 0;
+  return batch_upload(b);
+}
+
+int fdlbm_batch_set_grid(fdlbm_batch *b, const int *grid, int graph_steps) {
+  if (!b) return FDLBM_E_INVALID;
+  if (grid)
+    for (int k = 0; k < BL_NUM; ++k) {
+      if (grid[k] <= 0 || grid[k] % 8) return bset_err(b, FDLBM_E_INVALID, "grids are positive multiples of 8");
+    }
+  if (graph_steps < 0 || graph_steps % 2) return bset_err(b, FDLBM_E_INVALID, "graph steps: even and >= 0");
+  if (grid)
+    for (int k = 0; k < BL_NUM; ++k) b->grid[k] = grid[k];
+  if (graph_steps > 0) b->graph_steps = graph_steps;
+  batch_drop_graphs(b);
+  return FDLBM_OK;
+}
+
+int fdlbm_batch_get_grid(const fdlbm_batch *b, int *grid, int *graph_steps) {
+  if (!b) return FDLBM_E_INVALID;
+  if (grid)
+    for (int k = 0; k < BL_NUM; ++k) grid[k] = b->grid[k];
+  if (graph_steps) *graph_steps = b->graph_steps;
+  return FDLBM_OK;
+}
+
+// one step of the kinds in `mask` (bit k = launch kind k) at parity cur
+static hipError_t batch_launch(fdlbm_batch *b, int cur, unsigned mask) {
+  BatchLaunch bl;
+  bl.params = b->ws + b->off_params;
+  bl.bufs = b->ws + b->off_bufs;
+  for (int k = 0; k < BL_NUM; ++k) {
+    bl.items[k] = (const int2 *)(b->ws + b->off_items[k]);
+    bl.max_items[k] = b->max_items[k];
+    bl.grid[k] = ((mask >> k) & 1u) ? std::min(b->grid[k], std::max(8, round8(b->max_items[k]))) : 0;
+  }
+  bl.count = (const int *)(b->ws + b->off_count);
+  bl.stream = b->stream;
+  return (hipError_t)with_prec(b->ctx[0], [&](auto tag) {
+    using Tg = decltype(tag);
+    return (int)launch_batch_step<typename Tg::real, typename Tg::pop>(b->D, b->ns, bl, cur);
+  });
+}
+
+static void batch_advance(fdlbm_batch *b, int64_t steps) {
+  for (int s = 0; s < b->n; ++s)
+    if (b->active[s]) {
+      b->ctx[s]->step += steps;
+      b->ctx[s]->cur ^= (int)(steps & 1);
+    }
+  b->cur ^= (int)(steps & 1);
+}
+
+static int batch_capture(fdlbm_batch *b, int parity) {
+  hipGraph_t g = nullptr;
+  BHIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < b->graph_steps && e == hipSuccess; ++k) e = batch_launch(b, parity ^ (k & 1), (1u << BL_NUM) - 1);
+  const hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return bset_err(b, FDLBM_E_HIP, "graph capture: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+  }
+  e = hipGraphInstantiate(&b->exec[parity], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    b->exec[parity] = nullptr;
+    return bset_err(b, FDLBM_E_HIP, "graph instantiate: %s", hipGetErrorString(e));
+  }
+  return FDLBM_OK;
+}
+
+int fdlbm_batch_step(fdlbm_batch *b, int64_t n_steps) {
+  if (!b) return FDLBM_E_INVALID;
+  if (!b->bound) return bset_err(b, FDLBM_E_STATE, "bind the batch workspace first");
+  if (n_steps < 0) return bset_err(b, FDLBM_E_INVALID, "negative step count");
+  bool any = false;
+  for (int s = 0; s < b->n; ++s) any = any || b->active[s];
+  if (!any || n_steps == 0) return FDLBM_OK;
+  // the legacy default stream cannot be captured: direct launches only there
+  while (b->stream != nullptr && n_steps >= b->graph_steps) {
+    if (!b->exec[b->cur]) {
+      const int rc = batch_capture(b, b->cur);
+      if (rc != FDLBM_OK) return rc;
+    }
+    BHIPCHK(b, hipGraphLaunch(b->exec[b->cur], b->stream));
+    batch_advance(b, b->graph_steps);  // even: parity unchanged
+    n_steps -= b->graph_steps;
+  }
+  for (; n_steps > 0; --n_steps) {
+    const hipError_t e = batch_launch(b, b->cur, (1u << BL_NUM) - 1);
+    if (e != hipSuccess) return bset_err(b, FDLBM_E_HIP, "batch launch: %s", hipGetErrorString(e));
+    batch_advance(b, 1);
+  }
+  return FDLBM_OK;
+}
+
+// Autotuner of the persistent launch shapes: for each candidate grid size
+// (workgroups per launch, a multiple of 8) every launch kind is timed with
+// HIP events over `steps` steps (after one warm-up step), and each kind keeps
+// its fastest grid.  The tuning steps are real steps of the active samples.
+int fdlbm_batch_autotune(fdlbm_batch *b, int steps, int *grid_out) {
+  if (!b) return FDLBM_E_INVALID;
+  if (!b->bound) return bset_err(b, FDLBM_E_STATE, "bind the batch workspace first");
+  if (steps <= 0 || steps > 10000) return bset_err(b, FDLBM_E_INVALID, "steps in 1..10000");
+  static const int cand[] = {256, 512, 1024, 2048, 4096, 8192, 16384};
+  const int ncand = (int)(sizeof cand / sizeof cand[0]);
+  std::vector<hipEvent_t> ev((size_t)BL_NUM * 2);
+  for (auto &e : ev) BHIPCHK(b, hipEventCreate(&e));
+  double best_t[BL_NUM];
+  int best_g[BL_NUM];
+  const int saved[BL_NUM] = {b->grid[0], b->grid[1], b->grid[2], b->grid[3], b->grid[4], b->grid[5]};
+  for (int k = 0; k < BL_NUM; ++k) {
+    best_t[k] = HUGE_VAL;
+    best_g[k] = saved[k];
+  }
+  int rc = FDLBM_OK;
+  int maxcap = 8;
+  for (int k = 0; k < BL_NUM; ++k) maxcap = std::max(maxcap, round8(b->max_items[k]));
+  // candidates up to the first one that gives every kind all its blocks
+  for (int ci = 0; ci < ncand && rc == FDLBM_OK && (ci == 0 || cand[ci - 1] < maxcap); ++ci) {
+    for (int k = 0; k < BL_NUM; ++k) b->grid[k] = std::min(cand[ci], std::max(8, round8(b->max_items[k])));
+    double t[BL_NUM] = {0, 0, 0, 0, 0, 0};
+    for (int s = 0; s <= steps && rc == FDLBM_OK; ++s) {
+      for (int k = 0; k < BL_NUM; ++k) {
+        if (s > 0) (void)hipEventRecord(ev[2 * k], b->stream);
+        const hipError_t e = batch_launch(b, b->cur, 1u << k);
+        if (e != hipSuccess) {
+          rc = bset_err(b, FDLBM_E_HIP, "autotune launch: %s", hipGetErrorString(e));
+          break;
+        }
+        if (s > 0) (void)hipEventRecord(ev[2 * k + 1], b->stream);
+      }
+      if (rc != FDLBM_OK) break;
+      batch_advance(b, 1);
+      if (s > 0) {
+        if (hipStreamSynchronize(b->stream) != hipSuccess) {
+          rc = bset_err(b, FDLBM_E_HIP, "autotune sync");
+          break;
+        }
+        for (int k = 0; k < BL_NUM; ++k) {
+          float ms = 0;
+          (void)hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]);
+          t[k] += ms;
+        }
+      }
+    }
+    for (int k = 0; k < BL_NUM; ++k)
+      if (t[k] < best_t[k]) {
+        best_t[k] = t[k];
+        best_g[k] = b->grid[k];
+      }
+  }
+  for (auto &e : ev) (void)hipEventDestroy(e);
+  for (int k = 0; k < BL_NUM; ++k) b->grid[k] = rc == FDLBM_OK ? best_g[k] : saved[k];
+  batch_drop_graphs(b);
+  if (grid_out)
+    for (int k = 0; k < BL_NUM; ++k) grid_out[k] = b->grid[k];
+  return rc;
+}

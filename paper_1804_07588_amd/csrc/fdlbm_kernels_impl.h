@@ -194,12 +194,26 @@ __device__ inline void pop_store_raw(PT *__restrict__ Gi, int slot, const Rec<re
     strec<real, NS>(Gi, slot, v);
   }
 }
+// The 16-bit storage transform g = (d + w_i) rho_ref and its inverse, kept
+// out of floating-point contraction: the compiler would otherwise fuse them
+// with neighbouring arithmetic differently in different kernels, and the
+// batched and single-domain launches would round stored values differently.
+template <typename real>
+__device__ inline real dev_decode(real d, real w, real rho_ref) {
+#pragma clang fp contract(off)
+  return (d + w) * rho_ref;
+}
+template <typename real>
+__device__ inline real dev_encode(real g, real inv_rho_ref, real w) {
+#pragma clang fp contract(off)
+  return g * inv_rho_ref - w;
+}
 template <typename real, typename PT, int D, int NS>
 __device__ inline Rec<real, NS> pop_load(const Params<real> &p, const PT *__restrict__ Gi, int slot, int i) {
   Rec<real, NS> r = pop_load_raw<real, PT, NS>(Gi, slot);
   if constexpr (narrow<PT>()) {
 #pragma unroll
-    for (int j = 0; j < NS; ++j) r.v[j] = (r.v[j] + real(wlat<D>(i))) * p.rho_ref[j];
+    for (int j = 0; j < NS; ++j) r.v[j] = dev_decode(r.v[j], real(wlat<D>(i)), p.rho_ref[j]);
   }
   return r;
 }
@@ -207,7 +221,7 @@ template <typename real, typename PT, int D, int NS>
 __device__ inline void pop_store(const Params<real> &p, PT *__restrict__ Gi, int slot, int i, Rec<real, NS> v) {
   if constexpr (narrow<PT>()) {
 #pragma unroll
-    for (int j = 0; j < NS; ++j) v.v[j] = v.v[j] * p.inv_rho_ref[j] - real(wlat<D>(i));
+    for (int j = 0; j < NS; ++j) v.v[j] = dev_encode(v.v[j], p.inv_rho_ref[j], real(wlat<D>(i)));
   }
   pop_store_raw<real, PT, NS>(Gi, slot, v);
 }
@@ -245,7 +259,7 @@ __device__ inline Rec<real, NS> stream_rec(const Params<real> &p, const PT *__re
   for (int j = 0; j < NS; ++j) {
     g.v[j] = wt.w[j][cls][0] * r0.v[j] + wt.w[j][cls][1] * r1.v[j] + wt.w[j][cls][2] * r2.v[j];
     // the weights sum to one: deviations interpolate like the populations
-    if constexpr (narrow<PT>()) g.v[j] = (g.v[j] + real(wlat<D>(i))) * p.rho_ref[j];
+    if constexpr (narrow<PT>()) g.v[j] = dev_decode(g.v[j], real(wlat<D>(i)), p.rho_ref[j]);
   }
   return g;
 }
@@ -441,19 +455,26 @@ __device__ inline double wall_node(const Params<real> &p, const Bufs<real, PT> &
   return (double)r;
 }
 
-// FAST: the node list holds only nodes whose taps never wrap a periodic axis
+// FAST: the node list holds only nodes whose taps never wrap a periodic axis.
+// One block of wall nodes (logical block lb of the list).
 template <bool FAST, typename real, typename PT, int D, int NS>
-__global__ void __launch_bounds__(BLOCK) k_wall(Params<real> p, Bufs<real, PT> b, int cur) {
-  __shared__ WTab<real> wtab;
-  load_wtab<real, NS>(p, wtab);
+__device__ __forceinline__ void wall_block(const Params<real> &p, const Bufs<real, PT> &b, int cur,
+                                           const WTab<real> &wtab, int lb) {
   const int first = FAST ? 0 : p.n_wall_fast, count = FAST ? p.n_wall_fast : p.n_wall - p.n_wall_fast;
-  const int nb = (count + BLOCK - 1) / BLOCK, lb = xcd_block(nb);
-  if (lb >= nb) return;  // whole block: no barrier follows for it
   const int t = lb * BLOCK + threadIdx.x;
   double r_out = 0.0;
   if (t < count) r_out = wall_node<FAST, real, PT, D, NS>(p, b, cur, wtab, first + t);
   const double s = block_sum(r_out);
   if (threadIdx.x == 0) b.acc_moles[lb + (FAST ? 0 : p.slot_off_wall)] += s;
+}
+template <bool FAST, typename real, typename PT, int D, int NS>
+__global__ void __launch_bounds__(BLOCK) k_wall(Params<real> p, Bufs<real, PT> b, int cur) {
+  __shared__ WTab<real> wtab;
+  load_wtab<real, NS>(p, wtab);
+  const int count = FAST ? p.n_wall_fast : p.n_wall - p.n_wall_fast;
+  const int nb = (count + BLOCK - 1) / BLOCK, lb = xcd_block(nb);
+  if (lb >= nb) return;  // whole block: no barrier follows for it
+  wall_block<FAST, real, PT, D, NS>(p, b, cur, wtab, lb);
 }
 
 // ===========================================================================
@@ -461,18 +482,12 @@ __global__ void __launch_bounds__(BLOCK) k_wall(Params<real> p, Bufs<real, PT> b
 // moments of the streamed populations and every local quantity of the node
 // (Eq.(3), (5), (7)-(8), (11), (14)-(17), (25)), one thread per node.
 // ===========================================================================
+// one gas node (slot t) of the streaming-and-moments pass
 template <bool FAST, typename real, typename PT, int D, int NS>
-__global__ void __launch_bounds__(BLOCK) k_moments(Params<real> p, Bufs<real, PT> b, int cur) {
+__device__ __forceinline__ void moments_node(const Params<real> &p, const Bufs<real, PT> &b, int cur,
+                                             const WTab<real> &wtab, int t) {
   constexpr int Q = lat_q<D>();
   constexpr int NR = fr_count(D, NS), NX = fx_count(D, NS);
-  __shared__ WTab<real> wtab;
-  load_wtab_gas<real, NS>(p, wtab);
-  const int first = FAST ? 0 : p.n_gas_fast, count = FAST ? p.n_gas_fast : p.n_gas - p.n_gas_fast;
-  const int nb = (count + BLOCK - 1) / BLOCK, lb = xcd_block(nb);
-  if (lb >= nb) return;
-  const int tl = lb * BLOCK + threadIdx.x;
-  if (tl >= count) return;
-  const int t = first + tl;  // slot
   const int node = (int)b.gas_list[t];
   const Addr<D> ad(node, p);
   const uint64_t cw = b.scls[t];
@@ -601,6 +616,23 @@ __global__ void __launch_bounds__(BLOCK) k_moments(Params<real> p, Bufs<real, PT
   fx.v[fx_ediff(D)] = ediff;
   strec<real, NR>(b.FR, t, fr);
   strec<real, NX>(b.FX, t, fx);
+}
+
+template <bool FAST, typename real, typename PT, int D, int NS>
+__device__ __forceinline__ void moments_block(const Params<real> &p, const Bufs<real, PT> &b, int cur,
+                                              const WTab<real> &wtab, int lb) {
+  const int first = FAST ? 0 : p.n_gas_fast, count = FAST ? p.n_gas_fast : p.n_gas - p.n_gas_fast;
+  const int tl = lb * BLOCK + threadIdx.x;
+  if (tl < count) moments_node<FAST, real, PT, D, NS>(p, b, cur, wtab, first + tl);
+}
+template <bool FAST, typename real, typename PT, int D, int NS>
+__global__ void __launch_bounds__(BLOCK, 4) k_moments(Params<real> p, Bufs<real, PT> b, int cur) {
+  __shared__ WTab<real> wtab;
+  load_wtab_gas<real, NS>(p, wtab);
+  const int count = FAST ? p.n_gas_fast : p.n_gas - p.n_gas_fast;
+  const int nb = (count + BLOCK - 1) / BLOCK, lb = xcd_block(nb);
+  if (lb >= nb) return;
+  moments_block<FAST, real, PT, D, NS>(p, b, cur, wtab, lb);
 }
 
 // ===========================================================================
@@ -943,9 +975,7 @@ __device__ inline void outlet_node(const Params<real> &p, const Bufs<real, PT> &
 // (FP32 arithmetic: at least 2 waves per SIMD, i.e. at most 256 VGPRs; the
 // 16-bit storage variants would otherwise spill into AGPRs and run 1 wave)
 template <typename real, typename PT, int D, int NS>
-__global__ void __launch_bounds__(BLOCK, sizeof(real) == 4 ? 2 : 1) k_collide(Params<real> p, Bufs<real, PT> b, int cur) {
-  const int nb = (p.n_gas + BLOCK - 1) / BLOCK, lb = xcd_block(nb);
-  if (lb >= nb) return;  // whole block: no barrier follows for it
+__device__ __forceinline__ void collide_block(const Params<real> &p, const Bufs<real, PT> &b, int cur, int lb) {
   const int t = lb * BLOCK + threadIdx.x;
   double work = 0.0;
   if (t < p.n_gas) {
@@ -970,18 +1000,24 @@ __global__ void __launch_bounds__(BLOCK, sizeof(real) == 4 ? 2 : 1) k_collide(Pa
   const double s = block_sum(work);
   if (threadIdx.x == 0 && s != 0.0) b.acc_work[lb] += s;
 }
+template <typename real, typename PT, int D, int NS>
+__global__ void __launch_bounds__(BLOCK, sizeof(real) == 4 ? 2 : 1) k_collide(Params<real> p, Bufs<real, PT> b, int cur) {
+  const int nb = (p.n_gas + BLOCK - 1) / BLOCK, lb = xcd_block(nb);
+  if (lb >= nb) return;  // whole block: no barrier follows for it
+  collide_block<real, PT, D, NS>(p, b, cur, lb);
+}
 
 // ===========================================================================
 // k_solid: forward-Euler heat step over an LDS tile with a one-node halo
 // ===========================================================================
 template <typename real, typename PT, int D>
-__global__ void __launch_bounds__(BLOCK) k_solid(Params<real> p, Bufs<real, PT> b, int cur) {
+__device__ __forceinline__ void solid_block(const Params<real> &p, const Bufs<real, PT> &b, int cur, int tile) {
   constexpr int TX = SolidTile<D>::TX, TY = SolidTile<D>::TY, TZ = SolidTile<D>::TZ;
   constexpr int HX = TX + 2, HY = TY + 2, HZ = D == 3 ? TZ + 2 : 1;
   __shared__ real sT[HZ * HY * HX];
   __shared__ uint8_t sK[HZ * HY * HX];  // 1 solid, 0 not solid, 2 outside a closed axis
   const int tilesX = (p.nx + TX - 1) / TX, tilesY = (p.ny + TY - 1) / TY;
-  int bid = blockIdx.x;
+  int bid = tile;
   const int bx = bid % tilesX;
   bid /= tilesX;
   const int by = bid % tilesY;
@@ -1052,7 +1088,11 @@ __global__ void __launch_bounds__(BLOCK) k_solid(Params<real> p, Bufs<real, PT> 
     bflux += (double)(p.alpha_s * p.C_s * bf);
   }
   const double s = block_sum(bflux);
-  if (threadIdx.x == 0 && s != 0.0) b.acc_bheat[blockIdx.x] += s;
+  if (threadIdx.x == 0 && s != 0.0) b.acc_bheat[tile] += s;
+}
+template <typename real, typename PT, int D>
+__global__ void __launch_bounds__(BLOCK) k_solid(Params<real> p, Bufs<real, PT> b, int cur) {
+  solid_block<real, PT, D>(p, b, cur, blockIdx.x);
 }
 
 
@@ -1213,6 +1253,76 @@ __global__ void __launch_bounds__(BLOCK) k_residual(Params<real> p, Bufs<real, P
 }
 
 // ===========================================================================
+// batched persistent kernels: many independent domains (samples) advance in
+// one launch per kernel.  Each sample has its own Params and Bufs in device
+// memory; a work list holds (sample, logical block) pairs for every launch
+// kind.  The work list is split into 8 contiguous runs, one per XCD, and the
+// workgroups of an XCD walk their run in order, so neighbouring blocks of
+// one sample share that XCD's L2 as in the single-domain launches.
+// ===========================================================================
+template <typename F>
+__device__ __forceinline__ void for_items(const int2 *__restrict__ items, int n, F &&f) {
+  const int per = (n + NXCD - 1) / NXCD;
+  // gridDim.x is a multiple of NXCD: a workgroup keeps its XCD (q % NXCD)
+  for (int q = (int)blockIdx.x; q < per * NXCD; q += (int)gridDim.x) {
+    const int L = (q % NXCD) * per + q / NXCD;
+    if (L < n) f(items[L]);
+  }
+}
+
+template <bool FAST, typename real, typename PT, int D, int NS>
+__global__ void __launch_bounds__(BLOCK) kb_wall(const Params<real> *__restrict__ P,
+                                                 const Bufs<real, PT> *__restrict__ B,
+                                                 const int2 *__restrict__ items, const int *__restrict__ count,
+                                                 int cur) {
+  __shared__ WTab<real> wtab;
+  int prev = -1;
+  for_items(items, *count, [&](int2 it) {
+    if (it.x != prev) {
+      __syncthreads();  // every thread is done with the previous sample's table
+      load_wtab<real, NS>(P[it.x], wtab);
+      prev = it.x;
+    }
+    wall_block<FAST, real, PT, D, NS>(P[it.x], B[it.x], cur, wtab, it.y);
+  });
+}
+
+template <bool FAST, typename real, typename PT, int D, int NS>
+__global__ void __launch_bounds__(BLOCK, 4) kb_moments(const Params<real> *__restrict__ P,
+                                                    const Bufs<real, PT> *__restrict__ B,
+                                                    const int2 *__restrict__ items,
+                                                    const int *__restrict__ count, int cur) {
+  __shared__ WTab<real> wtab;
+  int prev = -1;
+  for_items(items, *count, [&](int2 it) {
+    if (it.x != prev) {
+      __syncthreads();
+      load_wtab_gas<real, NS>(P[it.x], wtab);
+      prev = it.x;
+    }
+    moments_block<FAST, real, PT, D, NS>(P[it.x], B[it.x], cur, wtab, it.y);
+  });
+}
+
+template <typename real, typename PT, int D, int NS>
+__global__ void __launch_bounds__(BLOCK, sizeof(real) == 4 ? 2 : 1)
+    kb_collide(const Params<real> *__restrict__ P, const Bufs<real, PT> *__restrict__ B,
+               const int2 *__restrict__ items, const int *__restrict__ count, int cur) {
+  for_items(items, *count, [&](int2 it) { collide_block<real, PT, D, NS>(P[it.x], B[it.x], cur, it.y); });
+}
+
+template <typename real, typename PT, int D>
+__global__ void __launch_bounds__(BLOCK) kb_solid(const Params<real> *__restrict__ P,
+                                                  const Bufs<real, PT> *__restrict__ B,
+                                                  const int2 *__restrict__ items, const int *__restrict__ count,
+                                                  int cur) {
+  for_items(items, *count, [&](int2 it) {
+    __syncthreads();  // the LDS tile of the previous item has been consumed
+    solid_block<real, PT, D>(P[it.x], B[it.x], cur, it.y);
+  });
+}
+
+// ===========================================================================
 // launchers
 // ===========================================================================
 template <typename real, typename PT, int D, int NS>
@@ -1250,6 +1360,34 @@ inline hipError_t step_impl(const Params<real> &p, const Bufs<real, PT> &b, int 
 }
 
 template <typename real, typename PT, int D, int NS>
+inline hipError_t batch_step_impl(const BatchLaunch &bl, int cur) {
+  const dim3 blk(BLOCK);
+  const auto *P = static_cast<const Params<real> *>(bl.params);
+  const auto *B = static_cast<const Bufs<real, PT> *>(bl.bufs);
+  hipStream_t st = bl.stream;
+  auto go = [&](int k) { return bl.grid[k] > 0 && bl.max_items[k] > 0; };
+  if (go(BL_WALL_FAST))
+    hipLaunchKernelGGL((kb_wall<true, real, PT, D, NS>), dim3(bl.grid[BL_WALL_FAST]), blk, 0, st, P, B,
+                       bl.items[BL_WALL_FAST], bl.count + BL_WALL_FAST, cur);
+  if (go(BL_WALL_SLOW))
+    hipLaunchKernelGGL((kb_wall<false, real, PT, D, NS>), dim3(bl.grid[BL_WALL_SLOW]), blk, 0, st, P, B,
+                       bl.items[BL_WALL_SLOW], bl.count + BL_WALL_SLOW, cur);
+  if (go(BL_GAS_FAST))
+    hipLaunchKernelGGL((kb_moments<true, real, PT, D, NS>), dim3(bl.grid[BL_GAS_FAST]), blk, 0, st, P, B,
+                       bl.items[BL_GAS_FAST], bl.count + BL_GAS_FAST, cur);
+  if (go(BL_GAS_SLOW))
+    hipLaunchKernelGGL((kb_moments<false, real, PT, D, NS>), dim3(bl.grid[BL_GAS_SLOW]), blk, 0, st, P, B,
+                       bl.items[BL_GAS_SLOW], bl.count + BL_GAS_SLOW, cur);
+  if (go(BL_COLLIDE))
+    hipLaunchKernelGGL((kb_collide<real, PT, D, NS>), dim3(bl.grid[BL_COLLIDE]), blk, 0, st, P, B,
+                       bl.items[BL_COLLIDE], bl.count + BL_COLLIDE, cur);
+  if (go(BL_SOLID))
+    hipLaunchKernelGGL((kb_solid<real, PT, D>), dim3(bl.grid[BL_SOLID]), blk, 0, st, P, B, bl.items[BL_SOLID],
+                       bl.count + BL_SOLID, cur);
+  return hipGetLastError();
+}
+
+template <typename real, typename PT, int D, int NS>
 inline hipError_t residual_impl(const Params<real> &p, const Bufs<real, PT> &b, int cur, int blocks,
                                 hipStream_t st) {
   hipLaunchKernelGGL((k_residual<real, PT, D, NS>), dim3(blocks), dim3(BLOCK), 0, st, p, b, cur);
@@ -1265,6 +1403,18 @@ inline hipError_t observe_impl(const Params<real> &p, const Bufs<real, PT> &b, i
 
 // species-count dispatch for one (precision, lattice); FDLBM_NS_CASES lists
 // the species counts this translation unit instantiates
+template <typename real, typename PT, int D>
+hipError_t batch_step_lat(int ns, const BatchLaunch &bl, int cur) {
+  switch (ns) {
+#define FDLBM_CASE(k) \
+  case k:             \
+    return batch_step_impl<real, PT, D, k>(bl, cur);
+    FDLBM_NS_CASES
+#undef FDLBM_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
 template <typename real, typename PT, int D>
 hipError_t step_lat(const Params<real> &p, const Bufs<real, PT> &b, int cur, LaunchInfo &li) {
   switch (p.ns) {

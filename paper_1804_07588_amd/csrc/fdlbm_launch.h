@@ -16,6 +16,30 @@ struct LaunchInfo {
   bool recorded[K_NUM];  // set by the launcher for the ids it recorded
 };
 
+// Batched launches (many samples per launch): per launch kind, a device work
+// list of (sample, logical block) pairs, its length in device memory (read by
+// the kernels, so a captured graph follows later edits of the list), the
+// largest length it may take (0: the launch is skipped) and the persistent
+// grid (a multiple of 8 workgroups).
+enum { BL_WALL_FAST = 0, BL_WALL_SLOW, BL_GAS_FAST, BL_GAS_SLOW, BL_COLLIDE, BL_SOLID, BL_NUM };
+struct BatchLaunch {
+  const void *params;  // Params<real>[n_samples], device
+  const void *bufs;    // Bufs<real, PT>[n_samples], device
+  const int2 *items[BL_NUM];
+  const int *count;    // BL_NUM ints, device
+  int max_items[BL_NUM];
+  int grid[BL_NUM];
+  hipStream_t stream;
+};
+
+template <typename real, typename PT, int D>
+hipError_t batch_step_lat(int ns, const BatchLaunch &bl, int cur);
+
+template <typename real, typename PT>
+inline hipError_t launch_batch_step(int D, int ns, const BatchLaunch &bl, int cur) {
+  return D == 2 ? batch_step_lat<real, PT, 2>(ns, bl, cur) : batch_step_lat<real, PT, 3>(ns, bl, cur);
+}
+
 // one time step on lattice D: wall, moments, collide (with inlet/outlet),
 // solid; real = arithmetic type, PT = population storage type
 template <typename real, typename PT, int D>

@@ -9,4 +9,5 @@ template hipError_t observe_lat<float, __bf16, 3>(const Params<float> &, const B
                                              int, hipStream_t);
 template hipError_t residual_lat<float, __bf16, 3>(const Params<float> &, const Bufs<float, __bf16> &, int, int,
                                            hipStream_t);
+template hipError_t batch_step_lat<float, __bf16, 3>(int, const BatchLaunch &, int);
 }  // namespace fdlbm

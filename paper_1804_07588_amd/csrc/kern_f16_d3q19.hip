@@ -9,4 +9,5 @@ template hipError_t observe_lat<float, _Float16, 3>(const Params<float> &, const
                                              int, hipStream_t);
 template hipError_t residual_lat<float, _Float16, 3>(const Params<float> &, const Bufs<float, _Float16> &, int, int,
                                            hipStream_t);
+template hipError_t batch_step_lat<float, _Float16, 3>(int, const BatchLaunch &, int);
 }  // namespace fdlbm

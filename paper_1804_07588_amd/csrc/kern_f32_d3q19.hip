@@ -9,4 +9,5 @@ template hipError_t observe_lat<float, float, 3>(const Params<float> &, const Bu
                                              int, hipStream_t);
 template hipError_t residual_lat<float, float, 3>(const Params<float> &, const Bufs<float, float> &, int, int,
                                            hipStream_t);
+template hipError_t batch_step_lat<float, float, 3>(int, const BatchLaunch &, int);
 }  // namespace fdlbm

@@ -9,4 +9,5 @@ template hipError_t observe_lat<double, double, 3>(const Params<double> &, const
                                              int, hipStream_t);
 template hipError_t residual_lat<double, double, 3>(const Params<double> &, const Bufs<double, double> &, int, int,
                                            hipStream_t);
+template hipError_t batch_step_lat<double, double, 3>(int, const BatchLaunch &, int);
 }  // namespace fdlbm

@@ -31,7 +31,11 @@ EXPORTS = ["fdlbm_create", "fdlbm_destroy", "fdlbm_last_error", "fdlbm_set_geome
            "fdlbm_workspace_bytes", "fdlbm_bind_workspace", "fdlbm_init_fields", "fdlbm_step",
            "fdlbm_sync", "fdlbm_observe", "fdlbm_get_field", "fdlbm_state_bytes",
            "fdlbm_save_state", "fdlbm_load_state", "fdlbm_set_profiling", "fdlbm_kernel_times",
-           "fdlbm_counts", "fdlbm_residual"]
+           "fdlbm_counts", "fdlbm_residual", "fdlbm_batch_create", "fdlbm_batch_destroy",
+           "fdlbm_batch_last_error", "fdlbm_batch_workspace_bytes", "fdlbm_batch_bind_workspace",
+           "fdlbm_batch_set_active", "fdlbm_batch_step", "fdlbm_batch_set_grid",
+           "fdlbm_batch_get_grid", "fdlbm_batch_autotune"]
+BATCH_KINDS = ["wall_fast", "wall_slow", "gas_fast", "gas_slow", "collide", "solid"]
 
 
 class FdlbmError(RuntimeError):
@@ -98,6 +102,19 @@ def lib() -> ct.CDLL:
         L.fdlbm_kernel_times.argtypes = [vp, dp, ct.POINTER(i64)]
         L.fdlbm_counts.argtypes = [vp, ct.POINTER(i64), ct.POINTER(i64), ct.POINTER(i64)]
         L.fdlbm_residual.argtypes = [vp, dp]
+        ip = ct.POINTER(ct.c_int)
+        L.fdlbm_batch_create.argtypes = [ct.POINTER(vp), ct.c_int, ct.POINTER(vp)]
+        L.fdlbm_batch_destroy.argtypes = [vp]
+        L.fdlbm_batch_destroy.restype = None
+        L.fdlbm_batch_last_error.argtypes = [vp]
+        L.fdlbm_batch_last_error.restype = ct.c_char_p
+        L.fdlbm_batch_workspace_bytes.argtypes = [vp, ct.POINTER(ct.c_size_t)]
+        L.fdlbm_batch_bind_workspace.argtypes = [vp, vp, ct.c_size_t]
+        L.fdlbm_batch_set_active.argtypes = [vp, ct.POINTER(ct.c_uint8)]
+        L.fdlbm_batch_step.argtypes = [vp, i64]
+        L.fdlbm_batch_set_grid.argtypes = [vp, ip, ct.c_int]
+        L.fdlbm_batch_get_grid.argtypes = [vp, ip, ip]
+        L.fdlbm_batch_autotune.argtypes = [vp, ct.c_int, ip]
         _lib = L
     return _lib
 
@@ -226,6 +243,74 @@ class Sim:
     def close(self):
         if getattr(self, "h", None):
             lib().fdlbm_destroy(self.h)
+            self.h = None
+            self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many Sims (same lattice, species count, precision and stream) advanced
+    by shared persistent launches replayed from captured HIP graphs.  The
+    Sims stay usable on their own (observe, residual, field) between batch
+    steps; do not call Sim.step on an active member."""
+
+    def __init__(self, sims: list):
+        import torch
+        L = lib()
+        self.sims = list(sims)
+        arr = (ct.c_void_p * len(self.sims))(*[s.h for s in self.sims])
+        h = ct.c_void_p()
+        rc = L.fdlbm_batch_create(arr, len(self.sims), ct.byref(h))
+        if rc != OK:
+            raise FdlbmError(rc, L.fdlbm_last_error(self.sims[0].h).decode())
+        self.h = h
+        nbytes = ct.c_size_t()
+        self._check(L.fdlbm_batch_workspace_bytes(h, ct.byref(nbytes)))
+        with torch.cuda.stream(self.sims[0].stream):
+            self.workspace = torch.empty(nbytes.value + 256, dtype=torch.uint8, device="cuda")
+        aligned = (self.workspace.data_ptr() + 255) & ~255
+        self._check(L.fdlbm_batch_bind_workspace(h, ct.c_void_p(aligned), nbytes.value))
+        self.active = np.ones(len(self.sims), dtype=np.uint8)
+
+    def _check(self, rc: int):
+        if rc != OK:
+            raise FdlbmError(rc, lib().fdlbm_batch_last_error(self.h).decode())
+
+    def step(self, n: int = 1):
+        self._check(lib().fdlbm_batch_step(self.h, int(n)))
+
+    def set_active(self, active):
+        a = np.ascontiguousarray(np.asarray(active, dtype=np.uint8).reshape(-1))
+        if a.size != len(self.sims):
+            raise ValueError("one flag per sample")
+        self._check(lib().fdlbm_batch_set_active(self.h, a.ctypes.data_as(ct.POINTER(ct.c_uint8))))
+        self.active = a.copy()
+
+    def set_grid(self, grid=None, graph_steps: int = 0):
+        g = None
+        if grid is not None:
+            g = (ct.c_int * len(BATCH_KINDS))(*[int(v) for v in grid])
+        self._check(lib().fdlbm_batch_set_grid(self.h, g, int(graph_steps)))
+
+    def grid(self) -> tuple[list, int]:
+        g = (ct.c_int * len(BATCH_KINDS))()
+        k = ct.c_int()
+        self._check(lib().fdlbm_batch_get_grid(self.h, g, ct.byref(k)))
+        return list(g), k.value
+
+    def autotune(self, steps: int = 5) -> dict:
+        g = (ct.c_int * len(BATCH_KINDS))()
+        self._check(lib().fdlbm_batch_autotune(self.h, int(steps), g))
+        return dict(zip(BATCH_KINDS, list(g)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fdlbm_batch_destroy(self.h)
             self.h = None
             self.workspace = None
 
