@@ -49,6 +49,13 @@ def parse():
     ap.add_argument("--stage-tol", type=float, default=1e-5,
                     help="16-bit storage: residual at which the FP32 stage takes over")
     ap.add_argument("--max-steps", type=int, default=400000)
+    ap.add_argument("--batch", action="store_true",
+                    help="instead of the throughput run: a batch of packed beds of uneven size "
+                         "run together to the steady-state residual --tol")
+    ap.add_argument("--batch-samples", type=int, default=64)
+    ap.add_argument("--batch-min", type=int, default=48)
+    ap.add_argument("--batch-max", type=int, default=96)
+    ap.add_argument("--batch-seed", type=int, default=2024)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
     return ap.parse_args()
@@ -126,6 +133,9 @@ def main():
     from paper_1804_07588_amd import fdlbm
 
     torch.cuda.set_device(0)
+    if args.batch:
+        batch_run(args)
+        return
     if args.calib_copy_mib:
         calib_copy(args.calib_copy_mib)
     cfg, init, nsph = bed(args.n)
@@ -295,6 +305,126 @@ def steady(args, sim, cfg, n_gas, ns, init):
         "config": {"workload": f"packed bed {args.n}^3 D3Q19 cold start (inlet gas at rest), "
                                f"5 species WGS", "gas_nodes": n_gas, "species": ns},
         "bad": obs["bad"], "T_max": obs["T_max"], "u_max": obs["u_max"],
+    }), flush=True)
+
+
+def batch_run(args):
+    """A batch of packed beds of uneven size (edge uniform in [batch_min,
+    batch_max], bed porosity uniform in [0.4, 0.7), radius-6 spheres, the
+    water-gas-shift chemistry), cold start, advanced together by the batched
+    persistent launches with autotuned launch shapes until every sample's
+    residual (checked every 100 steps) is <= args.tol; converged samples are
+    frozen.  Setup (geometry, contexts) is excluded from the clock; the
+    autotuner's steps are inside it.  Afterwards the throughput of the batch
+    is compared with the same samples stepped one context at a time."""
+    import numpy as np
+    import torch
+    from paper_1804_07588_amd import fdlbm, workloads as W
+    prec = {"f32": fdlbm.F32, "f64": fdlbm.F64, "f16": fdlbm.F16, "bf16": fdlbm.BF16}[args.precision]
+    t_setup = time.perf_counter()
+    cfgs = W.batch_beds(args.batch_samples, n_min=args.batch_min, n_max=args.batch_max,
+                        seed=args.batch_seed)
+    stream = torch.cuda.Stream()   # default priority; graph capture needs a non-default stream
+    sims = []
+    for k, c in enumerate(cfgs):
+        sims.append(fdlbm.Sim(c, precision=prec, init=W.uniform_init(c), stream=stream))
+        if (k + 1) % 8 == 0:
+            print(f"# batch setup: {k + 1}/{len(cfgs)} samples", file=sys.stderr, flush=True)
+    ns = len(cfgs[0]["species"]["M"])
+    gas = np.array([s.counts()[0] for s in sims], dtype=np.int64)
+    setup_s = time.perf_counter() - t_setup
+    B = fdlbm.Batch(sims)
+    S = len(sims)
+    steps = np.zeros(S, dtype=np.int64)
+    done = np.zeros(S, dtype=bool)
+    failed = np.zeros(S, dtype=bool)
+    last_r = np.full(S, np.inf)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tuned = B.autotune(5)
+    B.step(1)
+    for s in sims:
+        s.residual()  # first snapshots
+    last = time.perf_counter()
+    check = 100
+    while not done.all():
+        B.step(check)
+        newly = []
+        for k, s in enumerate(sims):
+            if done[k]:
+                continue
+            r = s.residual()
+            last_r[k] = r["max"]
+            if r["max"] <= args.tol:
+                newly.append(k)
+        for k, s in enumerate(sims):
+            if done[k]:
+                continue
+            o = s.observe()
+            steps[k] = o["step"]
+            if o["bad"] and k not in newly:
+                failed[k] = True   # unstable: frozen, reported, never converges
+                newly.append(k)
+        if newly:
+            done[newly] = True
+            if not done.all():
+                B.set_active(~done)
+        if steps[~done].max(initial=0) >= args.max_steps:
+            break
+        if time.perf_counter() - last > 30:
+            print(f"# batch: {int(done.sum())}/{S} converged, step {int(steps.max())}",
+                  file=sys.stderr, flush=True)
+            last = time.perf_counter()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    conv = done & ~failed
+    bad = [k for k in range(S) if failed[k]]
+    work = float((gas * ns * steps).sum())
+    umax = [s.observe()["u_max"] for s in sims]
+    per_sample = [dict(n=c["sample"]["n"], porosity=round(c["sample"]["porosity"], 3),
+                       force=float(c["flow"]["F"][0]), gas=int(gas[k]), steps=int(steps[k]),
+                       converged=bool(conv[k]), u_max=round(float(umax[k]), 4),
+                       residual=float(last_r[k]))
+                  for k, c in enumerate(cfgs)]
+    # throughput: the whole batch together versus one context at a time
+    B.set_active(np.ones(S, dtype=np.uint8))
+    K = 100
+    B.step(K)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    B.step(K)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - tb
+    for s in sims:
+        s.step(K)   # even: the batch parity is unchanged
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for s in sims:
+        s.step(K)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - ts
+    per_step_work = float(gas.sum() * ns)
+    mlups_b = per_step_work * K / tb / 1e6
+    mlups_s = per_step_work * K / ts / 1e6
+    print(json.dumps({
+        "metric": "seconds for a batch of packed beds to reach steady state (cold start)",
+        "value": round(elapsed, 3), "unit": "s", "higher_is_better": False, "n_gpus": 1,
+        "converged": int(conv.sum()), "samples": S, "tol": args.tol, "bad_samples": bad,
+        "steps_to_steady": {"min": int(steps[conv].min()) if conv.any() else None,
+                            "median": int(np.median(steps[conv])) if conv.any() else None,
+                            "max": int(steps[conv].max()) if conv.any() else None},
+        "mlups_species_during_run": round(work / elapsed / 1e6, 1),
+        "batched_mlups_species": round(mlups_b, 1), "one_at_a_time_mlups_species": round(mlups_s, 1),
+        "batched_speedup": round(mlups_b / mlups_s, 3),
+        "tuned_grids": tuned, "setup_seconds": round(setup_s, 1),
+        "dtype": "f64" if prec == fdlbm.F64 else "f32", "population_storage": args.precision,
+        "data": "synthetic",
+        "config": {"workload": f"{S} packed beds, edges {args.batch_min}-{args.batch_max} "
+                               f"(uniform), bed porosity 0.4-0.7, spheres r=6, 5 species WGS, "
+                               f"seed {args.batch_seed}",
+                   "nodes": int(sum(c["nx"] * c["ny"] * c["nz"] for c in cfgs)),
+                   "gas_nodes": int(gas.sum()), "species": ns},
+        "per_sample": per_sample,
     }), flush=True)
 
 
