@@ -15,7 +15,7 @@ CALIB_SRC = os.path.join(CSRC, "calib_copy.hip")
 SOURCES = [os.path.join(CSRC, f) for f in
            ("kern_f32_d3q19.hip", "kern_f64_d3q19.hip", "kern_f32_d2q9.hip", "kern_f64_d2q9.hip",
             "kern_f16_d3q19.hip", "kern_bf16_d3q19.hip", "kern_f16_d2q9.hip", "kern_bf16_d2q9.hip",
-            "fdlbm_api.cpp")]
+            "unet_kernels.hip", "fdlbm_api.cpp", "unet_api.cpp")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

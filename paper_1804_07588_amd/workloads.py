@@ -347,3 +347,39 @@ def perturbed_init(cfg: dict, seed: int, amp_rho: float = 0.02, amp_u: float = 0
     T = base["T"] * (1.0 + field(amp_T))
     Ts = base["Ts"] * (1.0 + field(amp_T))
     return dict(rho=rho, u=u, T=T, Ts=Ts)
+
+
+# ---------------------------------------------------------------------------
+# learned warm start: the U-Net's layer table and seeded initial parameters
+# (architecture data and random numbers only; the network arithmetic lives in
+# the HIP library and, independently, in the oracle)
+# ---------------------------------------------------------------------------
+# (c_in, c_out, level, relu) per convolution, level = log2 of the pooling
+UNET_LAYERS = [(32, 32, 0, 1), (32, 32, 0, 1), (32, 64, 1, 1), (64, 64, 1, 1),
+               (64, 160, 2, 1), (160, 160, 2, 1), (224, 64, 1, 1), (64, 64, 1, 1),
+               (96, 32, 0, 1), (32, 32, 0, 1), (32, 32, 0, 0)]
+
+
+def unet_layout(layers=None) -> tuple[list, int]:
+    """[(w_off, b_off)] per layer and the parameter count: each layer's
+    weights W[c_out][27][c_in] followed by its biases [c_out]."""
+    layers = UNET_LAYERS if layers is None else layers
+    offs, p = [], 0
+    for ci, co, _, _ in layers:
+        offs.append((p, p + co * 27 * ci))
+        p += co * 27 * ci + co
+    return offs, p
+
+
+def unet_init_params(seed: int = 1, layers=None, bias_scale: float = 0.0) -> np.ndarray:
+    """He-normal weights (std sqrt(2 / (27 c_in))) and zero (or small normal)
+    biases, float32, from numpy's PCG64 generator."""
+    layers = UNET_LAYERS if layers is None else layers
+    offs, n = unet_layout(layers)
+    rng = np.random.default_rng(seed)
+    p = np.zeros(n, dtype=np.float64)
+    for (ci, co, _, _), (wo, bo) in zip(layers, offs):
+        p[wo:bo] = rng.standard_normal(co * 27 * ci) * np.sqrt(2.0 / (27 * ci))
+        if bias_scale:
+            p[bo:bo + co] = rng.standard_normal(co) * bias_scale
+    return p.astype(np.float32)

@@ -1,5 +1,5 @@
 """C-ABI checks that need no GPU: the library loads, exports every function
-declared in include/fdlbm.h, validates its inputs and classifies geometry
+declared in include/fdlbm.h and include/fdlbm_unet.h, validates its inputs and classifies geometry
 like the oracle does.  No call here touches a HIP device."""
 import ctypes as ct
 import os
@@ -13,8 +13,8 @@ from paper_1804_07588_amd import fdlbm, workloads as W
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def header_functions():
-    src = open(os.path.join(ROOT, "include", "fdlbm.h")).read()
+def header_functions(name="fdlbm.h"):
+    src = open(os.path.join(ROOT, "include", name)).read()
     return sorted(set(re.findall(r"\b(fdlbm_[a-z_]+)\s*\(", src)))
 
 
@@ -31,6 +31,11 @@ def test_exports_match_header(L):
     for nme in names:
         assert hasattr(L, nme), nme
     assert sorted(fdlbm.EXPORTS) == names
+    from paper_1804_07588_amd import surrogate
+    unet = header_functions("fdlbm_unet.h")
+    for nme in unet:
+        assert hasattr(L, nme), nme
+    assert sorted(surrogate.UNET_EXPORTS) == unet
 
 
 def make_ctx(L, cfg, precision=fdlbm.F64):
