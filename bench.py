@@ -56,6 +56,17 @@ def parse():
     ap.add_argument("--batch-min", type=int, default=48)
     ap.add_argument("--batch-max", type=int, default=96)
     ap.add_argument("--batch-seed", type=int, default=2024)
+    ap.add_argument("--surrogate", action="store_true",
+                    help="instead of the throughput run: learned warm start -- steady states of "
+                         "64^3 beds from a batched run, U-Net training on the GPU, then held-out "
+                         "beds to --tol from the prediction versus from a cold start")
+    ap.add_argument("--sur-n", type=int, default=64, help="bed edge of the learned warm start")
+    ap.add_argument("--sur-train", type=int, default=48)
+    ap.add_argument("--sur-test", type=int, default=16)
+    ap.add_argument("--sur-epochs", type=int, default=60)
+    ap.add_argument("--sur-batch", type=int, default=4)
+    ap.add_argument("--sur-lr", type=float, default=1e-3)
+    ap.add_argument("--sur-seed", type=int, default=77)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
     return ap.parse_args()
@@ -135,6 +146,9 @@ def main():
     torch.cuda.set_device(0)
     if args.batch:
         batch_run(args)
+        return
+    if args.surrogate:
+        surrogate_run(args)
         return
     if args.calib_copy_mib:
         calib_copy(args.calib_copy_mib)
@@ -425,6 +439,88 @@ def batch_run(args):
                    "nodes": int(sum(c["nx"] * c["ny"] * c["nz"] for c in cfgs)),
                    "gas_nodes": int(gas.sum()), "species": ns},
         "per_sample": per_sample,
+    }), flush=True)
+
+
+def unet_flops(R, n):
+    """Multiply-adds x 2 of one training iteration over n samples: forward
+    convolutions, plus the input-gradient and weight-gradient convolutions
+    of the backward pass (the first layer needs no input gradient)."""
+    from paper_1804_07588_amd import workloads as W
+    fwd = [2 * 27 * ci * co * n * (R >> lvl) ** 3 for ci, co, lvl, _ in W.UNET_LAYERS]
+    return sum(fwd) * 3 - fwd[0]
+
+
+def surrogate_run(args):
+    """Learned warm start, end to end on the GPU: (1) sur_train + sur_test
+    packed beds of edge sur_n (porosity 0.4-0.7) run together from a cold
+    start to the steady-state residual --tol (the steps of the held-out beds
+    are their cold-start baseline); (2) the U-Net is trained on the training
+    beds' steady mole fractions, temperature and velocity; (3) the held-out
+    beds are run again, once from a cold start and once from the network's
+    prediction, each as one batch, to --tol.  Prints one JSON line."""
+    import numpy as np
+    import torch
+    from paper_1804_07588_amd import fdlbm, surrogate, warmstart, workloads as W
+    S = args.sur_train + args.sur_test
+    cfgs = W.batch_beds(S, n_min=args.sur_n, n_max=args.sur_n, seed=args.sur_seed)
+    stream = torch.cuda.Stream()   # default priority
+    with torch.cuda.stream(stream):
+        sims = warmstart.make_sims(cfgs, fdlbm.F32, stream, log="data setup")
+        gen = warmstart.run_to_steady(sims, args.tol, args.max_steps, log="steady states")
+        X, T, Wt = warmstart.dataset(sims, cfgs)
+        for s_ in sims:
+            s_.close()
+        del sims
+        ok = gen["converged"]
+        tr = [k for k in range(args.sur_train) if ok[k]]
+        te = [k for k in range(args.sur_train, S) if ok[k]]
+        norm = surrogate.Normaliser([T[k] for k in tr], [Wt[k] for k in tr])
+        ns = len(cfgs[0]["species"]["M"])
+        net = surrogate.UNet(args.sur_n, args.sur_batch, surrogate.N_IN, ns + 4, stream=stream)
+        net.set_params(W.unet_init_params(seed=args.sur_seed))
+        Tn = np.stack([norm.encode(T[k]) for k in tr])
+        Wn = np.stack([Wt[k] for k in tr])
+        fit = warmstart.train(net, X[tr], Tn, Wn, args.sur_epochs, args.sur_batch, args.sur_lr,
+                              log="training")
+        flops = unet_flops(args.sur_n, 1) * len(tr) * args.sur_epochs
+        # held-out prediction error (normalised units, weighted RMS per channel)
+        errs = []
+        for k in te:
+            y = net.forward(torch.as_tensor(X[k][None]).cuda().contiguous()).cpu().numpy()[0]
+            d = (y - norm.encode(T[k])) ** 2 * Wt[k]
+            errs.append(np.sqrt(d.sum(axis=0) / np.maximum(Wt[k].sum(axis=0), 1)))
+        test_cfgs = [cfgs[k] for k in te]
+        inits = warmstart.predict_inits(net, norm, test_cfgs)
+        cold_sims = warmstart.make_sims(test_cfgs, fdlbm.F32, stream)
+        cold = warmstart.run_to_steady(cold_sims, args.tol, args.max_steps, log="held-out cold")
+        for s_ in cold_sims:
+            s_.close()
+        warm_sims = warmstart.make_sims(test_cfgs, fdlbm.F32, stream, inits=inits)
+        warm = warmstart.run_to_steady(warm_sims, args.tol, args.max_steps, log="held-out warm")
+    cs, ws = cold["steps"], warm["steps"]
+    both = cold["converged"] & warm["converged"]
+    print(json.dumps({
+        "metric": "time to steady state of held-out packed beds: learned warm start vs cold start",
+        "value": round(cold["seconds"] / warm["seconds"], 3), "unit": "x (cold seconds / warm seconds)",
+        "higher_is_better": True, "n_gpus": 1, "tol": args.tol,
+        "cold": {"seconds": round(cold["seconds"], 2), "steps_mean": float(cs[both].mean()) if both.any() else None,
+                 "converged": int(cold["converged"].sum())},
+        "warm": {"seconds": round(warm["seconds"], 2), "steps_mean": float(ws[both].mean()) if both.any() else None,
+                 "converged": int(warm["converged"].sum())},
+        "steps_ratio": float(cs[both].mean() / ws[both].mean()) if both.any() else None,
+        "per_test_steps": [[int(a), int(b)] for a, b in zip(cs, ws)],
+        "training": {"samples": len(tr), "epochs": args.sur_epochs, "batch": args.sur_batch,
+                     "seconds": round(fit["seconds"], 2), "loss_first": fit["losses"][0],
+                     "loss_last": fit["losses"][-1], "params": int(net.n_params),
+                     "tflops": round(flops / fit["seconds"] / 1e12, 2)},
+        "test_rms_error_normalised": np.mean(errs, axis=0).round(4).tolist() if errs else None,
+        "data_generation": {"samples": S, "converged": int(ok.sum()), "seconds": round(gen["seconds"], 1),
+                            "steps_median": int(np.median(gen["steps"]))},
+        "data": "synthetic", "dtype": "f32 (method), bf16 MFMA with f32 accumulation (network)",
+        "config": {"workload": f"packed beds {args.sur_n}^3, porosity 0.4-0.7, spheres r=6, 5 species WGS, "
+                               f"seed {args.sur_seed}; U-Net 32/64/160 channels",
+                   "train": len(tr), "test": len(te)},
     }), flush=True)
 
 

@@ -178,20 +178,60 @@ class Normaliser:
         self.mean = (t * w).sum(axis=0) / s
         self.std = np.sqrt(((t - self.mean) ** 2 * w).sum(axis=0) / s)
         self.std = np.where(self.std > 0, self.std, 1.0)
+        on = w > 0
+        self.lo = np.array([t[on[:, c], c].min() if on[:, c].any() else -np.inf for c in range(t.shape[1])])
+        self.hi = np.array([t[on[:, c], c].max() if on[:, c].any() else np.inf for c in range(t.shape[1])])
 
     def encode(self, t):
         return ((t - self.mean) / self.std).astype(np.float32)
 
     def decode(self, y):
-        return y * self.std + self.mean
+        """Physical values, clamped to the range of the training targets: an
+        unseen value (e.g. a trace species' mole fraction below its inlet
+        level) would put a steep, unphysical gradient into the warm start,
+        and the diffusion velocity of a nearly absent species then makes its
+        equilibrium negative within a step."""
+        return np.clip(y * self.std + self.mean, self.lo, self.hi)
 
 
-def warm_init(cfg: dict, pred: np.ndarray) -> dict:
+def smooth_gas(field: np.ndarray, gas: np.ndarray, shape, passes: int) -> np.ndarray:
+    """`passes` sweeps of the mean over each gas node and its gas face
+    neighbours (x closed, y and z periodic); other nodes keep their values.
+    field: [n] or [n][c] over nodes x + nx (y + ny z)."""
+    nz, ny, nx = shape
+    f = field.reshape(nz, ny, nx, -1).astype(np.float64)
+    g = gas.reshape(nz, ny, nx, 1).astype(np.float64)
+    for _ in range(passes):
+        acc, cnt = f * g, g.copy()
+        for ax, per in ((0, True), (1, True), (2, False)):
+            for d in (1, -1):
+                fs, gs = np.roll(f * g, d, axis=ax), np.roll(g, d, axis=ax)
+                if not per:
+                    idx = [slice(None)] * 4
+                    idx[ax] = 0 if d == 1 else -1
+                    gs[tuple(idx)] = 0.0
+                    fs[tuple(idx)] = 0.0
+                acc += fs
+                cnt += gs
+        f = np.where(g > 0, acc / np.maximum(cnt, 1.0), f)
+    return f.reshape(field.shape)
+
+
+def warm_init(cfg: dict, pred: np.ndarray, passes: int = 4) -> dict:
     """Initial fields for fdlbm_init_fields from a decoded prediction
-    [R^3][ns + 4]: densities from the mole fractions at the inlet pressure
-    and the predicted temperature, velocity as predicted, solid temperature
-    = predicted T."""
+    [R^3][ns + 4]: mole fractions and velocity smoothed over the gas
+    (`passes` neighbour-mean sweeps: the network's node-to-node noise puts
+    steep gradients into trace species, whose diffusion velocities then turn
+    their equilibria negative within a few steps), densities from the mole
+    fractions at the inlet pressure and the predicted temperature, solid
+    temperature = predicted T."""
     ns = len(cfg["species"]["M"])
+    gas = np.asarray(cfg["mask"]).reshape(-1) == 0
+    shape = (cfg["nz"], cfg["ny"], cfg["nx"])
+    if passes:
+        pred = pred.copy()
+        pred[:, :ns] = smooth_gas(pred[:, :ns], gas, shape, passes)
+        pred[:, ns + 1:ns + 4] = smooth_gas(pred[:, ns + 1:ns + 4], gas, shape, passes)
     M = np.asarray(cfg["species"]["M"], np.float64)
     X = np.clip(pred[:, :ns].T.astype(np.float64), 1e-6, None)
     X /= X.sum(axis=0, keepdims=True)
