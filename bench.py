@@ -60,6 +60,9 @@ def parse():
                     help="instead of the throughput run: learned warm start -- steady states of "
                          "64^3 beds from a batched run, U-Net training on the GPU, then held-out "
                          "beds to --tol from the prediction versus from a cold start")
+    ap.add_argument("--unet-bench", action="store_true",
+                    help="instead of the throughput run: U-Net training iterations on synthetic "
+                         "64^3 inputs (convolution throughput against the bf16 MFMA peak)")
     ap.add_argument("--sur-n", type=int, default=64, help="bed edge of the learned warm start")
     ap.add_argument("--sur-train", type=int, default=48)
     ap.add_argument("--sur-test", type=int, default=16)
@@ -67,6 +70,8 @@ def parse():
     ap.add_argument("--sur-batch", type=int, default=4)
     ap.add_argument("--sur-lr", type=float, default=1e-3)
     ap.add_argument("--sur-seed", type=int, default=77)
+    ap.add_argument("--sur-no-augment", action="store_true",
+                    help="train without the bed symmetries (y/z shifts and reflections)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
     return ap.parse_args()
@@ -149,6 +154,9 @@ def main():
         return
     if args.surrogate:
         surrogate_run(args)
+        return
+    if args.unet_bench:
+        unet_bench(args)
         return
     if args.calib_copy_mib:
         calib_copy(args.calib_copy_mib)
@@ -451,6 +459,43 @@ def unet_flops(R, n):
     return sum(fwd) * 3 - fwd[0]
 
 
+def unet_bench(args):
+    """Training iterations of the warm-start U-Net (mini-batch sur_batch at
+    edge sur_n, synthetic seeded inputs): time per iteration and the
+    convolution work rate against the dense bf16 MFMA peak."""
+    import numpy as np
+    import torch
+    from paper_1804_07588_amd import surrogate, workloads as W
+    R, n = args.sur_n, args.sur_batch
+    net = surrogate.UNet(R, n, surrogate.N_IN, 9)
+    net.set_params(W.unet_init_params(seed=1))
+    rng = np.random.default_rng(0)
+    x = torch.as_tensor(rng.standard_normal((n, R ** 3, surrogate.N_IN)).astype(np.float32)).cuda()
+    t = torch.as_tensor(rng.standard_normal((n, R ** 3, 9)).astype(np.float32)).cuda()
+    w = torch.ones_like(t)
+    ws = float(w.sum().item())
+    for _ in range(args.warmup if args.warmup < 50 else 3):
+        net.train_step(x, t, w, ws, 1e-4, want_loss=False)
+    torch.cuda.synchronize()
+    steps = min(args.steps, 20)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.train_step(x, t, w, ws, 1e-4, want_loss=False)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    fl = unet_flops(R, n)
+    print(json.dumps({
+        "metric": "U-Net training iteration (forward, backward, Adam)", "value": round(dt * 1e3, 3),
+        "unit": "ms", "higher_is_better": False, "n_gpus": 1, "steps": steps,
+        "roofline": {"bound": "mfma", "achieved": round(fl / dt / 1e12, 2), "peak": 2500.0,
+                     "unit": "TFLOP/s", "frac": round(fl / dt / 1e12 / 2500.0, 4),
+                     "flops_per_iteration": fl},
+        "dtype": "bf16 (MFMA, f32 accumulate)", "data": "synthetic",
+        "config": {"workload": f"U-Net 32/64/160, {n} samples of {R}^3, 3 -> 9 channels",
+                   "params": int(net.n_params)},
+    }), flush=True)
+
+
 def surrogate_run(args):
     """Learned warm start, end to end on the GPU: (1) sur_train + sur_test
     packed beds of edge sur_n (porosity 0.4-0.7) run together from a cold
@@ -482,7 +527,7 @@ def surrogate_run(args):
         Tn = np.stack([norm.encode(T[k]) for k in tr])
         Wn = np.stack([Wt[k] for k in tr])
         fit = warmstart.train(net, X[tr], Tn, Wn, args.sur_epochs, args.sur_batch, args.sur_lr,
-                              log="training")
+                              log="training", norm=None if args.sur_no_augment else norm, ns=ns)
         flops = unet_flops(args.sur_n, 1) * len(tr) * args.sur_epochs
         # held-out prediction error (normalised units, weighted RMS per channel)
         errs = []
@@ -498,6 +543,22 @@ def surrogate_run(args):
             s_.close()
         warm_sims = warmstart.make_sims(test_cfgs, fdlbm.F32, stream, inits=inits)
         warm = warmstart.run_to_steady(warm_sims, args.tol, args.max_steps, log="held-out warm")
+        for s_ in warm_sims:
+            s_.close()
+        # warm start plus reduced-precision storage: FP16 populations to a
+        # residual of 1e-5, then FP32 from those fields to --tol
+        h_sims = warmstart.make_sims(test_cfgs, fdlbm.F16, stream, inits=inits)
+        f_sims = warmstart.make_sims(test_cfgs, fdlbm.F32, stream)
+        torch.cuda.synchronize()
+        t_h = time.perf_counter()
+        h1 = warmstart.run_to_steady(h_sims, max(args.tol, 1e-5), args.max_steps, log="held-out warm f16")
+        for hs, fs in zip(h_sims, f_sims):
+            fs.init_fields(fields_of(hs, ns))
+        h2 = warmstart.run_to_steady(f_sims, args.tol, args.max_steps, log="held-out warm f16->f32")
+        torch.cuda.synchronize()
+        warm16_s = time.perf_counter() - t_h
+        warm16_steps = h1["steps"] + h2["steps"]
+        warm16_ok = h2["converged"]
     cs, ws = cold["steps"], warm["steps"]
     both = cold["converged"] & warm["converged"]
     print(json.dumps({
@@ -509,8 +570,13 @@ def surrogate_run(args):
         "warm": {"seconds": round(warm["seconds"], 2), "steps_mean": float(ws[both].mean()) if both.any() else None,
                  "converged": int(warm["converged"].sum())},
         "steps_ratio": float(cs[both].mean() / ws[both].mean()) if both.any() else None,
+        "warm_f16_then_f32": {"seconds": round(warm16_s, 2), "steps_mean": float(warm16_steps.mean()),
+                              "f16_steps_mean": float(h1["steps"].mean()),
+                              "converged": int(warm16_ok.sum()),
+                              "speedup_vs_cold": round(cold["seconds"] / warm16_s, 3)},
         "per_test_steps": [[int(a), int(b)] for a, b in zip(cs, ws)],
         "training": {"samples": len(tr), "epochs": args.sur_epochs, "batch": args.sur_batch,
+                     "augmented": not args.sur_no_augment,
                      "seconds": round(fit["seconds"], 2), "loss_first": fit["losses"][0],
                      "loss_last": fit["losses"][-1], "params": int(net.n_params),
                      "tflops": round(flops / fit["seconds"] / 1e12, 2)},

@@ -11,6 +11,8 @@
 //   D (16 x 16):        rows 4 (l / 16) .. + 3, column l % 16
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "unet_launch.h"
 
 namespace unet {
@@ -29,39 +31,72 @@ __device__ inline bf16x8 zero8() {
 
 // ---------------------------------------------------------------------------
 // convolution as implicit GEMM: out[s][co] = act(sum_{tap,ci} W[co][tap][ci]
-// X[s + off(tap)][ci] + bias[co]).  One workgroup: 64 consecutive positions
-// (M) x BN output channels; wave w owns positions 16w .. 16w + 15.
+// X[s + off(tap)][ci] + bias[co]).  One workgroup: 128 consecutive positions
+// (M) x BN output channels.  Per K step (one tap, 32 input channels) the
+// workgroup stages the 128 shifted input rows (zero outside the cube) and the
+// BN weight rows in LDS; wave w then multiplies positions 32w .. 32w + 31
+// (two 16-row tiles) by all BN channels (BN/16 tiles) from LDS.
 // mode: 0 store bf16, 1 store f32, 2 add into f32.  Ci % 32 == 0,
-// Co % BN == 0, S % 64 == 0 (host-checked).
+// Co % BN == 0, S % 128 == 0 (host-checked).
 // ---------------------------------------------------------------------------
+constexpr int CV_M = 128;
+
 template <int BN>
 __global__ void __launch_bounds__(TPB) k_conv(const __bf16 *__restrict__ X, int Ci, const __bf16 *__restrict__ W,
                                               const float *__restrict__ bias, int Co, int R, int mode, int relu,
                                               void *__restrict__ out) {
-  constexpr int NT = BN / 16;
+  constexpr int NT = BN / 16, MT = 2;
+  __shared__ bf16x8 sa[CV_M * 4];  // [position][4 chunks of 8 channels]
+  __shared__ bf16x8 sb[BN * 4];    // [output channel][4 chunks]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int m = lane & 15, kq = lane >> 4;
-  const int s0 = blockIdx.x * 64 + wave * 16;
+  const int s_blk = blockIdx.x * CV_M;
   const int co0 = blockIdx.y * BN;
   const int R3 = R * R * R;
-  const int s = s0 + m;  // this lane's A row
-  const int x = s % R, y = (s / R) % R, z = (s / (R * R)) % R, base = s - (s % R3);
-  f32x4 acc[NT];
+  // staging assignment: A chunks q = tid, tid + 256 (position q / 4, chunk q % 4)
+  int a_x[2], a_y[2], a_z[2], a_base[2];
 #pragma unroll
-  for (int j = 0; j < NT; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int h = 0; h < 2; ++h) {
+    const int s = s_blk + ((int)threadIdx.x + h * TPB) / 4;
+
+    a_x[h] = s % R;
+    a_y[h] = (s / R) % R;
+    a_z[h] = (s / (R * R)) % R;
+    a_base[h] = s - (s % R3);
+  }
+  const int a_ch = ((int)threadIdx.x % 4) * 8;
+  f32x4 acc[MT][NT];
+#pragma unroll
+  for (int i = 0; i < MT; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   for (int tap = 0; tap < 27; ++tap) {
     const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-    const int zz = z + dz, yy = y + dy, xx = x + dx;
-    const bool ok = (unsigned)zz < (unsigned)R && (unsigned)yy < (unsigned)R && (unsigned)xx < (unsigned)R;
-    const __bf16 *xp = X + (size_t)(ok ? base + (zz * R + yy) * R + xx : 0) * Ci + kq * 8;
-    const __bf16 *wp = W + ((size_t)(co0 + m) * 27 + tap) * Ci + kq * 8;
-    for (int c0 = 0; c0 < Ci; c0 += 32) {
-      const bf16x8 a = ok ? *reinterpret_cast<const bf16x8 *>(xp + c0) : zero8();
+    const __bf16 *src[2];
 #pragma unroll
-      for (int j = 0; j < NT; ++j) {
-        const bf16x8 b = *reinterpret_cast<const bf16x8 *>(wp + (size_t)j * 16 * 27 * Ci + c0);
-        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
-      }
+    for (int h = 0; h < 2; ++h) {
+      const int zz = a_z[h] + dz, yy = a_y[h] + dy, xx = a_x[h] + dx;
+      const bool ok = (unsigned)zz < (unsigned)R && (unsigned)yy < (unsigned)R && (unsigned)xx < (unsigned)R;
+      src[h] = ok ? X + (size_t)(a_base[h] + (zz * R + yy) * R + xx) * Ci + a_ch : nullptr;
+    }
+    for (int c0 = 0; c0 < Ci; c0 += 32) {
+      __syncthreads();  // the previous step's tiles are consumed
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        sa[threadIdx.x + h * TPB] = src[h] ? *reinterpret_cast<const bf16x8 *>(src[h] + c0) : zero8();
+      for (int q = threadIdx.x; q < BN * 4; q += TPB)
+        sb[q] = *reinterpret_cast<const bf16x8 *>(W + ((size_t)(co0 + q / 4) * 27 + tap) * Ci + c0 + (q % 4) * 8);
+      __syncthreads();
+      bf16x8 a[MT], b[NT];
+#pragma unroll
+      for (int i = 0; i < MT; ++i) a[i] = sa[(wave * 32 + i * 16 + m) * 4 + kq];
+#pragma unroll
+      for (int j = 0; j < NT; ++j) b[j] = sb[(j * 16 + m) * 4 + kq];
+#pragma unroll
+      for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
   }
 #pragma unroll
@@ -69,14 +104,16 @@ __global__ void __launch_bounds__(TPB) k_conv(const __bf16 *__restrict__ X, int 
     const int co = co0 + j * 16 + m;
     const float bv = bias ? bias[co] : 0.0f;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const size_t o = (size_t)(s0 + 4 * kq + i) * Co + co;
-      float v = acc[j][i] + bv;
-      if (relu) v = fmaxf(v, 0.0f);
-      if (mode == 0) static_cast<__bf16 *>(out)[o] = (__bf16)v;
-      else if (mode == 1) static_cast<float *>(out)[o] = v;
-      else static_cast<float *>(out)[o] += v;
-    }
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const size_t o = (size_t)(s_blk + wave * 32 + i * 16 + 4 * kq + r) * Co + co;
+        float v = acc[i][j][r] + bv;
+        if (relu) v = fmaxf(v, 0.0f);
+        if (mode == 0) static_cast<__bf16 *>(out)[o] = (__bf16)v;
+        else if (mode == 1) static_cast<float *>(out)[o] = v;
+        else static_cast<float *>(out)[o] += v;
+      }
   }
 }
 
@@ -90,11 +127,18 @@ constexpr int WG_CH = 2048;  // positions per workgroup
 constexpr int WG_MAXT = 4;   // tiles per wave
 constexpr int WG_MAXC = 224; // largest channel count staged
 
+constexpr int WG_K = 64;              // positions staged per step
+constexpr int WG_LD = WG_K + 8;       // LDS row stride (bf16): 16-byte aligned rows
+
 __global__ void __launch_bounds__(TPB) k_wgrad(const __bf16 *__restrict__ GY, int Co,
                                                const __bf16 *__restrict__ X, int Ci, int R, int S,
                                                float *__restrict__ GW) {
-  __shared__ __bf16 sg[32 * WG_MAXC];
-  __shared__ __bf16 sx[32 * WG_MAXC];
+  // transposed tiles [channel][WG_K positions], so a fragment's 8
+  // consecutive positions are one 16-byte LDS read; staged with 16-byte
+  // global loads (8 channels of one position) by threads that walk the
+  // positions fastest (conflict-free LDS writes)
+  extern __shared__ __attribute__((aligned(16))) __bf16 wg_lds[];  // (Co + Ci) rows of WG_LD
+  __bf16 *sg = wg_lds, *sx = wg_lds + (size_t)Co * WG_LD;
   const int tap = blockIdx.x;
   const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -105,21 +149,22 @@ __global__ void __launch_bounds__(TPB) k_wgrad(const __bf16 *__restrict__ GY, in
 #pragma unroll
   for (int t = 0; t < WG_MAXT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int p0 = blockIdx.y * WG_CH, p1 = min(S, p0 + WG_CH);
-  for (int sb = p0; sb < p1; sb += 32) {
+  const int r = (int)threadIdx.x % WG_K;  // this thread's staged position
+  for (int sb = p0; sb < p1; sb += WG_K) {
     __syncthreads();
-    // stage 32 rows of gY (Co wide) and of shifted X (Ci wide)
-    for (int e = threadIdx.x; e < 32 * Co; e += TPB) {
-      const int r = e / Co, c = e % Co;
-      sg[r * Co + c] = GY[(size_t)(sb + r) * Co + c];
+    const int s = sb + r;
+    for (int q = (int)threadIdx.x / WG_K; q < Co / 8; q += TPB / WG_K) {
+      const bf16x8 v = *reinterpret_cast<const bf16x8 *>(GY + (size_t)s * Co + 8 * q);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) sg[(8 * q + i) * WG_LD + r] = v[i];
     }
-    for (int e = threadIdx.x; e < 32 * Ci; e += TPB) {
-      const int r = e / Ci, c = e % Ci;
-      const int s = sb + r;
-      const int x = s % R + dx, y = (s / R) % R + dy, z = (s / (R * R)) % R + dz;
-      __bf16 v = (__bf16)0.0f;
-      if ((unsigned)x < (unsigned)R && (unsigned)y < (unsigned)R && (unsigned)z < (unsigned)R)
-        v = X[(size_t)(s - (s % R3) + (z * R + y) * R + x) * Ci + c];
-      sx[r * Ci + c] = v;
+    const int x = s % R + dx, y = (s / R) % R + dy, z = (s / (R * R)) % R + dz;
+    const bool ok = (unsigned)x < (unsigned)R && (unsigned)y < (unsigned)R && (unsigned)z < (unsigned)R;
+    const __bf16 *xs = X + (size_t)(ok ? s - (s % R3) + (z * R + y) * R + x : 0) * Ci;
+    for (int q = (int)threadIdx.x / WG_K; q < Ci / 8; q += TPB / WG_K) {
+      const bf16x8 v = ok ? *reinterpret_cast<const bf16x8 *>(xs + 8 * q) : zero8();
+#pragma unroll
+      for (int i = 0; i < 8; ++i) sx[(8 * q + i) * WG_LD + r] = v[i];
     }
     __syncthreads();
 #pragma unroll
@@ -127,13 +172,13 @@ __global__ void __launch_bounds__(TPB) k_wgrad(const __bf16 *__restrict__ GY, in
       const int tile = tile0 + wave + 4 * t;
       if (tile < ntile) {
         const int ct = tile / nci, it = tile % nci;
-        bf16x8 a, b;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          a[i] = sg[(8 * kq + i) * Co + ct * 16 + m];  // A[m = co][k = position]
-          b[i] = sx[(8 * kq + i) * Ci + it * 16 + m];  // B[k = position][n = ci]
+        for (int ks = 0; ks < WG_K / 32; ++ks) {
+          // A[m = co][k = position], B[k = position][n = ci]
+          const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&sg[(ct * 16 + m) * WG_LD + 32 * ks + 8 * kq]);
+          const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&sx[(it * 16 + m) * WG_LD + 32 * ks + 8 * kq]);
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
         }
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
       }
     }
   }
@@ -263,15 +308,15 @@ __global__ void __launch_bounds__(TPB) k_loss(const float *__restrict__ P, int C
                                               const float *__restrict__ Wt, int nt, size_t npos, double inv_wsum,
                                               float *__restrict__ G, double *__restrict__ loss) {
   __shared__ double sh[TPB];
-  const size_t e = (size_t)blockIdx.x * TPB + threadIdx.x;
   double l = 0.0;
-  if (e < npos * Cp) {
+  const size_t n = npos * Cp;
+  for (size_t e = (size_t)blockIdx.x * TPB + threadIdx.x; e < n; e += (size_t)gridDim.x * TPB) {
     const size_t s = e / Cp;
     const int c = (int)(e % Cp);
     float g = 0.0f;
     if (c < nt) {
       const float d = P[e] - T[s * nt + c], w = Wt[s * nt + c];
-      l = (double)w * d * d;
+      l += (double)w * d * d;
       g = (float)(2.0 * inv_wsum * w * d);
     }
     G[e] = g;
@@ -318,20 +363,23 @@ static unsigned nblk(size_t n) { return (unsigned)((n + TPB - 1) / TPB); }
 hipError_t conv(const __bf16 *X, int Ci, const __bf16 *W, const float *bias, int Co, int R, int N, int mode,
                 int relu, void *out, hipStream_t st) {
   const int S = N * R * R * R;
-  if (Ci % 32 || Co % 32 || S % 64) return hipErrorInvalidValue;
+  if (Ci % 32 || Co % 32 || S % CV_M) return hipErrorInvalidValue;
   if (Co % 64 == 0)
-    hipLaunchKernelGGL(k_conv<64>, dim3(S / 64, Co / 64), dim3(TPB), 0, st, X, Ci, W, bias, Co, R, mode, relu, out);
+    hipLaunchKernelGGL(k_conv<64>, dim3(S / CV_M, Co / 64), dim3(TPB), 0, st, X, Ci, W, bias, Co, R, mode, relu,
+                       out);
   else
-    hipLaunchKernelGGL(k_conv<32>, dim3(S / 64, Co / 32), dim3(TPB), 0, st, X, Ci, W, bias, Co, R, mode, relu, out);
+    hipLaunchKernelGGL(k_conv<32>, dim3(S / CV_M, Co / 32), dim3(TPB), 0, st, X, Ci, W, bias, Co, R, mode, relu,
+                       out);
   return hipGetLastError();
 }
 
 hipError_t wgrad(const __bf16 *GY, int Co, const __bf16 *X, int Ci, int R, int N, float *GW, hipStream_t st) {
   const int S = N * R * R * R;
-  if (Ci % 16 || Co % 16 || Ci > WG_MAXC || Co > WG_MAXC || S % 32) return hipErrorInvalidValue;
+  if (Ci % 16 || Co % 16 || Ci > WG_MAXC || Co > WG_MAXC || S % WG_K) return hipErrorInvalidValue;
   const int groups = ((Co / 16) * (Ci / 16) + 15) / 16;
-  hipLaunchKernelGGL(k_wgrad, dim3(27, (S + WG_CH - 1) / WG_CH, groups), dim3(TPB), 0, st, GY, Co, X, Ci, R, S,
-                     GW);
+  const size_t lds = (size_t)(Co + Ci) * WG_LD * sizeof(__bf16);
+  hipLaunchKernelGGL(k_wgrad, dim3(27, (S + WG_CH - 1) / WG_CH, groups), dim3(TPB), lds, st, GY, Co, X, Ci, R,
+                     S, GW);
   return hipGetLastError();
 }
 
@@ -379,7 +427,8 @@ hipError_t input(const float *in, int cin, int Cp, size_t npos, __bf16 *X, hipSt
 }
 hipError_t loss(const float *P, int Cp, const float *T, const float *Wt, int nt, size_t npos, double inv_wsum,
                 float *G, double *l, hipStream_t st) {
-  hipLaunchKernelGGL(k_loss, dim3(nblk(npos * Cp)), dim3(TPB), 0, st, P, Cp, T, Wt, nt, npos, inv_wsum, G, l);
+  const unsigned g = std::min(nblk(npos * Cp), 2048u);  // grid-stride: few atomics on the sum
+  hipLaunchKernelGGL(k_loss, dim3(g), dim3(TPB), 0, st, P, Cp, T, Wt, nt, npos, inv_wsum, G, l);
   return hipGetLastError();
 }
 hipError_t adam(float *p, float *m, float *v, const float *g, size_t n, float lr, float b1, float b2, float eps,

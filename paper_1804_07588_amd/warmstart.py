@@ -81,12 +81,45 @@ def dataset(sims, cfgs):
     return X, [t for t, _ in TW], [w for _, w in TW]
 
 
-def train(net, X, T, Wt, epochs: int, batch: int, lr: float, seed: int = 0, log: str | None = None) -> dict:
+def augment(x, t, w, R, flip_sign, rng):
+    """A symmetry of the beds applied to a mini-batch on the device: periodic
+    shifts along y and z (the beds are periodic there) and reflections of y
+    and z, with the reflected velocity component's sign flipped.  flip_sign:
+    per target channel (a, b) such that a reflected normalised value is
+    a * t + b, or None for channels a reflection leaves unchanged."""
+    import torch
+    b = x.shape[0]
+    sh = lambda a: a.view(b, R, R, R, a.shape[-1])  # [n][z][y][x][c]
+    xs, ts, ws = sh(x), sh(t), sh(w)
+    dz, dy = int(rng.integers(R)), int(rng.integers(R))
+    xs, ts, ws = (torch.roll(a, shifts=(dz, dy), dims=(1, 2)) for a in (xs, ts, ws))
+    for dim, key in ((1, "z"), (2, "y")):
+        if rng.random() < 0.5:
+            xs, ts, ws = (torch.flip(a, dims=(dim,)) for a in (xs, ts, ws))
+            c, (a, off) = flip_sign[key]
+            ts = ts.clone()
+            ts[..., c] = a * ts[..., c] + off
+    return (xs.reshape(x.shape).contiguous(), ts.reshape(t.shape).contiguous(),
+            ws.reshape(w.shape).contiguous())
+
+
+def train(net, X, T, Wt, epochs: int, batch: int, lr: float, seed: int = 0, log: str | None = None,
+          norm=None, ns: int = 5) -> dict:
     """Adam on the weighted squared error of the normalised targets, in
     shuffled mini-batches; the learning rate decays as a cosine to lr/20.
-    X [S][R^3][c_in], T and Wt [S][R^3][n_out] (normalised), numpy."""
+    X [S][R^3][c_in], T and Wt [S][R^3][n_out] (normalised), numpy.  With
+    `norm` (the targets' Normaliser) every mini-batch is a random symmetry of
+    the beds (augment)."""
     import torch
     S = X.shape[0]
+    R = net.R
+    flip = None
+    if norm is not None:
+        # velocity channels ns+1 (x), ns+2 (y), ns+3 (z): reflecting y negates
+        # u_y, i.e. t -> -t - 2 mean/std in normalised units
+        cy, cz = ns + 2, ns + 3
+        flip = {"y": (cy, (-1.0, float(-2 * norm.mean[cy] / norm.std[cy]))),
+                "z": (cz, (-1.0, float(-2 * norm.mean[cz] / norm.std[cz])))}
     xd = torch.as_tensor(X).cuda()
     td = torch.as_tensor(T).cuda()
     wd = torch.as_tensor(Wt).cuda()
@@ -102,6 +135,8 @@ def train(net, X, T, Wt, epochs: int, batch: int, lr: float, seed: int = 0, log:
         for b0 in range(0, S, batch):
             idx = torch.as_tensor(order[b0:b0 + batch]).cuda()
             x, t, w = xd[idx].contiguous(), td[idx].contiguous(), wd[idx].contiguous()
+            if flip is not None:
+                x, t, w = augment(x, t, w, R, flip, rng)
             cur = lr * (0.05 + 0.95 * 0.5 * (1 + np.cos(np.pi * it / max(1, n_it - 1))))
             want = b0 == 0
             l = net.train_step(x, t, w, float(w.sum().item()), cur, want_loss=want)
