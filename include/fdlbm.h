@@ -217,9 +217,17 @@ int fdlbm_state_bytes(const fdlbm_ctx *ctx, size_t *bytes);
 int fdlbm_save_state(fdlbm_ctx *ctx, void *host_buf, size_t bytes);
 int fdlbm_load_state(fdlbm_ctx *ctx, const void *host_buf, size_t bytes);
 
-/* Per-kernel timing with HIP events on the context's stream.  While enabled
- * (fdlbm_set_profiling(ctx, 1), which also resets the record), each step
- * brackets its kernels with events, for up to 4096 steps; fdlbm_kernel_times
+/* Concurrency within a step (default on): the wall and solid kernels run on
+ * a second stream of the library's, beside the moments and collision kernels
+ * on the context's stream, ordered by events; every step still completes on
+ * the context's stream.  Off: all four on the context's stream, one after the
+ * other (per-kernel timings then measure each kernel alone).  Results are
+ * identical either way. */
+int fdlbm_set_overlap(fdlbm_ctx *ctx, int enable);
+
+/* Per-kernel timing with HIP events on the stream each kernel runs on.
+ * While enabled (fdlbm_set_profiling(ctx, 1), which also resets the record),
+ * each step brackets its kernels with events, for up to 4096 steps; fdlbm_kernel_times
  * synchronises and writes avg_ms[FDLBM_K_COUNT], the average duration in
  * milliseconds of each kernel group over the recorded steps (0 for a group
  * that did not run), and the number of recorded steps.  A group covers both

@@ -71,6 +71,11 @@ struct fdlbm_ctx {
   std::vector<hipEvent_t> events;  // [launch][kernel][2]
   int64_t prof_launches = 0;
   bool prof_recorded[K_NUM]{};  // kernel ids whose events the step records
+  // second stream for the wall and solid kernels (created on the first step)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_wall = nullptr, ev_solid = nullptr;
+  bool side_tried = false;
+  bool overlap = true;  // use the second stream when it exists
 };
 
 static int set_err(fdlbm_ctx *c, int code, const char *fmt, ...) {
@@ -502,6 +507,12 @@ int fdlbm_create(const fdlbm_desc *d, fdlbm_ctx **out) {
 void fdlbm_destroy(fdlbm_ctx *c) {
   if (!c) return;
   for (auto &e : c->events) (void)hipEventDestroy(e);
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    (void)hipStreamDestroy(c->side);
+  }
+  for (hipEvent_t e : {c->ev_fork, c->ev_wall, c->ev_solid})
+    if (e) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -749,10 +760,27 @@ template <typename real, typename PT>
 static int step_impl(fdlbm_ctx *c, int64_t n_steps) {
   const Params<real> pr = params<real>(c);
   const Bufs<real, PT> bu = bufs<real, PT>(c);
+  if (!c->side_tried) {
+    // a non-blocking second stream at the default priority, ordered against
+    // the context's stream by events only; without it the step runs on one
+    c->side_tried = true;
+    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_wall, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_solid, hipEventDisableTiming) != hipSuccess) {
+      if (c->side) (void)hipStreamDestroy(c->side);
+      c->side = nullptr;
+      (void)hipGetLastError();
+    }
+  }
   for (int64_t s = 0; s < n_steps; ++s) {
     LaunchInfo li;
     li.stream = c->stream;
     li.n_solid = (int)c->n_solid;
+    li.side = c->overlap ? c->side : nullptr;
+    li.ev_fork = c->ev_fork;
+    li.ev_wall = c->ev_wall;
+    li.ev_solid = c->ev_solid;
     li.events = nullptr;
     for (int k = 0; k < K_NUM; ++k) li.recorded[k] = false;
     if (c->prof && c->prof_launches < NPROF)
@@ -777,6 +805,12 @@ int fdlbm_step(fdlbm_ctx *c, int64_t n_steps) {
     using Tg = decltype(tag);
     return step_impl<typename Tg::real, typename Tg::pop>(c, n_steps);
   });
+}
+
+int fdlbm_set_overlap(fdlbm_ctx *c, int enable) {
+  if (!c) return FDLBM_E_INVALID;
+  c->overlap = enable != 0;
+  return FDLBM_OK;
 }
 
 int fdlbm_sync(fdlbm_ctx *c) {

@@ -1325,36 +1325,62 @@ __global__ void __launch_bounds__(BLOCK) kb_solid(const Params<real> *__restrict
 // ===========================================================================
 // launchers
 // ===========================================================================
+// One time step.  Dependencies within the step: the collision needs the
+// moments (same step) and the wall's state records (same step); the solid
+// needs the wall's rate and energy exchange.  The wall reads the previous
+// step's gas populations and writes the wall slots of the other buffer, which
+// only the next step's moments read, so the wall (then the solid) can run on
+// a second stream beside the moments (then the collision).
 template <typename real, typename PT, int D, int NS>
 inline hipError_t step_impl(const Params<real> &p, const Bufs<real, PT> &b, int cur,
                             LaunchInfo &li) {
   const int gwf = (p.n_wall_fast + BLOCK - 1) / BLOCK, gws = (p.n_wall - p.n_wall_fast + BLOCK - 1) / BLOCK;
   const int ggf = (p.n_gas_fast + BLOCK - 1) / BLOCK, ggs = (p.n_gas - p.n_gas_fast + BLOCK - 1) / BLOCK;
   hipStream_t st = li.stream;
-  auto mark = [&](int k, int which) {
+  const bool two = li.side != nullptr;
+  hipStream_t sw = two ? li.side : st;  // stream of the wall and solid kernels
+  auto mark = [&](int k, int which, hipStream_t s) {
     if (li.events) {
-      (void)hipEventRecord(li.events[2 * k + which], st);
+      (void)hipEventRecord(li.events[2 * k + which], s);
       li.recorded[k] = true;
     }
   };
   const dim3 blk(BLOCK);
-  mark(K_WALL_ID, 0);
-  if (gwf > 0) hipLaunchKernelGGL((k_wall<true, real, PT, D, NS>), dim3(xcd_grid(gwf)), blk, 0, st, p, b, cur);
-  if (gws > 0) hipLaunchKernelGGL((k_wall<false, real, PT, D, NS>), dim3(xcd_grid(gws)), blk, 0, st, p, b, cur);
-  mark(K_WALL_ID, 1);
-  mark(K_MOMENTS_ID, 0);
+  if (two) {
+    // everything enqueued before on the main stream (the previous step's
+    // collision among it) precedes this step's wall kernel
+    (void)hipEventRecord(li.ev_fork, st);
+    (void)hipStreamWaitEvent(sw, li.ev_fork, 0);
+  }
+  mark(K_WALL_ID, 0, sw);
+  if (gwf > 0) hipLaunchKernelGGL((k_wall<true, real, PT, D, NS>), dim3(xcd_grid(gwf)), blk, 0, sw, p, b, cur);
+  if (gws > 0) hipLaunchKernelGGL((k_wall<false, real, PT, D, NS>), dim3(xcd_grid(gws)), blk, 0, sw, p, b, cur);
+  mark(K_WALL_ID, 1, sw);
+  if (two) (void)hipEventRecord(li.ev_wall, sw);
+  if (two && li.n_solid > 0) {
+    const int tiles = solid_tiles<D>(p.nx, p.ny, p.nz);
+    mark(K_SOLID_ID, 0, sw);
+    hipLaunchKernelGGL((k_solid<real, PT, D>), dim3(tiles), blk, 0, sw, p, b, cur);
+    mark(K_SOLID_ID, 1, sw);
+  }
+  mark(K_MOMENTS_ID, 0, st);
   if (ggf > 0) hipLaunchKernelGGL((k_moments<true, real, PT, D, NS>), dim3(xcd_grid(ggf)), blk, 0, st, p, b, cur);
   if (ggs > 0) hipLaunchKernelGGL((k_moments<false, real, PT, D, NS>), dim3(xcd_grid(ggs)), blk, 0, st, p, b, cur);
-  mark(K_MOMENTS_ID, 1);
-  mark(K_COLLIDE_ID, 0);
+  mark(K_MOMENTS_ID, 1, st);
+  if (two) (void)hipStreamWaitEvent(st, li.ev_wall, 0);
+  mark(K_COLLIDE_ID, 0, st);
   const int gg = (p.n_gas + BLOCK - 1) / BLOCK;
   if (gg > 0) hipLaunchKernelGGL((k_collide<real, PT, D, NS>), dim3(xcd_grid(gg)), blk, 0, st, p, b, cur);
-  mark(K_COLLIDE_ID, 1);
-  if (li.n_solid > 0) {
+  mark(K_COLLIDE_ID, 1, st);
+  if (two) {
+    // join: the step is complete on the main stream
+    (void)hipEventRecord(li.ev_solid, sw);
+    (void)hipStreamWaitEvent(st, li.ev_solid, 0);
+  } else if (li.n_solid > 0) {
     const int tiles = solid_tiles<D>(p.nx, p.ny, p.nz);
-    mark(K_SOLID_ID, 0);
+    mark(K_SOLID_ID, 0, st);
     hipLaunchKernelGGL((k_solid<real, PT, D>), dim3(tiles), blk, 0, st, p, b, cur);
-    mark(K_SOLID_ID, 1);
+    mark(K_SOLID_ID, 1, st);
   }
   return hipGetLastError();
 }

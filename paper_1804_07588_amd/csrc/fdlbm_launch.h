@@ -14,6 +14,10 @@ struct LaunchInfo {
   int n_solid;
   hipEvent_t *events;  // 2 per kernel id (start, stop) or null
   bool recorded[K_NUM];  // set by the launcher for the ids it recorded
+  // optional second stream: the wall and solid kernels run there, beside the
+  // moments and collision kernels on `stream` (null: one stream)
+  hipStream_t side;
+  hipEvent_t ev_fork, ev_wall, ev_solid;
 };
 
 // Batched launches (many samples per launch): per launch kind, a device work

@@ -31,7 +31,7 @@ EXPORTS = ["fdlbm_create", "fdlbm_destroy", "fdlbm_last_error", "fdlbm_set_geome
            "fdlbm_workspace_bytes", "fdlbm_bind_workspace", "fdlbm_init_fields", "fdlbm_step",
            "fdlbm_sync", "fdlbm_observe", "fdlbm_get_field", "fdlbm_state_bytes",
            "fdlbm_save_state", "fdlbm_load_state", "fdlbm_set_profiling", "fdlbm_kernel_times",
-           "fdlbm_counts", "fdlbm_residual", "fdlbm_batch_create", "fdlbm_batch_destroy",
+           "fdlbm_counts", "fdlbm_residual", "fdlbm_set_overlap", "fdlbm_batch_create", "fdlbm_batch_destroy",
            "fdlbm_batch_last_error", "fdlbm_batch_workspace_bytes", "fdlbm_batch_bind_workspace",
            "fdlbm_batch_set_active", "fdlbm_batch_step", "fdlbm_batch_set_grid",
            "fdlbm_batch_get_grid", "fdlbm_batch_autotune"]
@@ -102,6 +102,7 @@ def lib() -> ct.CDLL:
         L.fdlbm_kernel_times.argtypes = [vp, dp, ct.POINTER(i64)]
         L.fdlbm_counts.argtypes = [vp, ct.POINTER(i64), ct.POINTER(i64), ct.POINTER(i64)]
         L.fdlbm_residual.argtypes = [vp, dp]
+        L.fdlbm_set_overlap.argtypes = [vp, ct.c_int]
         ip = ct.POINTER(ct.c_int)
         L.fdlbm_batch_create.argtypes = [ct.POINTER(vp), ct.c_int, ct.POINTER(vp)]
         L.fdlbm_batch_destroy.argtypes = [vp]
@@ -230,6 +231,9 @@ class Sim:
         r = np.zeros(5)
         self._check(lib().fdlbm_residual(self.h, _d(r)))
         return dict(X=r[0], T=r[1], u=r[2], Ts=r[3], max=r[4])
+
+    def set_overlap(self, on: bool):
+        self._check(lib().fdlbm_set_overlap(self.h, 1 if on else 0))
 
     def set_profiling(self, on: bool):
         self._check(lib().fdlbm_set_profiling(self.h, 1 if on else 0))

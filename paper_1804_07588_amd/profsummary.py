@@ -57,11 +57,17 @@ def _db(d: str) -> str:
     return found[0]
 
 
-def kernel_stats(d: str) -> dict:
+def kernel_stats(d: str, skip: int = 0, take: int = 0) -> dict:
+    """Per kernel: launch count and durations.  With take > 0 only launches
+    skip .. skip + take - 1 of each kernel, in start order (a kernel with
+    fewer launches keeps all of them)."""
     c = sqlite3.connect(_db(d)).cursor()
-    agg = collections.defaultdict(list)
-    for name, s, e in c.execute("select name, start, end from kernels"):
-        agg[short(name)].append((e - s) / 1e3)
+    runs = collections.defaultdict(list)
+    for name, s, e in c.execute("select name, start, end from kernels order by start"):
+        runs[short(name)].append((e - s) / 1e3)
+    agg = {}
+    for k, v in runs.items():
+        agg[k] = v[skip:skip + take] if take > 0 and len(v) >= skip + take else v
     return {k: dict(calls=len(v), avg_us=sum(v) / len(v), min_us=min(v), max_us=max(v),
                     total_ms=sum(v) / 1e3) for k, v in agg.items()}
 
@@ -77,8 +83,9 @@ def counters(d: str, counter: str) -> dict:
 
 def main(argv):
     d, out_txt, out_json, calib_mib, cmd_kt, cmd_pmc = argv[1:7]
+    skip, take = (int(argv[7]), int(argv[8])) if len(argv) > 8 else (0, 0)
     calib_bytes = int(calib_mib) * 2**20
-    ks = kernel_stats(os.path.join(d, "kt"))
+    ks = kernel_stats(os.path.join(d, "kt"), skip, take)
     fetch = counters(os.path.join(d, "fetch"), "FETCH_SIZE")   # KiB per dispatch
     write = counters(os.path.join(d, "write"), "WRITE_SIZE")
     cal_f = calib_bytes / (fetch["k_copy_words"] * 1024)
@@ -86,8 +93,11 @@ def main(argv):
     lines = ["rocprofv3 summary of the packed-bed step (128^3 D3Q19, 5 species, FP32)", "",
              "kernel trace:    " + cmd_kt, "counter passes:  " + cmd_pmc,
              "summary:         python3 -m paper_1804_07588_amd.profsummary " + " ".join(argv[1:5]) +
-             " '<kernel trace command>' '<counter command>'",
-             "(rocprofv3 runs from the repository root after cd /tmp && export TMPDIR=/tmp)", "",
+             " '<kernel trace command>' '<counter command>'" + (f" {skip} {take}" if take else ""),
+             "(rocprofv3 runs from the repository root after cd /tmp && export TMPDIR=/tmp)",
+             (f"durations: launches {skip} .. {skip + take - 1} of each kernel, the pass of bench.py in which "
+              "the kernels run one after the other (its timed pass overlaps the wall and solid kernels "
+              "with the others)" if take else "durations: every launch"), "",
              f"calibration: k_copy_words over {calib_mib} MiB reads and writes {calib_bytes} B;",
              f"  FETCH_SIZE reports {fetch['k_copy_words'] * 1024:.4g} B -> factor {cal_f:.3f}",
              f"  WRITE_SIZE reports {write['k_copy_words'] * 1024:.4g} B -> factor {cal_w:.3f}", "",
