@@ -302,6 +302,11 @@ int fdlbm_batch_step(fdlbm_batch *b, int64_t n_steps);
 int fdlbm_batch_set_grid(fdlbm_batch *b, const int *grid, int graph_steps);
 int fdlbm_batch_get_grid(const fdlbm_batch *b, int *grid, int *graph_steps);
 
+/* As fdlbm_set_overlap for the batched steps (default on): the wall and
+ * solid launches run on a second stream beside the moments and collision
+ * launches, inside the captured graphs too.  Drops captured graphs. */
+int fdlbm_batch_set_overlap(fdlbm_batch *b, int enable);
+
 /* Autotuner of the launch shapes: for each candidate grid (256 ... 16384
  * workgroups, capped at one workgroup per block of work), every launch kind
  * is timed with HIP events over `steps` steps after one warm-up step, and each

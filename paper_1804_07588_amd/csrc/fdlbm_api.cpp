@@ -1056,6 +1056,10 @@ struct fdlbm_batch {
   int graph_steps = 20;
   hipGraphExec_t exec[2] = {nullptr, nullptr};  // one per starting parity
   bool bound = false;
+  // second stream for the wall and solid launches of a full step
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_wall = nullptr, ev_solid = nullptr;
+  bool overlap = true;
 };
 
 static int bset_err(fdlbm_batch *b, int code, const char *fmt, ...) {
@@ -1152,6 +1156,16 @@ int fdlbm_batch_create(fdlbm_ctx *const *ctxs, int n, fdlbm_batch **out) {
   // default persistent grids: every logical block its own workgroup up to
   // 8 per CU (256 CUs), a multiple of the 8 XCDs
   for (int k = 0; k < BL_NUM; ++k) b->grid[k] = round8(std::min(b->max_items[k], 2048));
+  // a non-blocking second stream at the default priority (ordered by events
+  // only); without it the batched steps run on one stream
+  if (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_wall, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_solid, hipEventDisableTiming) != hipSuccess) {
+    if (b->side) (void)hipStreamDestroy(b->side);
+    b->side = nullptr;
+    (void)hipGetLastError();
+  }
   *out = b;
   return FDLBM_OK;
 }
@@ -1159,6 +1173,12 @@ int fdlbm_batch_create(fdlbm_ctx *const *ctxs, int n, fdlbm_batch **out) {
 void fdlbm_batch_destroy(fdlbm_batch *b) {
   if (!b) return;
   batch_drop_graphs(b);
+  if (b->side) {
+    (void)hipStreamSynchronize(b->side);
+    (void)hipStreamDestroy(b->side);
+  }
+  for (hipEvent_t e : {b->ev_fork, b->ev_wall, b->ev_solid})
+    if (e) (void)hipEventDestroy(e);
   delete b;
 }
 
@@ -1251,6 +1271,13 @@ int fdlbm_batch_set_grid(fdlbm_batch *b, const int *grid, int graph_steps) {
   return FDLBM_OK;
 }
 
+int fdlbm_batch_set_overlap(fdlbm_batch *b, int enable) {
+  if (!b) return FDLBM_E_INVALID;
+  b->overlap = enable != 0;
+  batch_drop_graphs(b);
+  return FDLBM_OK;
+}
+
 int fdlbm_batch_get_grid(const fdlbm_batch *b, int *grid, int *graph_steps) {
   if (!b) return FDLBM_E_INVALID;
   if (grid)
@@ -1271,6 +1298,12 @@ static hipError_t batch_launch(fdlbm_batch *b, int cur, unsigned mask) {
   }
   bl.count = (const int *)(b->ws + b->off_count);
   bl.stream = b->stream;
+  // the second stream only for whole steps (the autotuner times single kinds)
+  const bool whole = mask == (1u << BL_NUM) - 1;
+  bl.side = whole && b->overlap ? b->side : nullptr;
+  bl.ev_fork = b->ev_fork;
+  bl.ev_wall = b->ev_wall;
+  bl.ev_solid = b->ev_solid;
   return (hipError_t)with_prec(b->ctx[0], [&](auto tag) {
     using Tg = decltype(tag);
     return (int)launch_batch_step<typename Tg::real, typename Tg::pop>(b->D, b->ns, bl, cur);

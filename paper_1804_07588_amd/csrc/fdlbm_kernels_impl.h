@@ -1385,31 +1385,51 @@ inline hipError_t step_impl(const Params<real> &p, const Bufs<real, PT> &b, int 
   return hipGetLastError();
 }
 
+// A batched step: the launch kinds in step order; with a side stream the
+// wall and solid kinds run there beside the moments and collision kinds (the
+// same dependencies as the single-domain step).
 template <typename real, typename PT, int D, int NS>
 inline hipError_t batch_step_impl(const BatchLaunch &bl, int cur) {
   const dim3 blk(BLOCK);
   const auto *P = static_cast<const Params<real> *>(bl.params);
   const auto *B = static_cast<const Bufs<real, PT> *>(bl.bufs);
   hipStream_t st = bl.stream;
+  const bool two = bl.side != nullptr;
+  hipStream_t sw = two ? bl.side : st;
   auto go = [&](int k) { return bl.grid[k] > 0 && bl.max_items[k] > 0; };
+  if (two) {
+    (void)hipEventRecord(bl.ev_fork, st);
+    (void)hipStreamWaitEvent(sw, bl.ev_fork, 0);
+  }
   if (go(BL_WALL_FAST))
-    hipLaunchKernelGGL((kb_wall<true, real, PT, D, NS>), dim3(bl.grid[BL_WALL_FAST]), blk, 0, st, P, B,
+    hipLaunchKernelGGL((kb_wall<true, real, PT, D, NS>), dim3(bl.grid[BL_WALL_FAST]), blk, 0, sw, P, B,
                        bl.items[BL_WALL_FAST], bl.count + BL_WALL_FAST, cur);
   if (go(BL_WALL_SLOW))
-    hipLaunchKernelGGL((kb_wall<false, real, PT, D, NS>), dim3(bl.grid[BL_WALL_SLOW]), blk, 0, st, P, B,
+    hipLaunchKernelGGL((kb_wall<false, real, PT, D, NS>), dim3(bl.grid[BL_WALL_SLOW]), blk, 0, sw, P, B,
                        bl.items[BL_WALL_SLOW], bl.count + BL_WALL_SLOW, cur);
+  if (two) {
+    (void)hipEventRecord(bl.ev_wall, sw);
+    if (go(BL_SOLID))
+      hipLaunchKernelGGL((kb_solid<real, PT, D>), dim3(bl.grid[BL_SOLID]), blk, 0, sw, P, B, bl.items[BL_SOLID],
+                         bl.count + BL_SOLID, cur);
+    (void)hipEventRecord(bl.ev_solid, sw);
+  }
   if (go(BL_GAS_FAST))
     hipLaunchKernelGGL((kb_moments<true, real, PT, D, NS>), dim3(bl.grid[BL_GAS_FAST]), blk, 0, st, P, B,
                        bl.items[BL_GAS_FAST], bl.count + BL_GAS_FAST, cur);
   if (go(BL_GAS_SLOW))
     hipLaunchKernelGGL((kb_moments<false, real, PT, D, NS>), dim3(bl.grid[BL_GAS_SLOW]), blk, 0, st, P, B,
                        bl.items[BL_GAS_SLOW], bl.count + BL_GAS_SLOW, cur);
+  if (two) (void)hipStreamWaitEvent(st, bl.ev_wall, 0);
   if (go(BL_COLLIDE))
     hipLaunchKernelGGL((kb_collide<real, PT, D, NS>), dim3(bl.grid[BL_COLLIDE]), blk, 0, st, P, B,
                        bl.items[BL_COLLIDE], bl.count + BL_COLLIDE, cur);
-  if (go(BL_SOLID))
+  if (two) {
+    (void)hipStreamWaitEvent(st, bl.ev_solid, 0);
+  } else if (go(BL_SOLID)) {
     hipLaunchKernelGGL((kb_solid<real, PT, D>), dim3(bl.grid[BL_SOLID]), blk, 0, st, P, B, bl.items[BL_SOLID],
                        bl.count + BL_SOLID, cur);
+  }
   return hipGetLastError();
 }
 

@@ -34,6 +34,9 @@ struct BatchLaunch {
   int max_items[BL_NUM];
   int grid[BL_NUM];
   hipStream_t stream;
+  // optional second stream for the wall and solid launches (null: one stream)
+  hipStream_t side;
+  hipEvent_t ev_fork, ev_wall, ev_solid;
 };
 
 template <typename real, typename PT, int D>

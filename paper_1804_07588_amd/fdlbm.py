@@ -34,7 +34,7 @@ EXPORTS = ["fdlbm_create", "fdlbm_destroy", "fdlbm_last_error", "fdlbm_set_geome
            "fdlbm_counts", "fdlbm_residual", "fdlbm_set_overlap", "fdlbm_batch_create", "fdlbm_batch_destroy",
            "fdlbm_batch_last_error", "fdlbm_batch_workspace_bytes", "fdlbm_batch_bind_workspace",
            "fdlbm_batch_set_active", "fdlbm_batch_step", "fdlbm_batch_set_grid",
-           "fdlbm_batch_get_grid", "fdlbm_batch_autotune"]
+           "fdlbm_batch_get_grid", "fdlbm_batch_autotune", "fdlbm_batch_set_overlap"]
 BATCH_KINDS = ["wall_fast", "wall_slow", "gas_fast", "gas_slow", "collide", "solid"]
 
 
@@ -116,6 +116,7 @@ def lib() -> ct.CDLL:
         L.fdlbm_batch_set_grid.argtypes = [vp, ip, ct.c_int]
         L.fdlbm_batch_get_grid.argtypes = [vp, ip, ip]
         L.fdlbm_batch_autotune.argtypes = [vp, ct.c_int, ip]
+        L.fdlbm_batch_set_overlap.argtypes = [vp, ct.c_int]
         _lib = L
     return _lib
 
@@ -300,6 +301,9 @@ class Batch:
         if grid is not None:
             g = (ct.c_int * len(BATCH_KINDS))(*[int(v) for v in grid])
         self._check(lib().fdlbm_batch_set_grid(self.h, g, int(graph_steps)))
+
+    def set_overlap(self, on: bool):
+        self._check(lib().fdlbm_batch_set_overlap(self.h, 1 if on else 0))
 
     def grid(self) -> tuple[list, int]:
         g = (ct.c_int * len(BATCH_KINDS))()

@@ -105,9 +105,11 @@ def test_batch_bitwise_equals_single(fd, stream, lattice, prec):
     cfgs = bed_cfgs() if lattice == 3 else channel_cfgs()
     print(f"[batch] lattice {lattice} {prec} samples {len(cfgs)}", flush=True)
     ref = make(fd, cfgs, precision)
+    for r in ref:
+        r.set_overlap(False)  # the reference: one stream, kernels in sequence
     bat = make(fd, cfgs, precision, stream)
     b = fd.Batch(bat)
-    b.set_grid(graph_steps=4)
+    b.set_grid(graph_steps=4)  # the batch: wall and solid on a second stream
     # 10 steps: two graph replays and two direct launches
     b.step(10)
     for s in ref:
