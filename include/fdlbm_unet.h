@@ -5,8 +5,8 @@
  * maps a geometry (solid mask) and the flow state of a packed bed to its
  * steady mole fractions, temperature and velocity.  Its prediction only
  * initialises the fields of the lattice-Boltzmann solve (fdlbm_init_fields),
- * which then relaxes them to the steady state: the method itself stays the
- * judge of the result.  This is an addition to the paper's method (which has
+ * which then relaxes them to the steady state: the method itself decides
+ * the result.  This is an addition to the paper's method (which has
  * no learned component), not a reading of it.
  *
  * Network (cube edge R, a multiple of 4, >= 16; tensors channels-last
