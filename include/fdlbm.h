@@ -146,6 +146,13 @@ int fdlbm_set_species(fdlbm_ctx *ctx, const double *M, const double *mu0, double
                       const double *Djk0, double D_T_exp, double D_p_exp, double T_ref,
                       double p_ref, double Pr, unsigned corr_flags);
 
+/* Per-species Prandtl numbers Pr_j (> 0, n_species values; NULL: every
+ * species at the Pr of fdlbm_set_species, which also resets them).  The
+ * Prandtl correction of Eq.(19)-(21) then uses q^Pr_j = (D+2)(1/Pr_j - 1)
+ * tau1_j C_j T grad T / M_j for species j: the per-species extension Sec. 3
+ * mentions after Eq.(21).  Call after fdlbm_set_species. */
+int fdlbm_set_prandtl(fdlbm_ctx *ctx, const double *Pr_j);
+
 /* Solid (Eq.(45)-(47)): thermal diffusivity alpha_s (0 <= alpha_s <= 1/(2D),
  * the forward-Euler bound, else FDLBM_E_INVALID), volumetric heat capacity
  * C_s > 0, and T_bc6[6] Dirichlet temperatures of the closed domain faces

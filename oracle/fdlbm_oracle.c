@@ -40,6 +40,7 @@ struct oracle_sim {
   /* species and transport */
   double M[MAXS], cj[MAXS], sj[MAXS], mu0[MAXS], mu_T_exp, Djk0[MAXS * MAXS], D_T_exp,
       D_p_exp, T_ref, p_ref, Pr;
+  double Pr_j[MAXS]; /* per-species Prandtl numbers (all Pr unless set separately) */
   unsigned flags;
   /* solid */
   double alpha_s, C_s, T_bc[6];
@@ -556,8 +557,21 @@ int oracle_set_species(oracle_sim *s, const double *M, const double *mu0, double
   s->T_ref = T_ref;
   s->p_ref = p_ref;
   s->Pr = Pr;
+  for (int j = 0; j < MAXS; ++j) s->Pr_j[j] = Pr;
   s->flags = flags;
   s->species_set = 1;
+  return 0;
+}
+
+/* Per-species Prandtl numbers (Sec. 3, the extension noted after Eq.(21));
+ * NULL restores the common value of oracle_set_species. */
+int oracle_set_prandtl(oracle_sim *s, const double *Pr_j) {
+  if (!s) return fail(s, "null argument");
+  for (int j = 0; j < s->ns; ++j) {
+    const double v = Pr_j ? Pr_j[j] : s->Pr;
+    if (!(v > 0)) return fail(s, "Prandtl numbers must be positive");
+  }
+  for (int j = 0; j < s->ns; ++j) s->Pr_j[j] = Pr_j ? Pr_j[j] : s->Pr;
   return 0;
 }
 
@@ -997,20 +1011,21 @@ static void collide(oracle_sim *s) {
         for (int a = 0; a < D; ++a)
           for (int b = 0; b < D; ++b) Y[a] += 0.5 * (Rdev(s, j, &nbp[b], a, b) - Rdev(s, j, &nbm[b], a, b));
       }
-      if ((s->flags & F_PR) && s->Pr != 1.0) {
+      if ((s->flags & F_PR) && s->Pr_j[j] != 1.0) {
         /* Eq.(19)-(21): Phi^Pr = phi_ji d_a q^Pr_ja with, reading, the species
          * heat capacity c_p,j = (D+2)/(2 M_j), so
-         * q^Pr_j = (D+2)(1/Pr - 1) tau1_j C_j T dT / M_j (zero at Pr = 1);
-         * compact face-flux form with arithmetic face averages; wall faces carry
-         * no correction flux (gas-solid exchange is the kinetic wall's). */
-        double Kx = (D + 2.0) * (1.0 / s->Pr - 1.0) * s->tau1[(size_t)j * n + x] *
-                    me.rho[j] / s->M[j] * me.T / s->M[j];
+         * q^Pr_j = (D+2)(1/Pr_j - 1) tau1_j C_j T dT / M_j (zero at Pr_j = 1;
+         * Pr_j = Pr for every species unless set per species, the extension
+         * Sec. 3 mentions after Eq.(21)); compact face-flux form with
+         * arithmetic face averages; wall faces carry no correction flux
+         * (gas-solid exchange is the kinetic wall's). */
+        const double kprj = (D + 2.0) * (1.0 / s->Pr_j[j] - 1.0);
+        double Kx = kprj * s->tau1[(size_t)j * n + x] * me.rho[j] / s->M[j] * me.T / s->M[j];
         for (int a = 0; a < D; ++a) {
           const nbstate *nb[2] = {&nbp[a], &nbm[a]};
           for (int q = 0; q < 2; ++q) {
             if (nb[q]->is_wall || nb[q]->missing) continue;
-            double Kn = (D + 2.0) * (1.0 / s->Pr - 1.0) * nb[q]->tau1[j] * nb[q]->rho[j] / s->M[j] *
-                        nb[q]->T / s->M[j];
+            double Kn = kprj * nb[q]->tau1[j] * nb[q]->rho[j] / s->M[j] * nb[q]->T / s->M[j];
             e += 0.5 * (Kx + Kn) * (nb[q]->T - me.T);
           }
         }

@@ -58,6 +58,8 @@ int oracle_set_geometry(oracle_sim *s, const uint8_t *mask, int inout);
 int oracle_set_species(oracle_sim *s, const double *M, const double *mu0, double mu_T_exp,
                        const double *Djk0, double D_T_exp, double D_p_exp, double T_ref,
                        double p_ref, double Pr, unsigned flags);
+/* per-species Prandtl numbers (NULL: every species at the common Pr) */
+int oracle_set_prandtl(oracle_sim *s, const double *Pr_j);
 int oracle_set_solid(oracle_sim *s, double alpha_s, double C_s, const double *T_bc6);
 int oracle_set_reaction(oracle_sim *s, const double *nu, const double *order, double k0,
                         double ea, double T_ref, double dH, int wall_mode, double T_iso,

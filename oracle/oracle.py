@@ -65,6 +65,7 @@ def lib():
                                          ct.c_double, ct.c_double, ct.c_double, ct.c_double,
                                          ct.c_uint]
         L.oracle_set_solid.argtypes = [ct.c_void_p, ct.c_double, ct.c_double, dp]
+        L.oracle_set_prandtl.argtypes = [ct.c_void_p, dp]
         L.oracle_set_reaction.argtypes = [ct.c_void_p, dp, dp, ct.c_double, ct.c_double,
                                           ct.c_double, ct.c_double, ct.c_int, ct.c_double,
                                           ct.c_double, ct.c_int]
@@ -157,6 +158,9 @@ class OracleSim:
         self._check(L.oracle_set_species(h, _d(M), _d(mu0), sp["mu_T_exp"], _d(Djk), sp["D_T_exp"],
                                          sp["D_p_exp"], sp["T_ref"], sp["p_ref"], sp["Pr"],
                                          int(sp["flags"])))
+        if sp.get("Pr_j") is not None:
+            prj = _arr(sp["Pr_j"])
+            self._check(L.oracle_set_prandtl(h, _d(prj)))
         so = cfg["solid"]
         tbc = _arr(so["T_bc"])
         self._check(L.oracle_set_solid(h, so["alpha_s"], so["C_s"], _d(tbc)))

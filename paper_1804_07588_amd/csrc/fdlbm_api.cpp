@@ -33,6 +33,7 @@ struct fdlbm_ctx {
   // parameters (double on the host)
   double M[MAXS]{}, mu0[MAXS]{}, mu_T_exp = 0, Djk0[MAXS * MAXS]{}, D_T_exp = 0, D_p_exp = 0,
          T_ref = 1.0 / 3, p_ref = 1.0 / 3, Pr = 1;
+  double Pr_j[MAXS] = {1, 1, 1, 1, 1, 1, 1, 1};  // per-species Prandtl numbers
   unsigned flags = FDLBM_CORR_ALL;
   double alpha_s = 0, C_s = 1, T_bc[6];
   double nu[MAXS]{}, order[MAXS]{}, k0 = 0, ea = 0, T_ref_rxn = 1.0 / 3, dH = 0, T_iso = 1.0 / 3,
@@ -272,7 +273,7 @@ static Params<real> params(const fdlbm_ctx *c) {
   p.D_p_exp = (real)c->D_p_exp;
   p.T_ref = (real)c->T_ref;
   p.p_ref = (real)c->p_ref;
-  p.kpr = (real)((c->D + 2.0) * (1.0 / c->Pr - 1.0));
+  for (int j = 0; j < c->ns; ++j) p.kprj[j] = (real)((c->D + 2.0) * (1.0 / c->Pr_j[j] - 1.0));
   p.alpha_s = (real)c->alpha_s;
   p.C_s = (real)c->C_s;
   p.invCs = (real)(1.0 / c->C_s);
@@ -546,8 +547,20 @@ int fdlbm_set_species(fdlbm_ctx *c, const double *M, const double *mu0, double m
   c->T_ref = T_ref;
   c->p_ref = p_ref;
   c->Pr = Pr;
+  for (int j = 0; j < MAXS; ++j) c->Pr_j[j] = Pr;
   c->flags = flags;
   c->species_set = true;
+  return FDLBM_OK;
+}
+
+int fdlbm_set_prandtl(fdlbm_ctx *c, const double *Pr_j) {
+  if (!c) return FDLBM_E_INVALID;
+  if (!c->species_set) return set_err(c, FDLBM_E_STATE, "set the species first");
+  for (int j = 0; j < c->ns; ++j) {
+    const double v = Pr_j ? Pr_j[j] : c->Pr;
+    if (!(v > 0)) return set_err(c, FDLBM_E_INVALID, "Prandtl numbers must be positive");
+  }
+  for (int j = 0; j < c->ns; ++j) c->Pr_j[j] = Pr_j ? Pr_j[j] : c->Pr;
   return FDLBM_OK;
 }
 

@@ -92,7 +92,7 @@ struct Params {
   real wilke[MAXS][MAXS];          // phi_jk of Eq.(15) (temperature independent)
   real invD0[MAXS][MAXS];          // 1 / Djk0
   real D_T_exp, D_p_exp, T_ref, p_ref;
-  real kpr;                        // (D+2)(1/Pr - 1)
+  real kprj[MAXS];                 // (D+2)(1/Pr_j - 1) per species
   // solid
   real alpha_s, invCs, C_s;
   real T_bc[6];

@@ -737,7 +737,7 @@ __device__ inline void collide_node(const Params<real> &p, const Bufs<real, PT> 
   const real kdiff = ((p.flags & 1u) && NS > 1) ? real(1) : real(0);
   const real kvisc = (p.flags & 2u) ? real(1) : real(0);
   const real kener = (p.flags & 4u) ? real(1) : real(0);
-  const real kpr = (p.flags & 8u) ? p.kpr : real(0);
+  const bool prc = (p.flags & 8u) != 0;  // Prandtl correction on
   // ---- source moments of every species ----
   real m[NS][D], Pd[NS][D], Po[NS][3], Y[NS][D], e[NS];
 #pragma unroll
@@ -801,6 +801,7 @@ __device__ inline void collide_node(const Params<real> &p, const Bufs<real, PT> 
       for (int c = 0; c < D; ++c)
         Y[j][c] += kener * real(0.5) * (r_dev<real, D>(rp, iM, up, Tp, c, a) - r_dev<real, D>(rm, iM, um, Tm, c, a));
       // Eq.(19)-(21), face-flux form; wall faces carry no correction flux
+      const real kpr = prc ? p.kprj[j] : real(0);
       const real Kx = kpr * me.v[fr_tau1(D, j)] * rj * iM * Tt * iM;
       const real ep = real(0.5) * (Kx + kpr * nr[0].v[fr_tau1(D, j)] * rp * iM * Tp * iM) * (Tp - Tt);
       const real em = real(0.5) * (Kx + kpr * nr[1].v[fr_tau1(D, j)] * rm * iM * Tm * iM) * (Tm - Tt);

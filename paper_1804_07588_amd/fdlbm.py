@@ -31,7 +31,7 @@ EXPORTS = ["fdlbm_create", "fdlbm_destroy", "fdlbm_last_error", "fdlbm_set_geome
            "fdlbm_workspace_bytes", "fdlbm_bind_workspace", "fdlbm_init_fields", "fdlbm_step",
            "fdlbm_sync", "fdlbm_observe", "fdlbm_get_field", "fdlbm_state_bytes",
            "fdlbm_save_state", "fdlbm_load_state", "fdlbm_set_profiling", "fdlbm_kernel_times",
-           "fdlbm_counts", "fdlbm_residual", "fdlbm_set_overlap", "fdlbm_batch_create", "fdlbm_batch_destroy",
+           "fdlbm_counts", "fdlbm_residual", "fdlbm_set_overlap", "fdlbm_set_prandtl", "fdlbm_batch_create", "fdlbm_batch_destroy",
            "fdlbm_batch_last_error", "fdlbm_batch_workspace_bytes", "fdlbm_batch_bind_workspace",
            "fdlbm_batch_set_active", "fdlbm_batch_step", "fdlbm_batch_set_grid",
            "fdlbm_batch_get_grid", "fdlbm_batch_autotune", "fdlbm_batch_set_overlap"]
@@ -103,6 +103,7 @@ def lib() -> ct.CDLL:
         L.fdlbm_counts.argtypes = [vp, ct.POINTER(i64), ct.POINTER(i64), ct.POINTER(i64)]
         L.fdlbm_residual.argtypes = [vp, dp]
         L.fdlbm_set_overlap.argtypes = [vp, ct.c_int]
+        L.fdlbm_set_prandtl.argtypes = [vp, dp]
         ip = ct.POINTER(ct.c_int)
         L.fdlbm_batch_create.argtypes = [ct.POINTER(vp), ct.c_int, ct.POINTER(vp)]
         L.fdlbm_batch_destroy.argtypes = [vp]
@@ -162,6 +163,9 @@ class Sim:
         self._check(L.fdlbm_set_species(h, _d(M), _d(mu0), sp["mu_T_exp"], _d(Djk), sp["D_T_exp"],
                                         sp["D_p_exp"], sp["T_ref"], sp["p_ref"], sp["Pr"],
                                         int(sp["flags"])))
+        if sp.get("Pr_j") is not None:
+            prj = _arr(sp["Pr_j"])
+            self._check(L.fdlbm_set_prandtl(h, _d(prj)))
         so = cfg["solid"]
         tbc = _arr(so["T_bc"])
         self._check(L.fdlbm_set_solid(h, so["alpha_s"], so["C_s"], _d(tbc)))

@@ -221,3 +221,37 @@ def test_enthalpy_error_below_paper_level(oracle_lib):
     1e-5; the C1 channel (trace product species) stays well below it."""
     res, heat, _ = energy_residual(oracle_lib, W.channel_c1(), steps=300)
     assert abs(res) / heat < 1e-5
+
+
+@pytest.mark.parametrize("lattice", [2, 3])
+def test_species_prandtl_numbers_set_the_mixture_diffusivity(oracle_lib, lattice):
+    """Per-species Prandtl numbers (the extension noted after Eq.(21)): with
+    q^Pr_j built on Pr_j, kappa = sum_j (D+2) tau1_j C_j T / (2 M_j Pr_j), so
+    the isobaric thermal diffusivity of two identical-mass species is
+    tau1 T (X_1/Pr_1 + X_2/Pr_2): 1.5 tau1 T for X = (1/2, 1/2), Pr = (1/2, 1)."""
+    nx, tau1 = 128, 0.3
+    side = 1 if lattice == 2 else 2
+    cfg = one_species(nx, side, side if lattice == 3 else 1, lattice=lattice, tau1=tau1,
+                      periodic=(1, 1, 1), wall_mode=0)
+    sp = cfg["species"]
+    sp.update(M=[1.0, 1.0], mu0=[tau1 * T0] * 2, Djk0=[[0.0, 0.1], [0.1, 0.0]], Pr=1.0,
+              Pr_j=[0.5, 1.0])
+    cfg["reaction"].update(nu=[0.0, 0.0], order=[0.0, 0.0])
+    cfg["flow"]["X_in"] = [0.5, 0.5]
+    cfg["init"]["X"] = [0.5, 0.5]
+    init = W.uniform_init(cfg)
+    x = np.arange(cfg["nx"] * cfg["ny"] * cfg["nz"]) % nx
+    k = 2 * np.pi / nx
+    T = T0 * (1 + 0.001 * np.sin(k * x))
+    init["T"] = T
+    init["rho"][0] = init["rho"][1] = 0.5 * T0 / T   # uniform pressure and composition
+    sim = oracle_lib.OracleSim(cfg, init)
+    sim.step(300)
+
+    def amp():
+        return 2 * np.mean(sim.field(oracle_lib.OF_T) * np.sin(k * x))
+
+    a1 = amp()
+    sim.step(3000)
+    r = -np.log(amp() / a1) / 3000 / (1.5 * tau1 * T0 * k * k)
+    assert r == pytest.approx(1.0, abs=0.015)

@@ -134,6 +134,19 @@ def test_bed_3d_fp32(oracle_lib, fd):
     assert_errs(field_errors(o, g, fd, 5, 3), 1e-5, tol_rate=2e-5)
 
 
+@pytest.mark.parametrize("prec", ["F64", "F32"])
+def test_bed_3d_species_prandtl(oracle_lib, fd, prec):
+    """Per-species Prandtl numbers (fdlbm_set_prandtl) on the sphere pack."""
+    cfg = small_bed()
+    cfg["species"]["Pr_j"] = [0.5, 0.7, 0.9, 1.3, 0.8]
+    precision = getattr(fd, prec)
+    o, g = run_both(oracle_lib, fd, cfg, W.perturbed_init(cfg, 6, amp_u=0.005), 60, precision)
+    if prec == "F64":
+        assert_errs(field_errors(o, g, fd, 5, 3), 1e-10)
+    else:
+        assert_errs(field_errors(o, g, fd, 5, 3), 1e-5, tol_rate=2e-5)
+
+
 def test_c1_fp32(oracle_lib, fd):
     cfg = W.channel_c1()
     o, g = run_both(oracle_lib, fd, cfg, W.uniform_init(cfg), 1000, fd.F32)
