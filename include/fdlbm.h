@@ -159,6 +159,20 @@ int fdlbm_set_prandtl(fdlbm_ctx *ctx, const double *Pr_j);
  * (-x, +x, -y, +y, -z, +z; NaN = adiabatic; NULL = all adiabatic). */
 int fdlbm_set_solid(fdlbm_ctx *ctx, double alpha_s, double C_s, const double *T_bc6);
 
+/* Time scheme of the solid heat equation.  FDLBM_SOLID_EULER (default):
+ * forward Euler, Eq.(46)-(47), stable for alpha_s <= 1/(2D).
+ * FDLBM_SOLID_CN: Crank-Nicolson, the extension Sec. 5 recommends for larger
+ * alpha_s: T' - (alpha_s/2) L T' = T + (alpha_s/2) L T + wall sources/C_s,
+ * solved by Jacobi sweeps from T, as many as make the error bound
+ * (a D / (1 + a D))^k fall below 1e-15 (FP64) or 1e-8 (FP32 arithmetic)
+ * relative to the step (at most 5000); the Dirichlet-face heat is the mean
+ * of the old and new face fluxes.  Choose CN before fdlbm_set_solid with
+ * alpha_s > 1/(2D); switching back to Euler with such an alpha_s fails.
+ * Not available in batches (fdlbm_batch_create rejects such contexts). */
+#define FDLBM_SOLID_EULER 0
+#define FDLBM_SOLID_CN 1
+int fdlbm_set_solid_scheme(fdlbm_ctx *ctx, int scheme);
+
 /* Surface reaction (Eq.(50) generalised): molar rate per wall node and step
  * r = k0 exp[ea (1 - T_ref/T_w)] prod_j C_jw^order_j, species j produced at
  * nu_j per unit extent (nu < 0 reactants); orders must be integers 0..3.

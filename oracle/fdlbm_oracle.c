@@ -44,6 +44,7 @@ struct oracle_sim {
   unsigned flags;
   /* solid */
   double alpha_s, C_s, T_bc[6];
+  int solid_scheme; /* 0 forward Euler, 1 Crank-Nicolson */
   /* reaction */
   double nu[MAXS], order[MAXS], k0, ea, T_ref_rxn, dH, T_iso, tol;
   int wall_mode, max_iter;
@@ -577,12 +578,24 @@ int oracle_set_prandtl(oracle_sim *s, const double *Pr_j) {
 
 int oracle_set_solid(oracle_sim *s, double alpha_s, double C_s, const double *T_bc6) {
   if (!s) return fail(s, "null argument");
-  /* Eq.(46)-(47): forward Euler is stable only for alpha_s <= 1/(2D) */
-  if (!(alpha_s >= 0.0 && alpha_s <= 0.5 / s->D)) return fail(s, "alpha_s out of the stable range");
+  /* Eq.(46)-(47): forward Euler is stable only for alpha_s <= 1/(2D); the
+   * Crank-Nicolson scheme for any alpha_s */
+  if (!(alpha_s >= 0.0)) return fail(s, "alpha_s must be non-negative");
+  if (s->solid_scheme == 0 && alpha_s > 0.5 / s->D) return fail(s, "alpha_s out of the stable range");
   if (!(C_s > 0.0)) return fail(s, "C_s must be positive");
   s->alpha_s = alpha_s;
   s->C_s = C_s;
   for (int a = 0; a < 6; ++a) s->T_bc[a] = T_bc6 ? T_bc6[a] : NAN;
+  return 0;
+}
+
+/* Time scheme of the solid heat equation (Sec. 5: Crank-Nicolson is the
+ * recommended extension for alpha_s > 1/(2D)): 0 forward Euler, 1 CN. */
+int oracle_set_solid_scheme(oracle_sim *s, int scheme) {
+  if (!s) return fail(s, "null argument");
+  if (scheme != 0 && scheme != 1) return fail(s, "scheme must be 0 or 1");
+  if (scheme == 0 && s->alpha_s > 0.5 / s->D) return fail(s, "alpha_s out of the stable range");
+  s->solid_scheme = scheme;
   return 0;
 }
 
@@ -1115,6 +1128,86 @@ static void solid(oracle_sim *s) {
   }
 }
 
+/* 6b. Crank-Nicolson variant of the solid step (Sec. 5, recommended for
+ * alpha_s > 1/(2D)): the Laplacian (with the Dirichlet faces) averaged over
+ * the old and new temperature, the wall sources explicit,
+ *   T' - (a/2) L T' = T + (a/2) L T + (Q_rxn - dE_gas)/C_s,
+ * solved by Jacobi sweeps until no node changes by more than 2.5e-16 (1 + |T'|);
+ * boundary heat alpha_s C_s times the mean of the old and new face fluxes. */
+static double solid_lap(const oracle_sim *s, const double *T, int x, double *bflux, int *cnt,
+                        double *nbsum, double *bcsum) {
+  double lap = 0.0;
+  *bflux = 0.0;
+  *cnt = 0;
+  *nbsum = 0.0;
+  *bcsum = 0.0;
+  for (int a = 0; a < s->D; ++a)
+    for (int d = -1; d <= 1; d += 2) {
+      int nb = face_nbr(s, x, a, d);
+      if (nb < 0) {
+        double tb = s->T_bc[2 * a + (d > 0)];
+        if (!isnan(tb)) {
+          lap += tb - T[x];
+          *bflux += tb - T[x];
+          *bcsum += tb;
+          ++*cnt;
+        }
+      } else if (s->kind[nb] == K_SOLID || s->kind[nb] == K_WALL) {
+        lap += T[nb] - T[x];
+        *nbsum += T[nb];
+        ++*cnt;
+      }
+    }
+  return lap;
+}
+
+static void solid_cn(oracle_sim *s) {
+  int n = s->n;
+  double a = s->alpha_s;
+  double *rhs = malloc((size_t)n * sizeof(double));
+  double *X = malloc((size_t)n * sizeof(double));
+  double *Y = malloc((size_t)n * sizeof(double));
+  for (int x = 0; x < n; ++x) {
+    X[x] = s->Ts[x];
+    rhs[x] = s->Ts[x];
+    if (!(s->kind[x] == K_SOLID || s->kind[x] == K_WALL)) continue;
+    double bf, nbs, bcs;
+    int cnt;
+    double lap = solid_lap(s, s->Ts, x, &bf, &cnt, &nbs, &bcs);
+    rhs[x] = s->Ts[x] + 0.5 * a * lap;
+    if (s->kind[x] == K_WALL && s->wall_mode == 0) rhs[x] += (-s->dH * s->wall_r[x] - s->wall_dE[x]) / s->C_s;
+    s->bheat += 0.5 * a * s->C_s * bf;
+  }
+  for (int it = 0; it < 1000000; ++it) {
+    double dmax = 0.0;
+    for (int x = 0; x < n; ++x) {
+      Y[x] = X[x];
+      if (!(s->kind[x] == K_SOLID || s->kind[x] == K_WALL)) continue;
+      double bf, nbs, bcs;
+      int cnt;
+      (void)solid_lap(s, X, x, &bf, &cnt, &nbs, &bcs);
+      Y[x] = (rhs[x] + 0.5 * a * (nbs + bcs)) / (1.0 + 0.5 * a * cnt);
+      double dd = fabs(Y[x] - X[x]) / (1.0 + fabs(Y[x]));
+      if (dd > dmax) dmax = dd;
+    }
+    double *t = X;
+    X = Y;
+    Y = t;
+    if (dmax <= 2.5e-16) break; /* a couple of ulps: the fixed point in FP64 */
+  }
+  for (int x = 0; x < n; ++x) {
+    s->Tsn[x] = X[x];
+    if (!(s->kind[x] == K_SOLID || s->kind[x] == K_WALL)) continue;
+    double bf, nbs, bcs;
+    int cnt;
+    (void)solid_lap(s, X, x, &bf, &cnt, &nbs, &bcs);
+    s->bheat += 0.5 * a * s->C_s * bf;
+  }
+  free(rhs);
+  free(X);
+  free(Y);
+}
+
 /* 7. inlet (equilibrium at the prescribed state, velocity of the first
  * interior plane) and outlet, reading for Sec. 6: equilibrium at the inlet
  * pressure with the mole fractions, temperature and velocity of the last
@@ -1163,7 +1256,8 @@ int oracle_step(oracle_sim *s, int64_t n_steps) {
     wall_bc(s);
     moments(s);
     collide(s);
-    solid(s);
+    if (s->solid_scheme == 1) solid_cn(s);
+    else solid(s);
     inlet_outlet(s);
     for (int w = 0; w < s->n; ++w)
       if (s->kind[w] == K_WALL) {

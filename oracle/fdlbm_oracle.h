@@ -61,6 +61,8 @@ int oracle_set_species(oracle_sim *s, const double *M, const double *mu0, double
 /* per-species Prandtl numbers (NULL: every species at the common Pr) */
 int oracle_set_prandtl(oracle_sim *s, const double *Pr_j);
 int oracle_set_solid(oracle_sim *s, double alpha_s, double C_s, const double *T_bc6);
+/* solid time scheme: 0 forward Euler (alpha_s <= 1/(2D)), 1 Crank-Nicolson */
+int oracle_set_solid_scheme(oracle_sim *s, int scheme);
 int oracle_set_reaction(oracle_sim *s, const double *nu, const double *order, double k0,
                         double ea, double T_ref, double dH, int wall_mode, double T_iso,
                         double tol, int max_iter);

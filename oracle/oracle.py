@@ -66,6 +66,7 @@ def lib():
                                          ct.c_uint]
         L.oracle_set_solid.argtypes = [ct.c_void_p, ct.c_double, ct.c_double, dp]
         L.oracle_set_prandtl.argtypes = [ct.c_void_p, dp]
+        L.oracle_set_solid_scheme.argtypes = [ct.c_void_p, ct.c_int]
         L.oracle_set_reaction.argtypes = [ct.c_void_p, dp, dp, ct.c_double, ct.c_double,
                                           ct.c_double, ct.c_double, ct.c_int, ct.c_double,
                                           ct.c_double, ct.c_int]
@@ -163,6 +164,8 @@ class OracleSim:
             self._check(L.oracle_set_prandtl(h, _d(prj)))
         so = cfg["solid"]
         tbc = _arr(so["T_bc"])
+        if so.get("scheme", 0):
+            self._check(L.oracle_set_solid_scheme(h, int(so["scheme"])))
         self._check(L.oracle_set_solid(h, so["alpha_s"], so["C_s"], _d(tbc)))
         rx = cfg["reaction"]
         nu, order = _arr(rx["nu"]), _arr(rx["order"])

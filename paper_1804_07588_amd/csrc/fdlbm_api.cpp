@@ -36,6 +36,7 @@ struct fdlbm_ctx {
   double Pr_j[MAXS] = {1, 1, 1, 1, 1, 1, 1, 1};  // per-species Prandtl numbers
   unsigned flags = FDLBM_CORR_ALL;
   double alpha_s = 0, C_s = 1, T_bc[6];
+  int solid_scheme = FDLBM_SOLID_EULER;
   double nu[MAXS]{}, order[MAXS]{}, k0 = 0, ea = 0, T_ref_rxn = 1.0 / 3, dH = 0, T_iso = 1.0 / 3,
          tol = 1e-13;
   int wall_mode = 0, max_iter = 64;
@@ -58,6 +59,7 @@ struct fdlbm_ctx {
   // workspace
   char *ws = nullptr;
   size_t ws_bytes = 0;
+  size_t off_cnr = 0, off_cnt = 0;  // Crank-Nicolson solid buffers
   size_t off_G[2]{}, off_Gs = 0, off_FR = 0, off_FX = 0, off_Ts[2]{}, off_wr = 0, off_wde = 0, off_kind = 0, off_slot = 0,
          off_scls = 0, off_wem = 0, off_gl = 0, off_wl = 0, off_am = 0, off_aw = 0, off_ab = 0,
          off_part = 0, off_snap = 0, off_snapts = 0;
@@ -149,6 +151,8 @@ static void layout(fdlbm_ctx *c) {
   c->off_Ts[1] = take(n * b);
   c->off_wr = take(n * b);
   c->off_wde = take(n * b);
+  c->off_cnr = take(n * b);
+  c->off_cnt = take(n * b);
   c->off_kind = take(n);
   c->off_slot = take(n * 4);
   c->off_scls = take(nsl * 8);
@@ -182,6 +186,8 @@ static Bufs<real, PT> bufs(const fdlbm_ctx *c) {
   b.Ts[1] = (real *)(w + c->off_Ts[1]);
   b.wall_r = (real *)(w + c->off_wr);
   b.wall_dE = (real *)(w + c->off_wde);
+  b.cn_rhs = (real *)(w + c->off_cnr);
+  b.cn_tmp = (real *)(w + c->off_cnt);
   b.kind = (const uint8_t *)(w + c->off_kind);
   b.slot_of = (const int32_t *)(w + c->off_slot);
   b.scls = (const uint64_t *)(w + c->off_scls);
@@ -277,6 +283,17 @@ static Params<real> params(const fdlbm_ctx *c) {
   p.alpha_s = (real)c->alpha_s;
   p.C_s = (real)c->C_s;
   p.invCs = (real)(1.0 / c->C_s);
+  // Crank-Nicolson: Jacobi sweeps from T contract the error by at most
+  // rho = a D / (1 + a D) each (row sums of the iteration matrix), so enough
+  // sweeps take it below the arithmetic's rounding relative to the step
+  p.solid_cn = c->solid_scheme == FDLBM_SOLID_CN ? 1 : 0;
+  p.cn_iters = 0;
+  if (p.solid_cn) {
+    const double rho = c->alpha_s * c->D / (1.0 + c->alpha_s * c->D);
+    const double tol = c->d.precision == FDLBM_F64 ? 1e-15 : 1e-8;
+    p.cn_iters = rho > 0 ? (int)std::min(5000.0, std::ceil(std::log(tol) / std::log(rho))) : 1;
+    p.cn_iters = std::max(p.cn_iters, 1);
+  }
   for (int a = 0; a < 6; ++a) {
     p.has_bc[a] = !std::isnan(c->T_bc[a]);
     p.T_bc[a] = p.has_bc[a] ? (real)c->T_bc[a] : real(0);
@@ -566,12 +583,23 @@ int fdlbm_set_prandtl(fdlbm_ctx *c, const double *Pr_j) {
 
 int fdlbm_set_solid(fdlbm_ctx *c, double alpha_s, double C_s, const double *T_bc6) {
   if (!c) return FDLBM_E_INVALID;
-  if (!(alpha_s >= 0.0 && alpha_s <= 0.5 / c->D))
+  if (!(alpha_s >= 0.0)) return set_err(c, FDLBM_E_INVALID, "alpha_s must be non-negative");
+  if (c->solid_scheme == FDLBM_SOLID_EULER && alpha_s > 0.5 / c->D)
     return set_err(c, FDLBM_E_INVALID, "alpha_s must lie in [0, 1/(2D)] (forward-Euler stability)");
   if (!(C_s > 0.0)) return set_err(c, FDLBM_E_INVALID, "C_s must be positive");
   c->alpha_s = alpha_s;
   c->C_s = C_s;
   for (int a = 0; a < 6; ++a) c->T_bc[a] = T_bc6 ? T_bc6[a] : NAN;
+  return FDLBM_OK;
+}
+
+int fdlbm_set_solid_scheme(fdlbm_ctx *c, int scheme) {
+  if (!c) return FDLBM_E_INVALID;
+  if (scheme != FDLBM_SOLID_EULER && scheme != FDLBM_SOLID_CN)
+    return set_err(c, FDLBM_E_INVALID, "unknown solid scheme %d", scheme);
+  if (scheme == FDLBM_SOLID_EULER && c->alpha_s > 0.5 / c->D)
+    return set_err(c, FDLBM_E_INVALID, "alpha_s > 1/(2D) needs the Crank-Nicolson scheme");
+  c->solid_scheme = scheme;
   return FDLBM_OK;
 }
 
@@ -1132,6 +1160,7 @@ int fdlbm_batch_create(fdlbm_ctx *const *ctxs, int n, fdlbm_batch **out) {
     const fdlbm_ctx *c = ctxs[s];
     if (!c) return fail("null context");
     if (!c->initialized) return fail("every context needs initialised fields");
+    if (c->solid_scheme == FDLBM_SOLID_CN) return fail("Crank-Nicolson solids are not batched");
     if (c->D != ctxs[0]->D || c->ns != ctxs[0]->ns || c->d.precision != ctxs[0]->d.precision ||
         c->stream != ctxs[0]->stream)
       return fail("contexts differ in lattice, species count, precision or stream");

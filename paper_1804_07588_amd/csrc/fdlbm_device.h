@@ -95,6 +95,7 @@ struct Params {
   real kprj[MAXS];                 // (D+2)(1/Pr_j - 1) per species
   // solid
   real alpha_s, invCs, C_s;
+  int solid_cn, cn_iters;          // Crank-Nicolson solid: on, Jacobi sweeps per step
   real T_bc[6];
   int has_bc[6];
   // reaction
@@ -145,6 +146,7 @@ struct Bufs {
   real *Ts[2];        // solid temperature per node, double-buffered
   real *wall_r;       // molar rate per node (wall nodes) of the last step
   real *wall_dE;      // kinetic energy the wall gave the gas, per node, last step
+  real *cn_rhs, *cn_tmp;  // Crank-Nicolson solid: right-hand side and sweep buffer, per node
   const uint8_t *kind;       // node class per node
   const int32_t *slot_of;    // slot per node
   const uint64_t *scls;      // streaming class word per gas/wall slot

@@ -1009,10 +1009,16 @@ __global__ void __launch_bounds__(BLOCK, sizeof(real) == 4 ? 2 : 1) k_collide(Pa
 }
 
 // ===========================================================================
-// k_solid: forward-Euler heat step over an LDS tile with a one-node halo
+// k_solid: the heat step of the solid over an LDS tile with a one-node halo.
+// MODE 0: forward Euler, Tout = Tin + a L Tin + source.  The Crank-Nicolson
+// variant (the extension Sec. 5 recommends for a > 1/(2D)) solves
+// T' - (a/2) L T' = T + (a/2) L T + source by Jacobi sweeps: MODE 1 writes
+// that right-hand side, MODE 2 is one sweep Tin -> Tout, MODE 3 adds the
+// new temperature's half of the Dirichlet-face heat.
 // ===========================================================================
-template <typename real, typename PT, int D>
-__device__ __forceinline__ void solid_block(const Params<real> &p, const Bufs<real, PT> &b, int cur, int tile) {
+template <typename real, typename PT, int D, int MODE>
+__device__ __forceinline__ void solid_pass(const Params<real> &p, const Bufs<real, PT> &b, const real *Tin,
+                                           real *Tout, int tile) {
   constexpr int TX = SolidTile<D>::TX, TY = SolidTile<D>::TY, TZ = SolidTile<D>::TZ;
   constexpr int HX = TX + 2, HY = TY + 2, HZ = D == 3 ? TZ + 2 : 1;
   __shared__ real sT[HZ * HY * HX];
@@ -1024,7 +1030,6 @@ __device__ __forceinline__ void solid_block(const Params<real> &p, const Bufs<re
   const int by = bid % tilesY;
   const int bz = bid / tilesY;
   const int x0 = bx * TX - 1, y0 = by * TY - 1, z0 = D == 3 ? bz * TZ - 1 : 0;
-  const real *Ts = b.Ts[cur];
   for (int q = threadIdx.x; q < HZ * HY * HX; q += BLOCK) {
     const int hx = q % HX, hy = (q / HX) % HY, hz = q / (HX * HY);
     int x = x0 + hx, y = y0 + hy, z = z0 + hz;
@@ -1050,7 +1055,7 @@ __device__ __forceinline__ void solid_block(const Params<real> &p, const Bufs<re
       const uint8_t kd = b.kind[nd];
       if (kd == KIND_SOLID || kd == KIND_WALL) {
         k = 1;
-        v = Ts[nd];
+        v = Tin[nd];
       }
     }
     sK[q] = k;
@@ -1065,31 +1070,57 @@ __device__ __forceinline__ void solid_block(const Params<real> &p, const Bufs<re
     const int hc = (lz + (D == 3 ? 1 : 0)) * HY * HX + (ly + 1) * HX + (lx + 1);
     if (sK[hc] != 1) continue;
     const real T = sT[hc];
-    real lap = 0, bf = 0;
+    real lap = 0, bf = 0, nbs = 0, bcs = 0;
+    int cnt = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
       for (int d = -1; d <= 1; d += 2) {
         const int off = a == 0 ? d : (a == 1 ? d * HX : d * HX * HY);
         const uint8_t kn = sK[hc + off];
-        if (kn == 1) lap += sT[hc + off] - T;
-        else if (kn == 2) {
+        if (kn == 1) {
+          lap += sT[hc + off] - T;
+          nbs += sT[hc + off];
+          ++cnt;
+        } else if (kn == 2) {
           const int face = 2 * a + (d > 0 ? 1 : 0);
           if (p.has_bc[face]) {
             lap += p.T_bc[face] - T;
             bf += p.T_bc[face] - T;
+            bcs += p.T_bc[face];
+            ++cnt;
           }
         }
       }
     const int nd = x + p.nx * (y + p.ny * z);
-    real Tn = T + p.alpha_s * lap;
-    if (p.wall_mode == 0 && b.kind[nd] == KIND_WALL)
-      Tn += (-p.dH * b.wall_r[nd] - b.wall_dE[nd]) * p.invCs;
-    b.Ts[cur ^ 1][nd] = Tn;
-    bflux += (double)(p.alpha_s * p.C_s * bf);
+    if constexpr (MODE == 0 || MODE == 1) {
+      const real h = MODE == 0 ? p.alpha_s : real(0.5) * p.alpha_s;
+      real Tn = T + h * lap;
+      if (p.wall_mode == 0 && b.kind[nd] == KIND_WALL)
+        Tn += (-p.dH * b.wall_r[nd] - b.wall_dE[nd]) * p.invCs;
+      if constexpr (MODE == 0) Tout[nd] = Tn;
+      else b.cn_rhs[nd] = Tn;
+      bflux += (double)(h * p.C_s * bf);
+    } else if constexpr (MODE == 2) {
+      const real h = real(0.5) * p.alpha_s;
+      Tout[nd] = (b.cn_rhs[nd] + h * (nbs + bcs)) / (real(1) + h * real(cnt));
+    } else {
+      bflux += (double)(real(0.5) * p.alpha_s * p.C_s * bf);
+    }
   }
-  const double s = block_sum(bflux);
-  if (threadIdx.x == 0 && s != 0.0) b.acc_bheat[tile] += s;
+  if constexpr (MODE != 2) {
+    const double s = block_sum(bflux);
+    if (threadIdx.x == 0 && s != 0.0) b.acc_bheat[tile] += s;
+  }
+}
+template <typename real, typename PT, int D>
+__device__ __forceinline__ void solid_block(const Params<real> &p, const Bufs<real, PT> &b, int cur, int tile) {
+  solid_pass<real, PT, D, 0>(p, b, b.Ts[cur], b.Ts[cur ^ 1], tile);
+}
+template <typename real, typename PT, int D, int MODE>
+__global__ void __launch_bounds__(BLOCK) k_solid_pass(Params<real> p, Bufs<real, PT> b, const real *Tin,
+                                                      real *Tout) {
+  solid_pass<real, PT, D, MODE>(p, b, Tin, Tout, blockIdx.x);
 }
 template <typename real, typename PT, int D>
 __global__ void __launch_bounds__(BLOCK) k_solid(Params<real> p, Bufs<real, PT> b, int cur) {
@@ -1358,12 +1389,26 @@ inline hipError_t step_impl(const Params<real> &p, const Bufs<real, PT> &b, int 
   if (gws > 0) hipLaunchKernelGGL((k_wall<false, real, PT, D, NS>), dim3(xcd_grid(gws)), blk, 0, sw, p, b, cur);
   mark(K_WALL_ID, 1, sw);
   if (two) (void)hipEventRecord(li.ev_wall, sw);
-  if (two && li.n_solid > 0) {
+  // the solid step: forward Euler, or Crank-Nicolson by p.cn_iters Jacobi
+  // sweeps from T (right-hand side first, the last sweep into Ts[cur ^ 1])
+  auto solid = [&](hipStream_t s) {
     const int tiles = solid_tiles<D>(p.nx, p.ny, p.nz);
-    mark(K_SOLID_ID, 0, sw);
-    hipLaunchKernelGGL((k_solid<real, PT, D>), dim3(tiles), blk, 0, sw, p, b, cur);
-    mark(K_SOLID_ID, 1, sw);
-  }
+    mark(K_SOLID_ID, 0, s);
+    if (!p.solid_cn) {
+      hipLaunchKernelGGL((k_solid<real, PT, D>), dim3(tiles), blk, 0, s, p, b, cur);
+    } else {
+      hipLaunchKernelGGL((k_solid_pass<real, PT, D, 1>), dim3(tiles), blk, 0, s, p, b, b.Ts[cur], b.cn_tmp);
+      const real *src = b.Ts[cur];
+      for (int it = 0; it < p.cn_iters; ++it) {
+        real *dst = ((p.cn_iters - 1 - it) % 2 == 0) ? b.Ts[cur ^ 1] : b.cn_tmp;
+        hipLaunchKernelGGL((k_solid_pass<real, PT, D, 2>), dim3(tiles), blk, 0, s, p, b, src, dst);
+        src = dst;
+      }
+      hipLaunchKernelGGL((k_solid_pass<real, PT, D, 3>), dim3(tiles), blk, 0, s, p, b, b.Ts[cur ^ 1], b.cn_tmp);
+    }
+    mark(K_SOLID_ID, 1, s);
+  };
+  if (two && li.n_solid > 0) solid(sw);
   mark(K_MOMENTS_ID, 0, st);
   if (ggf > 0) hipLaunchKernelGGL((k_moments<true, real, PT, D, NS>), dim3(xcd_grid(ggf)), blk, 0, st, p, b, cur);
   if (ggs > 0) hipLaunchKernelGGL((k_moments<false, real, PT, D, NS>), dim3(xcd_grid(ggs)), blk, 0, st, p, b, cur);
@@ -1378,10 +1423,7 @@ inline hipError_t step_impl(const Params<real> &p, const Bufs<real, PT> &b, int 
     (void)hipEventRecord(li.ev_solid, sw);
     (void)hipStreamWaitEvent(st, li.ev_solid, 0);
   } else if (li.n_solid > 0) {
-    const int tiles = solid_tiles<D>(p.nx, p.ny, p.nz);
-    mark(K_SOLID_ID, 0, st);
-    hipLaunchKernelGGL((k_solid<real, PT, D>), dim3(tiles), blk, 0, st, p, b, cur);
-    mark(K_SOLID_ID, 1, st);
+    solid(st);
   }
   return hipGetLastError();
 }

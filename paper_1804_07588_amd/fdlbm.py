@@ -31,7 +31,7 @@ EXPORTS = ["fdlbm_create", "fdlbm_destroy", "fdlbm_last_error", "fdlbm_set_geome
            "fdlbm_workspace_bytes", "fdlbm_bind_workspace", "fdlbm_init_fields", "fdlbm_step",
            "fdlbm_sync", "fdlbm_observe", "fdlbm_get_field", "fdlbm_state_bytes",
            "fdlbm_save_state", "fdlbm_load_state", "fdlbm_set_profiling", "fdlbm_kernel_times",
-           "fdlbm_counts", "fdlbm_residual", "fdlbm_set_overlap", "fdlbm_set_prandtl", "fdlbm_batch_create", "fdlbm_batch_destroy",
+           "fdlbm_counts", "fdlbm_residual", "fdlbm_set_overlap", "fdlbm_set_prandtl", "fdlbm_set_solid_scheme", "fdlbm_batch_create", "fdlbm_batch_destroy",
            "fdlbm_batch_last_error", "fdlbm_batch_workspace_bytes", "fdlbm_batch_bind_workspace",
            "fdlbm_batch_set_active", "fdlbm_batch_step", "fdlbm_batch_set_grid",
            "fdlbm_batch_get_grid", "fdlbm_batch_autotune", "fdlbm_batch_set_overlap"]
@@ -104,6 +104,7 @@ def lib() -> ct.CDLL:
         L.fdlbm_residual.argtypes = [vp, dp]
         L.fdlbm_set_overlap.argtypes = [vp, ct.c_int]
         L.fdlbm_set_prandtl.argtypes = [vp, dp]
+        L.fdlbm_set_solid_scheme.argtypes = [vp, ct.c_int]
         ip = ct.POINTER(ct.c_int)
         L.fdlbm_batch_create.argtypes = [ct.POINTER(vp), ct.c_int, ct.POINTER(vp)]
         L.fdlbm_batch_destroy.argtypes = [vp]
@@ -168,6 +169,8 @@ class Sim:
             self._check(L.fdlbm_set_prandtl(h, _d(prj)))
         so = cfg["solid"]
         tbc = _arr(so["T_bc"])
+        if so.get("scheme", 0):
+            self._check(L.fdlbm_set_solid_scheme(h, int(so["scheme"])))
         self._check(L.fdlbm_set_solid(h, so["alpha_s"], so["C_s"], _d(tbc)))
         rx = cfg["reaction"]
         nu, order = _arr(rx["nu"]), _arr(rx["order"])

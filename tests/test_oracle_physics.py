@@ -255,3 +255,36 @@ def test_species_prandtl_numbers_set_the_mixture_diffusivity(oracle_lib, lattice
     sim.step(3000)
     r = -np.log(amp() / a1) / 3000 / (1.5 * tau1 * T0 * k * k)
     assert r == pytest.approx(1.0, abs=0.015)
+
+
+@pytest.mark.parametrize("alpha_s", [0.2, 2.0])
+def test_solid_crank_nicolson_discrete_mode(oracle_lib, alpha_s):
+    """Sec. 5, the Crank-Nicolson extension: a sine mode along a periodic
+    solid slab decays by (1 - 2 a s^2) / (1 + 2 a s^2) per step, s =
+    sin(pi k / N), also at alpha_s = 2, where forward Euler is unstable."""
+    nx, ny, lo, hi = 32, 12, 2, 6
+    mask = W.slab_mask(nx, ny, lo, hi)
+    cfg = one_species(nx, ny, mask=mask, periodic=(1, 1, 1), wall_mode=W.WALL_ISOTHERMAL,
+                      alpha_s=alpha_s, tau1=0.5)
+    cfg["solid"]["scheme"] = 1
+    init = W.uniform_init(cfg)
+    x = np.arange(nx * ny) % nx
+    init["Ts"] = T0 + 0.01 * np.sin(2 * np.pi * 3 * x / nx)
+    sim = oracle_lib.OracleSim(cfg, init)
+    steps = 40
+    sim.step(steps)
+    ts = sim.field(oracle_lib.OF_TS).reshape(ny, nx)[lo:hi]
+    s2 = np.sin(np.pi * 3 / nx) ** 2
+    factor = ((1 - 2 * alpha_s * s2) / (1 + 2 * alpha_s * s2)) ** steps
+    want = T0 + 0.01 * factor * np.sin(2 * np.pi * 3 * np.arange(nx) / nx)
+    assert np.abs(ts - want[None, :]).max() < 1e-12
+
+
+def test_energy_balance_is_exact_with_crank_nicolson(oracle_lib):
+    """The flux-matched energy identity also holds for the implicit solid
+    step (boundary heat from the mean of the old and new face fluxes)."""
+    cfg = W.with_changes(W.channel_c1(), init=dict(X=[0.7, 0.3]), reaction=dict(k0=1e-2))
+    cfg["solid"].update(scheme=1, alpha_s=1.5)
+    res, heat, E = energy_residual(oracle_lib, cfg)
+    assert heat > 1.0
+    assert abs(res) < 1e-12 * E

@@ -147,6 +147,30 @@ def test_bed_3d_species_prandtl(oracle_lib, fd, prec):
         assert_errs(field_errors(o, g, fd, 5, 3), 1e-5, tol_rate=2e-5)
 
 
+def test_crank_nicolson_solid_fp64(oracle_lib, fd):
+    """Crank-Nicolson solid (fdlbm_set_solid_scheme) at alpha_s = 1.5, six
+    times the forward-Euler limit, in the channel with Dirichlet outer faces
+    and fast reactive walls.  (This perturbed binary case amplifies small
+    differences by about 10^3 over 200 steps -- with the forward-Euler solid
+    too -- so an FP32 run drifts to 2e-4 from FP64 there; FP32 is checked on
+    the bed below.)"""
+    cfg = W.with_changes(W.channel_c1(), init=dict(X=[0.7, 0.3]), reaction=dict(k0=1e-2))
+    cfg["solid"].update(scheme=1, alpha_s=1.5)
+    init = W.perturbed_init(cfg, 8)
+    o, g = run_both(oracle_lib, fd, cfg, init, 200, fd.F64)
+    assert_errs(field_errors(o, g, fd, 2, 2), 1e-10)
+    oo, og = o.observe(), g.observe()
+    assert abs(og["heat_boundary"] - oo["heat_boundary"]) <= 1e-10 * abs(oo["heat_boundary"])
+
+
+def test_crank_nicolson_solid_bed_fp32(oracle_lib, fd):
+    """The same on the sphere pack (D3Q19), alpha_s = 0.5 (Euler limit 1/6)."""
+    cfg = small_bed()
+    cfg["solid"].update(scheme=1, alpha_s=0.5)
+    o, g = run_both(oracle_lib, fd, cfg, W.perturbed_init(cfg, 12, amp_u=0.005), 60, fd.F32)
+    assert_errs(field_errors(o, g, fd, 5, 3), 1e-5, tol_rate=2e-5)
+
+
 def test_c1_fp32(oracle_lib, fd):
     cfg = W.channel_c1()
     o, g = run_both(oracle_lib, fd, cfg, W.uniform_init(cfg), 1000, fd.F32)
