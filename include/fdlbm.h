@@ -153,6 +153,23 @@ int fdlbm_set_species(fdlbm_ctx *ctx, const double *M, const double *mu0, double
  * mentions after Eq.(21).  Call after fdlbm_set_species. */
 int fdlbm_set_prandtl(fdlbm_ctx *ctx, const double *Pr_j);
 
+/* Lennard-Jones transport, Eq.(26)-(27): the viscosities and binary
+ * diffusivities take their temperature dependence from collision integrals
+ * instead of power laws, scaled from the reference values of
+ * fdlbm_set_species (mu0_j, Djk0 at T_ref, p_ref):
+ *   mu_j   = mu0_j  (T/T_ref)^(1/2) Omega_mu(T*_ref,j) / Omega_mu(T*_j),
+ *   D_jk   = Djk0   (T/T_ref)^(3/2) (p_ref/p) Omega_D(T*_ref,jk) / Omega_D(T*_jk),
+ * T*_j = T T_unit / eps_j, eps_jk = sqrt(eps_j eps_k) (the "T^3" of Eq.(27)
+ * read as T^(3/2)); Wilke's phi_jk (Eq.(15)) then follow the local
+ * viscosities.  eps_over_k: n_species well depths (K); T_unit: kelvin per
+ * lattice temperature unit; the table: n (2..64) values of Omega_mu and
+ * Omega_D on a uniform grid of T* from tstar_min to tstar_max, interpolated
+ * linearly and held constant beyond its ends (the caller supplies it, e.g.
+ * from a published collision-integral table).  eps_over_k NULL: power laws
+ * again.  Call after fdlbm_set_species; copied. */
+int fdlbm_set_lj_transport(fdlbm_ctx *ctx, const double *eps_over_k, double T_unit, double tstar_min,
+                           double tstar_max, int n, const double *omega_mu, const double *omega_d);
+
 /* Solid (Eq.(45)-(47)): thermal diffusivity alpha_s (0 <= alpha_s <= 1/(2D),
  * the forward-Euler bound, else FDLBM_E_INVALID), volumetric heat capacity
  * C_s > 0, and T_bc6[6] Dirichlet temperatures of the closed domain faces

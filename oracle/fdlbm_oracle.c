@@ -41,6 +41,10 @@ struct oracle_sim {
   double M[MAXS], cj[MAXS], sj[MAXS], mu0[MAXS], mu_T_exp, Djk0[MAXS * MAXS], D_T_exp,
       D_p_exp, T_ref, p_ref, Pr;
   double Pr_j[MAXS]; /* per-species Prandtl numbers (all Pr unless set separately) */
+  /* Lennard-Jones transport (Eq.(26)-(27)): T_unit / eps_j per species and a
+   * collision-integral table on a uniform T* grid */
+  int lj, lj_n;
+  double lj_ie[MAXS], lj_t0, lj_dt, lj_om_mu[64], lj_om_d[64];
   unsigned flags;
   /* solid */
   double alpha_s, C_s, T_bc[6];
@@ -576,6 +580,37 @@ int oracle_set_prandtl(oracle_sim *s, const double *Pr_j) {
   return 0;
 }
 
+/* Lennard-Jones transport (Eq.(26)-(27), with the collision integrals from a
+ * table on a uniform grid of reduced temperature T* = T T_unit / eps):
+ * eps_over_k per species (K), T_unit (K per lattice temperature unit),
+ * n >= 2 values of Omega_mu and Omega_D at T* = tmin .. tmax.  eps_over_k
+ * NULL: power laws again. */
+int oracle_set_lj(oracle_sim *s, const double *eps_over_k, double T_unit, double tmin, double tmax, int n,
+                  const double *om_mu, const double *om_d) {
+  if (!s) return fail(s, "null argument");
+  if (!eps_over_k) {
+    s->lj = 0;
+    return 0;
+  }
+  if (!om_mu || !om_d || n < 2 || n > 64 || !(tmax > tmin) || !(tmin > 0) || !(T_unit > 0))
+    return fail(s, "bad collision-integral table");
+  for (int i = 0; i < n; ++i)
+    if (!(om_mu[i] > 0 && om_d[i] > 0)) return fail(s, "collision integrals must be positive");
+  for (int j = 0; j < s->ns; ++j) {
+    if (!(eps_over_k[j] > 0)) return fail(s, "eps/k must be positive");
+    s->lj_ie[j] = T_unit / eps_over_k[j];
+  }
+  s->lj_n = n;
+  s->lj_t0 = tmin;
+  s->lj_dt = (tmax - tmin) / (n - 1);
+  for (int i = 0; i < n; ++i) {
+    s->lj_om_mu[i] = om_mu[i];
+    s->lj_om_d[i] = om_d[i];
+  }
+  s->lj = 1;
+  return 0;
+}
+
 int oracle_set_solid(oracle_sim *s, double alpha_s, double C_s, const double *T_bc6) {
   if (!s) return fail(s, "null argument");
   /* Eq.(46)-(47): forward Euler is stable only for alpha_s <= 1/(2D); the
@@ -633,6 +668,17 @@ int oracle_set_flow(oracle_sim *s, const double *F3, const double *X_in, double 
 /* ------------------------------------------------------------------------ */
 /* transport, Eq.(7)-(8), (14)-(17)                                          */
 /* ------------------------------------------------------------------------ */
+/* collision integral at reduced temperature ts from the table: linear
+ * interpolation on the uniform grid, constant beyond its ends */
+static double lj_omega(const oracle_sim *s, const double *om, double ts) {
+  double f = (ts - s->lj_t0) / s->lj_dt;
+  if (f <= 0.0) return om[0];
+  if (f >= s->lj_n - 1) return om[s->lj_n - 1];
+  int i = (int)f;
+  double w = f - i;
+  return (1.0 - w) * om[i] + w * om[i + 1];
+}
+
 static void transport(const oracle_sim *s, const double *rho, double T, double *tau1,
                       double *tau2) {
   int ns = s->ns;
@@ -652,10 +698,18 @@ static void transport(const oracle_sim *s, const double *rho, double T, double *
     sMX += s->M[j] * Xh[j];
   }
   for (int j = 0; j < ns; ++j) Yh[j] = s->M[j] * Xh[j] / sMX;
-  /* species viscosities; reading: power-law temperature dependence in place
-   * of the Lennard-Jones collision-integral tables */
+  /* species viscosities: power laws, or with Lennard-Jones collision
+   * integrals (Eq.(26): mu_j ~ sqrt(M_j T) / (sigma_j^2 Omega_mu(T*_j))),
+   * scaled from the reference value mu0_j at T_ref so that sigma_j and the
+   * unit constants drop out */
   double mu[MAXS];
-  for (int j = 0; j < ns; ++j) mu[j] = s->mu0[j] * pow(T / s->T_ref, s->mu_T_exp);
+  for (int j = 0; j < ns; ++j) {
+    if (s->lj)
+      mu[j] = s->mu0[j] * sqrt(T / s->T_ref) * lj_omega(s, s->lj_om_mu, s->T_ref * s->lj_ie[j]) /
+              lj_omega(s, s->lj_om_mu, T * s->lj_ie[j]);
+    else
+      mu[j] = s->mu0[j] * pow(T / s->T_ref, s->mu_T_exp);
+  }
   /* Wilke, Eq.(15) with the square of the bracket restored (phi_jj = 1) */
   for (int j = 0; j < ns; ++j) {
     double den = 0.0;
@@ -675,8 +729,15 @@ static void transport(const oracle_sim *s, const double *rho, double T, double *
     double sum = 0.0;
     for (int k = 0; k < ns; ++k) {
       if (k == j) continue;
-      double Djk = s->Djk0[j * MAXS + k] * pow(T / s->T_ref, s->D_T_exp) *
-                   pow(s->p_ref / p, s->D_p_exp);
+      double Djk;
+      if (s->lj) {
+        /* Eq.(27) with T^(3/2) and 1/p; eps_jk = sqrt(eps_j eps_k) */
+        double ie = sqrt(s->lj_ie[j] * s->lj_ie[k]);
+        Djk = s->Djk0[j * MAXS + k] * pow(T / s->T_ref, 1.5) * (s->p_ref / p) *
+              lj_omega(s, s->lj_om_d, s->T_ref * ie) / lj_omega(s, s->lj_om_d, T * ie);
+      } else {
+        Djk = s->Djk0[j * MAXS + k] * pow(T / s->T_ref, s->D_T_exp) * pow(s->p_ref / p, s->D_p_exp);
+      }
       sum += Xh[k] / Djk;
     }
     double Dj = (1.0 - Yh[j]) / sum; /* Eq.(8) */

@@ -60,6 +60,9 @@ int oracle_set_species(oracle_sim *s, const double *M, const double *mu0, double
                        double p_ref, double Pr, unsigned flags);
 /* per-species Prandtl numbers (NULL: every species at the common Pr) */
 int oracle_set_prandtl(oracle_sim *s, const double *Pr_j);
+/* Lennard-Jones transport from a collision-integral table (NULL eps: off) */
+int oracle_set_lj(oracle_sim *s, const double *eps_over_k, double T_unit, double tmin, double tmax, int n,
+                  const double *om_mu, const double *om_d);
 int oracle_set_solid(oracle_sim *s, double alpha_s, double C_s, const double *T_bc6);
 /* solid time scheme: 0 forward Euler (alpha_s <= 1/(2D)), 1 Crank-Nicolson */
 int oracle_set_solid_scheme(oracle_sim *s, int scheme);

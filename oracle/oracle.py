@@ -67,6 +67,8 @@ def lib():
         L.oracle_set_solid.argtypes = [ct.c_void_p, ct.c_double, ct.c_double, dp]
         L.oracle_set_prandtl.argtypes = [ct.c_void_p, dp]
         L.oracle_set_solid_scheme.argtypes = [ct.c_void_p, ct.c_int]
+        L.oracle_set_lj.argtypes = [ct.c_void_p, dp, ct.c_double, ct.c_double, ct.c_double, ct.c_int,
+                                    dp, dp]
         L.oracle_set_reaction.argtypes = [ct.c_void_p, dp, dp, ct.c_double, ct.c_double,
                                           ct.c_double, ct.c_double, ct.c_int, ct.c_double,
                                           ct.c_double, ct.c_int]
@@ -162,6 +164,11 @@ class OracleSim:
         if sp.get("Pr_j") is not None:
             prj = _arr(sp["Pr_j"])
             self._check(L.oracle_set_prandtl(h, _d(prj)))
+        lj = sp.get("lj")
+        if lj is not None:
+            eps, omu, omd = _arr(lj["eps_over_k"]), _arr(lj["omega_mu"]), _arr(lj["omega_d"])
+            self._check(L.oracle_set_lj(h, _d(eps), lj["T_unit"], lj["tstar_min"], lj["tstar_max"],
+                                        len(omu), _d(omu), _d(omd)))
         so = cfg["solid"]
         tbc = _arr(so["T_bc"])
         if so.get("scheme", 0):

@@ -34,6 +34,10 @@ struct fdlbm_ctx {
   double M[MAXS]{}, mu0[MAXS]{}, mu_T_exp = 0, Djk0[MAXS * MAXS]{}, D_T_exp = 0, D_p_exp = 0,
          T_ref = 1.0 / 3, p_ref = 1.0 / 3, Pr = 1;
   double Pr_j[MAXS] = {1, 1, 1, 1, 1, 1, 1, 1};  // per-species Prandtl numbers
+  // Lennard-Jones transport: T_unit / eps_j, collision-integral table
+  bool lj = false;
+  int lj_n = 0;
+  double lj_ie[MAXS]{}, lj_t0 = 0, lj_dt = 1, lj_om_mu[64]{}, lj_om_d[64]{};
   unsigned flags = FDLBM_CORR_ALL;
   double alpha_s = 0, C_s = 1, T_bc[6];
   int solid_scheme = FDLBM_SOLID_EULER;
@@ -60,6 +64,7 @@ struct fdlbm_ctx {
   char *ws = nullptr;
   size_t ws_bytes = 0;
   size_t off_cnr = 0, off_cnt = 0;  // Crank-Nicolson solid buffers
+  size_t off_lj = 0;                // collision-integral table
   size_t off_G[2]{}, off_Gs = 0, off_FR = 0, off_FX = 0, off_Ts[2]{}, off_wr = 0, off_wde = 0, off_kind = 0, off_slot = 0,
          off_scls = 0, off_wem = 0, off_gl = 0, off_wl = 0, off_am = 0, off_aw = 0, off_ab = 0,
          off_part = 0, off_snap = 0, off_snapts = 0;
@@ -153,6 +158,7 @@ static void layout(fdlbm_ctx *c) {
   c->off_wde = take(n * b);
   c->off_cnr = take(n * b);
   c->off_cnt = take(n * b);
+  c->off_lj = take(128 * b);
   c->off_kind = take(n);
   c->off_slot = take(n * 4);
   c->off_scls = take(nsl * 8);
@@ -188,6 +194,7 @@ static Bufs<real, PT> bufs(const fdlbm_ctx *c) {
   b.wall_dE = (real *)(w + c->off_wde);
   b.cn_rhs = (real *)(w + c->off_cnr);
   b.cn_tmp = (real *)(w + c->off_cnt);
+  b.lj_tab = (const real *)(w + c->off_lj);
   b.kind = (const uint8_t *)(w + c->off_kind);
   b.slot_of = (const int32_t *)(w + c->off_slot);
   b.scls = (const uint64_t *)(w + c->off_scls);
@@ -226,6 +233,16 @@ static void class_weights(double s, double w[7][3]) {
   w[5][1] = w[5][2] = 0;
   w[6][0] = 1.0;
   w[6][1] = w[6][2] = 0;
+}
+
+// collision integral from the table (the kernels' interpolation, in double)
+static double lj_omega_host(const fdlbm_ctx *c, const double *om, double ts) {
+  const double f = (ts - c->lj_t0) / c->lj_dt;
+  if (!(f > 0.0)) return om[0];
+  if (f >= c->lj_n - 1) return om[c->lj_n - 1];
+  const int i = (int)f;
+  const double w = f - i;
+  return (1.0 - w) * om[i] + w * om[i + 1];
 }
 
 template <typename real>
@@ -280,6 +297,22 @@ static Params<real> params(const fdlbm_ctx *c) {
   p.T_ref = (real)c->T_ref;
   p.p_ref = (real)c->p_ref;
   for (int j = 0; j < c->ns; ++j) p.kprj[j] = (real)((c->D + 2.0) * (1.0 / c->Pr_j[j] - 1.0));
+  p.lj = c->lj ? 1 : 0;
+  p.lj_n = c->lj_n;
+  p.lj_t0 = (real)c->lj_t0;
+  p.lj_idt = (real)(1.0 / c->lj_dt);
+  if (c->lj) {
+    // reference collision integrals folded into mu0 and 1/D0 (Eq.(26)-(27)
+    // scaled from the reference state)
+    for (int j = 0; j < c->ns; ++j) {
+      p.lj_ie[j] = (real)c->lj_ie[j];
+      p.mu0[j] = (real)(c->mu0[j] * lj_omega_host(c, c->lj_om_mu, c->T_ref * c->lj_ie[j]));
+      for (int k = 0; k < c->ns; ++k)
+        if (k != j)
+          p.invD0[j][k] = (real)(1.0 / (c->Djk0[j * c->ns + k] *
+                                        lj_omega_host(c, c->lj_om_d, c->T_ref * std::sqrt(c->lj_ie[j] * c->lj_ie[k]))));
+    }
+  }
   p.alpha_s = (real)c->alpha_s;
   p.C_s = (real)c->C_s;
   p.invCs = (real)(1.0 / c->C_s);
@@ -593,6 +626,52 @@ int fdlbm_set_solid(fdlbm_ctx *c, double alpha_s, double C_s, const double *T_bc
   return FDLBM_OK;
 }
 
+// the collision-integral table into the workspace, in the arithmetic type
+static int upload_lj(fdlbm_ctx *c) {
+  if (!c->bound || !c->lj) return FDLBM_OK;
+  const size_t b = real_size(c);
+  std::vector<char> buf(128 * b, 0);
+  for (int i = 0; i < c->lj_n; ++i) {
+    if (b == 8) {
+      reinterpret_cast<double *>(buf.data())[i] = c->lj_om_mu[i];
+      reinterpret_cast<double *>(buf.data())[c->lj_n + i] = c->lj_om_d[i];
+    } else {
+      reinterpret_cast<float *>(buf.data())[i] = (float)c->lj_om_mu[i];
+      reinterpret_cast<float *>(buf.data())[c->lj_n + i] = (float)c->lj_om_d[i];
+    }
+  }
+  HIPCHK(c, hipMemcpyAsync(c->ws + c->off_lj, buf.data(), buf.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return FDLBM_OK;
+}
+
+int fdlbm_set_lj_transport(fdlbm_ctx *c, const double *eps_over_k, double T_unit, double tstar_min,
+                           double tstar_max, int n, const double *omega_mu, const double *omega_d) {
+  if (!c) return FDLBM_E_INVALID;
+  if (!c->species_set) return set_err(c, FDLBM_E_STATE, "set the species first");
+  if (!eps_over_k) {
+    c->lj = false;
+    return FDLBM_OK;
+  }
+  if (!omega_mu || !omega_d || n < 2 || n > 64 || !(tstar_max > tstar_min) || !(tstar_min > 0) ||
+      !(T_unit > 0))
+    return set_err(c, FDLBM_E_INVALID, "bad collision-integral table (2..64 points on tmin < tmax)");
+  for (int i = 0; i < n; ++i)
+    if (!(omega_mu[i] > 0 && omega_d[i] > 0)) return set_err(c, FDLBM_E_INVALID, "collision integrals must be positive");
+  for (int j = 0; j < c->ns; ++j)
+    if (!(eps_over_k[j] > 0)) return set_err(c, FDLBM_E_INVALID, "eps/k must be positive");
+  for (int j = 0; j < c->ns; ++j) c->lj_ie[j] = T_unit / eps_over_k[j];
+  c->lj_n = n;
+  c->lj_t0 = tstar_min;
+  c->lj_dt = (tstar_max - tstar_min) / (n - 1);
+  for (int i = 0; i < n; ++i) {
+    c->lj_om_mu[i] = omega_mu[i];
+    c->lj_om_d[i] = omega_d[i];
+  }
+  c->lj = true;
+  return upload_lj(c);
+}
+
 int fdlbm_set_solid_scheme(fdlbm_ctx *c, int scheme) {
   if (!c) return FDLBM_E_INVALID;
   if (scheme != FDLBM_SOLID_EULER && scheme != FDLBM_SOLID_CN)
@@ -675,7 +754,7 @@ int fdlbm_bind_workspace(fdlbm_ctx *c, void *dev, size_t bytes) {
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->bound = true;
   c->initialized = false;
-  return FDLBM_OK;
+  return upload_lj(c);
 }
 
 // host-side equilibrium for the initial state (same closed form as the kernels)

@@ -93,6 +93,11 @@ struct Params {
   real invD0[MAXS][MAXS];          // 1 / Djk0
   real D_T_exp, D_p_exp, T_ref, p_ref;
   real kprj[MAXS];                 // (D+2)(1/Pr_j - 1) per species
+  // Lennard-Jones transport: on, table length, grid origin and 1/spacing of
+  // T*, T_unit / eps_j per species
+  int lj, lj_n;
+  real lj_t0, lj_idt;
+  real lj_ie[MAXS];
   // solid
   real alpha_s, invCs, C_s;
   int solid_cn, cn_iters;          // Crank-Nicolson solid: on, Jacobi sweeps per step
@@ -147,6 +152,7 @@ struct Bufs {
   real *wall_r;       // molar rate per node (wall nodes) of the last step
   real *wall_dE;      // kinetic energy the wall gave the gas, per node, last step
   real *cn_rhs, *cn_tmp;  // Crank-Nicolson solid: right-hand side and sweep buffer, per node
+  const real *lj_tab;     // collision integrals: Omega_mu[lj_n] then Omega_D[lj_n]
   const uint8_t *kind;       // node class per node
   const int32_t *slot_of;    // slot per node
   const uint64_t *scls;      // streaming class word per gas/wall slot

@@ -482,6 +482,18 @@ __global__ void __launch_bounds__(BLOCK) k_wall(Params<real> p, Bufs<real, PT> b
 // moments of the streamed populations and every local quantity of the node
 // (Eq.(3), (5), (7)-(8), (11), (14)-(17), (25)), one thread per node.
 // ===========================================================================
+// collision integral at reduced temperature ts from a table on a uniform grid
+// (linear interpolation, constant beyond the ends)
+template <typename real>
+__device__ inline real lj_omega(const Params<real> &p, const real *tab, real ts) {
+  const real f = (ts - p.lj_t0) * p.lj_idt;
+  if (!(f > real(0))) return tab[0];
+  if (f >= real(p.lj_n - 1)) return tab[p.lj_n - 1];
+  const int i = (int)f;
+  const real w = f - real(i);
+  return (real(1) - w) * tab[i] + w * tab[i + 1];
+}
+
 // one gas node (slot t) of the streaming-and-moments pass
 template <bool FAST, typename real, typename PT, int D, int NS>
 __device__ __forceinline__ void moments_node(const Params<real> &p, const Bufs<real, PT> &b, int cur,
@@ -558,29 +570,57 @@ __device__ __forceinline__ void moments_node(const Params<real> &p, const Bufs<r
     sMX += p.M[j] * Xh[j];
   }
   const real lT = log(T / p.T_ref);
-  const real fmu = p.mu_T_exp == real(0) ? real(1) : exp(p.mu_T_exp * lT);
   const real CT = C * T;
   Rec<real, NR> fr;
   Rec<real, NX> fx;
   real tau2[NS];
+  if (!p.lj) {
+    // power laws: the viscosity ratios, hence Wilke's phi_jk, do not depend on T
+    const real fmu = p.mu_T_exp == real(0) ? real(1) : exp(p.mu_T_exp * lT);
 #pragma unroll
-  for (int j = 0; j < NS; ++j) {
-    real den = 0;
+    for (int j = 0; j < NS; ++j) {
+      real den = 0;
 #pragma unroll
-    for (int k = 0; k < NS; ++k) den += Xh[k] * p.wilke[j][k];
-    const real tau1 = p.mu0[j] * fmu / (CT * den);  // Eq.(17)
-    fr.v[fr_tau1(D, j)] = tau1;
-    fr.v[fr_rho(D, j)] = rho[j];
-    tau2[j] = tau1;
+      for (int k = 0; k < NS; ++k) den += Xh[k] * p.wilke[j][k];
+      const real tau1 = p.mu0[j] * fmu / (CT * den);  // Eq.(17)
+      fr.v[fr_tau1(D, j)] = tau1;
+      tau2[j] = tau1;
+    }
+  } else {
+    // Eq.(26) with collision integrals: mu_j = mu0_j Omega_mu(T*_ref) sqrt(T/T_ref)
+    // / Omega_mu(T*_j) (the reference factor is folded into mu0 on the host);
+    // Wilke's phi_jk, Eq.(15) with the square, from these viscosities
+    const real sq = sqrt(T / p.T_ref);
+    real mu[NS];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) mu[j] = p.mu0[j] * sq / lj_omega(p, b.lj_tab, T * p.lj_ie[j]);
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      real den = 0;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        const real br = real(1) + sqrt(mu[j] / mu[k]) * sqrt(p.sqM[k] / p.sqM[j]);
+        den += Xh[k] * br * br / sqrt(real(8) * (real(1) + p.M[j] * p.invM[k]));
+      }
+      const real tau1 = mu[j] / (CT * den);  // Eq.(17)
+      fr.v[fr_tau1(D, j)] = tau1;
+      tau2[j] = tau1;
+    }
   }
+#pragma unroll
+  for (int j = 0; j < NS; ++j) fr.v[fr_rho(D, j)] = rho[j];
   if (NS > 1) {
-    const real gD = exp(p.D_T_exp * lT + p.D_p_exp * log(p.p_ref / CT));
+    // Eq.(27) with T^(3/2) and 1/p when collision integrals are on
+    const real gD = p.lj ? sqrt(T / p.T_ref) * (T / p.T_ref) * (p.p_ref / CT)
+                         : exp(p.D_T_exp * lT + p.D_p_exp * log(p.p_ref / CT));
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
       real sum = 0;
 #pragma unroll
       for (int k = 0; k < NS; ++k)
-        if (k != j) sum += Xh[k] * p.invD0[j][k];
+        if (k != j)
+          sum += Xh[k] * p.invD0[j][k] *
+                 (p.lj ? lj_omega(p, b.lj_tab + p.lj_n, T * sqrt(p.lj_ie[j] * p.lj_ie[k])) : real(1));
       const real Dj = gD * (real(1) - p.M[j] * Xh[j] / sMX) / sum;  // Eq.(8)
       tau2[j] = p.M[j] * Dj / T;                                    // Eq.(7)
     }

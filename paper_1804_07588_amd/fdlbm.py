@@ -31,7 +31,8 @@ EXPORTS = ["fdlbm_create", "fdlbm_destroy", "fdlbm_last_error", "fdlbm_set_geome
            "fdlbm_workspace_bytes", "fdlbm_bind_workspace", "fdlbm_init_fields", "fdlbm_step",
            "fdlbm_sync", "fdlbm_observe", "fdlbm_get_field", "fdlbm_state_bytes",
            "fdlbm_save_state", "fdlbm_load_state", "fdlbm_set_profiling", "fdlbm_kernel_times",
-           "fdlbm_counts", "fdlbm_residual", "fdlbm_set_overlap", "fdlbm_set_prandtl", "fdlbm_set_solid_scheme", "fdlbm_batch_create", "fdlbm_batch_destroy",
+           "fdlbm_counts", "fdlbm_residual", "fdlbm_set_overlap", "fdlbm_set_prandtl", "fdlbm_set_solid_scheme",
+           "fdlbm_set_lj_transport", "fdlbm_batch_create", "fdlbm_batch_destroy",
            "fdlbm_batch_last_error", "fdlbm_batch_workspace_bytes", "fdlbm_batch_bind_workspace",
            "fdlbm_batch_set_active", "fdlbm_batch_step", "fdlbm_batch_set_grid",
            "fdlbm_batch_get_grid", "fdlbm_batch_autotune", "fdlbm_batch_set_overlap"]
@@ -105,6 +106,7 @@ def lib() -> ct.CDLL:
         L.fdlbm_set_overlap.argtypes = [vp, ct.c_int]
         L.fdlbm_set_prandtl.argtypes = [vp, dp]
         L.fdlbm_set_solid_scheme.argtypes = [vp, ct.c_int]
+        L.fdlbm_set_lj_transport.argtypes = [vp, dp, ct.c_double, ct.c_double, ct.c_double, ct.c_int, dp, dp]
         ip = ct.POINTER(ct.c_int)
         L.fdlbm_batch_create.argtypes = [ct.POINTER(vp), ct.c_int, ct.POINTER(vp)]
         L.fdlbm_batch_destroy.argtypes = [vp]
@@ -167,6 +169,11 @@ class Sim:
         if sp.get("Pr_j") is not None:
             prj = _arr(sp["Pr_j"])
             self._check(L.fdlbm_set_prandtl(h, _d(prj)))
+        lj = sp.get("lj")
+        if lj is not None:
+            eps, omu, omd = _arr(lj["eps_over_k"]), _arr(lj["omega_mu"]), _arr(lj["omega_d"])
+            self._check(L.fdlbm_set_lj_transport(h, _d(eps), lj["T_unit"], lj["tstar_min"], lj["tstar_max"],
+                                                 len(omu), _d(omu), _d(omd)))
         so = cfg["solid"]
         tbc = _arr(so["T_bc"])
         if so.get("scheme", 0):

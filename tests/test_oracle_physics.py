@@ -288,3 +288,57 @@ def test_energy_balance_is_exact_with_crank_nicolson(oracle_lib):
     res, heat, E = energy_residual(oracle_lib, cfg)
     assert heat > 1.0
     assert abs(res) < 1e-12 * E
+
+
+LJ_LINEAR = dict(T_unit=3.0, tstar_min=0.5, tstar_max=3.0,
+                 omega_mu=list(1.5 - 0.2 * (np.linspace(0.5, 3.0, 11) - 1.0)),
+                 omega_d=list(1.2 - 0.1 * (np.linspace(0.5, 3.0, 11) - 1.0)))
+
+
+def test_lj_viscosity_from_the_collision_integral(oracle_lib):
+    """Eq.(26) with a collision-integral table (linear in T*, so the
+    interpolation is exact): at T = 1/3 with T_ref = 1/4 and eps/k = 1 K,
+    T_unit = 3 K, the viscosity is mu0 sqrt(T/T_ref) Omega(0.75)/Omega(1.0);
+    a body-force channel measures it through the curvature -F/(2 nu)."""
+    H, wall, tau1, F = 16, 3, 0.5, 1e-6
+    ny = H + 2 * wall
+    cfg = one_species(2, ny, tau1=tau1, F=F, mask=W.channel_mask(2, ny, wall))
+    sp = cfg["species"]
+    sp["T_ref"] = 0.25
+    sp["lj"] = dict(LJ_LINEAR, eps_over_k=[1.0])
+    om = lambda t: 1.5 - 0.2 * (t - 1.0)
+    nu = tau1 * T0 * np.sqrt(T0 / 0.25) * om(0.75) / om(1.0)   # mu0 = tau1 T0, rho = 1
+    y = np.arange(ny)
+    y0, y1 = wall - 1, ny - wall
+    prof = np.where((y >= wall) & (y < ny - wall), F / (2 * nu) * (y - y0) * (y1 - y), 0.0)
+    init = W.uniform_init(cfg)
+    init["u"][0] = np.repeat(prof, 2)
+    sim = oracle_lib.OracleSim(cfg, init)
+    sim.step(int(3 * H * H / nu))
+    u = sim.field(oracle_lib.OF_U, 0).reshape(ny, 2)[:, 0]
+    g = slice(wall, ny - wall)
+    a = np.polyfit(y[g], u[g], 2)[0]
+    assert a == pytest.approx(-F / (2 * nu), rel=1e-6)
+
+
+def test_lj_constant_table_is_the_power_law(oracle_lib):
+    """With constant collision integrals the Lennard-Jones laws reduce to
+    mu ~ T^(1/2) and D ~ T^(3/2)/p: the same run as the power-law model with
+    those exponents, to rounding."""
+    mask, _ = W.sphere_pack_mask(16, radius=3.0, porosity=0.6, seed=3, buffer=4)
+    cfg = W.packed_bed(mask=mask, k0=1e-3, force=1e-5)
+    cfg["species"].update(mu_T_exp=0.5, D_T_exp=1.5, D_p_exp=1.0)
+    lj = W.with_changes(cfg)
+    lj["species"]["lj"] = dict(T_unit=1209.0, tstar_min=1.0, tstar_max=10.0,
+                               eps_over_k=[100.0, 300.0, 200.0, 60.0, 80.0],  # synthetic
+                               omega_mu=[1.3] * 4, omega_d=[1.1] * 4)
+    init = W.perturbed_init(cfg, 3, amp_u=0.005)
+    a = oracle_lib.OracleSim(cfg, init)
+    b = oracle_lib.OracleSim(lj, init)
+    a.step(30)
+    b.step(30)
+    for j in range(5):
+        ra, rb = a.field(oracle_lib.OF_RHO, j), b.field(oracle_lib.OF_RHO, j)
+        assert np.abs(ra - rb).max() <= 1e-13 * np.abs(ra).max()
+    ta, tb = a.field(oracle_lib.OF_T), b.field(oracle_lib.OF_T)
+    assert np.abs(ta - tb).max() <= 1e-13

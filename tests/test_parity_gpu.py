@@ -171,6 +171,30 @@ def test_crank_nicolson_solid_bed_fp32(oracle_lib, fd):
     assert_errs(field_errors(o, g, fd, 5, 3), 1e-5, tol_rate=2e-5)
 
 
+def lj_table(n=40, tmin=0.5, tmax=10.0):
+    """A smooth synthetic collision-integral table (decreasing in T*, like the
+    published ones), not a published table."""
+    t = np.linspace(tmin, tmax, n)
+    return dict(T_unit=1209.0, tstar_min=tmin, tstar_max=tmax,
+                omega_mu=list(1.1 + 0.9 * np.exp(-0.6 * t) + 0.02 * np.cos(t)),
+                omega_d=list(1.0 + 0.8 * np.exp(-0.5 * t)))
+
+
+@pytest.mark.parametrize("prec", ["F64", "F32"])
+def test_bed_3d_lj_transport(oracle_lib, fd, prec):
+    """Lennard-Jones transport (fdlbm_set_lj_transport) on the sphere pack:
+    viscosities, Wilke coefficients and diffusivities from the table."""
+    cfg = small_bed()
+    cfg["species"]["lj"] = dict(lj_table(), eps_over_k=[100.0, 300.0, 200.0, 60.0, 80.0])
+    precision = getattr(fd, prec)
+    o, g = run_both(oracle_lib, fd, cfg, W.perturbed_init(cfg, 14, amp_u=0.005, amp_T=0.03), 60,
+                    precision)
+    if prec == "F64":
+        assert_errs(field_errors(o, g, fd, 5, 3), 1e-10)
+    else:
+        assert_errs(field_errors(o, g, fd, 5, 3), 1e-5, tol_rate=2e-5)
+
+
 def test_c1_fp32(oracle_lib, fd):
     cfg = W.channel_c1()
     o, g = run_both(oracle_lib, fd, cfg, W.uniform_init(cfg), 1000, fd.F32)
