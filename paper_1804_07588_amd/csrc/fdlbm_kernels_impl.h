@@ -178,21 +178,51 @@ __device__ inline Rec<real, NS> pop_load_raw(const PT *__restrict__ Gi, int slot
   }
   return r;
 }
-template <typename real, typename PT, int NS>
+// NW 4-byte words to a 4-byte aligned address with the non-temporal hint, in
+// the widest vector stores that alignment allows
+template <int NW>
+__device__ inline void st_words_nt(uint32_t *__restrict__ p, const uint32_t *w) {
+  typedef uint32_t u4 __attribute__((ext_vector_type(4), aligned(4)));
+  typedef uint32_t u3 __attribute__((ext_vector_type(3), aligned(4)));
+  typedef uint32_t u2 __attribute__((ext_vector_type(2), aligned(4)));
+  constexpr int N4 = NW / 4, R = NW % 4;
+#pragma unroll
+  for (int k = 0; k < N4; ++k) {
+    const u4 x = {w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]};
+    __builtin_nontemporal_store(x, reinterpret_cast<u4 *>(p + 4 * k));
+  }
+  if constexpr (R == 3) {
+    const u3 x = {w[4 * N4], w[4 * N4 + 1], w[4 * N4 + 2]};
+    __builtin_nontemporal_store(x, reinterpret_cast<u3 *>(p + 4 * N4));
+  } else if constexpr (R == 2) {
+    const u2 x = {w[4 * N4], w[4 * N4 + 1]};
+    __builtin_nontemporal_store(x, reinterpret_cast<u2 *>(p + 4 * N4));
+  } else if constexpr (R == 1) {
+    __builtin_nontemporal_store(w[4 * N4], p + 4 * N4);
+  }
+}
+
+// NT: a streaming (non-temporal) store, for populations that no kernel of
+// the same step reads again (the post-collision and wall-emitted populations,
+// read by the next step after the rest of this step's traffic)
+template <typename real, typename PT, int NS, bool NT = false>
 __device__ inline void pop_store_raw(PT *__restrict__ Gi, int slot, const Rec<real, NS> &v) {
   constexpr int RL = rec_len<PT>(NS);
+  constexpr int NW = int(RL * sizeof(PT)) / 4;
+  static_assert(RL * sizeof(PT) % 4 == 0, "records are whole 4-byte words");
+  const uint32_t off = uint32_t(slot) * uint32_t(RL * sizeof(PT));
+  uint32_t *p = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(Gi) + off);
+  uint32_t w[NW];
   if constexpr (narrow<PT>()) {
     PT h[RL];
 #pragma unroll
     for (int j = 0; j < RL; ++j) h[j] = j < NS ? PT(float(v.v[j])) : PT(0.0f);
-    Rec<uint32_t, RL / 2> w;
-    __builtin_memcpy(&w, h, sizeof w);
-    const uint32_t off = uint32_t(slot) * uint32_t(RL * sizeof(PT));
-    uint32_t *p = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(Gi) + off);
-    __builtin_memcpy(p, &w, sizeof w);
+    __builtin_memcpy(w, h, sizeof w);
   } else {
-    strec<real, NS>(Gi, slot, v);
+    __builtin_memcpy(w, &v, sizeof w);
   }
+  if constexpr (NT) st_words_nt<NW>(p, w);
+  else __builtin_memcpy(p, w, sizeof w);
 }
 // The 16-bit storage transform g = (d + w_i) rho_ref and its inverse, kept
 // out of floating-point contraction: the compiler would otherwise fuse them
@@ -217,13 +247,19 @@ __device__ inline Rec<real, NS> pop_load(const Params<real> &p, const PT *__rest
   }
   return r;
 }
-template <typename real, typename PT, int D, int NS>
+template <typename real, typename PT, int D, int NS, bool NT = false>
 __device__ inline void pop_store(const Params<real> &p, PT *__restrict__ Gi, int slot, int i, Rec<real, NS> v) {
   if constexpr (narrow<PT>()) {
 #pragma unroll
     for (int j = 0; j < NS; ++j) v.v[j] = dev_encode(v.v[j], p.inv_rho_ref[j], real(wlat<D>(i)));
   }
-  pop_store_raw<real, PT, NS>(Gi, slot, v);
+  pop_store_raw<real, PT, NS, NT>(Gi, slot, v);
+}
+// store into the next step's buffer (streaming)
+template <typename real, typename PT, int D, int NS>
+__device__ inline void pop_store_next(const Params<real> &p, PT *__restrict__ Gi, int slot, int i,
+                                      const Rec<real, NS> &v) {
+  pop_store<real, PT, D, NS, true>(p, Gi, slot, i, v);
 }
 
 // Slots of the three taps of direction i for stencil class cls (0..6) around
@@ -436,7 +472,7 @@ __device__ inline double wall_node(const Params<real> &p, const Bufs<real, PT> &
       W.v[j] = rw[j] * wt[i];
       Ei += p.cj2[j] * W.v[j];
     }
-    pop_store<real, PT, D, NS>(p, Gn + (size_t)i * nsl * RL, slot, i, W);
+    pop_store_next<real, PT, D, NS>(p, Gn + (size_t)i * nsl * RL, slot, i, W);
     Eout += real(cnorm2<D>(i)) * Ei;
   }
   // wall state seen by the neighbours' gradient stencils
@@ -522,7 +558,8 @@ __device__ __forceinline__ void moments_node(const Params<real> &p, const Bufs<r
     const int cls = cls_at(cw, i);
     const Rec<real, NS> g = stream_rec<real, PT, D, NS>(p, G + (size_t)i * nsl * RL,
                                                      gas_tap_slots<FAST>(b, ad, i, cls, t), wtab, cls, i);
-    pop_store<real, PT, D, NS>(p, b.Gs + (size_t)i * nsl * RL, t, i, g);  // for the collision
+    // for the collision, which reads it right after: an ordinary (cached) store
+    pop_store<real, PT, D, NS>(p, b.Gs + (size_t)i * nsl * RL, t, i, g);
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
       rho[j] += g.v[j];
@@ -906,7 +943,7 @@ __device__ inline void collide_node(const Params<real> &p, const Bufs<real, PT> 
     Rec<real, NS> o;
 #pragma unroll
     for (int j = 0; j < NS; ++j) o.v[j] = g0.v[j] - sp[j].w * (g0.v[j] - sp[j].r_st) - sp[j].r_rest;
-    pop_store<real, PT, D, NS>(p, Gn, t, 0, o);
+    pop_store_next<real, PT, D, NS>(p, Gn, t, 0, o);
   }
   static_for<1, Q>([&](auto ic_) __attribute__((always_inline)) {
     constexpr int i = decltype(ic_)::value;
@@ -934,7 +971,7 @@ __device__ inline void collide_node(const Params<real> &p, const Bufs<real, PT> 
       }
       o.v[j] = g.v[j] - c.w * (g.v[j] - c.rho * ps) - c.a2 * (ps - pe) + S;
     }
-    pop_store<real, PT, D, NS>(p, Gn + (size_t)i * nsl * RL, t, i, o);
+    pop_store_next<real, PT, D, NS>(p, Gn + (size_t)i * nsl * RL, t, i, o);
   });
 }
 
@@ -960,14 +997,14 @@ __device__ inline void inlet_node(const Params<real> &p, const Bufs<real, PT> &b
     Rec<real, NS> o;
 #pragma unroll
     for (int j = 0; j < NS; ++j) o.v[j] = p.rho_in[j] * eq_rest<real, D>(U[j], p.T_in);
-    pop_store<real, PT, D, NS>(p, Gn, t, 0, o);
+    pop_store_next<real, PT, D, NS>(p, Gn, t, 0, o);
   }
   static_for<1, Q>([&](auto ic_) __attribute__((always_inline)) {
     constexpr int i = decltype(ic_)::value;
     Rec<real, NS> o;
 #pragma unroll
     for (int j = 0; j < NS; ++j) o.v[j] = p.rho_in[j] * eq_moving<real, D, i>(U[j], p.T_in);
-    pop_store<real, PT, D, NS>(p, Gn + (size_t)i * nsl * RL, t, i, o);
+    pop_store_next<real, PT, D, NS>(p, Gn + (size_t)i * nsl * RL, t, i, o);
   });
 }
 
@@ -1001,14 +1038,14 @@ __device__ inline void outlet_node(const Params<real> &p, const Bufs<real, PT> &
     Rec<real, NS> o;
 #pragma unroll
     for (int j = 0; j < NS; ++j) o.v[j] = rj[j] * eq_rest<real, D>(U[j], T);
-    pop_store<real, PT, D, NS>(p, Gn, t, 0, o);
+    pop_store_next<real, PT, D, NS>(p, Gn, t, 0, o);
   }
   static_for<1, Q>([&](auto ic_) __attribute__((always_inline)) {
     constexpr int i = decltype(ic_)::value;
     Rec<real, NS> o;
 #pragma unroll
     for (int j = 0; j < NS; ++j) o.v[j] = rj[j] * eq_moving<real, D, i>(U[j], T);
-    pop_store<real, PT, D, NS>(p, Gn + (size_t)i * nsl * RL, t, i, o);
+    pop_store_next<real, PT, D, NS>(p, Gn + (size_t)i * nsl * RL, t, i, o);
   });
 }
 
