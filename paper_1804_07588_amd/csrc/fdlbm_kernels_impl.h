@@ -50,6 +50,13 @@ __device__ inline int xcd_block(int nb) {
   const int per = (nb + NXCD - 1) / NXCD;
   return (int)(blockIdx.x % NXCD) * per + (int)(blockIdx.x / NXCD);
 }
+// The same runs walked from their ends: a kernel that reads what the previous
+// kernel wrote in xcd_block order starts with the records written last, which
+// are the likeliest to be still cached.
+__device__ inline int xcd_block_reversed(int nb) {
+  const int per = (nb + NXCD - 1) / NXCD;
+  return (int)(blockIdx.x % NXCD) * per + (per - 1 - (int)(blockIdx.x / NXCD));
+}
 
 // Per-thread addressing: taps are node + k*stride(i) unless a periodic axis
 // wraps within 3 nodes (FAST = the node list holds no such node).
@@ -1080,7 +1087,9 @@ __device__ __forceinline__ void collide_block(const Params<real> &p, const Bufs<
 }
 template <typename real, typename PT, int D, int NS>
 __global__ void __launch_bounds__(BLOCK, sizeof(real) == 4 ? 2 : 1) k_collide(Params<real> p, Bufs<real, PT> b, int cur) {
-  const int nb = (p.n_gas + BLOCK - 1) / BLOCK, lb = xcd_block(nb);
+  // reversed: the streamed copy and moment records of the last blocks of
+  // k_moments come first
+  const int nb = (p.n_gas + BLOCK - 1) / BLOCK, lb = xcd_block_reversed(nb);
   if (lb >= nb) return;  // whole block: no barrier follows for it
   collide_block<real, PT, D, NS>(p, b, cur, lb);
 }
