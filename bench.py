@@ -141,8 +141,8 @@ def measured_traffic(kernel):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
-                                   "design-only", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the solver runs on one GPU; sharding a domain over several "
+                                   "GPUs is not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
     import torch

@@ -135,8 +135,9 @@ def _arr(x) -> np.ndarray:
 
 class Sim:
     """One simulation on the current HIP device, built from a workload dict
-    (see workloads.py).  precision: F64 or F32.  stream: a torch.cuda.Stream
-    or None for torch's current stream."""
+    (see workloads.py).  precision: F64, F32, or F16 / BF16 (16-bit
+    population storage, FP32 arithmetic).  stream: a torch.cuda.Stream or
+    None for torch's current stream."""
 
     def __init__(self, cfg: dict, precision: int = F32, init: dict | None = None, stream=None):
         import torch
