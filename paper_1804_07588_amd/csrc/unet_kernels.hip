@@ -201,7 +201,10 @@ __global__ void __launch_bounds__(TPB) k_wgrad(const __bf16 *__restrict__ GY, in
 // ---------------------------------------------------------------------------
 // bf16 gradient of a pre-activation from the f32 gradient of the layer
 // output (ReLU mask from the stored output y when y is given) and the bias
-// gradient (sum over positions, one atomic per channel and block)
+// gradient (sum over positions).  A thread's channel advances by TPB mod C per
+// element; when that is 0 (C divides TPB) the thread sums its channel in a
+// register and adds it to the block's LDS sum once, else per element.  One
+// atomic per channel and block into gbias.
 __global__ void __launch_bounds__(TPB) k_act_bwd(const float *__restrict__ g, const __bf16 *__restrict__ y,
                                                  size_t n, int C, __bf16 *__restrict__ gb,
                                                  float *__restrict__ gbias) {
@@ -210,15 +213,25 @@ __global__ void __launch_bounds__(TPB) k_act_bwd(const float *__restrict__ g, co
   __syncthreads();
   const size_t per = (size_t)TPB * 16;
   const size_t e0 = (size_t)blockIdx.x * per;
+  const int step = TPB % C;
+  int c = (int)((e0 + threadIdx.x) % (size_t)C);
+  float acc = 0.0f;
   for (size_t e = e0 + threadIdx.x; e < e0 + per && e < n; e += TPB) {
     float v = g[e];
     if (y && !((float)y[e] > 0.0f)) v = 0.0f;
     gb[e] = (__bf16)v;
-    atomicAdd(&sb[e % C], v);
+    if (step == 0) {
+      acc += v;
+    } else {
+      atomicAdd(&sb[c], v);
+      c += step;
+      if (c >= C) c -= C;
+    }
   }
+  if (step == 0 && acc != 0.0f) atomicAdd(&sb[c], acc);
   __syncthreads();
-  for (int c = threadIdx.x; c < C; c += TPB)
-    if (sb[c] != 0.0f) atomicAdd(&gbias[c], sb[c]);
+  for (int k = threadIdx.x; k < C; k += TPB)
+    if (sb[k] != 0.0f) atomicAdd(&gbias[k], sb[k]);
 }
 
 // 2x2x2 average pooling, edge R -> R/2
@@ -239,59 +252,82 @@ __global__ void k_pool(const __bf16 *__restrict__ X, int R, int C, size_t n_out,
   Y[e] = (__bf16)(0.125f * s);
 }
 // its adjoint: G_in += G_out / 8 (f32)
-__global__ void k_pool_bwd(const float *__restrict__ GO, int R, int C, size_t n_in, float *__restrict__ GI) {
+__global__ void k_pool_bwd(const float *__restrict__ GO, int R, int C, size_t n_in8, float *__restrict__ GI) {
+  // one thread per (input position, 8 channels); C % 8 == 0 (host-checked)
   const size_t e = (size_t)blockIdx.x * TPB + threadIdx.x;
-  if (e >= n_in) return;
-  const int r = R / 2;
-  const int c = (int)(e % C);
-  const size_t p = e / C;
+  if (e >= n_in8) return;
+  const int r = R / 2, C8 = C / 8;
+  const int c = 8 * (int)(e % C8);
+  const size_t p = e / C8;
   const int x = (int)(p % R), y = (int)((p / R) % R), z = (int)((p / ((size_t)R * R)) % R);
   const size_t b = p / ((size_t)R * R * R);
-  GI[e] += 0.125f * GO[(((b * r + z / 2) * r + y / 2) * r + x / 2) * (size_t)C + c];
+  const float *q = GO + (((b * r + z / 2) * r + y / 2) * r + x / 2) * (size_t)C + c;
+  f32x4 *o = reinterpret_cast<f32x4 *>(GI + p * C + c);
+  o[0] += 0.125f * *reinterpret_cast<const f32x4 *>(q);
+  o[1] += 0.125f * *reinterpret_cast<const f32x4 *>(q + 4);
 }
 
-// nearest 2x upsampling of X (edge r, C channels) into channels [off, off+C)
-// of Y (edge 2r, Ct channels)
+// nearest 2x upsampling, edge r -> R = 2r, into channels off .. off + C - 1
+// of a Ct-channel tensor; one thread per (output position, 8 channels)
+// (C, Ct and off multiples of 8, host-checked: 16-byte moves)
 __global__ void k_up(const __bf16 *__restrict__ X, int r, int C, __bf16 *__restrict__ Y, int Ct, int off,
-                     size_t n_out) {
+                     size_t n_out8) {
   const size_t e = (size_t)blockIdx.x * TPB + threadIdx.x;
-  if (e >= n_out) return;
-  const int R = 2 * r;
-  const int c = (int)(e % C);
-  const size_t p = e / C;
+  if (e >= n_out8) return;
+  const int R = 2 * r, C8 = C / 8;
+  const int c = 8 * (int)(e % C8);
+  const size_t p = e / C8;
   const int x = (int)(p % R), y = (int)((p / R) % R), z = (int)((p / ((size_t)R * R)) % R);
   const size_t b = p / ((size_t)R * R * R);
-  Y[p * Ct + off + c] = X[(((b * r + z / 2) * r + y / 2) * r + x / 2) * (size_t)C + c];
+  const bf16x8 v = *reinterpret_cast<const bf16x8 *>(X + (((b * r + z / 2) * r + y / 2) * r + x / 2) * (size_t)C + c);
+  *reinterpret_cast<bf16x8 *>(Y + p * Ct + off + c) = v;
 }
-// its adjoint: G_in (edge r, C) = sum of the 8 children's G_out[.., off + c]
-__global__ void k_up_bwd(const float *__restrict__ GO, int r, int C, int Ct, int off, size_t n_in,
+// its adjoint: G_in (edge r, C) = sum of the 8 children's G_out[.., off + c],
+// one thread per (input position, 8 channels)
+__global__ void k_up_bwd(const float *__restrict__ GO, int r, int C, int Ct, int off, size_t n_in8,
                          float *__restrict__ GI) {
   const size_t e = (size_t)blockIdx.x * TPB + threadIdx.x;
-  if (e >= n_in) return;
-  const int R = 2 * r;
-  const int c = (int)(e % C);
-  const size_t p = e / C;
+  if (e >= n_in8) return;
+  const int R = 2 * r, C8 = C / 8;
+  const int c = 8 * (int)(e % C8);
+  const size_t p = e / C8;
   const int x = (int)(p % r), y = (int)((p / r) % r), z = (int)((p / ((size_t)r * r)) % r);
   const size_t b = p / ((size_t)r * r * r);
-  float s = 0.0f;
+  f32x4 s0 = {0.0f, 0.0f, 0.0f, 0.0f}, s1 = s0;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const int zz = 2 * z + (k >> 2), yy = 2 * y + ((k >> 1) & 1), xx = 2 * x + (k & 1);
-    s += GO[(((b * R + zz) * R + yy) * (size_t)R + xx) * Ct + off + c];
+    const float *q = GO + (((b * R + zz) * R + yy) * (size_t)R + xx) * Ct + off + c;
+    s0 += *reinterpret_cast<const f32x4 *>(q);
+    s1 += *reinterpret_cast<const f32x4 *>(q + 4);
   }
-  GI[e] = s;
+  float *o = GI + p * C + c;
+  *reinterpret_cast<f32x4 *>(o) = s0;
+  *reinterpret_cast<f32x4 *>(o + 4) = s1;
 }
 
-// channel copy X (C) -> Y[.., off + c] (Ct channels), and its adjoint (+=)
-__global__ void k_copy_ch(const __bf16 *__restrict__ X, int C, __bf16 *__restrict__ Y, int Ct, int off, size_t n) {
+// channel copy X (C) -> Y[.., off + c] (Ct channels), and its adjoint (+=);
+// one thread per (position, 8 channels), C, Ct and off multiples of 8
+// (host-checked)
+__global__ void k_copy_ch(const __bf16 *__restrict__ X, int C, __bf16 *__restrict__ Y, int Ct, int off, size_t n8) {
   const size_t e = (size_t)blockIdx.x * TPB + threadIdx.x;
-  if (e >= n) return;
-  Y[(e / C) * Ct + off + e % C] = X[e];
+  if (e >= n8) return;
+  const int C8 = C / 8;
+  const size_t p = e / C8;
+  const int c = 8 * (int)(e % C8);
+  *reinterpret_cast<bf16x8 *>(Y + p * Ct + off + c) = *reinterpret_cast<const bf16x8 *>(X + p * C + c);
 }
-__global__ void k_copy_ch_bwd(const float *__restrict__ GY, int C, int Ct, int off, size_t n, float *__restrict__ GX) {
+__global__ void k_copy_ch_bwd(const float *__restrict__ GY, int C, int Ct, int off, size_t n8,
+                              float *__restrict__ GX) {
   const size_t e = (size_t)blockIdx.x * TPB + threadIdx.x;
-  if (e >= n) return;
-  GX[e] += GY[(e / C) * Ct + off + e % C];
+  if (e >= n8) return;
+  const int C8 = C / 8;
+  const size_t p = e / C8;
+  const int c = 8 * (int)(e % C8);
+  const float *q = GY + p * Ct + off + c;
+  f32x4 *o = reinterpret_cast<f32x4 *>(GX + p * C + c);
+  o[0] += *reinterpret_cast<const f32x4 *>(q);
+  o[1] += *reinterpret_cast<const f32x4 *>(q + 4);
 }
 
 // network input: f32 [s][cin] -> bf16 [s][Cp] zero-padded
@@ -396,28 +432,33 @@ hipError_t pool(const __bf16 *X, int R, int C, int N, __bf16 *Y, hipStream_t st)
   return hipGetLastError();
 }
 hipError_t pool_bwd(const float *GO, int R, int C, int N, float *GI, hipStream_t st) {
-  const size_t n = (size_t)N * R * R * R * C;
-  hipLaunchKernelGGL(k_pool_bwd, dim3(nblk(n)), dim3(TPB), 0, st, GO, R, C, n, GI);
+  if (C % 8) return hipErrorInvalidValue;
+  const size_t n8 = (size_t)N * R * R * R * (C / 8);
+  hipLaunchKernelGGL(k_pool_bwd, dim3(nblk(n8)), dim3(TPB), 0, st, GO, R, C, n8, GI);
   return hipGetLastError();
 }
 hipError_t up(const __bf16 *X, int r, int C, int N, __bf16 *Y, int Ct, int off, hipStream_t st) {
-  const size_t n = (size_t)N * 8 * r * r * r * C;
-  hipLaunchKernelGGL(k_up, dim3(nblk(n)), dim3(TPB), 0, st, X, r, C, Y, Ct, off, n);
+  if (C % 8 || Ct % 8 || off % 8) return hipErrorInvalidValue;
+  const size_t n8 = (size_t)N * 8 * r * r * r * (C / 8);
+  hipLaunchKernelGGL(k_up, dim3(nblk(n8)), dim3(TPB), 0, st, X, r, C, Y, Ct, off, n8);
   return hipGetLastError();
 }
 hipError_t up_bwd(const float *GO, int r, int C, int Ct, int off, int N, float *GI, hipStream_t st) {
-  const size_t n = (size_t)N * r * r * r * C;
-  hipLaunchKernelGGL(k_up_bwd, dim3(nblk(n)), dim3(TPB), 0, st, GO, r, C, Ct, off, n, GI);
+  if (C % 8 || Ct % 8 || off % 8) return hipErrorInvalidValue;
+  const size_t n8 = (size_t)N * r * r * r * (C / 8);
+  hipLaunchKernelGGL(k_up_bwd, dim3(nblk(n8)), dim3(TPB), 0, st, GO, r, C, Ct, off, n8, GI);
   return hipGetLastError();
 }
 hipError_t copy_ch(const __bf16 *X, int C, __bf16 *Y, int Ct, int off, size_t npos, hipStream_t st) {
-  const size_t n = npos * C;
-  hipLaunchKernelGGL(k_copy_ch, dim3(nblk(n)), dim3(TPB), 0, st, X, C, Y, Ct, off, n);
+  if (C % 8 || Ct % 8 || off % 8) return hipErrorInvalidValue;
+  const size_t n8 = npos * (C / 8);
+  hipLaunchKernelGGL(k_copy_ch, dim3(nblk(n8)), dim3(TPB), 0, st, X, C, Y, Ct, off, n8);
   return hipGetLastError();
 }
 hipError_t copy_ch_bwd(const float *GY, int C, int Ct, int off, size_t npos, float *GX, hipStream_t st) {
-  const size_t n = npos * C;
-  hipLaunchKernelGGL(k_copy_ch_bwd, dim3(nblk(n)), dim3(TPB), 0, st, GY, C, Ct, off, n, GX);
+  if (C % 8 || Ct % 8 || off % 8) return hipErrorInvalidValue;
+  const size_t n8 = npos * (C / 8);
+  hipLaunchKernelGGL(k_copy_ch_bwd, dim3(nblk(n8)), dim3(TPB), 0, st, GY, C, Ct, off, n8, GX);
   return hipGetLastError();
 }
 hipError_t input(const float *in, int cin, int Cp, size_t npos, __bf16 *X, hipStream_t st) {
