@@ -328,7 +328,8 @@ def perturbed_init(cfg: dict, seed: int, amp_rho: float = 0.02, amp_u: float = 0
     base = uniform_init(cfg)
     nx, ny, nz = cfg["nx"], cfg["ny"], cfg["nz"]
     rng = SplitMix64(seed)
-    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    # broadcast views instead of full coordinate grids (same values)
+    z, y, x = (np.arange(nz)[:, None, None], np.arange(ny)[None, :, None], np.arange(nx)[None, None, :])
 
     def field(amp):
         f = np.zeros((nz, ny, nx))

@@ -289,6 +289,55 @@ BOUNDS_16 = {
 }
 
 
+def test_bed_256_16bit_storage_against_fp32(fd):
+    """The 256^3 bed of the 16-bit storage benchmark (same construction and
+    launch configuration), from a smoothly perturbed state, two steps: FP16
+    and BF16 population storage against FP32 storage, which the full 128^3
+    case pins to the oracle at 1e-5 (the FP64 oracle would need about 25 GB
+    and minutes per step at this size).  Bounds as for the 16-bit runs
+    against the oracle at 128^3; fields finite; per-species mass and the
+    reaction totals as in the FP32 run."""
+    mask, _ = W.sphere_pack_mask(256, radius=6.0, porosity=0.6, seed=12345, buffer=8)
+    cfg = W.packed_bed(mask=mask)
+    init = W.uniform_init(cfg)
+    n = 256
+    s = np.sin(2 * np.pi * np.arange(n) / n)
+    c = np.cos(2 * np.pi * np.arange(n) / n)
+    smooth = (s[:, None, None] * c[None, :, None] * s[None, None, :]).reshape(-1)  # [z][y][x]
+    for a in range(3):
+        init["u"][a] = 0.005 * np.roll(smooth, 4097 * a)
+    init["T"] = init["T"] * (1.0 + 0.01 * np.roll(smooth, 77))
+    init["rho"] = init["rho"] * (1.0 + 0.02 * np.roll(smooth, 12345))[None, :]
+    print("[parity] bed 256^3, 2 steps, 16-bit storage against FP32", flush=True)
+    ns = len(cfg["species"]["M"])
+    ref = fd.Sim(cfg, precision=fd.F32, init=init)
+    ref.step(2)
+    ref.sync()
+    ref_obs = ref.observe()
+    assert not ref_obs["bad"]
+    for prec, tol in ((fd.F16, 5e-4), (fd.BF16, 5e-3)):
+        g = fd.Sim(cfg, precision=prec, init=init)
+        g.step(2)
+        g.sync()
+        obs = g.observe()
+        assert not obs["bad"]
+        errs = {}
+        for j in range(ns):
+            a, b = g.field(fd.FIELD_RHO, j), ref.field(fd.FIELD_RHO, j)
+            assert np.all(np.isfinite(a))
+            errs[f"rho{j}"] = rel_err(a, b)
+        for a in range(3):
+            errs[f"u{a}"] = np.abs(g.field(fd.FIELD_U, a) - ref.field(fd.FIELD_U, a)).max() / np.sqrt(T0)
+        errs["T"] = rel_err(g.field(fd.FIELD_T), ref.field(fd.FIELD_T))
+        errs["Ts"] = rel_err(g.field(fd.FIELD_TS), ref.field(fd.FIELD_TS))
+        errs["wall_r"] = rel_err(g.field(fd.FIELD_WALL_R), ref.field(fd.FIELD_WALL_R))
+        errs["mass"] = float(np.abs(obs["mass"] - ref_obs["mass"]).max() / np.abs(ref_obs["mass"]).max())
+        errs["moles_reacted"] = abs(obs["moles_reacted"] - ref_obs["moles_reacted"]) / abs(ref_obs["moles_reacted"])
+        assert_errs(errs, tol)
+        g.close()
+    ref.close()
+
+
 @pytest.mark.parametrize("prec_name", ["F16", "BF16"])
 def test_16bit_storage_errors(oracle_lib, fd, prec_name):
     """16-bit population storage (deviations from w_i rho_ref,j, FP32
