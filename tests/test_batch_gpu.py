@@ -171,3 +171,33 @@ def test_batch_rejects_mixed_members(fd):
         fd.Batch([a, c])
     with pytest.raises(fd.FdlbmError):
         fd.Batch([a, a])
+
+
+def test_batch_of_benchmark_beds(fd, stream, oracle_lib):
+    """The first six beds of the 64-bed batch benchmark (same generator and
+    seed: edges 48-96, porosity 0.4-0.7, FP32), batched with graph replays
+    and direct steps: bitwise the same samples stepped alone; the smallest
+    one also against the oracle."""
+    cfgs = W.batch_beds(6)
+    print("[batch] benchmark beds", [c["sample"]["n"] for c in cfgs], flush=True)
+    init = [W.uniform_init(c) for c in cfgs]
+    bat = [fd.Sim(c, precision=fd.F32, init=i, stream=stream) for c, i in zip(cfgs, init)]
+    b = fd.Batch(bat)
+    b.set_grid(graph_steps=4)
+    b.step(10)
+    for k, (c, i) in enumerate(zip(cfgs, init)):
+        ref = fd.Sim(c, precision=fd.F32, init=i)
+        ref.set_overlap(False)
+        ref.step(10)
+        assert_same(snapshot(fd, ref), snapshot(fd, bat[k]), f"benchmark bed {k} (edge {c['sample']['n']})")
+        ref.close()
+    k = min(range(len(cfgs)), key=lambda q: cfgs[q]["sample"]["n"])
+    o = oracle_lib.OracleSim(cfgs[k], init[k])
+    o.step(10)
+    for j in range(len(cfgs[k]["species"]["M"])):
+        g, r = bat[k].field(fd.FIELD_RHO, j), o.field(oracle_lib.OF_RHO, j)
+        assert np.abs(g - r).max() / np.abs(r).max() < 1e-5
+    g, r = bat[k].field(fd.FIELD_T), o.field(oracle_lib.OF_T)
+    assert np.abs(g - r).max() / np.abs(r).max() < 1e-5
+    o.close()
+    b.close()
