@@ -95,3 +95,42 @@ def test_training_reduces_the_loss(net):
     l1 = net.train_step(xd, td, wd, ws, 1e-3)
     print(f"[unet] loss {l0:.4f} -> {l1:.4f}", flush=True)
     assert np.isfinite(l1) and l1 < 0.7 * l0
+
+
+def test_full_size_forward_and_gradient():
+    """The network at the size the learned warm start uses (64^3 cubes; one
+    sample, so the FP64 oracle finishes in seconds): forward output and every
+    layer's gradient against the oracle, to the bounds above."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1804_07588_amd import surrogate
+    R64 = 64
+    big = surrogate.UNet(R64, 1, NIN, NOUT)
+    p = W.unet_init_params(seed=6, bias_scale=0.1)
+    big.set_params(p)
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal((1, R64 ** 3, NIN)).astype(np.float32)
+    t = rng.standard_normal((1, R64 ** 3, NOUT)).astype(np.float32)
+    w = (rng.random((1, R64 ** 3, NOUT)) > 0.25).astype(np.float32)
+    print("[unet] forward and gradient R=64 n=1", flush=True)
+    y = big.forward(dev(x)).cpu().numpy()
+    shape_in, shape_out = (1, R64, R64, R64, NIN), (1, R64, R64, R64, NOUT)
+    ref = U.forward(p.astype(np.float64), x.reshape(shape_in), W.UNET_LAYERS).numpy()
+    ref = ref[..., :NOUT].reshape(1, R64 ** 3, NOUT)
+    assert rel(y, ref) < 2e-2
+    loss, g = big.gradient(dev(x), dev(t), dev(w), float(w.sum()))
+    lo, go = U.loss_and_grad(p.astype(np.float64), x.reshape(shape_in), t.reshape(shape_out),
+                             w.reshape(shape_out), float(w.sum()), W.UNET_LAYERS)
+    assert abs(loss - lo) < 1e-2 * abs(lo)
+    offs, n = W.unet_layout()
+    bounds = [o for pair in offs for o in pair] + [n]
+    errs = []
+    for k, (a, b) in enumerate(zip(bounds[:-1], bounds[1:])):
+        e = rel(g[a:b], go[a:b])
+        cos = float(np.dot(g[a:b], go[a:b]) / (np.linalg.norm(g[a:b]) * np.linalg.norm(go[a:b]) + 1e-300))
+        errs.append((k // 2, "w" if k % 2 == 0 else "b", round(e, 4), round(cos, 5)))
+    print("[unet] R=64 per-layer gradient (layer, part, rel L2 error, cosine):", errs, flush=True)
+    for layer, part, e, cos in errs:
+        assert e < 0.1 and cos > 0.995, (layer, part, e, cos)
+    big.close()
