@@ -13,8 +13,9 @@
  *     Eq.(11)-(13), Prandtl number Eq.(19)-(21), lattice-deviation terms);
  *   - the reactive diffusive wall on the solid nodes, Eq.(37)-(41) with the
  *     rate law Eq.(50) and the reaction enthalpy Eq.(42);
- *   - the solid: forward-Euler heat equation Eq.(45)-(47) coupled at the wall
- *     nodes (Eq.(48), flux-matched form).
+ *   - the solid: heat equation Eq.(45)-(47) by forward Euler (or, as an
+ *     option, Crank-Nicolson) coupled at the wall nodes (Eq.(48),
+ *     flux-matched form).
  *
  * Units: lattice units.  Masses relative to the lightest species (>= 1);
  * the reference temperature is 1/3; pressure p = C T with C = sum rho_j/M_j.
@@ -170,8 +171,9 @@ int fdlbm_set_prandtl(fdlbm_ctx *ctx, const double *Pr_j);
 int fdlbm_set_lj_transport(fdlbm_ctx *ctx, const double *eps_over_k, double T_unit, double tstar_min,
                            double tstar_max, int n, const double *omega_mu, const double *omega_d);
 
-/* Solid (Eq.(45)-(47)): thermal diffusivity alpha_s (0 <= alpha_s <= 1/(2D),
- * the forward-Euler bound, else FDLBM_E_INVALID), volumetric heat capacity
+/* Solid (Eq.(45)-(47)): thermal diffusivity alpha_s (alpha_s >= 0; with the
+ * forward-Euler scheme, the default, also alpha_s <= 1/(2D), its stability
+ * bound; else FDLBM_E_INVALID), volumetric heat capacity
  * C_s > 0, and T_bc6[6] Dirichlet temperatures of the closed domain faces
  * (-x, +x, -y, +y, -z, +z; NaN = adiabatic; NULL = all adiabatic). */
 int fdlbm_set_solid(fdlbm_ctx *ctx, double alpha_s, double C_s, const double *T_bc6);

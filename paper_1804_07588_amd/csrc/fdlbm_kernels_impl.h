@@ -1,6 +1,7 @@
 // HIP kernels (gfx950) of the coupled FD-LBM time step.
 //
-// Per step, on one stream:
+// Per step (k_wall then k_solid on a second stream beside k_moments then
+// k_collide, ordered by events; or all four in sequence on one stream):
 //   k_wall     reactive diffusive wall at every wall node: streaming of the
 //              populations arriving from the gas, wall densities and the
 //              thermalised emission (Eq.(37)-(42), (50))
@@ -12,8 +13,9 @@
 //              and of the auxiliary state, equilibria and the trapezoidal
 //              collision (Eq.(4), (6), (12)-(13), (19)-(21), (24)); writes the
 //              inlet/outlet planes directly
-//   k_solid    forward-Euler heat step in the solid on an LDS tile with the
-//              wall-node interface source (Eq.(45)-(48))
+//   k_solid    heat step in the solid on an LDS tile with the wall-node
+//              interface source (Eq.(45)-(48)): forward Euler, or
+//              Crank-Nicolson solved by Jacobi sweeps (k_solid_pass)
 //
 // Storage is per SLOT (gas nodes in processing order, then wall nodes).
 // Populations are records of the NS species per (direction, slot),
@@ -22,6 +24,8 @@
 // consecutive records.  Only the moments kernel gathers taps; it stores the
 // streamed records in slot order, so the collision reads them as contiguous
 // records (a gather costs several times a coalesced load on this GPU).
+// Populations that only the next step reads (post-collision and
+// wall-emitted) are written with non-temporal stores.
 #pragma once
 #include <type_traits>
 
