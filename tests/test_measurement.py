@@ -1,0 +1,95 @@
+"""Host logic of the measurement: the rocprofv3 summary (calibration of the
+HBM counters by a plain copy of known size, per-step kernel groups) on
+synthetic rocpd-shaped databases, and the rule that the benchmark reports a
+counter record only while the kernel sources still hash to it."""
+import json
+import os
+import sqlite3
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+from paper_1804_07588_amd import profsummary  # noqa: E402
+
+
+def _db(path, kernels=(), pmc=()):
+    os.makedirs(path, exist_ok=True)
+    con = sqlite3.connect(os.path.join(path, "run_results.db"))
+    con.execute("create table kernels (name text, start integer, end integer)")
+    con.execute("create table pmc_events (name text, counter_name text, counter_value real)")
+    con.executemany("insert into kernels values (?, ?, ?)", kernels)
+    con.executemany("insert into pmc_events values (?, ?, ?)", pmc)
+    con.commit()
+    con.close()
+
+
+def test_summary_calibrates_counters_and_groups_launches(tmp_path):
+    mib = 64
+    true = mib * 2**20
+    d = str(tmp_path)
+    # kernel trace: two launches of each list variant of k_moments (ns)
+    _db(os.path.join(d, "kt"), kernels=[
+        ("void fdlbm::k_moments<true, float, float, 3, 5>(...)", 0, 300_000),
+        ("void fdlbm::k_moments<true, float, float, 3, 5>(...)", 1_000_000, 1_320_000),
+        ("void fdlbm::k_moments<false, float, float, 3, 5>(...)", 400_000, 440_000),
+        ("void fdlbm::k_moments<false, float, float, 3, 5>(...)", 1_400_000, 1_440_000),
+    ])
+    # counters in KiB per dispatch: the copy reads `true` bytes but FETCH_SIZE
+    # reports half of them, WRITE_SIZE all of them
+    _db(os.path.join(d, "fetch"), pmc=[
+        ("k_copy_words(...)", "FETCH_SIZE", true / 2 / 1024),
+        ("void fdlbm::k_moments<true, float, float, 3, 5>(...)", "FETCH_SIZE", 1000.0),
+        ("void fdlbm::k_moments<false, float, float, 3, 5>(...)", "FETCH_SIZE", 100.0),
+    ])
+    _db(os.path.join(d, "write"), pmc=[
+        ("k_copy_words(...)", "WRITE_SIZE", true / 1024),
+        ("void fdlbm::k_moments<true, float, float, 3, 5>(...)", "WRITE_SIZE", 500.0),
+        ("void fdlbm::k_moments<false, float, float, 3, 5>(...)", "WRITE_SIZE", 50.0),
+    ])
+    out_txt, out_json = os.path.join(d, "s.txt"), os.path.join(d, "t.json")
+    profsummary.main(["x", d, out_txt, out_json, str(mib), "kt cmd", "pmc cmd"])
+    rec = json.load(open(out_json))
+    assert rec["factors"] == {"fetch": pytest.approx(2.0), "write": pytest.approx(1.0)}
+    g = rec["kernels"]["k_moments"]
+    assert g["fetch_bytes"] == pytest.approx((1000.0 + 100.0) * 1024 * 2.0)
+    assert g["write_bytes"] == pytest.approx((500.0 + 50.0) * 1024 * 1.0)
+    assert g["avg_us"] == pytest.approx(310.0 + 40.0)   # mean durations of both lists, summed
+    assert rec["source_sha256"] == profsummary.source_hash()
+    assert "k_moments" in open(out_txt).read()
+
+
+def test_traffic_is_reported_only_for_the_profiled_sources(tmp_path, monkeypatch):
+    import bench
+    rec = {"source_sha256": profsummary.source_hash(),
+           "kernels": {"k_moments": {"fetch_bytes": 3.0, "write_bytes": 4.0, "avg_us": 1.0}}}
+    path = os.path.join(str(tmp_path), "t.json")
+    with open(path, "w") as fh:
+        json.dump(rec, fh)
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", path)
+    assert bench.measured_traffic("k_moments") == 7.0
+    assert bench.measured_traffic("k_collide") is None
+    rec["source_sha256"] = "0" * 64
+    with open(path, "w") as fh:
+        json.dump(rec, fh)
+    assert bench.measured_traffic("k_moments") is None
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", os.path.join(str(tmp_path), "missing.json"))
+    assert bench.measured_traffic("k_moments") is None
+
+
+def test_source_hash_ignores_the_network_sources(tmp_path, monkeypatch):
+    """The record covers the lattice-Boltzmann kernels and their C ABI; the
+    U-Net's sources and the calibration copy do not enter the hash."""
+    csrc = tmp_path / "csrc"
+    csrc.mkdir()
+    (csrc / "fdlbm_kernels_impl.h").write_text("a")
+    (csrc / "unet_kernels.hip").write_text("b")
+    monkeypatch.setattr(profsummary, "HERE", str(tmp_path))
+    h1 = profsummary.source_hash()
+    (csrc / "unet_kernels.hip").write_text("c")
+    (csrc / "calib_copy.hip").write_text("d")
+    assert profsummary.source_hash() == h1
+    (csrc / "fdlbm_kernels_impl.h").write_text("e")
+    assert profsummary.source_hash() != h1
