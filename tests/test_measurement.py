@@ -93,3 +93,13 @@ def test_source_hash_ignores_the_network_sources(tmp_path, monkeypatch):
     assert profsummary.source_hash() == h1
     (csrc / "fdlbm_kernels_impl.h").write_text("e")
     assert profsummary.source_hash() != h1
+
+
+def test_bench_refuses_several_gpus():
+    """The solver runs on one GPU: more than one exits with a message."""
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
