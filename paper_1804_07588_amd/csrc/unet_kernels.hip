@@ -201,34 +201,52 @@ __global__ void __launch_bounds__(TPB) k_wgrad(const __bf16 *__restrict__ GY, in
 // ---------------------------------------------------------------------------
 // bf16 gradient of a pre-activation from the f32 gradient of the layer
 // output (ReLU mask from the stored output y when y is given) and the bias
-// gradient (sum over positions).  A thread's channel advances by TPB mod C per
-// element; when that is 0 (C divides TPB) the thread sums its channel in a
-// register and adds it to the block's LDS sum once, else per element.  One
-// atomic per channel and block into gbias.
+// gradient (sum over positions).  A thread moves 8 channels of a position
+// per element group (C % 8 == 0, host-checked); its channel group advances
+// by TPB mod C/8 per group, and when that is 0 (C/8 divides TPB) the thread
+// sums its channels in registers and adds them to the block's LDS sums once,
+// else per group.  One atomic per channel and block into gbias.
 __global__ void __launch_bounds__(TPB) k_act_bwd(const float *__restrict__ g, const __bf16 *__restrict__ y,
-                                                 size_t n, int C, __bf16 *__restrict__ gb,
+                                                 size_t n8, int C, __bf16 *__restrict__ gb,
                                                  float *__restrict__ gbias) {
   __shared__ float sb[WG_MAXC];
   for (int c = threadIdx.x; c < C; c += TPB) sb[c] = 0.0f;
   __syncthreads();
+  const int C8 = C / 8;
   const size_t per = (size_t)TPB * 16;
   const size_t e0 = (size_t)blockIdx.x * per;
-  const int step = TPB % C;
-  int c = (int)((e0 + threadIdx.x) % (size_t)C);
-  float acc = 0.0f;
-  for (size_t e = e0 + threadIdx.x; e < e0 + per && e < n; e += TPB) {
-    float v = g[e];
-    if (y && !((float)y[e] > 0.0f)) v = 0.0f;
-    gb[e] = (__bf16)v;
+  const int step = TPB % C8;
+  int cg = (int)((e0 + threadIdx.x) % (size_t)C8);
+  float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (size_t e = e0 + threadIdx.x; e < e0 + per && e < n8; e += TPB) {
+    const f32x4 v0 = *reinterpret_cast<const f32x4 *>(g + 8 * e);
+    const f32x4 v1 = *reinterpret_cast<const f32x4 *>(g + 8 * e + 4);
+    float v[8] = {v0[0], v0[1], v0[2], v0[3], v1[0], v1[1], v1[2], v1[3]};
+    if (y) {
+      const bf16x8 yy = *reinterpret_cast<const bf16x8 *>(y + 8 * e);
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (!((float)yy[i] > 0.0f)) v[i] = 0.0f;
+    }
+    bf16x8 o;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) o[i] = (__bf16)v[i];
+    *reinterpret_cast<bf16x8 *>(gb + 8 * e) = o;
     if (step == 0) {
-      acc += v;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) acc[i] += v[i];
     } else {
-      atomicAdd(&sb[c], v);
-      c += step;
-      if (c >= C) c -= C;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) atomicAdd(&sb[8 * cg + i], v[i]);
+      cg += step;
+      if (cg >= C8) cg -= C8;
     }
   }
-  if (step == 0 && acc != 0.0f) atomicAdd(&sb[c], acc);
+  if (step == 0) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (acc[i] != 0.0f) atomicAdd(&sb[8 * cg + i], acc[i]);
+  }
   __syncthreads();
   for (int k = threadIdx.x; k < C; k += TPB)
     if (sb[k] != 0.0f) atomicAdd(&gbias[k], sb[k]);
@@ -420,9 +438,9 @@ hipError_t wgrad(const __bf16 *GY, int Co, const __bf16 *X, int Ci, int R, int N
 }
 
 hipError_t act_bwd(const float *g, const __bf16 *y, size_t n, int C, __bf16 *gb, float *gbias, hipStream_t st) {
-  if (C > WG_MAXC) return hipErrorInvalidValue;
-  const size_t per = (size_t)TPB * 16;
-  hipLaunchKernelGGL(k_act_bwd, dim3((unsigned)((n + per - 1) / per)), dim3(TPB), 0, st, g, y, n, C, gb, gbias);
+  if (C > WG_MAXC || C % 8 || n % C) return hipErrorInvalidValue;
+  const size_t n8 = n / 8, per = (size_t)TPB * 16;
+  hipLaunchKernelGGL(k_act_bwd, dim3((unsigned)((n8 + per - 1) / per)), dim3(TPB), 0, st, g, y, n8, C, gb, gbias);
   return hipGetLastError();
 }
 
