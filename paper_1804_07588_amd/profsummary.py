@@ -18,6 +18,7 @@ bytes it reports for that copy.
 
 Usage: python3 -m paper_1804_07588_amd.profsummary <dir> <out.txt> <traffic.json>
        <calib MiB> "<command of the kt run>" "<command of the counter runs>"
+       [<first launch> <launches> ["<workload title>"]]
 """
 from __future__ import annotations
 
@@ -47,6 +48,15 @@ def source_hash() -> str:
 
 
 def short(name: str) -> str:
+    # names the trace left mangled (the 16-bit storage instantiations): the
+    # kernel's identifier and its leading bool template argument, if any
+    m = re.match(r"_ZN5fdlbm(\d+)", name)
+    if m:
+        n = int(m.group(1))
+        ident = name[m.end():m.end() + n]
+        rest = name[m.end() + n:]
+        flag = {"ILb1E": "<true, ...>", "ILb0E": "<false, ...>"}.get(rest[:5], "<...>")
+        return ident + flag
     name = re.sub(r"\(.*", "", name)
     name = name.replace("fdlbm::", "").replace("at::native::", "").strip()
     return name[5:] if name.startswith("void ") else name
@@ -86,16 +96,18 @@ def counters(d: str, counter: str) -> dict:
 def main(argv):
     d, out_txt, out_json, calib_mib, cmd_kt, cmd_pmc = argv[1:7]
     skip, take = (int(argv[7]), int(argv[8])) if len(argv) > 8 else (0, 0)
+    title = argv[9] if len(argv) > 9 else "128^3 D3Q19, 5 species, FP32"
     calib_bytes = int(calib_mib) * 2**20
     ks = kernel_stats(os.path.join(d, "kt"), skip, take)
     fetch = counters(os.path.join(d, "fetch"), "FETCH_SIZE")   # KiB per dispatch
     write = counters(os.path.join(d, "write"), "WRITE_SIZE")
     cal_f = calib_bytes / (fetch["k_copy_words"] * 1024)
     cal_w = calib_bytes / (write["k_copy_words"] * 1024)
-    lines = ["rocprofv3 summary of the packed-bed step (128^3 D3Q19, 5 species, FP32)", "",
+    lines = [f"rocprofv3 summary of the packed-bed step ({title})", "",
              "kernel trace:    " + cmd_kt, "counter passes:  " + cmd_pmc,
              "summary:         python3 -m paper_1804_07588_amd.profsummary " + " ".join(argv[1:5]) +
-             " '<kernel trace command>' '<counter command>'" + (f" {skip} {take}" if take else ""),
+             " '<kernel trace command>' '<counter command>'" + (f" {skip} {take}" if take else "") +
+             (f" '{title}'" if len(argv) > 9 else ""),
              "(rocprofv3 runs from the repository root after cd /tmp && export TMPDIR=/tmp)",
              (f"durations: launches {skip} .. {skip + take - 1} of each kernel, the pass of bench.py in which "
               "the kernels run one after the other (its timed pass overlaps the wall and solid kernels "
