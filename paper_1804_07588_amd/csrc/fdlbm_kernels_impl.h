@@ -713,14 +713,17 @@ __device__ __forceinline__ void moments_block(const Params<real> &p, const Bufs<
   const int tl = lb * BLOCK + threadIdx.x;
   if (tl < count) moments_node<FAST, real, PT, D, NS>(p, b, cur, wtab, first + tl);
 }
-template <bool FAST, typename real, typename PT, int D, int NS>
+// one launch over both node lists (the plain-stride blocks, then the
+// periodic-wrap ones): the second list's blocks fill the first one's tail
+template <typename real, typename PT, int D, int NS>
 __global__ void __launch_bounds__(BLOCK, 4) k_moments(Params<real> p, Bufs<real, PT> b, int cur) {
   __shared__ WTab<real> wtab;
   load_wtab_gas<real, NS>(p, wtab);
-  const int count = FAST ? p.n_gas_fast : p.n_gas - p.n_gas_fast;
-  const int nb = (count + BLOCK - 1) / BLOCK, lb = xcd_block(nb);
-  if (lb >= nb) return;
-  moments_block<FAST, real, PT, D, NS>(p, b, cur, wtab, lb);
+  const int nf = (p.n_gas_fast + BLOCK - 1) / BLOCK, nw = (p.n_gas - p.n_gas_fast + BLOCK - 1) / BLOCK;
+  const int lb = xcd_block(nf + nw);
+  if (lb >= nf + nw) return;
+  if (lb < nf) moments_block<true, real, PT, D, NS>(p, b, cur, wtab, lb);
+  else moments_block<false, real, PT, D, NS>(p, b, cur, wtab, lb - nf);
 }
 
 // ===========================================================================
@@ -1500,8 +1503,8 @@ inline hipError_t step_impl(const Params<real> &p, const Bufs<real, PT> &b, int 
   };
   if (two && li.n_solid > 0) solid(sw);
   mark(K_MOMENTS_ID, 0, st);
-  if (ggf > 0) hipLaunchKernelGGL((k_moments<true, real, PT, D, NS>), dim3(xcd_grid(ggf)), blk, 0, st, p, b, cur);
-  if (ggs > 0) hipLaunchKernelGGL((k_moments<false, real, PT, D, NS>), dim3(xcd_grid(ggs)), blk, 0, st, p, b, cur);
+  if (ggf + ggs > 0)
+    hipLaunchKernelGGL((k_moments<real, PT, D, NS>), dim3(xcd_grid(ggf + ggs)), blk, 0, st, p, b, cur);
   mark(K_MOMENTS_ID, 1, st);
   if (two) (void)hipStreamWaitEvent(st, li.ev_wall, 0);
   mark(K_COLLIDE_ID, 0, st);
