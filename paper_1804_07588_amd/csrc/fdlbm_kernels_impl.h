@@ -713,6 +713,17 @@ __device__ __forceinline__ void moments_block(const Params<real> &p, const Bufs<
   const int tl = lb * BLOCK + threadIdx.x;
   if (tl < count) moments_node<FAST, real, PT, D, NS>(p, b, cur, wtab, first + tl);
 }
+// one node list per launch (BF16 storage: there the combined kernel below
+// ran 12 % slower on the 256^3 bed, the others gain from it)
+template <bool FAST, typename real, typename PT, int D, int NS>
+__global__ void __launch_bounds__(BLOCK, 4) k_moments_list(Params<real> p, Bufs<real, PT> b, int cur) {
+  __shared__ WTab<real> wtab;
+  load_wtab_gas<real, NS>(p, wtab);
+  const int count = FAST ? p.n_gas_fast : p.n_gas - p.n_gas_fast;
+  const int nb = (count + BLOCK - 1) / BLOCK, lb = xcd_block(nb);
+  if (lb >= nb) return;
+  moments_block<FAST, real, PT, D, NS>(p, b, cur, wtab, lb);
+}
 // one launch over both node lists (the plain-stride blocks, then the
 // periodic-wrap ones): the second list's blocks fill the first one's tail
 template <typename real, typename PT, int D, int NS>
@@ -1503,8 +1514,14 @@ inline hipError_t step_impl(const Params<real> &p, const Bufs<real, PT> &b, int 
   };
   if (two && li.n_solid > 0) solid(sw);
   mark(K_MOMENTS_ID, 0, st);
-  if (ggf + ggs > 0)
+  if constexpr (std::is_same_v<PT, __bf16>) {
+    if (ggf > 0)
+      hipLaunchKernelGGL((k_moments_list<true, real, PT, D, NS>), dim3(xcd_grid(ggf)), blk, 0, st, p, b, cur);
+    if (ggs > 0)
+      hipLaunchKernelGGL((k_moments_list<false, real, PT, D, NS>), dim3(xcd_grid(ggs)), blk, 0, st, p, b, cur);
+  } else if (ggf + ggs > 0) {
     hipLaunchKernelGGL((k_moments<real, PT, D, NS>), dim3(xcd_grid(ggf + ggs)), blk, 0, st, p, b, cur);
+  }
   mark(K_MOMENTS_ID, 1, st);
   if (two) (void)hipStreamWaitEvent(st, li.ev_wall, 0);
   mark(K_COLLIDE_ID, 0, st);
