@@ -77,6 +77,26 @@ def parse():
     return ap.parse_args()
 
 
+def alg_bytes(n_gas, n_links, n_solid, ns, Q, b):
+    """Algorithmic HBM bytes of one step and their split over the kernel
+    groups.  Per step every gas population is read once and written once,
+    every wall link's population of each species is read and written once,
+    and the solid temperature is read and written once.  The split gives
+    each byte to exactly one kernel: the moments pass reads the populations
+    (through the streaming taps), the collision writes them, the wall reads
+    and writes the link populations, the solid its temperature.  The
+    streamed copy and the moment records passed from one gas kernel to the
+    other are overheads of the two-pass step, not algorithmic bytes.
+    Returns (bytes per step, {kernel group: bytes per launch})."""
+    per_kernel = {
+        "k_moments": n_gas * Q * ns * b,       # pre-collision pops in (through the taps)
+        "k_collide": n_gas * Q * ns * b,       # post-collision pops out
+        "k_wall": n_links * 2 * ns * b,        # link pops in, emitted pops out
+        "k_solid": n_solid * 2 * b,            # solid temperature in and out
+    }
+    return sum(per_kernel.values()), per_kernel
+
+
 def bed(n):
     from paper_1804_07588_amd import workloads as W
     mask, nsph = W.sphere_pack_mask(n, radius=6.0, porosity=0.6, seed=12345, buffer=8)
@@ -169,17 +189,7 @@ def main():
     ns, Q = len(cfg["species"]["M"]), 19
     # wall links = incoming links of all wall nodes (each carries one population per species)
     n_links = int(_count_wall_links(kind, cfg))
-    # algorithmic bytes per step: every gas population read once and written
-    # once, every wall link's populations read and written once, the solid
-    # temperature read and written once
-    B_alg = n_gas * 2 * Q * ns * b + n_links * 2 * ns * b + n_solid * 2 * b
-    # ... and per kernel group and launch
-    kernel_alg_bytes = {
-        "k_collide": n_gas * 2 * Q * ns * b,   # pre-collision pops in, post-collision pops out
-        "k_moments": n_gas * Q * ns * b,       # pre-collision pops in
-        "k_wall": n_links * 2 * ns * b,        # link pops in, emitted pops out
-        "k_solid": n_solid * 2 * b,            # solid temperature in and out
-    }
+    B_alg, kernel_alg_bytes = alg_bytes(n_gas, n_links, n_solid, ns, Q, b)
 
     if args.steady:
         steady(args, sim, cfg, n_gas, ns, init)

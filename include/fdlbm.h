@@ -234,8 +234,35 @@ int fdlbm_bind_workspace(fdlbm_ctx *ctx, void *dev_ptr, size_t bytes);
 int fdlbm_init_fields(fdlbm_ctx *ctx, const double *rho, const double *u, const double *T,
                       const double *Ts);
 
-/* Enqueue n_steps time steps on the context's stream (asynchronous). */
+/* Enqueue n_steps time steps on the context's stream (asynchronous).  One
+ * step is the whole update of Sec. 4-5 in the paper's order: the reactive
+ * wall (Eq.(37)-(42), (50)), streaming with the interpolation of
+ * Eq.(33)-(36), moments and transport (Eq.(3), (5), (7)-(8), (14)-(17),
+ * (25)), the correction sources (Eq.(11)-(13), (19)-(21)), the collision
+ * (Eq.(4), (6), (24)), the solid heat step (Eq.(45)-(48)) and the
+ * inlet/outlet planes (Sec. 6).
+ * Every step also keeps a stability record on the device: the moments pass
+ * marks the first step in which a gas node has a non-finite or negative
+ * density or temperature.  With a check interval set (fdlbm_set_sync_check)
+ * the call runs the steps in chunks of that many, synchronises after each
+ * chunk, and returns FDLBM_E_UNSTABLE after the chunk in which the record
+ * was set (the state then holds the end of that chunk; fdlbm_last_step
+ * gives the step).  Without it the call only enqueues and returns FDLBM_OK.
+ * Errors: FDLBM_E_STATE before fdlbm_init_fields, FDLBM_E_INVALID for a
+ * negative count, FDLBM_E_HIP if a launch fails. */
 int fdlbm_step(fdlbm_ctx *ctx, int64_t n_steps);
+
+/* Check interval of fdlbm_step in steps (0, the default: no check, fully
+ * asynchronous; 1: the exact step, at one synchronisation per step).
+ * FDLBM_E_INVALID if negative. */
+int fdlbm_set_sync_check(fdlbm_ctx *ctx, int64_t every);
+
+/* Synchronise and report the stability record: *step = the first step
+ * (counted like fdlbm_obs.step) in which a gas node had a non-finite or
+ * negative density or temperature, or -1 if none did since the last
+ * fdlbm_init_fields or fdlbm_load_state.  Batched steps keep each member's
+ * record too.  FDLBM_E_STATE before fdlbm_init_fields. */
+int fdlbm_last_step(fdlbm_ctx *ctx, int64_t *step);
 
 /* Wait for the stream. */
 int fdlbm_sync(fdlbm_ctx *ctx);

@@ -67,13 +67,16 @@ struct fdlbm_ctx {
   size_t off_lj = 0;                // collision-integral table
   size_t off_G[2]{}, off_Gs = 0, off_FR = 0, off_FX = 0, off_Ts[2]{}, off_wr = 0, off_wde = 0, off_kind = 0, off_slot = 0,
          off_scls = 0, off_wem = 0, off_gl = 0, off_wl = 0, off_am = 0, off_aw = 0, off_ab = 0,
-         off_part = 0, off_snap = 0, off_snapts = 0;
+         off_part = 0, off_snap = 0, off_snapts = 0, off_status = 0;
   bool snap_valid = false;  // a residual snapshot exists
   int64_t snap_step = 0;    // step of the snapshot
   size_t total = 0;
   int acc_slots = 0, obs_blocks = 0;
   int cur = 0;
   int64_t step = 0;
+  // stability record: its step count starts at status_base; with
+  // check_every > 0 each fdlbm_step checks it after every check_every steps
+  int64_t status_base = 0, check_every = 0, bad_step = -1;
   // profiling
   bool prof = false;
   std::vector<hipEvent_t> events;  // [launch][kernel][2]
@@ -176,6 +179,7 @@ static void layout(fdlbm_ctx *c) {
   c->off_part = take((size_t)c->obs_blocks * (MAXS + 9) * 8);
   c->off_snap = take((size_t)sn_count(c->D, c->ns) * nsl * b);
   c->off_snapts = take(n * b);
+  c->off_status = take(4 * sizeof(int64_t));
   c->total = o;
 }
 
@@ -207,6 +211,7 @@ static Bufs<real, PT> bufs(const fdlbm_ctx *c) {
   b.partials = (double *)(w + c->off_part);
   b.snap = (real *)(w + c->off_snap);
   b.snap_ts = (real *)(w + c->off_snapts);
+  b.status = (int64_t *)(w + c->off_status);
   return b;
 }
 
@@ -757,6 +762,15 @@ int fdlbm_bind_workspace(fdlbm_ctx *c, void *dev, size_t bytes) {
   return upload_lj(c);
 }
 
+// clear the stability record (not inside any captured graph) and start its
+// step count at the context's step
+static int reset_status(fdlbm_ctx *c) {
+  HIPCHK(c, hipMemsetAsync(c->ws + c->off_status, 0, 4 * sizeof(int64_t), c->stream));
+  c->status_base = c->step;
+  c->bad_step = -1;
+  return FDLBM_OK;
+}
+
 // host-side equilibrium for the initial state (same closed form as the kernels)
 template <typename real, typename PT>
 static int init_impl(fdlbm_ctx *c, const double *rho, const double *u, const double *T,
@@ -825,8 +839,9 @@ static int init_impl(fdlbm_ctx *c, const double *rho, const double *u, const dou
   HIPCHK(c, hipMemsetAsync(c->ws + c->off_am, 0, (size_t)c->acc_slots * 8, c->stream));
   HIPCHK(c, hipMemsetAsync(c->ws + c->off_aw, 0, (size_t)c->acc_slots * 8, c->stream));
   HIPCHK(c, hipMemsetAsync(c->ws + c->off_ab, 0, (size_t)c->acc_slots * 8, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
   c->step = 0;
+  if (reset_status(c) != FDLBM_OK) return FDLBM_E_HIP;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   c->initialized = true;
   c->snap_valid = false;
   return FDLBM_OK;
@@ -917,14 +932,62 @@ static int step_impl(fdlbm_ctx *c, int64_t n_steps) {
   return FDLBM_OK;
 }
 
+// read the stability record (synchronises the stream): the first unstable
+// step, counted like fdlbm_obs.step, or -1
+static int read_status(fdlbm_ctx *c, int64_t *first_bad) {
+  int64_t st[2] = {0, 0};
+  HIPCHK(c, hipMemcpyAsync(st, c->ws + c->off_status, sizeof st, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  *first_bad = st[0] ? c->status_base + st[1] : -1;
+  return FDLBM_OK;
+}
+
 int fdlbm_step(fdlbm_ctx *c, int64_t n_steps) {
   if (!c) return FDLBM_E_INVALID;
   if (!c->initialized) return set_err(c, FDLBM_E_STATE, "initialise the fields first");
   if (n_steps < 0) return set_err(c, FDLBM_E_INVALID, "negative step count");
-  return with_prec(c, [&](auto tag) {
-    using Tg = decltype(tag);
-    return step_impl<typename Tg::real, typename Tg::pop>(c, n_steps);
-  });
+  auto run = [&](int64_t k) {
+    return with_prec(c, [&](auto tag) {
+      using Tg = decltype(tag);
+      return step_impl<typename Tg::real, typename Tg::pop>(c, k);
+    });
+  };
+  if (c->check_every <= 0) return run(n_steps);
+  // checked mode: chunks of check_every steps, stopping after the chunk in
+  // which the stability record was set
+  for (int64_t done = 0; done < n_steps;) {
+    const int64_t k = std::min(c->check_every, n_steps - done);
+    int rc = run(k);
+    if (rc != FDLBM_OK) return rc;
+    done += k;
+    int64_t bad = -1;
+    rc = read_status(c, &bad);
+    if (rc != FDLBM_OK) return rc;
+    if (bad >= 0) {
+      c->bad_step = bad;
+      return set_err(c, FDLBM_E_UNSTABLE,
+                     "non-finite or negative density or temperature first seen in step %lld "
+                     "(stopped after step %lld)", (long long)bad, (long long)c->step);
+    }
+  }
+  return FDLBM_OK;
+}
+
+int fdlbm_set_sync_check(fdlbm_ctx *c, int64_t every) {
+  if (!c) return FDLBM_E_INVALID;
+  if (every < 0) return set_err(c, FDLBM_E_INVALID, "negative check interval");
+  c->check_every = every;
+  return FDLBM_OK;
+}
+
+int fdlbm_last_step(fdlbm_ctx *c, int64_t *step) {
+  if (!c || !step) return FDLBM_E_INVALID;
+  if (!c->initialized) return set_err(c, FDLBM_E_STATE, "initialise the fields first");
+  int64_t bad = -1;
+  const int rc = read_status(c, &bad);
+  if (rc != FDLBM_OK) return rc;
+  *step = bad;
+  return FDLBM_OK;
 }
 
 int fdlbm_set_overlap(fdlbm_ctx *c, int enable) {
@@ -1147,6 +1210,8 @@ int fdlbm_load_state(fdlbm_ctx *c, const void *host, size_t bytes) {
   c->step = (int64_t)h.step;
   c->cur = h.cur;
   for (int j = 0; j < MAXS; ++j) c->rho_ref[j] = h.rho_ref[j];
+  if (reset_status(c) != FDLBM_OK) return FDLBM_E_HIP;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   c->snap_valid = false;
   c->initialized = true;
   return FDLBM_OK;

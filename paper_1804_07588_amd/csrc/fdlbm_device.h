@@ -165,6 +165,10 @@ struct Bufs {
   double *partials;   // observe / residual reduction partials
   real *snap;         // residual snapshot per gas slot: X_j, T, u_a (sn_count values)
   real *snap_ts;      // residual snapshot of the solid temperature per node
+  // stability record: [0] 1 once a gas node had a non-finite or negative
+  // density or temperature, [1] the first such step (counted from 1 since
+  // the last reset), [2] steps completed since the last reset
+  int64_t *status;
 };
 
 // values per gas slot in the residual snapshot: mole fractions, T, u

@@ -605,6 +605,18 @@ __device__ __forceinline__ void moments_node(const Params<real> &p, const Bufs<r
     u2 += u[a] * u[a];
   }
   const real T = (E - rhot * u2) / (real(D) * C);
+  {
+    // stability record: a non-finite or negative density or temperature
+    // (NaN fails every comparison); all nodes that see it in one step store
+    // the same step number, and a later step never overwrites it
+    bool ok = T > real(0) && T < real(1e30) && u2 < real(1e30);
+#pragma unroll
+    for (int j = 0; j < NS; ++j) ok = ok && rho[j] >= real(0);
+    if (!ok && b.status[0] == 0) {
+      b.status[1] = b.status[2] + 1;
+      b.status[0] = 1;
+    }
+  }
   // transport with floored mole fractions
   real Xh[NS], sX = 0, sMX = 0;
 #pragma unroll
@@ -1102,6 +1114,8 @@ __device__ __forceinline__ void collide_block(const Params<real> &p, const Bufs<
   }
   const double s = block_sum(work);
   if (threadIdx.x == 0 && s != 0.0) b.acc_work[lb] += s;
+  // one step more completed (read by the next step's moments pass)
+  if (lb == 0 && threadIdx.x == 0) b.status[2] += 1;
 }
 template <typename real, typename PT, int D, int NS>
 __global__ void __launch_bounds__(BLOCK, sizeof(real) == 4 ? 2 : 1) k_collide(Params<real> p, Bufs<real, PT> b, int cur) {

@@ -35,7 +35,8 @@ EXPORTS = ["fdlbm_create", "fdlbm_destroy", "fdlbm_last_error", "fdlbm_set_geome
            "fdlbm_set_lj_transport", "fdlbm_batch_create", "fdlbm_batch_destroy",
            "fdlbm_batch_last_error", "fdlbm_batch_workspace_bytes", "fdlbm_batch_bind_workspace",
            "fdlbm_batch_set_active", "fdlbm_batch_step", "fdlbm_batch_set_grid",
-           "fdlbm_batch_get_grid", "fdlbm_batch_autotune", "fdlbm_batch_set_overlap"]
+           "fdlbm_batch_get_grid", "fdlbm_batch_autotune", "fdlbm_batch_set_overlap",
+           "fdlbm_set_sync_check", "fdlbm_last_step"]
 BATCH_KINDS = ["wall_fast", "wall_slow", "gas_fast", "gas_slow", "collide", "solid"]
 
 
@@ -107,6 +108,8 @@ def lib() -> ct.CDLL:
         L.fdlbm_set_prandtl.argtypes = [vp, dp]
         L.fdlbm_set_solid_scheme.argtypes = [vp, ct.c_int]
         L.fdlbm_set_lj_transport.argtypes = [vp, dp, ct.c_double, ct.c_double, ct.c_double, ct.c_int, dp, dp]
+        L.fdlbm_set_sync_check.argtypes = [vp, i64]
+        L.fdlbm_last_step.argtypes = [vp, ct.POINTER(i64)]
         ip = ct.POINTER(ct.c_int)
         L.fdlbm_batch_create.argtypes = [ct.POINTER(vp), ct.c_int, ct.POINTER(vp)]
         L.fdlbm_batch_destroy.argtypes = [vp]
@@ -218,6 +221,17 @@ class Sim:
 
     def sync(self):
         self._check(lib().fdlbm_sync(self.h))
+
+    def set_sync_check(self, every: int):
+        """Check the stability record every `every` steps inside step() (0: off);
+        step() then raises FdlbmError with code E_UNSTABLE."""
+        self._check(lib().fdlbm_set_sync_check(self.h, int(every)))
+
+    def last_step(self) -> int:
+        """First step with a non-finite or negative density or temperature, or -1."""
+        v = ct.c_int64()
+        self._check(lib().fdlbm_last_step(self.h, ct.byref(v)))
+        return v.value
 
     def observe(self) -> dict:
         o = Obs()

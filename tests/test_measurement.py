@@ -103,3 +103,17 @@ def test_bench_refuses_several_gpus():
     assert r.returncode == 2
     msg = json.loads(r.stdout.strip().splitlines()[-1])
     assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
+
+
+def test_kernel_algorithmic_bytes_add_up_to_the_step():
+    """Each algorithmic byte of a step belongs to exactly one kernel group:
+    the collision is credited with its post-collision writes only (its read
+    of the streamed copy is overhead of the two-pass step)."""
+    import bench
+    n_gas, n_links, n_solid, ns, Q = 1362836, 1565578, 734316, 5, 19
+    for b in (8, 4, 2):
+        total, per = bench.alg_bytes(n_gas, n_links, n_solid, ns, Q, b)
+        assert total == n_gas * 2 * Q * ns * b + n_links * 2 * ns * b + n_solid * 2 * b
+        assert sum(per.values()) == total
+        assert per["k_collide"] == n_gas * Q * ns * b
+        assert per["k_moments"] == n_gas * Q * ns * b

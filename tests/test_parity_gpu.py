@@ -1,15 +1,16 @@
 """GPU (HIP library, through the C ABI) versus the FP64 CPU oracle on the same
 seeded inputs.  Parity metric per field q: max|q_gpu - q_oracle| / scale_q,
-with scale_q = max|q_oracle| for densities, populations, temperatures and
-the reaction rate, and the lattice sound speed sqrt(T0) = 0.577 for the
-velocity components (the natural velocity scale of the scheme: max|u| is
-~1e-4..1e-2 in these runs, far below the population scale the FP32 storage
-rounds at).
+with scale_q = max|q_oracle| (velocity: the largest |u_a| of the oracle over
+all components, so every component is measured against the flow's speed;
+the same error per lattice sound speed sqrt(T0) is recorded beside it as
+`u*_cs`).
 
-Tolerances: FP64 runs agree to rounding (1e-10 after hundreds of steps: the
-two sides sum in different orders and the GPU uses closed forms where the
-oracle inverts matrices).  FP32 runs: 1e-5 relative on every field except
-the wall reaction rate, a product of two FP32 wall densities (2e-5).
+Tolerances: FP64 runs agree to rounding, 1e-12 (the two sides sum in
+different orders and the GPU uses closed forms where the oracle inverts
+matrices).  FP32 runs: 1e-5 relative on every field, the wall reaction rate
+included.  Where a case cannot meet these, its own bound is stated at the
+test with the reason.  Every measured maximum is written to the record
+named by FDLBM_PARITY_RECORD (see conftest.py).
 """
 import numpy as np
 import pytest
@@ -20,6 +21,17 @@ from paper_1804_07588_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 T0 = 1.0 / 3.0
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+_REC = [None]
+
+
+@pytest.fixture(autouse=True)
+def _record(parity_record):
+    _REC[0] = parity_record
+    yield
+    _REC[0] = None
 
 
 @pytest.fixture(scope="module")
@@ -54,20 +66,36 @@ def field_errors(o, g, fd, ns, D):
     for j in range(ns):
         errs[f"rho{j}"] = rel_err(g.field(fd.FIELD_RHO, j), o.field(of.OF_RHO, j))
         errs[f"pop{j}"] = rel_err(g.field(fd.FIELD_POP, j), o.field(of.OF_POP, j))
-    # velocity components relative to the lattice sound speed sqrt(T0)
+    uo = [o.field(of.OF_U, a) for a in range(D)]
+    ug = [g.field(fd.FIELD_U, a) for a in range(D)]
+    umax = max(np.abs(x).max() for x in uo)
     cs = np.sqrt(T0)
     for a in range(D):
-        errs[f"u{a}"] = np.abs(g.field(fd.FIELD_U, a) - o.field(of.OF_U, a)).max() / cs
+        d = np.abs(ug[a] - uo[a]).max()
+        # a run at rest has no speed scale: then the sound speed is the scale
+        errs[f"u{a}"] = d / (umax if umax > 1e-12 else cs)
+        errs[f"u{a}_cs"] = d / cs
     errs["T"] = rel_err(g.field(fd.FIELD_T), o.field(of.OF_T))
     errs["Ts"] = rel_err(g.field(fd.FIELD_TS), o.field(of.OF_TS))
     errs["wall_r"] = rel_err(g.field(fd.FIELD_WALL_R), o.field(of.OF_WALL_R))
     return errs
 
 
-def assert_errs(errs, tol, tol_rate=None):
+def assert_errs(errs, tol, tol_rate=None, tol_u=None):
+    """Every field within tol; the wall rate within tol_rate and the
+    velocity (relative to max|u|) within tol_u where a case states its own
+    bound for them.  The `*_cs` figures are recorded, not asserted."""
     print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    if _REC[0] is not None:
+        _REC[0](errs, tol)
     for k, v in errs.items():
-        t = tol_rate if (tol_rate is not None and k == "wall_r") else tol
+        if k.endswith("_cs"):
+            continue
+        t = tol
+        if tol_rate is not None and k == "wall_r":
+            t = tol_rate
+        if tol_u is not None and k[0] == "u" and k[1:].isdigit():
+            t = tol_u
         assert v <= t, (k, v)
 
 
@@ -102,14 +130,14 @@ def small_bed(n=20, inout=1, seed=3):
 def test_c1_fp64_parity(oracle_lib, fd):
     cfg = W.channel_c1()
     o, g = run_both(oracle_lib, fd, cfg, W.uniform_init(cfg), 1000, fd.F64)
-    assert_errs(field_errors(o, g, fd, 2, 2), 1e-10)
+    assert_errs(field_errors(o, g, fd, 2, 2), TOL64)
 
 
 def test_c1_interpolated_species_fp64(oracle_lib, fd):
     cfg = W.with_changes(W.channel_c1(), init=dict(X=[0.7, 0.3]))
     cfg["species"].update(M=[1.0, 4.0], mu0=[0.1, 0.2])
     o, g = run_both(oracle_lib, fd, cfg, W.perturbed_init(cfg, 5), 300, fd.F64)
-    assert_errs(field_errors(o, g, fd, 2, 2), 1e-10)
+    assert_errs(field_errors(o, g, fd, 2, 2), TOL64)
 
 
 def test_porous_2d_three_species_fp64(oracle_lib, fd):
@@ -117,7 +145,7 @@ def test_porous_2d_three_species_fp64(oracle_lib, fd):
     degraded stencil classes; three species of masses 1, 4, 9; Pr = 0.71."""
     cfg = noisy_2d()
     o, g = run_both(oracle_lib, fd, cfg, W.perturbed_init(cfg, 9), 200, fd.F64)
-    assert_errs(field_errors(o, g, fd, 3, 2), 1e-10)
+    assert_errs(field_errors(o, g, fd, 3, 2), TOL64)
 
 
 def test_bed_3d_fp64(oracle_lib, fd):
@@ -125,13 +153,13 @@ def test_bed_3d_fp64(oracle_lib, fd):
     inlet/outlet planes, body force."""
     cfg = small_bed()
     o, g = run_both(oracle_lib, fd, cfg, W.perturbed_init(cfg, 4, amp_u=0.005), 40, fd.F64)
-    assert_errs(field_errors(o, g, fd, 5, 3), 1e-10)
+    assert_errs(field_errors(o, g, fd, 5, 3), TOL64)
 
 
 def test_bed_3d_fp32(oracle_lib, fd):
     cfg = small_bed(n=20)
     o, g = run_both(oracle_lib, fd, cfg, W.perturbed_init(cfg, 4, amp_u=0.005), 100, fd.F32)
-    assert_errs(field_errors(o, g, fd, 5, 3), 1e-5, tol_rate=2e-5)
+    assert_errs(field_errors(o, g, fd, 5, 3), TOL32)
 
 
 @pytest.mark.parametrize("prec", ["F64", "F32"])
@@ -142,9 +170,9 @@ def test_bed_3d_species_prandtl(oracle_lib, fd, prec):
     precision = getattr(fd, prec)
     o, g = run_both(oracle_lib, fd, cfg, W.perturbed_init(cfg, 6, amp_u=0.005), 60, precision)
     if prec == "F64":
-        assert_errs(field_errors(o, g, fd, 5, 3), 1e-10)
+        assert_errs(field_errors(o, g, fd, 5, 3), TOL64)
     else:
-        assert_errs(field_errors(o, g, fd, 5, 3), 1e-5, tol_rate=2e-5)
+        assert_errs(field_errors(o, g, fd, 5, 3), TOL32)
 
 
 def test_crank_nicolson_solid_fp64(oracle_lib, fd):
@@ -158,7 +186,7 @@ def test_crank_nicolson_solid_fp64(oracle_lib, fd):
     cfg["solid"].update(scheme=1, alpha_s=1.5)
     init = W.perturbed_init(cfg, 8)
     o, g = run_both(oracle_lib, fd, cfg, init, 200, fd.F64)
-    assert_errs(field_errors(o, g, fd, 2, 2), 1e-10)
+    assert_errs(field_errors(o, g, fd, 2, 2), TOL64)
     oo, og = o.observe(), g.observe()
     assert abs(og["heat_boundary"] - oo["heat_boundary"]) <= 1e-10 * abs(oo["heat_boundary"])
 
@@ -168,7 +196,7 @@ def test_crank_nicolson_solid_bed_fp32(oracle_lib, fd):
     cfg = small_bed()
     cfg["solid"].update(scheme=1, alpha_s=0.5)
     o, g = run_both(oracle_lib, fd, cfg, W.perturbed_init(cfg, 12, amp_u=0.005), 60, fd.F32)
-    assert_errs(field_errors(o, g, fd, 5, 3), 1e-5, tol_rate=2e-5)
+    assert_errs(field_errors(o, g, fd, 5, 3), TOL32)
 
 
 def lj_table(n=40, tmin=0.5, tmax=10.0):
@@ -190,16 +218,16 @@ def test_bed_3d_lj_transport(oracle_lib, fd, prec):
     o, g = run_both(oracle_lib, fd, cfg, W.perturbed_init(cfg, 14, amp_u=0.005, amp_T=0.03), 60,
                     precision)
     if prec == "F64":
-        assert_errs(field_errors(o, g, fd, 5, 3), 1e-10)
+        assert_errs(field_errors(o, g, fd, 5, 3), TOL64)
     else:
-        assert_errs(field_errors(o, g, fd, 5, 3), 1e-5, tol_rate=2e-5)
+        assert_errs(field_errors(o, g, fd, 5, 3), TOL32)
 
 
 def test_c1_fp32(oracle_lib, fd):
     cfg = W.channel_c1()
     o, g = run_both(oracle_lib, fd, cfg, W.uniform_init(cfg), 1000, fd.F32)
     errs = field_errors(o, g, fd, 2, 2)
-    assert_errs(errs, 1e-5, tol_rate=2e-5)
+    assert_errs(errs, TOL32)
 
 
 def test_observables_fp64(oracle_lib, fd):
@@ -295,7 +323,7 @@ def test_full_bed_two_steps_all_precisions(oracle_lib, fd):
     o.step(2)
     # 16-bit storage: one rounding of a few-percent deviation already costs
     # ~1e-4 (FP16, 11-bit significand) or ~1e-3 (BF16, 8-bit) of a density
-    for prec, tol, tol_rate in ((fd.F32, 1e-5, 2e-5), (fd.F64, 1e-10, 1e-10), (fd.F16, 5e-4, 5e-4),
+    for prec, tol, tol_rate in ((fd.F32, TOL32, TOL32), (fd.F64, TOL64, TOL64), (fd.F16, 5e-4, 5e-4),
                                 (fd.BF16, 5e-3, 5e-3)):
         g = fd.Sim(cfg, precision=prec, init=init)
         g.step(2)
@@ -432,3 +460,59 @@ def test_overlapped_step_is_bitwise_the_serial_step(fd):
     oa, ob = a.observe(), b.observe()
     for k in ("e_gas", "e_solid", "moles_reacted", "heat_released", "work_body"):
         assert oa[k] == ob[k], k
+
+
+def _first_unstable_step(oracle_lib, cfg, init, max_steps):
+    """The oracle stepped one step at a time: the first step whose moments
+    (densities, temperature at the gas nodes) are non-finite or negative."""
+    o = oracle_lib.OracleSim(cfg, init)
+    kind = o.field(of.OF_KIND)
+    gas = (kind == 0) | (kind >= 3)
+    ns = len(cfg["species"]["M"])
+    for s in range(1, max_steps + 1):
+        o.step(1)
+        T = o.field(of.OF_T)[gas]
+        rho = np.stack([o.field(of.OF_RHO, j)[gas] for j in range(ns)])
+        if not (np.all(T > 0) and np.all(np.isfinite(T)) and np.all(rho >= 0)):
+            o.close()
+            return s
+    o.close()
+    return -1
+
+
+@pytest.mark.parametrize("prec", ["F64", "F32"])
+def test_unstable_step_is_reported(oracle_lib, fd, prec):
+    """A numerical blow-up forced through the parameters (a body force of
+    0.02 per step drives the binary channel past the lattice sound speed):
+    fdlbm_step with a check interval returns FDLBM_E_UNSTABLE and
+    fdlbm_last_step names the step at which the oracle's moments first turn
+    non-physical (in FP64 exactly; FP32 within two steps).  Unchecked steps
+    only enqueue, and the record is read afterwards; a re-initialised
+    context reports no unstable step."""
+    cfg = W.with_changes(W.channel_c1(nx=16, ny=16, wall=2), flow=dict(F=[0.02, 0, 0]),
+                         init=dict(X=[0.7, 0.3]))
+    init = W.uniform_init(cfg)
+    s_ref = _first_unstable_step(oracle_lib, cfg, init, 300)
+    assert s_ref > 10, s_ref
+    precision = getattr(fd, prec)
+    slack = 0 if prec == "F64" else 2
+    print(f"[unstable] {prec}: oracle first bad step {s_ref}", flush=True)
+    for every in (1, 10):
+        g = fd.Sim(cfg, precision=precision, init=init)
+        g.set_sync_check(every)
+        with pytest.raises(fd.FdlbmError) as ei:
+            g.step(s_ref + 50)
+        assert ei.value.code == fd.E_UNSTABLE
+        bad = g.last_step()
+        assert abs(bad - s_ref) <= slack, (bad, s_ref)
+        # the call stops after the chunk in which the record was set
+        assert g.observe()["step"] == (bad + every - 1) // every * every
+        g.close()
+    g = fd.Sim(cfg, precision=precision, init=init)
+    g.step(s_ref - 5)
+    assert g.last_step() == -1
+    g.step(20)
+    assert abs(g.last_step() - s_ref) <= slack
+    g.init_fields(init)
+    assert g.last_step() == -1
+    g.close()
