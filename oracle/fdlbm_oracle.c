@@ -63,6 +63,7 @@ struct oracle_sim {
   /* per-node fields of the current step */
   double *rho, *u, *T, *tau1, *tau2, *Jf, *Uc;
   double *wall_r, *wall_dE;
+  double *wall_u;   /* wall velocity U_w per node, 3 rows (NULL: walls at rest) */
   /* cumulative counters */
   double moles, heat, bheat, work;
   int64_t step;
@@ -492,6 +493,7 @@ void oracle_destroy(oracle_sim *s) {
   free(s->Jf);
   free(s->Uc);
   free(s->wall_r);
+  free(s->wall_u);
   free(s->wall_dE);
   free(s->kind);
   free(s);
@@ -755,10 +757,25 @@ int oracle_transport(oracle_sim *s, const double *rho, double T, double *tau1, d
 /* ------------------------------------------------------------------------ */
 /* initial state                                                             */
 /* ------------------------------------------------------------------------ */
-static double wall_weight(const oracle_sim *s, int i, double Tw) {
-  double f[MAXQ], u0[3] = {0, 0, 0};
-  equilibrium(s->D, s->Q, s->c, 1.0, 1.0, u0, Tw, f);
+/* Eq.(39): the wall's thermalised populations per unit density,
+ * f^eq_ji(1, U_w, T_w) of species j (species independent at U_w = 0) */
+static double wall_weight(const oracle_sim *s, int w, int j, int i, double Tw) {
+  double f[MAXQ], uw[3] = {0, 0, 0};
+  if (s->wall_u)
+    for (int a = 0; a < 3; ++a) uw[a] = s->wall_u[(size_t)a * s->n + w];
+  equilibrium(s->D, s->Q, s->c, 1.0, s->M[j], uw, Tw, f);
   return f[i];
+}
+
+/* velocity of the wall at node w (Eq.(39)'s U_w; zero unless set) */
+int oracle_set_wall_velocity(oracle_sim *s, const double *u3) {
+  if (!s) return fail(s, "null simulation");
+  free(s->wall_u);
+  s->wall_u = NULL;
+  if (!u3) return 0;
+  s->wall_u = (double *)malloc(sizeof(double) * 3 * (size_t)s->n);
+  memcpy(s->wall_u, u3, sizeof(double) * 3 * (size_t)s->n);
+  return 0;
 }
 
 static double wall_temperature(const oracle_sim *s, int w) {
@@ -799,7 +816,7 @@ int oracle_init_fields(oracle_sim *s, const double *rho, const double *u, const 
       }
       double rw = sum / cnt;
       for (int i = 1; i < Q; ++i)
-        if (gaslike(s, shift(s, node, i, 1))) *pop(s, s->G, j, i, node) = rw * wall_weight(s, i, Tw);
+        if (gaslike(s, shift(s, node, i, 1))) *pop(s, s->G, j, i, node) = rw * wall_weight(s, node, j, i, Tw);
     }
   }
   s->moles = s->heat = s->bheat = s->work = 0.0;
@@ -845,7 +862,7 @@ static void wall_bc(oracle_sim *s) {
      * For a flat wall the |c.n| weights of Eq.(38)-(39) are all equal to
      * c_j and cancel against the c_j of S_j (Eq.(50)), leaving the per-link
      * lattice mass balance below. */
-    double A[MAXS] = {0}, Ein = 0.0, Z = 0.0;
+    double A[MAXS] = {0}, Ein = 0.0, Z[MAXS] = {0};
     for (int i = 1; i < Q; ++i) {
       if (is_destination(s, w, i)) {
         double c2 = (double)(s->c[i][0] * s->c[i][0] + s->c[i][1] * s->c[i][1] +
@@ -856,34 +873,33 @@ static void wall_bc(oracle_sim *s) {
           Ein += s->cj[j] * s->cj[j] * c2 * g;
         }
       }
-      if (emits(s, w, i)) Z += wall_weight(s, i, Tw);
+      if (emits(s, w, i))
+        for (int j = 0; j < ns; ++j) Z[j] += wall_weight(s, w, j, i, Tw);
     }
-    /* Eq.(40)-(41): emitted populations rho_w f^eq(1, 0, T_w); the wall
-     * density of species j satisfies rho_w Z = A_j + nu_j M_j r, i.e. the
+    /* Eq.(40)-(41): emitted populations rho_w f^eq(1, U_w, T_w); the wall
+     * density of species j satisfies rho_w Z_j = A_j + nu_j M_j r, i.e. the
      * lattice mass of species j grows by nu_j M_j r per wall node and step
      * (the sign reading of S_j: net production into the gas).
      * The paper's fixed-point iteration for rho_w, started here from the
      * non-reactive wall density A_j / Z; each pass treats a reactant's own
      * concentration implicitly (rho_j = A_j / (Z + |nu_j| r / C_j)). */
-    /* reading: S_j of Eq.(50) is a flux per unit wall area, so a wall node
-     * reacts in proportion to its wetted area, measured by its equilibrium
-     * emission Z relative to that of a flat lattice wall, which is T_w / 2
-     * on both lattices (area factor exactly 1 on the paper's planar walls) */
-    double area = Z / (0.5 * Tw);
+    /* one reaction term S_j per wall node, also at corners: corner nodes
+     * differ from plane ones only in which populations enter Eq.(41)
+     * (Sec. 4.3, after the wall-density iteration) */
     double rw[MAXS];
-    for (int j = 0; j < ns; ++j) rw[j] = A[j] / Z;
+    for (int j = 0; j < ns; ++j) rw[j] = A[j] / Z[j];
     for (int it = 0; it < s->max_iter; ++it) {
       double nw[MAXS], dmax = 0.0;
       for (int j = 0; j < ns; ++j) {
         nw[j] = rw[j];
         if (s->nu[j] < 0.0 && s->order[j] > 0.0) {
           /* r / C_j with C_j's own power lowered by one */
-          double R = area * s->k0 * exp(s->ea * (1.0 - s->T_ref_rxn / Tw));
+          double R = s->k0 * exp(s->ea * (1.0 - s->T_ref_rxn / Tw));
           for (int m = 0; m < ns; ++m) {
             double o = s->order[m] - (m == j ? 1.0 : 0.0);
             if (o != 0.0) R *= pow(rw[m] / s->M[m], o);
           }
-          nw[j] = A[j] / (Z - s->nu[j] * R);
+          nw[j] = A[j] / (Z[j] - s->nu[j] * R);
         }
         double d = fabs(nw[j] - rw[j]) / fmax(fabs(nw[j]), 1e-300);
         if (d > dmax) dmax = d;
@@ -891,17 +907,16 @@ static void wall_bc(oracle_sim *s) {
       for (int j = 0; j < ns; ++j) rw[j] = nw[j];
       if (dmax <= s->tol) break;
     }
-    double r = area * rate(s, rw, Tw);
+    double r = rate(s, rw, Tw);
     /* final wall densities from the exact mass balance at the final rate */
-    for (int j = 0; j < ns; ++j) rw[j] = (A[j] + s->nu[j] * s->M[j] * r) / Z;
+    for (int j = 0; j < ns; ++j) rw[j] = (A[j] + s->nu[j] * s->M[j] * r) / Z[j];
     double Eout = 0.0;
     for (int i = 1; i < Q; ++i) {
       if (!emits(s, w, i)) continue;
       double c2 = (double)(s->c[i][0] * s->c[i][0] + s->c[i][1] * s->c[i][1] +
                            s->c[i][2] * s->c[i][2]);
-      double wi = wall_weight(s, i, Tw);
       for (int j = 0; j < ns; ++j) {
-        double W = rw[j] * wi;
+        double W = rw[j] * wall_weight(s, w, j, i, Tw);
         *pop(s, s->Gn, j, i, w) = W;
         Eout += s->cj[j] * s->cj[j] * c2 * W;
       }
@@ -910,7 +925,7 @@ static void wall_bc(oracle_sim *s) {
     s->wall_dE[w] = 0.5 * (Eout - Ein); /* kinetic energy handed to the gas */
     /* wall state seen by the gradient stencils of neighbouring gas nodes */
     for (int j = 0; j < ns; ++j) s->rho[(size_t)j * s->n + w] = rw[j];
-    for (int a = 0; a < 3; ++a) s->u[(size_t)a * s->n + w] = 0.0;
+    for (int a = 0; a < 3; ++a) s->u[(size_t)a * s->n + w] = s->wall_u ? s->wall_u[(size_t)a * s->n + w] : 0.0;
     s->T[w] = Tw;
   }
 }

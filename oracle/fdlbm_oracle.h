@@ -69,6 +69,10 @@ int oracle_set_solid_scheme(oracle_sim *s, int scheme);
 int oracle_set_reaction(oracle_sim *s, const double *nu, const double *order, double k0,
                         double ea, double T_ref, double dH, int wall_mode, double T_iso,
                         double tol, int max_iter);
+/* wall velocity U_w of Eq.(39) per node (u3[a*n + node], read at wall
+ * nodes; NULL: walls at rest, the default): the diffusive wall then emits
+ * rho_w f^eq(1, U_w, T_w) and its state seen by the gradients moves */
+int oracle_set_wall_velocity(oracle_sim *s, const double *u3);
 int oracle_set_flow(oracle_sim *s, const double *F3, const double *X_in, double p_in,
                     double T_in);
 /* rho[j*n + node], u[a*n + node] (3 rows), T[n], Ts[n]; populations set to f^eq. */

@@ -73,6 +73,7 @@ def lib():
                                           ct.c_double, ct.c_double, ct.c_int, ct.c_double,
                                           ct.c_double, ct.c_int]
         L.oracle_set_flow.argtypes = [ct.c_void_p, dp, dp, ct.c_double, ct.c_double]
+        L.oracle_set_wall_velocity.argtypes = [ct.c_void_p, dp]
         L.oracle_init_fields.argtypes = [ct.c_void_p, dp, dp, dp, dp]
         L.oracle_step.argtypes = [ct.c_void_p, ct.c_int64]
         L.oracle_observe.argtypes = [ct.c_void_p, ct.POINTER(Obs)]
@@ -182,6 +183,12 @@ class OracleSim:
         fl = cfg["flow"]
         F, Xin = _arr(fl["F"]), _arr(fl["X_in"])
         self._check(L.oracle_set_flow(h, _d(F), _d(Xin), fl["p_in"], fl["T_in"]))
+        if cfg.get("wall_u") is not None:
+            # per-node wall velocity [3][n] (Eq.(39)'s U_w), read at wall nodes
+            wu = _arr(cfg["wall_u"]).reshape(-1)
+            assert wu.size == 3 * self.n
+            self._wall_u = wu
+            self._check(L.oracle_set_wall_velocity(h, _d(wu)))
         if init is not None:
             self.init_fields(init)
 

@@ -11,11 +11,39 @@ against brute-force loops and finite differences.
 """
 from __future__ import annotations
 
+import os
+import re
+
 import numpy as np
 import torch
 import torch.nn.functional as F
 
 torch.set_num_threads(max(1, min(8, torch.get_num_threads())))
+
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
+                      "fdlbm_unet.h")
+
+
+def header_convs(path: str = HEADER) -> list:
+    """(c_in, c_out) of every convolution, in the order the header's network
+    description lists them ("conv a->b")."""
+    with open(path) as fh:
+        text = fh.read()
+    desc = text[text.index("Network"):text.index("Parameters:")]
+    return [(int(a), int(b)) for a, b in re.findall(r"conv (\d+)->(\d+)", desc)]
+
+
+def param_offsets(layers) -> tuple[list, int]:
+    """[(weight offset, bias offset)] per convolution and the parameter count,
+    from the header's statement of the layout: for each convolution in order,
+    its weights W[c_out][tap][c_in], then its biases [c_out]."""
+    offs, p = [], 0
+    for layer in layers:
+        ci, co = layer[0], layer[1]
+        offs.append((p, p + co * 27 * ci))
+        p += co * 27 * ci + co
+    return offs, p
 
 
 def _w(params: torch.Tensor, off: int, ci: int, co: int) -> torch.Tensor:
@@ -31,13 +59,12 @@ def conv(x: torch.Tensor, params: torch.Tensor, w_off: int, b_off: int, ci: int,
 def forward(params, x, layers, cpad: int = 32) -> torch.Tensor:
     """x: [n][R][R][R][c_in] (channels last, c_in <= cpad), float64 tensor or
     array; returns the head output [n][R][R][R][c_out of the head]."""
-    from paper_1804_07588_amd.workloads import unet_layout
     p = params if isinstance(params, torch.Tensor) else torch.as_tensor(np.asarray(params, np.float64))
     xt = x if isinstance(x, torch.Tensor) else torch.as_tensor(np.asarray(x, np.float64))
     xt = xt.permute(0, 4, 1, 2, 3)
     if xt.shape[1] < cpad:
         xt = F.pad(xt, (0, 0, 0, 0, 0, 0, 0, cpad - xt.shape[1]))
-    offs, _ = unet_layout(layers)
+    offs, _ = param_offsets(layers)
 
     def L(i, h):
         ci, co, _, relu = layers[i]

@@ -444,9 +444,9 @@ __device__ inline double wall_node(const Params<real> &p, const Bufs<real, PT> &
   real rw[NS];
 #pragma unroll
   for (int j = 0; j < NS; ++j) rw[j] = A[j] / Z;
-  // the rate law is a flux per unit wall area: scale by the node's wetted
-  // area, its emission Z relative to a flat wall's T_w / 2
-  const real keff = (Z / (real(0.5) * Tw)) * p.k0 * exp(p.ea * (real(1) - p.T_ref_rxn / Tw));
+  // rate constant at T_w (Eq.(50) with the Arrhenius factor); one reaction
+  // term per wall node, corners included (Sec. 4.3)
+  const real keff = p.k0 * exp(p.ea * (real(1) - p.T_ref_rxn / Tw));
   for (int it = 0; it < p.max_iter; ++it) {
     real nw[NS], dmax = 0;
 #pragma unroll

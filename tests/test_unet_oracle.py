@@ -85,3 +85,15 @@ def test_gradient_matches_finite_differences():
         lm, _ = U.loss_and_grad(p - e, x, t, w, w.sum(), NARROW, cpad=4)
         fd = (lp - lm) / (2 * h)
         assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(g[k])), (k, fd, g[k])
+
+
+def test_oracle_layout_is_the_headers():
+    """The oracle reads the network's channel counts from the header and
+    lays the parameters out by the header's statement; the product's table
+    must agree with both."""
+    convs = U.header_convs()
+    assert len(convs) == 11
+    assert [(ci, co) for ci, co, _, _ in W.UNET_LAYERS] == convs
+    offs, n = U.param_offsets(convs)
+    p_offs, p_n = W.unet_layout()
+    assert offs == [tuple(o) for o in p_offs] and n == p_n == 1825504
