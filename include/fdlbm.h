@@ -267,8 +267,27 @@ int fdlbm_last_step(fdlbm_ctx *ctx, int64_t *step);
 /* Wait for the stream. */
 int fdlbm_sync(fdlbm_ctx *ctx);
 
-/* Synchronise and reduce the observables (FP64, deterministic order). */
+/* Synchronise and reduce the observables (FP64, deterministic order): the
+ * per-species mass conserved up to the reacted mass (Eq.(37), summed over
+ * gas and wall-emitted populations), the gas and solid energies and the
+ * cumulative reaction heat (Eq.(42)) whose balance is Eq.(49)'s enthalpy
+ * error, the Dirichlet-face heat, the body-force work, extrema and the
+ * `bad` flag.  FDLBM_E_STATE before fdlbm_init_fields. */
 int fdlbm_observe(fdlbm_ctx *ctx, fdlbm_obs *out);
+
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid allocation): fdlbm_observe with the
+ * same result, bitwise, that allocates nothing.  Its scratch -- the observe
+ * kernel's per-block partial sums and their folded totals, at most
+ * 1024 x (FDLBM_MAX_SPECIES + 9) + 64 doubles (139,776 bytes) -- lives in a
+ * static device array of the library that each GPU holds until the process
+ * ends; a context whose observables would not fit is rejected with
+ * FDLBM_E_INVALID (none can with the library's fixed grid).  It calls no
+ * allocating routine, host or device; the host side uses stack memory only.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU
+ * (several host threads, or streams not ordered against each other) race.
+ * Synchronises the context's stream. */
+int fdlbm_observe_noalloc(fdlbm_ctx *ctx, fdlbm_obs *out);
 
 /* Steady-state residual (the convergence test of the time-to-steady-state
  * measurement): for each field group q -- mole fractions X_j and temperature

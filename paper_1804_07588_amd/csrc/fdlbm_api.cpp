@@ -1054,6 +1054,116 @@ int fdlbm_observe(fdlbm_ctx *c, fdlbm_obs *o) {
   return FDLBM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// fdlbm_observe_noalloc: the observables with every scratch value in a
+// file-scope device array instead of the workspace and host vectors.  The
+// observe kernel writes its per-block partial sums there (every block
+// overwrites its row, so nothing needs clearing), k_obs_fold folds them in
+// the host's order, and the host copies the folded values into a stack
+// array.  Each GPU holds its own copy of the array until the process ends;
+// its device address is looked up once per device.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int OBS_BLOCKS = 1024;                       // grid of the observe kernel
+constexpr int OBS_FOLD = MAXS + 9 + 3;                 // folded values: partial slots + 3 sums
+constexpr size_t SCRATCH_DOUBLES = (size_t)OBS_BLOCKS * (MAXS + 9) + 64;  // 139,776 bytes
+constexpr int MAX_DEVICES = 64;
+}  // namespace
+
+static __device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+
+// Fold the per-block partials (blocks rows of np values at part) and the
+// three accumulator arrays (acc_slots each) exactly as fdlbm_observe does on
+// the host: sums in block order, minima and maxima by the same comparisons,
+// so the results are bitwise those of fdlbm_observe.  One thread per value.
+__global__ void k_obs_fold(const double *part, int blocks, int ns, const double *am, const double *aw,
+                           const double *ab, int acc_slots, double *out) {
+  const int k = threadIdx.x, np = ns + 9;
+  if (k < np) {
+    const bool is_min = k == ns + 2 || k == ns + 5 || k == ns + 6;
+    const bool is_max = k == ns + 3 || k == ns + 4 || k == ns + 7;
+    double v = is_min ? 1e300 : (k == ns + 3 || k == ns + 7 ? -1e300 : 0.0);
+    for (int bk = 0; bk < blocks; ++bk) {
+      const double q = part[(size_t)bk * np + k];
+      if (is_min) v = q < v ? q : v;
+      else if (is_max) v = v < q ? q : v;
+      else if (k == ns + 8) v = (q != 0.0) ? 1.0 : v;
+      else v += q;
+    }
+    out[k] = v;
+  } else if (k < np + 3) {
+    const double *a = k == np ? am : (k == np + 1 ? aw : ab);
+    double v = 0.0;
+    for (int s = 0; s < acc_slots; ++s) v += a[s];
+    out[k] = v;
+  }
+}
+
+// device address of this GPU's scratch array (looked up on the first call)
+static int scratch_ptr(fdlbm_ctx *c, double **ptr) {
+  static void *addr[MAX_DEVICES] = {};
+  int dev = 0;
+  HIPCHK(c, hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return set_err(c, FDLBM_E_INVALID, "device %d out of range", dev);
+  if (!addr[dev]) {
+    void *a = nullptr;
+    HIPCHK(c, hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)));
+    addr[dev] = a;
+  }
+  *ptr = (double *)addr[dev];
+  return FDLBM_OK;
+}
+
+int fdlbm_observe_noalloc(fdlbm_ctx *c, fdlbm_obs *o) {
+  if (!c || !o) return FDLBM_E_INVALID;
+  if (!c->initialized) return set_err(c, FDLBM_E_STATE, "initialise the fields first");
+  const int ns = c->ns, NP = ns + 9;
+  if ((size_t)c->obs_blocks * NP + OBS_FOLD > SCRATCH_DOUBLES || c->obs_blocks > OBS_BLOCKS)
+    return set_err(c, FDLBM_E_INVALID, "observe needs %zu scratch values, the static array holds %zu",
+                   (size_t)c->obs_blocks * NP + OBS_FOLD, SCRATCH_DOUBLES);
+  double *sp = nullptr;
+  const int rc = scratch_ptr(c, &sp);
+  if (rc != FDLBM_OK) return rc;
+  double *part = sp, *fold = sp + (size_t)c->obs_blocks * NP;
+  const hipError_t e = (hipError_t)with_prec(c, [&](auto tag) {
+    using Tg = decltype(tag);
+    using real = typename Tg::real;
+    using PT = typename Tg::pop;
+    Bufs<real, PT> bu = bufs<real, PT>(c);
+    bu.partials = part;  // the kernel's partial sums go to the static array
+    return (int)launch_observe<real, PT>(c->D, params<real>(c), bu, c->cur, c->obs_blocks, c->stream);
+  });
+  if (e != hipSuccess) return set_err(c, FDLBM_E_HIP, "observe launch: %s", hipGetErrorString(e));
+  hipLaunchKernelGGL(k_obs_fold, dim3(1), dim3(64), 0, c->stream, (const double *)part, c->obs_blocks, ns,
+                     (const double *)(c->ws + c->off_am), (const double *)(c->ws + c->off_aw),
+                     (const double *)(c->ws + c->off_ab), c->acc_slots, fold);
+  HIPCHK(c, hipGetLastError());
+  double v[OBS_FOLD];
+  HIPCHK(c, hipMemcpyAsync(v, fold, (size_t)(NP + 3) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::memset(o, 0, sizeof *o);
+  for (int j = 0; j < ns; ++j) o->mass[j] = v[j];
+  o->e_gas = v[ns];
+  o->e_solid = v[ns + 1];
+  o->T_min = v[ns + 2];
+  o->T_max = v[ns + 3];
+  o->u_max = v[ns + 4];
+  o->rho_min = v[ns + 5];
+  o->Ts_min = v[ns + 6];
+  o->Ts_max = v[ns + 7];
+  o->bad = v[ns + 8] != 0.0 ? 1 : 0;
+  o->moles_reacted = v[NP];
+  o->work_body = v[NP + 1];
+  o->heat_boundary = v[NP + 2];
+  o->heat_released = -c->dH * o->moles_reacted;
+  if (o->rho_min < 0) o->bad = 1;
+  o->step = c->step;
+  o->n_gas = (int32_t)c->gas_list.size();
+  o->n_wall = (int32_t)c->wall_list.size();
+  o->n_solid = (int32_t)c->n_solid;
+  return FDLBM_OK;
+}
+
 int fdlbm_residual(fdlbm_ctx *c, double *r5) {
   if (!c || !r5) return FDLBM_E_INVALID;
   if (!c->initialized || c->step == 0) return set_err(c, FDLBM_E_STATE, "the residual needs a completed step");

@@ -36,7 +36,7 @@ EXPORTS = ["fdlbm_create", "fdlbm_destroy", "fdlbm_last_error", "fdlbm_set_geome
            "fdlbm_batch_last_error", "fdlbm_batch_workspace_bytes", "fdlbm_batch_bind_workspace",
            "fdlbm_batch_set_active", "fdlbm_batch_step", "fdlbm_batch_set_grid",
            "fdlbm_batch_get_grid", "fdlbm_batch_autotune", "fdlbm_batch_set_overlap",
-           "fdlbm_set_sync_check", "fdlbm_last_step"]
+           "fdlbm_set_sync_check", "fdlbm_last_step", "fdlbm_observe_noalloc"]
 BATCH_KINDS = ["wall_fast", "wall_slow", "gas_fast", "gas_slow", "collide", "solid"]
 
 
@@ -96,6 +96,7 @@ def lib() -> ct.CDLL:
         L.fdlbm_step.argtypes = [vp, i64]
         L.fdlbm_sync.argtypes = [vp]
         L.fdlbm_observe.argtypes = [vp, ct.POINTER(Obs)]
+        L.fdlbm_observe_noalloc.argtypes = [vp, ct.POINTER(Obs)]
         L.fdlbm_get_field.argtypes = [vp, ct.c_int, ct.c_int, dp]
         L.fdlbm_state_bytes.argtypes = [vp, ct.POINTER(ct.c_size_t)]
         L.fdlbm_save_state.argtypes = [vp, vp, ct.c_size_t]
@@ -236,6 +237,12 @@ class Sim:
     def observe(self) -> dict:
         o = Obs()
         self._check(lib().fdlbm_observe(self.h, ct.byref(o)))
+        return o.as_dict(self.ns)
+
+    def observe_noalloc(self) -> dict:
+        """fdlbm_observe_noalloc: the observables without any allocation."""
+        o = Obs()
+        self._check(lib().fdlbm_observe_noalloc(self.h, ct.byref(o)))
         return o.as_dict(self.ns)
 
     def field(self, fid: int, comp: int = 0) -> np.ndarray:
