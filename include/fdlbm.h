@@ -72,12 +72,14 @@ extern "C" {
 #define FDLBM_CORR_ENERGY 4u     /* energy-flux lattice-deviation correction     */
 #define FDLBM_CORR_PRANDTL 8u    /* variable Prandtl number, Eq.(19)-(21)        */
 #define FDLBM_CORR_ALL 15u
-/* The energy-flux and Prandtl corrections add heat diffusion explicitly.  On
- * D2Q9 the energy-flux term supplies three quarters of it, and it amplifies
- * short diagonal disturbances: a perturbed periodic box blows up after
- * 10^3 steps at tau1 = 0.3 (later for smaller tau1).  The same happens with
- * the Prandtl correction alone at Pr = 0.25.  Starts from rest and D3Q19 runs
- * are not affected.  For perturbed 2-D starts, drop FDLBM_CORR_ENERGY. */
+/* The energy-flux correction's heat-conduction part and the Prandtl
+ * correction add heat diffusion explicitly (as energy sources in face-flux
+ * form), which bounds the relaxation times: with Pr = 1 the step is
+ * linearly stable for tau1 below 1/2 (the checkerboard mode is multiplied
+ * by 1 - 4 tau1 on D3Q19); the Prandtl term tightens this for Pr < 1
+ * (single species, Pr = 0.71: stable at tau1 = 0.1 on D3Q19 and 0.45 on
+ * D2Q9).  The packed bed's mixture is stable.  A run beyond the bound
+ * blows up; fdlbm_set_sync_check reports it. */
 
 /* wall modes */
 #define FDLBM_WALL_REACTIVE 0   /* T_w = solid temperature, heat exchanged (Sec. 5) */
@@ -207,6 +209,22 @@ int fdlbm_set_solid_scheme(fdlbm_ctx *ctx, int scheme);
 int fdlbm_set_reaction(fdlbm_ctx *ctx, const double *nu, const double *order, double k0,
                        double ea, double T_ref, double dH, int wall_mode, double T_iso,
                        double tol, int max_iter);
+
+/* Scaling of the surface rate at a wall node.  FDLBM_RATE_PER_NODE (the
+ * default): one reaction term S_j per wall node, also at corner nodes, as
+ * Sec. 4.3 states for walls built from plane and convex corner nodes.
+ * FDLBM_RATE_PER_AREA (a reading for geometries with concave corners, such
+ * as sphere packs, which the paper excludes): the rate is a flux per unit
+ * wall area, so each node's rate is multiplied by its wetted area, its rest
+ * emission weight over the links into the gas relative to a plane wall's
+ * T_w / 2 (1 on plane walls; summed over a staircase sphere it is 1.21 times
+ * the sphere's area).  Per node, the one-link wall nodes of a sphere pack
+ * emit their whole production through one link, and trace product
+ * densities next to them turn negative within steps at k0 = 2e-3.
+ * FDLBM_E_INVALID for another value.  Takes effect at the next step. */
+#define FDLBM_RATE_PER_NODE 0
+#define FDLBM_RATE_PER_AREA 1
+int fdlbm_set_rate_scaling(fdlbm_ctx *ctx, int mode);
 
 /* Flow: body force per unit mass F3[3]; inlet mole fractions X_in[ns],
  * pressure p_in and temperature T_in (used when inout = 1). */

@@ -64,6 +64,8 @@ struct oracle_sim {
   double *rho, *u, *T, *tau1, *tau2, *Jf, *Uc;
   double *wall_r, *wall_dE;
   double *wall_u;   /* wall velocity U_w per node, 3 rows (NULL: walls at rest) */
+  int literal_eq6;  /* 1: f* at the mixture temperature as printed in Eq.(6) */
+  int rate_area;    /* 1: rate scaled by the wall node's wetted area (reading) */
   /* cumulative counters */
   double moles, heat, bheat, work;
   int64_t step;
@@ -883,9 +885,22 @@ static void wall_bc(oracle_sim *s) {
      * The paper's fixed-point iteration for rho_w, started here from the
      * non-reactive wall density A_j / Z; each pass treats a reactant's own
      * concentration implicitly (rho_j = A_j / (Z + |nu_j| r / C_j)). */
-    /* one reaction term S_j per wall node, also at corners: corner nodes
+    /* One reaction term S_j per wall node, also at corners: corner nodes
      * differ from plane ones only in which populations enter Eq.(41)
-     * (Sec. 4.3, after the wall-density iteration) */
+     * (Sec. 4.3, after the wall-density iteration; the paper builds its
+     * walls from plane and convex corner nodes only).  Option (reading, for
+     * geometries with concave corners such as sphere packs): the rate is a
+     * flux per unit wall area, so it is scaled by the node's wetted area,
+     * its rest emission weight over the links into the gas relative to a
+     * plane wall's T_w / 2 (factor 1 on plane walls). */
+    double area = 1.0;
+    if (s->rate_area) {
+      double Zg = 0.0, f0[MAXQ], u0[3] = {0, 0, 0};
+      equilibrium(s->D, s->Q, s->c, 1.0, 1.0, u0, Tw, f0);
+      for (int i = 1; i < Q; ++i)
+        if (emits(s, w, i)) Zg += f0[i];
+      area = Zg / (0.5 * Tw);
+    }
     double rw[MAXS];
     for (int j = 0; j < ns; ++j) rw[j] = A[j] / Z[j];
     for (int it = 0; it < s->max_iter; ++it) {
@@ -894,7 +909,7 @@ static void wall_bc(oracle_sim *s) {
         nw[j] = rw[j];
         if (s->nu[j] < 0.0 && s->order[j] > 0.0) {
           /* r / C_j with C_j's own power lowered by one */
-          double R = s->k0 * exp(s->ea * (1.0 - s->T_ref_rxn / Tw));
+          double R = area * s->k0 * exp(s->ea * (1.0 - s->T_ref_rxn / Tw));
           for (int m = 0; m < ns; ++m) {
             double o = s->order[m] - (m == j ? 1.0 : 0.0);
             if (o != 0.0) R *= pow(rw[m] / s->M[m], o);
@@ -907,7 +922,7 @@ static void wall_bc(oracle_sim *s) {
       for (int j = 0; j < ns; ++j) rw[j] = nw[j];
       if (dmax <= s->tol) break;
     }
-    double r = rate(s, rw, Tw);
+    double r = area * rate(s, rw, Tw);
     /* final wall densities from the exact mass balance at the final rate */
     for (int j = 0; j < ns; ++j) rw[j] = (A[j] + s->nu[j] * s->M[j] * r) / Z[j];
     double Eout = 0.0;
@@ -1096,9 +1111,32 @@ static void collide(oracle_sim *s) {
         }
       }
       if (s->flags & F_ENER) {
-        /* reading: energy-flux correction with moments sum_i c_a c^2 S = d_b R'_ab */
+        /* reading: the energy-flux correction removes the deviation R'_ab of
+         * the lattice's energy flux (c_a c_b c^2 moment) from the
+         * Maxwellian's.  Off-diagonal part: a source with moments
+         * sum_i c_a c^2 S = d_b R'_ab (b != a), which the streaming turns
+         * into a heat-flux correction.  Diagonal part (at rest the
+         * heat-conduction defect, R'_aa = rho T (1 - 3T) / M^2): carried as
+         * the divergence of that heat flux, -tau1 d_a R'_aa, in the compact
+         * face-flux form of the Prandtl term -- an energy source
+         * e = sum over faces of (-tau1 face average) (R'_aa(nb) - R'_aa(x)),
+         * no flux through gas-wall faces.  A source's energy moment counts in
+         * full in the trapezoidal step, which fixes the factor tau1.  (The
+         * same term as a flux moment, d_a R'_aa, makes the step linearly
+         * unstable: D2Q9 at every tau1, D3Q19 with a mean flow at small
+         * tau1.) */
         for (int a = 0; a < D; ++a)
-          for (int b = 0; b < D; ++b) Y[a] += 0.5 * (Rdev(s, j, &nbp[b], a, b) - Rdev(s, j, &nbm[b], a, b));
+          for (int b = 0; b < D; ++b)
+            if (b != a) Y[a] += 0.5 * (Rdev(s, j, &nbp[b], a, b) - Rdev(s, j, &nbm[b], a, b));
+        const double tx = s->tau1[(size_t)j * n + x];
+        for (int a = 0; a < D; ++a) {
+          const double rx = Rdev(s, j, &me, a, a);
+          const nbstate *nb[2] = {&nbp[a], &nbm[a]};
+          for (int q = 0; q < 2; ++q) {
+            if (nb[q]->is_wall || nb[q]->missing) continue;
+            e += -0.5 * (tx + nb[q]->tau1[j]) * (Rdev(s, j, nb[q], a, a) - rx);
+          }
+        }
       }
       if ((s->flags & F_PR) && s->Pr_j[j] != 1.0) {
         /* Eq.(19)-(21): Phi^Pr = phi_ji d_a q^Pr_ja with, reading, the species
@@ -1151,7 +1189,7 @@ static void collide(oracle_sim *s) {
      * (Taking T* = T would let the two-step relaxation create energy at the
      * rate sum_j rho_j |u_j - u|^2 (1/tau1 - 1/tau2), against the paper's
      * statement that the corrected equation conserves energy.) */
-    double Tstar = Tf - ediff / (D * C);
+    double Tstar = s->literal_eq6 ? Tf : Tf - ediff / (D * C);
     for (int j = 0; j < ns; ++j) {
       double tau1 = s->tau1[(size_t)j * n + x], tau2 = s->tau2[(size_t)j * n + x];
       double feq[MAXQ], fst[MAXQ];
@@ -1448,6 +1486,34 @@ int oracle_get_field(oracle_sim *s, int field, int comp, double *dst) {
       return 0;
   }
   return fail(s, "unknown field");
+}
+
+/* Temperature of the auxiliary equilibrium f*: 0 (default) the reading that
+ * holds the mixture energy fixed, 1 the printed Eq.(6), f* at the mixture
+ * temperature T (for comparing the two). */
+int oracle_set_literal_eq6(oracle_sim *s, int on) {
+  if (!s) return fail(s, "null simulation");
+  s->literal_eq6 = on != 0;
+  return 0;
+}
+
+/* Rate per wall node (0, the default, as in Sec. 4.3) or per unit wetted
+ * wall area (1, the reading for sphere packs). */
+int oracle_set_rate_area(oracle_sim *s, int on) {
+  if (!s) return fail(s, "null simulation");
+  s->rate_area = on != 0;
+  return 0;
+}
+
+/* Overwrite the populations of species comp (Q*n values, the layout of
+ * oracle_get_field's OF_POP): a building block for the linear stability
+ * analysis, which needs arbitrary, not only equilibrium, states. */
+int oracle_set_pops(oracle_sim *s, int comp, const double *src) {
+  if (!s || !src) return fail(s, "null argument");
+  if (!s->init_done) return fail(s, "initialise the fields first");
+  if (comp < 0 || comp >= s->ns) return fail(s, "bad species");
+  memcpy(&s->G[(size_t)comp * s->Q * s->n], src, sizeof(double) * (size_t)s->Q * s->n);
+  return 0;
 }
 
 /* Third-moment and energy-flux deviations of the lattice equilibrium from the

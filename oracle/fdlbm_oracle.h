@@ -85,6 +85,12 @@ int oracle_observe(oracle_sim *s, oracle_obs *out);
 enum { OF_RHO = 0, OF_U = 1, OF_T = 2, OF_TS = 3, OF_POP = 4, OF_KIND = 5, OF_WALL_R = 6,
        OF_WALL_DE = 7 };
 int oracle_get_field(oracle_sim *s, int field, int comp, double *dst);
+/* reaction rate per wall node (0, default) or per unit wetted area (1) */
+int oracle_set_rate_area(oracle_sim *s, int on);
+/* f* temperature: 0 the energy-holding reading (default), 1 Eq.(6) as printed */
+int oracle_set_literal_eq6(oracle_sim *s, int on);
+/* overwrite the populations of species comp (Q*n values, OF_POP layout) */
+int oracle_set_pops(oracle_sim *s, int comp, const double *src);
 
 /* ---- building blocks exposed for the pin tests ---- */
 /* equilibrium populations of one species, Eq.(4)/(6) (D2Q9) or the D3Q19 reading */

@@ -74,6 +74,9 @@ def lib():
                                           ct.c_double, ct.c_int]
         L.oracle_set_flow.argtypes = [ct.c_void_p, dp, dp, ct.c_double, ct.c_double]
         L.oracle_set_wall_velocity.argtypes = [ct.c_void_p, dp]
+        L.oracle_set_pops.argtypes = [ct.c_void_p, ct.c_int, dp]
+        L.oracle_set_literal_eq6.argtypes = [ct.c_void_p, ct.c_int]
+        L.oracle_set_rate_area.argtypes = [ct.c_void_p, ct.c_int]
         L.oracle_init_fields.argtypes = [ct.c_void_p, dp, dp, dp, dp]
         L.oracle_step.argtypes = [ct.c_void_p, ct.c_int64]
         L.oracle_observe.argtypes = [ct.c_void_p, ct.POINTER(Obs)]
@@ -183,6 +186,10 @@ class OracleSim:
         fl = cfg["flow"]
         F, Xin = _arr(fl["F"]), _arr(fl["X_in"])
         self._check(L.oracle_set_flow(h, _d(F), _d(Xin), fl["p_in"], fl["T_in"]))
+        if rx.get("rate_area"):
+            self._check(L.oracle_set_rate_area(h, 1))
+        if cfg.get("literal_eq6"):
+            self._check(L.oracle_set_literal_eq6(h, 1))
         if cfg.get("wall_u") is not None:
             # per-node wall velocity [3][n] (Eq.(39)'s U_w), read at wall nodes
             wu = _arr(cfg["wall_u"]).reshape(-1)
@@ -214,6 +221,12 @@ class OracleSim:
         out = np.zeros(size)
         self._check(lib().oracle_get_field(self.h, fid, comp, _d(out)))
         return out
+
+    def set_pops(self, comp: int, g) -> None:
+        """Overwrite species comp's populations ([Q*n], the OF_POP layout)."""
+        a = _arr(g).reshape(-1)
+        assert a.size == self.Q * self.n
+        self._check(lib().oracle_set_pops(self.h, int(comp), _d(a)))
 
     def transport(self, rho, T):
         t1, t2 = np.zeros(self.ns), np.zeros(self.ns)

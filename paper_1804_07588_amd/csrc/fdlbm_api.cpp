@@ -44,6 +44,7 @@ struct fdlbm_ctx {
   double nu[MAXS]{}, order[MAXS]{}, k0 = 0, ea = 0, T_ref_rxn = 1.0 / 3, dH = 0, T_iso = 1.0 / 3,
          tol = 1e-13;
   int wall_mode = 0, max_iter = 64;
+  bool rate_area = false;  // rate per unit wetted wall area instead of per wall node
   double F[3]{}, X_in[MAXS]{}, p_in = 1.0 / 3, T_in = 1.0 / 3;
   double rho_ref[MAXS]{};  // reference densities of 16-bit storage (mean initial density)
   bool species_set = false, geometry_set = false, bound = false, initialized = false;
@@ -343,6 +344,7 @@ static Params<real> params(const fdlbm_ctx *c) {
   p.T_iso = (real)c->T_iso;
   p.tol = (real)std::max(c->tol, c->d.precision == FDLBM_F64 ? 0.0 : 4.0 * 1.1920929e-7);
   p.max_iter = c->max_iter;
+  p.rate_area = c->rate_area ? 1 : 0;
   for (int a = 0; a < 3; ++a) p.F[a] = a < c->D ? (real)c->F[a] : real(0);
   p.T_in = (real)c->T_in;
   p.p_in = (real)c->p_in;
@@ -710,6 +712,14 @@ int fdlbm_set_reaction(fdlbm_ctx *c, const double *nu, const double *order, doub
   c->T_iso = T_iso;
   c->tol = tol;
   c->max_iter = max_iter;
+  return FDLBM_OK;
+}
+
+int fdlbm_set_rate_scaling(fdlbm_ctx *c, int mode) {
+  if (!c) return FDLBM_E_INVALID;
+  if (mode != FDLBM_RATE_PER_NODE && mode != FDLBM_RATE_PER_AREA)
+    return set_err(c, FDLBM_E_INVALID, "rate scaling must be FDLBM_RATE_PER_NODE or FDLBM_RATE_PER_AREA");
+  c->rate_area = mode == FDLBM_RATE_PER_AREA;
   return FDLBM_OK;
 }
 

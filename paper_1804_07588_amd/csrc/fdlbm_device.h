@@ -107,6 +107,7 @@ struct Params {
   real nu[MAXS], k0, ea, T_ref_rxn, dH, T_iso, tol;
   int order[MAXS];
   int max_iter;
+  int rate_area;                   // 1: rate scaled by the wall node's wetted area
   // flow
   real F[3];
   real rho_in[MAXS], T_in, p_in;

@@ -445,8 +445,11 @@ __device__ inline double wall_node(const Params<real> &p, const Bufs<real, PT> &
 #pragma unroll
   for (int j = 0; j < NS; ++j) rw[j] = A[j] / Z;
   // rate constant at T_w (Eq.(50) with the Arrhenius factor); one reaction
-  // term per wall node, corners included (Sec. 4.3)
-  const real keff = p.k0 * exp(p.ea * (real(1) - p.T_ref_rxn / Tw));
+  // term per wall node, corners included (Sec. 4.3), or, as an option, per
+  // unit wetted area: the node's rest emission weight over its links into
+  // the gas relative to a plane wall's T_w / 2 (Z itself: the wall emits at
+  // rest, so Z is that weight)
+  const real keff = (p.rate_area ? Z / (real(0.5) * Tw) : real(1)) * p.k0 * exp(p.ea * (real(1) - p.T_ref_rxn / Tw));
   for (int it = 0; it < p.max_iter; ++it) {
     real nw[NS], dmax = 0;
 #pragma unroll
@@ -911,9 +914,21 @@ __device__ inline void collide_node(const Params<real> &p, const Bufs<real, PT> 
         const real dq = real(0.5) * (-rp * up[0] * up[1] * up[2] + rm * um[0] * um[1] * um[2]);
         Po[j][2 - a] += kvisc * dq;  // a = x -> yz (2), y -> xz (1), z -> xy (0)
       }
+      // energy-flux deviation R'_ca: the off-diagonal part as a source of
+      // c_c c^2 moment d_a R'_ca; the diagonal (heat-conduction) part as
+      // the energy source of the heat flux -tau1 d_a R'_aa in face-flux form
+      // (face-averaged tau1, no flux through wall or missing faces)
 #pragma unroll
       for (int c = 0; c < D; ++c)
-        Y[j][c] += kener * real(0.5) * (r_dev<real, D>(rp, iM, up, Tp, c, a) - r_dev<real, D>(rm, iM, um, Tm, c, a));
+        if (c != a)
+          Y[j][c] += kener * real(0.5) * (r_dev<real, D>(rp, iM, up, Tp, c, a) - r_dev<real, D>(rm, iM, um, Tm, c, a));
+      {
+        const real Rx = r_dev<real, D>(rj, iM, u, Tt, a, a);
+        const real t1x = me.v[fr_tau1(D, j)];
+        const real gp = real(-0.5) * (t1x + nr[0].v[fr_tau1(D, j)]) * (r_dev<real, D>(rp, iM, up, Tp, a, a) - Rx);
+        const real gm = real(-0.5) * (t1x + nr[1].v[fr_tau1(D, j)]) * (r_dev<real, D>(rm, iM, um, Tm, a, a) - Rx);
+        e[j] += kener * ((fp ? gp : real(0)) + (fm ? gm : real(0)));
+      }
       // Eq.(19)-(21), face-flux form; wall faces carry no correction flux
       const real kpr = prc ? p.kprj[j] : real(0);
       const real Kx = kpr * me.v[fr_tau1(D, j)] * rj * iM * Tt * iM;

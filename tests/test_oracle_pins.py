@@ -72,17 +72,20 @@ def test_total_momentum_is_conserved_with_unequal_masses(oracle_lib):
     sim.close()
 
 
-def test_wall_density_and_rate_first_step_closed_form(oracle_lib):
+@pytest.mark.parametrize("per_area", [False, True])
+def test_wall_density_and_rate_first_step_closed_form(oracle_lib, per_area):
     """Sec. 4.3, Eq.(37)-(41) with a first-order rate (Eq.(50) form
     r = k C_A,w): from a uniform gas at rest every wall node receives
     A = rho_A Z (Z = sum over its links into the gas of the rest weights at
     T_w, the same set mirrored), so the converged wall density of the
-    reactant is rho_A,w = A / (Z + k) and the rate r = k rho_A,w / M_A, at
-    every wall node of a sphere pack: plane, convex and concave corner nodes
-    alike (one reaction term per wall node, corners differing only in which
-    populations enter Eq.(41)).  The product's wall density is
-    (A_B + M_B r) / Z.  A heavy reactant (M_A = 4) streams through the
-    interpolated classes, degraded ones included."""
+    reactant is rho_A,w = A / (Z + k a) and the rate r = a k rho_A,w / M_A at
+    every wall node of a sphere pack, plane, convex and concave corner nodes
+    alike.  a = 1 per wall node (the paper's form: one reaction term per
+    node, corners differing only in which populations enter Eq.(41)); with
+    the per-area option a = Z / (T_w / 2), the node's wetted area relative
+    to a plane wall.  The product's wall density is (A_B + M_B r) / Z.  A
+    heavy reactant (M_A = 4) streams through the interpolated classes,
+    degraded ones included."""
     of = oracle_lib
     mask, _ = W.sphere_pack_mask(16, radius=3.0, porosity=0.6, seed=5, buffer=0)
     k = 0.05
@@ -90,7 +93,8 @@ def test_wall_density_and_rate_first_step_closed_form(oracle_lib):
     cfg["mask"] = mask
     X = [0.6, 0.4]
     cfg["init"]["X"] = X
-    cfg["reaction"].update(nu=[-1.0, 1.0], order=[1.0, 0.0], k0=k, ea=3.0, T_ref=T0, max_iter=200)
+    cfg["reaction"].update(nu=[-1.0, 1.0], order=[1.0, 0.0], k0=k, ea=3.0, T_ref=T0, max_iter=200,
+                           rate_area=per_area)
     sim = of.OracleSim(cfg, W.uniform_init(cfg))
     sim.step(1)
     kind = sim.field(of.OF_KIND).reshape(mask.shape)
@@ -106,10 +110,11 @@ def test_wall_density_and_rate_first_step_closed_form(oracle_lib):
                 Z[q] += W19[i]
     # a pack of overlapping spheres has plane, convex and concave wall nodes
     assert len(np.unique(np.round(Z * 36))) >= 6
+    a = Z / (0.5 * T0) if per_area else np.ones_like(Z)
     M_A, M_B = 4.0, 4.0
     rho_A, rho_B = M_A * X[0], M_B * X[1]
-    rw_A = rho_A * Z / (Z + k)
-    r = k * rw_A / M_A
+    rw_A = rho_A * Z / (Z + k * a)
+    r = a * k * rw_A / M_A
     rw_B = (rho_B * Z + M_B * r) / Z
     flat = walls[:, 0] * ny * nx + walls[:, 1] * nx + walls[:, 2]
     got_r = sim.field(of.OF_WALL_R)[flat]
@@ -119,7 +124,7 @@ def test_wall_density_and_rate_first_step_closed_form(oracle_lib):
     assert np.abs(got_A - rw_A).max() <= 1e-12 * rw_A.max()
     assert np.abs(got_B - rw_B).max() <= 1e-12 * rw_B.max()
     # the rate is the rate law at the converged wall density
-    assert np.abs(got_r - k * got_A / M_A).max() <= 1e-13 * r.max()
+    assert np.abs(got_r - a * k * got_A / M_A).max() <= 1e-13 * r.max()
     assert sim.observe()["moles_reacted"] == pytest.approx(r.sum(), rel=1e-12)
     sim.close()
 
@@ -333,3 +338,156 @@ def test_erf_conduction(oracle_lib, lattice, pr, tol):
     (al,), _ = curve_fit(lambda xv, a: prof(4 * alpha * t0 + 4 * a * t), x, Tn, p0=[alpha])
     assert al == pytest.approx(alpha, rel=tol), (al, alpha)
     assert np.abs(Tn - prof(4 * alpha * t0 + 4 * al * t)).max() < 3e-3 * dT
+
+
+def _vn_box(N, lattice, tau1, u0):
+    nz = N if lattice == 3 else 1
+    return dict(lattice=lattice, nx=N, ny=N, nz=nz, periodic=(1, 1, 1),
+                mask=np.zeros((nz, N, N), np.uint8), inout=0,
+                species=dict(M=[1.0], mu0=[tau1 * T0], mu_T_exp=0.0, Djk0=[[0.0]], D_T_exp=0.0,
+                             D_p_exp=0.0, T_ref=T0, p_ref=T0, Pr=1.0, flags=W.CORR_ALL),
+                solid=dict(alpha_s=0.0, C_s=1.0, T_bc=[np.nan] * 6),
+                reaction=dict(nu=[0.0], order=[0.0], k0=0.0, ea=0.0, T_ref=T0, dH=0.0,
+                              wall_mode=W.WALL_REACTIVE, T_iso=T0, tol=1e-14, max_iter=8),
+                flow=dict(F=[0, 0, 0], X_in=[1.0], p_in=T0, T_in=T0),
+                init=dict(X=[1.0], C=1.0, T=T0, Ts=T0, u=list(u0)))
+
+
+def amplification(of, N, lattice, tau1, u0=(0.0, 0.0, 0.0), eps=1e-6):
+    """Largest |eigenvalue| over all wavevectors of the linearised step
+    around a uniform equilibrium state (von Neumann analysis).  The step is
+    translation invariant, so the responses to one kicked population at one
+    node (central differences of one full oracle step) give, by Fourier
+    transform, the Q x Q amplification matrix of every wavevector."""
+    cfg = _vn_box(N, lattice, tau1, u0)
+    sim = of.OracleSim(cfg, W.uniform_init(cfg))
+    Q, n = sim.Q, sim.n
+    base = sim.field(of.OF_POP, 0).copy()
+    H = np.zeros((Q, Q, n))
+    for q in range(Q):
+        out = []
+        for sg in (1.0, -1.0):
+            g = base.copy()
+            g[q * n] += sg * eps
+            sim.init_fields(W.uniform_init(cfg))
+            sim.set_pops(0, g)
+            sim.step(1)
+            out.append(sim.field(of.OF_POP, 0))
+        H[q] = ((out[0] - out[1]) / (2 * eps)).reshape(Q, n)
+    sim.close()
+    dims = (N, N) if lattice == 2 else (N, N, N)
+    axes = tuple(range(2, 2 + len(dims)))
+    Hk = np.fft.fftn(H.reshape((Q, Q) + dims), axes=axes)
+    Gk = np.moveaxis(Hk, (0, 1), (-1, -2)).reshape(-1, Q, Q)
+    return np.abs(np.linalg.eigvals(Gk)).max()
+
+
+@pytest.mark.parametrize("lattice,N", [(2, 16), (3, 8)])
+@pytest.mark.parametrize("tau1", [0.05, 0.3, 0.45])
+@pytest.mark.parametrize("u0", [(0.0, 0.0, 0.0), (0.03, 0.0, 0.02)])
+def test_corrected_step_is_linearly_stable(oracle_lib, lattice, N, tau1, u0):
+    """Von Neumann analysis of the full corrected step (all four correction
+    terms) around a uniform state, at rest and in a mean flow of the bed's
+    peak speed: for tau1 below 1/2 no wavevector grows (largest |eigenvalue|
+    1 within rounding, from the conserved modes).  This decides the form of
+    the energy-flux correction's heat-conduction part (a face-flux energy
+    source rather than a flux moment: the latter grew by about
+    1 + 0.18 tau1 per step at k = (3/4, 3/4) pi on D2Q9, at every tau1)."""
+    lam = amplification(oracle_lib, N, lattice, tau1, u0)
+    assert lam < 1.0 + 1e-7, lam
+
+
+def test_energy_correction_bound_on_tau1(oracle_lib):
+    """The bound the explicit heat-conduction correction sets: on D3Q19 the
+    checkerboard mode is multiplied by 1 - 4 tau1 per step, so the step is
+    stable up to tau1 = 1/2 and not beyond (|lambda| = 1.4 at tau1 = 0.6)."""
+    assert amplification(oracle_lib, 8, 3, 0.6) == pytest.approx(1.4, abs=1e-6)
+
+
+def test_printed_eq6_temperature_does_not_conserve_energy(oracle_lib):
+    """Reading of Eq.(6): the auxiliary state f* is taken at the temperature
+    that keeps the mixture energy (T* = T - sum rho_j |u_j - u|^2 / (D C));
+    Eq.(6) as printed puts it at the mixture T.  Two species of equal mass
+    and viscosity (hence one relaxation time tau1, so the first relaxation
+    conserves energy) with a diffusion front (species velocities differ):
+    a periodic box conserves the total energy to rounding with the reading;
+    with the printed form it changes at the rate
+    sum_j rho_j |u_j - u|^2 (1/tau1 - 1/tau2) (here it loses 4e-4 in 200
+    steps, tau2 < tau1)."""
+    of = oracle_lib
+    cfg = mixture_box(8, (1.0, 1.0), [[0, 0.02], [0.02, 0]], (0.05, 0.05), lattice=3)
+    cfg["init"]["X"] = [0.5, 0.5]
+    init = W.uniform_init(cfg)
+    n = cfg["nx"] ** 3
+    x = np.tile(np.arange(8), 64)
+    front = 0.2 * np.sin(2 * np.pi * x / 8)
+    init["rho"][0] *= 1 + front
+    init["rho"][1] *= 1 - front
+    gains = []
+    for literal in (False, True):
+        sim = of.OracleSim(dict(cfg, literal_eq6=literal), init)
+        e0 = sim.observe()["e_gas"]
+        sim.step(200)
+        gains.append((sim.observe()["e_gas"] - e0) / e0)
+        sim.close()
+    assert abs(gains[0]) < 1e-13, gains
+    assert gains[1] < -1e-5, gains
+
+
+def test_bed_mixture_is_linearly_stable(oracle_lib):
+    """The packed bed's five-species mixture (masses 14, 9, 22, 1, 14,
+    Pr = 0.71, relaxation times tau1 from 0.05 to 0.36 at the inlet state)
+    with all corrections, in a mean flow of the bed's peak speed: the
+    linearised step has no growing wavevector (largest |eigenvalue| within
+    the analysis' numerical floor of 1e-5 of one; the response matrices are
+    95 x 95 per wavevector)."""
+    of = oracle_lib
+    N, eps = 8, 1e-7
+    cfg = W.packed_bed(mask=np.zeros((N, N, N), np.uint8))
+    cfg.update(inout=0, periodic=(1, 1, 1))
+    cfg["reaction"]["k0"] = 0.0
+    cfg["init"]["u"] = [0.03, 0.0, 0.01]
+    sim = of.OracleSim(cfg, W.uniform_init(cfg))
+    Q, n, ns = sim.Q, sim.n, sim.ns
+    base = [sim.field(of.OF_POP, j).copy() for j in range(ns)]
+    H = np.zeros((Q * ns, Q * ns, n))
+    for j in range(ns):
+        for q in range(Q):
+            h = eps * base[j][q * n]
+            out = []
+            for sg in (1.0, -1.0):
+                sim.init_fields(W.uniform_init(cfg))
+                for jj in range(ns):
+                    g = base[jj].copy()
+                    if jj == j:
+                        g[q * n] += sg * h
+                    sim.set_pops(jj, g)
+                sim.step(1)
+                out.append(np.concatenate([sim.field(of.OF_POP, jj) for jj in range(ns)]))
+            H[j * Q + q] = ((out[0] - out[1]) / (2 * h)).reshape(ns * Q, n)
+    sim.close()
+    Hk = np.fft.fftn(H.reshape((Q * ns, Q * ns, N, N, N)), axes=(2, 3, 4))
+    Gk = np.moveaxis(Hk, (0, 1), (-1, -2)).reshape(-1, Q * ns, Q * ns)
+    lam = np.abs(np.linalg.eigvals(Gk)).max()
+    assert lam < 1.0 + 1e-5, lam
+
+
+@pytest.mark.parametrize("r", [6, 10])
+def test_wetted_area_of_a_staircase_sphere(r):
+    """The per-area rate option measures a wall node's wetted area by its
+    rest emission weight over the links into the gas relative to a plane
+    wall's T/2.  Summed over the wall nodes of a solid sphere in gas this is
+    1.2 times the sphere's area 4 pi r^2 (the staircase surface has more
+    links than a smooth one; the plain wall-node count gives 1.06 - 1.2): a
+    consistent, not an exact, area measure."""
+    n = 2 * r + 8
+    z, y, x = np.mgrid[0:n, 0:n, 0:n]
+    c = (n - 1) / 2.0
+    solid = (x - c) ** 2 + (y - c) ** 2 + (z - c) ** 2 <= r * r
+    Z = np.zeros(solid.shape)
+    for i in range(1, 19):
+        cx, cy, cz = D3Q19[i]
+        nb = np.roll(solid, (-cz, -cy, -cx), axis=(0, 1, 2))
+        Z += (solid & ~nb) * W19[i]
+    ratio = (Z / (0.5 * T0)).sum() / (4 * np.pi * r * r)
+    assert 1.18 < ratio < 1.23, ratio
