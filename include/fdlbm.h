@@ -200,6 +200,23 @@ int fdlbm_set_solid(fdlbm_ctx *ctx, double alpha_s, double C_s, const double *T_
 #define FDLBM_SOLID_CN 1
 int fdlbm_set_solid_scheme(fdlbm_ctx *ctx, int scheme);
 
+/* Solid-gas coupling at the wall nodes (Sec. 5, Eq.(48)).
+ * FDLBM_COUPLING_FLUX (default): the wall node's solid energy changes by
+ * the reaction heat (Eq.(42)) minus the kinetic energy the diffusive wall
+ * handed the gas in the same step, so the interface conserves energy
+ * exactly (the enthalpy error of Eq.(49) is rounding).
+ * FDLBM_COUPLING_EQ48: Eq.(48) itself, the third term read with the sign
+ * that moves heat from the warmer side: per gas face neighbour
+ * kappa_f (T^f - T^s) / C_s with kappa_f = sum_j (D+2) tau1_j C_j T /
+ * (2 M_j Pr_j) from that neighbour's moments of the step; the diffusive
+ * wall still hands the gas its energy, so the interface does not conserve
+ * energy (Eq.(49)'s error is then about 3 % on the channel workload) and
+ * the solid step waits for the moments (no overlap).  Forward-Euler solid
+ * only, not in batches; FDLBM_E_INVALID otherwise or for another value. */
+#define FDLBM_COUPLING_FLUX 0
+#define FDLBM_COUPLING_EQ48 1
+int fdlbm_set_solid_coupling(fdlbm_ctx *ctx, int mode);
+
 /* Surface reaction (Eq.(50) generalised): molar rate per wall node and step
  * r = k0 exp[ea (1 - T_ref/T_w)] prod_j C_jw^order_j, species j produced at
  * nu_j per unit extent (nu < 0 reactants); orders must be integers 0..3.

@@ -66,6 +66,7 @@ struct oracle_sim {
   double *wall_u;   /* wall velocity U_w per node, 3 rows (NULL: walls at rest) */
   int literal_eq6;  /* 1: f* at the mixture temperature as printed in Eq.(6) */
   int rate_area;    /* 1: rate scaled by the wall node's wetted area (reading) */
+  int eq48;         /* 1: solid-gas coupling of Eq.(48) instead of the flux-matched one */
   /* cumulative counters */
   double moles, heat, bheat, work;
   int64_t step;
@@ -1236,8 +1237,31 @@ static void solid(oracle_sim *s) {
     double Tn = T + s->alpha_s * lap;
     s->bheat += s->alpha_s * s->C_s * bflux;
     /* isothermal walls (prior art) exchange nothing with the solid */
-    if (s->kind[x] == K_WALL && s->wall_mode == 0)
-      Tn += (-s->dH * s->wall_r[x] - s->wall_dE[x]) / s->C_s;
+    if (s->kind[x] == K_WALL && s->wall_mode == 0) {
+      if (!s->eq48) {
+        Tn += (-s->dH * s->wall_r[x] - s->wall_dE[x]) / s->C_s;
+      } else {
+        /* Eq.(48): the third term is the heat the gas next to the wall
+         * exchanges with it, alpha^f rho^f c_p^f / (rho^s c_p^s) (T^f - T^s)
+         * = kappa_f (T^f - T^s) / C_s per gas face neighbour, with the gas
+         * conductivity kappa_f = sum_j (D+2) tau1_j C_j T / (2 M_j Pr_j)
+         * (reading of the Prandtl number's kappa) at that neighbour.
+         * Reading: the sign that makes heat flow from the warmer side (the
+         * printed minus would move it up the gradient). */
+        double qf = 0.0;
+        for (int a = 0; a < D; ++a)
+          for (int d = -1; d <= 1; d += 2) {
+            int nb = face_nbr(s, x, a, d);
+            if (nb < 0 || !gaslike(s, nb)) continue;
+            double kap = 0.0;
+            for (int j = 0; j < s->ns; ++j)
+              kap += (D + 2.0) * s->tau1[(size_t)j * n + nb] * (s->rho[(size_t)j * n + nb] / s->M[j]) *
+                     s->T[nb] / (2.0 * s->M[j] * s->Pr_j[j]);
+            qf += kap * (s->T[nb] - T);
+          }
+        Tn += (-s->dH * s->wall_r[x] + qf) / s->C_s;
+      }
+    }
     s->Tsn[x] = Tn;
   }
 }
@@ -1494,6 +1518,14 @@ int oracle_get_field(oracle_sim *s, int field, int comp, double *dst) {
 int oracle_set_literal_eq6(oracle_sim *s, int on) {
   if (!s) return fail(s, "null simulation");
   s->literal_eq6 = on != 0;
+  return 0;
+}
+
+/* Solid-gas coupling at wall nodes: 0 (default) flux-matched, 1 Eq.(48) */
+int oracle_set_coupling(oracle_sim *s, int eq48) {
+  if (!s) return fail(s, "null simulation");
+  if (eq48 && s->solid_scheme == 1) return fail(s, "Eq.(48) coupling with the forward-Euler solid only");
+  s->eq48 = eq48 != 0;
   return 0;
 }
 

@@ -85,6 +85,8 @@ int oracle_observe(oracle_sim *s, oracle_obs *out);
 enum { OF_RHO = 0, OF_U = 1, OF_T = 2, OF_TS = 3, OF_POP = 4, OF_KIND = 5, OF_WALL_R = 6,
        OF_WALL_DE = 7 };
 int oracle_get_field(oracle_sim *s, int field, int comp, double *dst);
+/* solid-gas coupling at wall nodes: 0 flux-matched (default), 1 Eq.(48) */
+int oracle_set_coupling(oracle_sim *s, int eq48);
 /* reaction rate per wall node (0, default) or per unit wetted area (1) */
 int oracle_set_rate_area(oracle_sim *s, int on);
 /* f* temperature: 0 the energy-holding reading (default), 1 Eq.(6) as printed */

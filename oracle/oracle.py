@@ -77,6 +77,7 @@ def lib():
         L.oracle_set_pops.argtypes = [ct.c_void_p, ct.c_int, dp]
         L.oracle_set_literal_eq6.argtypes = [ct.c_void_p, ct.c_int]
         L.oracle_set_rate_area.argtypes = [ct.c_void_p, ct.c_int]
+        L.oracle_set_coupling.argtypes = [ct.c_void_p, ct.c_int]
         L.oracle_init_fields.argtypes = [ct.c_void_p, dp, dp, dp, dp]
         L.oracle_step.argtypes = [ct.c_void_p, ct.c_int64]
         L.oracle_observe.argtypes = [ct.c_void_p, ct.POINTER(Obs)]
@@ -178,6 +179,8 @@ class OracleSim:
         if so.get("scheme", 0):
             self._check(L.oracle_set_solid_scheme(h, int(so["scheme"])))
         self._check(L.oracle_set_solid(h, so["alpha_s"], so["C_s"], _d(tbc)))
+        if so.get("coupling", 0):
+            self._check(L.oracle_set_coupling(h, int(so["coupling"])))
         rx = cfg["reaction"]
         nu, order = _arr(rx["nu"]), _arr(rx["order"])
         self._check(L.oracle_set_reaction(h, _d(nu), _d(order), rx["k0"], rx["ea"], rx["T_ref"],

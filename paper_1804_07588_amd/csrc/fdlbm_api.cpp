@@ -45,6 +45,7 @@ struct fdlbm_ctx {
          tol = 1e-13;
   int wall_mode = 0, max_iter = 64;
   bool rate_area = false;  // rate per unit wetted wall area instead of per wall node
+  int coupling = FDLBM_COUPLING_FLUX;  // solid-gas coupling at the wall nodes
   double F[3]{}, X_in[MAXS]{}, p_in = 1.0 / 3, T_in = 1.0 / 3;
   double rho_ref[MAXS]{};  // reference densities of 16-bit storage (mean initial density)
   bool species_set = false, geometry_set = false, bound = false, initialized = false;
@@ -326,6 +327,8 @@ static Params<real> params(const fdlbm_ctx *c) {
   // rho = a D / (1 + a D) each (row sums of the iteration matrix), so enough
   // sweeps take it below the arithmetic's rounding relative to the step
   p.solid_cn = c->solid_scheme == FDLBM_SOLID_CN ? 1 : 0;
+  p.eq48 = c->coupling == FDLBM_COUPLING_EQ48 ? 1 : 0;
+  for (int j = 0; j < c->ns; ++j) p.kap[j] = (real)((c->D + 2.0) / (2.0 * c->Pr_j[j]));
   p.cn_iters = 0;
   if (p.solid_cn) {
     const double rho = c->alpha_s * c->D / (1.0 + c->alpha_s * c->D);
@@ -685,6 +688,8 @@ int fdlbm_set_solid_scheme(fdlbm_ctx *c, int scheme) {
     return set_err(c, FDLBM_E_INVALID, "unknown solid scheme %d", scheme);
   if (scheme == FDLBM_SOLID_EULER && c->alpha_s > 0.5 / c->D)
     return set_err(c, FDLBM_E_INVALID, "alpha_s > 1/(2D) needs the Crank-Nicolson scheme");
+  if (scheme == FDLBM_SOLID_CN && c->coupling == FDLBM_COUPLING_EQ48)
+    return set_err(c, FDLBM_E_INVALID, "the Eq.(48) coupling needs the forward-Euler solid");
   c->solid_scheme = scheme;
   return FDLBM_OK;
 }
@@ -712,6 +717,16 @@ int fdlbm_set_reaction(fdlbm_ctx *c, const double *nu, const double *order, doub
   c->T_iso = T_iso;
   c->tol = tol;
   c->max_iter = max_iter;
+  return FDLBM_OK;
+}
+
+int fdlbm_set_solid_coupling(fdlbm_ctx *c, int mode) {
+  if (!c) return FDLBM_E_INVALID;
+  if (mode != FDLBM_COUPLING_FLUX && mode != FDLBM_COUPLING_EQ48)
+    return set_err(c, FDLBM_E_INVALID, "coupling must be FDLBM_COUPLING_FLUX or FDLBM_COUPLING_EQ48");
+  if (mode == FDLBM_COUPLING_EQ48 && c->solid_scheme != FDLBM_SOLID_EULER)
+    return set_err(c, FDLBM_E_INVALID, "the Eq.(48) coupling needs the forward-Euler solid");
+  c->coupling = mode;
   return FDLBM_OK;
 }
 
@@ -1425,6 +1440,7 @@ int fdlbm_batch_create(fdlbm_ctx *const *ctxs, int n, fdlbm_batch **out) {
     if (!c) return fail("null context");
     if (!c->initialized) return fail("every context needs initialised fields");
     if (c->solid_scheme == FDLBM_SOLID_CN) return fail("Crank-Nicolson solids are not batched");
+    if (c->coupling != FDLBM_COUPLING_FLUX) return fail("the Eq.(48) coupling is not batched");
     if (c->D != ctxs[0]->D || c->ns != ctxs[0]->ns || c->d.precision != ctxs[0]->d.precision ||
         c->stream != ctxs[0]->stream)
       return fail("contexts differ in lattice, species count, precision or stream");

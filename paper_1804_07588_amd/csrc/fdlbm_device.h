@@ -108,6 +108,8 @@ struct Params {
   int order[MAXS];
   int max_iter;
   int rate_area;                   // 1: rate scaled by the wall node's wetted area
+  int eq48;                        // 1: solid-gas coupling of Eq.(48) (else flux-matched)
+  real kap[MAXS];                  // (D+2) / (2 Pr_j): gas conductivity per tau1_j C_j T / M_j
   // flow
   real F[3];
   real rho_in[MAXS], T_in, p_in;

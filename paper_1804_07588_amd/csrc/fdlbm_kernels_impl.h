@@ -1229,8 +1229,38 @@ __device__ __forceinline__ void solid_pass(const Params<real> &p, const Bufs<rea
     if constexpr (MODE == 0 || MODE == 1) {
       const real h = MODE == 0 ? p.alpha_s : real(0.5) * p.alpha_s;
       real Tn = T + h * lap;
-      if (p.wall_mode == 0 && b.kind[nd] == KIND_WALL)
-        Tn += (-p.dH * b.wall_r[nd] - b.wall_dE[nd]) * p.invCs;
+      if (p.wall_mode == 0 && b.kind[nd] == KIND_WALL) {
+        real qg;
+        if (!p.eq48) {
+          qg = -b.wall_dE[nd];  // flux-matched: the energy the wall gave the gas
+        } else {
+          // Eq.(48): kappa_f (T^f - T^s) per gas face neighbour, kappa_f =
+          // sum_j (D+2) tau1_j C_j T / (2 M_j Pr_j) from the neighbour's
+          // moments of this step (the solid then runs after them)
+          qg = 0;
+          const int NRr = fr_count(D, p.ns);
+          const int c3[3] = {x, y, z}, lim[3] = {p.nx, p.ny, p.nz};
+#pragma unroll
+          for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int d = -1; d <= 1; d += 2) {
+              const int off = a == 0 ? d : (a == 1 ? d * HX : d * HX * HY);
+              if (sK[hc + off] != 0) continue;  // solid, or outside a closed axis
+              int q[3] = {c3[0], c3[1], c3[2]};
+              q[a] += d;
+              q[a] = q[a] < 0 ? q[a] + lim[a] : (q[a] >= lim[a] ? q[a] - lim[a] : q[a]);
+              const int ng = q[0] + p.nx * (q[1] + p.ny * q[2]);
+              if (!gaslike(b.kind[ng])) continue;
+              const real *fr = b.FR + (size_t)b.slot_of[ng] * NRr;
+              const real Tf = fr[fr_T(D)];
+              real kap = 0;
+              for (int j = 0; j < p.ns; ++j)
+                kap += p.kap[j] * fr[fr_tau1(D, j)] * fr[fr_rho(D, j)] * p.invM[j] * Tf * p.invM[j];
+              qg += kap * (Tf - T);
+            }
+        }
+        Tn += (-p.dH * b.wall_r[nd] + qg) * p.invCs;
+      }
       if constexpr (MODE == 0) Tout[nd] = Tn;
       else b.cn_rhs[nd] = Tn;
       bflux += (double)(h * p.C_s * bf);
@@ -1541,7 +1571,9 @@ inline hipError_t step_impl(const Params<real> &p, const Bufs<real, PT> &b, int 
     }
     mark(K_SOLID_ID, 1, s);
   };
-  if (two && li.n_solid > 0) solid(sw);
+  // the Eq.(48) coupling reads the gas moments of this step: its solid step
+  // runs after them, on the main stream
+  if (two && li.n_solid > 0 && !p.eq48) solid(sw);
   mark(K_MOMENTS_ID, 0, st);
   if constexpr (std::is_same_v<PT, __bf16>) {
     if (ggf > 0)
@@ -1561,9 +1593,8 @@ inline hipError_t step_impl(const Params<real> &p, const Bufs<real, PT> &b, int 
     // join: the step is complete on the main stream
     (void)hipEventRecord(li.ev_solid, sw);
     (void)hipStreamWaitEvent(st, li.ev_solid, 0);
-  } else if (li.n_solid > 0) {
-    solid(st);
   }
+  if ((!two || p.eq48) && li.n_solid > 0) solid(st);
   return hipGetLastError();
 }
 

@@ -37,7 +37,8 @@ EXPORTS = ["fdlbm_create", "fdlbm_destroy", "fdlbm_last_error", "fdlbm_set_geome
            "fdlbm_batch_last_error", "fdlbm_batch_workspace_bytes", "fdlbm_batch_bind_workspace",
            "fdlbm_batch_set_active", "fdlbm_batch_step", "fdlbm_batch_set_grid",
            "fdlbm_batch_get_grid", "fdlbm_batch_autotune", "fdlbm_batch_set_overlap",
-           "fdlbm_set_sync_check", "fdlbm_last_step", "fdlbm_observe_noalloc", "fdlbm_set_rate_scaling"]
+           "fdlbm_set_sync_check", "fdlbm_last_step", "fdlbm_observe_noalloc", "fdlbm_set_rate_scaling",
+           "fdlbm_set_solid_coupling"]
 BATCH_KINDS = ["wall_fast", "wall_slow", "gas_fast", "gas_slow", "collide", "solid"]
 
 
@@ -112,6 +113,7 @@ def lib() -> ct.CDLL:
         L.fdlbm_set_lj_transport.argtypes = [vp, dp, ct.c_double, ct.c_double, ct.c_double, ct.c_int, dp, dp]
         L.fdlbm_set_sync_check.argtypes = [vp, i64]
         L.fdlbm_set_rate_scaling.argtypes = [vp, ct.c_int]
+        L.fdlbm_set_solid_coupling.argtypes = [vp, ct.c_int]
         L.fdlbm_last_step.argtypes = [vp, ct.POINTER(i64)]
         ip = ct.POINTER(ct.c_int)
         L.fdlbm_batch_create.argtypes = [ct.POINTER(vp), ct.c_int, ct.POINTER(vp)]
@@ -186,6 +188,8 @@ class Sim:
         if so.get("scheme", 0):
             self._check(L.fdlbm_set_solid_scheme(h, int(so["scheme"])))
         self._check(L.fdlbm_set_solid(h, so["alpha_s"], so["C_s"], _d(tbc)))
+        if so.get("coupling", 0):
+            self._check(L.fdlbm_set_solid_coupling(h, int(so["coupling"])))
         rx = cfg["reaction"]
         nu, order = _arr(rx["nu"]), _arr(rx["order"])
         self._check(L.fdlbm_set_reaction(h, _d(nu), _d(order), rx["k0"], rx["ea"], rx["T_ref"],

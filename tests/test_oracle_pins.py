@@ -491,3 +491,62 @@ def test_wetted_area_of_a_staircase_sphere(r):
         Z += (solid & ~nb) * W19[i]
     ratio = (Z / (0.5 * T0)).sum() / (4 * np.pi * r * r)
     assert 1.18 < ratio < 1.23, ratio
+
+
+def test_eq48_coupling_one_step(oracle_lib):
+    """Sec. 5, Eq.(48) coupling option: after one step, a wall node's solid
+    temperature is T^s + alpha_s sum_solid faces (T^s_nb - T^s)
+    + [sum_gas faces kappa_f (T^f - T^s) - dH r] / C_s, with T^f the gas
+    node's temperature of the step and kappa_f = sum_j (D+2) tau1_j C_j T /
+    (2 M_j Pr_j) from the transport at that node (Eq.(7)-(8), (14)-(17));
+    checked at every wall node of a channel with a warm solid, to 1e-12."""
+    of = oracle_lib
+    cfg = W.with_changes(W.channel_c1(nx=8, ny=16, wall=3), init=dict(X=[0.7, 0.3]),
+                         solid=dict(coupling=1, T_bc=[np.nan] * 6))
+    cfg["species"]["Pr"] = 0.71
+    init = W.uniform_init(cfg)
+    ny, nx = 16, 8
+    y = np.repeat(np.arange(ny), nx)
+    init["Ts"] = T0 * (1.0 + 0.01 * np.cos(y) + 0.02 * (y < 8))
+    sim = of.OracleSim(cfg, init)
+    sim.step(1)
+    kind = sim.field(of.OF_KIND).reshape(ny, nx)
+    Ts1 = sim.field(of.OF_TS).reshape(ny, nx)
+    Tg = sim.field(of.OF_T).reshape(ny, nx)
+    rho = np.stack([sim.field(of.OF_RHO, j).reshape(ny, nx) for j in range(2)])
+    r = sim.field(of.OF_WALL_R).reshape(ny, nx)
+    Ts0 = init["Ts"].reshape(ny, nx)
+    a_s, C_s, dH = cfg["solid"]["alpha_s"], cfg["solid"]["C_s"], cfg["reaction"]["dH"]
+    M = np.asarray(cfg["species"]["M"])
+    errs = []
+    for yy, xx in np.argwhere(kind == 2):
+        lap, q = 0.0, 0.0
+        for dy, dx in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+            y2, x2 = yy + dy, (xx + dx) % nx
+            if not 0 <= y2 < ny:
+                continue
+            if kind[y2, x2] in (1, 2):
+                lap += Ts0[y2, x2] - Ts0[yy, xx]
+            else:
+                tau1, _ = sim.transport(rho[:, y2, x2], Tg[y2, x2])
+                kap = sum(4.0 * tau1[j] * rho[j, y2, x2] / M[j] * Tg[y2, x2] / (2 * M[j] * 0.71)
+                          for j in range(2))
+                q += kap * (Tg[y2, x2] - Ts0[yy, xx])
+        want = Ts0[yy, xx] + a_s * lap + (q - dH * r[yy, xx]) / C_s
+        errs.append(abs(Ts1[yy, xx] - want))
+    assert max(errs) < 1e-12 * T0
+    sim.close()
+
+
+def test_enthalpy_error_of_the_two_couplings(oracle_lib):
+    """Eq.(49)'s enthalpy-conservation error on the channel workload
+    (reactive walls, trace product): the flux-matched coupling keeps it at
+    rounding (below the paper's ~1e-5); the literal Eq.(48) coupling, where
+    the gas gains the diffusive wall's energy while the solid is credited
+    kappa_f (T^f - T^s), loses several per cent of the reaction heat."""
+    import test_oracle_physics as P
+    res0, heat0, _ = P.energy_residual(oracle_lib, W.channel_c1(), steps=300)
+    res1, heat1, _ = P.energy_residual(oracle_lib, W.with_changes(W.channel_c1(), solid=dict(coupling=1)),
+                                       steps=300)
+    assert abs(res0 / heat0) < 1e-6
+    assert abs(res1 / heat1) > 1e-2

@@ -582,3 +582,25 @@ def test_unstable_step_is_reported(oracle_lib, fd, prec):
     g.init_fields(init)
     assert g.last_step() == -1
     g.close()
+
+
+@pytest.mark.parametrize("prec", ["F64", "F32"])
+def test_eq48_coupling(oracle_lib, fd, prec):
+    """The Eq.(48) solid-gas coupling option (fdlbm_set_solid_coupling): the
+    wall node's solid temperature takes kappa_f (T^f - T^s) / C_s from each
+    gas face neighbour's moments of the step.  FP64 on the channel with a
+    solid warmer than the gas (heat flows through the coupling), FP32 on the
+    sphere pack."""
+    if prec == "F64":
+        cfg = W.with_changes(W.channel_c1(), init=dict(X=[0.7, 0.3]), solid=dict(coupling=1))
+        init = W.uniform_init(cfg)
+        init["Ts"] = init["Ts"] * 1.02
+        o, g = run_both(oracle_lib, fd, cfg, init, 300, fd.F64)
+        ok64(field_errors(o, g, fd, 2, 2))
+    else:
+        cfg = small_bed()
+        cfg["solid"]["coupling"] = 1
+        init = W.perturbed_init(cfg, 5, amp_u=0.005)
+        init["Ts"] = init["Ts"] * 1.01
+        o, g = run_both(oracle_lib, fd, cfg, init, 60, fd.F32)
+        ok32(field_errors(o, g, fd, 5, 3))
