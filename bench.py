@@ -105,23 +105,33 @@ def bed(n):
 
 
 def cpu_baseline(n, steps):
-    """The FP64 oracle (single thread) on a bed of edge n built the same way
-    (same sphere radius, porosity, chemistry and flow): setup excluded,
-    `steps` full time steps timed."""
+    """The FP64 oracle on a bed of edge n built the same way (same sphere
+    radius, porosity, chemistry and flow): setup excluded, timed full time
+    steps, once on every host thread the process may use (OpenMP over nodes;
+    OMP_NUM_THREADS if set, else the CPU count) over 3 * steps steps, once
+    on one thread over `steps` steps (the oracle's results do not depend on
+    the thread count)."""
     from oracle import oracle
     oracle.build(force=not os.path.exists(oracle.LIB_PATH))
     cfg, init, _ = bed(n)
-    sim = oracle.OracleSim(cfg, init)
-    t0 = time.perf_counter()
-    sim.step(steps)
-    dt = time.perf_counter() - t0
-    o = sim.observe()
     ns = len(cfg["species"]["M"])
-    val = o["n_gas"] * ns * steps / dt / 1e6
-    sim.close()
-    return dict(value=round(val, 4), unit="MLUPS*species", cores=1, kind="oracle",
-                sample=f"{steps} full step(s) of a {n}^3 bed of the same construction "
-                       f"({o['n_gas']} gas nodes), FP64, one thread, {dt:.1f} s")
+    threads = int(os.environ.get("OMP_NUM_THREADS", 0) or os.cpu_count() or 1)
+    res = {}
+    for nt, k in ((threads, 3 * steps), (1, steps)):
+        used = oracle.set_threads(nt)
+        sim = oracle.OracleSim(cfg, init)
+        t0 = time.perf_counter()
+        sim.step(k)
+        dt = time.perf_counter() - t0
+        o = sim.observe()
+        sim.close()
+        res[nt] = (o["n_gas"] * ns * k / dt / 1e6, used, k, dt, o["n_gas"])
+    v, used, k, dt, ng = res[threads]
+    v1, _, k1, dt1, _ = res[1]
+    return dict(value=round(v, 4), unit="MLUPS*species", cores=used, kind="oracle",
+                value_1thread=round(v1, 4),
+                sample=f"{k} full step(s) of a {n}^3 bed of the same construction ({ng} gas nodes), "
+                       f"FP64, {used} OpenMP threads, {dt:.1f} s; one thread: {k1} step(s), {dt1:.1f} s")
 
 
 def calib_copy(mib):

@@ -125,11 +125,16 @@ typedef struct {
   int32_t n_gas, n_wall, n_solid;
 } fdlbm_obs;
 
-/* Create a context (no device memory yet).  *out owned by the caller until
- * fdlbm_destroy.  Errors: FDLBM_E_INVALID on bad sizes or counts. */
+/* Create a context for one domain (no device memory yet): the lattice of
+ * Sec. 2 (D2Q9 of Eq.(2), or the D3Q19 extension), the grid of lattice
+ * units of Sec. 4.1 (one node per lattice spacing, one step per time step),
+ * the number of gas species of the mixture and the precision.  *out owned
+ * by the caller until fdlbm_destroy.  Errors: FDLBM_E_INVALID on bad sizes
+ * or counts. */
 int fdlbm_create(const fdlbm_desc *d, fdlbm_ctx **out);
 
-/* Release the context.  Does not free the caller's workspace. */
+/* Release the context (no step of the method).  Does not free the
+ * caller's workspace. */
 void fdlbm_destroy(fdlbm_ctx *ctx);
 
 /* Message of the last error on this context (static storage of ctx). */
@@ -248,8 +253,10 @@ int fdlbm_set_rate_scaling(fdlbm_ctx *ctx, int mode);
 int fdlbm_set_flow(fdlbm_ctx *ctx, const double *F3, const double *X_in, double p_in,
                    double T_in);
 
-/* Device bytes the caller must provide (depends on the geometry: valid after
- * fdlbm_set_geometry, else FDLBM_E_STATE). */
+/* Device bytes the caller must provide for the state of Sec. 4-5 (the
+ * populations of every gas species and wall node, their moments, the solid
+ * temperature; depends on the geometry: valid after fdlbm_set_geometry,
+ * else FDLBM_E_STATE). */
 int fdlbm_workspace_bytes(const fdlbm_ctx *ctx, size_t *bytes);
 
 /* Bind the caller's device buffer (>= fdlbm_workspace_bytes, 256-byte
@@ -299,7 +306,7 @@ int fdlbm_set_sync_check(fdlbm_ctx *ctx, int64_t every);
  * record too.  FDLBM_E_STATE before fdlbm_init_fields. */
 int fdlbm_last_step(fdlbm_ctx *ctx, int64_t *step);
 
-/* Wait for the stream. */
+/* Wait for the stream (no step of the method). */
 int fdlbm_sync(fdlbm_ctx *ctx);
 
 /* Synchronise and reduce the observables (FP64, deterministic order): the
@@ -335,11 +342,23 @@ int fdlbm_observe_noalloc(fdlbm_ctx *ctx, fdlbm_obs *out);
 int fdlbm_residual(fdlbm_ctx *ctx, double *r5);
 
 /* Copy a field into dst_host (double): n values, or Q*n for FDLBM_FIELD_POP.
- * RHO/U/T are the moments of f of the last step at gas nodes (the wall state
- * at wall nodes, 0 elsewhere); valid after at least one step. */
+ * RHO/U/T are the moments of the last step at gas nodes -- species density
+ * and mixture velocity and temperature of Eq.(3), (5) with Eq.(25)'s
+ * half-source terms (before the correction sources' energy) -- and the
+ * wall state (rho_w of Eq.(39)-(41), U_w = 0, T_w) at wall nodes, 0
+ * elsewhere; TS the solid temperature of Eq.(45)-(48); POP the stored
+ * populations g of Eq.(23) (post-collision, the next step streams them);
+ * WALL_R / WALL_DE the rate of Eq.(50) and the energy of the diffusive
+ * exchange per wall node.  Valid after at least one step.  FDLBM_E_INVALID
+ * for an unknown field or component. */
 int fdlbm_get_field(fdlbm_ctx *ctx, int field, int comp, double *dst_host);
 
-/* Checkpoint: bytes needed, save to / restore from a host buffer (bitwise). */
+/* Checkpoint (no step of the method): bytes needed, save to / restore from
+ * a host buffer (bitwise: the whole device state of the step of
+ * fdlbm_step, populations of Eq.(23), solid temperature, cumulative
+ * counters of Eq.(42)/(49), step count).  host_buf is the caller's; load
+ * requires a context with the same geometry and precision (else
+ * FDLBM_E_INVALID) and resets the stability record. */
 int fdlbm_state_bytes(const fdlbm_ctx *ctx, size_t *bytes);
 int fdlbm_save_state(fdlbm_ctx *ctx, void *host_buf, size_t bytes);
 int fdlbm_load_state(fdlbm_ctx *ctx, const void *host_buf, size_t bytes);
@@ -367,8 +386,8 @@ int fdlbm_set_overlap(fdlbm_ctx *ctx, int enable);
 int fdlbm_set_profiling(fdlbm_ctx *ctx, int enable);
 int fdlbm_kernel_times(fdlbm_ctx *ctx, double *avg_ms, int64_t *launches);
 
-/* Node counts after fdlbm_set_geometry: gas (incl. inlet/outlet), wall,
- * solid (incl. wall). */
+/* Node counts after fdlbm_set_geometry (Sec. 4.3: wall nodes are the
+ * first solid nodes): gas (incl. inlet/outlet), wall, solid (incl. wall). */
 int fdlbm_counts(const fdlbm_ctx *ctx, int64_t *n_gas, int64_t *n_wall, int64_t *n_solid);
 
 /* ------------------------------------------------------------------------

@@ -17,6 +17,9 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define MAXS ORACLE_MAXS
 #define MAXQ 19
@@ -63,6 +66,7 @@ struct oracle_sim {
   /* per-node fields of the current step */
   double *rho, *u, *T, *tau1, *tau2, *Jf, *Uc;
   double *wall_r, *wall_dE;
+  double *acc_node; /* per-node terms of the cumulative sums, added in node order */
   double *wall_u;   /* wall velocity U_w per node, 3 rows (NULL: walls at rest) */
   int literal_eq6;  /* 1: f* at the mixture temperature as printed in Eq.(6) */
   int rate_area;    /* 1: rate scaled by the wall node's wetted area (reading) */
@@ -457,6 +461,7 @@ oracle_sim *oracle_create(int lattice, int nx, int ny, int nz, const int *period
   s->Uc = (double *)calloc((size_t)3 * s->n, sizeof(double));
   s->wall_r = (double *)calloc(s->n, sizeof(double));
   s->wall_dE = (double *)calloc(s->n, sizeof(double));
+  s->acc_node = (double *)calloc(s->n, sizeof(double));
   s->kind = (uint8_t *)calloc(s->n, 1);
   if (!s->G || !s->Gn || !s->gpre || !s->Ts || !s->Tsn || !s->rho || !s->u || !s->T ||
       !s->tau1 || !s->tau2 || !s->Jf || !s->Uc || !s->wall_r || !s->wall_dE || !s->kind) {
@@ -497,6 +502,7 @@ void oracle_destroy(oracle_sim *s) {
   free(s->Uc);
   free(s->wall_r);
   free(s->wall_u);
+  free(s->acc_node);
   free(s->wall_dE);
   free(s->kind);
   free(s);
@@ -834,6 +840,7 @@ int oracle_init_fields(oracle_sim *s, const double *rho, const double *u, const 
 
 /* 1. streaming into every destination, Eq.(33)-(36) */
 static void stream_all(oracle_sim *s) {
+#pragma omp parallel for schedule(static)
   for (int x = 0; x < s->n; ++x) {
     if (gaslike(s, x))
       for (int j = 0; j < s->ns; ++j) *pop(s, s->gpre, j, 0, x) = *pop(s, s->G, j, 0, x);
@@ -856,6 +863,7 @@ static double rate(const oracle_sim *s, const double *rhow, double Tw) {
 /* 2. reactive diffusive wall, Eq.(37)-(41), P:wall-on-solid-node, Eq.(42) */
 static void wall_bc(oracle_sim *s) {
   int Q = s->Q, ns = s->ns;
+#pragma omp parallel for schedule(static)
   for (int w = 0; w < s->n; ++w) {
     if (s->kind[w] != K_WALL) continue;
     double Tw = wall_temperature(s, w);
@@ -949,6 +957,7 @@ static void wall_bc(oracle_sim *s) {
 /* 3. moments and transport at gas nodes, Eq.(3), (5), (7)-(8), (11), (14)-(17), (25) */
 static void moments(oracle_sim *s) {
   int Q = s->Q, ns = s->ns, n = s->n, D = s->D;
+#pragma omp parallel for schedule(static)
   for (int x = 0; x < n; ++x) {
     if (!gaslike(s, x)) continue;
     double rho[MAXS], Jg[MAXS][3], E = 0.0, rhot = 0.0, C = 0.0;
@@ -1061,7 +1070,9 @@ static double Rdev(const oracle_sim *s, int j, const nbstate *v, int a, int b) {
 /* 4-5. sources, temperature of f, equilibria and the collision, Eq.(24) */
 static void collide(oracle_sim *s) {
   int Q = s->Q, ns = s->ns, n = s->n, D = s->D;
+#pragma omp parallel for schedule(static)
   for (int x = 0; x < n; ++x) {
+    s->acc_node[x] = 0.0;
     if (!gaslike(s, x)) continue;
     nbstate me, nbp[3], nbm[3];
     get_nb(s, x, x, &me);
@@ -1077,7 +1088,7 @@ static void collide(oracle_sim *s) {
       rhot += me.rho[j];
     }
     /* work of the body force this step, rho u.F (half the trace of its source) */
-    s->work += rhot * (me.u[0] * s->F[0] + me.u[1] * s->F[1] + me.u[2] * s->F[2]);
+    s->acc_node[x] = rhot * (me.u[0] * s->F[0] + me.u[1] * s->F[1] + me.u[2] * s->F[2]);
     double S[MAXS][MAXQ];
     double esum = 0.0;
     for (int j = 0; j < ns; ++j) {
@@ -1205,6 +1216,7 @@ static void collide(oracle_sim *s) {
       }
     }
   }
+  for (int x = 0; x < n; ++x) s->work += s->acc_node[x];  /* in node order */
 }
 
 /* 6. solid heat step, Eq.(45)-(47), and the interface source.
@@ -1215,7 +1227,9 @@ static void collide(oracle_sim *s) {
  * (or adiabatic where T_bc is NaN). */
 static void solid(oracle_sim *s) {
   int n = s->n, D = s->D;
+#pragma omp parallel for schedule(static)
   for (int x = 0; x < n; ++x) {
+    s->acc_node[x] = 0.0;
     if (!(s->kind[x] == K_SOLID || s->kind[x] == K_WALL)) {
       s->Tsn[x] = s->Ts[x];
       continue;
@@ -1235,7 +1249,7 @@ static void solid(oracle_sim *s) {
         }
       }
     double Tn = T + s->alpha_s * lap;
-    s->bheat += s->alpha_s * s->C_s * bflux;
+    s->acc_node[x] = s->alpha_s * s->C_s * bflux;
     /* isothermal walls (prior art) exchange nothing with the solid */
     if (s->kind[x] == K_WALL && s->wall_mode == 0) {
       if (!s->eq48) {
@@ -1264,6 +1278,7 @@ static void solid(oracle_sim *s) {
     }
     s->Tsn[x] = Tn;
   }
+  for (int x = 0; x < n; ++x) s->bheat += s->acc_node[x];  /* in node order */
 }
 
 /* 6b. Crank-Nicolson variant of the solid step (Sec. 5, recommended for
@@ -1305,19 +1320,23 @@ static void solid_cn(oracle_sim *s) {
   double *rhs = malloc((size_t)n * sizeof(double));
   double *X = malloc((size_t)n * sizeof(double));
   double *Y = malloc((size_t)n * sizeof(double));
+#pragma omp parallel for schedule(static)
   for (int x = 0; x < n; ++x) {
     X[x] = s->Ts[x];
     rhs[x] = s->Ts[x];
+    s->acc_node[x] = 0.0;
     if (!(s->kind[x] == K_SOLID || s->kind[x] == K_WALL)) continue;
     double bf, nbs, bcs;
     int cnt;
     double lap = solid_lap(s, s->Ts, x, &bf, &cnt, &nbs, &bcs);
     rhs[x] = s->Ts[x] + 0.5 * a * lap;
     if (s->kind[x] == K_WALL && s->wall_mode == 0) rhs[x] += (-s->dH * s->wall_r[x] - s->wall_dE[x]) / s->C_s;
-    s->bheat += 0.5 * a * s->C_s * bf;
+    s->acc_node[x] = 0.5 * a * s->C_s * bf;
   }
+  for (int x = 0; x < n; ++x) s->bheat += s->acc_node[x];
   for (int it = 0; it < 1000000; ++it) {
     double dmax = 0.0;
+#pragma omp parallel for schedule(static) reduction(max : dmax)
     for (int x = 0; x < n; ++x) {
       Y[x] = X[x];
       if (!(s->kind[x] == K_SOLID || s->kind[x] == K_WALL)) continue;
@@ -1333,14 +1352,17 @@ static void solid_cn(oracle_sim *s) {
     Y = t;
     if (dmax <= 2.5e-16) break; /* a couple of ulps: the fixed point in FP64 */
   }
+#pragma omp parallel for schedule(static)
   for (int x = 0; x < n; ++x) {
     s->Tsn[x] = X[x];
+    s->acc_node[x] = 0.0;
     if (!(s->kind[x] == K_SOLID || s->kind[x] == K_WALL)) continue;
     double bf, nbs, bcs;
     int cnt;
     (void)solid_lap(s, X, x, &bf, &cnt, &nbs, &bcs);
-    s->bheat += 0.5 * a * s->C_s * bf;
+    s->acc_node[x] = 0.5 * a * s->C_s * bf;
   }
+  for (int x = 0; x < n; ++x) s->bheat += s->acc_node[x];
   free(rhs);
   free(X);
   free(Y);
@@ -1519,6 +1541,18 @@ int oracle_set_literal_eq6(oracle_sim *s, int on) {
   if (!s) return fail(s, "null simulation");
   s->literal_eq6 = on != 0;
   return 0;
+}
+
+/* Threads of the node loops (OpenMP; every sum runs in node order, so the
+ * results do not depend on the count).  Returns the count in use. */
+int oracle_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
 }
 
 /* Solid-gas coupling at wall nodes: 0 (default) flux-matched, 1 Eq.(48) */

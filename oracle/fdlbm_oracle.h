@@ -7,7 +7,8 @@
  * HIP library) never links, loads or calls it, and it shares no code, header or
  * table with the product.
  *
- * Everything is double precision, plain nested loops, one thread.  Equation
+ * Everything is double precision, plain nested loops over nodes (split over
+ * OpenMP threads where the nodes are independent; every sum in node order).  Equation
  * numbers refer to the paper in the order of its display equations:
  *   Eq.(1)  two-step BGK kinetic equation          Eq.(2)  species lattice velocities
  *   Eq.(4)  mixture equilibrium                     Eq.(5)  mixture moments
@@ -85,6 +86,8 @@ int oracle_observe(oracle_sim *s, oracle_obs *out);
 enum { OF_RHO = 0, OF_U = 1, OF_T = 2, OF_TS = 3, OF_POP = 4, OF_KIND = 5, OF_WALL_R = 6,
        OF_WALL_DE = 7 };
 int oracle_get_field(oracle_sim *s, int field, int comp, double *dst);
+/* threads of the node loops (<= 0: keep); returns the count in use */
+int oracle_set_threads(int n);
 /* solid-gas coupling at wall nodes: 0 flux-matched (default), 1 Eq.(48) */
 int oracle_set_coupling(oracle_sim *s, int eq48);
 /* reaction rate per wall node (0, default) or per unit wetted area (1) */

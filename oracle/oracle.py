@@ -22,7 +22,7 @@ OF_RHO, OF_U, OF_T, OF_TS, OF_POP, OF_KIND, OF_WALL_R, OF_WALL_DE = range(8)
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc into oracle/liboracle.so."""
     if force or not os.path.exists(LIB_PATH):
-        cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall", "-o", LIB_PATH + ".tmp",
+        cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", LIB_PATH + ".tmp",
                *SOURCES, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(LIB_PATH + ".tmp", LIB_PATH)
@@ -78,6 +78,7 @@ def lib():
         L.oracle_set_literal_eq6.argtypes = [ct.c_void_p, ct.c_int]
         L.oracle_set_rate_area.argtypes = [ct.c_void_p, ct.c_int]
         L.oracle_set_coupling.argtypes = [ct.c_void_p, ct.c_int]
+        L.oracle_set_threads.argtypes = [ct.c_int]
         L.oracle_init_fields.argtypes = [ct.c_void_p, dp, dp, dp, dp]
         L.oracle_step.argtypes = [ct.c_void_p, ct.c_int64]
         L.oracle_observe.argtypes = [ct.c_void_p, ct.POINTER(Obs)]
@@ -105,6 +106,11 @@ def _arr(x) -> np.ndarray:
 # ---------------------------------------------------------------------------
 # building blocks
 # ---------------------------------------------------------------------------
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's node loops (results do not depend on it)."""
+    return int(lib().oracle_set_threads(int(n)))
+
 
 def velocities(lattice: int) -> np.ndarray:
     c = (ct.c_int * 57)()

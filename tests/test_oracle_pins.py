@@ -4,6 +4,8 @@ of total momentum with unequal masses and diffusivities), the wall-density
 fixed point and the rate law at the reactive wall (closed form of the
 first step at every wall node of a sphere pack, corners included).  CPU
 only."""
+import os
+
 import numpy as np
 import pytest
 
@@ -550,3 +552,29 @@ def test_enthalpy_error_of_the_two_couplings(oracle_lib):
                                        steps=300)
     assert abs(res0 / heat0) < 1e-6
     assert abs(res1 / heat1) > 1e-2
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_oracle_results_do_not_depend_on_threads(oracle_lib, scheme):
+    """The oracle's node loops run on OpenMP threads, every sum in node
+    order: a sphere pack with reaction, body force, inlet/outlet and the
+    Euler or Crank-Nicolson solid gives bitwise the same populations, solid
+    temperatures and cumulative counters with one thread and with four."""
+    of = oracle_lib
+    mask, _ = W.sphere_pack_mask(16, radius=3.0, porosity=0.6, seed=3, buffer=4)
+    cfg = W.packed_bed(mask=mask, k0=1e-3, force=1e-5)
+    cfg["solid"].update(scheme=scheme, alpha_s=0.4 if scheme else 0.03)
+    init = W.perturbed_init(cfg, 4, amp_u=0.005)
+    out = []
+    for nt in (1, 4):
+        of.set_threads(nt)
+        sim = of.OracleSim(cfg, init)
+        sim.step(6)
+        out.append(([sim.field(of.OF_POP, j) for j in range(5)], sim.field(of.OF_TS), sim.observe()))
+        sim.close()
+    of.set_threads(os.cpu_count() or 1)
+    for a, b in zip(out[0][0], out[1][0]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(out[0][1], out[1][1])
+    for k in ("moles_reacted", "work_body", "heat_boundary", "e_gas", "e_solid"):
+        assert out[0][2][k] == out[1][2][k], k
