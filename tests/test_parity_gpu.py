@@ -9,11 +9,10 @@ Tolerances (measured maxima in the record named by FDLBM_PARITY_RECORD,
 see conftest.py):
 * FP64: 1e-12 on densities, populations, temperatures and the wall rate
   (the two sides sum in different orders and the GPU uses closed forms
-  where the oracle inverts matrices).  Velocity relative to max|u|: 2e-11 --
-  the flows are slow (max|u| down to 1e-4 of the populations' scale), and
-  the same differences are below 1e-13 of the sound speed.  Perturbed
-  transients that amplify rounding differences (stated at their tests):
-  1e-11.
+  where the oracle inverts matrices; measured at most 3e-14).  Velocity
+  relative to max|u|: 2e-12 -- the flows are slow (max|u| down to 1e-4 of
+  the populations' scale; measured at most 8e-13), and the same differences
+  are below 2e-15 of the sound speed.
 * FP32: 1e-5 on densities, populations and temperatures.  The wall rate is
   quadratic in two FP32 wall densities: 2e-5.  Velocity relative to max|u|:
   5e-5 on the beds (max|u| about 5e-3), and the same differences below
@@ -31,8 +30,7 @@ pytestmark = pytest.mark.gpu
 
 T0 = 1.0 / 3.0
 TOL64 = 1e-12
-TOL64_U = 2e-11
-TOL64_AMP = 1e-11
+TOL64_U = 2e-12
 TOL32 = 1e-5
 TOL32_RATE = 2e-5
 TOL32_U = 5e-5
@@ -162,9 +160,7 @@ def test_c1_interpolated_species_fp64(oracle_lib, fd):
     cfg = W.with_changes(W.channel_c1(), init=dict(X=[0.7, 0.3]))
     cfg["species"].update(M=[1.0, 4.0], mu0=[0.1, 0.2])
     o, g = run_both(oracle_lib, fd, cfg, W.perturbed_init(cfg, 5), 300, fd.F64)
-    # a perturbed binary transient over 300 steps amplifies rounding
-    # differences (measured 3.1e-12 on the populations)
-    ok64(field_errors(o, g, fd, 2, 2), TOL64_AMP)
+    ok64(field_errors(o, g, fd, 2, 2))
 
 
 def test_porous_2d_three_species_fp64(oracle_lib, fd):
@@ -202,21 +198,21 @@ def test_bed_3d_species_prandtl(oracle_lib, fd, prec):
         ok32(field_errors(o, g, fd, 5, 3))
 
 
-def test_crank_nicolson_solid_fp64(oracle_lib, fd):
+@pytest.mark.parametrize("prec", ["F64", "F32"])
+def test_crank_nicolson_solid_channel(oracle_lib, fd, prec):
     """Crank-Nicolson solid (fdlbm_set_solid_scheme) at alpha_s = 1.5, six
-    times the forward-Euler limit, in the channel with Dirichlet outer faces
-    and fast reactive walls.  (This perturbed binary case amplifies small
-    differences by about 10^3 over 200 steps -- with the forward-Euler solid
-    too -- so an FP32 run drifts to 2e-4 from FP64 there; FP32 is checked on
-    the bed below.)"""
+    times the forward-Euler limit, in the channel with Dirichlet outer faces,
+    fast reactive walls and a perturbed binary mixture."""
     cfg = W.with_changes(W.channel_c1(), init=dict(X=[0.7, 0.3]), reaction=dict(k0=1e-2))
     cfg["solid"].update(scheme=1, alpha_s=1.5)
     init = W.perturbed_init(cfg, 8)
-    o, g = run_both(oracle_lib, fd, cfg, init, 200, fd.F64)
-    # the amplifying transient described above: measured 2.0e-12
-    ok64(field_errors(o, g, fd, 2, 2), TOL64_AMP)
-    oo, og = o.observe(), g.observe()
-    assert abs(og["heat_boundary"] - oo["heat_boundary"]) <= 1e-10 * abs(oo["heat_boundary"])
+    o, g = run_both(oracle_lib, fd, cfg, init, 200, getattr(fd, prec))
+    if prec == "F64":
+        ok64(field_errors(o, g, fd, 2, 2))
+        oo, og = o.observe(), g.observe()
+        assert abs(og["heat_boundary"] - oo["heat_boundary"]) <= 1e-10 * abs(oo["heat_boundary"])
+    else:
+        ok32(field_errors(o, g, fd, 2, 2), tol_u=1e-3, tol_ucs=3e-6)
 
 
 def test_crank_nicolson_solid_bed_fp32(oracle_lib, fd):
