@@ -6,6 +6,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -44,6 +45,7 @@ struct fdlbm_unet {
   size_t total = 0;
   // workspace offsets (bytes)
   size_t o_p = 0, o_g = 0, o_m = 0, o_v = 0, o_w = 0, o_wt = 0, o_loss = 0;
+  size_t o_red = 0;  // per-block partials of the fixed-order reductions
   size_t o_in = 0, o_a[NL]{}, o_p1 = 0, o_p2 = 0, o_c1 = 0, o_c2 = 0, o_out = 0;
   size_t o_gout = 0, o_ga[NL]{}, o_gc1 = 0, o_gc2 = 0, o_gp1 = 0, o_gp2 = 0, o_gb = 0;
   int64_t t_adam = 0;
@@ -108,6 +110,18 @@ int fdlbm_unet_create(int R, int n_max, int cin, int nout, void *hip_stream, fdl
   u->o_w = take(bw * 2);
   u->o_wt = take(bw * 2);
   u->o_loss = take(8);
+  {
+    // the largest partial set of any reduction (they run one after another
+    // on the network's stream and share the region)
+    size_t red = (size_t)unet::LOSS_BLOCKS * 8;
+    for (int l = 0; l < NL; ++l) {
+      const Layer &L = LAYERS[l];
+      const int Rl = R >> L.level;
+      red = std::max(red, (size_t)unet::wgrad_chunks(Rl, n_max) * wcount(L) * 4);
+      red = std::max(red, (size_t)unet::act_bwd_blocks(npos(u, L.level, n_max) * L.co, L.co) * L.co * 4);
+    }
+    u->o_red = take(red);
+  }
   u->o_in = take(npos(u, 0, n) * CP * 2);
   for (int l = 0; l < NL - 1; ++l) u->o_a[l] = take(npos(u, LAYERS[l].level, n) * LAYERS[l].co * 2);
   u->o_p1 = take(npos(u, 1, n) * C1 * 2);
@@ -244,8 +258,10 @@ static int backward(fdlbm_unet *u, int n) {
   auto layer_bwd = [&](int l, const float *g, const __bf16 *y, const __bf16 *in, float *gin) -> int {
     const Layer &L = LAYERS[l];
     const int Rl = R >> L.level;
-    UCHK(u, unet::act_bwd(g, L.relu ? y : nullptr, npos(u, L.level, n) * L.co, L.co, gb, G + u->boff[l], st));
-    UCHK(u, unet::wgrad(gb, L.co, in, L.ci, Rl, n, G + u->woff[l], st));
+    float *part = at<float>(u, u->o_red);
+    UCHK(u, unet::act_bwd(g, L.relu ? y : nullptr, npos(u, L.level, n) * L.co, L.co, gb, G + u->boff[l], part,
+                          st));
+    UCHK(u, unet::wgrad(gb, L.co, in, L.ci, Rl, n, G + u->woff[l], part, st));
     if (gin)
       UCHK(u, unet::conv(gb, L.co, at<__bf16>(u, u->o_wt) + u->bwoff[l], nullptr, L.ci, Rl, n, 1, 0, gin, st));
     return FDLBM_OK;
@@ -275,7 +291,7 @@ static int loss_grad(fdlbm_unet *u, const float *t, const float *w, int n, doubl
   if (!(wsum > 0)) return uerr(u, FDLBM_E_INVALID, "the weight sum must be positive");
   UCHK(u, hipMemsetAsync(u->ws + u->o_loss, 0, 8, u->stream));
   UCHK(u, unet::loss(at<float>(u, u->o_out), CP, t, w, u->nout, npos(u, 0, n), 1.0 / wsum,
-                     at<float>(u, u->o_gout), at<double>(u, u->o_loss), u->stream));
+                     at<float>(u, u->o_gout), at<double>(u, u->o_loss), at<double>(u, u->o_red), u->stream));
   if (loss) {
     UCHK(u, hipMemcpyAsync(loss, u->ws + u->o_loss, 8, hipMemcpyDeviceToHost, u->stream));
     UCHK(u, hipStreamSynchronize(u->stream));

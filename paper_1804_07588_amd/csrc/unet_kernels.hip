@@ -118,12 +118,16 @@ __global__ void __launch_bounds__(TPB) k_conv(const __bf16 *__restrict__ X, int 
 }
 
 // ---------------------------------------------------------------------------
-// weight gradient: gW[co][tap][ci] += sum_s gY[s][co] X[s + off(tap)][ci].
-// Grid (27 taps, chunks of WG_CH positions, groups of 16 output tiles of
-// 16 x 16).  Per step of 32 positions the workgroup stages gY and the shifted
-// X rows in LDS; wave w of group g owns tiles 16 g + w + 4 t, t < 4.
+// weight gradient, one partial per chunk of positions:
+// gWp[chunk][co][tap][ci] = sum over the chunk's s of gY[s][co] X[s + off(tap)][ci]
+// (k_colsum then adds the chunks in a fixed order, so the result does not
+// depend on the order in which workgroups run).
+// Grid (27 taps, chunks of L positions, groups of 16 output tiles of
+// 16 x 16).  Per step of WG_K positions the workgroup stages gY and the
+// shifted X rows in LDS; wave w of group g owns tiles 16 g + w + 4 t, t < 4.
 // ---------------------------------------------------------------------------
-constexpr int WG_CH = 2048;  // positions per workgroup
+constexpr int WG_CH = 2048;  // positions per workgroup, at least
+constexpr int WG_NC = 64;    // chunks per launch, at most
 constexpr int WG_MAXT = 4;   // tiles per wave
 constexpr int WG_MAXC = 224; // largest channel count staged
 
@@ -131,8 +135,8 @@ constexpr int WG_K = 64;              // positions staged per step
 constexpr int WG_LD = WG_K + 8;       // LDS row stride (bf16): 16-byte aligned rows
 
 __global__ void __launch_bounds__(TPB) k_wgrad(const __bf16 *__restrict__ GY, int Co,
-                                               const __bf16 *__restrict__ X, int Ci, int R, int S,
-                                               float *__restrict__ GW) {
+                                               const __bf16 *__restrict__ X, int Ci, int R, int S, int L,
+                                               float *__restrict__ GWp) {
   // transposed tiles [channel][WG_K positions], so a fragment's 8
   // consecutive positions are one 16-byte LDS read; staged with 16-byte
   // global loads (8 channels of one position) by threads that walk the
@@ -148,7 +152,7 @@ __global__ void __launch_bounds__(TPB) k_wgrad(const __bf16 *__restrict__ GY, in
   f32x4 acc[WG_MAXT];
 #pragma unroll
   for (int t = 0; t < WG_MAXT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int p0 = blockIdx.y * WG_CH, p1 = min(S, p0 + WG_CH);
+  const int p0 = blockIdx.y * L, p1 = min(S, p0 + L);
   const int r = (int)threadIdx.x % WG_K;  // this thread's staged position
   for (int sb = p0; sb < p1; sb += WG_K) {
     __syncthreads();
@@ -190,7 +194,7 @@ __global__ void __launch_bounds__(TPB) k_wgrad(const __bf16 *__restrict__ GY, in
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int co = ct * 16 + 4 * kq + i, ci = it * 16 + m;
-        atomicAdd(&GW[((size_t)co * 27 + tap) * Ci + ci], acc[t][i]);
+        GWp[(size_t)blockIdx.y * Co * 27 * Ci + ((size_t)co * 27 + tap) * Ci + ci] = acc[t][i];
       }
     }
   }
@@ -200,56 +204,66 @@ __global__ void __launch_bounds__(TPB) k_wgrad(const __bf16 *__restrict__ GY, in
 // elementwise and reductions
 // ---------------------------------------------------------------------------
 // bf16 gradient of a pre-activation from the f32 gradient of the layer
-// output (ReLU mask from the stored output y when y is given) and the bias
-// gradient (sum over positions).  A thread moves 8 channels of a position
-// per element group (C % 8 == 0, host-checked); its channel group advances
-// by TPB mod C/8 per group, and when that is 0 (C/8 divides TPB) the thread
-// sums its channels in registers and adds them to the block's LDS sums once,
-// else per group.  One atomic per channel and block into gbias.
+// output (ReLU mask from the stored output y when y is given) and this
+// block's share of the bias gradient (sum over positions).  C % 8 == 0
+// (host-checked); thread t < (TPB / C8) C8 always moves channel group
+// t % C8 (8 channels) of positions t / C8 + k TPB / C8 of the block's range,
+// adds them in position order, and the block adds its threads' sums in
+// thread order into part[block][C]; k_colsum adds the blocks in order.
 __global__ void __launch_bounds__(TPB) k_act_bwd(const float *__restrict__ g, const __bf16 *__restrict__ y,
-                                                 size_t n8, int C, __bf16 *__restrict__ gb,
-                                                 float *__restrict__ gbias) {
-  __shared__ float sb[WG_MAXC];
-  for (int c = threadIdx.x; c < C; c += TPB) sb[c] = 0.0f;
-  __syncthreads();
-  const int C8 = C / 8;
-  const size_t per = (size_t)TPB * 16;
-  const size_t e0 = (size_t)blockIdx.x * per;
-  const int step = TPB % C8;
-  int cg = (int)((e0 + threadIdx.x) % (size_t)C8);
+                                                 size_t npos, int C, int pos_per_block, __bf16 *__restrict__ gb,
+                                                 float *__restrict__ part) {
+  __shared__ float sb[TPB][8];
+  const int C8 = C / 8, per_round = TPB / C8;
+  const int cg = (int)threadIdx.x % C8, q = (int)threadIdx.x / C8;
   float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  for (size_t e = e0 + threadIdx.x; e < e0 + per && e < n8; e += TPB) {
-    const f32x4 v0 = *reinterpret_cast<const f32x4 *>(g + 8 * e);
-    const f32x4 v1 = *reinterpret_cast<const f32x4 *>(g + 8 * e + 4);
-    float v[8] = {v0[0], v0[1], v0[2], v0[3], v1[0], v1[1], v1[2], v1[3]};
-    if (y) {
-      const bf16x8 yy = *reinterpret_cast<const bf16x8 *>(y + 8 * e);
+  if (q < per_round) {
+    const size_t s0 = (size_t)blockIdx.x * pos_per_block;
+    const size_t s1 = min(npos, s0 + (size_t)pos_per_block);
+    for (size_t s = s0 + q; s < s1; s += per_round) {
+      const size_t e = s * C8 + cg;
+      const f32x4 v0 = *reinterpret_cast<const f32x4 *>(g + 8 * e);
+      const f32x4 v1 = *reinterpret_cast<const f32x4 *>(g + 8 * e + 4);
+      float v[8] = {v0[0], v0[1], v0[2], v0[3], v1[0], v1[1], v1[2], v1[3]};
+      if (y) {
+        const bf16x8 yy = *reinterpret_cast<const bf16x8 *>(y + 8 * e);
 #pragma unroll
-      for (int i = 0; i < 8; ++i)
-        if (!((float)yy[i] > 0.0f)) v[i] = 0.0f;
-    }
-    bf16x8 o;
+        for (int i = 0; i < 8; ++i)
+          if (!((float)yy[i] > 0.0f)) v[i] = 0.0f;
+      }
+      bf16x8 o;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) o[i] = (__bf16)v[i];
-    *reinterpret_cast<bf16x8 *>(gb + 8 * e) = o;
-    if (step == 0) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) acc[i] += v[i];
-    } else {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) atomicAdd(&sb[8 * cg + i], v[i]);
-      cg += step;
-      if (cg >= C8) cg -= C8;
+      for (int i = 0; i < 8; ++i) {
+        o[i] = (__bf16)v[i];
+        acc[i] += v[i];
+      }
+      *reinterpret_cast<bf16x8 *>(gb + 8 * e) = o;
     }
   }
-  if (step == 0) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
-      if (acc[i] != 0.0f) atomicAdd(&sb[8 * cg + i], acc[i]);
-  }
+  for (int i = 0; i < 8; ++i) sb[threadIdx.x][i] = acc[i];
   __syncthreads();
-  for (int k = threadIdx.x; k < C; k += TPB)
-    if (sb[k] != 0.0f) atomicAdd(&gbias[k], sb[k]);
+  for (int c = threadIdx.x; c < C; c += TPB) {
+    float sum = 0.0f;
+    for (int k = 0; k < per_round; ++k) sum += sb[k * C8 + c / 8][c % 8];
+    part[(size_t)blockIdx.x * C + c] = sum;
+  }
+}
+
+// out[col] = sum over rows r of P[r][col], rows added in the fixed order
+// ((r = 0, 4, 8, ...) + (1, 5, ...)) + ... : 64 columns per workgroup, four
+// row classes per column, combined in class order
+__global__ void __launch_bounds__(TPB) k_colsum(const float *__restrict__ P, int nrow, size_t ncol,
+                                                float *__restrict__ out) {
+  __shared__ float sh[4][64];
+  const int lc = (int)threadIdx.x % 64, cls = (int)threadIdx.x / 64;
+  const size_t col = (size_t)blockIdx.x * 64 + lc;
+  float sum = 0.0f;
+  if (col < ncol)
+    for (int r = cls; r < nrow; r += 4) sum += P[(size_t)r * ncol + col];
+  sh[cls][lc] = sum;
+  __syncthreads();
+  if (cls == 0 && col < ncol) out[col] = ((sh[0][lc] + sh[1][lc]) + sh[2][lc]) + sh[3][lc];
 }
 
 // 2x2x2 average pooling, edge R -> R/2
@@ -357,10 +371,11 @@ __global__ void k_input(const float *__restrict__ in, int cin, int Cp, size_t n,
 }
 
 // weighted squared error: out f32 [s][Cp] (first nt used), target and weight
-// f32 [s][nt]; loss = sum w (p - t)^2 / wsum, gradient into G [s][Cp]
+// f32 [s][nt]; loss = sum w (p - t)^2 / wsum, gradient into G [s][Cp]; each
+// block's share of the sum into part[block] (k_loss_sum adds them in order)
 __global__ void __launch_bounds__(TPB) k_loss(const float *__restrict__ P, int Cp, const float *__restrict__ T,
                                               const float *__restrict__ Wt, int nt, size_t npos, double inv_wsum,
-                                              float *__restrict__ G, double *__restrict__ loss) {
+                                              float *__restrict__ G, double *__restrict__ part) {
   __shared__ double sh[TPB];
   double l = 0.0;
   const size_t n = npos * Cp;
@@ -381,7 +396,14 @@ __global__ void __launch_bounds__(TPB) k_loss(const float *__restrict__ P, int C
     if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
     __syncthreads();
   }
-  if (threadIdx.x == 0 && sh[0] != 0.0) atomicAdd(loss, sh[0] * inv_wsum);
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+// loss = inv_wsum * (sum of the blocks' partials in block order)
+__global__ void k_loss_sum(const double *__restrict__ part, int nb, double inv_wsum, double *__restrict__ loss) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double l = 0.0;
+  for (int b = 0; b < nb; ++b) l += part[b];
+  *loss = l * inv_wsum;
 }
 
 // Adam on the FP32 master parameters, then the bf16 copies the convolutions
@@ -427,20 +449,38 @@ hipError_t conv(const __bf16 *X, int Ci, const __bf16 *W, const float *bias, int
   return hipGetLastError();
 }
 
-hipError_t wgrad(const __bf16 *GY, int Co, const __bf16 *X, int Ci, int R, int N, float *GW, hipStream_t st) {
+int wgrad_chunks(int R, int N) {
+  const int S = N * R * R * R;
+  return std::min(WG_NC, (S + WG_CH - 1) / WG_CH);
+}
+
+hipError_t wgrad(const __bf16 *GY, int Co, const __bf16 *X, int Ci, int R, int N, float *GW, float *part,
+                 hipStream_t st) {
   const int S = N * R * R * R;
   if (Ci % 16 || Co % 16 || Ci > WG_MAXC || Co > WG_MAXC || S % WG_K) return hipErrorInvalidValue;
   const int groups = ((Co / 16) * (Ci / 16) + 15) / 16;
   const size_t lds = (size_t)(Co + Ci) * WG_LD * sizeof(__bf16);
-  hipLaunchKernelGGL(k_wgrad, dim3(27, (S + WG_CH - 1) / WG_CH, groups), dim3(TPB), lds, st, GY, Co, X, Ci, R,
-                     S, GW);
+  const int nc = wgrad_chunks(R, N);
+  const int L = ((S + nc - 1) / nc + WG_K - 1) / WG_K * WG_K;  // chunk length, whole staging steps
+  const int ncl = (S + L - 1) / L;
+  hipLaunchKernelGGL(k_wgrad, dim3(27, ncl, groups), dim3(TPB), lds, st, GY, Co, X, Ci, R, S, L, part);
+  const size_t nw = (size_t)Co * 27 * Ci;
+  hipLaunchKernelGGL(k_colsum, dim3((unsigned)((nw + 63) / 64)), dim3(TPB), 0, st, part, ncl, nw, GW);
   return hipGetLastError();
 }
 
-hipError_t act_bwd(const float *g, const __bf16 *y, size_t n, int C, __bf16 *gb, float *gbias, hipStream_t st) {
+int act_bwd_blocks(size_t n, int C) {
+  const int C8 = C / 8, pos_per_block = TPB / C8 * 16;
+  return (int)((n / C + pos_per_block - 1) / pos_per_block);
+}
+
+hipError_t act_bwd(const float *g, const __bf16 *y, size_t n, int C, __bf16 *gb, float *gbias, float *part,
+                   hipStream_t st) {
   if (C > WG_MAXC || C % 8 || n % C) return hipErrorInvalidValue;
-  const size_t n8 = n / 8, per = (size_t)TPB * 16;
-  hipLaunchKernelGGL(k_act_bwd, dim3((unsigned)((n8 + per - 1) / per)), dim3(TPB), 0, st, g, y, n8, C, gb, gbias);
+  const int C8 = C / 8, pos_per_block = TPB / C8 * 16;  // 16 positions per active thread
+  const int nb = act_bwd_blocks(n, C);
+  hipLaunchKernelGGL(k_act_bwd, dim3(nb), dim3(TPB), 0, st, g, y, n / C, C, pos_per_block, gb, part);
+  hipLaunchKernelGGL(k_colsum, dim3((unsigned)((C + 63) / 64)), dim3(TPB), 0, st, part, nb, (size_t)C, gbias);
   return hipGetLastError();
 }
 
@@ -485,9 +525,10 @@ hipError_t input(const float *in, int cin, int Cp, size_t npos, __bf16 *X, hipSt
   return hipGetLastError();
 }
 hipError_t loss(const float *P, int Cp, const float *T, const float *Wt, int nt, size_t npos, double inv_wsum,
-                float *G, double *l, hipStream_t st) {
-  const unsigned g = std::min(nblk(npos * Cp), 2048u);  // grid-stride: few atomics on the sum
-  hipLaunchKernelGGL(k_loss, dim3(g), dim3(TPB), 0, st, P, Cp, T, Wt, nt, npos, inv_wsum, G, l);
+                float *G, double *l, double *part, hipStream_t st) {
+  const unsigned g = std::min(nblk(npos * Cp), (unsigned)LOSS_BLOCKS);  // grid-stride
+  hipLaunchKernelGGL(k_loss, dim3(g), dim3(TPB), 0, st, P, Cp, T, Wt, nt, npos, inv_wsum, G, part);
+  hipLaunchKernelGGL(k_loss_sum, dim3(1), dim3(64), 0, st, part, (int)g, inv_wsum, l);
   return hipGetLastError();
 }
 hipError_t adam(float *p, float *m, float *v, const float *g, size_t n, float lr, float b1, float b2, float eps,

@@ -5,7 +5,9 @@ trip.  Tolerances follow bf16 rounding of activations, weights and
 back-propagated gradients (8-bit mantissa, relative 4e-3 per rounding)
 compounded over 11 layers: forward 2e-2 relative L2; gradients 0.1 relative
 L2 per layer with a cosine above 0.995 (the deepest layer sees ten rounded
-backward convolutions)."""
+backward convolutions).  Every reduction over positions (weight and bias
+gradients, the loss) adds per-block partials in a fixed order, so repeated
+gradients and training runs are bitwise equal."""
 import numpy as np
 import pytest
 
@@ -95,6 +97,28 @@ def test_training_reduces_the_loss(net):
     l1 = net.train_step(xd, td, wd, ws, 1e-3)
     print(f"[unet] loss {l0:.4f} -> {l1:.4f}", flush=True)
     assert np.isfinite(l1) and l1 < 0.7 * l0
+
+
+def test_gradient_and_training_are_bitwise_reproducible(net):
+    """Two gradients of the same batch, and two 5-step training runs from the
+    same parameters, agree bit for bit (no atomics in any reduction)."""
+    p = W.unet_init_params(seed=8, bias_scale=0.1)
+    x, t, w = data(4)
+    xd, td, wd = dev(x), dev(t), dev(w)
+    ws = float(w.sum())
+    print("[unet] reproducibility R=16 n=2", flush=True)
+    net.set_params(p)
+    l1, g1 = net.gradient(xd, td, wd, ws)
+    l2, g2 = net.gradient(xd, td, wd, ws)
+    assert l1 == l2 and np.array_equal(g1, g2)
+    runs = []
+    for _ in range(2):
+        net.set_params(p)
+        losses = [net.train_step(xd, td, wd, ws, 1e-3) for _ in range(5)]
+        runs.append((losses, net.params()))
+    assert runs[0][0] == runs[1][0]
+    assert np.array_equal(runs[0][1], runs[1][1])
+    assert not np.array_equal(runs[0][1], p)
 
 
 def test_full_size_forward_and_gradient():
