@@ -13,20 +13,27 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
+SAN_PATH = os.path.join(HERE, "liboracle_san.so")
 SOURCES = [os.path.join(HERE, "fdlbm_oracle.c")]
 
 MAXS = 8
 OF_RHO, OF_U, OF_T, OF_TS, OF_POP, OF_KIND, OF_WALL_R, OF_WALL_DE = range(8)
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc into oracle/liboracle.so."""
-    if force or not os.path.exists(LIB_PATH):
-        cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", LIB_PATH + ".tmp",
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc into oracle/liboracle.so; with sanitize,
+    an AddressSanitizer + UndefinedBehaviorSanitizer build liboracle_san.so
+    (load it by naming it in FDLBM_ORACLE_LIB, in a process that preloads
+    gcc's libasan)."""
+    out = SAN_PATH if sanitize else LIB_PATH
+    if force or not os.path.exists(out):
+        opt = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+               "-fno-sanitize-recover=undefined"] if sanitize else ["-O2"]
+        cmd = ["gcc", *opt, "-std=c99", "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", out + ".tmp",
                *SOURCES, "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(LIB_PATH + ".tmp", LIB_PATH)
-    return LIB_PATH
+        os.replace(out + ".tmp", out)
+    return out
 
 
 class Obs(ct.Structure):
@@ -50,9 +57,10 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            build()
-        L = ct.CDLL(LIB_PATH)
+        path = os.environ.get("FDLBM_ORACLE_LIB") or LIB_PATH
+        if not os.path.exists(path):
+            build(sanitize=path == SAN_PATH)
+        L = ct.CDLL(path)
         dp = ct.POINTER(ct.c_double)
         L.oracle_create.restype = ct.c_void_p
         L.oracle_create.argtypes = [ct.c_int, ct.c_int, ct.c_int, ct.c_int,

@@ -63,5 +63,46 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     return LIB
 
 
+# host code under AddressSanitizer and UndefinedBehaviorSanitizer (device code
+# unchanged): the C ABI's argument checks, geometry and stencil-class
+# pre-processing and layout run instrumented on the CPU; load it by naming it
+# in FDLBM_LIB in a process that preloads clang's ASan runtime
+HOST_SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
+            "-Xarch_host", "-g"]
+SAN_LIB = os.path.join(ROOT, "_build", "hostsan", "libfdlbm.so")
+
+
+def build_host_sanitized(jobs: int | None = None) -> str:
+    """libfdlbm.so with sanitized host code, out of tree (_build/hostsan)."""
+    out_dir = os.path.dirname(SAN_LIB)
+    os.makedirs(out_dir, exist_ok=True)
+    jobs = jobs or min(len(SOURCES), max(1, min(os.cpu_count() or 1, 16)))
+    objs, procs, pending = [], [], list(SOURCES)
+    while pending or procs:
+        while pending and len(procs) < jobs:
+            src = pending.pop(0)
+            obj = os.path.join(out_dir, os.path.basename(src) + ".o")
+            cmd = [HIPCC, *FLAGS, *HOST_SAN, "-c", src, "-o", obj]
+            if src.endswith(".cpp"):
+                cmd[1:1] = ["-x", "hip"]
+            procs.append((src, obj, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE,
+                                                     text=True)))
+        src, obj, pr = procs.pop(0)
+        _, err = pr.communicate()
+        if pr.returncode != 0:
+            sys.stderr.write(err)
+            for _, _, other in procs:
+                other.kill()
+            raise RuntimeError(f"hipcc failed on {src}")
+        objs.append(obj)
+    subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *HOST_SAN, "-shared-libsan", "-o",
+                    SAN_LIB + ".tmp", *objs], check=True)
+    os.replace(SAN_LIB + ".tmp", SAN_LIB)
+    for o in objs:
+        os.remove(o)
+    return SAN_LIB
+
+
 if __name__ == "__main__":
     print(build(verbose=True))

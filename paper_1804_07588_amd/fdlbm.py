@@ -13,7 +13,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libfdlbm.so")
+# FDLBM_LIB names another build of the same library (the host-sanitized
+# build of build.py, for instance); by default the in-tree libfdlbm.so
+LIB_PATH = os.environ.get("FDLBM_LIB") or os.path.join(HERE, "libfdlbm.so")
 
 # constants mirrored from include/fdlbm.h
 OK, E_INVALID, E_GEOMETRY, E_ALIGN, E_HIP, E_UNSTABLE, E_STATE = 0, -1, -2, -3, -4, -5, -6
@@ -141,6 +143,50 @@ def _arr(x) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(x, dtype=np.float64))
 
 
+def configure(h, cfg: dict) -> None:
+    """Hand a context everything of the configuration dict up to the
+    workspace: geometry, species, transport options, solid, reaction and
+    flow.  Host-side work only (no HIP call); raises FdlbmError with the
+    library's message on a rejected value."""
+    L = lib()
+
+    def check(rc: int):
+        if rc != OK:
+            raise FdlbmError(rc, L.fdlbm_last_error(h).decode())
+
+    mask = np.ascontiguousarray(np.asarray(cfg["mask"], dtype=np.uint8).reshape(-1))
+    check(L.fdlbm_set_geometry(h, mask.ctypes.data_as(ct.POINTER(ct.c_uint8)),
+                               int(cfg.get("inout", 0))))
+    sp = cfg["species"]
+    M, mu0, Djk = _arr(sp["M"]), _arr(sp["mu0"]), _arr(sp["Djk0"]).reshape(-1)
+    check(L.fdlbm_set_species(h, _d(M), _d(mu0), sp["mu_T_exp"], _d(Djk), sp["D_T_exp"],
+                              sp["D_p_exp"], sp["T_ref"], sp["p_ref"], sp["Pr"], int(sp["flags"])))
+    if sp.get("Pr_j") is not None:
+        prj = _arr(sp["Pr_j"])
+        check(L.fdlbm_set_prandtl(h, _d(prj)))
+    lj = sp.get("lj")
+    if lj is not None:
+        eps, omu, omd = _arr(lj["eps_over_k"]), _arr(lj["omega_mu"]), _arr(lj["omega_d"])
+        check(L.fdlbm_set_lj_transport(h, _d(eps), lj["T_unit"], lj["tstar_min"], lj["tstar_max"],
+                                       len(omu), _d(omu), _d(omd)))
+    so = cfg["solid"]
+    tbc = _arr(so["T_bc"])
+    if so.get("scheme", 0):
+        check(L.fdlbm_set_solid_scheme(h, int(so["scheme"])))
+    check(L.fdlbm_set_solid(h, so["alpha_s"], so["C_s"], _d(tbc)))
+    if so.get("coupling", 0):
+        check(L.fdlbm_set_solid_coupling(h, int(so["coupling"])))
+    rx = cfg["reaction"]
+    nu, order = _arr(rx["nu"]), _arr(rx["order"])
+    check(L.fdlbm_set_reaction(h, _d(nu), _d(order), rx["k0"], rx["ea"], rx["T_ref"],
+                               rx["dH"], int(rx["wall_mode"]), rx["T_iso"], rx["tol"], int(rx["max_iter"])))
+    if rx.get("rate_area"):
+        check(L.fdlbm_set_rate_scaling(h, RATE_PER_AREA))
+    fl = cfg["flow"]
+    F, Xin = _arr(fl["F"]), _arr(fl["X_in"])
+    check(L.fdlbm_set_flow(h, _d(F), _d(Xin), fl["p_in"], fl["T_in"]))
+
+
 class Sim:
     """One simulation on the current HIP device, built from a workload dict
     (see workloads.py).  precision: F64, F32, or F16 / BF16 (16-bit
@@ -167,39 +213,7 @@ class Sim:
         if rc != OK:
             raise FdlbmError(rc, "fdlbm_create rejected the description")
         self.h = h
-        mask = np.ascontiguousarray(np.asarray(cfg["mask"], dtype=np.uint8).reshape(-1))
-        self._check(L.fdlbm_set_geometry(h, mask.ctypes.data_as(ct.POINTER(ct.c_uint8)),
-                                         int(cfg.get("inout", 0))))
-        sp = cfg["species"]
-        M, mu0, Djk = _arr(sp["M"]), _arr(sp["mu0"]), _arr(sp["Djk0"]).reshape(-1)
-        self._check(L.fdlbm_set_species(h, _d(M), _d(mu0), sp["mu_T_exp"], _d(Djk), sp["D_T_exp"],
-                                        sp["D_p_exp"], sp["T_ref"], sp["p_ref"], sp["Pr"],
-                                        int(sp["flags"])))
-        if sp.get("Pr_j") is not None:
-            prj = _arr(sp["Pr_j"])
-            self._check(L.fdlbm_set_prandtl(h, _d(prj)))
-        lj = sp.get("lj")
-        if lj is not None:
-            eps, omu, omd = _arr(lj["eps_over_k"]), _arr(lj["omega_mu"]), _arr(lj["omega_d"])
-            self._check(L.fdlbm_set_lj_transport(h, _d(eps), lj["T_unit"], lj["tstar_min"], lj["tstar_max"],
-                                                 len(omu), _d(omu), _d(omd)))
-        so = cfg["solid"]
-        tbc = _arr(so["T_bc"])
-        if so.get("scheme", 0):
-            self._check(L.fdlbm_set_solid_scheme(h, int(so["scheme"])))
-        self._check(L.fdlbm_set_solid(h, so["alpha_s"], so["C_s"], _d(tbc)))
-        if so.get("coupling", 0):
-            self._check(L.fdlbm_set_solid_coupling(h, int(so["coupling"])))
-        rx = cfg["reaction"]
-        nu, order = _arr(rx["nu"]), _arr(rx["order"])
-        self._check(L.fdlbm_set_reaction(h, _d(nu), _d(order), rx["k0"], rx["ea"], rx["T_ref"],
-                                         rx["dH"], int(rx["wall_mode"]), rx["T_iso"], rx["tol"],
-                                         int(rx["max_iter"])))
-        if rx.get("rate_area"):
-            self._check(L.fdlbm_set_rate_scaling(h, RATE_PER_AREA))
-        fl = cfg["flow"]
-        F, Xin = _arr(fl["F"]), _arr(fl["X_in"])
-        self._check(L.fdlbm_set_flow(h, _d(F), _d(Xin), fl["p_in"], fl["T_in"]))
+        configure(h, cfg)
         nbytes = ct.c_size_t()
         self._check(L.fdlbm_workspace_bytes(h, ct.byref(nbytes)))
         self.workspace_bytes = nbytes.value

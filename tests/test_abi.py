@@ -112,3 +112,75 @@ def test_geometry_errors(L):
     open_edge = dict(cfg, mask=np.zeros((1, 40, 64), np.uint8))
     assert set_geom(L, h, open_edge) == fdlbm.E_GEOMETRY
     L.fdlbm_destroy(h)
+
+
+def host_cases():
+    """Configurations that reach every branch of the host set-up: D2Q9 and
+    D3Q19, periodic and closed axes, inlet/outlet rows, sphere packs of the
+    benchmark's construction (the 128^3 bed and three batch beds), the
+    Crank-Nicolson solid, Eq.(48) coupling, per-area rates, species Prandtl
+    numbers and a Lennard-Jones table."""
+    c1 = W.channel_c1()
+    rng = np.random.default_rng(3)
+    noisy = (rng.random((1, 24, 32)) < 0.3).astype(np.uint8)
+    noisy[:, :2, :] = 1
+    noisy[:, -2:, :] = 1
+    cases = [("c1", c1),
+             ("c1_pr_cn", W.with_changes(W.channel_c1(pr=0.71), solid=dict(scheme=1, alpha_s=1.5))),
+             ("noisy2d", W.with_changes(c1, mask=noisy, nx=32, ny=24)),
+             ("bed128", W.packed_bed())]
+    cases += [(f"batch{k}", c) for k, c in enumerate(W.batch_beds(3))]
+    mask, _ = W.sphere_pack_mask(24, radius=3.0, porosity=0.6, seed=9, buffer=4)
+    bed = W.packed_bed(mask=mask)
+    eq48 = W.with_changes(bed, solid=dict(coupling=1))
+    t = np.linspace(0.5, 10.0, 40)
+    lj = W.with_changes(bed)
+    lj["species"]["lj"] = dict(T_unit=1209.0, tstar_min=0.5, tstar_max=10.0,
+                               omega_mu=list(1.1 + 0.9 * np.exp(-0.6 * t)), omega_d=list(1.0 + 0.8 * np.exp(-0.5 * t)),
+                               eps_over_k=[100.0, 300.0, 200.0, 60.0, 80.0])
+    lj["species"]["Pr_j"] = [0.7, 0.8, 0.9, 1.0, 0.75]
+    return cases + [("bed_eq48", eq48), ("bed_lj_prj", lj)]
+
+
+@pytest.mark.parametrize("precision", [fdlbm.F64, fdlbm.F32, fdlbm.F16, fdlbm.BF16])
+def test_host_setup_of_every_workload(L, precision):
+    """The whole host set-up (geometry, stencil classes, slot order, species,
+    transport, solid, reaction, flow, workspace layout) without a device, at
+    every storage precision; node counts add up and the workspace holds at
+    least the two population copies."""
+    for name, cfg in host_cases():
+        if cfg["lattice"] == 2 and name == "bed128":
+            continue
+        h = make_ctx(L, cfg, precision)
+        try:
+            fdlbm.configure(h, cfg)
+            ng, nw, nsol = ct.c_int64(), ct.c_int64(), ct.c_int64()
+            assert L.fdlbm_counts(h, ct.byref(ng), ct.byref(nw), ct.byref(nsol)) == fdlbm.OK
+            n = cfg["nx"] * cfg["ny"] * cfg["nz"]
+            assert 0 < ng.value and nw.value >= 0 and ng.value + nsol.value <= n, name
+            nbytes = ct.c_size_t()
+            assert L.fdlbm_workspace_bytes(h, ct.byref(nbytes)) == fdlbm.OK
+            pop = {fdlbm.F64: 8, fdlbm.F32: 4}.get(precision, 2)
+            Q = 9 if cfg["lattice"] == 2 else 19
+            assert nbytes.value >= 2 * Q * len(cfg["species"]["M"]) * (ng.value + nw.value) * pop, name
+        finally:
+            L.fdlbm_destroy(h)
+
+
+def test_unet_host_setup(L):
+    """Network contexts of several sizes: parameter count and workspace
+    layout on the host, and the argument checks."""
+    from paper_1804_07588_amd import surrogate
+    S = surrogate._L()
+    vp = ct.c_void_p
+    for R, n in [(16, 2), (32, 1), (64, 4)]:
+        u = vp()
+        assert S.fdlbm_unet_create(R, n, 3, 9, None, ct.byref(u)) == fdlbm.OK
+        npar, nbytes = ct.c_size_t(), ct.c_size_t()
+        assert S.fdlbm_unet_param_count(u, ct.byref(npar)) == fdlbm.OK
+        assert npar.value == W.unet_layout()[1]
+        assert S.fdlbm_unet_workspace_bytes(u, ct.byref(nbytes)) == fdlbm.OK
+        assert nbytes.value > n * R ** 3 * 4
+        S.fdlbm_unet_destroy(u)
+    u = vp()
+    assert S.fdlbm_unet_create(18, 1, 3, 9, None, ct.byref(u)) == fdlbm.E_INVALID
