@@ -248,6 +248,24 @@ int fdlbm_set_reaction(fdlbm_ctx *ctx, const double *nu, const double *order, do
 #define FDLBM_RATE_PER_AREA 1
 int fdlbm_set_rate_scaling(fdlbm_ctx *ctx, int mode);
 
+/* Population mass the reactive wall adds per unit of nu_j M_j r (Eq.(38)-(41)
+ * with Eq.(50)).  FDLBM_SOURCE_LATTICE (the default): S_j / c_j = nu_j M_j r
+ * (the flux sums of Eq.(38)-(39) taken with the species velocities c_j e_i
+ * and S_j as Eq.(50) prints it).  FDLBM_SOURCE_FLUX: nu_j M_j r / c_j.  An
+ * interpolated species (c_j < 1) moves a population c_j of a link per step,
+ * so the mass the gas receives per step is the emitted excess times about
+ * c_j: with the default the gas receives about c_j nu_j M_j r of species j
+ * (a product of mass ratio 4 arrives about half short in a reactive channel),
+ * with FDLBM_SOURCE_FLUX it receives nu_j M_j r after a start-up transient
+ * (the stoichiometric product balance Sec. 7 reports).  On sphere packs the
+ * 1/c_j larger emission at one-link wall nodes drives trace product densities
+ * negative within steps; the default keeps them positive.  On-lattice species
+ * (c_j = 1) are the same in both.  FDLBM_E_INVALID for another value.  Takes
+ * effect at the next step. */
+#define FDLBM_SOURCE_LATTICE 0
+#define FDLBM_SOURCE_FLUX 1
+int fdlbm_set_wall_source(fdlbm_ctx *ctx, int mode);
+
 /* Flow: body force per unit mass F3[3]; inlet mole fractions X_in[ns],
  * pressure p_in and temperature T_in (used when inout = 1). */
 int fdlbm_set_flow(fdlbm_ctx *ctx, const double *F3, const double *X_in, double p_in,

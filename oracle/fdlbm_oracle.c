@@ -70,6 +70,7 @@ struct oracle_sim {
   double *wall_u;   /* wall velocity U_w per node, 3 rows (NULL: walls at rest) */
   int literal_eq6;  /* 1: f* at the mixture temperature as printed in Eq.(6) */
   int rate_area;    /* 1: rate scaled by the wall node's wetted area (reading) */
+  int src_flux;     /* 1: wall source scaled by 1/c_j (stoichiometric mass flux, reading) */
   int eq48;         /* 1: solid-gas coupling of Eq.(48) instead of the flux-matched one */
   /* cumulative counters */
   double moles, heat, bheat, work;
@@ -910,6 +911,15 @@ static void wall_bc(oracle_sim *s) {
         if (emits(s, w, i)) Zg += f0[i];
       area = Zg / (0.5 * Tw);
     }
+    /* Source in population units per unit of nu_j M_j r: 1 (default: the
+     * flux sums of Eq.(38)-(40) taken with the species velocities c_j e_i,
+     * so that S_j / c_j = nu_j M_j r is added at the wall), or, as an
+     * option, 1 / c_j: the wall adds the population mass that interpolated
+     * streaming, which moves a population c_j of a link per step, carries
+     * away as the mass flux nu_j M_j r (stoichiometric delivery, the product
+     * balance of Sec. 7). */
+    double srcf[MAXS];
+    for (int j = 0; j < ns; ++j) srcf[j] = s->src_flux ? 1.0 / s->cj[j] : 1.0;
     double rw[MAXS];
     for (int j = 0; j < ns; ++j) rw[j] = A[j] / Z[j];
     for (int it = 0; it < s->max_iter; ++it) {
@@ -923,7 +933,7 @@ static void wall_bc(oracle_sim *s) {
             double o = s->order[m] - (m == j ? 1.0 : 0.0);
             if (o != 0.0) R *= pow(rw[m] / s->M[m], o);
           }
-          nw[j] = A[j] / (Z[j] - s->nu[j] * R);
+          nw[j] = A[j] / (Z[j] - s->nu[j] * srcf[j] * R);
         }
         double d = fabs(nw[j] - rw[j]) / fmax(fabs(nw[j]), 1e-300);
         if (d > dmax) dmax = d;
@@ -933,7 +943,7 @@ static void wall_bc(oracle_sim *s) {
     }
     double r = area * rate(s, rw, Tw);
     /* final wall densities from the exact mass balance at the final rate */
-    for (int j = 0; j < ns; ++j) rw[j] = (A[j] + s->nu[j] * s->M[j] * r) / Z[j];
+    for (int j = 0; j < ns; ++j) rw[j] = (A[j] + s->nu[j] * s->M[j] * srcf[j] * r) / Z[j];
     double Eout = 0.0;
     for (int i = 1; i < Q; ++i) {
       if (!emits(s, w, i)) continue;
@@ -1565,6 +1575,12 @@ int oracle_set_coupling(oracle_sim *s, int eq48) {
 
 /* Rate per wall node (0, the default, as in Sec. 4.3) or per unit wetted
  * wall area (1, the reading for sphere packs). */
+int oracle_set_source_flux(oracle_sim *s, int on) {
+  if (!s) return fail(s, "null simulation");
+  s->src_flux = on != 0;
+  return 0;
+}
+
 int oracle_set_rate_area(oracle_sim *s, int on) {
   if (!s) return fail(s, "null simulation");
   s->rate_area = on != 0;

@@ -92,6 +92,8 @@ int oracle_set_threads(int n);
 int oracle_set_coupling(oracle_sim *s, int eq48);
 /* reaction rate per wall node (0, default) or per unit wetted area (1) */
 int oracle_set_rate_area(oracle_sim *s, int on);
+/* wall source in population units: nu_j M_j r (0, default) or nu_j M_j r / c_j (1) */
+int oracle_set_source_flux(oracle_sim *s, int on);
 /* f* temperature: 0 the energy-holding reading (default), 1 Eq.(6) as printed */
 int oracle_set_literal_eq6(oracle_sim *s, int on);
 /* overwrite the populations of species comp (Q*n values, OF_POP layout) */

@@ -85,6 +85,7 @@ def lib():
         L.oracle_set_pops.argtypes = [ct.c_void_p, ct.c_int, dp]
         L.oracle_set_literal_eq6.argtypes = [ct.c_void_p, ct.c_int]
         L.oracle_set_rate_area.argtypes = [ct.c_void_p, ct.c_int]
+        L.oracle_set_source_flux.argtypes = [ct.c_void_p, ct.c_int]
         L.oracle_set_coupling.argtypes = [ct.c_void_p, ct.c_int]
         L.oracle_set_threads.argtypes = [ct.c_int]
         L.oracle_init_fields.argtypes = [ct.c_void_p, dp, dp, dp, dp]
@@ -205,6 +206,8 @@ class OracleSim:
         self._check(L.oracle_set_flow(h, _d(F), _d(Xin), fl["p_in"], fl["T_in"]))
         if rx.get("rate_area"):
             self._check(L.oracle_set_rate_area(h, 1))
+        if rx.get("source_flux"):
+            self._check(L.oracle_set_source_flux(h, 1))
         if cfg.get("literal_eq6"):
             self._check(L.oracle_set_literal_eq6(h, 1))
         if cfg.get("wall_u") is not None:

@@ -45,6 +45,7 @@ struct fdlbm_ctx {
          tol = 1e-13;
   int wall_mode = 0, max_iter = 64;
   bool rate_area = false;  // rate per unit wetted wall area instead of per wall node
+  bool source_flux = false;  // wall source nu_j M_j r / c_j (stoichiometric mass flux)
   int coupling = FDLBM_COUPLING_FLUX;  // solid-gas coupling at the wall nodes
   double F[3]{}, X_in[MAXS]{}, p_in = 1.0 / 3, T_in = 1.0 / 3;
   double rho_ref[MAXS]{};  // reference densities of 16-bit storage (mean initial density)
@@ -287,6 +288,7 @@ static Params<real> params(const fdlbm_ctx *c) {
       for (int q = 0; q < 3; ++q) p.wint[j][k][q] = (real)w[k][q];
     p.mu0[j] = (real)c->mu0[j];
     p.nu[j] = (real)c->nu[j];
+    p.srcf[j] = (real)(c->source_flux ? 1.0 / cj : 1.0);
     p.order[j] = (int)c->order[j];
     p.rho_in[j] = (real)(c->M[j] * c->X_in[j] * c->p_in / c->T_in);
   }
@@ -735,6 +737,14 @@ int fdlbm_set_rate_scaling(fdlbm_ctx *c, int mode) {
   if (mode != FDLBM_RATE_PER_NODE && mode != FDLBM_RATE_PER_AREA)
     return set_err(c, FDLBM_E_INVALID, "rate scaling must be FDLBM_RATE_PER_NODE or FDLBM_RATE_PER_AREA");
   c->rate_area = mode == FDLBM_RATE_PER_AREA;
+  return FDLBM_OK;
+}
+
+int fdlbm_set_wall_source(fdlbm_ctx *c, int mode) {
+  if (!c) return FDLBM_E_INVALID;
+  if (mode != FDLBM_SOURCE_LATTICE && mode != FDLBM_SOURCE_FLUX)
+    return set_err(c, FDLBM_E_INVALID, "wall source must be FDLBM_SOURCE_LATTICE or FDLBM_SOURCE_FLUX");
+  c->source_flux = mode == FDLBM_SOURCE_FLUX;
   return FDLBM_OK;
 }
 

@@ -438,7 +438,8 @@ __device__ inline double wall_node(const Params<real> &p, const Bufs<real, PT> &
   real Ein = 0;
 #pragma unroll
   for (int j = 0; j < NS; ++j) Ein += p.cj2[j] * Ej[j];
-  // wall densities: rho_w,j Z = A_j + nu_j M_j r (Eq.(41) with Eq.(50));
+  // wall densities: rho_w,j Z = A_j + nu_j M_j r s_j (Eq.(41) with Eq.(50);
+  // s_j = 1, or 1 / c_j for a stoichiometric mass flux out of the wall);
   // fixed point started at the non-reactive density, each reactant's own
   // concentration treated implicitly
   real rw[NS];
@@ -459,7 +460,7 @@ __device__ inline double wall_node(const Params<real> &p, const Bufs<real, PT> &
         real R = keff;
 #pragma unroll
         for (int m = 0; m < NS; ++m) R *= ipow(rw[m] * p.invM[m], p.order[m] - (m == j ? 1 : 0));
-        nw[j] = A[j] / (Z - p.nu[j] * R);
+        nw[j] = A[j] / (Z - p.nu[j] * p.srcf[j] * R);
       }
       const real d = fabs(nw[j] - rw[j]) / fmax(fabs(nw[j]), tiny<real>());
       dmax = fmax(dmax, d);
@@ -473,7 +474,7 @@ __device__ inline double wall_node(const Params<real> &p, const Bufs<real, PT> &
   for (int m = 0; m < NS; ++m) r *= ipow(rw[m] * p.invM[m], p.order[m]);
   const real invZ = real(1) / Z;
 #pragma unroll
-  for (int j = 0; j < NS; ++j) rw[j] = (A[j] + p.nu[j] * p.M[j] * r) * invZ;
+  for (int j = 0; j < NS; ++j) rw[j] = (A[j] + p.nu[j] * p.M[j] * p.srcf[j] * r) * invZ;
   // emission: rho_w,j f^eq_i(1, 0, T_w) on the links into the gas
   real Eout = 0;
 #pragma unroll
@@ -572,8 +573,10 @@ __device__ __forceinline__ void moments_node(const Params<real> &p, const Bufs<r
     const int cls = cls_at(cw, i);
     const Rec<real, NS> g = stream_rec<real, PT, D, NS>(p, G + (size_t)i * nsl * RL,
                                                      gas_tap_slots<FAST>(b, ad, i, cls, t), wtab, cls, i);
-    // for the collision, which reads it right after: an ordinary (cached) store
-    pop_store<real, PT, D, NS>(p, b.Gs + (size_t)i * nsl * RL, t, i, g);
+    // streaming store: the collision reads it in its own launch, after more
+    // than the L2 holds has passed (measured 3 % faster than a cached store
+    // here, 1 % slower to read back)
+    pop_store<real, PT, D, NS, true>(p, b.Gs + (size_t)i * nsl * RL, t, i, g);
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
       rho[j] += g.v[j];
