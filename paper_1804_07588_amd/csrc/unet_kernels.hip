@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(TPB) k_conv(const __bf16 *__restrict__ X, int 
 // shifted X rows in LDS; wave w of group g owns tiles 16 g + w + 4 t, t < 4.
 // ---------------------------------------------------------------------------
 constexpr int WG_CH = 2048;  // positions per workgroup, at least
-constexpr int WG_NC = 64;    // chunks per launch, at most
+constexpr int WG_NC = 256;   // chunks per launch, at most
 constexpr int WG_MAXT = 4;   // tiles per wave
 constexpr int WG_MAXC = 224; // largest channel count staged
 
@@ -250,20 +250,35 @@ __global__ void __launch_bounds__(TPB) k_act_bwd(const float *__restrict__ g, co
   }
 }
 
-// out[col] = sum over rows r of P[r][col], rows added in the fixed order
-// ((r = 0, 4, 8, ...) + (1, 5, ...)) + ... : 64 columns per workgroup, four
-// row classes per column, combined in class order
+// out[col] = sum over rows r of P[r][col] in a fixed association: CW
+// columns per workgroup, TPB / CW row classes per column (class k adds rows
+// k, k + TPB/CW, ... in order), the classes then added in class order.  CW =
+// 64 for wide matrices (few rows: weight-gradient chunks), CW = 8 for narrow
+// ones (many rows: the bias partials of many blocks).
+template <int CW>
 __global__ void __launch_bounds__(TPB) k_colsum(const float *__restrict__ P, int nrow, size_t ncol,
                                                 float *__restrict__ out) {
-  __shared__ float sh[4][64];
-  const int lc = (int)threadIdx.x % 64, cls = (int)threadIdx.x / 64;
-  const size_t col = (size_t)blockIdx.x * 64 + lc;
+  constexpr int NCLS = TPB / CW;
+  __shared__ float sh[NCLS][CW];
+  const int lc = (int)threadIdx.x % CW, cls = (int)threadIdx.x / CW;
+  const size_t col = (size_t)blockIdx.x * CW + lc;
   float sum = 0.0f;
   if (col < ncol)
-    for (int r = cls; r < nrow; r += 4) sum += P[(size_t)r * ncol + col];
+    for (int r = cls; r < nrow; r += NCLS) sum += P[(size_t)r * ncol + col];
   sh[cls][lc] = sum;
   __syncthreads();
-  if (cls == 0 && col < ncol) out[col] = ((sh[0][lc] + sh[1][lc]) + sh[2][lc]) + sh[3][lc];
+  if (cls == 0 && col < ncol) {
+    float t = sh[0][lc];
+    for (int k = 1; k < NCLS; ++k) t += sh[k][lc];
+    out[col] = t;
+  }
+}
+
+static void colsum(const float *P, int nrow, size_t ncol, float *out, hipStream_t st) {
+  if (ncol >= 64 * 256)
+    hipLaunchKernelGGL(k_colsum<64>, dim3((unsigned)((ncol + 63) / 64)), dim3(TPB), 0, st, P, nrow, ncol, out);
+  else
+    hipLaunchKernelGGL(k_colsum<8>, dim3((unsigned)((ncol + 7) / 8)), dim3(TPB), 0, st, P, nrow, ncol, out);
 }
 
 // 2x2x2 average pooling, edge R -> R/2
@@ -398,12 +413,21 @@ __global__ void __launch_bounds__(TPB) k_loss(const float *__restrict__ P, int C
   }
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
-// loss = inv_wsum * (sum of the blocks' partials in block order)
-__global__ void k_loss_sum(const double *__restrict__ part, int nb, double inv_wsum, double *__restrict__ loss) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// loss = inv_wsum * (sum of the blocks' partials): thread t adds partials
+// t, t + TPB, ... in order, then the threads' sums are added pairwise in a
+// fixed tree
+__global__ void __launch_bounds__(TPB) k_loss_sum(const double *__restrict__ part, int nb, double inv_wsum,
+                                                  double *__restrict__ loss) {
+  __shared__ double sh[TPB];
   double l = 0.0;
-  for (int b = 0; b < nb; ++b) l += part[b];
-  *loss = l * inv_wsum;
+  for (int b = (int)threadIdx.x; b < nb; b += TPB) l += part[b];
+  sh[threadIdx.x] = l;
+  __syncthreads();
+  for (int k = TPB / 2; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = sh[0] * inv_wsum;
 }
 
 // Adam on the FP32 master parameters, then the bf16 copies the convolutions
@@ -465,7 +489,7 @@ hipError_t wgrad(const __bf16 *GY, int Co, const __bf16 *X, int Ci, int R, int N
   const int ncl = (S + L - 1) / L;
   hipLaunchKernelGGL(k_wgrad, dim3(27, ncl, groups), dim3(TPB), lds, st, GY, Co, X, Ci, R, S, L, part);
   const size_t nw = (size_t)Co * 27 * Ci;
-  hipLaunchKernelGGL(k_colsum, dim3((unsigned)((nw + 63) / 64)), dim3(TPB), 0, st, part, ncl, nw, GW);
+  colsum(part, ncl, nw, GW, st);
   return hipGetLastError();
 }
 
@@ -480,7 +504,7 @@ hipError_t act_bwd(const float *g, const __bf16 *y, size_t n, int C, __bf16 *gb,
   const int C8 = C / 8, pos_per_block = TPB / C8 * 16;  // 16 positions per active thread
   const int nb = act_bwd_blocks(n, C);
   hipLaunchKernelGGL(k_act_bwd, dim3(nb), dim3(TPB), 0, st, g, y, n / C, C, pos_per_block, gb, part);
-  hipLaunchKernelGGL(k_colsum, dim3((unsigned)((C + 63) / 64)), dim3(TPB), 0, st, part, nb, (size_t)C, gbias);
+  colsum(part, nb, (size_t)C, gbias, st);
   return hipGetLastError();
 }
 
@@ -528,7 +552,7 @@ hipError_t loss(const float *P, int Cp, const float *T, const float *Wt, int nt,
                 float *G, double *l, double *part, hipStream_t st) {
   const unsigned g = std::min(nblk(npos * Cp), (unsigned)LOSS_BLOCKS);  // grid-stride
   hipLaunchKernelGGL(k_loss, dim3(g), dim3(TPB), 0, st, P, Cp, T, Wt, nt, npos, inv_wsum, G, part);
-  hipLaunchKernelGGL(k_loss_sum, dim3(1), dim3(64), 0, st, part, (int)g, inv_wsum, l);
+  hipLaunchKernelGGL(k_loss_sum, dim3(1), dim3(TPB), 0, st, part, (int)g, inv_wsum, l);
   return hipGetLastError();
 }
 hipError_t adam(float *p, float *m, float *v, const float *g, size_t n, float lr, float b1, float b2, float eps,
