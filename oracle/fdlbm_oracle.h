@@ -59,6 +59,10 @@ int oracle_set_geometry(oracle_sim *s, const uint8_t *mask, int inout);
 int oracle_set_species(oracle_sim *s, const double *M, const double *mu0, double mu_T_exp,
                        const double *Djk0, double D_T_exp, double D_p_exp, double T_ref,
                        double p_ref, double Pr, unsigned flags);
+/* flags: 1 diffusion velocity, 2 viscous, 4 energy-flux, 8 Prandtl
+ * corrections; diagnostic bits for the pin tests: 16 drops the cubic Q'_xyz
+ * part of the viscous correction, 32 the off-diagonal R'_ab of the energy-flux
+ * correction */
 /* per-species Prandtl numbers (NULL: every species at the common Pr) */
 int oracle_set_prandtl(oracle_sim *s, const double *Pr_j);
 /* Lennard-Jones transport from a collision-integral table (NULL eps: off) */
