@@ -366,15 +366,22 @@ def test_full_bed_two_steps_all_precisions(oracle_lib, fd):
     o.close()
 
 
-# Bounds on max|error| / max|field| against the FP64 oracle (measured values
-# are about a third to a half of these).  The stored deviation from the
-# fixed reference w_i rho_ref,j is small only while a species stays near its
-# reference density: in the channel the product species grows from
-# X = 1e-6, so it is effectively stored at the format's full relative
-# precision and its error accumulates over the 1000 steps.
+# Bounds on max|error| / max|field| against the FP64 oracle.  The stored
+# deviation from the fixed reference w_i rho_ref,j is small only while a
+# species stays near its reference density: in the channel the product
+# species grows from X = 1e-6, so it is effectively stored at the format's
+# full relative precision and its error accumulates over the 1000 steps.
+# In units of the storage format's unit roundoff u16 (FP16 2^-11, BF16 2^-8,
+# each stored deviation rounded once per step): the bed (100 steps) within
+# 4 u16 on densities, populations, T and T^s (measured 1.5 u16 FP16, 2.6 u16
+# BF16); the channel (1000 steps of a flow at 1e-4 of the sound speed, with a
+# trace product grown from X = 1e-6) within 16 u16 FP16 (measured 9 u16) and
+# 80 u16 BF16 (measured 63 u16: BF16 cannot resolve that flow, so the
+# composition near the reacting walls follows a wrong velocity field).
+U16 = {"F16": 2.0 ** -11, "BF16": 2.0 ** -8}
 BOUNDS_16 = {
-    ("F16", "bed"): 2e-3, ("F16", "channel"): 2e-2,
-    ("BF16", "bed"): 2e-2, ("BF16", "channel"): 3e-1,
+    ("F16", "bed"): 4 * U16["F16"], ("F16", "channel"): 16 * U16["F16"],
+    ("BF16", "bed"): 4 * U16["BF16"], ("BF16", "channel"): 80 * U16["BF16"],
 }
 # velocity: relative to max|u| on the bed (max|u| ~ 5e-3); per sound speed in
 # the channel, whose flow (max|u| ~ 1e-4) 16-bit storage cannot resolve
