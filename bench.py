@@ -46,6 +46,8 @@ def parse():
                     help="instead of the throughput run: steps and seconds from a cold start to "
                          "a steady-state residual of --tol (checked every 100 steps)")
     ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--log", default=None,
+                    help="JSON-lines run log (observables and residual at every check of --steady)")
     ap.add_argument("--stage-tol", type=float, default=1e-5,
                     help="16-bit storage: residual at which the FP32 stage takes over")
     ap.add_argument("--max-steps", type=int, default=400000)
@@ -292,11 +294,12 @@ def fields_of(sim, ns):
                 T=sim.field(fdlbm.FIELD_T), Ts=sim.field(fdlbm.FIELD_TS))
 
 
-def run_to(sim, tol, max_steps, check=100, plateau=None, label=""):
+def run_to(sim, tol, max_steps, check=100, plateau=None, label="", log=None):
     """Step until the residual (checked every `check` steps) is <= tol, or the
     step budget is spent, or (plateau = (window, factor)) the residual has not
     dropped below factor x its value `window` checks earlier.  Returns
-    (steps, last residual dict)."""
+    (steps, last residual dict).  log: a fdlbm.RunLog that records the
+    observables and residual at every check."""
     sim.step(1)
     sim.residual()  # first snapshot
     steps, r, hist, last = 1, None, [], time.perf_counter()
@@ -304,6 +307,8 @@ def run_to(sim, tol, max_steps, check=100, plateau=None, label=""):
         sim.step(check)
         steps += check
         r = sim.residual()
+        if log is not None:
+            log.record(sim, residual=r, label=label)
         hist.append(r["max"])
         if r["max"] <= tol:
             break
@@ -327,11 +332,14 @@ def steady(args, sim, cfg, n_gas, ns, init):
     from paper_1804_07588_amd import fdlbm
     two_stage = args.precision in ("f16", "bf16")
     fin = fdlbm.Sim(cfg, precision=fdlbm.F32, init=init) if two_stage else None
+    log = fdlbm.RunLog(args.log, dict(run="steady", n=args.n, precision=args.precision,
+                                      tol=args.tol)) if args.log else None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stages = []
     if two_stage:
-        s1, r1 = run_to(sim, args.stage_tol, args.max_steps, plateau=(20, 0.9), label=args.precision)
+        s1, r1 = run_to(sim, args.stage_tol, args.max_steps, plateau=(20, 0.9), label=args.precision,
+                        log=log)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         stages.append(dict(storage=args.precision, steps=s1, seconds=round(t1 - t0, 3),
@@ -340,17 +348,19 @@ def steady(args, sim, cfg, n_gas, ns, init):
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         stages.append(dict(handover_seconds=round(t2 - t1, 3)))
-        s2, r = run_to(fin, args.tol, args.max_steps - s1, label="f32")
+        s2, r = run_to(fin, args.tol, args.max_steps - s1, label="f32", log=log)
         steps = s1 + s2
         torch.cuda.synchronize()
         stages.append(dict(storage="f32", steps=s2, seconds=round(time.perf_counter() - t2, 3),
                            residual=float(r["max"])))
         obs = fin.observe()
     else:
-        steps, r = run_to(sim, args.tol, args.max_steps, label=args.precision)
+        steps, r = run_to(sim, args.tol, args.max_steps, label=args.precision, log=log)
         torch.cuda.synchronize()
         obs = sim.observe()
     dt = time.perf_counter() - t0
+    if log is not None:
+        log.close()
     print(json.dumps({
         "metric": "steps and seconds from a cold start to steady state",
         "value": round(dt, 3), "unit": "s", "steps_to_steady": steps,

@@ -1596,6 +1596,62 @@ int oracle_set_rate_area(oracle_sim *s, int on) {
   return 0;
 }
 
+/* Checkpoint: everything a later step or observation reads -- populations
+ * (gas and wall slots), solid temperature, the last step's node fields
+ * (densities, velocity, temperature, wall rate and energy exchange) and the
+ * cumulative counters -- as one flat block of doubles.  A restored run
+ * continues bitwise like the uninterrupted one. */
+static size_t state_doubles(const oracle_sim *s) {
+  const size_t n = (size_t)s->n;
+  return (size_t)s->ns * s->Q * n + n + (size_t)s->ns * n + 3 * n + n + 2 * n + 5;
+}
+
+size_t oracle_state_bytes(const oracle_sim *s) { return s ? state_doubles(s) * sizeof(double) : 0; }
+
+static void state_copy(oracle_sim *s, double *buf, int save) {
+  const size_t n = (size_t)s->n;
+  double *p = buf;
+  struct {
+    double *a;
+    size_t len;
+  } parts[] = {{s->G, (size_t)s->ns * s->Q * n}, {s->Ts, n}, {s->rho, (size_t)s->ns * n},
+               {s->u, 3 * n}, {s->T, n}, {s->wall_r, n}, {s->wall_dE, n}};
+  for (size_t k = 0; k < sizeof parts / sizeof parts[0]; ++k) {
+    if (save) memcpy(p, parts[k].a, parts[k].len * sizeof(double));
+    else memcpy(parts[k].a, p, parts[k].len * sizeof(double));
+    p += parts[k].len;
+  }
+  if (save) {
+    p[0] = s->moles;
+    p[1] = s->heat;
+    p[2] = s->bheat;
+    p[3] = s->work;
+    p[4] = (double)s->step;
+  } else {
+    s->moles = p[0];
+    s->heat = p[1];
+    s->bheat = p[2];
+    s->work = p[3];
+    s->step = (int64_t)p[4];
+  }
+}
+
+int oracle_save_state(oracle_sim *s, void *dst, size_t bytes) {
+  if (!s || !dst) return fail(s, "null argument");
+  if (!s->init_done) return fail(s, "initialise the fields first");
+  if (bytes < oracle_state_bytes(s)) return fail(s, "checkpoint buffer too small");
+  state_copy(s, (double *)dst, 1);
+  return 0;
+}
+
+int oracle_load_state(oracle_sim *s, const void *src, size_t bytes) {
+  if (!s || !src) return fail(s, "null argument");
+  if (!s->init_done) return fail(s, "initialise the fields first");
+  if (bytes != oracle_state_bytes(s)) return fail(s, "checkpoint of another size");
+  state_copy(s, (double *)src, 0);
+  return 0;
+}
+
 /* Overwrite the populations of species comp (Q*n values, the layout of
  * oracle_get_field's OF_POP): a building block for the linear stability
  * analysis, which needs arbitrary, not only equilibrium, states. */

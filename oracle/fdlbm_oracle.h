@@ -23,6 +23,7 @@
 #ifndef FDLBM_ORACLE_H
 #define FDLBM_ORACLE_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -102,6 +103,11 @@ int oracle_set_source_flux(oracle_sim *s, int on);
 int oracle_set_literal_eq6(oracle_sim *s, int on);
 /* overwrite the populations of species comp (Q*n values, OF_POP layout) */
 int oracle_set_pops(oracle_sim *s, int comp, const double *src);
+/* checkpoint of the state (populations, solid temperature, last node fields,
+ * counters): size, save into dst, restore from src (same geometry) */
+size_t oracle_state_bytes(const oracle_sim *s);
+int oracle_save_state(oracle_sim *s, void *dst, size_t bytes);
+int oracle_load_state(oracle_sim *s, const void *src, size_t bytes);
 
 /* ---- building blocks exposed for the pin tests ---- */
 /* equilibrium populations of one species, Eq.(4)/(6) (D2Q9) or the D3Q19 reading */

@@ -83,6 +83,10 @@ def lib():
         L.oracle_set_flow.argtypes = [ct.c_void_p, dp, dp, ct.c_double, ct.c_double]
         L.oracle_set_wall_velocity.argtypes = [ct.c_void_p, dp]
         L.oracle_set_pops.argtypes = [ct.c_void_p, ct.c_int, dp]
+        L.oracle_state_bytes.restype = ct.c_size_t
+        L.oracle_state_bytes.argtypes = [ct.c_void_p]
+        L.oracle_save_state.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_size_t]
+        L.oracle_load_state.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_size_t]
         L.oracle_set_literal_eq6.argtypes = [ct.c_void_p, ct.c_int]
         L.oracle_set_rate_area.argtypes = [ct.c_void_p, ct.c_int]
         L.oracle_set_source_flux.argtypes = [ct.c_void_p, ct.c_int]
@@ -247,6 +251,18 @@ class OracleSim:
         a = _arr(g).reshape(-1)
         assert a.size == self.Q * self.n
         self._check(lib().oracle_set_pops(self.h, int(comp), _d(a)))
+
+    def save_state(self) -> bytes:
+        """Checkpoint: populations, solid temperature, the last step's node
+        fields and the cumulative counters."""
+        nb = lib().oracle_state_bytes(self.h)
+        buf = ct.create_string_buffer(nb)
+        self._check(lib().oracle_save_state(self.h, buf, nb))
+        return buf.raw
+
+    def load_state(self, state: bytes) -> None:
+        buf = ct.create_string_buffer(state, len(state))
+        self._check(lib().oracle_load_state(self.h, buf, len(state)))
 
     def transport(self, rho, T):
         t1, t2 = np.zeros(self.ns), np.zeros(self.ns)

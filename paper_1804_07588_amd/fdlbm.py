@@ -192,6 +192,47 @@ def configure(h, cfg: dict) -> None:
     check(L.fdlbm_set_flow(h, _d(F), _d(Xin), fl["p_in"], fl["T_in"]))
 
 
+
+class RunLog:
+    """JSON-lines run log: one object per line, flushed at once, so the log
+    of a run that stops is complete up to its last record.  The first line
+    ({"event": "open", ...}) carries the caller's metadata; each record
+    ({"event": "step", ...}) the step, seconds since the log opened, every
+    observable of Sim.observe() and whatever the caller adds (a residual
+    dict, a label).  Usable from any object with an observe() method."""
+
+    def __init__(self, path: str, meta: dict | None = None):
+        import json
+        import time
+        self._json, self._time = json, time
+        self._t0 = time.perf_counter()
+        self._fh = open(path, "a", buffering=1)
+        self._write({"event": "open", "unix_time": time.time(), **(meta or {})})
+
+    @staticmethod
+    def _plain(v):
+        if isinstance(v, np.ndarray):
+            return v.tolist()
+        if isinstance(v, (np.floating, np.integer)):
+            return v.item()
+        if isinstance(v, dict):
+            return {k: RunLog._plain(x) for k, x in v.items()}
+        return v
+
+    def _write(self, obj: dict):
+        self._fh.write(self._json.dumps(self._plain(obj), allow_nan=True) + "\n")
+
+    def record(self, sim, **extra):
+        o = sim.observe()
+        self._write({"event": "step", "step": int(o["step"]), "t": self._time.perf_counter() - self._t0,
+                     **o, **extra})
+
+    def close(self):
+        if self._fh:
+            self._write({"event": "close", "t": self._time.perf_counter() - self._t0})
+            self._fh.close()
+            self._fh = None
+
 class Sim:
     """One simulation on the current HIP device, built from a workload dict
     (see workloads.py).  precision: F64, F32, or F16 / BF16 (16-bit

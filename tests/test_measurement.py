@@ -117,3 +117,34 @@ def test_kernel_algorithmic_bytes_add_up_to_the_step():
         assert sum(per.values()) == total
         assert per["k_collide"] == n_gas * Q * ns * b
         assert per["k_moments"] == n_gas * Q * ns * b
+
+
+def test_run_log_writes_one_json_object_per_line(tmp_path):
+    """fdlbm.RunLog: an open line with the metadata, one line per record with
+    the step, elapsed seconds, every observable (arrays as lists, non-finite
+    values kept) and the caller's extras, and a close line."""
+    import json
+    import numpy as np
+    from paper_1804_07588_amd import fdlbm
+
+    class Fake:
+        def __init__(self):
+            self.k = 0
+
+        def observe(self):
+            self.k += 100
+            return {"step": np.int64(self.k), "mass": np.array([1.5, 2.5]), "e_gas": np.float64(3.0),
+                    "u_max": float("inf"), "bad": 0}
+
+    path = tmp_path / "run.jsonl"
+    log = fdlbm.RunLog(str(path), dict(run="test", n=8))
+    sim = Fake()
+    log.record(sim, residual={"max": 1e-3}, label="a")
+    log.record(sim, residual={"max": 5e-4}, label="a")
+    log.close()
+    lines = [json.loads(x) for x in path.read_text().splitlines()]
+    assert [x["event"] for x in lines] == ["open", "step", "step", "close"]
+    assert lines[0]["run"] == "test" and lines[0]["n"] == 8
+    assert lines[1]["step"] == 100 and lines[2]["step"] == 200
+    assert lines[2]["mass"] == [1.5, 2.5] and lines[2]["residual"]["max"] == 5e-4
+    assert lines[1]["u_max"] == float("inf") and lines[2]["t"] >= lines[1]["t"] >= 0

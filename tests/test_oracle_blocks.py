@@ -278,3 +278,41 @@ def test_transport_special_cases(oracle_lib):
     _, t2 = sim3.transport(rho, T)
     Dab = 0.05 * (T * 3) ** 1.5 * ((1 / 3) / p)
     assert np.allclose(t2, 1.0 * Dab / T, rtol=1e-13)
+
+
+@pytest.mark.parametrize("case", ["bed", "channel_cn"])
+def test_oracle_checkpoint_restart_is_bitwise(oracle_lib, case):
+    """oracle_save_state / oracle_load_state: run n steps, save, run m; restore,
+    run m again: every population, the solid temperature and every
+    observable are bitwise those of the first run, and the observables right
+    after the restore are those at the save."""
+    from paper_1804_07588_amd import workloads as W
+    of = oracle_lib
+    if case == "bed":
+        mask, _ = W.sphere_pack_mask(16, radius=3.0, porosity=0.6, seed=3, buffer=4)
+        cfg = W.packed_bed(mask=mask, k0=1e-3, force=1e-5)
+        init = W.perturbed_init(cfg, 4, amp_u=0.005)
+    else:
+        cfg = W.with_changes(W.channel_c1(), init=dict(X=[0.7, 0.3]), reaction=dict(k0=1e-2))
+        cfg["solid"].update(scheme=1, alpha_s=1.5)
+        init = W.perturbed_init(cfg, 8)
+    ns = len(cfg["species"]["M"])
+    sim = of.OracleSim(cfg, init)
+    sim.step(10)
+    saved_obs = sim.observe()
+    state = sim.save_state()
+    sim.step(15)
+    first = [sim.field(of.OF_POP, j) for j in range(ns)] + [sim.field(of.OF_TS)]
+    first_obs = sim.observe()
+    sim.load_state(state)
+    assert _same_obs(sim.observe(), saved_obs)
+    sim.step(15)
+    again = [sim.field(of.OF_POP, j) for j in range(ns)] + [sim.field(of.OF_TS)]
+    for a, b in zip(first, again):
+        assert np.array_equal(a, b)
+    assert _same_obs(sim.observe(), first_obs)
+    sim.close()
+
+
+def _same_obs(a, b):
+    return all(np.array_equal(np.asarray(a[k]), np.asarray(b[k])) for k in a)
