@@ -756,3 +756,38 @@ def test_flux_scaled_wall_source(oracle_lib, fd, prec):
     else:
         # slow perturbed 2-D flow: the velocity bound is taken per sound speed
         ok32(e, tol_u=np.inf, tol_ucs=3e-6)
+
+
+def n_species(cfg, ns, masses=(1.0, 2.0, 4.0, 9.0, 14.0, 22.0)):
+    """The configuration with ns species of the given masses: species 0 reacts
+    to species 1 at the walls (first order), the others are inert; binary
+    diffusivities from the masses, viscosities sqrt(M) scaled; the inlet and
+    initial composition equal fractions."""
+    M = list(masses[:ns])
+    X = [1.0 / ns] * ns
+    cfg = W.with_changes(cfg)
+    cfg["species"].update(M=M, mu0=[0.03 * np.sqrt(m) for m in M],
+                          Djk0=[[0.0 if j == k else 0.06 * np.sqrt(0.5 * (1 / M[j] + 1 / M[k]))
+                                 for k in range(ns)] for j in range(ns)])
+    cfg["reaction"].update(nu=[-1.0, 1.0] + [0.0] * (ns - 2), order=[1.0] + [0.0] * (ns - 1), k0=2e-3)
+    cfg["flow"]["X_in"] = X
+    cfg["init"]["X"] = X
+    cfg["species"].pop("Pr_j", None)
+    return cfg
+
+
+@pytest.mark.parametrize("lattice,ns", [(2, 4), (2, 6), (3, 4), (3, 6)])
+def test_four_and_six_species(oracle_lib, fd, lattice, ns):
+    """The kernels' instantiations for four and six species (the others run
+    in the cases above), on the random porous 2-D geometry and on a sphere
+    pack with inlet/outlet, in FP64 against the oracle, and in FP32 for six
+    species on the sphere pack."""
+    base = noisy_2d() if lattice == 2 else small_bed(n=16)
+    cfg = n_species(base, ns)
+    steps = 120 if lattice == 2 else 40
+    init = W.perturbed_init(cfg, 30 + ns, amp_u=0.005)
+    o, g = run_both(oracle_lib, fd, cfg, init, steps, fd.F64)
+    ok64(field_errors(o, g, fd, ns, lattice))
+    if lattice == 3 and ns == 6:
+        o, g = run_both(oracle_lib, fd, cfg, init, steps, fd.F32)
+        ok32(field_errors(o, g, fd, ns, lattice))
