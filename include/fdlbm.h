@@ -130,7 +130,8 @@ typedef struct {
  * units of Sec. 4.1 (one node per lattice spacing, one step per time step),
  * the number of gas species of the mixture and the precision.  *out owned
  * by the caller until fdlbm_destroy.  Errors: FDLBM_E_INVALID on bad sizes
- * or counts. */
+ * or counts, and on more than 2^30 nodes (the kernels address node-indexed
+ * tables with 32-bit byte offsets). */
 int fdlbm_create(const fdlbm_desc *d, fdlbm_ctx **out);
 
 /* Release the context (no step of the method).  Does not free the
@@ -148,7 +149,12 @@ const char *fdlbm_last_error(const fdlbm_ctx *ctx);
  * fractions, temperature and velocity of x = nx-3); x must then be
  * non-periodic, those planes gas and x = nx-3 gas wherever the outlet is.
  * FDLBM_E_GEOMETRY if no gas node exists, a gas node touches a closed domain
- * edge or an outlet row has no interior gas node to copy. */
+ * edge or an outlet row has no interior gas node to copy; FDLBM_E_INVALID if
+ * one direction's populations (gas and wall nodes times the stored record:
+ * 4 bytes per species in FP32, 8 in FP64, 2 in 16-bit storage, rounded up to
+ * an even count) would exceed 4 GiB, the span the population gathers
+ * address with 32-bit offsets (FP32 with five species: about 214 million gas
+ * and wall nodes, a 640^3 bed). */
 int fdlbm_set_geometry(fdlbm_ctx *ctx, const uint8_t *mask_host, int inout);
 
 /* Species and transport (Sec. 3, Eq.(7)-(8), (14)-(17), (19)-(21)):

@@ -524,6 +524,14 @@ int fdlbm_set_geometry(fdlbm_ctx *c, const uint8_t *mask, int inout) {
     c->wem[w] = c->emask[c->wall_list[w]];
   }
   layout(c);
+  // the population gathers use 32-bit byte offsets within one direction's
+  // array: n_gas + n_wall slots of rec_count values each must stay below 4 GiB
+  const double span = (double)c->nsl * rec_count(c) * (double)pop_size(c);
+  if (span >= 4294967296.0)
+    return set_err(c, FDLBM_E_INVALID,
+                   "%zu gas and wall nodes: one direction's populations would take %.3g bytes, "
+                   "more than the 4 GiB the kernels address",
+                   c->gas_list.size() + c->wall_list.size(), span);
   c->geometry_set = true;
   return FDLBM_OK;
 }
@@ -553,8 +561,9 @@ int fdlbm_create(const fdlbm_desc *d, fdlbm_ctx **out) {
       d->nz < 1 || (d->lattice == FDLBM_D2Q9 && d->nz != 1) || d->n_species < 1 ||
       d->n_species > MAX_NS || d->precision < FDLBM_F64 || d->precision > FDLBM_BF16)
     return FDLBM_E_INVALID;
+  // node lookups (slot of a node, 4 bytes) use 32-bit byte offsets
   const double nn = (double)d->nx * d->ny * d->nz;
-  if (nn > 2.0e9 || nn * d->n_species * 19 > 9.0e18) return FDLBM_E_INVALID;
+  if (nn > 1073741824.0) return FDLBM_E_INVALID;
   fdlbm_ctx *c = new fdlbm_ctx();
   c->d = *d;
   c->D = d->lattice;

@@ -147,14 +147,15 @@ __device__ inline void st(T *__restrict__ base, int idx, T v) {
 
 // N consecutive values: record `rec` of an array of N-value records, moved as
 // one contiguous access per lane (the compiler splits it into the widest
-// loads and stores the element alignment allows)
+// loads and stores the element alignment allows).  64-bit byte offsets: the
+// moment records (up to 192 bytes per slot) exceed 4 GiB on large domains.
 template <typename real, int N>
 struct Rec {
   real v[N];
 };
 template <typename real, int N>
 __device__ inline Rec<real, N> ldrec(const real *__restrict__ base, int rec) {
-  const uint32_t off = uint32_t(rec) * uint32_t(N * sizeof(real));
+  const size_t off = size_t(rec) * (N * sizeof(real));
   const real *p = reinterpret_cast<const real *>(reinterpret_cast<const char *>(base) + off);
   Rec<real, N> r;
   __builtin_memcpy(&r, p, sizeof r);
@@ -162,7 +163,7 @@ __device__ inline Rec<real, N> ldrec(const real *__restrict__ base, int rec) {
 }
 template <typename real, int N>
 __device__ inline void strec(real *__restrict__ base, int rec, const Rec<real, N> &r) {
-  const uint32_t off = uint32_t(rec) * uint32_t(N * sizeof(real));
+  const size_t off = size_t(rec) * (N * sizeof(real));
   real *p = reinterpret_cast<real *>(reinterpret_cast<char *>(base) + off);
   __builtin_memcpy(p, &r, sizeof r);
 }
@@ -185,7 +186,10 @@ __device__ inline Rec<real, NS> pop_load_raw(const PT *__restrict__ Gi, int slot
 #pragma unroll
     for (int j = 0; j < NS; ++j) r.v[j] = real(float(h[j]));
   } else {
-    r = ldrec<real, NS>(Gi, slot);
+    // 32-bit byte offset within one direction's array (the geometry set-up
+    // rejects domains whose per-direction arrays would exceed 4 GiB)
+    const uint32_t off = uint32_t(slot) * uint32_t(NS * sizeof(real));
+    __builtin_memcpy(&r, reinterpret_cast<const char *>(Gi) + off, sizeof r);
   }
   return r;
 }

@@ -78,6 +78,12 @@ def test_invalid_inputs_are_rejected(L):
     bad = fdlbm.Desc(7, 4, 4, 1, (ct.c_int * 3)(1, 1, 1), 0, 1, None)
     h = ct.c_void_p()
     assert L.fdlbm_create(ct.byref(bad), ct.byref(h)) == fdlbm.E_INVALID
+    # more than 2^30 nodes: beyond the kernels' 32-bit node-table offsets
+    huge = fdlbm.Desc(3, 1025, 1024, 1024, (ct.c_int * 3)(1, 1, 1), fdlbm.F32, 5, None)
+    assert L.fdlbm_create(ct.byref(huge), ct.byref(h)) == fdlbm.E_INVALID
+    ok = fdlbm.Desc(3, 1024, 1024, 1024, (ct.c_int * 3)(1, 1, 1), fdlbm.F32, 5, None)
+    assert L.fdlbm_create(ct.byref(ok), ct.byref(h)) == fdlbm.OK
+    L.fdlbm_destroy(h)
     h = make_ctx(L, cfg)
     # step / init before the workspace exists
     assert L.fdlbm_step(h, 1) == fdlbm.E_STATE
