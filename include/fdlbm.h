@@ -94,6 +94,7 @@ extern "C" {
 #define FDLBM_FIELD_KIND 5    /* node class: 0 gas 1 solid 2 wall 3 inlet 4 outlet */
 #define FDLBM_FIELD_WALL_R 6  /* molar rate per wall node in the last step      */
 #define FDLBM_FIELD_WALL_DE 7 /* kinetic energy the wall gave the gas, last step */
+#define FDLBM_FIELD_X 8       /* mole fraction (comp = species), Eq.(14)        */
 
 #define FDLBM_MAX_SPECIES 8
 
@@ -376,6 +377,16 @@ int fdlbm_residual(fdlbm_ctx *ctx, double *r5);
  * exchange per wall node.  Valid after at least one step.  FDLBM_E_INVALID
  * for an unknown field or component. */
 int fdlbm_get_field(fdlbm_ctx *ctx, int field, int comp, double *dst_host);
+
+/* The same fields into a caller-owned device buffer dst_device (n doubles,
+ * node order), without a host round trip: RHO, X, U, T, TS, KIND, WALL_R,
+ * WALL_DE (not POP).  Enqueued on the context's stream (ordered after the
+ * steps enqueued before it; no synchronisation); bitwise the values
+ * fdlbm_get_field returns.  X_j = (rho_j / M_j) / sum_k (rho_k / M_k) at gas
+ * and wall nodes, 0 elsewhere.  FDLBM_E_INVALID for POP, an unknown field or
+ * component; FDLBM_E_STATE before the first step (TS and KIND: after
+ * fdlbm_init_fields). */
+int fdlbm_get_field_device(fdlbm_ctx *ctx, int field, int comp, double *dst_device);
 
 /* Checkpoint (no step of the method): bytes needed, save to / restore from
  * a host buffer (bitwise: the whole device state of the step of

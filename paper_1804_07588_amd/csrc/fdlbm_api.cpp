@@ -1278,6 +1278,26 @@ int fdlbm_get_field(fdlbm_ctx *c, int field, int comp, double *dst) {
         dst[x] = (gaslike(c->kind[x]) || c->kind[x] == KIND_WALL) ? v[(size_t)c->slot_of[x] * NR + k] : 0.0;
       return FDLBM_OK;
     }
+    case FDLBM_FIELD_X: {
+      if (c->step == 0) return set_err(c, FDLBM_E_STATE, "moments exist after the first step");
+      if (comp < 0 || comp >= c->ns) return set_err(c, FDLBM_E_INVALID, "bad species");
+      const size_t NR = (size_t)fr_count(c->D, c->ns);
+      std::vector<double> v((size_t)c->nsl * NR);
+      rc = f64 ? copy_field<double>(c, c->off_FR, v.size(), v.data())
+               : copy_field<float>(c, c->off_FR, v.size(), v.data());
+      if (rc) return rc;
+      for (size_t x = 0; x < n; ++x) {
+        // the same arithmetic as the device copy (fdlbm_get_field_device)
+#pragma clang fp contract(off)
+        dst[x] = 0.0;
+        if (!(gaslike(c->kind[x]) || c->kind[x] == KIND_WALL)) continue;
+        const double *r = &v[(size_t)c->slot_of[x] * NR];
+        double C = 0.0;
+        for (int j = 0; j < c->ns; ++j) C += r[fr_rho(c->D, j)] * (1.0 / c->M[j]);
+        dst[x] = C > 0.0 ? r[fr_rho(c->D, comp)] * (1.0 / c->M[comp]) / C : 0.0;
+      }
+      return FDLBM_OK;
+    }
     case FDLBM_FIELD_TS:
       rc = cp(c->off_Ts[c->cur], n);
       if (rc) return rc;
@@ -1323,6 +1343,113 @@ int fdlbm_get_field(fdlbm_ctx *c, int field, int comp, double *dst) {
       return FDLBM_OK;
   }
   return set_err(c, FDLBM_E_INVALID, "unknown field");
+}
+
+// Fields into a device buffer (node order, FP64): a gather from the slot
+// records, or a masked copy of a node-ordered array.
+namespace {
+constexpr int FIELD_BLOCK = 256;
+struct InvM {
+  double v[MAXS];
+};
+// mode 0: record entry k; 1: mole fraction of species k; 2: zero
+template <typename real>
+__global__ void __launch_bounds__(FIELD_BLOCK) k_field_rec(const real *__restrict__ FR, int NR, int mode, int k,
+                                                          int D, int ns, InvM im,
+                                                          const int32_t *__restrict__ slot_of,
+                                                          const uint8_t *__restrict__ kind, int n,
+                                                          double *__restrict__ dst) {
+  const int x = blockIdx.x * FIELD_BLOCK + threadIdx.x;
+  if (x >= n) return;
+  const uint8_t kd = kind[x];
+  double v = 0.0;
+  if (mode != 2 && (gaslike(kd) || kd == KIND_WALL)) {
+    const real *r = FR + (size_t)slot_of[x] * NR;
+    if (mode == 0) {
+      v = (double)r[k];
+    } else {
+      // no fused multiply-add: the host copy rounds each product
+#pragma clang fp contract(off)
+      double C = 0.0;
+      for (int j = 0; j < ns; ++j) C += (double)r[fr_rho(D, j)] * im.v[j];
+      v = C > 0.0 ? (double)r[fr_rho(D, k)] * im.v[k] / C : 0.0;
+    }
+  }
+  dst[x] = v;
+}
+// mode 0: solid and wall nodes; 1: wall nodes; 2: every node (a byte array)
+template <typename real>
+__global__ void __launch_bounds__(FIELD_BLOCK) k_field_node(const real *__restrict__ a,
+                                                           const uint8_t *__restrict__ bytes, int mode,
+                                                           const uint8_t *__restrict__ kind, int n,
+                                                           double *__restrict__ dst) {
+  const int x = blockIdx.x * FIELD_BLOCK + threadIdx.x;
+  if (x >= n) return;
+  const uint8_t kd = kind[x];
+  double v;
+  if (mode == 2) v = (double)bytes[x];
+  else if (mode == 1) v = kd == KIND_WALL ? (double)a[x] : 0.0;
+  else v = (kd == KIND_SOLID || kd == KIND_WALL) ? (double)a[x] : 0.0;
+  dst[x] = v;
+}
+}  // namespace
+
+template <typename real>
+static int field_device(fdlbm_ctx *c, int field, int comp, double *dst) {
+  const int n = (int)c->n;
+  const dim3 grid((unsigned)((n + FIELD_BLOCK - 1) / FIELD_BLOCK)), blk(FIELD_BLOCK);
+  const real *FR = reinterpret_cast<const real *>(c->ws + c->off_FR);
+  const int32_t *so = reinterpret_cast<const int32_t *>(c->ws + c->off_slot);
+  const uint8_t *kind = reinterpret_cast<const uint8_t *>(c->ws + c->off_kind);
+  const int NR = fr_count(c->D, c->ns);
+  InvM im{};
+  for (int j = 0; j < c->ns; ++j) im.v[j] = 1.0 / c->M[j];
+  switch (field) {
+    case FDLBM_FIELD_RHO:
+    case FDLBM_FIELD_X:
+    case FDLBM_FIELD_U:
+    case FDLBM_FIELD_T: {
+      int mode = 0, k = 0;
+      if (field == FDLBM_FIELD_RHO || field == FDLBM_FIELD_X) {
+        if (comp < 0 || comp >= c->ns) return set_err(c, FDLBM_E_INVALID, "bad species");
+        mode = field == FDLBM_FIELD_X ? 1 : 0;
+        k = field == FDLBM_FIELD_X ? comp : fr_rho(c->D, comp);
+      } else if (field == FDLBM_FIELD_U) {
+        if (comp < 0 || comp > 2) return set_err(c, FDLBM_E_INVALID, "bad axis");
+        mode = comp >= c->D ? 2 : 0;
+        k = comp >= c->D ? 0 : fr_u(comp);
+      } else {
+        k = fr_T(c->D);
+      }
+      hipLaunchKernelGGL(k_field_rec<real>, grid, blk, 0, c->stream, FR, NR, mode, k, c->D, c->ns, im, so,
+                         kind, n, dst);
+      break;
+    }
+    case FDLBM_FIELD_TS:
+    case FDLBM_FIELD_WALL_R:
+    case FDLBM_FIELD_WALL_DE: {
+      const size_t off = field == FDLBM_FIELD_TS ? c->off_Ts[c->cur] : field == FDLBM_FIELD_WALL_R ? c->off_wr : c->off_wde;
+      hipLaunchKernelGGL(k_field_node<real>, grid, blk, 0, c->stream, reinterpret_cast<const real *>(c->ws + off),
+                         nullptr, field == FDLBM_FIELD_TS ? 0 : 1, kind, n, dst);
+      break;
+    }
+    case FDLBM_FIELD_KIND:
+      hipLaunchKernelGGL(k_field_node<real>, grid, blk, 0, c->stream, nullptr, kind, 2, kind, n, dst);
+      break;
+    default:
+      return set_err(c, FDLBM_E_INVALID, "field not available on the device");
+  }
+  HIPCHK(c, hipGetLastError());
+  return FDLBM_OK;
+}
+
+int fdlbm_get_field_device(fdlbm_ctx *c, int field, int comp, double *dst_device) {
+  if (!c || !dst_device) return FDLBM_E_INVALID;
+  if (!c->initialized) return set_err(c, FDLBM_E_STATE, "initialise the fields first");
+  if (c->step == 0 && field != FDLBM_FIELD_TS && field != FDLBM_FIELD_KIND)
+    return set_err(c, FDLBM_E_STATE, "moments and wall values exist after the first step");
+  return c->d.precision == FDLBM_F64 ? field_device<double>(c, field, comp, dst_device)
+                                     : field_device<float>(c, field, comp, dst_device);
 }
 
 // checkpoint: header, populations (current buffer), solid temperature,

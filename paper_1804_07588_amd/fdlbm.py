@@ -23,7 +23,7 @@ D2Q9, D3Q19 = 2, 3
 F64, F32, F16, BF16 = 0, 1, 2, 3  # F16/BF16: 16-bit population storage, FP32 arithmetic
 CORR_DIFFUSION, CORR_VISCOUS, CORR_ENERGY, CORR_PRANDTL, CORR_ALL = 1, 2, 4, 8, 15
 WALL_REACTIVE, WALL_ISOTHERMAL = 0, 1
-FIELD_RHO, FIELD_U, FIELD_T, FIELD_TS, FIELD_POP, FIELD_KIND, FIELD_WALL_R, FIELD_WALL_DE = range(8)
+FIELD_RHO, FIELD_U, FIELD_T, FIELD_TS, FIELD_POP, FIELD_KIND, FIELD_WALL_R, FIELD_WALL_DE, FIELD_X = range(9)
 K_WALL, K_MOMENTS, K_COLLIDE, K_SOLID = range(4)
 RATE_PER_NODE, RATE_PER_AREA = 0, 1
 SOURCE_LATTICE, SOURCE_FLUX = 0, 1
@@ -41,7 +41,7 @@ EXPORTS = ["fdlbm_create", "fdlbm_destroy", "fdlbm_last_error", "fdlbm_set_geome
            "fdlbm_batch_set_active", "fdlbm_batch_step", "fdlbm_batch_set_grid",
            "fdlbm_batch_get_grid", "fdlbm_batch_autotune", "fdlbm_batch_set_overlap",
            "fdlbm_set_sync_check", "fdlbm_last_step", "fdlbm_observe_noalloc", "fdlbm_set_rate_scaling",
-           "fdlbm_set_wall_source",
+           "fdlbm_set_wall_source", "fdlbm_get_field_device",
            "fdlbm_set_solid_coupling"]
 BATCH_KINDS = ["wall_fast", "wall_slow", "gas_fast", "gas_slow", "collide", "solid"]
 
@@ -118,6 +118,7 @@ def lib() -> ct.CDLL:
         L.fdlbm_set_sync_check.argtypes = [vp, i64]
         L.fdlbm_set_rate_scaling.argtypes = [vp, ct.c_int]
         L.fdlbm_set_wall_source.argtypes = [vp, ct.c_int]
+        L.fdlbm_get_field_device.argtypes = [vp, ct.c_int, ct.c_int, vp]
         L.fdlbm_set_solid_coupling.argtypes = [vp, ct.c_int]
         L.fdlbm_last_step.argtypes = [vp, ct.POINTER(i64)]
         ip = ct.POINTER(ct.c_int)
@@ -317,6 +318,20 @@ class Sim:
         size = self.Q * self.n if fid == FIELD_POP else self.n
         out = np.zeros(size)
         self._check(lib().fdlbm_get_field(self.h, fid, comp, _d(out)))
+        return out
+
+    def field_device(self, fid: int, comp: int = 0, out=None):
+        """The field as a float64 torch tensor on the device (n values, node
+        order), filled on the context's stream without a host round trip;
+        `out` (a contiguous float64 device tensor of n values) is reused if
+        given."""
+        import torch
+        if out is None:
+            with torch.cuda.stream(self.stream):
+                out = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        if not (out.is_cuda and out.dtype == torch.float64 and out.is_contiguous() and out.numel() == self.n):
+            raise FdlbmError(E_INVALID, "out must be a contiguous float64 device tensor of n values")
+        self._check(lib().fdlbm_get_field_device(self.h, fid, comp, ct.c_void_p(out.data_ptr())))
         return out
 
     def save_state(self) -> bytes:

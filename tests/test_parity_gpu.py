@@ -791,3 +791,36 @@ def test_four_and_six_species(oracle_lib, fd, lattice, ns):
     if lattice == 3 and ns == 6:
         o, g = run_both(oracle_lib, fd, cfg, init, steps, fd.F32)
         ok32(field_errors(o, g, fd, ns, lattice))
+
+
+@pytest.mark.parametrize("prec", ["F64", "F32"])
+def test_fields_on_device_and_mole_fractions(oracle_lib, fd, prec):
+    """fdlbm_get_field_device: every field it offers equals the host copy of
+    fdlbm_get_field bitwise; the mole fractions X_j = (rho_j/M_j)/sum_k
+    (rho_k/M_k) against the oracle's densities (FP64 1e-12, FP32 1e-5);
+    populations are refused on the device path."""
+    import torch
+    cfg = small_bed(n=16)
+    M = np.asarray(cfg["species"]["M"])
+    ns = len(M)
+    o, g = run_both(oracle_lib, fd, cfg, W.perturbed_init(cfg, 21, amp_u=0.005), 20, getattr(fd, prec))
+    cases = [(fd.FIELD_RHO, j) for j in range(ns)] + [(fd.FIELD_X, j) for j in range(ns)]
+    cases += [(fd.FIELD_U, a) for a in range(3)] + [(fd.FIELD_T, 0), (fd.FIELD_TS, 0), (fd.FIELD_KIND, 0),
+                                                    (fd.FIELD_WALL_R, 0), (fd.FIELD_WALL_DE, 0)]
+    buf = None
+    for fid, comp in cases:
+        buf = g.field_device(fid, comp, out=buf)
+        torch.cuda.synchronize()
+        assert np.array_equal(buf.cpu().numpy(), g.field(fid, comp)), (fid, comp)
+    kind = g.field(fd.FIELD_KIND)
+    live = (kind == 0) | (kind >= 2)
+    ro = np.stack([o.field(of.OF_RHO, j) for j in range(ns)])
+    Co = (ro / M[:, None]).sum(0)
+    tol = TOL64 if prec == "F64" else TOL32
+    for j in range(ns):
+        x = g.field(fd.FIELD_X, j)
+        xo = np.where(live, ro[j] / M[j] / np.where(live, Co, 1.0), 0.0)
+        assert rel_err(x, xo) <= tol, (j, rel_err(x, xo))
+        assert np.all(x[~live] == 0.0)
+    with pytest.raises(fd.FdlbmError):
+        g.field_device(fd.FIELD_POP, 0)
