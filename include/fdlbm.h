@@ -477,6 +477,15 @@ int fdlbm_batch_set_active(fdlbm_batch *b, const uint8_t *active);
  * counters. */
 int fdlbm_batch_step(fdlbm_batch *b, int64_t n_steps);
 
+/* Stability check of a batch (failure detection of the step, as
+ * fdlbm_step's checked mode): synchronises the stream and reads every
+ * sample's stability record.  FDLBM_E_UNSTABLE if a sample has had a gas
+ * node with a non-finite or negative density or temperature, with *sample
+ * the lowest such sample index and *step its first such step (counted like
+ * fdlbm_obs.step, the same as fdlbm_last_step on that member); otherwise
+ * FDLBM_OK with both set to -1. */
+int fdlbm_batch_check(fdlbm_batch *b, int *sample, int64_t *step);
+
 /* Persistent grid per launch kind (FDLBM_BL_COUNT values, positive multiples
  * of 8 workgroups; NULL keeps them) and steps per captured graph (even, > 0;
  * 0 keeps it).  Drops captured graphs. */

@@ -1831,6 +1831,27 @@ int fdlbm_batch_step(fdlbm_batch *b, int64_t n_steps) {
   return FDLBM_OK;
 }
 
+int fdlbm_batch_check(fdlbm_batch *b, int *sample, int64_t *step) {
+  if (!b || !sample || !step) return FDLBM_E_INVALID;
+  if (!b->bound) return bset_err(b, FDLBM_E_STATE, "bind the batch workspace first");
+  *sample = -1;
+  *step = -1;
+  BHIPCHK(b, hipStreamSynchronize(b->stream));
+  for (int s = 0; s < b->n; ++s) {
+    int64_t bad = -1;
+    if (read_status(b->ctx[s], &bad) != FDLBM_OK)
+      return bset_err(b, FDLBM_E_HIP, "sample %d: %s", s, b->ctx[s]->err.c_str());
+    if (bad >= 0) {
+      *sample = s;
+      *step = bad;
+      return bset_err(b, FDLBM_E_UNSTABLE,
+                      "sample %d: non-finite or negative density or temperature first seen in step %lld", s,
+                      (long long)bad);
+    }
+  }
+  return FDLBM_OK;
+}
+
 // Autotuner of the persistent launch shapes: for each candidate grid size
 // (workgroups per launch, a multiple of 8) every launch kind is timed with
 // HIP events over `steps` steps (after one warm-up step), and each kind keeps

@@ -41,7 +41,7 @@ EXPORTS = ["fdlbm_create", "fdlbm_destroy", "fdlbm_last_error", "fdlbm_set_geome
            "fdlbm_batch_set_active", "fdlbm_batch_step", "fdlbm_batch_set_grid",
            "fdlbm_batch_get_grid", "fdlbm_batch_autotune", "fdlbm_batch_set_overlap",
            "fdlbm_set_sync_check", "fdlbm_last_step", "fdlbm_observe_noalloc", "fdlbm_set_rate_scaling",
-           "fdlbm_set_wall_source", "fdlbm_get_field_device",
+           "fdlbm_set_wall_source", "fdlbm_get_field_device", "fdlbm_batch_check",
            "fdlbm_set_solid_coupling"]
 BATCH_KINDS = ["wall_fast", "wall_slow", "gas_fast", "gas_slow", "collide", "solid"]
 
@@ -119,6 +119,7 @@ def lib() -> ct.CDLL:
         L.fdlbm_set_rate_scaling.argtypes = [vp, ct.c_int]
         L.fdlbm_set_wall_source.argtypes = [vp, ct.c_int]
         L.fdlbm_get_field_device.argtypes = [vp, ct.c_int, ct.c_int, vp]
+        L.fdlbm_batch_check.argtypes = [vp, ct.POINTER(ct.c_int), ct.POINTER(i64)]
         L.fdlbm_set_solid_coupling.argtypes = [vp, ct.c_int]
         L.fdlbm_last_step.argtypes = [vp, ct.POINTER(i64)]
         ip = ct.POINTER(ct.c_int)
@@ -233,6 +234,7 @@ class RunLog:
             self._write({"event": "close", "t": self._time.perf_counter() - self._t0})
             self._fh.close()
             self._fh = None
+
 
 class Sim:
     """One simulation on the current HIP device, built from a workload dict
@@ -407,6 +409,18 @@ class Batch:
 
     def step(self, n: int = 1):
         self._check(lib().fdlbm_batch_step(self.h, int(n)))
+
+    def check(self):
+        """Synchronise and read every sample's stability record: None if all
+        are sound, else raise FdlbmError (code E_UNSTABLE) whose `sample` and
+        `step` name the lowest unstable sample and its first unstable step."""
+        s, st = ct.c_int(), ct.c_int64()
+        rc = lib().fdlbm_batch_check(self.h, ct.byref(s), ct.byref(st))
+        if rc != OK:
+            err = FdlbmError(rc, lib().fdlbm_batch_last_error(self.h).decode())
+            err.sample, err.step = s.value, st.value
+            raise err
+        return None
 
     def set_active(self, active):
         a = np.ascontiguousarray(np.asarray(active, dtype=np.uint8).reshape(-1))

@@ -201,3 +201,34 @@ def test_batch_of_benchmark_beds(fd, stream, oracle_lib):
     assert np.abs(g - r).max() / np.abs(r).max() < 1e-5
     o.close()
     b.close()
+
+
+@pytest.mark.parametrize("prec", ["F64", "F32"])
+def test_batch_check_names_the_unstable_sample(fd, stream, prec):
+    """fdlbm_batch_check: three channels batched, the middle one driven past
+    the lattice sound speed by a body force of 0.02 per step (the blow-up of
+    test_parity_gpu's unstable-step test); the check reports that sample and
+    the step at which it alone, stepped on its own context, first turns
+    non-physical; before that step the check is clean."""
+    precision = getattr(fd, prec)
+    base = W.with_changes(W.channel_c1(nx=16, ny=16, wall=2), init=dict(X=[0.7, 0.3]))
+    cfgs = [W.with_changes(base, flow=dict(F=[F, 0, 0])) for F in (1e-6, 0.02, 2e-6)]
+    init = W.uniform_init(base)
+    ref = fd.Sim(cfgs[1], precision=precision, init=init)
+    ref.step(300)
+    s_bad = ref.last_step()
+    ref.close()
+    assert s_bad > 10, s_bad
+    print(f"[batch] {prec}: sample 1 first unstable at step {s_bad}", flush=True)
+    sims = [fd.Sim(c, precision=precision, init=init, stream=stream) for c in cfgs]
+    b = fd.Batch(sims)
+    b.set_grid(graph_steps=4)
+    b.step(s_bad - 3)
+    assert b.check() is None
+    b.step(40)
+    with pytest.raises(fd.FdlbmError) as ei:
+        b.check()
+    assert ei.value.code == fd.E_UNSTABLE
+    assert (ei.value.sample, ei.value.step) == (1, s_bad)
+    assert sims[0].last_step() == -1 and sims[2].last_step() == -1
+    b.close()
