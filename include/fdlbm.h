@@ -273,6 +273,25 @@ int fdlbm_set_rate_scaling(fdlbm_ctx *ctx, int mode);
 #define FDLBM_SOURCE_FLUX 1
 int fdlbm_set_wall_source(fdlbm_ctx *ctx, int mode);
 
+/* Where the diffusive wall sits (Sec. 4.3).  FDLBM_WALL_ON_NODE (the
+ * default): on the wall node, which thermalises at its own state
+ * f^eq(rho_w, 0, T_w) (Eq.(39)).  FDLBM_WALL_HALFWAY: half-way between the
+ * wall node and each gas node it emits into; the paper names the extra
+ * interpolation step this needs without giving it, and the reading here is
+ * the linear one: along link i into gas node x the wall node emits
+ * rho_w f^eq_i(1, -u(x), 2 T_w - T(x)), the state whose linear interpolant
+ * with x takes the wall's velocity (zero) and temperature at the link's
+ * midpoint, with u(x) and T(x) from x's moments of the previous step.  rho_w
+ * still solves the mass balance of Eq.(41) with these weights, so mass and
+ * energy stay conserved.  A Poiseuille channel's velocity zeros then sit half
+ * a node from the wall nodes.  The moments pass then waits for the wall
+ * kernel (which reads the moments it overwrites), so the step loses the wall
+ * kernel's overlap.  Not batched (fdlbm_batch_create fails).  FDLBM_E_INVALID
+ * for another value.  Takes effect at the next step. */
+#define FDLBM_WALL_ON_NODE 0
+#define FDLBM_WALL_HALFWAY 1
+int fdlbm_set_wall_position(fdlbm_ctx *ctx, int position);
+
 /* Flow: body force per unit mass F3[3]; inlet mole fractions X_in[ns],
  * pressure p_in and temperature T_in (used when inout = 1). */
 int fdlbm_set_flow(fdlbm_ctx *ctx, const double *F3, const double *X_in, double p_in,

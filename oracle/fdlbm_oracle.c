@@ -80,6 +80,7 @@ struct oracle_sim {
   int rate_area;    /* 1: rate scaled by the wall node's wetted area (reading) */
   int src_flux;     /* 1: wall source scaled by 1/c_j (stoichiometric mass flux, reading) */
   int eq48;         /* 1: solid-gas coupling of Eq.(48) instead of the flux-matched one */
+  int halfway;      /* 1: wall placed half-way along each link (Sec. 4.3, reading) */
   /* cumulative counters */
   double moles, heat, bheat, work;
   int64_t step;
@@ -800,6 +801,32 @@ static double wall_temperature(const oracle_sim *s, int w) {
   return s->wall_mode == 1 ? s->T_iso : s->Ts[w];
 }
 
+/* Emission weight of the wall node w along link i (into the gas node
+ * x = w + e_i) for species j, per unit wall density.
+ * Default: the wall sits on the solid node and thermalises at its own state,
+ * f^eq_ji(1, U_w, T_w) (Eq.(39)).
+ * Option (reading of Sec. 4.3's half-way wall, whose interpolation step the
+ * paper leaves to the work it cites): the wall sits half-way along each link.
+ * The state the wall node emits at is the one that puts the wall's values at
+ * the link's midpoint when interpolated linearly with the gas node x: velocity
+ * 2 U_w - u(x) and temperature 2 T_w - T(x), with u(x) and T(x) from x's
+ * latest moments (the previous step).  The wall density still solves the
+ * mass balance of Eq.(41) with these weights, so mass and (through Delta
+ * E_gas) energy stay conserved link by link. */
+static double emit_weight(const oracle_sim *s, int w, int j, int i, double Tw) {
+  if (!s->halfway) return wall_weight(s, w, j, i, Tw);
+  size_t n = (size_t)s->n;
+  int x = shift(s, w, i, 1);
+  double ul[3], f[MAXQ];
+  for (int a = 0; a < 3; ++a) {
+    double uw = s->wall_u ? s->wall_u[(size_t)a * n + w] : 0.0;
+    ul[a] = 2.0 * uw - s->u[(size_t)a * n + x];
+  }
+  if (s->D == 2) ul[2] = 0.0;
+  equilibrium(s->D, s->Q, s->c, 1.0, s->M[j], ul, 2.0 * Tw - s->T[x], f);
+  return f[i];
+}
+
 /* reading: initial populations g = f^eq of the given state; wall nodes emit
  * rho_w w_i(T_w) with rho_w the mean of the given densities of their gas
  * link partners */
@@ -817,7 +844,11 @@ int oracle_init_fields(oracle_sim *s, const double *rho, const double *u, const 
       if (s->D == 2) uu[2] = 0.0;
       equilibrium(s->D, Q, s->c, rho[(size_t)j * n + node], s->M[j], uu, T[node], f);
       for (int i = 0; i < Q; ++i) *pop(s, s->G, j, i, node) = f[i];
+      s->rho[(size_t)j * n + node] = rho[(size_t)j * n + node];
     }
+    /* the gas state before the first step (read by the half-way wall) */
+    for (int a = 0; a < 3; ++a) s->u[(size_t)a * n + node] = a < s->D ? u[(size_t)a * n + node] : 0.0;
+    s->T[node] = T[node];
   }
   for (int node = 0; node < n; ++node) {
     if (s->kind[node] != K_WALL) continue;
@@ -894,7 +925,7 @@ static void wall_bc(oracle_sim *s) {
         }
       }
       if (emits(s, w, i))
-        for (int j = 0; j < ns; ++j) Z[j] += wall_weight(s, w, j, i, Tw);
+        for (int j = 0; j < ns; ++j) Z[j] += emit_weight(s, w, j, i, Tw);
     }
     /* Eq.(40)-(41): emitted populations rho_w f^eq(1, U_w, T_w); the wall
      * density of species j satisfies rho_w Z_j = A_j + nu_j M_j r, i.e. the
@@ -958,7 +989,7 @@ static void wall_bc(oracle_sim *s) {
       double c2 = (double)(s->c[i][0] * s->c[i][0] + s->c[i][1] * s->c[i][1] +
                            s->c[i][2] * s->c[i][2]);
       for (int j = 0; j < ns; ++j) {
-        double W = rw[j] * wall_weight(s, w, j, i, Tw);
+        double W = rw[j] * emit_weight(s, w, j, i, Tw);
         *pop(s, s->Gn, j, i, w) = W;
         Eout += s->cj[j] * s->cj[j] * c2 * W;
       }
@@ -1593,6 +1624,13 @@ int oracle_set_source_flux(oracle_sim *s, int on) {
 int oracle_set_rate_area(oracle_sim *s, int on) {
   if (!s) return fail(s, "null simulation");
   s->rate_area = on != 0;
+  return 0;
+}
+
+int oracle_set_wall_position(oracle_sim *s, int halfway) {
+  if (!s) return fail(s, "null simulation");
+  if (halfway != 0 && halfway != 1) return fail(s, "wall position must be 0 (on the node) or 1 (half-way)");
+  s->halfway = halfway;
   return 0;
 }
 

@@ -99,6 +99,10 @@ int oracle_set_coupling(oracle_sim *s, int eq48);
 int oracle_set_rate_area(oracle_sim *s, int on);
 /* wall source in population units: nu_j M_j r (0, default) or nu_j M_j r / c_j (1) */
 int oracle_set_source_flux(oracle_sim *s, int on);
+/* wall position: on the solid node (0, default, Eq.(39)) or half-way along
+ * each link (1): the wall node emits at the state extrapolated through the
+ * link's midpoint from the gas node it emits into (Sec. 4.3, reading) */
+int oracle_set_wall_position(oracle_sim *s, int halfway);
 /* f* temperature: 0 the energy-holding reading (default), 1 Eq.(6) as printed */
 int oracle_set_literal_eq6(oracle_sim *s, int on);
 /* overwrite the populations of species comp (Q*n values, OF_POP layout) */

@@ -90,6 +90,7 @@ def lib():
         L.oracle_set_literal_eq6.argtypes = [ct.c_void_p, ct.c_int]
         L.oracle_set_rate_area.argtypes = [ct.c_void_p, ct.c_int]
         L.oracle_set_source_flux.argtypes = [ct.c_void_p, ct.c_int]
+        L.oracle_set_wall_position.argtypes = [ct.c_void_p, ct.c_int]
         L.oracle_set_coupling.argtypes = [ct.c_void_p, ct.c_int]
         L.oracle_set_threads.argtypes = [ct.c_int]
         L.oracle_init_fields.argtypes = [ct.c_void_p, dp, dp, dp, dp]
@@ -212,6 +213,8 @@ class OracleSim:
             self._check(L.oracle_set_rate_area(h, 1))
         if rx.get("source_flux"):
             self._check(L.oracle_set_source_flux(h, 1))
+        if rx.get("halfway"):
+            self._check(L.oracle_set_wall_position(h, 1))
         if cfg.get("literal_eq6"):
             self._check(L.oracle_set_literal_eq6(h, 1))
         if cfg.get("wall_u") is not None:

@@ -46,6 +46,7 @@ struct fdlbm_ctx {
   int wall_mode = 0, max_iter = 64;
   bool rate_area = false;  // rate per unit wetted wall area instead of per wall node
   bool source_flux = false;  // wall source nu_j M_j r / c_j (stoichiometric mass flux)
+  bool halfway = false;      // wall half-way along each link instead of on the solid node
   int coupling = FDLBM_COUPLING_FLUX;  // solid-gas coupling at the wall nodes
   double F[3]{}, X_in[MAXS]{}, p_in = 1.0 / 3, T_in = 1.0 / 3;
   double rho_ref[MAXS]{};  // reference densities of 16-bit storage (mean initial density)
@@ -350,6 +351,7 @@ static Params<real> params(const fdlbm_ctx *c) {
   p.tol = (real)std::max(c->tol, c->d.precision == FDLBM_F64 ? 0.0 : 4.0 * 1.1920929e-7);
   p.max_iter = c->max_iter;
   p.rate_area = c->rate_area ? 1 : 0;
+  p.halfway = c->halfway ? 1 : 0;
   for (int a = 0; a < 3; ++a) p.F[a] = a < c->D ? (real)c->F[a] : real(0);
   p.T_in = (real)c->T_in;
   p.p_in = (real)c->p_in;
@@ -757,6 +759,14 @@ int fdlbm_set_wall_source(fdlbm_ctx *c, int mode) {
   return FDLBM_OK;
 }
 
+int fdlbm_set_wall_position(fdlbm_ctx *c, int position) {
+  if (!c) return FDLBM_E_INVALID;
+  if (position != FDLBM_WALL_ON_NODE && position != FDLBM_WALL_HALFWAY)
+    return set_err(c, FDLBM_E_INVALID, "wall position must be FDLBM_WALL_ON_NODE or FDLBM_WALL_HALFWAY");
+  c->halfway = position == FDLBM_WALL_HALFWAY;
+  return FDLBM_OK;
+}
+
 int fdlbm_set_flow(fdlbm_ctx *c, const double *F3, const double *X_in, double p_in, double T_in) {
   if (!c) return FDLBM_E_INVALID;
   if (!(p_in > 0 && T_in > 0)) return set_err(c, FDLBM_E_INVALID, "inlet p and T must be positive");
@@ -834,6 +844,11 @@ static int init_impl(fdlbm_ctx *c, const double *rho, const double *u, const dou
   const Params<real> pr = params<real>(c);
   std::vector<PT> G((size_t)RL * Q * nsl, PT(0.0f));
   std::vector<real> hT(n, real(0));
+  // moment records of the gas slots before the first step (the half-way
+  // wall reads their velocity and temperature); the wall slots' records are
+  // written by every step's wall kernel
+  const int NR = fr_count(c->D, ns);
+  std::vector<real> FRh((size_t)NR * nsl, real(0));
   auto put = [&](int i, size_t slot, int j, real v) {
     if (narrow<PT>()) v = v * pr.inv_rho_ref[j] - real(wlat_of(c->D, i));  // as the kernels do
     G[((size_t)i * nsl + slot) * RL + j] = PT(v);
@@ -843,6 +858,9 @@ static int init_impl(fdlbm_ctx *c, const double *rho, const double *u, const dou
     if (!gaslike(c->kind[node])) continue;
     const size_t slot = (size_t)c->slot_of[node];
     real uu[3] = {(real)u[node], (real)u[n + node], (real)u[2 * n + node]};
+    for (int a = 0; a < c->D; ++a) FRh[slot * NR + fr_u(a)] = uu[a];
+    FRh[slot * NR + fr_T(c->D)] = (real)T[node];
+    for (int j = 0; j < ns; ++j) FRh[slot * NR + fr_rho(c->D, j)] = (real)rho[j * n + node];
     for (int j = 0; j < ns; ++j) {
       real f[19];
       const real sq = (real)std::sqrt(c->M[j]);
@@ -876,6 +894,8 @@ static int init_impl(fdlbm_ctx *c, const double *rho, const double *u, const dou
   c->cur = 0;
   HIPCHK(c, hipMemcpyAsync(c->ws + c->off_G[0], G.data(), G.size() * sizeof(PT),
                            hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->ws + c->off_FR, FRh.data(), FRh.size() * sizeof(real), hipMemcpyHostToDevice,
+                           c->stream));
   HIPCHK(c, hipMemcpyAsync(c->ws + c->off_Ts[0], hT.data(), n * sizeof(real), hipMemcpyHostToDevice,
                            c->stream));
   HIPCHK(c, hipMemcpyAsync(c->ws + c->off_Ts[1], hT.data(), n * sizeof(real), hipMemcpyHostToDevice,
@@ -1587,6 +1607,7 @@ int fdlbm_batch_create(fdlbm_ctx *const *ctxs, int n, fdlbm_batch **out) {
     if (!c->initialized) return fail("every context needs initialised fields");
     if (c->solid_scheme == FDLBM_SOLID_CN) return fail("Crank-Nicolson solids are not batched");
     if (c->coupling != FDLBM_COUPLING_FLUX) return fail("the Eq.(48) coupling is not batched");
+    if (c->halfway) return fail("half-way walls are not batched");
     if (c->D != ctxs[0]->D || c->ns != ctxs[0]->ns || c->d.precision != ctxs[0]->d.precision ||
         c->stream != ctxs[0]->stream)
       return fail("contexts differ in lattice, species count, precision or stream");

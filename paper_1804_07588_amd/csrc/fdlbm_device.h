@@ -108,6 +108,7 @@ struct Params {
   int order[MAXS];
   int max_iter;
   int rate_area;                   // 1: rate scaled by the wall node's wetted area
+  int halfway;                     // 1: wall placed half-way along each link
   real srcf[MAXS];                 // wall source factor: 1, or 1 / c_j (stoichiometric mass flux)
   int eq48;                        // 1: solid-gas coupling of Eq.(48) (else flux-matched)
   real kap[MAXS];                  // (D+2) / (2 Pr_j): gas conductivity per tau1_j C_j T / M_j

@@ -167,6 +167,15 @@ __device__ inline void strec(real *__restrict__ base, int rec, const Rec<real, N
   real *p = reinterpret_cast<real *>(reinterpret_cast<char *>(base) + off);
   __builtin_memcpy(p, &r, sizeof r);
 }
+// the first K values of record `rec` of an array of N-value records
+template <typename real, int N, int K>
+__device__ inline Rec<real, K> ldhead(const real *__restrict__ base, int rec) {
+  const size_t off = size_t(rec) * (N * sizeof(real));
+  const real *p = reinterpret_cast<const real *>(reinterpret_cast<const char *>(base) + off);
+  Rec<real, K> r;
+  __builtin_memcpy(&r, p, sizeof r);
+  return r;
+}
 
 // Population records: RL = rec_len<PT>(NS) stored values per (direction,
 // slot).  For a 16-bit storage type the record is moved as 4-byte words and
@@ -400,7 +409,31 @@ __device__ inline real ipow(real x, int k) {
 // ===========================================================================
 // k_wall: the reactive diffusive wall, one thread per wall node
 // ===========================================================================
-template <bool FAST, typename real, typename PT, int D, int NS>
+// Half-way wall (Sec. 4.3; the interpolation step taken linear): along link i
+// into gas node x the wall node thermalises at the state whose linear
+// interpolant with x takes the wall's values at the link's midpoint,
+// velocity -u(x) and temperature 2 T_w - T(x), read from x's moment record
+// of the previous step.  Weights f^eq_ji(1, -u(x), 2 T_w - T(x)) of every
+// species for the compile-time direction I.
+template <int I, bool FAST, typename real, int D, int NS, typename BF>
+__device__ inline void halfway_weights(const Params<real> &p, const BF &b, const Addr<D> &ad, real Tw,
+                                       real (&f)[NS]) {
+  constexpr int NR = fr_count(D, NS);
+  const int xs = ld(b.slot_of, ad.template at<FAST>(I, 1));
+  const Rec<real, D + 1> h = ldhead<real, NR, D + 1>(b.FR, xs);
+  real ul[3] = {real(0), real(0), real(0)};
+#pragma unroll
+  for (int a = 0; a < D; ++a) ul[a] = -h.v[fr_u(a)];
+  const real Tl = real(2) * Tw - h.v[fr_T(D)];
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    real e[lat_q<D>()];
+    equilibrium<real, D>(real(1), p.sqM[j], ul, Tl, e);
+    f[j] = e[I];
+  }
+}
+
+template <bool FAST, bool HALF, typename real, typename PT, int D, int NS>
 __device__ inline double wall_node(const Params<real> &p, const Bufs<real, PT> &b, int cur,
                                    const WTab<real> &wtab, const int wi) {
   constexpr int Q = lat_q<D>();
@@ -423,6 +456,21 @@ __device__ inline double wall_node(const Params<real> &p, const Bufs<real, PT> &
 #pragma unroll
   for (int i = 1; i < Q; ++i)
     if (em & (1u << i)) Z += wt[i];
+  // the emission weight of each species: Z, or for the half-way wall the
+  // sum of its per-link weights
+  real Zj[NS];
+#pragma unroll
+  for (int j = 0; j < NS; ++j) Zj[j] = HALF ? real(0) : Z;
+  if constexpr (HALF) {
+    static_for<1, Q>([&](auto I) {
+      if (em & (1u << I.value)) {
+        real f[NS];
+        halfway_weights<I.value, FAST, real, D, NS>(p, b, ad, Tw, f);
+#pragma unroll
+        for (int j = 0; j < NS; ++j) Zj[j] += f[j];
+      }
+    });
+  }
   // A_j: mass arriving from the gas (incoming links), with its energy
   real A[NS], Ej[NS];
 #pragma unroll
@@ -448,7 +496,7 @@ __device__ inline double wall_node(const Params<real> &p, const Bufs<real, PT> &
   // concentration treated implicitly
   real rw[NS];
 #pragma unroll
-  for (int j = 0; j < NS; ++j) rw[j] = A[j] / Z;
+  for (int j = 0; j < NS; ++j) rw[j] = A[j] / Zj[j];
   // rate constant at T_w (Eq.(50) with the Arrhenius factor); one reaction
   // term per wall node, corners included (Sec. 4.3), or, as an option, per
   // unit wetted area: the node's rest emission weight over its links into
@@ -464,7 +512,7 @@ __device__ inline double wall_node(const Params<real> &p, const Bufs<real, PT> &
         real R = keff;
 #pragma unroll
         for (int m = 0; m < NS; ++m) R *= ipow(rw[m] * p.invM[m], p.order[m] - (m == j ? 1 : 0));
-        nw[j] = A[j] / (Z - p.nu[j] * p.srcf[j] * R);
+        nw[j] = A[j] / (Zj[j] - p.nu[j] * p.srcf[j] * R);
       }
       const real d = fabs(nw[j] - rw[j]) / fmax(fabs(nw[j]), tiny<real>());
       dmax = fmax(dmax, d);
@@ -476,24 +524,32 @@ __device__ inline double wall_node(const Params<real> &p, const Bufs<real, PT> &
   real r = keff;
 #pragma unroll
   for (int m = 0; m < NS; ++m) r *= ipow(rw[m] * p.invM[m], p.order[m]);
-  const real invZ = real(1) / Z;
+  if constexpr (HALF) {
 #pragma unroll
-  for (int j = 0; j < NS; ++j) rw[j] = (A[j] + p.nu[j] * p.M[j] * p.srcf[j] * r) * invZ;
-  // emission: rho_w,j f^eq_i(1, 0, T_w) on the links into the gas
+    for (int j = 0; j < NS; ++j) rw[j] = (A[j] + p.nu[j] * p.M[j] * p.srcf[j] * r) / Zj[j];
+  } else {
+    const real invZ = real(1) / Z;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) rw[j] = (A[j] + p.nu[j] * p.M[j] * p.srcf[j] * r) * invZ;
+  }
+  // emission: rho_w,j f^eq_i(1, 0, T_w) on the links into the gas (half-way:
+  // the link's own weights, computed again)
   real Eout = 0;
-#pragma unroll
-  for (int i = 1; i < Q; ++i) {
-    if (!(em & (1u << i))) continue;
+  static_for<1, Q>([&](auto I) {
+    constexpr int i = I.value;
+    if (!(em & (1u << i))) return;
+    real f[NS];
+    if constexpr (HALF) halfway_weights<i, FAST, real, D, NS>(p, b, ad, Tw, f);
     Rec<real, NS> W;
     real Ei = 0;
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
-      W.v[j] = rw[j] * wt[i];
+      W.v[j] = rw[j] * (HALF ? f[j] : wt[i]);
       Ei += p.cj2[j] * W.v[j];
     }
     pop_store_next<real, PT, D, NS>(p, Gn + (size_t)i * nsl * RL, slot, i, W);
     Eout += real(cnorm2<D>(i)) * Ei;
-  }
+  });
   // wall state seen by the neighbours' gradient stencils
   Rec<real, NR> fr;
 #pragma unroll
@@ -512,24 +568,24 @@ __device__ inline double wall_node(const Params<real> &p, const Bufs<real, PT> &
 
 // FAST: the node list holds only nodes whose taps never wrap a periodic axis.
 // One block of wall nodes (logical block lb of the list).
-template <bool FAST, typename real, typename PT, int D, int NS>
+template <bool FAST, bool HALF, typename real, typename PT, int D, int NS>
 __device__ __forceinline__ void wall_block(const Params<real> &p, const Bufs<real, PT> &b, int cur,
                                            const WTab<real> &wtab, int lb) {
   const int first = FAST ? 0 : p.n_wall_fast, count = FAST ? p.n_wall_fast : p.n_wall - p.n_wall_fast;
   const int t = lb * BLOCK + threadIdx.x;
   double r_out = 0.0;
-  if (t < count) r_out = wall_node<FAST, real, PT, D, NS>(p, b, cur, wtab, first + t);
+  if (t < count) r_out = wall_node<FAST, HALF, real, PT, D, NS>(p, b, cur, wtab, first + t);
   const double s = block_sum(r_out);
   if (threadIdx.x == 0) b.acc_moles[lb + (FAST ? 0 : p.slot_off_wall)] += s;
 }
-template <bool FAST, typename real, typename PT, int D, int NS>
+template <bool FAST, bool HALF, typename real, typename PT, int D, int NS>
 __global__ void __launch_bounds__(BLOCK) k_wall(Params<real> p, Bufs<real, PT> b, int cur) {
   __shared__ WTab<real> wtab;
   load_wtab<real, NS>(p, wtab);
   const int count = FAST ? p.n_wall_fast : p.n_wall - p.n_wall_fast;
   const int nb = (count + BLOCK - 1) / BLOCK, lb = xcd_block(nb);
   if (lb >= nb) return;  // whole block: no barrier follows for it
-  wall_block<FAST, real, PT, D, NS>(p, b, cur, wtab, lb);
+  wall_block<FAST, HALF, real, PT, D, NS>(p, b, cur, wtab, lb);
 }
 
 // ===========================================================================
@@ -1485,7 +1541,7 @@ __global__ void __launch_bounds__(BLOCK) kb_wall(const Params<real> *__restrict_
       load_wtab<real, NS>(P[it.x], wtab);
       prev = it.x;
     }
-    wall_block<FAST, real, PT, D, NS>(P[it.x], B[it.x], cur, wtab, it.y);
+    wall_block<FAST, false, real, PT, D, NS>(P[it.x], B[it.x], cur, wtab, it.y);  // batches: walls on the node
   });
 }
 
@@ -1555,8 +1611,13 @@ inline hipError_t step_impl(const Params<real> &p, const Bufs<real, PT> &b, int 
     (void)hipStreamWaitEvent(sw, li.ev_fork, 0);
   }
   mark(K_WALL_ID, 0, sw);
-  if (gwf > 0) hipLaunchKernelGGL((k_wall<true, real, PT, D, NS>), dim3(xcd_grid(gwf)), blk, 0, sw, p, b, cur);
-  if (gws > 0) hipLaunchKernelGGL((k_wall<false, real, PT, D, NS>), dim3(xcd_grid(gws)), blk, 0, sw, p, b, cur);
+  if (p.halfway) {
+    if (gwf > 0) hipLaunchKernelGGL((k_wall<true, true, real, PT, D, NS>), dim3(xcd_grid(gwf)), blk, 0, sw, p, b, cur);
+    if (gws > 0) hipLaunchKernelGGL((k_wall<false, true, real, PT, D, NS>), dim3(xcd_grid(gws)), blk, 0, sw, p, b, cur);
+  } else {
+    if (gwf > 0) hipLaunchKernelGGL((k_wall<true, false, real, PT, D, NS>), dim3(xcd_grid(gwf)), blk, 0, sw, p, b, cur);
+    if (gws > 0) hipLaunchKernelGGL((k_wall<false, false, real, PT, D, NS>), dim3(xcd_grid(gws)), blk, 0, sw, p, b, cur);
+  }
   mark(K_WALL_ID, 1, sw);
   if (two) (void)hipEventRecord(li.ev_wall, sw);
   // the solid step: forward Euler, or Crank-Nicolson by p.cn_iters Jacobi
@@ -1581,6 +1642,9 @@ inline hipError_t step_impl(const Params<real> &p, const Bufs<real, PT> &b, int 
   // the Eq.(48) coupling reads the gas moments of this step: its solid step
   // runs after them, on the main stream
   if (two && li.n_solid > 0 && !p.eq48) solid(sw);
+  // the half-way wall reads the gas nodes' moment records of the previous
+  // step, which the moments kernel overwrites
+  if (two && p.halfway) (void)hipStreamWaitEvent(st, li.ev_wall, 0);
   mark(K_MOMENTS_ID, 0, st);
   if constexpr (std::is_same_v<PT, __bf16>) {
     if (ggf > 0)

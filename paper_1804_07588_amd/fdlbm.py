@@ -27,6 +27,7 @@ FIELD_RHO, FIELD_U, FIELD_T, FIELD_TS, FIELD_POP, FIELD_KIND, FIELD_WALL_R, FIEL
 K_WALL, K_MOMENTS, K_COLLIDE, K_SOLID = range(4)
 RATE_PER_NODE, RATE_PER_AREA = 0, 1
 SOURCE_LATTICE, SOURCE_FLUX = 0, 1
+WALL_ON_NODE, WALL_HALFWAY = 0, 1
 KERNEL_NAMES = ["k_wall", "k_moments", "k_collide", "k_solid"]
 MAX_SPECIES = 8
 
@@ -42,6 +43,7 @@ EXPORTS = ["fdlbm_create", "fdlbm_destroy", "fdlbm_last_error", "fdlbm_set_geome
            "fdlbm_batch_get_grid", "fdlbm_batch_autotune", "fdlbm_batch_set_overlap",
            "fdlbm_set_sync_check", "fdlbm_last_step", "fdlbm_observe_noalloc", "fdlbm_set_rate_scaling",
            "fdlbm_set_wall_source", "fdlbm_get_field_device", "fdlbm_batch_check",
+           "fdlbm_set_wall_position",
            "fdlbm_set_solid_coupling"]
 BATCH_KINDS = ["wall_fast", "wall_slow", "gas_fast", "gas_slow", "collide", "solid"]
 
@@ -118,6 +120,7 @@ def lib() -> ct.CDLL:
         L.fdlbm_set_sync_check.argtypes = [vp, i64]
         L.fdlbm_set_rate_scaling.argtypes = [vp, ct.c_int]
         L.fdlbm_set_wall_source.argtypes = [vp, ct.c_int]
+        L.fdlbm_set_wall_position.argtypes = [vp, ct.c_int]
         L.fdlbm_get_field_device.argtypes = [vp, ct.c_int, ct.c_int, vp]
         L.fdlbm_batch_check.argtypes = [vp, ct.POINTER(ct.c_int), ct.POINTER(i64)]
         L.fdlbm_set_solid_coupling.argtypes = [vp, ct.c_int]
@@ -189,6 +192,8 @@ def configure(h, cfg: dict) -> None:
         check(L.fdlbm_set_rate_scaling(h, RATE_PER_AREA))
     if rx.get("source_flux"):
         check(L.fdlbm_set_wall_source(h, SOURCE_FLUX))
+    if rx.get("halfway"):
+        check(L.fdlbm_set_wall_position(h, WALL_HALFWAY))
     fl = cfg["flow"]
     F, Xin = _arr(fl["F"]), _arr(fl["X_in"])
     check(L.fdlbm_set_flow(h, _d(F), _d(Xin), fl["p_in"], fl["T_in"]))

@@ -102,6 +102,11 @@ def test_invalid_inputs_are_rejected(L):
     order = np.array([1.5, 0.0])
     assert L.fdlbm_set_reaction(h, nu.ctypes.data_as(dp), order.ctypes.data_as(dp), 1e-3, 0, 1 / 3,
                                 -0.1, 0, 1 / 3, 1e-12, 20) == fdlbm.E_INVALID
+    # options outside their sets
+    assert L.fdlbm_set_wall_position(h, 2) == fdlbm.E_INVALID
+    assert L.fdlbm_set_wall_source(h, -1) == fdlbm.E_INVALID
+    assert L.fdlbm_set_wall_position(h, fdlbm.WALL_HALFWAY) == fdlbm.OK
+    assert L.fdlbm_set_wall_position(h, fdlbm.WALL_ON_NODE) == fdlbm.OK
     # binding before the geometry, then a misaligned workspace
     assert L.fdlbm_bind_workspace(h, ct.c_void_p(256), 1 << 30) == fdlbm.E_STATE
     assert set_geom(L, h, cfg) == fdlbm.OK
@@ -125,7 +130,7 @@ def host_cases():
     D3Q19, periodic and closed axes, inlet/outlet rows, sphere packs of the
     benchmark's construction (the 128^3 bed and three batch beds), the
     Crank-Nicolson solid, Eq.(48) coupling, per-area rates, species Prandtl
-    numbers and a Lennard-Jones table."""
+    numbers, a Lennard-Jones table and the half-way wall."""
     c1 = W.channel_c1()
     rng = np.random.default_rng(3)
     noisy = (rng.random((1, 24, 32)) < 0.3).astype(np.uint8)
@@ -145,7 +150,8 @@ def host_cases():
                                omega_mu=list(1.1 + 0.9 * np.exp(-0.6 * t)), omega_d=list(1.0 + 0.8 * np.exp(-0.5 * t)),
                                eps_over_k=[100.0, 300.0, 200.0, 60.0, 80.0])
     lj["species"]["Pr_j"] = [0.7, 0.8, 0.9, 1.0, 0.75]
-    return cases + [("bed_eq48", eq48), ("bed_lj_prj", lj)]
+    half = W.with_changes(bed, reaction=dict(halfway=True))
+    return cases + [("bed_eq48", eq48), ("bed_lj_prj", lj), ("bed_halfway", half)]
 
 
 @pytest.mark.parametrize("precision", [fdlbm.F64, fdlbm.F32, fdlbm.F16, fdlbm.BF16])

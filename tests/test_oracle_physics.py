@@ -54,6 +54,91 @@ def test_poiseuille_viscosity_and_second_order_slip(oracle_lib):
     assert errs[0] / errs[1] > 3.5          # second order
 
 
+def poiseuille_roots(oracle_lib, H, halfway, wall=3, tau1=0.5, F=1e-6):
+    """Steady body-force channel of width H gas rows between diffusive walls
+    (isothermal, at rest): the curvature of the quadratic fit to the gas
+    velocity relative to -F / (2 nu), and the fit's two zeros."""
+    ny = H + 2 * wall
+    cfg = one_species(2, ny, tau1=tau1, F=F, mask=W.channel_mask(2, ny, wall))
+    cfg["reaction"]["halfway"] = halfway
+    nu = tau1 * T0
+    y = np.arange(ny)
+    y0, y1 = wall - 1 + 0.5 * halfway, ny - wall - 0.5 * halfway
+    init = W.uniform_init(cfg)
+    init["u"][0] = np.repeat(np.where((y >= wall) & (y < ny - wall), F / (2 * nu) * (y - y0) * (y1 - y), 0.0), 2)
+    sim = oracle_lib.OracleSim(cfg, init)
+    sim.step(int(3 * H * H / nu))
+    u = sim.field(oracle_lib.OF_U, 0).reshape(ny, 2)[:, 0]
+    g = slice(wall, ny - wall)
+    a = np.polyfit(y[g], u[g], 2)
+    return a[0] / (-F / (2 * nu)), np.sort(np.roots(a).real), (y0, y1)
+
+
+def test_halfway_wall_moves_the_no_slip_point_half_a_node(oracle_lib):
+    """Sec. 4.3's half-way wall: a steady Poiseuille profile keeps its
+    curvature -F / (2 nu) and its zeros move from the wall nodes to half a
+    node into the gas, up to the diffusive wall's slip, which halves as the
+    channel width doubles (its relative size falls at second order)."""
+    slips = []
+    for H in (16, 32):
+        curv0, r0, (w0, w1) = poiseuille_roots(oracle_lib, H, False)
+        curv1, r1, (h0, h1) = poiseuille_roots(oracle_lib, H, True)
+        assert curv0 == pytest.approx(1.0, rel=1e-6) and curv1 == pytest.approx(1.0, rel=1e-6)
+        assert h0 == w0 + 0.5 and h1 == w1 - 0.5
+        # symmetric channel
+        assert r1[0] - h0 == pytest.approx(h1 - r1[1], abs=1e-9)
+        slip0, slip1 = w0 - r0[0], h0 - r1[0]
+        assert 0 < slip0 < 2.0 / H and 0 < slip1 < 2.0 / H
+        # the two placements differ by half a node, up to the slip's change
+        assert r1[0] - r0[0] == pytest.approx(0.5, abs=0.5 / H)
+        slips.append(slip1)
+    assert slips[0] / slips[1] == pytest.approx(2.0, rel=0.1)
+
+
+def conduction_crossings(oracle_lib, H, halfway, ws=3, tau1=0.5):
+    """Gas at rest between two solid slabs held at T_l and T_h (no solid
+    conduction, an effectively infinite heat capacity): where the linear fit
+    to the steady gas temperature reaches T_l and T_h, and the slope."""
+    nx = 2
+    ny = 2 * ws + H
+    Tl, Th = T0 * 0.99, T0 * 1.01
+    cfg = one_species(nx, ny, mask=W.channel_mask(nx, ny, ws), periodic=(1, 0, 1), tau1=tau1,
+                      wall_mode=W.WALL_REACTIVE, alpha_s=0.0, C_s=1e30)
+    cfg["reaction"]["halfway"] = halfway
+    init = W.uniform_init(cfg)
+    y = np.repeat(np.arange(ny), nx)
+    init["Ts"] = np.where(y < ny // 2, Tl, Th).astype(float)
+    init["T"] = Tl + (Th - Tl) * (y - ws + 1) / (ny - 2 * ws + 1)
+    init["rho"][0] = T0 / init["T"]
+    sim = oracle_lib.OracleSim(cfg, init)
+    sim.step(int(4 * H * H / (tau1 * T0)))
+    T = sim.field(oracle_lib.OF_T).reshape(ny, nx)[:, 0]
+    ys = np.arange(ny)
+    g = slice(ws, ny - ws)
+    a = np.polyfit(ys[g], T[g], 1)
+    assert np.abs(np.polyval(a, ys[g]) - T[g]).max() < 1e-3 * (Th - Tl)   # steady and linear
+    return (Tl - a[1]) / a[0], (Th - a[1]) / a[0], ws - 1, ny - ws
+
+
+def test_halfway_wall_temperature_is_the_linear_extrapolation(oracle_lib):
+    """The half-way wall emits at 2 T_w - T(x) along each link (the linear
+    interpolation through the link's midpoint).  The diffusive wall has a
+    temperature jump: on the node, the gas profile reaches T_w a distance z
+    beyond the wall node, with T(y_w) - T_w = z T'.  Emitting at the
+    extrapolated temperature instead gives T(y_w) - (2 T_w - T(y_w + 1)) =
+    z T', so the profile reaches T_w at y_w - (z - 1) / 2 (linear theory of
+    the same jump law; an emission at T_w itself leaves it at y_w - z, and
+    one at the gas node's own temperature carries no heat)."""
+    for H in (16, 24):
+        c0l, c0h, yl, yh = conduction_crossings(oracle_lib, H, False)
+        c1l, c1h, _, _ = conduction_crossings(oracle_lib, H, True)
+        z = yl - c0l
+        assert 1.0 < z < 6.0                                  # a jump, as the diffusive wall has
+        assert c0h - yh == pytest.approx(z, abs=5e-3)         # symmetric
+        assert c1l == pytest.approx(yl - (z - 1) / 2, abs=5e-3)
+        assert c1h == pytest.approx(yh + (z - 1) / 2, abs=5e-3)
+
+
 def binary_gas(nx, tau1, tau2, M=(1.0, 1.0), flags=W.CORR_ALL):
     Dab = tau2 * T0 / M[0]
     return dict(lattice=2, nx=nx, ny=1, nz=1, periodic=(1, 1, 1),
@@ -182,10 +267,12 @@ def test_steady_slab_conduction_flux_continuity(oracle_lib):
     assert gf / gs == pytest.approx(10.0, rel=0.02)
 
 
-def test_mass_balance_with_reaction_is_exact(oracle_lib):
+@pytest.mark.parametrize("halfway", [False, True])
+def test_mass_balance_with_reaction_is_exact(oracle_lib, halfway):
     """Eq.(37)-(41) with Eq.(50): each wall node adds nu_j M_j r to species j
-    (on-lattice species), so the per-species mass changes are exact."""
-    cfg = W.channel_c1()
+    (on-lattice species), so the per-species mass changes are exact; the
+    half-way wall's emission weights leave this balance unchanged."""
+    cfg = W.with_changes(W.channel_c1(), reaction=dict(halfway=halfway))
     sim = oracle_lib.OracleSim(cfg, W.uniform_init(cfg))
     o0 = sim.observe()
     sim.step(200)
@@ -206,11 +293,13 @@ def energy_residual(oracle_lib, cfg, steps=200):
     return dE - src, o1["heat_released"], o0["e_gas"] + o0["e_solid"]
 
 
-def test_energy_balance_is_exact(oracle_lib):
+@pytest.mark.parametrize("halfway", [False, True])
+def test_energy_balance_is_exact(oracle_lib, halfway):
     """Eq.(42) with the flux-matched coupling: total gas + solid energy
     changes by exactly the reaction heat plus the Dirichlet-face heat plus
-    the body-force work (equal-mass species, all corrections on)."""
-    cfg = W.with_changes(W.channel_c1(), init=dict(X=[0.7, 0.3]), reaction=dict(k0=1e-2))
+    the body-force work (equal-mass species, all corrections on), with the
+    wall on the node or half-way."""
+    cfg = W.with_changes(W.channel_c1(), init=dict(X=[0.7, 0.3]), reaction=dict(k0=1e-2, halfway=halfway))
     res, heat, E = energy_residual(oracle_lib, cfg)
     assert heat > 1.0
     assert abs(res) < 1e-12 * E

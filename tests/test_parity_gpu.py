@@ -758,6 +758,51 @@ def test_flux_scaled_wall_source(oracle_lib, fd, prec):
         ok32(e, tol_u=np.inf, tol_ucs=3e-6)
 
 
+@pytest.mark.parametrize("prec", ["F64", "F32"])
+def test_halfway_wall(oracle_lib, fd, prec):
+    """fdlbm_set_wall_position(FDLBM_WALL_HALFWAY) (Sec. 4.3): the reactive
+    channel with an interpolated product (mass ratio 4) and the five-species
+    sphere pack with inlet/outlet, both from perturbed states, so that the
+    gas next to the walls moves and differs in temperature from them; and
+    the overlapped step (the moments pass waits for the wall) bitwise the
+    serial one."""
+    precision = getattr(fd, prec)
+    cfg = W.with_changes(W.channel_c1(), init=dict(X=[0.7, 0.3]), reaction=dict(k0=1e-2, halfway=True))
+    cfg["species"].update(M=[1.0, 4.0], mu0=[0.1, 0.2])
+    cfg["flow"]["X_in"] = [0.7, 0.3]
+    init = W.perturbed_init(cfg, 21, amp_T=0.02)
+    o, g = run_both(oracle_lib, fd, cfg, init, 300, precision)
+    e = field_errors(o, g, fd, 2, 2)
+    if prec == "F64":
+        ok64(e)
+        # the option changes the run far beyond these bounds
+        on_node = oracle_lib.OracleSim(W.with_changes(cfg, reaction=dict(halfway=False)), init)
+        on_node.step(300)
+        assert rel_err(on_node.field(of.OF_POP, 1), o.field(of.OF_POP, 1)) > 1e-5
+        on_node.close()
+    else:
+        ok32(e, tol_u=2e-3, tol_ucs=3e-6)
+    oo, og = o.observe(), g.observe()
+    assert og["moles_reacted"] == pytest.approx(oo["moles_reacted"], rel=1e-10 if prec == "F64" else 2e-5)
+    cfg = small_bed()
+    cfg["reaction"]["halfway"] = True
+    init = W.perturbed_init(cfg, 22, amp_u=0.005, amp_T=0.02)
+    o, g = run_both(oracle_lib, fd, cfg, init, 40 if prec == "F64" else 100, precision)
+    e = field_errors(o, g, fd, 5, 3)
+    if prec == "F64":
+        ok64(e)
+    else:
+        ok32(e)
+        a = fd.Sim(cfg, precision=precision, init=init)
+        a.set_overlap(False)
+        a.step(100)
+        for fid, comps in ((fd.FIELD_RHO, 5), (fd.FIELD_U, 3), (fd.FIELD_T, 1), (fd.FIELD_TS, 1),
+                           (fd.FIELD_POP, 5), (fd.FIELD_WALL_R, 1)):
+            for c in range(comps):
+                assert np.array_equal(a.field(fid, c), g.field(fid, c)), (fid, c)
+        a.close()
+
+
 def n_species(cfg, ns, masses=(1.0, 2.0, 4.0, 9.0, 14.0, 22.0)):
     """The configuration with ns species of the given masses: species 0 reacts
     to species 1 at the walls (first order), the others are inert; binary

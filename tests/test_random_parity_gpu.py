@@ -4,7 +4,8 @@ inlet/outlet, periodic or closed axes), one to six species with masses from
 1 to 22, a subset of the correction terms, species or common Prandtl
 numbers, the solid scheme (forward Euler or Crank-Nicolson) and coupling
 (flux-matched or Eq.(48)), the rate law's constants and options (per node or
-per area, lattice or flux-scaled source) and a body force, runs a few dozen
+per area, lattice or flux-scaled source), the wall position (on the node or
+half-way) and a body force, runs a few dozen
 FP64 steps from a perturbed state on both sides and compares every field to
 the FP64 bounds of test_parity_gpu.py.  The draws stay in ranges where the
 method is stable; a case whose oracle run turns non-physical is reported and
@@ -83,6 +84,7 @@ def random_case(seed: int) -> tuple[dict, dict, int]:
     cfg["flow"].update(F=F, X_in=X)
     cfg["init"].update(X=X)
     init = W.perturbed_init(cfg, 77 + seed, amp_rho=0.01, amp_u=0.004, amp_T=0.005)
+    rx["halfway"] = bool(rng.random() < 0.3)   # drawn last: the earlier draws stay as they were
     return cfg, init, steps
 
 
@@ -98,7 +100,7 @@ def test_random_case_fp64(fd, seed):
     desc = (f"lattice {D}, {cfg['nx']}x{cfg['ny']}x{cfg['nz']}, inout {cfg['inout']}, ns {ns}, "
             f"M {cfg['species']['M']}, flags {cfg['species']['flags']}, solid {cfg['solid'].get('scheme', 0)}"
             f"/{cfg['solid'].get('coupling', 0)}, area {cfg['reaction']['rate_area']}, "
-            f"flux {cfg['reaction']['source_flux']}")
+            f"flux {cfg['reaction']['source_flux']}, halfway {cfg['reaction']['halfway']}")
     print(f"[random {seed}] {desc}", flush=True)
     o = of.OracleSim(cfg, init)
     o.step(steps)
