@@ -234,10 +234,27 @@ int fdlbm_set_solid_coupling(fdlbm_ctx *ctx, int mode);
  * nu_j per unit extent (nu < 0 reactants); orders must be integers 0..3.
  * dH reaction enthalpy per unit extent (< 0 exothermic), Eq.(42).
  * wall_mode FDLBM_WALL_*; T_iso the wall temperature in isothermal mode;
- * tol / max_iter bound the wall-density fixed point of Sec. 4.3. */
+ * tol / max_iter bound the wall-density fixed point of Sec. 4.3.  Replaces
+ * every reaction set before (one reaction afterwards). */
 int fdlbm_set_reaction(fdlbm_ctx *ctx, const double *nu, const double *order, double k0,
                        double ea, double T_ref, double dH, int wall_mode, double T_iso,
                        double tol, int max_iter);
+
+/* A further surface reaction at every wall node, with the same arguments as
+ * the rate law of fdlbm_set_reaction (nu, order: n_species values, copied).
+ * Sec. 4.3 takes any source S_j in the flux balance of Eq.(38)-(41); with
+ * several reactions S_j = sum_k nu_jk M_j r_k.  The wall-density fixed point
+ * then updates every species some reaction consumes with a positive order,
+ * each with its own consumption implicit and its production at the current
+ * densities; the reaction heat at the node is sum_k -dH_k r_k (Eq.(42)),
+ * FDLBM_FIELD_WALL_R and moles_reacted count the summed rates, and
+ * heat_released sums the heat node by node.  Up to FDLBM_MAX_REACTIONS in
+ * all.  FDLBM_E_STATE before fdlbm_set_reaction; FDLBM_E_INVALID beyond the
+ * limit or for orders outside 0..3.  Not batched (fdlbm_batch_create
+ * fails).  Takes effect at the next step. */
+#define FDLBM_MAX_REACTIONS 4
+int fdlbm_add_reaction(fdlbm_ctx *ctx, const double *nu, const double *order, double k0, double ea,
+                       double T_ref, double dH);
 
 /* Scaling of the surface rate at a wall node.  FDLBM_RATE_PER_NODE (the
  * default): one reaction term S_j per wall node, also at corner nodes, as

@@ -28,6 +28,7 @@
 
 #define MAXS ORACLE_MAXS
 #define MAXQ 19
+#define MAXR ORACLE_MAXR
 
 enum { K_GAS = 0, K_SOLID = 1, K_WALL = 2, K_INLET = 3, K_OUTLET = 4 };
 
@@ -60,8 +61,11 @@ struct oracle_sim {
   /* solid */
   double alpha_s, C_s, T_bc[6];
   int solid_scheme; /* 0 forward Euler, 1 Crank-Nicolson */
-  /* reaction */
-  double nu[MAXS], order[MAXS], k0, ea, T_ref_rxn, dH, T_iso, tol;
+  /* reactions: the rate law of oracle_set_reaction is reaction 0; further
+   * ones are appended by oracle_add_reaction */
+  int n_rx;
+  double rnu[MAXR][MAXS], rorder[MAXR][MAXS], rk0[MAXR], rea[MAXR], rTref[MAXR], rdH[MAXR];
+  double T_iso, tol;
   int wall_mode, max_iter;
   /* flow */
   double F[3], X_in[MAXS], p_in, T_in;
@@ -74,6 +78,7 @@ struct oracle_sim {
   /* per-node fields of the current step */
   double *rho, *u, *T, *tau1, *tau2, *Jf, *Uc;
   double *wall_r, *wall_dE;
+  double *wall_q;   /* reaction heat per wall node and step, sum_k -dH_k r_k */
   double *acc_node; /* per-node terms of the cumulative sums, added in node order */
   double *wall_u;   /* wall velocity U_w per node, 3 rows (NULL: walls at rest) */
   int literal_eq6;  /* 1: f* at the mixture temperature as printed in Eq.(6) */
@@ -470,11 +475,12 @@ oracle_sim *oracle_create(int lattice, int nx, int ny, int nz, const int *period
   s->Jf = (double *)calloc((size_t)n_species * 3 * s->n, sizeof(double));
   s->Uc = (double *)calloc((size_t)3 * s->n, sizeof(double));
   s->wall_r = (double *)calloc(s->n, sizeof(double));
+  s->wall_q = (double *)calloc(s->n, sizeof(double));
   s->wall_dE = (double *)calloc(s->n, sizeof(double));
   s->acc_node = (double *)calloc(s->n, sizeof(double));
   s->kind = (uint8_t *)calloc(s->n, 1);
   if (!s->G || !s->Gn || !s->gpre || !s->Ts || !s->Tsn || !s->rho || !s->u || !s->T ||
-      !s->tau1 || !s->tau2 || !s->Jf || !s->Uc || !s->wall_r || !s->wall_dE || !s->kind) {
+      !s->tau1 || !s->tau2 || !s->Jf || !s->Uc || !s->wall_r || !s->wall_dE || !s->wall_q || !s->kind) {
     oracle_destroy(s);
     return NULL;
   }
@@ -511,6 +517,7 @@ void oracle_destroy(oracle_sim *s) {
   free(s->Jf);
   free(s->Uc);
   free(s->wall_r);
+  free(s->wall_q);
   free(s->wall_u);
   free(s->acc_node);
   free(s->wall_dE);
@@ -655,23 +662,45 @@ int oracle_set_solid_scheme(oracle_sim *s, int scheme) {
   return 0;
 }
 
+/* reaction k's stoichiometry, orders and rate constants */
+static int put_reaction(oracle_sim *s, int k, const double *nu, const double *order, double k0,
+                        double ea, double T_ref, double dH) {
+  for (int j = 0; j < s->ns; ++j)
+    if (order[j] < 0) return fail(s, "negative reaction order");
+  for (int j = 0; j < s->ns; ++j) {
+    s->rnu[k][j] = nu[j];
+    s->rorder[k][j] = order[j];
+  }
+  s->rk0[k] = k0;
+  s->rea[k] = ea;
+  s->rTref[k] = T_ref;
+  s->rdH[k] = dH;
+  return 0;
+}
+
 int oracle_set_reaction(oracle_sim *s, const double *nu, const double *order, double k0,
                         double ea, double T_ref, double dH, int wall_mode, double T_iso,
                         double tol, int max_iter) {
   if (!s || !nu || !order) return fail(s, "null argument");
-  for (int j = 0; j < s->ns; ++j) {
-    s->nu[j] = nu[j];
-    s->order[j] = order[j];
-    if (order[j] < 0) return fail(s, "negative reaction order");
-  }
-  s->k0 = k0;
-  s->ea = ea;
-  s->T_ref_rxn = T_ref;
-  s->dH = dH;
+  if (put_reaction(s, 0, nu, order, k0, ea, T_ref, dH)) return -1;
+  s->n_rx = 1;
   s->wall_mode = wall_mode;
   s->T_iso = T_iso;
   s->tol = tol;
   s->max_iter = max_iter;
+  return 0;
+}
+
+/* a further surface reaction at every wall node (the paper's flux boundary
+ * condition takes any source S_j; with several reactions S_j is the sum of
+ * their contributions, reading) */
+int oracle_add_reaction(oracle_sim *s, const double *nu, const double *order, double k0, double ea,
+                        double T_ref, double dH) {
+  if (!s || !nu || !order) return fail(s, "null argument");
+  if (s->n_rx < 1) return fail(s, "set the first reaction with oracle_set_reaction");
+  if (s->n_rx >= MAXR) return fail(s, "too many reactions");
+  if (put_reaction(s, s->n_rx, nu, order, k0, ea, T_ref, dH)) return -1;
+  s->n_rx++;
   return 0;
 }
 
@@ -891,12 +920,13 @@ static void stream_all(oracle_sim *s) {
   }
 }
 
-/* rate law of Eq.(50) generalised: r = k(T_w) prod_m C_m^order_m with the
- * Arrhenius factor k = k0 exp[ea (1 - T_ref / T_w)] (ea = E_a / (R T_ref)) */
-static double rate(const oracle_sim *s, const double *rhow, double Tw) {
-  double r = s->k0 * exp(s->ea * (1.0 - s->T_ref_rxn / Tw));
+/* rate law of reaction k, Eq.(50) generalised: r = k(T_w) prod_m C_m^order_m
+ * with the Arrhenius factor k = k0 exp[ea (1 - T_ref / T_w)]
+ * (ea = E_a / (R T_ref)) */
+static double rate(const oracle_sim *s, int k, const double *rhow, double Tw) {
+  double r = s->rk0[k] * exp(s->rea[k] * (1.0 - s->rTref[k] / Tw));
   for (int m = 0; m < s->ns; ++m)
-    if (s->order[m] != 0.0) r *= pow(rhow[m] / s->M[m], s->order[m]);
+    if (s->rorder[k][m] != 0.0) r *= pow(rhow[m] / s->M[m], s->rorder[k][m]);
   return r;
 }
 
@@ -959,20 +989,41 @@ static void wall_bc(oracle_sim *s) {
      * balance of Sec. 7). */
     double srcf[MAXS];
     for (int j = 0; j < ns; ++j) srcf[j] = s->src_flux ? 1.0 / s->cj[j] : 1.0;
+    /* Several reactions (reading): S_j sums the reactions' terms.  The
+     * iteration updates the species some reaction consumes with a positive
+     * order; each pass treats such a species' own concentration implicitly
+     * in the reactions that consume it and takes the reactions that produce
+     * it at the current densities.  The other species keep A_j / Z_j until
+     * the final balance (they do not enter a rate that consumes them). */
+    int upd[MAXS];
+    for (int j = 0; j < ns; ++j) {
+      upd[j] = 0;
+      for (int k = 0; k < s->n_rx; ++k)
+        if (s->rnu[k][j] < 0.0 && s->rorder[k][j] > 0.0) upd[j] = 1;
+    }
     double rw[MAXS];
     for (int j = 0; j < ns; ++j) rw[j] = A[j] / Z[j];
     for (int it = 0; it < s->max_iter; ++it) {
-      double nw[MAXS], dmax = 0.0;
+      double nw[MAXS], rk[MAXR], dmax = 0.0;
+      for (int k = 0; k < s->n_rx; ++k) rk[k] = area * rate(s, k, rw, Tw);
       for (int j = 0; j < ns; ++j) {
         nw[j] = rw[j];
-        if (s->nu[j] < 0.0 && s->order[j] > 0.0) {
-          /* r / C_j with C_j's own power lowered by one */
-          double R = area * s->k0 * exp(s->ea * (1.0 - s->T_ref_rxn / Tw));
-          for (int m = 0; m < ns; ++m) {
-            double o = s->order[m] - (m == j ? 1.0 : 0.0);
-            if (o != 0.0) R *= pow(rw[m] / s->M[m], o);
+        if (upd[j]) {
+          double num = 0.0, den = 0.0;
+          for (int k = 0; k < s->n_rx; ++k) {
+            if (s->rnu[k][j] < 0.0 && s->rorder[k][j] > 0.0) {
+              /* r_k / C_j with C_j's own power lowered by one */
+              double R = area * s->rk0[k] * exp(s->rea[k] * (1.0 - s->rTref[k] / Tw));
+              for (int m = 0; m < ns; ++m) {
+                double o = s->rorder[k][m] - (m == j ? 1.0 : 0.0);
+                if (o != 0.0) R *= pow(rw[m] / s->M[m], o);
+              }
+              den += s->rnu[k][j] * srcf[j] * R;
+            } else if (s->rnu[k][j] != 0.0) {
+              num += s->rnu[k][j] * s->M[j] * srcf[j] * rk[k];
+            }
           }
-          nw[j] = A[j] / (Z[j] - s->nu[j] * srcf[j] * R);
+          nw[j] = (A[j] + num) / (Z[j] - den);
         }
         double d = fabs(nw[j] - rw[j]) / fmax(fabs(nw[j]), 1e-300);
         if (d > dmax) dmax = d;
@@ -980,9 +1031,19 @@ static void wall_bc(oracle_sim *s) {
       for (int j = 0; j < ns; ++j) rw[j] = nw[j];
       if (dmax <= s->tol) break;
     }
-    double r = area * rate(s, rw, Tw);
-    /* final wall densities from the exact mass balance at the final rate */
-    for (int j = 0; j < ns; ++j) rw[j] = (A[j] + s->nu[j] * s->M[j] * srcf[j] * r) / Z[j];
+    /* final rates, and the wall densities from the exact mass balance at them */
+    double rk[MAXR], r = 0.0, q = 0.0;
+    for (int k = 0; k < s->n_rx; ++k) rk[k] = area * rate(s, k, rw, Tw);
+    for (int j = 0; j < ns; ++j) {
+      double src = 0.0;
+      for (int k = 0; k < s->n_rx; ++k) src += s->rnu[k][j] * s->M[j] * srcf[j] * rk[k];
+      rw[j] = (A[j] + src) / Z[j];
+    }
+    /* total rate (moles reacted per node and step) and reaction heat, Eq.(42) */
+    for (int k = 0; k < s->n_rx; ++k) {
+      r += rk[k];
+      q += -s->rdH[k] * rk[k];
+    }
     double Eout = 0.0;
     for (int i = 1; i < Q; ++i) {
       if (!emits(s, w, i)) continue;
@@ -995,6 +1056,7 @@ static void wall_bc(oracle_sim *s) {
       }
     }
     s->wall_r[w] = r;
+    s->wall_q[w] = q;
     s->wall_dE[w] = 0.5 * (Eout - Ein); /* kinetic energy handed to the gas */
     /* wall state seen by the gradient stencils of neighbouring gas nodes */
     for (int j = 0; j < ns; ++j) s->rho[(size_t)j * s->n + w] = rw[j];
@@ -1303,7 +1365,7 @@ static void solid(oracle_sim *s) {
     /* isothermal walls (prior art) exchange nothing with the solid */
     if (s->kind[x] == K_WALL && s->wall_mode == 0) {
       if (!s->eq48) {
-        Tn += (-s->dH * s->wall_r[x] - s->wall_dE[x]) / s->C_s;
+        Tn += (s->wall_q[x] - s->wall_dE[x]) / s->C_s;
       } else {
         /* Eq.(48): the third term is the heat the gas next to the wall
          * exchanges with it, alpha^f rho^f c_p^f / (rho^s c_p^s) (T^f - T^s)
@@ -1323,7 +1385,7 @@ static void solid(oracle_sim *s) {
                      s->T[nb] / (2.0 * s->M[j] * s->Pr_j[j]);
             qf += kap * (s->T[nb] - T);
           }
-        Tn += (-s->dH * s->wall_r[x] + qf) / s->C_s;
+        Tn += (s->wall_q[x] + qf) / s->C_s;
       }
     }
     s->Tsn[x] = Tn;
@@ -1380,7 +1442,7 @@ static void solid_cn(oracle_sim *s) {
     int cnt;
     double lap = solid_lap(s, s->Ts, x, &bf, &cnt, &nbs, &bcs);
     rhs[x] = s->Ts[x] + 0.5 * a * lap;
-    if (s->kind[x] == K_WALL && s->wall_mode == 0) rhs[x] += (-s->dH * s->wall_r[x] - s->wall_dE[x]) / s->C_s;
+    if (s->kind[x] == K_WALL && s->wall_mode == 0) rhs[x] += (s->wall_q[x] - s->wall_dE[x]) / s->C_s;
     s->acc_node[x] = 0.5 * a * s->C_s * bf;
   }
   for (int x = 0; x < n; ++x) s->bheat += s->acc_node[x];
@@ -1472,7 +1534,7 @@ int oracle_step(oracle_sim *s, int64_t n_steps) {
     for (int w = 0; w < s->n; ++w)
       if (s->kind[w] == K_WALL) {
         s->moles += s->wall_r[w];
-        s->heat += -s->dH * s->wall_r[w];
+        s->heat += s->wall_q[w];
       }
     double *t1 = s->G;
     s->G = s->Gn;

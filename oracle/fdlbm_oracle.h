@@ -31,6 +31,7 @@ extern "C" {
 #endif
 
 #define ORACLE_MAXS 8
+#define ORACLE_MAXR 4 /* surface reactions */
 
 typedef struct oracle_sim oracle_sim;
 
@@ -97,6 +98,11 @@ int oracle_set_threads(int n);
 int oracle_set_coupling(oracle_sim *s, int eq48);
 /* reaction rate per wall node (0, default) or per unit wetted area (1) */
 int oracle_set_rate_area(oracle_sim *s, int on);
+/* a further surface reaction (stoichiometry, orders, k0, E_a/(R T_ref),
+ * T_ref, dH) after the one of oracle_set_reaction, up to ORACLE_MAXR in all;
+ * every wall node runs all of them (reading) */
+int oracle_add_reaction(oracle_sim *s, const double *nu, const double *order, double k0, double ea,
+                        double T_ref, double dH);
 /* wall source in population units: nu_j M_j r (0, default) or nu_j M_j r / c_j (1) */
 int oracle_set_source_flux(oracle_sim *s, int on);
 /* wall position: on the solid node (0, default, Eq.(39)) or half-way along

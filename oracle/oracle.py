@@ -91,6 +91,8 @@ def lib():
         L.oracle_set_rate_area.argtypes = [ct.c_void_p, ct.c_int]
         L.oracle_set_source_flux.argtypes = [ct.c_void_p, ct.c_int]
         L.oracle_set_wall_position.argtypes = [ct.c_void_p, ct.c_int]
+        L.oracle_add_reaction.argtypes = [ct.c_void_p, dp, dp, ct.c_double, ct.c_double, ct.c_double,
+                                          ct.c_double]
         L.oracle_set_coupling.argtypes = [ct.c_void_p, ct.c_int]
         L.oracle_set_threads.argtypes = [ct.c_int]
         L.oracle_init_fields.argtypes = [ct.c_void_p, dp, dp, dp, dp]
@@ -215,6 +217,11 @@ class OracleSim:
             self._check(L.oracle_set_source_flux(h, 1))
         if rx.get("halfway"):
             self._check(L.oracle_set_wall_position(h, 1))
+        for more in rx.get("more", ()):
+            # further reactions at every wall node (same keys as the first)
+            mnu, mord = _arr(more["nu"]), _arr(more["order"])
+            self._check(L.oracle_add_reaction(h, _d(mnu), _d(mord), more["k0"], more["ea"], more["T_ref"],
+                                              more["dH"]))
         if cfg.get("literal_eq6"):
             self._check(L.oracle_set_literal_eq6(h, 1))
         if cfg.get("wall_u") is not None:

@@ -47,6 +47,10 @@ struct fdlbm_ctx {
   bool rate_area = false;  // rate per unit wetted wall area instead of per wall node
   bool source_flux = false;  // wall source nu_j M_j r / c_j (stoichiometric mass flux)
   bool halfway = false;      // wall half-way along each link instead of on the solid node
+  // further surface reactions (fdlbm_add_reaction); reaction 0 is the one above
+  int n_rx = 1;
+  double xnu[MAXR][MAXS]{}, xord[MAXR][MAXS]{}, xk0[MAXR]{}, xea[MAXR]{}, xTref[MAXR]{}, xdH[MAXR]{};
+  bool rx_set = false;
   int coupling = FDLBM_COUPLING_FLUX;  // solid-gas coupling at the wall nodes
   double F[3]{}, X_in[MAXS]{}, p_in = 1.0 / 3, T_in = 1.0 / 3;
   double rho_ref[MAXS]{};  // reference densities of 16-bit storage (mean initial density)
@@ -69,6 +73,7 @@ struct fdlbm_ctx {
   size_t ws_bytes = 0;
   size_t off_cnr = 0, off_cnt = 0;  // Crank-Nicolson solid buffers
   size_t off_lj = 0;                // collision-integral table
+  size_t off_rxt = 0, off_wq = 0, off_aq = 0;  // reaction table, heat per wall node, heat accumulator
   size_t off_G[2]{}, off_Gs = 0, off_FR = 0, off_FX = 0, off_Ts[2]{}, off_wr = 0, off_wde = 0, off_kind = 0, off_slot = 0,
          off_scls = 0, off_wem = 0, off_gl = 0, off_wl = 0, off_am = 0, off_aw = 0, off_ab = 0,
          off_part = 0, off_snap = 0, off_snapts = 0, off_status = 0;
@@ -166,6 +171,8 @@ static void layout(fdlbm_ctx *c) {
   c->off_cnr = take(n * b);
   c->off_cnt = take(n * b);
   c->off_lj = take(128 * b);
+  c->off_rxt = take((size_t)MAXR * RXS * b);
+  c->off_wq = take(n * b);
   c->off_kind = take(n);
   c->off_slot = take(n * 4);
   c->off_scls = take(nsl * 8);
@@ -179,6 +186,7 @@ static void layout(fdlbm_ctx *c) {
   c->off_am = take((size_t)c->acc_slots * 8);
   c->off_aw = take((size_t)c->acc_slots * 8);
   c->off_ab = take((size_t)c->acc_slots * 8);
+  c->off_aq = take((size_t)c->acc_slots * 8);
   c->obs_blocks = 1024;
   c->off_part = take((size_t)c->obs_blocks * (MAXS + 9) * 8);
   c->off_snap = take((size_t)sn_count(c->D, c->ns) * nsl * b);
@@ -203,6 +211,8 @@ static Bufs<real, PT> bufs(const fdlbm_ctx *c) {
   b.cn_rhs = (real *)(w + c->off_cnr);
   b.cn_tmp = (real *)(w + c->off_cnt);
   b.lj_tab = (const real *)(w + c->off_lj);
+  b.rxt = (const real *)(w + c->off_rxt);
+  b.wall_q = (real *)(w + c->off_wq);
   b.kind = (const uint8_t *)(w + c->off_kind);
   b.slot_of = (const int32_t *)(w + c->off_slot);
   b.scls = (const uint64_t *)(w + c->off_scls);
@@ -212,6 +222,7 @@ static Bufs<real, PT> bufs(const fdlbm_ctx *c) {
   b.acc_moles = (double *)(w + c->off_am);
   b.acc_work = (double *)(w + c->off_aw);
   b.acc_bheat = (double *)(w + c->off_ab);
+  b.acc_heat = (double *)(w + c->off_aq);
   b.partials = (double *)(w + c->off_part);
   b.snap = (real *)(w + c->off_snap);
   b.snap_ts = (real *)(w + c->off_snapts);
@@ -352,6 +363,7 @@ static Params<real> params(const fdlbm_ctx *c) {
   p.max_iter = c->max_iter;
   p.rate_area = c->rate_area ? 1 : 0;
   p.halfway = c->halfway ? 1 : 0;
+  p.n_rx = c->n_rx;
   for (int a = 0; a < 3; ++a) p.F[a] = a < c->D ? (real)c->F[a] : real(0);
   p.T_in = (real)c->T_in;
   p.p_in = (real)c->p_in;
@@ -668,6 +680,33 @@ static int upload_lj(fdlbm_ctx *c) {
   return FDLBM_OK;
 }
 
+// the reaction table into the workspace, in the arithmetic type (reaction 0
+// from fdlbm_set_reaction, the others from fdlbm_add_reaction)
+static int upload_rx(fdlbm_ctx *c) {
+  if (!c->bound || !c->rx_set) return FDLBM_OK;
+  std::vector<double> t((size_t)MAXR * RXS, 0.0);
+  for (int k = 0; k < c->n_rx; ++k) {
+    double *r = &t[(size_t)k * RXS];
+    r[RX_K0] = k ? c->xk0[k] : c->k0;
+    r[RX_EA] = k ? c->xea[k] : c->ea;
+    r[RX_TREF] = k ? c->xTref[k] : c->T_ref_rxn;
+    r[RX_DH] = k ? c->xdH[k] : c->dH;
+    for (int j = 0; j < c->ns; ++j) {
+      r[RX_NU + j] = k ? c->xnu[k][j] : c->nu[j];
+      r[RX_ORD + j] = k ? c->xord[k][j] : c->order[j];
+    }
+  }
+  const size_t b = real_size(c);
+  std::vector<char> buf(t.size() * b);
+  for (size_t i = 0; i < t.size(); ++i) {
+    if (b == 8) reinterpret_cast<double *>(buf.data())[i] = t[i];
+    else reinterpret_cast<float *>(buf.data())[i] = (float)t[i];
+  }
+  HIPCHK(c, hipMemcpyAsync(c->ws + c->off_rxt, buf.data(), buf.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return FDLBM_OK;
+}
+
 int fdlbm_set_lj_transport(fdlbm_ctx *c, const double *eps_over_k, double T_unit, double tstar_min,
                            double tstar_max, int n, const double *omega_mu, const double *omega_d) {
   if (!c) return FDLBM_E_INVALID;
@@ -730,7 +769,31 @@ int fdlbm_set_reaction(fdlbm_ctx *c, const double *nu, const double *order, doub
   c->T_iso = T_iso;
   c->tol = tol;
   c->max_iter = max_iter;
-  return FDLBM_OK;
+  c->n_rx = 1;
+  c->rx_set = true;
+  return upload_rx(c);
+}
+
+int fdlbm_add_reaction(fdlbm_ctx *c, const double *nu, const double *order, double k0, double ea, double T_ref,
+                       double dH) {
+  if (!c || !nu || !order) return set_err(c, FDLBM_E_INVALID, "null argument");
+  if (!c->rx_set) return set_err(c, FDLBM_E_STATE, "set the first reaction with fdlbm_set_reaction");
+  if (c->n_rx >= MAXR) return set_err(c, FDLBM_E_INVALID, "at most %d surface reactions", MAXR);
+  for (int j = 0; j < c->ns; ++j)
+    if (!(order[j] >= 0 && order[j] <= 3 && order[j] == std::floor(order[j])))
+      return set_err(c, FDLBM_E_INVALID, "reaction orders must be integers 0..3");
+  if (!(k0 >= 0) || !(T_ref > 0)) return set_err(c, FDLBM_E_INVALID, "reaction parameters out of range");
+  const int k = c->n_rx;
+  for (int j = 0; j < c->ns; ++j) {
+    c->xnu[k][j] = nu[j];
+    c->xord[k][j] = order[j];
+  }
+  c->xk0[k] = k0;
+  c->xea[k] = ea;
+  c->xTref[k] = T_ref;
+  c->xdH[k] = dH;
+  c->n_rx = k + 1;
+  return upload_rx(c);
 }
 
 int fdlbm_set_solid_coupling(fdlbm_ctx *c, int mode) {
@@ -813,7 +876,8 @@ int fdlbm_bind_workspace(fdlbm_ctx *c, void *dev, size_t bytes) {
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->bound = true;
   c->initialized = false;
-  return upload_lj(c);
+  const int rc = upload_lj(c);
+  return rc != FDLBM_OK ? rc : upload_rx(c);
 }
 
 // clear the stability record (not inside any captured graph) and start its
@@ -903,6 +967,7 @@ static int init_impl(fdlbm_ctx *c, const double *rho, const double *u, const dou
   HIPCHK(c, hipMemsetAsync(c->ws + c->off_am, 0, (size_t)c->acc_slots * 8, c->stream));
   HIPCHK(c, hipMemsetAsync(c->ws + c->off_aw, 0, (size_t)c->acc_slots * 8, c->stream));
   HIPCHK(c, hipMemsetAsync(c->ws + c->off_ab, 0, (size_t)c->acc_slots * 8, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->ws + c->off_aq, 0, (size_t)c->acc_slots * 8, c->stream));
   c->step = 0;
   if (reset_status(c) != FDLBM_OK) return FDLBM_E_HIP;
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1079,12 +1144,14 @@ int fdlbm_observe(fdlbm_ctx *c, fdlbm_obs *o) {
   if (e != hipSuccess) return set_err(c, FDLBM_E_HIP, "observe launch: %s", hipGetErrorString(e));
   const int NP = c->ns + 9;
   std::vector<double> part((size_t)c->obs_blocks * NP);
-  std::vector<double> acc(3 * (size_t)c->acc_slots);
+  std::vector<double> acc(4 * (size_t)c->acc_slots);
   HIPCHK(c, hipMemcpyAsync(part.data(), c->ws + c->off_part, part.size() * 8, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(acc.data(), c->ws + c->off_am, (size_t)c->acc_slots * 8, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(acc.data() + c->acc_slots, c->ws + c->off_aw, (size_t)c->acc_slots * 8,
                            hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(acc.data() + 2 * c->acc_slots, c->ws + c->off_ab, (size_t)c->acc_slots * 8,
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(acc.data() + 3 * c->acc_slots, c->ws + c->off_aq, (size_t)c->acc_slots * 8,
                            hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   std::memset(o, 0, sizeof *o);
@@ -1104,12 +1171,15 @@ int fdlbm_observe(fdlbm_ctx *c, fdlbm_obs *o) {
     o->Ts_max = std::max(o->Ts_max, q[ns + 7]);
     if (q[ns + 8] != 0.0) o->bad = 1;
   }
+  double heat = 0.0;
   for (int s = 0; s < c->acc_slots; ++s) {
     o->moles_reacted += acc[s];
     o->work_body += acc[c->acc_slots + s];
     o->heat_boundary += acc[2 * c->acc_slots + s];
+    heat += acc[3 * c->acc_slots + s];
   }
-  o->heat_released = -c->dH * o->moles_reacted;
+  // one reaction: its enthalpy times the moles; several: their heat summed per wall node
+  o->heat_released = c->n_rx == 1 ? -c->dH * o->moles_reacted : heat;
   if (o->rho_min < 0) o->bad = 1;
   o->step = c->step;
   o->n_gas = (int32_t)c->gas_list.size();
@@ -1129,7 +1199,7 @@ int fdlbm_observe(fdlbm_ctx *c, fdlbm_obs *o) {
 // ---------------------------------------------------------------------------
 namespace {
 constexpr int OBS_BLOCKS = 1024;                       // grid of the observe kernel
-constexpr int OBS_FOLD = MAXS + 9 + 3;                 // folded values: partial slots + 3 sums
+constexpr int OBS_FOLD = MAXS + 9 + 4;                 // folded values: partial slots + 4 sums
 constexpr size_t SCRATCH_DOUBLES = (size_t)OBS_BLOCKS * (MAXS + 9) + 64;  // 139,776 bytes
 constexpr int MAX_DEVICES = 64;
 }  // namespace
@@ -1137,11 +1207,11 @@ constexpr int MAX_DEVICES = 64;
 static __device__ __align__(256) double scratch[SCRATCH_DOUBLES];
 
 // Fold the per-block partials (blocks rows of np values at part) and the
-// three accumulator arrays (acc_slots each) exactly as fdlbm_observe does on
+// four accumulator arrays (acc_slots each) exactly as fdlbm_observe does on
 // the host: sums in block order, minima and maxima by the same comparisons,
 // so the results are bitwise those of fdlbm_observe.  One thread per value.
 __global__ void k_obs_fold(const double *part, int blocks, int ns, const double *am, const double *aw,
-                           const double *ab, int acc_slots, double *out) {
+                           const double *ab, const double *aq, int acc_slots, double *out) {
   const int k = threadIdx.x, np = ns + 9;
   if (k < np) {
     const bool is_min = k == ns + 2 || k == ns + 5 || k == ns + 6;
@@ -1155,8 +1225,8 @@ __global__ void k_obs_fold(const double *part, int blocks, int ns, const double 
       else v += q;
     }
     out[k] = v;
-  } else if (k < np + 3) {
-    const double *a = k == np ? am : (k == np + 1 ? aw : ab);
+  } else if (k < np + 4) {
+    const double *a = k == np ? am : (k == np + 1 ? aw : (k == np + 2 ? ab : aq));
     double v = 0.0;
     for (int s = 0; s < acc_slots; ++s) v += a[s];
     out[k] = v;
@@ -1200,10 +1270,11 @@ int fdlbm_observe_noalloc(fdlbm_ctx *c, fdlbm_obs *o) {
   if (e != hipSuccess) return set_err(c, FDLBM_E_HIP, "observe launch: %s", hipGetErrorString(e));
   hipLaunchKernelGGL(k_obs_fold, dim3(1), dim3(64), 0, c->stream, (const double *)part, c->obs_blocks, ns,
                      (const double *)(c->ws + c->off_am), (const double *)(c->ws + c->off_aw),
-                     (const double *)(c->ws + c->off_ab), c->acc_slots, fold);
+                     (const double *)(c->ws + c->off_ab), (const double *)(c->ws + c->off_aq), c->acc_slots,
+                     fold);
   HIPCHK(c, hipGetLastError());
   double v[OBS_FOLD];
-  HIPCHK(c, hipMemcpyAsync(v, fold, (size_t)(NP + 3) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(v, fold, (size_t)(NP + 4) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   std::memset(o, 0, sizeof *o);
   for (int j = 0; j < ns; ++j) o->mass[j] = v[j];
@@ -1219,7 +1290,7 @@ int fdlbm_observe_noalloc(fdlbm_ctx *c, fdlbm_obs *o) {
   o->moles_reacted = v[NP];
   o->work_body = v[NP + 1];
   o->heat_boundary = v[NP + 2];
-  o->heat_released = -c->dH * o->moles_reacted;
+  o->heat_released = c->n_rx == 1 ? -c->dH * o->moles_reacted : v[NP + 3];
   if (o->rho_min < 0) o->bad = 1;
   o->step = c->step;
   o->n_gas = (int32_t)c->gas_list.size();
@@ -1608,6 +1679,7 @@ int fdlbm_batch_create(fdlbm_ctx *const *ctxs, int n, fdlbm_batch **out) {
     if (c->solid_scheme == FDLBM_SOLID_CN) return fail("Crank-Nicolson solids are not batched");
     if (c->coupling != FDLBM_COUPLING_FLUX) return fail("the Eq.(48) coupling is not batched");
     if (c->halfway) return fail("half-way walls are not batched");
+    if (c->n_rx > 1) return fail("several surface reactions are not batched");
     if (c->D != ctxs[0]->D || c->ns != ctxs[0]->ns || c->d.precision != ctxs[0]->d.precision ||
         c->stream != ctxs[0]->stream)
       return fail("contexts differ in lattice, species count, precision or stream");

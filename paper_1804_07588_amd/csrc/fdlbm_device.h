@@ -11,6 +11,10 @@
 namespace fdlbm {
 
 constexpr int MAXS = 8;     // species slots in the parameter block
+constexpr int MAXR = 4;     // surface reactions per wall node
+// reaction table (several reactions): per reaction k0, E_a / (R T_ref),
+// T_ref, dH, then the stoichiometry nu_j and the orders of MAXS species
+constexpr int RX_K0 = 0, RX_EA = 1, RX_TREF = 2, RX_DH = 3, RX_NU = 4, RX_ORD = 4 + MAXS, RXS = 4 + 2 * MAXS;
 constexpr int MAX_NS = 6;   // species counts the kernels are instantiated for
 constexpr int BLOCK = 256;  // threads per block of the list kernels
 
@@ -107,6 +111,7 @@ struct Params {
   real nu[MAXS], k0, ea, T_ref_rxn, dH, T_iso, tol;
   int order[MAXS];
   int max_iter;
+  int n_rx;                        // surface reactions; the first is the one above, all n_rx in rxt
   int rate_area;                   // 1: rate scaled by the wall node's wetted area
   int halfway;                     // 1: wall placed half-way along each link
   real srcf[MAXS];                 // wall source factor: 1, or 1 / c_j (stoichiometric mass flux)
@@ -155,6 +160,8 @@ struct Bufs {
   real *FX;           // per-slot record of the node itself: tau2_j, u_j, U^c, energy defect
   real *Ts[2];        // solid temperature per node, double-buffered
   real *wall_r;       // molar rate per node (wall nodes) of the last step
+  real *wall_q;       // reaction heat per wall node, last step (several reactions)
+  const real *rxt;    // reaction table, RXS values per reaction (several reactions)
   real *wall_dE;      // kinetic energy the wall gave the gas, per node, last step
   real *cn_rhs, *cn_tmp;  // Crank-Nicolson solid: right-hand side and sweep buffer, per node
   const real *lj_tab;     // collision integrals: Omega_mu[lj_n] then Omega_D[lj_n]
@@ -167,6 +174,7 @@ struct Bufs {
   double *acc_moles;  // per-block cumulative reaction extent
   double *acc_work;   // per-block cumulative body-force work
   double *acc_bheat;  // per-block cumulative Dirichlet-face heat
+  double *acc_heat;   // per-block cumulative reaction heat (several reactions)
   double *partials;   // observe / residual reduction partials
   real *snap;         // residual snapshot per gas slot: X_j, T, u_a (sn_count values)
   real *snap_ts;      // residual snapshot of the solid temperature per node

@@ -409,6 +409,93 @@ __device__ inline real ipow(real x, int k) {
 // ===========================================================================
 // k_wall: the reactive diffusive wall, one thread per wall node
 // ===========================================================================
+// Several surface reactions at one wall node (the flux boundary condition
+// takes any source; with several reactions S_j sums theirs).  A_j arriving
+// mass, Zj_j emission weights, area the rate factor, rw_j in: A_j / Zj_j.
+// The fixed point updates the species some reaction consumes with a
+// positive order, each with its own consumption implicit and its production
+// at the current densities; then the rates at the converged densities and
+// the wall densities from the exact mass balance.  r: the summed rates
+// (moles per step), q: the reaction heat sum_k -dH_k r_k (Eq.(42)).
+template <typename real, int NS>
+__device__ inline void several_reactions(const Params<real> &p, const real *__restrict__ rxt, const real (&A)[NS],
+                                         const real (&Zj)[NS], real area, real Tw, real (&rw)[NS], real &r,
+                                         real &q) {
+  real kk[MAXR];
+  unsigned upd = 0;
+#pragma unroll
+  for (int k = 0; k < MAXR; ++k) {
+    kk[k] = real(0);
+    if (k < p.n_rx) {
+      const real *t = rxt + k * RXS;
+      kk[k] = area * t[RX_K0] * exp(t[RX_EA] * (real(1) - t[RX_TREF] / Tw));
+#pragma unroll
+      for (int j = 0; j < NS; ++j)
+        if (t[RX_NU + j] < real(0) && t[RX_ORD + j] > real(0)) upd |= 1u << j;
+    }
+  }
+  // rate of reaction k at rw, or (lower >= 0) divided by C_lower: that
+  // species' power lowered by one (lower has a positive order in k)
+  auto rate = [&](int k, int lower) {
+    const real *t = rxt + k * RXS;
+    real v = kk[k];
+#pragma unroll
+    for (int m = 0; m < NS; ++m) v *= ipow(rw[m] * p.invM[m], (int)t[RX_ORD + m] - (m == lower ? 1 : 0));
+    return v;
+  };
+  for (int it = 0; it < p.max_iter; ++it) {
+    real rk[MAXR];
+#pragma unroll
+    for (int k = 0; k < MAXR; ++k) rk[k] = k < p.n_rx ? rate(k, -1) : real(0);
+    real nw[NS], dmax = 0;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      nw[j] = rw[j];
+      if ((upd >> j) & 1u) {
+        real num = 0, den = 0;
+#pragma unroll
+        for (int k = 0; k < MAXR; ++k) {
+          if (k >= p.n_rx) continue;
+          const real *t = rxt + k * RXS;
+          const real nu = t[RX_NU + j];
+          if (nu < real(0) && t[RX_ORD + j] > real(0)) den += nu * p.srcf[j] * rate(k, j);
+          else if (nu != real(0)) num += nu * p.M[j] * p.srcf[j] * rk[k];
+        }
+        nw[j] = (A[j] + num) / (Zj[j] - den);
+      }
+      dmax = fmax(dmax, fabs(nw[j] - rw[j]) / fmax(fabs(nw[j]), tiny<real>()));
+    }
+#pragma unroll
+    for (int j = 0; j < NS; ++j) rw[j] = nw[j];
+    if (dmax <= p.tol) break;
+  }
+  real rk[MAXR];
+#pragma unroll
+  for (int k = 0; k < MAXR; ++k) rk[k] = k < p.n_rx ? rate(k, -1) : real(0);
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    real src = 0;
+#pragma unroll
+    for (int k = 0; k < MAXR; ++k)
+      if (k < p.n_rx) src += rxt[k * RXS + RX_NU + j] * p.M[j] * p.srcf[j] * rk[k];
+    rw[j] = (A[j] + src) / Zj[j];
+  }
+  r = 0;
+  q = 0;
+#pragma unroll
+  for (int k = 0; k < MAXR; ++k)
+    if (k < p.n_rx) {
+      r += rk[k];
+      q += -rxt[k * RXS + RX_DH] * rk[k];
+    }
+}
+
+// what a wall node hands to its block's sums: the moles reacted and (several
+// reactions) the reaction heat
+struct WallOut {
+  double r, q;
+};
+
 // Half-way wall (Sec. 4.3; the interpolation step taken linear): along link i
 // into gas node x the wall node thermalises at the state whose linear
 // interpolant with x takes the wall's values at the link's midpoint,
@@ -433,9 +520,11 @@ __device__ inline void halfway_weights(const Params<real> &p, const BF &b, const
   }
 }
 
-template <bool FAST, bool HALF, typename real, typename PT, int D, int NS>
-__device__ inline double wall_node(const Params<real> &p, const Bufs<real, PT> &b, int cur,
-                                   const WTab<real> &wtab, const int wi) {
+// HALF: the half-way wall; MULTI: several surface reactions (separate
+// instantiations, so that the common kernel keeps its register budget)
+template <bool FAST, bool HALF, bool MULTI, typename real, typename PT, int D, int NS>
+__device__ inline WallOut wall_node(const Params<real> &p, const Bufs<real, PT> &b, int cur,
+                                    const WTab<real> &wtab, const int wi) {
   constexpr int Q = lat_q<D>();
   constexpr int NR = fr_count(D, NS);
   const int slot = p.n_gas + wi;
@@ -500,37 +589,42 @@ __device__ inline double wall_node(const Params<real> &p, const Bufs<real, PT> &
   // rate constant at T_w (Eq.(50) with the Arrhenius factor); one reaction
   // term per wall node, corners included (Sec. 4.3), or, as an option, per
   // unit wetted area: the node's rest emission weight over its links into
-  // the gas relative to a plane wall's T_w / 2 (Z itself: the wall emits at
-  // rest, so Z is that weight)
-  const real keff = (p.rate_area ? Z / (real(0.5) * Tw) : real(1)) * p.k0 * exp(p.ea * (real(1) - p.T_ref_rxn / Tw));
-  for (int it = 0; it < p.max_iter; ++it) {
-    real nw[NS], dmax = 0;
-#pragma unroll
-    for (int j = 0; j < NS; ++j) {
-      nw[j] = rw[j];
-      if (p.nu[j] < real(0) && p.order[j] > 0) {
-        real R = keff;
-#pragma unroll
-        for (int m = 0; m < NS; ++m) R *= ipow(rw[m] * p.invM[m], p.order[m] - (m == j ? 1 : 0));
-        nw[j] = A[j] / (Zj[j] - p.nu[j] * p.srcf[j] * R);
-      }
-      const real d = fabs(nw[j] - rw[j]) / fmax(fabs(nw[j]), tiny<real>());
-      dmax = fmax(dmax, d);
-    }
-#pragma unroll
-    for (int j = 0; j < NS; ++j) rw[j] = nw[j];
-    if (dmax <= p.tol) break;
-  }
-  real r = keff;
-#pragma unroll
-  for (int m = 0; m < NS; ++m) r *= ipow(rw[m] * p.invM[m], p.order[m]);
-  if constexpr (HALF) {
-#pragma unroll
-    for (int j = 0; j < NS; ++j) rw[j] = (A[j] + p.nu[j] * p.M[j] * p.srcf[j] * r) / Zj[j];
+  // the gas relative to a plane wall's T_w / 2 (Z itself: the rest weights)
+  const real area = p.rate_area ? Z / (real(0.5) * Tw) : real(1);
+  real r, q = 0;
+  if constexpr (MULTI) {
+    several_reactions<real, NS>(p, b.rxt, A, Zj, area, Tw, rw, r, q);
   } else {
-    const real invZ = real(1) / Z;
+    const real keff = area * p.k0 * exp(p.ea * (real(1) - p.T_ref_rxn / Tw));
+    for (int it = 0; it < p.max_iter; ++it) {
+      real nw[NS], dmax = 0;
 #pragma unroll
-    for (int j = 0; j < NS; ++j) rw[j] = (A[j] + p.nu[j] * p.M[j] * p.srcf[j] * r) * invZ;
+      for (int j = 0; j < NS; ++j) {
+        nw[j] = rw[j];
+        if (p.nu[j] < real(0) && p.order[j] > 0) {
+          real R = keff;
+#pragma unroll
+          for (int m = 0; m < NS; ++m) R *= ipow(rw[m] * p.invM[m], p.order[m] - (m == j ? 1 : 0));
+          nw[j] = A[j] / (Zj[j] - p.nu[j] * p.srcf[j] * R);
+        }
+        const real d = fabs(nw[j] - rw[j]) / fmax(fabs(nw[j]), tiny<real>());
+        dmax = fmax(dmax, d);
+      }
+#pragma unroll
+      for (int j = 0; j < NS; ++j) rw[j] = nw[j];
+      if (dmax <= p.tol) break;
+    }
+    r = keff;
+#pragma unroll
+    for (int m = 0; m < NS; ++m) r *= ipow(rw[m] * p.invM[m], p.order[m]);
+    if constexpr (HALF) {
+#pragma unroll
+      for (int j = 0; j < NS; ++j) rw[j] = (A[j] + p.nu[j] * p.M[j] * p.srcf[j] * r) / Zj[j];
+    } else {
+      const real invZ = real(1) / Z;
+#pragma unroll
+      for (int j = 0; j < NS; ++j) rw[j] = (A[j] + p.nu[j] * p.M[j] * p.srcf[j] * r) * invZ;
+    }
   }
   // emission: rho_w,j f^eq_i(1, 0, T_w) on the links into the gas (half-way:
   // the link's own weights, computed again)
@@ -562,30 +656,36 @@ __device__ inline double wall_node(const Params<real> &p, const Bufs<real, PT> &
   }
   strec<real, NR>(b.FR, slot, fr);
   b.wall_r[w] = r;
+  if constexpr (MULTI) b.wall_q[w] = q;
   b.wall_dE[w] = real(0.5) * (Eout - Ein);
-  return (double)r;
+  return WallOut{(double)r, (double)q};
 }
 
 // FAST: the node list holds only nodes whose taps never wrap a periodic axis.
 // One block of wall nodes (logical block lb of the list).
-template <bool FAST, bool HALF, typename real, typename PT, int D, int NS>
+template <bool FAST, bool HALF, bool MULTI, typename real, typename PT, int D, int NS>
 __device__ __forceinline__ void wall_block(const Params<real> &p, const Bufs<real, PT> &b, int cur,
                                            const WTab<real> &wtab, int lb) {
   const int first = FAST ? 0 : p.n_wall_fast, count = FAST ? p.n_wall_fast : p.n_wall - p.n_wall_fast;
   const int t = lb * BLOCK + threadIdx.x;
-  double r_out = 0.0;
-  if (t < count) r_out = wall_node<FAST, HALF, real, PT, D, NS>(p, b, cur, wtab, first + t);
-  const double s = block_sum(r_out);
-  if (threadIdx.x == 0) b.acc_moles[lb + (FAST ? 0 : p.slot_off_wall)] += s;
+  WallOut o{0.0, 0.0};
+  if (t < count) o = wall_node<FAST, HALF, MULTI, real, PT, D, NS>(p, b, cur, wtab, first + t);
+  const int slot = lb + (FAST ? 0 : p.slot_off_wall);
+  const double s = block_sum(o.r);
+  if (threadIdx.x == 0) b.acc_moles[slot] += s;
+  if constexpr (MULTI) {
+    const double sq = block_sum(o.q);
+    if (threadIdx.x == 0) b.acc_heat[slot] += sq;
+  }
 }
-template <bool FAST, bool HALF, typename real, typename PT, int D, int NS>
+template <bool FAST, bool HALF, bool MULTI, typename real, typename PT, int D, int NS>
 __global__ void __launch_bounds__(BLOCK) k_wall(Params<real> p, Bufs<real, PT> b, int cur) {
   __shared__ WTab<real> wtab;
   load_wtab<real, NS>(p, wtab);
   const int count = FAST ? p.n_wall_fast : p.n_wall - p.n_wall_fast;
   const int nb = (count + BLOCK - 1) / BLOCK, lb = xcd_block(nb);
   if (lb >= nb) return;  // whole block: no barrier follows for it
-  wall_block<FAST, HALF, real, PT, D, NS>(p, b, cur, wtab, lb);
+  wall_block<FAST, HALF, MULTI, real, PT, D, NS>(p, b, cur, wtab, lb);
 }
 
 // ===========================================================================
@@ -1322,7 +1422,8 @@ __device__ __forceinline__ void solid_pass(const Params<real> &p, const Bufs<rea
               qg += kap * (Tf - T);
             }
         }
-        Tn += (-p.dH * b.wall_r[nd] + qg) * p.invCs;
+        // the reaction heat: one reaction's -dH r, or several reactions' sum
+        Tn += (p.n_rx == 1 ? -p.dH * b.wall_r[nd] + qg : b.wall_q[nd] + qg) * p.invCs;
       }
       if constexpr (MODE == 0) Tout[nd] = Tn;
       else b.cn_rhs[nd] = Tn;
@@ -1541,7 +1642,8 @@ __global__ void __launch_bounds__(BLOCK) kb_wall(const Params<real> *__restrict_
       load_wtab<real, NS>(P[it.x], wtab);
       prev = it.x;
     }
-    wall_block<FAST, false, real, PT, D, NS>(P[it.x], B[it.x], cur, wtab, it.y);  // batches: walls on the node
+    // batches: walls on the node, one reaction
+    wall_block<FAST, false, false, real, PT, D, NS>(P[it.x], B[it.x], cur, wtab, it.y);
   });
 }
 
@@ -1611,13 +1713,17 @@ inline hipError_t step_impl(const Params<real> &p, const Bufs<real, PT> &b, int 
     (void)hipStreamWaitEvent(sw, li.ev_fork, 0);
   }
   mark(K_WALL_ID, 0, sw);
-  if (p.halfway) {
-    if (gwf > 0) hipLaunchKernelGGL((k_wall<true, true, real, PT, D, NS>), dim3(xcd_grid(gwf)), blk, 0, sw, p, b, cur);
-    if (gws > 0) hipLaunchKernelGGL((k_wall<false, true, real, PT, D, NS>), dim3(xcd_grid(gws)), blk, 0, sw, p, b, cur);
-  } else {
-    if (gwf > 0) hipLaunchKernelGGL((k_wall<true, false, real, PT, D, NS>), dim3(xcd_grid(gwf)), blk, 0, sw, p, b, cur);
-    if (gws > 0) hipLaunchKernelGGL((k_wall<false, false, real, PT, D, NS>), dim3(xcd_grid(gws)), blk, 0, sw, p, b, cur);
-  }
+  // the wall variants: half-way wall and several reactions, as compile-time flags
+  auto wall = [&](auto half, auto multi) {
+    constexpr bool H = decltype(half)::value, MU = decltype(multi)::value;
+    if (gwf > 0) hipLaunchKernelGGL((k_wall<true, H, MU, real, PT, D, NS>), dim3(xcd_grid(gwf)), blk, 0, sw, p, b, cur);
+    if (gws > 0) hipLaunchKernelGGL((k_wall<false, H, MU, real, PT, D, NS>), dim3(xcd_grid(gws)), blk, 0, sw, p, b, cur);
+  };
+  const bool multi = p.n_rx > 1;
+  if (!p.halfway && !multi) wall(std::false_type{}, std::false_type{});
+  else if (p.halfway && !multi) wall(std::true_type{}, std::false_type{});
+  else if (!p.halfway) wall(std::false_type{}, std::true_type{});
+  else wall(std::true_type{}, std::true_type{});
   mark(K_WALL_ID, 1, sw);
   if (two) (void)hipEventRecord(li.ev_wall, sw);
   // the solid step: forward Euler, or Crank-Nicolson by p.cn_iters Jacobi

@@ -43,7 +43,7 @@ EXPORTS = ["fdlbm_create", "fdlbm_destroy", "fdlbm_last_error", "fdlbm_set_geome
            "fdlbm_batch_get_grid", "fdlbm_batch_autotune", "fdlbm_batch_set_overlap",
            "fdlbm_set_sync_check", "fdlbm_last_step", "fdlbm_observe_noalloc", "fdlbm_set_rate_scaling",
            "fdlbm_set_wall_source", "fdlbm_get_field_device", "fdlbm_batch_check",
-           "fdlbm_set_wall_position",
+           "fdlbm_set_wall_position", "fdlbm_add_reaction",
            "fdlbm_set_solid_coupling"]
 BATCH_KINDS = ["wall_fast", "wall_slow", "gas_fast", "gas_slow", "collide", "solid"]
 
@@ -121,6 +121,7 @@ def lib() -> ct.CDLL:
         L.fdlbm_set_rate_scaling.argtypes = [vp, ct.c_int]
         L.fdlbm_set_wall_source.argtypes = [vp, ct.c_int]
         L.fdlbm_set_wall_position.argtypes = [vp, ct.c_int]
+        L.fdlbm_add_reaction.argtypes = [vp, dp, dp, ct.c_double, ct.c_double, ct.c_double, ct.c_double]
         L.fdlbm_get_field_device.argtypes = [vp, ct.c_int, ct.c_int, vp]
         L.fdlbm_batch_check.argtypes = [vp, ct.POINTER(ct.c_int), ct.POINTER(i64)]
         L.fdlbm_set_solid_coupling.argtypes = [vp, ct.c_int]
@@ -194,6 +195,10 @@ def configure(h, cfg: dict) -> None:
         check(L.fdlbm_set_wall_source(h, SOURCE_FLUX))
     if rx.get("halfway"):
         check(L.fdlbm_set_wall_position(h, WALL_HALFWAY))
+    for more in rx.get("more", ()):
+        # further reactions at every wall node (same keys as the first)
+        mnu, mord = _arr(more["nu"]), _arr(more["order"])
+        check(L.fdlbm_add_reaction(h, _d(mnu), _d(mord), more["k0"], more["ea"], more["T_ref"], more["dH"]))
     fl = cfg["flow"]
     F, Xin = _arr(fl["F"]), _arr(fl["X_in"])
     check(L.fdlbm_set_flow(h, _d(F), _d(Xin), fl["p_in"], fl["T_in"]))

@@ -216,6 +216,27 @@ def channel_c1(nx: int = 64, ny: int = 40, wall: int = 4, pr: float = 1.0) -> di
     )
 
 
+def channel_two_reactions(kind: str = "parallel", k: tuple = (1e-2, 5e-3), dH: tuple = (-0.1, -0.04),
+                          M: tuple = (1.0, 1.0, 1.0)) -> dict:
+    """The D2Q9 channel with three species A, B, C and two first-order surface
+    reactions at every wall node: A -> B and A -> C ("parallel") or A -> B and
+    B -> C ("consecutive"); rate constants k, reaction enthalpies dH; inlet
+    and initial mole fractions 0.6, 0.25, 0.15."""
+    cfg = channel_c1()
+    T0 = 1.0 / 3.0
+    mu0 = cfg["species"]["mu0"][0]
+    dab = cfg["species"]["Djk0"][0][1]
+    X = [0.6, 0.25, 0.15]
+    cfg["species"].update(names=["A", "B", "C"], M=list(M), mu0=[mu0 * float(np.sqrt(m)) for m in M],
+                          Djk0=[[0.0 if a == b else dab for b in range(3)] for a in range(3)])
+    second = ([-1.0, 0.0, 1.0], [1.0, 0.0, 0.0]) if kind == "parallel" else ([0.0, -1.0, 1.0], [0.0, 1.0, 0.0])
+    cfg["reaction"].update(nu=[-1.0, 1.0, 0.0], order=[1.0, 0.0, 0.0], k0=k[0], ea=0.0, T_ref=T0, dH=dH[0],
+                           more=[dict(nu=second[0], order=second[1], k0=k[1], ea=0.0, T_ref=T0, dH=dH[1])])
+    cfg["flow"]["X_in"] = list(X)
+    cfg["init"]["X"] = list(X)
+    return cfg
+
+
 # Water-gas shift species (masses relative to H2, Sec. 4.4 / Sec. 6).
 WGS_NAMES = ["CO", "H2O", "CO2", "H2", "N2"]
 WGS_M = [14.0, 9.0, 22.0, 1.0, 14.0]

@@ -102,6 +102,14 @@ def test_invalid_inputs_are_rejected(L):
     order = np.array([1.5, 0.0])
     assert L.fdlbm_set_reaction(h, nu.ctypes.data_as(dp), order.ctypes.data_as(dp), 1e-3, 0, 1 / 3,
                                 -0.1, 0, 1 / 3, 1e-12, 20) == fdlbm.E_INVALID
+    # a further reaction before the first one, then beyond the limit
+    z2 = np.zeros(2)
+    assert L.fdlbm_add_reaction(h, z2.ctypes.data_as(dp), z2.ctypes.data_as(dp), 1e-3, 0, 1 / 3, 0) == fdlbm.E_STATE
+    assert L.fdlbm_set_reaction(h, z2.ctypes.data_as(dp), z2.ctypes.data_as(dp), 1e-3, 0, 1 / 3, -0.1, 0,
+                                1 / 3, 1e-12, 20) == fdlbm.OK
+    for k in range(3):
+        assert L.fdlbm_add_reaction(h, z2.ctypes.data_as(dp), z2.ctypes.data_as(dp), 1e-3, 0, 1 / 3, 0) == fdlbm.OK
+    assert L.fdlbm_add_reaction(h, z2.ctypes.data_as(dp), z2.ctypes.data_as(dp), 1e-3, 0, 1 / 3, 0) == fdlbm.E_INVALID
     # options outside their sets
     assert L.fdlbm_set_wall_position(h, 2) == fdlbm.E_INVALID
     assert L.fdlbm_set_wall_source(h, -1) == fdlbm.E_INVALID
@@ -130,7 +138,7 @@ def host_cases():
     D3Q19, periodic and closed axes, inlet/outlet rows, sphere packs of the
     benchmark's construction (the 128^3 bed and three batch beds), the
     Crank-Nicolson solid, Eq.(48) coupling, per-area rates, species Prandtl
-    numbers, a Lennard-Jones table and the half-way wall."""
+    numbers, a Lennard-Jones table, the half-way wall and several reactions."""
     c1 = W.channel_c1()
     rng = np.random.default_rng(3)
     noisy = (rng.random((1, 24, 32)) < 0.3).astype(np.uint8)
@@ -151,7 +159,11 @@ def host_cases():
                                eps_over_k=[100.0, 300.0, 200.0, 60.0, 80.0])
     lj["species"]["Pr_j"] = [0.7, 0.8, 0.9, 1.0, 0.75]
     half = W.with_changes(bed, reaction=dict(halfway=True))
-    return cases + [("bed_eq48", eq48), ("bed_lj_prj", lj), ("bed_halfway", half)]
+    rev = W.with_changes(bed)
+    rev["reaction"]["more"] = [dict(nu=[1.0, 1.0, -1.0, -1.0, 0.0], order=[0.0, 0.0, 1.0, 1.0, 0.0], k0=1e-4,
+                                    ea=10.0, T_ref=1 / 3, dH=0.408)]
+    return cases + [("bed_eq48", eq48), ("bed_lj_prj", lj), ("bed_halfway", half),
+                    ("channel_consecutive", W.channel_two_reactions("consecutive")), ("bed_two_reactions", rev)]
 
 
 @pytest.mark.parametrize("precision", [fdlbm.F64, fdlbm.F32, fdlbm.F16, fdlbm.BF16])

@@ -701,3 +701,116 @@ def test_off_diagonal_energy_flux_correction_restores_galilean_invariance(oracle
     shift = 1.0 * U * U / (2.5 * T0 * T0)  # Pr = 1, c_p = 5/2
     assert rd_ / r0 - 1 == pytest.approx(-shift, abs=2e-3)
     assert ra_ / r0 - 1 == pytest.approx(+shift, abs=2e-3)
+
+
+def test_reaction_split_in_two_halves_is_the_same_reaction(oracle_lib):
+    """Several surface reactions sum their sources: a reaction split into two
+    identical ones of half the rate constant gives the same run.  Halving is
+    exact in binary, so every field and counter is bitwise that of the single
+    reaction (the channel with a heavy product, 150 steps)."""
+    of = oracle_lib
+    base = W.with_changes(W.channel_c1(), init=dict(X=[0.7, 0.3]), reaction=dict(k0=1e-2))
+    base["species"].update(M=[1.0, 4.0], mu0=[0.1, 0.2])
+    base["flow"]["X_in"] = [0.7, 0.3]
+    rx = base["reaction"]
+    split = W.with_changes(base, reaction=dict(k0=rx["k0"] / 2, more=[dict(
+        nu=rx["nu"], order=rx["order"], k0=rx["k0"] / 2, ea=rx["ea"], T_ref=rx["T_ref"], dH=rx["dH"])]))
+    init = W.perturbed_init(base, 31)
+    a, b = of.OracleSim(base, init), of.OracleSim(split, init)
+    a.step(150)
+    b.step(150)
+    for fid, comps in ((of.OF_POP, 2), (of.OF_RHO, 2), (of.OF_T, 1), (of.OF_TS, 1), (of.OF_WALL_R, 1)):
+        for c in range(comps):
+            assert np.array_equal(a.field(fid, c), b.field(fid, c)), (fid, c)
+    oa, ob = a.observe(), b.observe()
+    assert oa["moles_reacted"] > 0 and oa["moles_reacted"] == ob["moles_reacted"]
+    assert oa["heat_released"] == ob["heat_released"]
+    a.close()
+    b.close()
+
+
+def test_parallel_reactions_branch_and_balance_exactly(oracle_lib):
+    """Two first-order reactions of the same reactant, A -> B (k1, dH1) and
+    A -> C (k2, dH2), at every wall node of the channel (all species of mass
+    1, so the wall's sources reach the gas exactly): each wall node's rates
+    stand in the ratio k1 : k2 at every step, so B gains k1 / (k1 + k2) and C
+    k2 / (k1 + k2) of the reacted moles, A loses all of them, the reaction
+    heat is -(k1 dH1 + k2 dH2) / (k1 + k2) per mole, and total energy
+    (gas + solid) changes by exactly that heat plus the boundary heat and
+    the body-force work."""
+    of = oracle_lib
+    k1, k2, h1, h2 = 1e-2, 4e-3, -0.1, -0.03
+    cfg = W.channel_two_reactions("parallel", k=(k1, k2), dH=(h1, h2))
+    sim = of.OracleSim(cfg, W.uniform_init(cfg))
+    o0 = sim.observe()
+    sim.step(200)
+    o1 = sim.observe()
+    mol = o1["moles_reacted"]
+    assert mol > 1.0
+    dm = o1["mass"][:3] - o0["mass"][:3]
+    scale = 1e-12 * o0["mass"].sum()
+    assert abs(dm[0] + mol) < scale
+    assert abs(dm[1] - k1 / (k1 + k2) * mol) < scale
+    assert abs(dm[2] - k2 / (k1 + k2) * mol) < scale
+    assert o1["heat_released"] == pytest.approx(-(k1 * h1 + k2 * h2) / (k1 + k2) * mol, rel=1e-12)
+    dE = (o1["e_gas"] + o1["e_solid"]) - (o0["e_gas"] + o0["e_solid"])
+    src = o1["heat_released"] + o1["heat_boundary"] + o1["work_body"]
+    assert abs(dE - src) < 1e-12 * (o0["e_gas"] + o0["e_solid"])
+    sim.close()
+
+
+@pytest.mark.parametrize("per_area,flux", [(False, False), (True, False), (False, True)])
+def test_consecutive_reactions_first_step_closed_form(oracle_lib, per_area, flux):
+    """Consecutive first-order reactions A -> B (k1) and B -> C (k2) at every
+    wall node of a sphere pack, from a uniform gas at rest (A_j = rho_j Z, as
+    in the single-reaction closed form): the iteration treats each species'
+    own consumption implicitly and its production at the current densities,
+    so at convergence rho_A,w = A_A / (Z + k1 a s_A), r1 = a k1 rho_A,w / M_A,
+    rho_B,w = (A_B + s_B M_B r1) / (Z + k2 a s_B), r2 = a k2 rho_B,w / M_B and
+    rho_C,w = (A_C + s_C M_C r2) / Z (s_j = 1, or 1 / c_j with the
+    flux-scaled source; a the per-area factor or 1).  The wall rate field is
+    r1 + r2 and the first step's heat -dH1 sum r1 - dH2 sum r2.  Heavy species
+    (M = 4) stream through the interpolated and degraded classes."""
+    of = oracle_lib
+    mask, _ = W.sphere_pack_mask(16, radius=3.0, porosity=0.6, seed=5, buffer=0)
+    k1, k2, h1, h2 = 0.05, 0.03, -0.2, 0.05
+    cfg = mixture_box(16, (4.0, 4.0, 4.0), [[0, 0.05, 0.05], [0.05, 0, 0.05], [0.05, 0.05, 0]],
+                      (0.05, 0.05, 0.05))
+    cfg["mask"] = mask
+    X = [0.5, 0.3, 0.2]
+    cfg["init"]["X"] = X
+    cfg["reaction"].update(nu=[-1.0, 1.0, 0.0], order=[1.0, 0.0, 0.0], k0=k1, ea=3.0, T_ref=T0, dH=h1,
+                           max_iter=200, rate_area=per_area, source_flux=flux,
+                           more=[dict(nu=[0.0, -1.0, 1.0], order=[0.0, 1.0, 0.0], k0=k2, ea=3.0, T_ref=T0,
+                                      dH=h2)])
+    sim = of.OracleSim(cfg, W.uniform_init(cfg))
+    sim.step(1)
+    kind = sim.field(of.OF_KIND).reshape(mask.shape)
+    walls = np.argwhere(kind == 2)
+    gas = (kind == 0)
+    nz, ny, nx = mask.shape
+    Z = np.zeros(len(walls))
+    for q, (z, y, x) in enumerate(walls):
+        for i in range(1, 19):
+            cx, cy, cz = D3Q19[i]
+            if gas[(z + cz) % nz, (y + cy) % ny, (x + cx) % nx]:
+                Z[q] += W19[i]
+    a = Z / (0.5 * T0) if per_area else np.ones_like(Z)
+    M = 4.0
+    s = np.sqrt(M) if flux else 1.0
+    rho = [M * x for x in X]
+    rA = rho[0] * Z / (Z + k1 * a * s)
+    r1 = a * k1 * rA / M
+    rB = (rho[1] * Z + s * M * r1) / (Z + k2 * a * s)
+    r2 = a * k2 * rB / M
+    rC = (rho[2] * Z + s * M * r2) / Z
+    flat = walls[:, 0] * ny * nx + walls[:, 1] * nx + walls[:, 2]
+    for j, want in enumerate((rA, rB, rC)):
+        got = sim.field(of.OF_RHO, j)[flat]
+        assert np.abs(got - want).max() <= 1e-12 * want.max(), j
+    got_r = sim.field(of.OF_WALL_R)[flat]
+    assert np.abs(got_r - (r1 + r2)).max() <= 1e-12 * (r1 + r2).max()
+    o = sim.observe()
+    assert o["moles_reacted"] == pytest.approx((r1 + r2).sum(), rel=1e-12)
+    assert o["heat_released"] == pytest.approx(-h1 * r1.sum() - h2 * r2.sum(), rel=1e-12)
+    sim.close()

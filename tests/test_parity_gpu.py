@@ -803,6 +803,57 @@ def test_halfway_wall(oracle_lib, fd, prec):
         a.close()
 
 
+def with_reverse_shift(cfg, k0=2e-4):
+    """The bed's water-gas shift plus its reverse as a second surface
+    reaction (CO2 + H2 -> CO + H2O, opposite enthalpy, lower activation)."""
+    rx = cfg["reaction"]
+    rx["more"] = [dict(nu=[-x for x in rx["nu"]], order=[0.0, 0.0, 1.0, 1.0, 0.0], k0=k0, ea=0.5 * rx["ea"],
+                       T_ref=rx["T_ref"], dH=-rx["dH"])]
+    return cfg
+
+
+@pytest.mark.parametrize("prec", ["F64", "F32"])
+def test_several_reactions(oracle_lib, fd, prec):
+    """fdlbm_add_reaction: two surface reactions at every wall node.  The
+    channel with parallel reactions A -> B, A -> C, and with consecutive
+    ones A -> B -> C among species of masses 1, 4, 9 (interpolated
+    streaming, an intermediate updated by the wall-density iteration from
+    both sides), from perturbed states; the five-species sphere pack with
+    the water-gas shift and its reverse.  Fields, the summed rate and the
+    reaction heat against the oracle."""
+    precision = getattr(fd, prec)
+    cases = [("parallel", W.channel_two_reactions("parallel"), 300),
+             ("consecutive", W.channel_two_reactions("consecutive", k=(2e-2, 1e-2), M=(1.0, 4.0, 9.0)), 300)]
+    for name, cfg, steps in cases:
+        o, g = run_both(oracle_lib, fd, cfg, W.perturbed_init(cfg, 23, amp_T=0.01), steps, precision)
+        e = field_errors(o, g, fd, 3, 2)
+        if prec == "F64":
+            ok64(e)
+        else:
+            ok32(e, tol_u=2e-3, tol_ucs=3e-6)
+        oo, og = o.observe(), g.observe()
+        rel = 1e-10 if prec == "F64" else 2e-5
+        assert oo["moles_reacted"] > 0, name
+        assert og["moles_reacted"] == pytest.approx(oo["moles_reacted"], rel=rel), name
+        assert og["heat_released"] == pytest.approx(oo["heat_released"], rel=rel), name
+        assert og["heat_released"] != pytest.approx(-cfg["reaction"]["dH"] * og["moles_reacted"], rel=1e-3)
+    # 60 FP32 steps, as the bed's other variants: the trace reactants of the
+    # reverse reaction reached 1.2e-5 (two roundings per step) after 100
+    cfg = with_reverse_shift(small_bed())
+    o, g = run_both(oracle_lib, fd, cfg, W.perturbed_init(cfg, 24, amp_u=0.005), 40 if prec == "F64" else 60,
+                    precision)
+    e = field_errors(o, g, fd, 5, 3)
+    if prec == "F64":
+        ok64(e)
+    else:
+        ok32(e)
+    oo, og = o.observe(), g.observe()
+    rel = 1e-10 if prec == "F64" else 2e-5
+    assert og["heat_released"] == pytest.approx(oo["heat_released"], rel=rel)
+    # the noalloc observation sums the heat the same way
+    assert g.observe_noalloc()["heat_released"] == og["heat_released"]
+
+
 def n_species(cfg, ns, masses=(1.0, 2.0, 4.0, 9.0, 14.0, 22.0)):
     """The configuration with ns species of the given masses: species 0 reacts
     to species 1 at the walls (first order), the others are inert; binary
