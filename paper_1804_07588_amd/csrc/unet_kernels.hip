@@ -122,10 +122,15 @@ __global__ void __launch_bounds__(TPB) k_conv(const __bf16 *__restrict__ X, int 
 // gWp[chunk][co][tap][ci] = sum over the chunk's s of gY[s][co] X[s + off(tap)][ci]
 // (k_colsum then adds the chunks in a fixed order, so the result does not
 // depend on the order in which workgroups run).
-// Grid (27 taps, chunks of L positions, groups of 16 output tiles of
-// 16 x 16).  Per step of WG_K positions the workgroup stages gY and the
-// shifted X rows in LDS; wave w of group g owns tiles 16 g + w + 4 t, t < 4.
+// Work items (27 taps, chunks of L positions, groups of 16 output tiles of
+// 16 x 16) on a 1-D grid, XCD-aware: workgroups are dispatched round-robin
+// over the 8 XCDs, and every item of chunk c runs on XCD c % 8, so the 27
+// taps and all groups of a chunk, which read the same gY rows and
+// overlapping X rows, share that XCD's L2.  Per step of WG_K positions the
+// workgroup stages gY and the shifted X rows in LDS; wave w of group g owns
+// tiles 16 g + w + 4 t, t < 4.
 // ---------------------------------------------------------------------------
+constexpr int WG_XCD = 8;
 constexpr int WG_CH = 2048;  // positions per workgroup, at least
 constexpr int WG_NC = 256;   // chunks per launch, at most
 constexpr int WG_MAXT = 4;   // tiles per wave
@@ -136,23 +141,28 @@ constexpr int WG_LD = WG_K + 8;       // LDS row stride (bf16): 16-byte aligned 
 
 __global__ void __launch_bounds__(TPB) k_wgrad(const __bf16 *__restrict__ GY, int Co,
                                                const __bf16 *__restrict__ X, int Ci, int R, int S, int L,
-                                               float *__restrict__ GWp) {
+                                               int ncl, int groups, float *__restrict__ GWp) {
   // transposed tiles [channel][WG_K positions], so a fragment's 8
   // consecutive positions are one 16-byte LDS read; staged with 16-byte
   // global loads (8 channels of one position) by threads that walk the
   // positions fastest (conflict-free LDS writes)
   extern __shared__ __attribute__((aligned(16))) __bf16 wg_lds[];  // (Co + Ci) rows of WG_LD
   __bf16 *sg = wg_lds, *sx = wg_lds + (size_t)Co * WG_LD;
-  const int tap = blockIdx.x;
+  // work item of this workgroup: XCD blockIdx.x % 8 takes chunks of that
+  // residue, taps fastest, then groups
+  const int xcd = (int)blockIdx.x % WG_XCD, k = (int)blockIdx.x / WG_XCD;
+  const int chunk = (k / (27 * groups)) * WG_XCD + xcd;
+  if (chunk >= ncl) return;  // whole workgroup: no barrier reached
+  const int group = (k / 27) % groups, tap = k % 27;
   const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int m = lane & 15, kq = lane >> 4;
-  const int nci = Ci / 16, ntile = (Co / 16) * nci, tile0 = blockIdx.z * 16;
+  const int nci = Ci / 16, ntile = (Co / 16) * nci, tile0 = group * 16;
   const int R3 = R * R * R;
   f32x4 acc[WG_MAXT];
 #pragma unroll
   for (int t = 0; t < WG_MAXT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int p0 = blockIdx.y * L, p1 = min(S, p0 + L);
+  const int p0 = chunk * L, p1 = min(S, p0 + L);
   const int r = (int)threadIdx.x % WG_K;  // this thread's staged position
   for (int sb = p0; sb < p1; sb += WG_K) {
     __syncthreads();
@@ -194,7 +204,7 @@ __global__ void __launch_bounds__(TPB) k_wgrad(const __bf16 *__restrict__ GY, in
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int co = ct * 16 + 4 * kq + i, ci = it * 16 + m;
-        GWp[(size_t)blockIdx.y * Co * 27 * Ci + ((size_t)co * 27 + tap) * Ci + ci] = acc[t][i];
+        GWp[(size_t)chunk * Co * 27 * Ci + ((size_t)co * 27 + tap) * Ci + ci] = acc[t][i];
       }
     }
   }
@@ -487,7 +497,9 @@ hipError_t wgrad(const __bf16 *GY, int Co, const __bf16 *X, int Ci, int R, int N
   const int nc = wgrad_chunks(R, N);
   const int L = ((S + nc - 1) / nc + WG_K - 1) / WG_K * WG_K;  // chunk length, whole staging steps
   const int ncl = (S + L - 1) / L;
-  hipLaunchKernelGGL(k_wgrad, dim3(27, ncl, groups), dim3(TPB), lds, st, GY, Co, X, Ci, R, S, L, part);
+  const int per_xcd = (ncl + WG_XCD - 1) / WG_XCD;  // chunks per XCD, at most
+  hipLaunchKernelGGL(k_wgrad, dim3(WG_XCD * per_xcd * 27 * groups), dim3(TPB), lds, st, GY, Co, X, Ci, R, S, L,
+                     ncl, groups, part);
   const size_t nw = (size_t)Co * 27 * Ci;
   colsum(part, ncl, nw, GW, st);
   return hipGetLastError();
