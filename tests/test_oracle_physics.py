@@ -54,35 +54,41 @@ def test_poiseuille_viscosity_and_second_order_slip(oracle_lib):
     assert errs[0] / errs[1] > 3.5          # second order
 
 
-def poiseuille_roots(oracle_lib, H, halfway, wall=3, tau1=0.5, F=1e-6):
+def poiseuille_roots(oracle_lib, H, halfway, wall=3, tau1=0.5, F=1e-6, lattice=2):
     """Steady body-force channel of width H gas rows between diffusive walls
     (isothermal, at rest): the curvature of the quadratic fit to the gas
-    velocity relative to -F / (2 nu), and the fit's two zeros."""
+    velocity relative to -F / (2 nu), and the fit's two zeros (D2Q9, or
+    D3Q19 with two periodic planes)."""
     ny = H + 2 * wall
-    cfg = one_species(2, ny, tau1=tau1, F=F, mask=W.channel_mask(2, ny, wall))
+    nz = 2 if lattice == 3 else 1
+    cfg = one_species(2, ny, nz, lattice=lattice, tau1=tau1, F=F, mask=W.channel_mask(2, ny, wall, nz=nz))
     cfg["reaction"]["halfway"] = halfway
     nu = tau1 * T0
     y = np.arange(ny)
     y0, y1 = wall - 1 + 0.5 * halfway, ny - wall - 0.5 * halfway
     init = W.uniform_init(cfg)
-    init["u"][0] = np.repeat(np.where((y >= wall) & (y < ny - wall), F / (2 * nu) * (y - y0) * (y1 - y), 0.0), 2)
+    prof = np.where((y >= wall) & (y < ny - wall), F / (2 * nu) * (y - y0) * (y1 - y), 0.0)
+    init["u"][0] = np.tile(np.repeat(prof, 2), nz)
     sim = oracle_lib.OracleSim(cfg, init)
     sim.step(int(3 * H * H / nu))
-    u = sim.field(oracle_lib.OF_U, 0).reshape(ny, 2)[:, 0]
+    u = sim.field(oracle_lib.OF_U, 0).reshape(nz, ny, 2)[0, :, 0]
     g = slice(wall, ny - wall)
     a = np.polyfit(y[g], u[g], 2)
     return a[0] / (-F / (2 * nu)), np.sort(np.roots(a).real), (y0, y1)
 
 
-def test_halfway_wall_moves_the_no_slip_point_half_a_node(oracle_lib):
+@pytest.mark.parametrize("lattice", [2, 3])
+def test_halfway_wall_moves_the_no_slip_point_half_a_node(oracle_lib, lattice):
     """Sec. 4.3's half-way wall: a steady Poiseuille profile keeps its
     curvature -F / (2 nu) and its zeros move from the wall nodes to half a
     node into the gas, up to the diffusive wall's slip, which halves as the
-    channel width doubles (its relative size falls at second order)."""
+    channel width doubles (its relative size falls at second order); D2Q9 and
+    D3Q19 (where the diagonal links into the wall carry the reflected
+    velocity too)."""
     slips = []
     for H in (16, 32):
-        curv0, r0, (w0, w1) = poiseuille_roots(oracle_lib, H, False)
-        curv1, r1, (h0, h1) = poiseuille_roots(oracle_lib, H, True)
+        curv0, r0, (w0, w1) = poiseuille_roots(oracle_lib, H, False, lattice=lattice)
+        curv1, r1, (h0, h1) = poiseuille_roots(oracle_lib, H, True, lattice=lattice)
         assert curv0 == pytest.approx(1.0, rel=1e-6) and curv1 == pytest.approx(1.0, rel=1e-6)
         assert h0 == w0 + 0.5 and h1 == w1 - 0.5
         # symmetric channel
