@@ -10,10 +10,12 @@
  * correction) is deliberately different from the closed forms a fast
  * implementation would use, so that agreement between the two is evidence.
  *
- * Parity unpinned: the size of the mass drift of interpolated species next to
- * walls without a reaction (Sec. 4.2 names the error of the one-sided
- * stencils and gives no figure); every other function is pinned by the
- * CPU tests against closed forms, invariants or the paper's printed values.
+ * Every function is pinned by the CPU tests against closed forms,
+ * invariants or the paper's printed values.  The one quantity without a
+ * reference value is the size of the mass drift of interpolated species
+ * next to walls without a reaction (Sec. 4.2 names the error of the
+ * one-sided stencils and gives no figure): only its convergence with
+ * resolution is pinned.
  */
 #include "fdlbm_oracle.h"
 
