@@ -5,7 +5,7 @@ inlet/outlet, periodic or closed axes), one to six species with masses from
 numbers, the solid scheme (forward Euler or Crank-Nicolson) and coupling
 (flux-matched or Eq.(48)), the rate law's constants and options (per node or
 per area, lattice or flux-scaled source), the wall position (on the node or
-half-way) and a body force, runs a few dozen
+half-way), a second surface reaction and a body force, runs a few dozen
 FP64 steps from a perturbed state on both sides and compares every field to
 the FP64 bounds of test_parity_gpu.py.  The draws stay in ranges where the
 method is stable; a case whose oracle run turns non-physical is reported and
@@ -84,7 +84,13 @@ def random_case(seed: int) -> tuple[dict, dict, int]:
     cfg["flow"].update(F=F, X_in=X)
     cfg["init"].update(X=X)
     init = W.perturbed_init(cfg, 77 + seed, amp_rho=0.01, amp_u=0.004, amp_T=0.005)
-    rx["halfway"] = bool(rng.random() < 0.3)   # drawn last: the earlier draws stay as they were
+    rx["halfway"] = bool(rng.random() < 0.3)   # drawn after the rest: the earlier draws stay as they were
+    if ns >= 3 and rng.random() < 0.6:
+        # a second surface reaction consuming the first one's product
+        nu2, ord2 = [0.0] * ns, [0.0] * ns
+        nu2[1], nu2[2], ord2[1] = -1.0, 1.0, 1.0
+        rx["more"] = [dict(nu=nu2, order=ord2, k0=float(10 ** rng.uniform(-4, -2.3)), ea=float(rng.uniform(0, 5)),
+                           T_ref=rx["T_ref"], dH=float(rng.uniform(-0.4, 0.2)))]
     return cfg, init, steps
 
 
@@ -93,14 +99,15 @@ def rel(a, b):
     return np.abs(a - b).max() / (s if s > 0 else 1.0)
 
 
-@pytest.mark.parametrize("seed", range(16))
+@pytest.mark.parametrize("seed", range(24))
 def test_random_case_fp64(fd, seed):
     cfg, init, steps = random_case(seed)
     ns, D = len(cfg["species"]["M"]), cfg["lattice"]
     desc = (f"lattice {D}, {cfg['nx']}x{cfg['ny']}x{cfg['nz']}, inout {cfg['inout']}, ns {ns}, "
             f"M {cfg['species']['M']}, flags {cfg['species']['flags']}, solid {cfg['solid'].get('scheme', 0)}"
             f"/{cfg['solid'].get('coupling', 0)}, area {cfg['reaction']['rate_area']}, "
-            f"flux {cfg['reaction']['source_flux']}, halfway {cfg['reaction']['halfway']}")
+            f"flux {cfg['reaction']['source_flux']}, halfway {cfg['reaction']['halfway']}, "
+            f"reactions {1 + len(cfg['reaction'].get('more', []))}")
     print(f"[random {seed}] {desc}", flush=True)
     o = of.OracleSim(cfg, init)
     o.step(steps)
