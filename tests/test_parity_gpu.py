@@ -307,10 +307,16 @@ def test_bed_128_ten_thousand_steps(fd):
     g.close()
 
 
-def test_deterministic_and_checkpoint(fd):
+@pytest.mark.parametrize("variant", ["plain", "halfway_two_reactions"])
+def test_deterministic_and_checkpoint(fd, variant):
     """Two runs from the same state are bitwise identical; a saved state
-    restores bitwise."""
+    restores bitwise (also with the half-way wall, whose emission reads the
+    previous step's moments, and two surface reactions, whose heat is kept
+    per wall node)."""
     cfg = small_bed(n=20)
+    if variant != "plain":
+        cfg = with_reverse_shift(cfg)
+        cfg["reaction"]["halfway"] = True
     init = W.perturbed_init(cfg, 4, amp_u=0.005)
     g1 = fd.Sim(cfg, precision=fd.F32, init=init)
     g2 = fd.Sim(cfg, precision=fd.F32, init=init)
@@ -325,7 +331,9 @@ def test_deterministic_and_checkpoint(fd):
     for j in range(5):
         assert np.array_equal(g1.field(fd.FIELD_POP, j), g2.field(fd.FIELD_POP, j))
     assert np.array_equal(g1.field(fd.FIELD_TS), g2.field(fd.FIELD_TS))
-    assert g1.observe()["moles_reacted"] == g2.observe()["moles_reacted"]
+    o1, o2 = g1.observe(), g2.observe()
+    assert o1["moles_reacted"] == o2["moles_reacted"]
+    assert o1["heat_released"] == o2["heat_released"]
 
 
 def test_single_species_and_no_walls(oracle_lib, fd):
