@@ -250,8 +250,8 @@ int fdlbm_set_reaction(fdlbm_ctx *ctx, const double *nu, const double *order, do
  * FDLBM_FIELD_WALL_R and moles_reacted count the summed rates, and
  * heat_released sums the heat node by node.  Up to FDLBM_MAX_REACTIONS in
  * all.  FDLBM_E_STATE before fdlbm_set_reaction; FDLBM_E_INVALID beyond the
- * limit or for orders outside 0..3.  Not batched (fdlbm_batch_create
- * fails).  Takes effect at the next step. */
+ * limit or for orders outside 0..3.  In a batch, either every sample or
+ * none has several reactions.  Takes effect at the next step. */
 #define FDLBM_MAX_REACTIONS 4
 int fdlbm_add_reaction(fdlbm_ctx *ctx, const double *nu, const double *order, double k0, double ea,
                        double T_ref, double dH);
@@ -303,8 +303,8 @@ int fdlbm_set_wall_source(fdlbm_ctx *ctx, int mode);
  * energy stay conserved.  A Poiseuille channel's velocity zeros then sit half
  * a node from the wall nodes.  The moments pass then waits for the wall
  * kernel (which reads the moments it overwrites), so the step loses the wall
- * kernel's overlap.  Not batched (fdlbm_batch_create fails).  FDLBM_E_INVALID
- * for another value.  Takes effect at the next step. */
+ * kernel's overlap.  In a batch every sample has the same wall position.
+ * FDLBM_E_INVALID for another value.  Takes effect at the next step. */
 #define FDLBM_WALL_ON_NODE 0
 #define FDLBM_WALL_HALFWAY 1
 int fdlbm_set_wall_position(fdlbm_ctx *ctx, int position);
@@ -469,8 +469,9 @@ int fdlbm_counts(const fdlbm_ctx *ctx, int64_t *n_gas, int64_t *n_wall, int64_t 
  * steps replay a captured HIP graph.  The physics of each sample is exactly
  * that of fdlbm_step on its own context (the same kernels per node and the
  * same per-block accumulation order, so the results are bitwise equal).
- * Members must be initialised, share lattice, species count, precision and
- * stream, and keep their workspaces bound while the batch lives.  Parameters
+ * Members must be initialised, share lattice, species count, precision,
+ * stream, wall position and whether they have several surface reactions,
+ * and keep their workspaces bound while the batch lives.  Parameters
  * changed on a member after fdlbm_batch_bind_workspace take effect at the
  * next fdlbm_batch_set_active.  Each member's own calls (observe, residual,
  * get_field, save/load) keep working between batch steps; fdlbm_step on a

@@ -1629,7 +1629,7 @@ __device__ __forceinline__ void for_items(const int2 *__restrict__ items, int n,
   }
 }
 
-template <bool FAST, typename real, typename PT, int D, int NS>
+template <bool FAST, bool HALF, bool MULTI, typename real, typename PT, int D, int NS>
 __global__ void __launch_bounds__(BLOCK) kb_wall(const Params<real> *__restrict__ P,
                                                  const Bufs<real, PT> *__restrict__ B,
                                                  const int2 *__restrict__ items, const int *__restrict__ count,
@@ -1642,8 +1642,7 @@ __global__ void __launch_bounds__(BLOCK) kb_wall(const Params<real> *__restrict_
       load_wtab<real, NS>(P[it.x], wtab);
       prev = it.x;
     }
-    // batches: walls on the node, one reaction
-    wall_block<FAST, false, false, real, PT, D, NS>(P[it.x], B[it.x], cur, wtab, it.y);
+    wall_block<FAST, HALF, MULTI, real, PT, D, NS>(P[it.x], B[it.x], cur, wtab, it.y);
   });
 }
 
@@ -1791,18 +1790,28 @@ inline hipError_t batch_step_impl(const BatchLaunch &bl, int cur) {
     (void)hipEventRecord(bl.ev_fork, st);
     (void)hipStreamWaitEvent(sw, bl.ev_fork, 0);
   }
-  if (go(BL_WALL_FAST))
-    hipLaunchKernelGGL((kb_wall<true, real, PT, D, NS>), dim3(bl.grid[BL_WALL_FAST]), blk, 0, sw, P, B,
-                       bl.items[BL_WALL_FAST], bl.count + BL_WALL_FAST, cur);
-  if (go(BL_WALL_SLOW))
-    hipLaunchKernelGGL((kb_wall<false, real, PT, D, NS>), dim3(bl.grid[BL_WALL_SLOW]), blk, 0, sw, P, B,
-                       bl.items[BL_WALL_SLOW], bl.count + BL_WALL_SLOW, cur);
+  // the wall variants (half-way wall, several reactions) as compile-time flags
+  auto wall = [&](auto half, auto multi) {
+    constexpr bool H = decltype(half)::value, MU = decltype(multi)::value;
+    if (go(BL_WALL_FAST))
+      hipLaunchKernelGGL((kb_wall<true, H, MU, real, PT, D, NS>), dim3(bl.grid[BL_WALL_FAST]), blk, 0, sw, P, B,
+                         bl.items[BL_WALL_FAST], bl.count + BL_WALL_FAST, cur);
+    if (go(BL_WALL_SLOW))
+      hipLaunchKernelGGL((kb_wall<false, H, MU, real, PT, D, NS>), dim3(bl.grid[BL_WALL_SLOW]), blk, 0, sw, P, B,
+                         bl.items[BL_WALL_SLOW], bl.count + BL_WALL_SLOW, cur);
+  };
+  if (!bl.halfway && !bl.multi) wall(std::false_type{}, std::false_type{});
+  else if (bl.halfway && !bl.multi) wall(std::true_type{}, std::false_type{});
+  else if (!bl.halfway) wall(std::false_type{}, std::true_type{});
+  else wall(std::true_type{}, std::true_type{});
   if (two) {
     (void)hipEventRecord(bl.ev_wall, sw);
     if (go(BL_SOLID))
       hipLaunchKernelGGL((kb_solid<real, PT, D>), dim3(bl.grid[BL_SOLID]), blk, 0, sw, P, B, bl.items[BL_SOLID],
                          bl.count + BL_SOLID, cur);
     (void)hipEventRecord(bl.ev_solid, sw);
+    // the half-way wall reads the moment records the moments kernel overwrites
+    if (bl.halfway) (void)hipStreamWaitEvent(st, bl.ev_wall, 0);
   }
   if (go(BL_GAS_FAST))
     hipLaunchKernelGGL((kb_moments<true, real, PT, D, NS>), dim3(bl.grid[BL_GAS_FAST]), blk, 0, st, P, B,

@@ -37,6 +37,8 @@ struct BatchLaunch {
   // optional second stream for the wall and solid launches (null: one stream)
   hipStream_t side;
   hipEvent_t ev_fork, ev_wall, ev_solid;
+  // wall variants shared by every sample: half-way wall, several reactions
+  int halfway, multi;
 };
 
 template <typename real, typename PT, int D>

@@ -92,8 +92,22 @@ def stream(fd):
     return torch.cuda.Stream()  # default priority; graphs need a non-default stream
 
 
-@pytest.mark.parametrize("lattice,prec", [(3, "F32"), (3, "F16"), (3, "BF16"), (2, "F64")])
+def variant_cfgs():
+    """The beds with the half-way wall and a second surface reaction (the
+    reverse water-gas shift) in every sample."""
+    out = []
+    for c in bed_cfgs():
+        rx = c["reaction"]
+        rx["halfway"] = True
+        rx["more"] = [dict(nu=[-x for x in rx["nu"]], order=[0.0, 0.0, 1.0, 1.0, 0.0], k0=2e-4, ea=0.5 * rx["ea"],
+                           T_ref=rx["T_ref"], dH=-rx["dH"])]
+        out.append(c)
+    return out
+
+
+@pytest.mark.parametrize("lattice,prec", [(3, "F32"), (3, "F16"), (3, "BF16"), (2, "F64"), ("3v", "F32")])
 def test_batch_bitwise_equals_single(fd, stream, lattice, prec):
+    """lattice "3v": the beds with the half-way wall and two reactions."""
     precision = getattr(fd, prec)
     # FP32 / FP64 storage: bitwise.  16-bit storage: the batched kernels are
     # separate instantiations in which the compiler contracts a few FP32
@@ -102,7 +116,7 @@ def test_batch_bitwise_equals_single(fd, stream, lattice, prec):
     # trace species, so the 16-bit runs are compared over the first 10 steps
     narrow = prec in ("F16", "BF16")
     tol = 1e-5 if narrow else 0.0
-    cfgs = bed_cfgs() if lattice == 3 else channel_cfgs()
+    cfgs = bed_cfgs() if lattice == 3 else (variant_cfgs() if lattice == "3v" else channel_cfgs())
     print(f"[batch] lattice {lattice} {prec} samples {len(cfgs)}", flush=True)
     ref = make(fd, cfgs, precision)
     for r in ref:
@@ -171,6 +185,11 @@ def test_batch_rejects_mixed_members(fd):
         fd.Batch([a, c])
     with pytest.raises(fd.FdlbmError):
         fd.Batch([a, a])
+    # wall positions differ
+    h = W.with_changes(W.channel_c1(), reaction=dict(halfway=True))
+    d = fd.Sim(h, precision=fd.F64, init=W.uniform_init(h))
+    with pytest.raises(fd.FdlbmError):
+        fd.Batch([a, d])
 
 
 def test_batch_of_benchmark_beds(fd, stream, oracle_lib):
