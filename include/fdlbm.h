@@ -224,7 +224,8 @@ int fdlbm_set_solid_scheme(fdlbm_ctx *ctx, int scheme);
  * wall still hands the gas its energy, so the interface does not conserve
  * energy (Eq.(49)'s error is then about 3 % on the channel workload) and
  * the solid step waits for the moments (no overlap).  Forward-Euler solid
- * only, not in batches; FDLBM_E_INVALID otherwise or for another value. */
+ * only; in a batch every sample has the same coupling; FDLBM_E_INVALID
+ * otherwise or for another value. */
 #define FDLBM_COUPLING_FLUX 0
 #define FDLBM_COUPLING_EQ48 1
 int fdlbm_set_solid_coupling(fdlbm_ctx *ctx, int mode);
@@ -470,8 +471,9 @@ int fdlbm_counts(const fdlbm_ctx *ctx, int64_t *n_gas, int64_t *n_wall, int64_t 
  * that of fdlbm_step on its own context (the same kernels per node and the
  * same per-block accumulation order, so the results are bitwise equal).
  * Members must be initialised, share lattice, species count, precision,
- * stream, wall position and whether they have several surface reactions,
- * and keep their workspaces bound while the batch lives.  Parameters
+ * stream, wall position, solid-gas coupling and whether they have several
+ * surface reactions, use the forward-Euler solid, and keep their workspaces
+ * bound while the batch lives.  Parameters
  * changed on a member after fdlbm_batch_bind_workspace take effect at the
  * next fdlbm_batch_set_active.  Each member's own calls (observe, residual,
  * get_field, save/load) keep working between batch steps; fdlbm_step on a

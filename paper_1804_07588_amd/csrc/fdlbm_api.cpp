@@ -1618,6 +1618,7 @@ struct fdlbm_batch {
   hipEvent_t ev_fork = nullptr, ev_wall = nullptr, ev_solid = nullptr;
   bool overlap = true;
   bool halfway = false, multi = false;  // wall variants, the same in every sample
+  bool eq48 = false;                    // Eq.(48) coupling in every sample
 };
 
 static int bset_err(fdlbm_batch *b, int code, const char *fmt, ...) {
@@ -1678,7 +1679,7 @@ int fdlbm_batch_create(fdlbm_ctx *const *ctxs, int n, fdlbm_batch **out) {
     if (!c) return fail("null context");
     if (!c->initialized) return fail("every context needs initialised fields");
     if (c->solid_scheme == FDLBM_SOLID_CN) return fail("Crank-Nicolson solids are not batched");
-    if (c->coupling != FDLBM_COUPLING_FLUX) return fail("the Eq.(48) coupling is not batched");
+    if (c->coupling != ctxs[0]->coupling) return fail("samples differ in the solid-gas coupling");
     if (c->halfway != ctxs[0]->halfway || (c->n_rx > 1) != (ctxs[0]->n_rx > 1))
       return fail("samples differ in the wall position or in having several surface reactions");
     if (c->D != ctxs[0]->D || c->ns != ctxs[0]->ns || c->d.precision != ctxs[0]->d.precision ||
@@ -1691,6 +1692,7 @@ int fdlbm_batch_create(fdlbm_ctx *const *ctxs, int n, fdlbm_batch **out) {
   b->ns = ctxs[0]->ns;
   b->halfway = ctxs[0]->halfway;
   b->multi = ctxs[0]->n_rx > 1;
+  b->eq48 = ctxs[0]->coupling == FDLBM_COUPLING_EQ48;
   b->precision = ctxs[0]->d.precision;
   b->stream = ctxs[0]->stream;
   b->cur = ctxs[0]->cur;
@@ -1870,6 +1872,7 @@ static hipError_t batch_launch(fdlbm_batch *b, int cur, unsigned mask) {
   bl.ev_solid = b->ev_solid;
   bl.halfway = b->halfway ? 1 : 0;
   bl.multi = b->multi ? 1 : 0;
+  bl.eq48 = b->eq48 ? 1 : 0;
   return (hipError_t)with_prec(b->ctx[0], [&](auto tag) {
     using Tg = decltype(tag);
     return (int)launch_batch_step<typename Tg::real, typename Tg::pop>(b->D, b->ns, bl, cur);

@@ -1806,7 +1806,9 @@ inline hipError_t batch_step_impl(const BatchLaunch &bl, int cur) {
   else wall(std::true_type{}, std::true_type{});
   if (two) {
     (void)hipEventRecord(bl.ev_wall, sw);
-    if (go(BL_SOLID))
+    // the Eq.(48) coupling reads this step's gas moments: its solid step runs
+    // after them, on the main stream
+    if (go(BL_SOLID) && !bl.eq48)
       hipLaunchKernelGGL((kb_solid<real, PT, D>), dim3(bl.grid[BL_SOLID]), blk, 0, sw, P, B, bl.items[BL_SOLID],
                          bl.count + BL_SOLID, cur);
     (void)hipEventRecord(bl.ev_solid, sw);
@@ -1825,6 +1827,9 @@ inline hipError_t batch_step_impl(const BatchLaunch &bl, int cur) {
                        bl.items[BL_COLLIDE], bl.count + BL_COLLIDE, cur);
   if (two) {
     (void)hipStreamWaitEvent(st, bl.ev_solid, 0);
+    if (go(BL_SOLID) && bl.eq48)
+      hipLaunchKernelGGL((kb_solid<real, PT, D>), dim3(bl.grid[BL_SOLID]), blk, 0, st, P, B, bl.items[BL_SOLID],
+                         bl.count + BL_SOLID, cur);
   } else if (go(BL_SOLID)) {
     hipLaunchKernelGGL((kb_solid<real, PT, D>), dim3(bl.grid[BL_SOLID]), blk, 0, st, P, B, bl.items[BL_SOLID],
                        bl.count + BL_SOLID, cur);

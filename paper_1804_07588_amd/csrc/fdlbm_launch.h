@@ -37,8 +37,9 @@ struct BatchLaunch {
   // optional second stream for the wall and solid launches (null: one stream)
   hipStream_t side;
   hipEvent_t ev_fork, ev_wall, ev_solid;
-  // wall variants shared by every sample: half-way wall, several reactions
-  int halfway, multi;
+  // wall variants shared by every sample: half-way wall, several reactions;
+  // eq48: the Eq.(48) solid coupling (the solid step follows the moments)
+  int halfway, multi, eq48;
 };
 
 template <typename real, typename PT, int D>

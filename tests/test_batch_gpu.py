@@ -105,9 +105,16 @@ def variant_cfgs():
     return out
 
 
-@pytest.mark.parametrize("lattice,prec", [(3, "F32"), (3, "F16"), (3, "BF16"), (2, "F64"), ("3v", "F32")])
+def eq48_cfgs():
+    """The channels with the Eq.(48) solid coupling in every sample."""
+    return [W.with_changes(c, solid=dict(coupling=1)) for c in channel_cfgs()]
+
+
+@pytest.mark.parametrize("lattice,prec", [(3, "F32"), (3, "F16"), (3, "BF16"), (2, "F64"), ("3v", "F32"),
+                                          ("2e", "F64")])
 def test_batch_bitwise_equals_single(fd, stream, lattice, prec):
-    """lattice "3v": the beds with the half-way wall and two reactions."""
+    """lattice "3v": the beds with the half-way wall and two reactions; "2e":
+    the channels with the Eq.(48) coupling."""
     precision = getattr(fd, prec)
     # FP32 / FP64 storage: bitwise.  16-bit storage: the batched kernels are
     # separate instantiations in which the compiler contracts a few FP32
@@ -116,7 +123,7 @@ def test_batch_bitwise_equals_single(fd, stream, lattice, prec):
     # trace species, so the 16-bit runs are compared over the first 10 steps
     narrow = prec in ("F16", "BF16")
     tol = 1e-5 if narrow else 0.0
-    cfgs = bed_cfgs() if lattice == 3 else (variant_cfgs() if lattice == "3v" else channel_cfgs())
+    cfgs = {3: bed_cfgs, "3v": variant_cfgs, 2: channel_cfgs, "2e": eq48_cfgs}[lattice]()
     print(f"[batch] lattice {lattice} {prec} samples {len(cfgs)}", flush=True)
     ref = make(fd, cfgs, precision)
     for r in ref:
