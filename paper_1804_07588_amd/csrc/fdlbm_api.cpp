@@ -1760,6 +1760,16 @@ int fdlbm_batch_workspace_bytes(const fdlbm_batch *b, size_t *bytes) {
 // and solid-temperature buffers swapped where its parity differs from the
 // batch's) and the work lists of the active samples; synchronous.
 static int batch_upload(fdlbm_batch *b) {
+  // the launch variants are the batch's: a member changed since creation
+  // (wall position, several reactions, coupling, solid scheme) is refused
+  for (int s = 0; s < b->n; ++s) {
+    const fdlbm_ctx *c = b->ctx[s];
+    if (c->halfway != b->halfway || (c->n_rx > 1) != b->multi ||
+        (c->coupling == FDLBM_COUPLING_EQ48) != b->eq48 || c->solid_scheme != FDLBM_SOLID_EULER)
+      return bset_err(b, FDLBM_E_INVALID,
+                      "sample %d changed its wall position, reaction count, coupling or solid scheme "
+                      "after the batch was created", s);
+  }
   b->h_params.assign(b->p_size * b->n, 0);
   b->h_bufs.assign(b->b_size * b->n, 0);
   for (int s = 0; s < b->n; ++s) {

@@ -197,6 +197,17 @@ def test_batch_rejects_mixed_members(fd):
     d = fd.Sim(h, precision=fd.F64, init=W.uniform_init(h))
     with pytest.raises(fd.FdlbmError):
         fd.Batch([a, d])
+    # a member that gains a second reaction after the batch was made
+    e = fd.Sim(W.channel_c1(), precision=fd.F64, init=W.uniform_init(W.channel_c1()))
+    b = fd.Batch([a, e])
+    import ctypes as ct
+    dp = ct.POINTER(ct.c_double)
+    nu, order = np.array([-1.0, 1.0]), np.array([1.0, 0.0])
+    assert fd.lib().fdlbm_add_reaction(e.h, nu.ctypes.data_as(dp), order.ctypes.data_as(dp), 1e-3, 0.0,
+                                       1.0 / 3.0, -0.1) == fd.OK
+    with pytest.raises(fd.FdlbmError):
+        b.set_active(np.ones(2, dtype=np.uint8))
+    b.close()
 
 
 def test_batch_of_benchmark_beds(fd, stream, oracle_lib):
