@@ -207,7 +207,8 @@ int fdlbm_set_solid(fdlbm_ctx *ctx, double alpha_s, double C_s, const double *T_
  * relative to the step (at most 5000); the Dirichlet-face heat is the mean
  * of the old and new face fluxes.  Choose CN before fdlbm_set_solid with
  * alpha_s > 1/(2D); switching back to Euler with such an alpha_s fails.
- * Not available in batches (fdlbm_batch_create rejects such contexts). */
+ * In a batch every sample uses the same scheme; Crank-Nicolson samples may
+ * take different numbers of sweeps. */
 #define FDLBM_SOLID_EULER 0
 #define FDLBM_SOLID_CN 1
 int fdlbm_set_solid_scheme(fdlbm_ctx *ctx, int scheme);
@@ -471,9 +472,10 @@ int fdlbm_counts(const fdlbm_ctx *ctx, int64_t *n_gas, int64_t *n_wall, int64_t 
  * that of fdlbm_step on its own context (the same kernels per node and the
  * same per-block accumulation order, so the results are bitwise equal).
  * Members must be initialised, share lattice, species count, precision,
- * stream, wall position, solid-gas coupling and whether they have several
- * surface reactions, use the forward-Euler solid, and keep their workspaces
- * bound while the batch lives.  Parameters
+ * stream, wall position, solid-gas coupling, solid scheme and whether they
+ * have several surface reactions, and keep their workspaces bound while the
+ * batch lives (a member whose variant changes afterwards makes the next
+ * fdlbm_batch_set_active fail).  Parameters
  * changed on a member after fdlbm_batch_bind_workspace take effect at the
  * next fdlbm_batch_set_active.  Each member's own calls (observe, residual,
  * get_field, save/load) keep working between batch steps; fdlbm_step on a

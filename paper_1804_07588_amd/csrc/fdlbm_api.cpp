@@ -1619,6 +1619,8 @@ struct fdlbm_batch {
   bool overlap = true;
   bool halfway = false, multi = false;  // wall variants, the same in every sample
   bool eq48 = false;                    // Eq.(48) coupling in every sample
+  bool cn = false;                      // Crank-Nicolson solid in every sample
+  int cn_iters = 0;                     // the largest sample's Jacobi sweeps (at the last upload)
 };
 
 static int bset_err(fdlbm_batch *b, int code, const char *fmt, ...) {
@@ -1678,7 +1680,7 @@ int fdlbm_batch_create(fdlbm_ctx *const *ctxs, int n, fdlbm_batch **out) {
     const fdlbm_ctx *c = ctxs[s];
     if (!c) return fail("null context");
     if (!c->initialized) return fail("every context needs initialised fields");
-    if (c->solid_scheme == FDLBM_SOLID_CN) return fail("Crank-Nicolson solids are not batched");
+    if (c->solid_scheme != ctxs[0]->solid_scheme) return fail("samples differ in the solid scheme");
     if (c->coupling != ctxs[0]->coupling) return fail("samples differ in the solid-gas coupling");
     if (c->halfway != ctxs[0]->halfway || (c->n_rx > 1) != (ctxs[0]->n_rx > 1))
       return fail("samples differ in the wall position or in having several surface reactions");
@@ -1693,6 +1695,7 @@ int fdlbm_batch_create(fdlbm_ctx *const *ctxs, int n, fdlbm_batch **out) {
   b->halfway = ctxs[0]->halfway;
   b->multi = ctxs[0]->n_rx > 1;
   b->eq48 = ctxs[0]->coupling == FDLBM_COUPLING_EQ48;
+  b->cn = ctxs[0]->solid_scheme == FDLBM_SOLID_CN;
   b->precision = ctxs[0]->d.precision;
   b->stream = ctxs[0]->stream;
   b->cur = ctxs[0]->cur;
@@ -1765,13 +1768,15 @@ static int batch_upload(fdlbm_batch *b) {
   for (int s = 0; s < b->n; ++s) {
     const fdlbm_ctx *c = b->ctx[s];
     if (c->halfway != b->halfway || (c->n_rx > 1) != b->multi ||
-        (c->coupling == FDLBM_COUPLING_EQ48) != b->eq48 || c->solid_scheme != FDLBM_SOLID_EULER)
+        (c->coupling == FDLBM_COUPLING_EQ48) != b->eq48 || (c->solid_scheme == FDLBM_SOLID_CN) != b->cn)
       return bset_err(b, FDLBM_E_INVALID,
                       "sample %d changed its wall position, reaction count, coupling or solid scheme "
                       "after the batch was created", s);
   }
   b->h_params.assign(b->p_size * b->n, 0);
   b->h_bufs.assign(b->b_size * b->n, 0);
+  const int cn_before = b->cn_iters;  // graphs hold the sweep count they were captured with
+  b->cn_iters = 0;
   for (int s = 0; s < b->n; ++s) {
     const fdlbm_ctx *c = b->ctx[s];
     const bool flip = (c->cur ^ b->cur) != 0;
@@ -1787,9 +1792,11 @@ static int batch_upload(fdlbm_batch *b) {
       }
       std::memcpy(b->h_params.data() + b->p_size * s, &p, sizeof p);
       std::memcpy(b->h_bufs.data() + b->b_size * s, &bu, sizeof bu);
+      b->cn_iters = std::max(b->cn_iters, p.cn_iters);
       return 0;
     });
   }
+  if (b->cn_iters != cn_before) batch_drop_graphs(b);
   for (int k = 0; k < BL_NUM; ++k) b->h_items[k].clear();
   for (int s = 0; s < b->n; ++s) {
     if (!b->active[s]) continue;
@@ -1883,6 +1890,7 @@ static hipError_t batch_launch(fdlbm_batch *b, int cur, unsigned mask) {
   bl.halfway = b->halfway ? 1 : 0;
   bl.multi = b->multi ? 1 : 0;
   bl.eq48 = b->eq48 ? 1 : 0;
+  bl.cn_iters = b->cn ? b->cn_iters : 0;
   return (hipError_t)with_prec(b->ctx[0], [&](auto tag) {
     using Tg = decltype(tag);
     return (int)launch_batch_step<typename Tg::real, typename Tg::pop>(b->D, b->ns, bl, cur);

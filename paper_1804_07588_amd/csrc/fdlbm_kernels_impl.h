@@ -1681,6 +1681,33 @@ __global__ void __launch_bounds__(BLOCK) kb_solid(const Params<real> *__restrict
   });
 }
 
+// Crank-Nicolson solid of a batch: MODE 1 the right-hand side, MODE 2 Jacobi
+// sweep `it` of `max_it` (a sample with k = cn_iters sweeps takes the last k,
+// from T^s into the buffers the single-domain step uses, so that its last
+// sweep lands in Ts[cur ^ 1]), MODE 3 the new temperature's face heat.
+template <typename real, typename PT, int D, int MODE>
+__global__ void __launch_bounds__(BLOCK) kb_solid_cn(const Params<real> *__restrict__ P,
+                                                     const Bufs<real, PT> *__restrict__ B,
+                                                     const int2 *__restrict__ items, const int *__restrict__ count,
+                                                     int cur, int it, int max_it) {
+  for_items(items, *count, [&](int2 item) {
+    __syncthreads();  // the LDS tile of the previous item has been consumed
+    const Params<real> &p = P[item.x];
+    const Bufs<real, PT> &b = B[item.x];
+    if constexpr (MODE == 1) {
+      solid_pass<real, PT, D, 1>(p, b, b.Ts[cur], b.cn_tmp, item.y);
+    } else if constexpr (MODE == 2) {
+      const int li = it - (max_it - p.cn_iters);  // uniform over the workgroup
+      if (li >= 0) {
+        auto buf = [&](int l) { return ((p.cn_iters - 1 - l) % 2 == 0) ? b.Ts[cur ^ 1] : b.cn_tmp; };
+        solid_pass<real, PT, D, 2>(p, b, li == 0 ? b.Ts[cur] : buf(li - 1), buf(li), item.y);
+      }
+    } else {
+      solid_pass<real, PT, D, 3>(p, b, b.Ts[cur ^ 1], b.cn_tmp, item.y);
+    }
+  });
+}
+
 // ===========================================================================
 // launchers
 // ===========================================================================
@@ -1790,6 +1817,21 @@ inline hipError_t batch_step_impl(const BatchLaunch &bl, int cur) {
     (void)hipEventRecord(bl.ev_fork, st);
     (void)hipStreamWaitEvent(sw, bl.ev_fork, 0);
   }
+  // the solid step: forward Euler, or Crank-Nicolson (right-hand side, the
+  // largest sample's number of Jacobi sweeps, face heat)
+  auto solid = [&](hipStream_t s) {
+    const dim3 g(bl.grid[BL_SOLID]);
+    const int2 *items = bl.items[BL_SOLID];
+    const int *cnt = bl.count + BL_SOLID;
+    if (bl.cn_iters == 0) {
+      hipLaunchKernelGGL((kb_solid<real, PT, D>), g, blk, 0, s, P, B, items, cnt, cur);
+      return;
+    }
+    hipLaunchKernelGGL((kb_solid_cn<real, PT, D, 1>), g, blk, 0, s, P, B, items, cnt, cur, 0, bl.cn_iters);
+    for (int it = 0; it < bl.cn_iters; ++it)
+      hipLaunchKernelGGL((kb_solid_cn<real, PT, D, 2>), g, blk, 0, s, P, B, items, cnt, cur, it, bl.cn_iters);
+    hipLaunchKernelGGL((kb_solid_cn<real, PT, D, 3>), g, blk, 0, s, P, B, items, cnt, cur, 0, bl.cn_iters);
+  };
   // the wall variants (half-way wall, several reactions) as compile-time flags
   auto wall = [&](auto half, auto multi) {
     constexpr bool H = decltype(half)::value, MU = decltype(multi)::value;
@@ -1808,9 +1850,7 @@ inline hipError_t batch_step_impl(const BatchLaunch &bl, int cur) {
     (void)hipEventRecord(bl.ev_wall, sw);
     // the Eq.(48) coupling reads this step's gas moments: its solid step runs
     // after them, on the main stream
-    if (go(BL_SOLID) && !bl.eq48)
-      hipLaunchKernelGGL((kb_solid<real, PT, D>), dim3(bl.grid[BL_SOLID]), blk, 0, sw, P, B, bl.items[BL_SOLID],
-                         bl.count + BL_SOLID, cur);
+    if (go(BL_SOLID) && !bl.eq48) solid(sw);
     (void)hipEventRecord(bl.ev_solid, sw);
     // the half-way wall reads the moment records the moments kernel overwrites
     if (bl.halfway) (void)hipStreamWaitEvent(st, bl.ev_wall, 0);
@@ -1827,12 +1867,9 @@ inline hipError_t batch_step_impl(const BatchLaunch &bl, int cur) {
                        bl.items[BL_COLLIDE], bl.count + BL_COLLIDE, cur);
   if (two) {
     (void)hipStreamWaitEvent(st, bl.ev_solid, 0);
-    if (go(BL_SOLID) && bl.eq48)
-      hipLaunchKernelGGL((kb_solid<real, PT, D>), dim3(bl.grid[BL_SOLID]), blk, 0, st, P, B, bl.items[BL_SOLID],
-                         bl.count + BL_SOLID, cur);
+    if (go(BL_SOLID) && bl.eq48) solid(st);
   } else if (go(BL_SOLID)) {
-    hipLaunchKernelGGL((kb_solid<real, PT, D>), dim3(bl.grid[BL_SOLID]), blk, 0, st, P, B, bl.items[BL_SOLID],
-                       bl.count + BL_SOLID, cur);
+    solid(st);
   }
   return hipGetLastError();
 }

@@ -38,8 +38,10 @@ struct BatchLaunch {
   hipStream_t side;
   hipEvent_t ev_fork, ev_wall, ev_solid;
   // wall variants shared by every sample: half-way wall, several reactions;
-  // eq48: the Eq.(48) solid coupling (the solid step follows the moments)
-  int halfway, multi, eq48;
+  // eq48: the Eq.(48) solid coupling (the solid step follows the moments);
+  // cn_iters: 0 for the forward-Euler solid, else the largest sample's
+  // number of Crank-Nicolson Jacobi sweeps
+  int halfway, multi, eq48, cn_iters;
 };
 
 template <typename real, typename PT, int D>

@@ -110,11 +110,18 @@ def eq48_cfgs():
     return [W.with_changes(c, solid=dict(coupling=1)) for c in channel_cfgs()]
 
 
+def cn_cfgs():
+    """The channels with Crank-Nicolson solids of different diffusivities, so
+    that the samples take different numbers of Jacobi sweeps."""
+    return [W.with_changes(c, solid=dict(scheme=1, alpha_s=a)) for c, a in zip(channel_cfgs(), (1.5, 0.4, 3.0))]
+
+
 @pytest.mark.parametrize("lattice,prec", [(3, "F32"), (3, "F16"), (3, "BF16"), (2, "F64"), ("3v", "F32"),
-                                          ("2e", "F64")])
+                                          ("2e", "F64"), ("2c", "F64")])
 def test_batch_bitwise_equals_single(fd, stream, lattice, prec):
     """lattice "3v": the beds with the half-way wall and two reactions; "2e":
-    the channels with the Eq.(48) coupling."""
+    the channels with the Eq.(48) coupling; "2c": the channels with
+    Crank-Nicolson solids."""
     precision = getattr(fd, prec)
     # FP32 / FP64 storage: bitwise.  16-bit storage: the batched kernels are
     # separate instantiations in which the compiler contracts a few FP32
@@ -123,7 +130,7 @@ def test_batch_bitwise_equals_single(fd, stream, lattice, prec):
     # trace species, so the 16-bit runs are compared over the first 10 steps
     narrow = prec in ("F16", "BF16")
     tol = 1e-5 if narrow else 0.0
-    cfgs = {3: bed_cfgs, "3v": variant_cfgs, 2: channel_cfgs, "2e": eq48_cfgs}[lattice]()
+    cfgs = {3: bed_cfgs, "3v": variant_cfgs, 2: channel_cfgs, "2e": eq48_cfgs, "2c": cn_cfgs}[lattice]()
     print(f"[batch] lattice {lattice} {prec} samples {len(cfgs)}", flush=True)
     ref = make(fd, cfgs, precision)
     for r in ref:
