@@ -148,3 +148,22 @@ def test_run_log_writes_one_json_object_per_line(tmp_path):
     assert lines[1]["step"] == 100 and lines[2]["step"] == 200
     assert lines[2]["mass"] == [1.5, 2.5] and lines[2]["residual"]["max"] == 5e-4
     assert lines[1]["u_max"] == float("inf") and lines[2]["t"] >= lines[1]["t"] >= 0
+
+
+def test_steady_state_check_reports_a_failure_in_its_record(monkeypatch):
+    """The benchmark line's time-to-steady-state record: the reduced
+    configuration (24 beds of 64^3, 20 for training, 150 epochs, 1e-6), and
+    a failure of that part ends up in the record instead of losing the
+    throughput line."""
+    import argparse
+    import bench
+    seen = {}
+
+    def fake(sub, quiet=False):
+        seen.update(n=sub.sur_n, train=sub.sur_train, test=sub.sur_test, epochs=sub.sur_epochs, tol=sub.tol)
+        raise RuntimeError("no device")
+
+    monkeypatch.setattr(bench, "surrogate_pipeline", fake)
+    rec = bench.steady_state_check(argparse.Namespace(steps=1000))
+    assert seen == dict(n=64, train=20, test=4, epochs=150, tol=1e-6)
+    assert rec == {"error": "RuntimeError: no device"}
