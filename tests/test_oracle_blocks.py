@@ -316,3 +316,22 @@ def test_oracle_checkpoint_restart_is_bitwise(oracle_lib, case):
 
 def _same_obs(a, b):
     return all(np.array_equal(np.asarray(a[k]), np.asarray(b[k])) for k in a)
+
+
+def test_oracle_option_setters_reject_bad_values(oracle_lib):
+    """The oracle's own argument checks: a wall position other than on the
+    node (0) or half-way (1), and a fifth surface reaction (four at most),
+    are refused with a message."""
+    from paper_1804_07588_amd import workloads as W
+    cfg = W.channel_c1()
+    sim = oracle_lib.OracleSim(cfg, W.uniform_init(cfg))
+    L = oracle_lib.lib()
+    assert L.oracle_set_wall_position(sim.h, 2) != 0
+    assert "wall position" in L.oracle_error(sim.h).decode()
+    assert L.oracle_set_wall_position(sim.h, 1) == 0
+    sim.close()
+    more = [dict(nu=[-1.0, 1.0], order=[1.0, 0.0], k0=1e-3, ea=0.0, T_ref=1 / 3, dH=0.0)] * 4
+    with pytest.raises(ValueError, match="too many reactions"):
+        oracle_lib.OracleSim(W.with_changes(cfg, reaction=dict(more=more)), W.uniform_init(cfg))
+    ok = oracle_lib.OracleSim(W.with_changes(cfg, reaction=dict(more=more[:3])), W.uniform_init(cfg))
+    ok.close()
