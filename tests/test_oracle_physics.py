@@ -101,24 +101,26 @@ def test_halfway_wall_moves_the_no_slip_point_half_a_node(oracle_lib, lattice):
     assert slips[0] / slips[1] == pytest.approx(2.0, rel=0.1)
 
 
-def conduction_crossings(oracle_lib, H, halfway, ws=3, tau1=0.5):
+def conduction_crossings(oracle_lib, H, halfway, ws=3, tau1=0.5, lattice=2):
     """Gas at rest between two solid slabs held at T_l and T_h (no solid
     conduction, an effectively infinite heat capacity): where the linear fit
-    to the steady gas temperature reaches T_l and T_h, and the slope."""
+    to the steady gas temperature reaches T_l and T_h, and the slope (D2Q9,
+    or D3Q19 with two periodic planes)."""
     nx = 2
     ny = 2 * ws + H
+    nz = 2 if lattice == 3 else 1
     Tl, Th = T0 * 0.99, T0 * 1.01
-    cfg = one_species(nx, ny, mask=W.channel_mask(nx, ny, ws), periodic=(1, 0, 1), tau1=tau1,
-                      wall_mode=W.WALL_REACTIVE, alpha_s=0.0, C_s=1e30)
+    cfg = one_species(nx, ny, nz, lattice=lattice, mask=W.channel_mask(nx, ny, ws, nz=nz), periodic=(1, 0, 1),
+                      tau1=tau1, wall_mode=W.WALL_REACTIVE, alpha_s=0.0, C_s=1e30)
     cfg["reaction"]["halfway"] = halfway
     init = W.uniform_init(cfg)
-    y = np.repeat(np.arange(ny), nx)
+    y = np.tile(np.repeat(np.arange(ny), nx), nz)
     init["Ts"] = np.where(y < ny // 2, Tl, Th).astype(float)
     init["T"] = Tl + (Th - Tl) * (y - ws + 1) / (ny - 2 * ws + 1)
     init["rho"][0] = T0 / init["T"]
     sim = oracle_lib.OracleSim(cfg, init)
     sim.step(int(4 * H * H / (tau1 * T0)))
-    T = sim.field(oracle_lib.OF_T).reshape(ny, nx)[:, 0]
+    T = sim.field(oracle_lib.OF_T).reshape(nz, ny, nx)[0, :, 0]
     ys = np.arange(ny)
     g = slice(ws, ny - ws)
     a = np.polyfit(ys[g], T[g], 1)
@@ -126,7 +128,8 @@ def conduction_crossings(oracle_lib, H, halfway, ws=3, tau1=0.5):
     return (Tl - a[1]) / a[0], (Th - a[1]) / a[0], ws - 1, ny - ws
 
 
-def test_halfway_wall_temperature_is_the_linear_extrapolation(oracle_lib):
+@pytest.mark.parametrize("lattice", [2, 3])
+def test_halfway_wall_temperature_is_the_linear_extrapolation(oracle_lib, lattice):
     """The half-way wall emits at 2 T_w - T(x) along each link (the linear
     interpolation through the link's midpoint).  The diffusive wall has a
     temperature jump: on the node, the gas profile reaches T_w a distance z
@@ -136,8 +139,8 @@ def test_halfway_wall_temperature_is_the_linear_extrapolation(oracle_lib):
     the same jump law; an emission at T_w itself leaves it at y_w - z, and
     one at the gas node's own temperature carries no heat)."""
     for H in (16, 24):
-        c0l, c0h, yl, yh = conduction_crossings(oracle_lib, H, False)
-        c1l, c1h, _, _ = conduction_crossings(oracle_lib, H, True)
+        c0l, c0h, yl, yh = conduction_crossings(oracle_lib, H, False, lattice=lattice)
+        c1l, c1h, _, _ = conduction_crossings(oracle_lib, H, True, lattice=lattice)
         z = yl - c0l
         assert 1.0 < z < 6.0                                  # a jump, as the diffusive wall has
         assert c0h - yh == pytest.approx(z, abs=5e-3)         # symmetric
