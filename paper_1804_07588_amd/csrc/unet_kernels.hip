@@ -136,18 +136,41 @@ constexpr int WG_NC = 256;   // chunks per launch, at most
 constexpr int WG_MAXT = 4;   // tiles per wave
 constexpr int WG_MAXC = 224; // largest channel count staged
 
-constexpr int WG_K = 64;              // positions staged per step
-constexpr int WG_LD = WG_K + 8;       // LDS row stride (bf16): 16-byte aligned rows
+constexpr int WG_K = 64;  // positions staged per step
+
+// LDS row stride (bf16) of a staged [position][channel] tile: 16 x an odd
+// number, so that eight consecutive rows start in eight different 32-byte
+// bank groups and the transposing fragment reads below are conflict-free
+__host__ __device__ constexpr int wg_stride(int C) { return (C / 16) % 2 ? C : C + 16; }
+
+typedef short i16x4 __attribute__((ext_vector_type(4)));
+typedef short i16x8 __attribute__((ext_vector_type(8)));
+
+// 16 x 16 x 32 MFMA operand fragment from a [position][channel] LDS tile:
+// lane (m, kq) receives channel c0 + m at 8 positions, those of rows
+// row0 + 4 kq + e and row0 + 16 + 4 kq + e (e < 4).  Each transposing read
+// (ds_read_b64_tr_b16) serves 16 lanes: lane j of the group points at row
+// j / 4, channels 4 (j % 4) .. +3, and lane n of the group gets channel n of
+// those 4 rows.  A and B are read with the same rows, so every slot of the
+// contraction pairs the same position.
+__device__ inline bf16x8 wg_frag(const __bf16 *t, int stride, int row0, int c0, int lane) {
+  const int m = lane & 15, kq = lane >> 4;
+  const __bf16 *p = t + (size_t)(row0 + 4 * kq + (m >> 2)) * stride + c0 + 4 * (m & 3);
+  typedef __attribute__((address_space(3))) i16x4 lds_i16x4;
+  const i16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4 *)(p));
+  const i16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4 *)(p + (size_t)16 * stride));
+  return __builtin_bit_cast(bf16x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+}
 
 __global__ void __launch_bounds__(TPB) k_wgrad(const __bf16 *__restrict__ GY, int Co,
                                                const __bf16 *__restrict__ X, int Ci, int R, int S, int L,
                                                int ncl, int groups, float *__restrict__ GWp) {
-  // transposed tiles [channel][WG_K positions], so a fragment's 8
-  // consecutive positions are one 16-byte LDS read; staged with 16-byte
-  // global loads (8 channels of one position) by threads that walk the
-  // positions fastest (conflict-free LDS writes)
-  extern __shared__ __attribute__((aligned(16))) __bf16 wg_lds[];  // (Co + Ci) rows of WG_LD
-  __bf16 *sg = wg_lds, *sx = wg_lds + (size_t)Co * WG_LD;
+  // tiles [WG_K positions][channel] as they lie in memory, staged with one
+  // 16-byte global load and one 16-byte LDS write per 8 channels of a
+  // position; the MFMA fragments are read transposed (wg_frag)
+  extern __shared__ __attribute__((aligned(16))) __bf16 wg_lds[];  // WG_K rows of SG, then of SX
+  const int SG = wg_stride(Co), SX = wg_stride(Ci);
+  __bf16 *sg = wg_lds, *sx = wg_lds + (size_t)WG_K * SG;
   // work item of this workgroup: XCD blockIdx.x % 8 takes chunks of that
   // residue, taps fastest, then groups
   const int xcd = (int)blockIdx.x % WG_XCD, k = (int)blockIdx.x / WG_XCD;
@@ -167,19 +190,15 @@ __global__ void __launch_bounds__(TPB) k_wgrad(const __bf16 *__restrict__ GY, in
   for (int sb = p0; sb < p1; sb += WG_K) {
     __syncthreads();
     const int s = sb + r;
-    for (int q = (int)threadIdx.x / WG_K; q < Co / 8; q += TPB / WG_K) {
-      const bf16x8 v = *reinterpret_cast<const bf16x8 *>(GY + (size_t)s * Co + 8 * q);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) sg[(8 * q + i) * WG_LD + r] = v[i];
-    }
+    for (int q = (int)threadIdx.x / WG_K; q < Co / 8; q += TPB / WG_K)
+      *reinterpret_cast<bf16x8 *>(sg + r * SG + 8 * q) =
+          *reinterpret_cast<const bf16x8 *>(GY + (size_t)s * Co + 8 * q);
     const int x = s % R + dx, y = (s / R) % R + dy, z = (s / (R * R)) % R + dz;
     const bool ok = (unsigned)x < (unsigned)R && (unsigned)y < (unsigned)R && (unsigned)z < (unsigned)R;
     const __bf16 *xs = X + (size_t)(ok ? s - (s % R3) + (z * R + y) * R + x : 0) * Ci;
-    for (int q = (int)threadIdx.x / WG_K; q < Ci / 8; q += TPB / WG_K) {
-      const bf16x8 v = ok ? *reinterpret_cast<const bf16x8 *>(xs + 8 * q) : zero8();
-#pragma unroll
-      for (int i = 0; i < 8; ++i) sx[(8 * q + i) * WG_LD + r] = v[i];
-    }
+    for (int q = (int)threadIdx.x / WG_K; q < Ci / 8; q += TPB / WG_K)
+      *reinterpret_cast<bf16x8 *>(sx + r * SX + 8 * q) =
+          ok ? *reinterpret_cast<const bf16x8 *>(xs + 8 * q) : zero8();
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < WG_MAXT; ++t) {
@@ -189,8 +208,8 @@ __global__ void __launch_bounds__(TPB) k_wgrad(const __bf16 *__restrict__ GY, in
 #pragma unroll
         for (int ks = 0; ks < WG_K / 32; ++ks) {
           // A[m = co][k = position], B[k = position][n = ci]
-          const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&sg[(ct * 16 + m) * WG_LD + 32 * ks + 8 * kq]);
-          const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&sx[(it * 16 + m) * WG_LD + 32 * ks + 8 * kq]);
+          const bf16x8 a = wg_frag(sg, SG, 32 * ks, ct * 16, lane);
+          const bf16x8 b = wg_frag(sx, SX, 32 * ks, it * 16, lane);
           acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
         }
       }
@@ -493,7 +512,7 @@ hipError_t wgrad(const __bf16 *GY, int Co, const __bf16 *X, int Ci, int R, int N
   const int S = N * R * R * R;
   if (Ci % 16 || Co % 16 || Ci > WG_MAXC || Co > WG_MAXC || S % WG_K) return hipErrorInvalidValue;
   const int groups = ((Co / 16) * (Ci / 16) + 15) / 16;
-  const size_t lds = (size_t)(Co + Ci) * WG_LD * sizeof(__bf16);
+  const size_t lds = (size_t)WG_K * (wg_stride(Co) + wg_stride(Ci)) * sizeof(__bf16);
   const int nc = wgrad_chunks(R, N);
   const int L = ((S + nc - 1) / nc + WG_K - 1) / WG_K * WG_K;  // chunk length, whole staging steps
   const int ncl = (S + L - 1) / L;
