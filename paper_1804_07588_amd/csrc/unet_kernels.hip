@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(TPB) k_conv(const __bf16 *__restrict__ X, int 
 // 16 x 16) on a 1-D grid, XCD-aware: workgroups are dispatched round-robin
 // over the 8 XCDs, and every item of chunk c runs on XCD c % 8, so the 27
 // taps and all groups of a chunk, which read the same gY rows and
-// overlapping X rows, share that XCD's L2.  Per step of WG_K positions the
+// overlapping X rows, share that XCD's L2.  Per step of K positions the
 // workgroup stages gY and the shifted X rows in LDS; wave w of group g owns
 // tiles 16 g + w + 4 t, t < 4.
 // ---------------------------------------------------------------------------
@@ -136,7 +136,7 @@ constexpr int WG_NC = 256;   // chunks per launch, at most
 constexpr int WG_MAXT = 4;   // tiles per wave
 constexpr int WG_MAXC = 224; // largest channel count staged
 
-constexpr int WG_K = 64;  // positions staged per step
+constexpr int WG_K = 64;  // positions staged per step (128 for narrow layers)
 
 // LDS row stride (bf16) of a staged [position][channel] tile: 16 x an odd
 // number, so that eight consecutive rows start in eight different 32-byte
@@ -162,15 +162,16 @@ __device__ inline bf16x8 wg_frag(const __bf16 *t, int stride, int row0, int c0, 
   return __builtin_bit_cast(bf16x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
 }
 
+template <int K>
 __global__ void __launch_bounds__(TPB) k_wgrad(const __bf16 *__restrict__ GY, int Co,
                                                const __bf16 *__restrict__ X, int Ci, int R, int S, int L,
                                                int ncl, int groups, float *__restrict__ GWp) {
-  // tiles [WG_K positions][channel] as they lie in memory, staged with one
+  // tiles [K positions][channel] as they lie in memory, staged with one
   // 16-byte global load and one 16-byte LDS write per 8 channels of a
   // position; the MFMA fragments are read transposed (wg_frag)
-  extern __shared__ __attribute__((aligned(16))) __bf16 wg_lds[];  // WG_K rows of SG, then of SX
+  extern __shared__ __attribute__((aligned(16))) __bf16 wg_lds[];  // K rows of SG, then of SX
   const int SG = wg_stride(Co), SX = wg_stride(Ci);
-  __bf16 *sg = wg_lds, *sx = wg_lds + (size_t)WG_K * SG;
+  __bf16 *sg = wg_lds, *sx = wg_lds + (size_t)K * SG;
   // work item of this workgroup: XCD blockIdx.x % 8 takes chunks of that
   // residue, taps fastest, then groups
   const int xcd = (int)blockIdx.x % WG_XCD, k = (int)blockIdx.x / WG_XCD;
@@ -186,17 +187,17 @@ __global__ void __launch_bounds__(TPB) k_wgrad(const __bf16 *__restrict__ GY, in
 #pragma unroll
   for (int t = 0; t < WG_MAXT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int p0 = chunk * L, p1 = min(S, p0 + L);
-  const int r = (int)threadIdx.x % WG_K;  // this thread's staged position
-  for (int sb = p0; sb < p1; sb += WG_K) {
+  const int r = (int)threadIdx.x % K;  // this thread's staged position
+  for (int sb = p0; sb < p1; sb += K) {
     __syncthreads();
     const int s = sb + r;
-    for (int q = (int)threadIdx.x / WG_K; q < Co / 8; q += TPB / WG_K)
+    for (int q = (int)threadIdx.x / K; q < Co / 8; q += TPB / K)
       *reinterpret_cast<bf16x8 *>(sg + r * SG + 8 * q) =
           *reinterpret_cast<const bf16x8 *>(GY + (size_t)s * Co + 8 * q);
     const int x = s % R + dx, y = (s / R) % R + dy, z = (s / (R * R)) % R + dz;
     const bool ok = (unsigned)x < (unsigned)R && (unsigned)y < (unsigned)R && (unsigned)z < (unsigned)R;
     const __bf16 *xs = X + (size_t)(ok ? s - (s % R3) + (z * R + y) * R + x : 0) * Ci;
-    for (int q = (int)threadIdx.x / WG_K; q < Ci / 8; q += TPB / WG_K)
+    for (int q = (int)threadIdx.x / K; q < Ci / 8; q += TPB / K)
       *reinterpret_cast<bf16x8 *>(sx + r * SX + 8 * q) =
           ok ? *reinterpret_cast<const bf16x8 *>(xs + 8 * q) : zero8();
     __syncthreads();
@@ -206,7 +207,7 @@ __global__ void __launch_bounds__(TPB) k_wgrad(const __bf16 *__restrict__ GY, in
       if (tile < ntile) {
         const int ct = tile / nci, it = tile % nci;
 #pragma unroll
-        for (int ks = 0; ks < WG_K / 32; ++ks) {
+        for (int ks = 0; ks < K / 32; ++ks) {
           // A[m = co][k = position], B[k = position][n = ci]
           const bf16x8 a = wg_frag(sg, SG, 32 * ks, ct * 16, lane);
           const bf16x8 b = wg_frag(sx, SX, 32 * ks, it * 16, lane);
@@ -507,18 +508,29 @@ int wgrad_chunks(int R, int N) {
   return std::min(WG_NC, (S + WG_CH - 1) / WG_CH);
 }
 
+template <int K>
+static void wgrad_launch(const __bf16 *GY, int Co, const __bf16 *X, int Ci, int R, int S, int nc, int groups,
+                         float *part, int *ncl_out, hipStream_t st) {
+  const size_t lds = (size_t)K * (wg_stride(Co) + wg_stride(Ci)) * sizeof(__bf16);
+  const int L = ((S + nc - 1) / nc + K - 1) / K * K;  // chunk length, whole staging steps
+  const int ncl = (S + L - 1) / L;
+  const int per_xcd = (ncl + WG_XCD - 1) / WG_XCD;  // chunks per XCD, at most
+  hipLaunchKernelGGL(k_wgrad<K>, dim3(WG_XCD * per_xcd * 27 * groups), dim3(TPB), lds, st, GY, Co, X, Ci, R, S, L,
+                     ncl, groups, part);
+  *ncl_out = ncl;
+}
+
 hipError_t wgrad(const __bf16 *GY, int Co, const __bf16 *X, int Ci, int R, int N, float *GW, float *part,
                  hipStream_t st) {
   const int S = N * R * R * R;
   if (Ci % 16 || Co % 16 || Ci > WG_MAXC || Co > WG_MAXC || S % WG_K) return hipErrorInvalidValue;
   const int groups = ((Co / 16) * (Ci / 16) + 15) / 16;
-  const size_t lds = (size_t)WG_K * (wg_stride(Co) + wg_stride(Ci)) * sizeof(__bf16);
   const int nc = wgrad_chunks(R, N);
-  const int L = ((S + nc - 1) / nc + WG_K - 1) / WG_K * WG_K;  // chunk length, whole staging steps
-  const int ncl = (S + L - 1) / L;
-  const int per_xcd = (ncl + WG_XCD - 1) / WG_XCD;  // chunks per XCD, at most
-  hipLaunchKernelGGL(k_wgrad, dim3(WG_XCD * per_xcd * 27 * groups), dim3(TPB), lds, st, GY, Co, X, Ci, R, S, L,
-                     ncl, groups, part);
+  int ncl;
+  if (Co + Ci <= 64 && S % (2 * WG_K) == 0)
+    wgrad_launch<2 * WG_K>(GY, Co, X, Ci, R, S, nc, groups, part, &ncl, st);
+  else
+    wgrad_launch<WG_K>(GY, Co, X, Ci, R, S, nc, groups, part, &ncl, st);
   const size_t nw = (size_t)Co * 27 * Ci;
   colsum(part, ncl, nw, GW, st);
   return hipGetLastError();
