@@ -118,6 +118,89 @@ __global__ void __launch_bounds__(TPB) k_conv(const __bf16 *__restrict__ X, int 
 }
 
 // ---------------------------------------------------------------------------
+// the same convolution for cubes of side R = 16, 32 or 64 and at least 96
+// input channels (used there only: with one or two 32-channel chunks the
+// per-tap staging of k_conv, with its weights in LDS, is faster), where a block's
+// 128 positions are 128 / R whole x rows of one z plane: per 32 input
+// channels the workgroup stages the block's halo once (3 planes x (128/R + 2)
+// rows x (R + 2) positions, zero outside the cube) and every tap reads its
+// shifted rows from it; the weight fragments come straight from global
+// memory (the layer's weights stay in L2).  The K steps run chunk-major,
+// taps inside, which for Ci = 32 is the order k_conv takes.
+// ---------------------------------------------------------------------------
+constexpr int CH_ROWS = 3 * (128 / 64 + 2) * (64 + 2);  // largest halo (R = 64)
+
+template <int BN>
+__global__ void __launch_bounds__(TPB) k_conv_halo(const __bf16 *__restrict__ X, int Ci,
+                                                   const __bf16 *__restrict__ W, const float *__restrict__ bias,
+                                                   int Co, int R, int mode, int relu, void *__restrict__ out) {
+  constexpr int NT = BN / 16, MT = 2;
+  __shared__ bf16x8 sh[CH_ROWS * 4];  // [halo row][4 chunks of 8 channels]
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m = lane & 15, kq = lane >> 4;
+  const int s_blk = blockIdx.x * CV_M;
+  const int co0 = blockIdx.y * BN;
+  const int R2 = R * R, R3 = R2 * R;
+  const int YH = CV_M / R + 2, XH = R + 2, nrow = 3 * YH * XH;
+  const int base = s_blk - s_blk % R3;  // first position of this sample
+  const int z0 = (s_blk % R3) / R2, y0 = (s_blk % R2) / R;
+  // halo row of each MFMA row at tap (0, 0, 0), less the tap's offset
+  int hrow[MT];
+#pragma unroll
+  for (int i = 0; i < MT; ++i) {
+    const int p = wave * 32 + i * 16 + m;
+    hrow[i] = (p / R) * XH + p % R;
+  }
+  f32x4 acc[MT][NT];
+#pragma unroll
+  for (int i = 0; i < MT; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int c0 = 0; c0 < Ci; c0 += 32) {
+    __syncthreads();  // the previous chunk's halo is consumed
+    for (int u = threadIdx.x; u < nrow * 4; u += TPB) {
+      const int row = u / 4, a = row / (YH * XH), b = (row / XH) % YH, c = row % XH;
+      const int z = z0 + a - 1, y = y0 + b - 1, x = c - 1;
+      const bool ok = (unsigned)z < (unsigned)R && (unsigned)y < (unsigned)R && (unsigned)x < (unsigned)R;
+      sh[u] = ok ? *reinterpret_cast<const bf16x8 *>(X + (size_t)(base + (z * R + y) * R + x) * Ci + c0 + (u % 4) * 8)
+                 : zero8();
+    }
+    __syncthreads();
+    for (int tap = 0; tap < 27; ++tap) {
+      const int hz = tap / 9, hy = (tap / 3) % 3, hx = tap % 3;  // offsets + 1
+      const int off = (hz * YH + hy) * XH + hx;
+      bf16x8 a[MT], b[NT];
+#pragma unroll
+      for (int j = 0; j < NT; ++j)
+        b[j] = *reinterpret_cast<const bf16x8 *>(W + ((size_t)(co0 + j * 16 + m) * 27 + tap) * Ci + c0 + kq * 8);
+#pragma unroll
+      for (int i = 0; i < MT; ++i) a[i] = sh[(hrow[i] + off) * 4 + kq];
+#pragma unroll
+      for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    const int co = co0 + j * 16 + m;
+    const float bv = bias ? bias[co] : 0.0f;
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const size_t o = (size_t)(s_blk + wave * 32 + i * 16 + 4 * kq + r) * Co + co;
+        float v = acc[i][j][r] + bv;
+        if (relu) v = fmaxf(v, 0.0f);
+        if (mode == 0) static_cast<__bf16 *>(out)[o] = (__bf16)v;
+        else if (mode == 1) static_cast<float *>(out)[o] = v;
+        else static_cast<float *>(out)[o] += v;
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // weight gradient, one partial per chunk of positions:
 // gWp[chunk][co][tap][ci] = sum over the chunk's s of gY[s][co] X[s + off(tap)][ci]
 // (k_colsum then adds the chunks in a fixed order, so the result does not
@@ -494,7 +577,10 @@ hipError_t conv(const __bf16 *X, int Ci, const __bf16 *W, const float *bias, int
                 int relu, void *out, hipStream_t st) {
   const int S = N * R * R * R;
   if (Ci % 32 || Co % 32 || S % CV_M) return hipErrorInvalidValue;
-  if (Co % 64 == 0)
+  if (Co % 64 && Ci >= 96 && (R == 16 || R == 32 || R == 64))  // three or more 32-channel chunks
+    hipLaunchKernelGGL(k_conv_halo<32>, dim3(S / CV_M, Co / 32), dim3(TPB), 0, st, X, Ci, W, bias, Co, R, mode,
+                       relu, out);
+  else if (Co % 64 == 0)
     hipLaunchKernelGGL(k_conv<64>, dim3(S / CV_M, Co / 64), dim3(TPB), 0, st, X, Ci, W, bias, Co, R, mode, relu,
                        out);
   else
