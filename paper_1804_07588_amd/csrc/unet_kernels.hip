@@ -210,8 +210,10 @@ __global__ void __launch_bounds__(TPB) k_conv_halo(const __bf16 *__restrict__ X,
 // over the 8 XCDs, and every item of chunk c runs on XCD c % 8, so the 27
 // taps and all groups of a chunk, which read the same gY rows and
 // overlapping X rows, share that XCD's L2.  Per step of K positions the
-// workgroup stages gY and the shifted X rows in LDS; wave w of group g owns
-// tiles 16 g + w + 4 t, t < 4.
+// workgroup stages gY and, of the shifted X rows, the input channels of its
+// group in LDS: group g takes input-channel tiles g itg .. g itg + itg - 1
+// with every output-channel tile (at most 16 tiles), and wave w owns the
+// group's tiles w + 4 t, t < 4.
 // ---------------------------------------------------------------------------
 constexpr int WG_XCD = 8;
 constexpr int WG_CH = 2048;  // positions per workgroup, at least
@@ -248,12 +250,12 @@ __device__ inline bf16x8 wg_frag(const __bf16 *t, int stride, int row0, int c0, 
 template <int K>
 __global__ void __launch_bounds__(TPB) k_wgrad(const __bf16 *__restrict__ GY, int Co,
                                                const __bf16 *__restrict__ X, int Ci, int R, int S, int L,
-                                               int ncl, int groups, float *__restrict__ GWp) {
+                                               int ncl, int groups, int itg, float *__restrict__ GWp) {
   // tiles [K positions][channel] as they lie in memory, staged with one
   // 16-byte global load and one 16-byte LDS write per 8 channels of a
   // position; the MFMA fragments are read transposed (wg_frag)
   extern __shared__ __attribute__((aligned(16))) __bf16 wg_lds[];  // K rows of SG, then of SX
-  const int SG = wg_stride(Co), SX = wg_stride(Ci);
+  const int SG = wg_stride(Co), SX = wg_stride(min(Ci, 16 * itg));
   __bf16 *sg = wg_lds, *sx = wg_lds + (size_t)K * SG;
   // work item of this workgroup: XCD blockIdx.x % 8 takes chunks of that
   // residue, taps fastest, then groups
@@ -264,7 +266,9 @@ __global__ void __launch_bounds__(TPB) k_wgrad(const __bf16 *__restrict__ GY, in
   const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int m = lane & 15, kq = lane >> 4;
-  const int nci = Ci / 16, ntile = (Co / 16) * nci, tile0 = group * 16;
+  // group g: input-channel tiles it0 .. it0 + itn - 1 with every output-channel
+  // tile (at most 16 tiles), so it stages only those itn * 16 input channels
+  const int it0 = group * itg, itn = min(itg, Ci / 16 - it0), ntile = (Co / 16) * itn;
   const int R3 = R * R * R;
   f32x4 acc[WG_MAXT];
 #pragma unroll
@@ -279,16 +283,16 @@ __global__ void __launch_bounds__(TPB) k_wgrad(const __bf16 *__restrict__ GY, in
           *reinterpret_cast<const bf16x8 *>(GY + (size_t)s * Co + 8 * q);
     const int x = s % R + dx, y = (s / R) % R + dy, z = (s / (R * R)) % R + dz;
     const bool ok = (unsigned)x < (unsigned)R && (unsigned)y < (unsigned)R && (unsigned)z < (unsigned)R;
-    const __bf16 *xs = X + (size_t)(ok ? s - (s % R3) + (z * R + y) * R + x : 0) * Ci;
-    for (int q = (int)threadIdx.x / K; q < Ci / 8; q += TPB / K)
+    const __bf16 *xs = X + (size_t)(ok ? s - (s % R3) + (z * R + y) * R + x : 0) * Ci + 16 * it0;
+    for (int q = (int)threadIdx.x / K; q < 2 * itn; q += TPB / K)
       *reinterpret_cast<bf16x8 *>(sx + r * SX + 8 * q) =
           ok ? *reinterpret_cast<const bf16x8 *>(xs + 8 * q) : zero8();
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < WG_MAXT; ++t) {
-      const int tile = tile0 + wave + 4 * t;
+      const int tile = wave + 4 * t;
       if (tile < ntile) {
-        const int ct = tile / nci, it = tile % nci;
+        const int ct = tile / itn, it = tile % itn;
 #pragma unroll
         for (int ks = 0; ks < K / 32; ++ks) {
           // A[m = co][k = position], B[k = position][n = ci]
@@ -301,12 +305,12 @@ __global__ void __launch_bounds__(TPB) k_wgrad(const __bf16 *__restrict__ GY, in
   }
 #pragma unroll
   for (int t = 0; t < WG_MAXT; ++t) {
-    const int tile = tile0 + wave + 4 * t;
+    const int tile = wave + 4 * t;
     if (tile < ntile) {
-      const int ct = tile / nci, it = tile % nci;
+      const int ct = tile / itn, it = tile % itn;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int co = ct * 16 + 4 * kq + i, ci = it * 16 + m;
+        const int co = ct * 16 + 4 * kq + i, ci = (it0 + it) * 16 + m;
         GWp[(size_t)chunk * Co * 27 * Ci + ((size_t)co * 27 + tap) * Ci + ci] = acc[t][i];
       }
     }
@@ -596,13 +600,13 @@ int wgrad_chunks(int R, int N) {
 
 template <int K>
 static void wgrad_launch(const __bf16 *GY, int Co, const __bf16 *X, int Ci, int R, int S, int nc, int groups,
-                         float *part, int *ncl_out, hipStream_t st) {
-  const size_t lds = (size_t)K * (wg_stride(Co) + wg_stride(Ci)) * sizeof(__bf16);
+                         int itg, float *part, int *ncl_out, hipStream_t st) {
+  const size_t lds = (size_t)K * (wg_stride(Co) + wg_stride(std::min(Ci, 16 * itg))) * sizeof(__bf16);
   const int L = ((S + nc - 1) / nc + K - 1) / K * K;  // chunk length, whole staging steps
   const int ncl = (S + L - 1) / L;
   const int per_xcd = (ncl + WG_XCD - 1) / WG_XCD;  // chunks per XCD, at most
   hipLaunchKernelGGL(k_wgrad<K>, dim3(WG_XCD * per_xcd * 27 * groups), dim3(TPB), lds, st, GY, Co, X, Ci, R, S, L,
-                     ncl, groups, part);
+                     ncl, groups, itg, part);
   *ncl_out = ncl;
 }
 
@@ -610,13 +614,14 @@ hipError_t wgrad(const __bf16 *GY, int Co, const __bf16 *X, int Ci, int R, int N
                  hipStream_t st) {
   const int S = N * R * R * R;
   if (Ci % 16 || Co % 16 || Ci > WG_MAXC || Co > WG_MAXC || S % WG_K) return hipErrorInvalidValue;
-  const int groups = ((Co / 16) * (Ci / 16) + 15) / 16;
+  // tile groups: itg input-channel tiles with every output-channel tile each
+  const int itg = std::max(1, 16 / (Co / 16)), groups = (Ci / 16 + itg - 1) / itg;
   const int nc = wgrad_chunks(R, N);
   int ncl;
   if (Co + Ci <= 64 && S % (2 * WG_K) == 0)
-    wgrad_launch<2 * WG_K>(GY, Co, X, Ci, R, S, nc, groups, part, &ncl, st);
+    wgrad_launch<2 * WG_K>(GY, Co, X, Ci, R, S, nc, groups, itg, part, &ncl, st);
   else
-    wgrad_launch<WG_K>(GY, Co, X, Ci, R, S, nc, groups, part, &ncl, st);
+    wgrad_launch<WG_K>(GY, Co, X, Ci, R, S, nc, groups, itg, part, &ncl, st);
   const size_t nw = (size_t)Co * 27 * Ci;
   colsum(part, ncl, nw, GW, st);
   return hipGetLastError();
